@@ -1,0 +1,183 @@
+/*
+ * reff.h -- C ABI of libreff: effective resistance of stacked 3D-IC power
+ * delivery networks on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (arxiv 2607.05818):
+ *   The early-stage PDN is a stack of 2D resistive tier meshes joined by
+ *   TSV segments; supply bumps are ideal voltage sources (Sec. III-B).  Its
+ *   DC model is G V = I with G sparse, symmetric, positive definite
+ *   (Sec. II-A, Eq. 1).  The effective resistance between nodes a and b is
+ *   R(a,b) = (e_a - e_b)^T L^+ (e_a - e_b) (Sec. II-B, Eq. 2).  With every
+ *   bump merged into one grounded supply node, a node's resistance to the
+ *   supply is R_i = (G^-1)_ii, G being the Laplacian restricted to the
+ *   non-pad nodes.
+ *
+ * Conventions shared by every entry point:
+ *   - Node id = t*nx*ny + y*nx + x; tier 0 carries the pads (bumps).
+ *   - Every call returns reff_status; nothing throws or aborts across the ABI.
+ *   - All argument validation happens on the host before any device work;
+ *     on error the outputs are left untouched (one documented exception:
+ *     REFF_ERR_NO_CONVERGENCE).
+ *   - Pointers documented as "host" must be host memory; "device" pointers
+ *     must be device memory of the handle's device.
+ *   - A handle must be used by one thread at a time; distinct handles may be
+ *     used concurrently.  reff_last_error() is thread-local.
+ */
+#ifndef REFF_H
+#define REFF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  REFF_OK = 0,
+  REFF_ERR_INVALID_ARG = -1,    /* NULL pointer, dims < 1, conductance <= 0 or
+                                   non-finite, (x,y) out of range, duplicate
+                                   TSV column, node id out of range        */
+  REFF_ERR_DISCONNECTED = -2,   /* some node has no path to a pad: G singular */
+  REFF_ERR_NO_CONVERGENCE = -3, /* max_iters reached; R_out holds the solver's
+                                   lower bounds, stats->n_unconverged > 0    */
+  REFF_ERR_OUT_OF_MEMORY = -4,
+  REFF_ERR_DEVICE = -5,         /* HIP runtime error; see reff_last_error();
+                                   the handle stays valid for reff_free_pdn */
+  REFF_ERR_UNSUPPORTED = -6
+} reff_status;
+
+/* Opaque handle to a PDN resident on one GPU (library-owned). */
+typedef struct reff_pdn_t* reff_pdn;
+
+/*
+ * Stack description (Sec. III-B: 2D tier meshes joined by TSVs, bumps on one
+ * tier).  All arrays are host memory, borrowed for the duration of the call
+ * and deep-copied by reff_build_pdn.
+ */
+typedef struct {
+  int32_t n_tiers, nx, ny;  /* each >= 1                                     */
+  const double* gx;         /* [n_tiers][ny][nx-1] S, edge (t,x,y)-(t,x+1,y)  */
+  const double* gy;         /* [n_tiers][ny-1][nx] S, edge (t,x,y)-(t,x,y+1)  */
+  int32_t n_tsv;            /* >= 0                                          */
+  const int32_t* tsv_xy;    /* [n_tsv][2] (x,y); the column joins (t,x,y) and
+                               (t+1,x,y) for every t < n_tiers-1; distinct   */
+  const double* tsv_g;      /* [n_tsv][n_tiers-1] segment conductance, S     */
+  int32_t n_pads;           /* >= 1                                          */
+  const int32_t* pad_xy;    /* [n_pads][2] (x,y) on tier 0: ideal supply bumps,
+                               grounded (Dirichlet); duplicates allowed      */
+} reff_pdn_desc;
+
+typedef enum {
+  REFF_PREC_FP64 = 0,   /* block-PCG entirely in float64                    */
+  REFF_PREC_MIXED = 1   /* float32 block-PCG inside float64 iterative
+                           refinement; final R_i accumulated in float64     */
+} reff_precision;
+
+typedef enum {
+  REFF_KRYLOV_BLOCK = 0,       /* block-PCG: columns share one block Krylov
+                                  space, s x s Gram products              */
+  REFF_KRYLOV_INDEPENDENT = 1  /* s independent PCGs run side by side       */
+} reff_krylov;
+
+typedef struct {
+  reff_precision precision;
+  double rel_tol;        /* target relative error per R_i; 0 => 1e-8 (FP64)
+                            or 1e-5 (MIXED)                                 */
+  int32_t max_iters;     /* per block-PCG solve; 0 => 20000                 */
+  int32_t block_rhs;     /* right-hand sides per block: 64 (0 => 64)        */
+  void* stream;          /* hipStream_t to run on; NULL => default stream    */
+  int32_t out_on_device; /* 1: R_out is a device pointer; 0: host pointer   */
+  reff_krylov krylov;    /* 0 => block                                       */
+  int32_t max_ir_steps;  /* MIXED only: outer refinement steps; 0 => 3       */
+} reff_solve_opts;
+
+typedef struct {
+  int64_t n_solved;       /* distinct free nodes solved                      */
+  int64_t n_unconverged;  /* columns that hit max_iters                      */
+  int32_t iters_max;      /* largest inner iteration count of any block      */
+  int32_t ir_steps;       /* largest number of refinement steps (MIXED)      */
+  double seconds;         /* wall time of the call                           */
+  double est_max_rel_err; /* solver's own estimate of the worst relative
+                             error (not a bound)                             */
+  int64_t iters_total;    /* sum of block iterations over all blocks         */
+} reff_solve_stats;
+
+/*
+ * Validate a stack, check that every node reaches a pad (breadth-first
+ * search), build the per-node stencil coefficients of G and upload them to
+ * `device`.  *out receives a new handle; free it with reff_free_pdn.
+ * Errors: INVALID_ARG, DISCONNECTED, OUT_OF_MEMORY, DEVICE.
+ */
+reff_status reff_build_pdn(const reff_pdn_desc* d, int32_t device, reff_pdn* out);
+
+/* Release a handle and its device memory.  NULL is ignored. */
+void reff_free_pdn(reff_pdn p);
+
+/* Number of nodes of a handle (n_tiers*nx*ny), or -1 for NULL. */
+int64_t reff_pdn_num_nodes(reff_pdn p);
+
+/*
+ * Node-to-supply effective resistance R_i = (G^-1)_ii (Eq. 2 with all bumps
+ * merged into the grounded supply, Sec. II-B / III-B).
+ *   nodes    host int64[n_nodes] node ids, or NULL for all nodes in id order;
+ *            duplicates allowed; pads give 0.0.
+ *   R_out    float64[n_nodes] (host, or device if opts->out_on_device).
+ *   opts     NULL => defaults.  st nullable.
+ * Errors: INVALID_ARG (bad id, bad option), NO_CONVERGENCE (R_out holds the
+ * block-PCG lower bounds), OUT_OF_MEMORY, DEVICE.
+ */
+reff_status reff_solve_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes,
+                            double* R_out, const reff_solve_opts* opts,
+                            reff_solve_stats* st);
+
+typedef enum {
+  REFF_PAIRS_GROUNDED = 0, /* pads merged into the grounded supply:
+                              R(a,b) = K_aa + K_bb - 2 K_ab with K = G^-1   */
+  REFF_PAIRS_FLOATING = 1  /* Eq. 2 on the whole un-grounded stack: pads are
+                              ordinary nodes (the paper's bump-to-load
+                              resistance, Sec. III-C/D)                    */
+} reff_pair_mode;
+
+/*
+ * m x n pair resistances R(a_i, b_j), from m + n solves by linearity
+ * (Sec. III-D: m x n bump-load pairs from m + n solves).
+ *   a, b     host int64 node ids; R_out float64[m*n] row-major (host, or
+ *            device if opts->out_on_device).  R(x,x) = 0.
+ * Errors as reff_solve_diag.
+ */
+reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m,
+                             const int64_t* b, int64_t n, reff_pair_mode mode,
+                             double* R_out, const reff_solve_opts* opts,
+                             reff_solve_stats* st);
+
+typedef struct {
+  reff_solve_opts solve;   /* precision, tolerance, stream, out_on_device   */
+  const void* surrogate;   /* reserved; must be NULL                        */
+  double spot_frac;        /* reserved                                       */
+  double fallback_rel_err; /* reserved                                       */
+  const char* tune_db;     /* reserved                                       */
+} reff_batch_opts;
+
+/*
+ * Many candidate TSV plans in one call (design-option exploration, Sec. I
+ * and Sec. IV-B).  plans[i] is validated and solved like reff_build_pdn +
+ * reff_solve_diag; nodes[i] (host, NULL => all) and n_nodes[i] select the
+ * nodes of plan i and R_out[i] receives them.  per_plan (nullable) gets one
+ * stats record per plan.
+ */
+reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
+                             const int64_t* const* nodes, const int64_t* n_nodes,
+                             double* const* R_out, const reff_batch_opts* opts,
+                             reff_solve_stats* per_plan);
+
+/* Static description of a status code. */
+const char* reff_status_string(reff_status s);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char* reff_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REFF_H */

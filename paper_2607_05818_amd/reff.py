@@ -1,0 +1,296 @@
+"""Thin ctypes binding of libreff.so (the C ABI in include/reff.h).
+
+The functions keep the C names and only marshal arguments: every step of
+the computation runs in the library's HIP kernels.  Buffers may be numpy
+arrays (host) or torch CUDA tensors (device); a CUDA output tensor selects
+``out_on_device`` and the caller's current torch stream is used unless a
+stream is given.  Importing this module raises if the library has not been
+built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libreff.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2607_05818_amd.build` "
+        "(HIP for gfx950); there is no CPU fallback")
+
+try:  # share PyTorch's HIP runtime (libreff is linked against it)
+    import torch  # noqa: F401
+except ImportError:
+    torch = None
+_lib = C.CDLL(LIB_PATH)
+
+REFF_OK = 0
+REFF_ERR_INVALID_ARG = -1
+REFF_ERR_DISCONNECTED = -2
+REFF_ERR_NO_CONVERGENCE = -3
+REFF_ERR_OUT_OF_MEMORY = -4
+REFF_ERR_DEVICE = -5
+REFF_ERR_UNSUPPORTED = -6
+
+REFF_PREC_FP64 = 0
+REFF_PREC_MIXED = 1
+REFF_KRYLOV_BLOCK = 0
+REFF_KRYLOV_INDEPENDENT = 1
+REFF_PAIRS_GROUNDED = 0
+REFF_PAIRS_FLOATING = 1
+
+EXPORTED = [
+    "reff_build_pdn", "reff_free_pdn", "reff_pdn_num_nodes", "reff_solve_diag",
+    "reff_query_pairs", "reff_batch_plans", "reff_status_string", "reff_last_error",
+]
+
+
+class reff_pdn_desc(C.Structure):
+    _fields_ = [
+        ("n_tiers", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+        ("gx", C.POINTER(C.c_double)), ("gy", C.POINTER(C.c_double)),
+        ("n_tsv", C.c_int32), ("tsv_xy", C.POINTER(C.c_int32)),
+        ("tsv_g", C.POINTER(C.c_double)),
+        ("n_pads", C.c_int32), ("pad_xy", C.POINTER(C.c_int32)),
+    ]
+
+
+class reff_solve_opts(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int), ("rel_tol", C.c_double), ("max_iters", C.c_int32),
+        ("block_rhs", C.c_int32), ("stream", C.c_void_p), ("out_on_device", C.c_int32),
+        ("krylov", C.c_int), ("max_ir_steps", C.c_int32),
+    ]
+
+
+class reff_solve_stats(C.Structure):
+    _fields_ = [
+        ("n_solved", C.c_int64), ("n_unconverged", C.c_int64), ("iters_max", C.c_int32),
+        ("ir_steps", C.c_int32), ("seconds", C.c_double), ("est_max_rel_err", C.c_double),
+        ("iters_total", C.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class reff_batch_opts(C.Structure):
+    _fields_ = [
+        ("solve", reff_solve_opts), ("surrogate", C.c_void_p), ("spot_frac", C.c_double),
+        ("fallback_rel_err", C.c_double), ("tune_db", C.c_char_p),
+    ]
+
+
+_lib.reff_build_pdn.argtypes = [C.POINTER(reff_pdn_desc), C.c_int32, C.POINTER(C.c_void_p)]
+_lib.reff_build_pdn.restype = C.c_int
+_lib.reff_free_pdn.argtypes = [C.c_void_p]
+_lib.reff_free_pdn.restype = None
+_lib.reff_pdn_num_nodes.argtypes = [C.c_void_p]
+_lib.reff_pdn_num_nodes.restype = C.c_int64
+_lib.reff_solve_diag.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                 C.POINTER(reff_solve_opts), C.POINTER(reff_solve_stats)]
+_lib.reff_solve_diag.restype = C.c_int
+_lib.reff_query_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                  C.c_int, C.c_void_p, C.POINTER(reff_solve_opts),
+                                  C.POINTER(reff_solve_stats)]
+_lib.reff_query_pairs.restype = C.c_int
+_lib.reff_batch_plans.argtypes = [C.POINTER(reff_pdn_desc), C.c_int32,
+                                  C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_void_p), C.POINTER(reff_batch_opts),
+                                  C.POINTER(reff_solve_stats)]
+_lib.reff_batch_plans.restype = C.c_int
+_lib.reff_status_string.argtypes = [C.c_int]
+_lib.reff_status_string.restype = C.c_char_p
+_lib.reff_last_error.argtypes = []
+_lib.reff_last_error.restype = C.c_char_p
+
+
+class ReffError(RuntimeError):
+    def __init__(self, status, detail):
+        self.status = status
+        super().__init__(f"{reff_status_string(status)} ({status}): {detail}")
+
+
+def reff_status_string(status: int) -> str:
+    return _lib.reff_status_string(int(status)).decode()
+
+
+def reff_last_error() -> str:
+    return _lib.reff_last_error().decode()
+
+
+def _check(status, allow=()):
+    if status != REFF_OK and status not in allow:
+        raise ReffError(status, reff_last_error())
+    return status
+
+
+def _desc_struct(desc):
+    """Pack a descriptor dict into the C struct; returns (struct, keepalive)."""
+    nt, nx, ny = int(desc["n_tiers"]), int(desc["nx"]), int(desc["ny"])
+    arrs = {
+        "gx": np.ascontiguousarray(desc["gx"], dtype=np.float64).ravel(),
+        "gy": np.ascontiguousarray(desc["gy"], dtype=np.float64).ravel(),
+        "tsv_xy": np.ascontiguousarray(desc["tsv_xy"], dtype=np.int32).ravel(),
+        "tsv_g": np.ascontiguousarray(desc["tsv_g"], dtype=np.float64).ravel(),
+        "pad_xy": np.ascontiguousarray(desc["pad_xy"], dtype=np.int32).ravel(),
+    }
+    s = reff_pdn_desc()
+    s.n_tiers, s.nx, s.ny = nt, nx, ny
+    s.gx = arrs["gx"].ctypes.data_as(C.POINTER(C.c_double))
+    s.gy = arrs["gy"].ctypes.data_as(C.POINTER(C.c_double))
+    s.n_tsv = len(arrs["tsv_xy"]) // 2
+    s.tsv_xy = arrs["tsv_xy"].ctypes.data_as(C.POINTER(C.c_int32))
+    s.tsv_g = arrs["tsv_g"].ctypes.data_as(C.POINTER(C.c_double))
+    s.n_pads = len(arrs["pad_xy"]) // 2
+    s.pad_xy = arrs["pad_xy"].ctypes.data_as(C.POINTER(C.c_int32))
+    return s, arrs
+
+
+class PDN:
+    """Owner of a reff_pdn handle."""
+
+    def __init__(self, handle, device):
+        self.handle = handle
+        self.device = device
+
+    @property
+    def num_nodes(self):
+        return int(_lib.reff_pdn_num_nodes(self.handle))
+
+    def close(self):
+        if self.handle:
+            _lib.reff_free_pdn(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def reff_build_pdn(desc, device: int = 0) -> PDN:
+    s, keep = _desc_struct(desc)
+    h = C.c_void_p()
+    _check(_lib.reff_build_pdn(C.byref(s), int(device), C.byref(h)))
+    del keep
+    return PDN(h, device)
+
+
+def reff_free_pdn(pdn: PDN) -> None:
+    pdn.close()
+
+
+def _is_torch_cuda(x):
+    return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
+
+
+def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps):
+    o = reff_solve_opts()
+    o.precision = int(precision)
+    o.rel_tol = float(rel_tol)
+    o.max_iters = int(max_iters)
+    o.block_rhs = 0
+    o.krylov = int(krylov)
+    o.max_ir_steps = int(max_ir_steps)
+    o.out_on_device = 1 if out_dev else 0
+    if stream is None and out_dev:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    o.stream = C.c_void_p(int(stream) if stream is not None else 0)
+    return o
+
+
+def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP64,
+                    rel_tol=0.0, max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None,
+                    max_ir_steps=0, allow_unconverged=False):
+    """R_i = (G^-1)_ii for `nodes` (None = all).  Returns (R_out, stats)."""
+    if nodes is None:
+        count = pdn.num_nodes
+        nodes_arr = None
+        nptr = None
+    else:
+        nodes_arr = np.ascontiguousarray(nodes, dtype=np.int64)
+        count = len(nodes_arr)
+        nptr = nodes_arr.ctypes.data
+    if R_out is None:
+        R_out = np.empty(count, dtype=np.float64)
+    out_dev = _is_torch_cuda(R_out)
+    if out_dev:
+        assert R_out.dtype.__repr__().endswith("float64") and R_out.is_contiguous()
+        assert R_out.numel() >= count
+        optr = R_out.data_ptr()
+    else:
+        assert R_out.dtype == np.float64 and R_out.flags.c_contiguous and len(R_out) >= count
+        optr = R_out.ctypes.data
+    o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps)
+    st = reff_solve_stats()
+    allow = (REFF_ERR_NO_CONVERGENCE,) if allow_unconverged else ()
+    _check(_lib.reff_solve_diag(pdn.handle, nptr, count if nodes is not None else 0, optr,
+                                C.byref(o), C.byref(st)), allow)
+    return R_out, st.as_dict()
+
+
+def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
+                     precision=REFF_PREC_FP64, rel_tol=0.0, max_iters=0,
+                     krylov=REFF_KRYLOV_BLOCK, stream=None, max_ir_steps=0):
+    """m x n pair resistances R(a_i, b_j).  Returns (R_out, stats)."""
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    b = np.ascontiguousarray(b, dtype=np.int64)
+    m, n = len(a), len(b)
+    if R_out is None:
+        R_out = np.empty((m, n), dtype=np.float64)
+    out_dev = _is_torch_cuda(R_out)
+    optr = R_out.data_ptr() if out_dev else R_out.ctypes.data
+    o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps)
+    st = reff_solve_stats()
+    _check(_lib.reff_query_pairs(pdn.handle, a.ctypes.data, m, b.ctypes.data, n, int(mode),
+                                 optr, C.byref(o), C.byref(st)))
+    return R_out, st.as_dict()
+
+
+def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.0,
+                     max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None, R_out=None):
+    """Solve many plans in one call.  Returns (list of R arrays, list of stats)."""
+    k = len(plans)
+    structs = (reff_pdn_desc * k)()
+    keep = []
+    for i, d in enumerate(plans):
+        s, kp = _desc_struct(d)
+        structs[i] = s
+        keep.append(kp)
+    node_arrs = []
+    nptrs = (C.c_void_p * k)()
+    ncount = (C.c_int64 * k)()
+    outs = []
+    optrs = (C.c_void_p * k)()
+    out_dev = False
+    for i, d in enumerate(plans):
+        if nodes is None or nodes[i] is None:
+            nptrs[i] = None
+            cnt = int(d["n_tiers"]) * int(d["nx"]) * int(d["ny"])
+        else:
+            arr = np.ascontiguousarray(nodes[i], dtype=np.int64)
+            node_arrs.append(arr)
+            nptrs[i] = arr.ctypes.data
+            cnt = len(arr)
+        ncount[i] = cnt
+        if R_out is not None:
+            o = R_out[i]
+            out_dev = _is_torch_cuda(o)
+            optrs[i] = o.data_ptr() if out_dev else o.ctypes.data
+            outs.append(o)
+        else:
+            o = np.empty(cnt, dtype=np.float64)
+            optrs[i] = o.ctypes.data
+            outs.append(o)
+    bo = reff_batch_opts()
+    bo.solve = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, 0)
+    stats = (reff_solve_stats * k)()
+    _check(_lib.reff_batch_plans(structs, k, nptrs, ncount, optrs, C.byref(bo), stats))
+    return outs, [stats[i].as_dict() for i in range(k)]

@@ -1,0 +1,169 @@
+"""Parity of the HIP block-PCG path (through the C ABI) with the CPU oracle.
+
+Tolerances: max relative error 1e-6 for the float64 path and 1e-3 for the
+mixed float32/float64 path, per requested free node; pads are exactly 0.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import reff_oracle as ro
+from paper_2607_05818_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _reff():
+    from paper_2607_05818_amd import reff
+    return reff
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _max_rel(got, want):
+    got = np.asarray(got)
+    want = np.asarray(want)
+    m = want > 0
+    assert np.all(got[~m] == 0.0)
+    if not m.any():
+        return 0.0
+    rel = np.abs(got[m] - want[m]) / want[m]
+    i = int(np.argmax(rel))
+    print(f"  worst: idx {np.flatnonzero(m)[i]} got {got[m][i]!r} want {want[m][i]!r}; "
+          f"median rel {np.median(rel):.3e}", flush=True)
+    return float(rel[i])
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    d = gen.config1()
+    return d, ro.diag(d)
+
+
+@pytest.mark.parametrize("krylov", [0, 1], ids=["block", "indep"])
+def test_config1_full_map_fp64(cfg1, krylov):
+    reff = _reff()
+    d, want = cfg1
+    _say("config1 full map fp64 krylov", krylov)
+    h = reff.reff_build_pdn(d)
+    got, st = reff.reff_solve_diag(h, None, precision=reff.REFF_PREC_FP64, krylov=krylov,
+                                   rel_tol=1e-9)
+    err = _max_rel(got, want)
+    print("max rel err", err, st, flush=True)
+    assert err <= 1e-6
+    assert st["n_unconverged"] == 0
+    # Galerkin estimates approach R_i from below.
+    assert np.all(got <= want * (1 + 1e-12) + 1e-15)
+
+
+@pytest.mark.parametrize("krylov", [0, 1], ids=["block", "indep"])
+def test_config1_full_map_mixed(cfg1, krylov):
+    reff = _reff()
+    d, want = cfg1
+    _say("config1 full map mixed krylov", krylov)
+    h = reff.reff_build_pdn(d)
+    got, st = reff.reff_solve_diag(h, None, precision=reff.REFF_PREC_MIXED, krylov=krylov)
+    err = _max_rel(got, want)
+    print("max rel err", err, st, flush=True)
+    assert err <= 1e-3
+
+
+def test_config1_device_output_and_order(cfg1):
+    import torch
+    reff = _reff()
+    d, want = cfg1
+    _say("config1 device output, duplicates, pads, shuffled order")
+    rng = np.random.default_rng(3)
+    nodes = rng.integers(0, len(want), size=150)
+    nodes[:5] = ro.pad_nodes(d)[:5]
+    nodes[5:9] = nodes[10]
+    h = reff.reff_build_pdn(d)
+    out = torch.full((len(nodes),), -1.0, dtype=torch.float64, device="cuda")
+    reff.reff_solve_diag(h, nodes, out, precision=reff.REFF_PREC_FP64)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.all(got[:5] == 0.0)
+    assert _max_rel(got, want[nodes]) <= 1e-6
+
+
+SMALL = [
+    # seed, nt, nx, ny, n_tsv, n_pads  (ragged sizes, degenerate dims)
+    (101, 1, 7, 5, 0, 1), (102, 3, 1, 9, 1, 1), (103, 2, 33, 3, 4, 2),
+    (104, 4, 10, 10, 6, 3), (105, 1, 1, 1, 0, 1), (106, 2, 17, 19, 9, 5),
+    (107, 5, 6, 4, 3, 1),
+]
+
+
+@pytest.mark.parametrize("seed,nt,nx,ny,ntsv,npad", SMALL)
+def test_small_ragged_stacks(seed, nt, nx, ny, ntsv, npad):
+    reff = _reff()
+    d = gen.small_random_desc(seed, nt, nx, ny, max(ntsv, 1 if nt > 1 else 0), npad)
+    want = ro.diag(d)
+    _say("small", seed, nt, nx, ny, ntsv, npad)
+    h = reff.reff_build_pdn(d)
+    for prec, tol in ((reff.REFF_PREC_FP64, 1e-6), (reff.REFF_PREC_MIXED, 1e-3)):
+        got, _ = reff.reff_solve_diag(h, None, precision=prec)
+        assert _max_rel(got, want) <= tol, (prec, seed)
+
+
+def test_empty_request():
+    reff = _reff()
+    d = gen.config1()
+    h = reff.reff_build_pdn(d)
+    got, st = reff.reff_solve_diag(h, np.zeros(0, dtype=np.int64))
+    assert len(got) == 0 and st["n_solved"] == 0
+
+
+def test_no_convergence_returns_lower_bounds(cfg1):
+    reff = _reff()
+    d, want = cfg1
+    _say("max_iters=1 -> NO_CONVERGENCE with lower bounds")
+    h = reff.reff_build_pdn(d)
+    nodes = np.arange(64, 128)
+    got, st = reff.reff_solve_diag(h, nodes, precision=reff.REFF_PREC_FP64, max_iters=1,
+                                   allow_unconverged=True)
+    assert st["n_unconverged"] > 0
+    w = want[nodes]
+    free = w > 0
+    assert np.all(got[free] <= w[free] * (1 + 1e-12))
+    assert np.all(got[free] > 0)
+    with pytest.raises(reff.ReffError) as ei:
+        reff.reff_solve_diag(h, nodes, precision=reff.REFF_PREC_FP64, max_iters=1)
+    assert ei.value.status == reff.REFF_ERR_NO_CONVERGENCE
+
+
+def test_config2_shape_reduced():
+    """The mixed-precision workload's recipe at 1/16 of the area."""
+    reff = _reff()
+    d = gen.config2(side=128, n_tsv=64, sigma=10.0)
+    nodes = gen.sample_free_nodes(d, 192, 5)
+    want = ro.diag(d, nodes=nodes)
+    _say("config2 recipe side 128")
+    h = reff.reff_build_pdn(d)
+    got, st = reff.reff_solve_diag(h, nodes, precision=reff.REFF_PREC_MIXED, rel_tol=1e-4)
+    print("mixed", _max_rel(got, want), st, flush=True)
+    assert _max_rel(got, want) <= 1e-3
+    got, st = reff.reff_solve_diag(h, nodes, precision=reff.REFF_PREC_FP64, rel_tol=1e-8)
+    print("fp64", _max_rel(got, want), st, flush=True)
+    assert _max_rel(got, want) <= 1e-6
+
+
+def test_config2_full_size_sampled_golden():
+    """Full 4 x 512 x 512 stack; stored oracle values for a seeded sample
+    (written by tests/golden/make_golden.py, which calls only the oracle)."""
+    reff = _reff()
+    g = json.load(open(os.path.join(HERE, "golden", "config2_sample.json")))
+    nodes = np.array(g["nodes"][:64], dtype=np.int64)
+    want = np.array(g["R"][:64])
+    d = gen.config2()
+    _say("config2 full size, 64 sampled nodes, mixed")
+    h = reff.reff_build_pdn(d)
+    got, st = reff.reff_solve_diag(h, nodes, precision=reff.REFF_PREC_MIXED, rel_tol=1e-4)
+    print("mixed", _max_rel(got, want), st, flush=True)
+    assert _max_rel(got, want) <= 1e-3
