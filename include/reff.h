@@ -89,6 +89,8 @@ typedef struct {
   int32_t out_on_device; /* 1: R_out is a device pointer; 0: host pointer   */
   reff_krylov krylov;    /* 0 => block                                       */
   int32_t max_ir_steps;  /* MIXED only: outer refinement steps; 0 => 3       */
+  int32_t timing;        /* 1: time the three block kernels with HIP events on
+                            `stream` (fills the kernel_* fields of stats)    */
 } reff_solve_opts;
 
 typedef struct {
@@ -100,6 +102,11 @@ typedef struct {
   double est_max_rel_err; /* solver's own estimate of the worst relative
                              error (not a bound)                             */
   int64_t iters_total;    /* sum of block iterations over all blocks         */
+  /* With opts->timing: summed device time (ms) and launch count of the
+     stencil+Gram kernel [0], the residual-update kernel [1] and the
+     search-block kernel [2]. */
+  double kernel_ms[3];
+  int64_t kernel_launches[3];
 } reff_solve_stats;
 
 /*

@@ -228,6 +228,7 @@ struct Opts {
   int32_t max_ir;
   hipStream_t stream;
   bool out_dev;
+  bool timing;
 };
 
 reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
@@ -253,6 +254,8 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
   out.max_ir = o->max_ir_steps > 0 ? o->max_ir_steps : 3;
   out.stream = (hipStream_t)o->stream;
   out.out_dev = o->out_on_device == 1;
+  if (o->timing != 0 && o->timing != 1) return fail(REFF_ERR_INVALID_ARG, "timing must be 0 or 1");
+  out.timing = o->timing == 1;
   return REFF_OK;
 }
 
@@ -322,6 +325,18 @@ reff_status solve_columns(reff_pdn_t* p, const std::vector<int64_t>& cols, doubl
   HIPCHK(hipHostMalloc((void**)&pin.est, S * sizeof(double)));
 
   const int poll = 8;
+  // Optional per-kernel timing: one set of 6 events per iteration of a poll
+  // chunk, read back after the chunk's synchronisation.
+  struct EventPool {
+    std::vector<hipEvent_t> ev;
+    ~EventPool() {
+      for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+  } evp;
+  if (o.timing) {
+    evp.ev.resize(6 * poll);
+    for (auto& e : evp.ev) HIPCHK(hipEventCreate(&e));
+  }
   const int64_t nblk = ((int64_t)cols.size() + S - 1) / S;
   // Columns are dealt to blocks in a fixed pseudo-random order: right-hand
   // sides that sit next to each other span nearly the same block Krylov
@@ -358,11 +373,21 @@ reff_status solve_columns(reff_pdn_t* p, const std::vector<int64_t>& cols, doubl
       while (it < o.max_iters) {
         const int k = std::min(poll, o.max_iters - it);
         for (int i = 0; i < k; ++i)
-          HIPCHK(launch_iteration(fp32, o.indep, o.mixed, coef, b, n, o.tol, o.stream));
+          HIPCHK(launch_iteration(fp32, o.indep, o.mixed, coef, b, n, o.tol, o.stream,
+                                  o.timing ? &evp.ev[6 * i] : nullptr));
         it += k;
         HIPCHK(hipMemcpyAsync(pin.flags, &b.state->it, 2 * sizeof(int32_t),
                               hipMemcpyDeviceToHost, o.stream));
         HIPCHK(hipStreamSynchronize(o.stream));
+        if (o.timing && st) {
+          for (int i = 0; i < k; ++i)
+            for (int kk = 0; kk < 3; ++kk) {
+              float ms = 0.f;
+              HIPCHK(hipEventElapsedTime(&ms, evp.ev[6 * i + 2 * kk], evp.ev[6 * i + 2 * kk + 1]));
+              st->kernel_ms[kk] += ms;
+              st->kernel_launches[kk] += 1;
+            }
+        }
         if (pin.flags[1]) {
           conv = true;
           it = pin.flags[0];

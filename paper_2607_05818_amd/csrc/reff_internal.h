@@ -108,8 +108,11 @@ int grid_for(int64_t n);
 
 hipError_t launch_init_block(bool fp32, bool indep, const void* coef, const SolveBuffers& b,
                              hipStream_t st);
+// ev (nullable): 6 events recorded around the three block kernels
+// (before/after K1, K2, K3).
 hipError_t launch_iteration(bool fp32, bool indep, bool with_d, const void* coef,
-                            const SolveBuffers& b, int64_t n, double tol, hipStream_t st);
+                            const SolveBuffers& b, int64_t n, double tol, hipStream_t st,
+                            hipEvent_t* ev);
 hipError_t launch_zero_x(double* X, int64_t cnt, hipStream_t st);
 hipError_t launch_mixed_residual(const Coef<double>& c, const Coef<float>& cf,
                                  const SolveBuffers& b, double* out, const int64_t* pos,

@@ -803,7 +803,7 @@ __global__ void k_gather_out(const double* __restrict__ res, const int64_t* __re
 // ---------------------------------------------------------------- launchers
 template <typename T>
 static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const SolveBuffers& b,
-                              double tol, hipStream_t st) {
+                              double tol, hipStream_t st, hipEvent_t* ev) {
   const int G = grid_for(c.n);
   T* Y = (T*)b.Y;
   T* P = (T*)b.P;
@@ -817,16 +817,19 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
   const double tau = sizeof(T) == 8 ? 1e-26 : 1e-12;
   const int len = indep ? S : S * S;
   const dim3 g(G), blk(WG);
+  if (ev) hipEventRecord(ev[0], st);
   if (indep)
     hipLaunchKernelGGL((k_spmv_gram<T, true>), g, blk, 0, st, c, Y, (const T*)b.Tm, R, P, Q,
                        b.part);
   else
     hipLaunchKernelGGL((k_spmv_gram<T, false>), g, blk, 0, st, c, Y, (const T*)b.Tm, R, P, Q,
                        b.part);
+  if (ev) hipEventRecord(ev[1], st);
   hipLaunchKernelGGL(k_reduce, dim3((2 * len + 63) / 64), dim3(256), 0, st, b.part, b.W, G, 0,
                      2, len);
   hipLaunchKernelGGL((k_small1<T>), dim3(1), dim3(SM_THREADS), 0, st, b.W, (const T*)P, b.tgt,
                      b.winv, (T*)b.alpha, b.state, tol, eps1, indep ? 1 : 0);
+  if (ev) hipEventRecord(ev[2], st);
   if (indep) {
     if (with_d)
       hipLaunchKernelGGL((k_update_r<T, true, true>), g, blk, 0, st, c, (const T*)b.alpha, Q,
@@ -842,16 +845,20 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
       hipLaunchKernelGGL((k_update_r<T, false, false>), g, blk, 0, st, c, (const T*)b.alpha, Q,
                          P, R, D, b.part);
   }
+  if (ev) hipEventRecord(ev[3], st);
   hipLaunchKernelGGL(k_reduce, dim3((len + 63) / 64), dim3(256), 0, st, b.part, b.W, G, 2, 1,
                      len);
   hipLaunchKernelGGL((k_small2<T>), dim3(1), dim3(SM_THREADS), 0, st, b.W, b.winv,
                      (T*)b.delta, b.state, indep ? 1 : 0);
+  if (ev) hipEventRecord(ev[4], st);
   if (indep) {
     hipLaunchKernelGGL((k_update_y<T, true>), g, blk, 0, st, c, (const T*)b.delta, R, P, Y,
                        b.part);
+    if (ev) hipEventRecord(ev[5], st);
   } else {
     hipLaunchKernelGGL((k_update_y<T, false>), g, blk, 0, st, c, (const T*)b.delta, R, P, Y,
                        b.part);
+    if (ev) hipEventRecord(ev[5], st);
     hipLaunchKernelGGL(k_reduce, dim3((len + 63) / 64), dim3(256), 0, st, b.part, b.W, G, 3, 1,
                        len);
     hipLaunchKernelGGL((k_small3<T>), dim3(1), dim3(SM_THREADS), 0, st, b.W, (T*)b.Tm, b.state,
@@ -861,10 +868,11 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
 }
 
 hipError_t launch_iteration(bool fp32, bool indep, bool with_d, const void* coef,
-                            const SolveBuffers& b, int64_t n, double tol, hipStream_t st) {
+                            const SolveBuffers& b, int64_t n, double tol, hipStream_t st,
+                            hipEvent_t* ev) {
   (void)n;
-  if (fp32) return iteration_t<float>(indep, with_d, *(const Coef<float>*)coef, b, tol, st);
-  return iteration_t<double>(indep, with_d, *(const Coef<double>*)coef, b, tol, st);
+  if (fp32) return iteration_t<float>(indep, with_d, *(const Coef<float>*)coef, b, tol, st, ev);
+  return iteration_t<double>(indep, with_d, *(const Coef<double>*)coef, b, tol, st, ev);
 }
 
 template <typename T>

@@ -63,7 +63,7 @@ class reff_solve_opts(C.Structure):
     _fields_ = [
         ("precision", C.c_int), ("rel_tol", C.c_double), ("max_iters", C.c_int32),
         ("block_rhs", C.c_int32), ("stream", C.c_void_p), ("out_on_device", C.c_int32),
-        ("krylov", C.c_int), ("max_ir_steps", C.c_int32),
+        ("krylov", C.c_int), ("max_ir_steps", C.c_int32), ("timing", C.c_int32),
     ]
 
 
@@ -71,11 +71,16 @@ class reff_solve_stats(C.Structure):
     _fields_ = [
         ("n_solved", C.c_int64), ("n_unconverged", C.c_int64), ("iters_max", C.c_int32),
         ("ir_steps", C.c_int32), ("seconds", C.c_double), ("est_max_rel_err", C.c_double),
-        ("iters_total", C.c_int64),
+        ("iters_total", C.c_int64), ("kernel_ms", C.c_double * 3),
+        ("kernel_launches", C.c_int64 * 3),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if k.startswith("kernel_") else v
+        return out
 
 
 class reff_batch_opts(C.Structure):
@@ -190,8 +195,9 @@ def _is_torch_cuda(x):
     return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
 
 
-def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps):
+def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing=False):
     o = reff_solve_opts()
+    o.timing = 1 if timing else 0
     o.precision = int(precision)
     o.rel_tol = float(rel_tol)
     o.max_iters = int(max_iters)
@@ -208,7 +214,7 @@ def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps):
 
 def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP64,
                     rel_tol=0.0, max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None,
-                    max_ir_steps=0, allow_unconverged=False):
+                    max_ir_steps=0, allow_unconverged=False, timing=False):
     """R_i = (G^-1)_ii for `nodes` (None = all).  Returns (R_out, stats)."""
     if nodes is None:
         count = pdn.num_nodes
@@ -228,7 +234,7 @@ def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP6
     else:
         assert R_out.dtype == np.float64 and R_out.flags.c_contiguous and len(R_out) >= count
         optr = R_out.ctypes.data
-    o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps)
+    o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing)
     st = reff_solve_stats()
     allow = (REFF_ERR_NO_CONVERGENCE,) if allow_unconverged else ()
     _check(_lib.reff_solve_diag(pdn.handle, nptr, count if nodes is not None else 0, optr,
