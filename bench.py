@@ -31,11 +31,11 @@ S = 64
 def kernel_bytes(n, fp32=True, mixed_with_d=True):
     """Algorithmic HBM bytes per launch of the three block kernels for an
     n-node stack and S right-hand sides (w = bytes per word):
-      stencil+Gram (K1): read Y, R; write P, Q      -> 4 S w per node
-                         + coefficients d, cE, cN, slot
-      residual update (K2): read Q, R (P, D); write R (D) -> 3 (6) S w
+      stencil+Gram (K1): read Y, R; write P = Y T, Q = (G Y) T -> 4 S w per node
+                         + coefficients d, cE, cN (w each) and the TSV slot (4)
+      residual update (K2): read Q, R (P, D); write R (D)       -> 3 (6) S w
                          + Dinv
-      search block (K3): read P, R; write Y          -> 3 S w + d, Dinv
+      search block (K3): read P, R; write Y                     -> 3 S w + d, Dinv
     """
     w = 4 if fp32 else 8
     k1 = n * (4 * S * w + 3 * w + 4)

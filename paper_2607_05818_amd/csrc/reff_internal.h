@@ -88,20 +88,20 @@ namespace reff {
 // Kernel launchers (reff_kernels.hip).  All launch on `st` and return the
 // HIP error of the launch.
 struct SolveBuffers {
-  void* Y;      // n x S, T: search block before orthonormalisation
-  void* P;      // n x S, T: P = Y T
-  void* Q;      // n x S, T: Q = G P
-  void* R;      // n x S, T: residual block
-  void* D;      // n x S, T: accumulated solution (mixed path / pairs), may be null
-  double* X;    // n x S, float64 (mixed path accumulated solution), may be null
-  double* part; // grid x 4 x S*S partial Grams
-  double* W;    // 4 x S*S reduced Grams
-  double* winv; // S*S: W1^+
-  void* alpha;  // S*S in T
-  void* delta;  // S*S in T
-  void* Tm;     // S*S in T: orthonormalising map
+  void* Y;       // n x S, T: search block before orthonormalisation
+  void* P;       // n x S, T: P = Y T
+  void* Q;       // n x S, T: Q = G P
+  void* R;       // n x S, T: residual block
+  void* D;       // n x S, T: accumulated solution (mixed path), may be null
+  double* X;     // n x S, float64 (mixed path accumulated solution), may be null
+  double* part;  // grid x 4 x S*S partial Grams
+  double* W;     // 4 x S*S reduced Grams
+  double* winv;  // S*S: W1^+
+  void* alpha;   // S*S in T
+  void* delta;   // S*S in T
+  void* Tm;      // S*S in T: orthonormalising map T
   BlockState* state;
-  int64_t* tgt; // S target node ids (-1 = empty column)
+  int64_t* tgt;  // S target node ids (-1 = empty column)
 };
 
 int grid_for(int64_t n);
