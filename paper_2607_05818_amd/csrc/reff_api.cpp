@@ -93,7 +93,9 @@ struct HostCoef {
   std::vector<uint8_t> is_pad;
 };
 
-reff_status build_host(const reff_pdn_desc* ds, HostCoef& h) {
+// Coefficients of G = L[F, F] for the grounded (Dirichlet) node set `gnd`
+// and a breadth-first connectivity check from those nodes.
+reff_status build_host(const reff_pdn_desc* ds, const std::vector<int64_t>& gnd, HostCoef& h) {
   const int64_t nt = ds->n_tiers, nx = ds->nx, ny = ds->ny;
   const int64_t plane = nx * ny, n = nt * plane;
   h.d.assign((size_t)n, 0.0);
@@ -101,8 +103,7 @@ reff_status build_host(const reff_pdn_desc* ds, HostCoef& h) {
   h.cN.assign((size_t)n, 0.0);
   h.slot.assign((size_t)n, -1);
   h.is_pad.assign((size_t)n, 0);
-  for (int32_t j = 0; j < ds->n_pads; ++j)
-    h.is_pad[(size_t)(ds->pad_xy[2 * j + 1] * nx + ds->pad_xy[2 * j])] = 1;
+  for (int64_t v : gnd) h.is_pad[(size_t)v] = 1;
   auto edge = [&](int64_t u, int64_t v, double g, double* cu) {
     const bool fu = !h.is_pad[(size_t)u], fv = !h.is_pad[(size_t)v];
     if (fu) h.d[(size_t)u] += g;
@@ -148,8 +149,8 @@ reff_status build_host(const reff_pdn_desc* ds, HostCoef& h) {
   std::vector<int32_t> col((size_t)plane, -1);
   for (int32_t j = 0; j < ds->n_tsv; ++j) col[(size_t)(ds->tsv_xy[2 * j + 1] * nx + ds->tsv_xy[2 * j])] = j;
   std::deque<int64_t> q;
-  for (int64_t v = 0; v < plane; ++v)
-    if (h.is_pad[(size_t)v]) {
+  for (int64_t v : gnd)
+    if (!seen[(size_t)v]) {
       seen[(size_t)v] = 1;
       q.push_back(v);
     }
@@ -204,20 +205,85 @@ reff_status ensure(DevBuf& b, size_t bytes) {
   return REFF_OK;
 }
 
-template <typename T>
-Coef<T> coef_of(const reff_pdn_t* p);
-
-template <>
-Coef<double> coef_of<double>(const reff_pdn_t* p) {
-  Coef<double> c{p->d64, p->dinv64, p->cE64, p->cN64, p->slot, p->up64, p->dn64,
-                 p->n,   p->nx,     p->plane};
-  return c;
+Coef<double> coef64(const CoefSet& cs) {
+  return Coef<double>{cs.d64, cs.dinv64, cs.cE64, cs.cN64, cs.slot, cs.up64, cs.dn64};
 }
-template <>
-Coef<float> coef_of<float>(const reff_pdn_t* p) {
-  Coef<float> c{p->d32, p->dinv32, p->cE32, p->cN32, p->slot, p->up32, p->dn32,
-                p->n,   p->nx,     p->plane};
-  return c;
+Coef<float> coef32(const CoefSet& cs) {
+  return Coef<float>{cs.d32, cs.dinv32, cs.cE32, cs.cN32, cs.slot, cs.up32, cs.dn32};
+}
+
+// The handle's copy of its description, as a reff_pdn_desc view.
+reff_pdn_desc desc_view(const reff_pdn_t* p) {
+  reff_pdn_desc d;
+  d.n_tiers = p->nt;
+  d.nx = p->nx;
+  d.ny = p->ny;
+  d.gx = p->gx.data();
+  d.gy = p->gy.data();
+  d.n_tsv = (int32_t)(p->tsv_xy.size() / 2);
+  d.tsv_xy = p->tsv_xy.data();
+  d.tsv_g = p->tsv_g.data();
+  d.n_pads = (int32_t)(p->pad_xy.size() / 2);
+  d.pad_xy = p->pad_xy.data();
+  return d;
+}
+
+// Build and upload one coefficient set for several stacks (a batch), each
+// with its own grounded node list, concatenated in order; cbase[i] receives
+// the first coefficient index of stack i.
+reff_status make_coefset_multi(const std::vector<const reff_pdn_desc*>& ds,
+                               const std::vector<std::vector<int64_t>>& gnds, CoefSet& cs,
+                               std::vector<int64_t>& cbase, std::vector<void*>& extra) {
+  HostCoef h;
+  cbase.clear();
+  for (size_t i = 0; i < ds.size(); ++i) {
+    HostCoef hi;
+    reff_status s = build_host(ds[i], gnds[i], hi);
+    if (s != REFF_OK) return s;
+    cbase.push_back((int64_t)h.d.size());
+    const int32_t slot0 = (int32_t)h.up.size();
+    for (int32_t& sl : hi.slot)
+      if (sl >= 0) sl += slot0;
+    h.d.insert(h.d.end(), hi.d.begin(), hi.d.end());
+    h.cE.insert(h.cE.end(), hi.cE.begin(), hi.cE.end());
+    h.cN.insert(h.cN.end(), hi.cN.begin(), hi.cN.end());
+    h.up.insert(h.up.end(), hi.up.begin(), hi.up.end());
+    h.dn.insert(h.dn.end(), hi.dn.begin(), hi.dn.end());
+    h.slot.insert(h.slot.end(), hi.slot.begin(), hi.slot.end());
+    h.is_pad.insert(h.is_pad.end(), hi.is_pad.begin(), hi.is_pad.end());
+  }
+  std::vector<double> dinv(h.d.size());
+  for (size_t i = 0; i < h.d.size(); ++i) dinv[i] = 1.0 / h.d[i];
+  reff_status rs = REFF_OK;
+  auto& owned = extra;
+  auto upload_owned = [&](const std::vector<double>& src, double** d64, float** d32) {
+    if (rs != REFF_OK) return;
+    rs = upload<double>(src, d64, owned);
+    if (rs == REFF_OK) rs = upload<float>(src, d32, owned);
+  };
+  upload_owned(h.d, &cs.d64, &cs.d32);
+  upload_owned(dinv, &cs.dinv64, &cs.dinv32);
+  upload_owned(h.cE, &cs.cE64, &cs.cE32);
+  upload_owned(h.cN, &cs.cN64, &cs.cN32);
+  upload_owned(h.up, &cs.up64, &cs.up32);
+  upload_owned(h.dn, &cs.dn64, &cs.dn32);
+  if (rs != REFF_OK) return rs;
+  HIPCHK(hipMalloc((void**)&cs.slot, std::max<size_t>(1, h.slot.size()) * sizeof(int32_t)));
+  owned.push_back(cs.slot);
+  HIPCHK(hipMemcpy(cs.slot, h.slot.data(), h.slot.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  cs.grounded = h.is_pad;
+  cs.n_free = 0;
+  for (uint8_t f : h.is_pad) cs.n_free += f ? 0 : 1;
+  cs.n_slots = (int64_t)h.up.size();
+  cs.ready = true;
+  return REFF_OK;
+}
+
+// One stack of a handle.
+reff_status make_coefset(reff_pdn_t* p, const std::vector<int64_t>& gnd, CoefSet& cs) {
+  const reff_pdn_desc d = desc_view(p);
+  std::vector<int64_t> cbase;
+  return make_coefset_multi({&d}, {gnd}, cs, cbase, p->extra);
 }
 
 struct Opts {
@@ -259,74 +325,119 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
   return REFF_OK;
 }
 
-// Pinned host staging for the per-block small transfers.
-struct Pinned {
-  int64_t* tgt = nullptr;
-  int64_t* pos = nullptr;
-  int32_t* flags = nullptr;
-  double* est = nullptr;
-  ~Pinned() {
-    if (tgt) (void)hipHostFree(tgt);
-    if (pos) (void)hipHostFree(pos);
-    if (flags) (void)hipHostFree(flags);
-    if (est) (void)hipHostFree(est);
+// ---------------------------------------------------------------- solver core
+// A stack as seen by the block solver.
+struct StackInfo {
+  int64_t cbase, n, plane;
+  int32_t nx;
+};
+
+// One block of up to S unit-current columns on one stack: local target node
+// ids and the output positions of their results.
+struct BlockJob {
+  int32_t stack = 0;
+  int ncol = 0;
+  int64_t tgt[S];
+  int64_t pos[S];
+};
+
+struct BlockResult {
+  int32_t iters = 0;
+  int32_t ir = 0;
+  bool conv = false;
+  double est_max = 0.0;
+  int64_t n_unconv = 0;
+};
+
+}  // namespace
+
+void reff::Workspace::release() {
+  for (DevBuf* b : {&Y, &P, &Q, &R, &D, &X, &part, &W, &small, &state, &tgt, &pos, &plans, &units,
+                    &uid, &act, &out, &xs, &rows, &map, &flags})
+    if (b->p) {
+      (void)hipFree(b->p);
+      b->p = nullptr;
+      b->bytes = 0;
+    }
+}
+
+namespace {
+
+// Pinned host staging (freed on scope exit).
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  reff_status ensure(size_t b) {
+    if (bytes >= b && p) return REFF_OK;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    HIPCHK(hipHostMalloc(&p, std::max<size_t>(b, 64)));
+    bytes = std::max<size_t>(b, 64);
+    return REFF_OK;
   }
 };
 
-// Solve the unit-current columns for the free nodes `cols` (distinct, all
-// free), writing R estimates of column i into res_dev[i].
-reff_status solve_columns(reff_pdn_t* p, const std::vector<int64_t>& cols, double* res_dev,
-                          const Opts& o, reff_solve_stats* st) {
-  const int64_t n = p->n;
-  const bool fp32 = o.mixed;
-  const size_t tsz = fp32 ? sizeof(float) : sizeof(double);
-  const size_t vec = (size_t)n * S * tsz;
-  const int G = grid_for(n);
-  reff_status rs;
-  if ((rs = ensure(p->ws_Y, vec)) != REFF_OK) return rs;
-  if ((rs = ensure(p->ws_P, vec)) != REFF_OK) return rs;
-  if ((rs = ensure(p->ws_Q, vec)) != REFF_OK) return rs;
-  if ((rs = ensure(p->ws_R, vec)) != REFF_OK) return rs;
-  if (o.mixed) {
-    if ((rs = ensure(p->ws_D, vec)) != REFF_OK) return rs;
-    if ((rs = ensure(p->ws_X, (size_t)n * S * sizeof(double))) != REFF_OK) return rs;
+constexpr int TARGET_UNITS = 1024;  // 4 workgroups of 512 threads per CU
+
+// Split the solve blocks of a group into work units: each block's row range
+// is cut into chunk-aligned pieces, about TARGET_UNITS in total, in
+// proportion to the block sizes.
+void make_units(const std::vector<PlanDesc>& in, std::vector<PlanDesc>& plans,
+                std::vector<Unit>& units) {
+  int64_t rows = 0;
+  for (const PlanDesc& p : in) rows += p.n;
+  plans = in;
+  units.clear();
+  for (size_t i = 0; i < plans.size(); ++i) {
+    PlanDesc& p = plans[i];
+    const int64_t nch = (p.n + CH - 1) / CH;
+    int64_t k = (TARGET_UNITS * p.n + rows - 1) / std::max<int64_t>(rows, 1);
+    k = std::max<int64_t>(1, std::min<int64_t>(k, nch));
+    const int64_t cpu = (nch + k - 1) / k;  // chunks per unit
+    p.unit_begin = (int32_t)units.size();
+    for (int64_t c0 = 0; c0 < nch; c0 += cpu) {
+      Unit u;
+      u.begin = p.vbase + c0 * CH;
+      u.end = p.vbase + std::min<int64_t>(p.n, (c0 + cpu) * CH);
+      u.plan = (int32_t)i;
+      u.pad_ = 0;
+      units.push_back(u);
+    }
+    p.unit_end = (int32_t)units.size();
   }
-  if ((rs = ensure(p->ws_part, (size_t)G * 4 * S * S * sizeof(double))) != REFF_OK) return rs;
-  if ((rs = ensure(p->ws_W, 4 * S * S * sizeof(double))) != REFF_OK) return rs;
-  if ((rs = ensure(p->ws_small, 4 * S * S * sizeof(double))) != REFF_OK) return rs;
-  if ((rs = ensure(p->ws_state, sizeof(BlockState))) != REFF_OK) return rs;
-  if ((rs = ensure(p->ws_tgt, 2 * S * sizeof(int64_t))) != REFF_OK) return rs;
+}
 
-  SolveBuffers b;
-  b.Y = p->ws_Y.p;
-  b.P = p->ws_P.p;
-  b.Q = p->ws_Q.p;
-  b.R = p->ws_R.p;
-  b.D = o.mixed ? p->ws_D.p : nullptr;
-  b.X = o.mixed ? (double*)p->ws_X.p : nullptr;
-  b.part = (double*)p->ws_part.p;
-  b.W = (double*)p->ws_W.p;
-  b.winv = (double*)p->ws_small.p;
-  b.alpha = (double*)p->ws_small.p + S * S;
-  b.delta = (double*)p->ws_small.p + 2 * S * S;
-  b.Tm = (double*)p->ws_small.p + 3 * S * S;
-  b.state = (BlockState*)p->ws_state.p;
-  b.tgt = (int64_t*)p->ws_tgt.p;
-  int64_t* pos_dev = (int64_t*)p->ws_tgt.p + S;
+__global__ void k_gather_flags(const BlockState* __restrict__ st, int nb, int32_t* __restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
+    out[2 * i] = st[i].it;
+    out[2 * i + 1] = st[i].all_conv;
+  }
+}
 
-  Coef<double> c64 = coef_of<double>(p);
-  Coef<float> c32 = coef_of<float>(p);
+// Solve every job (block of unit-current columns) with the block PCG,
+// several blocks per launch (as many as fit the row budget), writing result
+// j of block b to res_dev[b.pos[j]].  With xstore, the float64 solution of
+// job i is copied to xstore + xoff[i] (stack n x S).
+reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<StackInfo>& stacks,
+                       const std::vector<BlockJob>& jobs, double* res_dev, const Opts& o,
+                       std::vector<BlockResult>& br, reff_solve_stats* st,
+                       double* xstore = nullptr, const std::vector<int64_t>* xoff = nullptr) {
+  br.assign(jobs.size(), BlockResult());
+  if (jobs.empty()) return REFF_OK;
+  const bool fp32 = o.mixed;
+  const bool with_d = o.mixed || xstore != nullptr;
+  const size_t tsz = fp32 ? sizeof(float) : sizeof(double);
+  const size_t row_bytes = S * (tsz * (5 + (with_d ? 1 : 0)) + (o.mixed ? sizeof(double) : 0));
+  const int64_t budget_rows = std::max<int64_t>(1, (int64_t)(48e9 / (double)row_bytes));
+  const Coef<double> c64 = coef64(cs);
+  const Coef<float> c32 = coef32(cs);
   const void* coef = fp32 ? (const void*)&c32 : (const void*)&c64;
-
-  Pinned pin;
-  HIPCHK(hipHostMalloc((void**)&pin.tgt, S * sizeof(int64_t)));
-  HIPCHK(hipHostMalloc((void**)&pin.pos, S * sizeof(int64_t)));
-  HIPCHK(hipHostMalloc((void**)&pin.flags, 4 * sizeof(int32_t)));
-  HIPCHK(hipHostMalloc((void**)&pin.est, S * sizeof(double)));
-
   const int poll = 8;
-  // Optional per-kernel timing: one set of 6 events per iteration of a poll
-  // chunk, read back after the chunk's synchronisation.
+
   struct EventPool {
     std::vector<hipEvent_t> ev;
     ~EventPool() {
@@ -337,46 +448,129 @@ reff_status solve_columns(reff_pdn_t* p, const std::vector<int64_t>& cols, doubl
     evp.ev.resize(6 * poll);
     for (auto& e : evp.ev) HIPCHK(hipEventCreate(&e));
   }
-  const int64_t nblk = ((int64_t)cols.size() + S - 1) / S;
-  // Columns are dealt to blocks in a fixed pseudo-random order: right-hand
-  // sides that sit next to each other span nearly the same block Krylov
-  // space, while spread-out ones give every block independent directions.
-  std::vector<int64_t> order(cols.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int64_t)i;
-  std::mt19937_64 rng(0x9e3779b97f4a7c15ull);
-  std::shuffle(order.begin(), order.end(), rng);
+  PinnedBuf pin_tab, pin_flags;
   bool any_unconv = false;
-  for (int64_t blk = 0; blk < nblk; ++blk) {
-    int ncol = 0;
-    for (int k = 0; k < S; ++k) {
-      const int64_t j = blk * S + k;
-      if (j < (int64_t)cols.size()) {
-        const int64_t i = order[(size_t)j];
-        pin.tgt[k] = cols[(size_t)i];
-        pin.pos[k] = i;
-        ++ncol;
-      } else {
-        pin.tgt[k] = -1;
-        pin.pos[k] = -1;
-      }
+  size_t j0 = 0;
+  while (j0 < jobs.size()) {
+    // ---- group of jobs within the row budget
+    size_t j1 = j0;
+    int64_t rows = 0;
+    std::vector<PlanDesc> pin;
+    while (j1 < jobs.size()) {
+      const StackInfo& sk = stacks[(size_t)jobs[j1].stack];
+      if (j1 > j0 && rows + sk.n > budget_rows) break;
+      PlanDesc pd{};
+      pd.cbase = sk.cbase;
+      pd.vbase = rows;
+      pd.n = sk.n;
+      pd.plane = sk.plane;
+      pd.nx = sk.nx;
+      pin.push_back(pd);
+      rows += sk.n;
+      ++j1;
     }
-    HIPCHK(hipMemcpyAsync(b.tgt, pin.tgt, S * sizeof(int64_t), hipMemcpyHostToDevice, o.stream));
-    HIPCHK(hipMemcpyAsync(pos_dev, pin.pos, S * sizeof(int64_t), hipMemcpyHostToDevice, o.stream));
-    HIPCHK(launch_init_block(fp32, o.indep, coef, b, o.stream));
-    if (o.mixed) HIPCHK(launch_zero_x(b.X, n * S, o.stream));
+    const int nb = (int)(j1 - j0);
+    std::vector<PlanDesc> plans;
+    std::vector<Unit> units;
+    make_units(pin, plans, units);
+    const int nu = (int)units.size();
+    // ---- buffers
+    reff_status rs;
+    const size_t vec = (size_t)rows * S * tsz;
+    if ((rs = ensure(ws.Y, vec)) != REFF_OK) return rs;
+    if ((rs = ensure(ws.P, vec)) != REFF_OK) return rs;
+    if ((rs = ensure(ws.Q, vec)) != REFF_OK) return rs;
+    if ((rs = ensure(ws.R, vec)) != REFF_OK) return rs;
+    if (with_d && (rs = ensure(ws.D, vec)) != REFF_OK) return rs;
+    if (o.mixed && (rs = ensure(ws.X, (size_t)rows * S * sizeof(double))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.part, (size_t)nu * NGRAM * S * S * sizeof(double))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.W, (size_t)nb * NGRAM * S * S * sizeof(double))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.small, (size_t)nb * 4 * S * S * sizeof(double))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.state, (size_t)nb * sizeof(BlockState))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.tgt, (size_t)nb * S * sizeof(int64_t))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.pos, (size_t)nb * S * sizeof(int64_t))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.plans, (size_t)nb * sizeof(PlanDesc))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.units, (size_t)nu * sizeof(Unit))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.uid, (size_t)nu * sizeof(int32_t))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.act, (size_t)nb * sizeof(int32_t))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.flags, (size_t)nb * 2 * sizeof(int32_t))) != REFF_OK) return rs;
+    // ---- tables (one pinned staging area, uploaded asynchronously)
+    const size_t tab_bytes = nb * sizeof(PlanDesc) + nu * sizeof(Unit) + nb * S * 16 +
+                             (nu + nb) * sizeof(int32_t) * 2 + 256;
+    if ((rs = pin_tab.ensure(tab_bytes)) != REFF_OK) return rs;
+    if ((rs = pin_flags.ensure((size_t)nb * 2 * sizeof(int32_t))) != REFF_OK) return rs;
+    char* hp = (char*)pin_tab.p;
+    PlanDesc* h_plans = (PlanDesc*)hp;
+    Unit* h_units = (Unit*)(h_plans + nb);
+    int64_t* h_tgt = (int64_t*)(h_units + nu);
+    int64_t* h_pos = h_tgt + (size_t)nb * S;
+    int32_t* h_uid = (int32_t*)(h_pos + (size_t)nb * S);
+    int32_t* h_act = h_uid + nu;
+    std::memcpy(h_plans, plans.data(), nb * sizeof(PlanDesc));
+    std::memcpy(h_units, units.data(), nu * sizeof(Unit));
+    for (int i = 0; i < nb; ++i) {
+      const BlockJob& jb = jobs[j0 + (size_t)i];
+      for (int k = 0; k < S; ++k) {
+        h_tgt[(size_t)i * S + k] = k < jb.ncol ? jb.tgt[k] : -1;
+        h_pos[(size_t)i * S + k] = k < jb.ncol ? jb.pos[k] : -1;
+      }
+      h_act[i] = i;
+    }
+    for (int u = 0; u < nu; ++u) h_uid[u] = u;
+    HIPCHK(hipMemcpyAsync(ws.plans.p, h_plans, nb * sizeof(PlanDesc), hipMemcpyHostToDevice, o.stream));
+    HIPCHK(hipMemcpyAsync(ws.units.p, h_units, nu * sizeof(Unit), hipMemcpyHostToDevice, o.stream));
+    HIPCHK(hipMemcpyAsync(ws.tgt.p, h_tgt, (size_t)nb * S * sizeof(int64_t), hipMemcpyHostToDevice, o.stream));
+    HIPCHK(hipMemcpyAsync(ws.pos.p, h_pos, (size_t)nb * S * sizeof(int64_t), hipMemcpyHostToDevice, o.stream));
+    HIPCHK(hipMemcpyAsync(ws.uid.p, h_uid, nu * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
+    HIPCHK(hipMemcpyAsync(ws.act.p, h_act, nb * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
+
+    SolveBuffers b;
+    b.Y = ws.Y.p;
+    b.P = ws.P.p;
+    b.Q = ws.Q.p;
+    b.R = ws.R.p;
+    b.D = with_d ? ws.D.p : nullptr;
+    b.X = o.mixed ? (double*)ws.X.p : nullptr;
+    b.part = (double*)ws.part.p;
+    b.W = (double*)ws.W.p;
+    b.winv = (double*)ws.small.p;
+    b.alpha = (double*)ws.small.p + (size_t)nb * S * S;
+    b.delta = (double*)ws.small.p + (size_t)2 * nb * S * S;
+    b.Tm = (double*)ws.small.p + (size_t)3 * nb * S * S;
+    b.state = (BlockState*)ws.state.p;
+    b.tgt = (int64_t*)ws.tgt.p;
+    b.pos = (int64_t*)ws.pos.p;
+    b.work.plans = (const PlanDesc*)ws.plans.p;
+    b.work.units = (const Unit*)ws.units.p;
+    b.work.uid = (const int32_t*)ws.uid.p;
+    b.act = (const int32_t*)ws.act.p;
+    b.n_act = nb;
+    b.n_units = nu;
+    b.rows = rows;
+
+    HIPCHK(launch_init_blocks(fp32, o.indep, coef, b, o.stream));
+    if (with_d && !fp32) HIPCHK(launch_zero_x((double*)b.D, rows * S, o.stream));
+    if (o.mixed) HIPCHK(launch_zero_x(b.X, rows * S, o.stream));
+
+    std::vector<char> done((size_t)nb, 0);     // converged in the current step
+    std::vector<int32_t> iters((size_t)nb, 0);
+    std::vector<int32_t> irs((size_t)nb, 0);
+    std::vector<int> active(nb);
+    for (int i = 0; i < nb; ++i) active[(size_t)i] = i;
     int ir = 0;
-    int it_block = 0;
-    bool conv = false;
     while (true) {
+      // ---- inner block-PCG iterations over the active blocks
       int it = 0;
-      conv = false;
-      while (it < o.max_iters) {
+      while (it < o.max_iters && !active.empty()) {
         const int k = std::min(poll, o.max_iters - it);
         for (int i = 0; i < k; ++i)
-          HIPCHK(launch_iteration(fp32, o.indep, o.mixed, coef, b, n, o.tol, o.stream,
+          HIPCHK(launch_iteration(fp32, o.indep, with_d, coef, b, o.tol, o.stream,
                                   o.timing ? &evp.ev[6 * i] : nullptr));
         it += k;
-        HIPCHK(hipMemcpyAsync(pin.flags, &b.state->it, 2 * sizeof(int32_t),
+        hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(256), 0, o.stream, b.state, nb,
+                           (int32_t*)ws.flags.p);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(pin_flags.p, ws.flags.p, (size_t)nb * 2 * sizeof(int32_t),
                               hipMemcpyDeviceToHost, o.stream));
         HIPCHK(hipStreamSynchronize(o.stream));
         if (o.timing && st) {
@@ -388,43 +582,169 @@ reff_status solve_columns(reff_pdn_t* p, const std::vector<int64_t>& cols, doubl
               st->kernel_launches[kk] += 1;
             }
         }
-        if (pin.flags[1]) {
-          conv = true;
-          it = pin.flags[0];
-          break;
+        // flags of every block (gathered into a small device array)
+        const int32_t* fl = (const int32_t*)pin_flags.p;
+        std::vector<int> still;
+        for (int bi : active) {
+          iters[(size_t)bi] += k;
+          if (fl[(size_t)bi * 2 + 1]) {
+            done[(size_t)bi] = 1;
+          } else {
+            still.push_back(bi);
+          }
+        }
+        if (still.size() != active.size() && !still.empty()) {
+          // Compact: later launches cover only the unconverged blocks.
+          active = still;
+          int na = 0, nuu = 0;
+          for (int bi : active) {
+            h_act[na++] = bi;
+            for (int u = plans[(size_t)bi].unit_begin; u < plans[(size_t)bi].unit_end; ++u)
+              h_uid[nuu++] = u;
+          }
+          HIPCHK(hipMemcpyAsync(ws.uid.p, h_uid, nuu * sizeof(int32_t), hipMemcpyHostToDevice,
+                                o.stream));
+          HIPCHK(hipMemcpyAsync(ws.act.p, h_act, na * sizeof(int32_t), hipMemcpyHostToDevice,
+                                o.stream));
+          b.n_act = na;
+          b.n_units = nuu;
+        } else {
+          active = still;
         }
       }
-      it_block += it;
       ++ir;
+      for (int i = 0; i < nb; ++i) irs[(size_t)i] = ir;
+      // ---- all blocks of the group again for the float64 step / results
+      for (int i = 0; i < nb; ++i) h_act[i] = i;
+      for (int u = 0; u < nu; ++u) h_uid[u] = u;
+      HIPCHK(hipMemcpyAsync(ws.uid.p, h_uid, nu * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
+      HIPCHK(hipMemcpyAsync(ws.act.p, h_act, nb * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
+      b.n_act = nb;
+      b.n_units = nu;
       if (!o.mixed) break;
-      HIPCHK(launch_mixed_residual(c64, c32, b, res_dev, pos_dev, o.stream));
+      HIPCHK(launch_mixed_residual(c64, c32, b, res_dev, o.stream));
       // One float32 solve carried to the tolerance plus the float64
-      // variational correction is enough unless the inner solve stalled or
-      // the tolerance is below what float32 iterates can resolve.
-      const bool need_more = !conv || o.tol < 2e-6;
+      // variational correction suffices unless the inner solve stalled or
+      // the tolerance is below what float32 iterates resolve.
+      bool need_more = o.tol < 2e-6;
+      for (int i = 0; i < nb; ++i) need_more = need_more || !done[(size_t)i];
       if (!need_more || ir >= o.max_ir) break;
       HIPCHK(launch_restart(c32, b, o.indep, o.stream));
+      std::fill(done.begin(), done.end(), 0);
+      active.resize(nb);
+      for (int i = 0; i < nb; ++i) active[(size_t)i] = i;
     }
-    if (!o.mixed) HIPCHK(launch_finalize_plain(b, res_dev, pos_dev, o.stream));
-    HIPCHK(hipMemcpyAsync(pin.est, b.state->est_rel, S * sizeof(double), hipMemcpyDeviceToHost,
-                          o.stream));
+    if (!o.mixed) HIPCHK(launch_finalize_plain(b, res_dev, o.stream));
+    if (xstore)
+      for (int i = 0; i < nb; ++i)
+        HIPCHK(hipMemcpyAsync(xstore + (*xoff)[j0 + (size_t)i],
+                              o.mixed ? (const void*)(b.X + plans[(size_t)i].vbase * S)
+                                      : (const void*)((double*)b.D + plans[(size_t)i].vbase * S),
+                              (size_t)plans[(size_t)i].n * S * sizeof(double),
+                              hipMemcpyDeviceToDevice, o.stream));
+    std::vector<BlockState> hs((size_t)nb);
+    HIPCHK(hipMemcpyAsync(hs.data(), b.state, (size_t)nb * sizeof(BlockState),
+                          hipMemcpyDeviceToHost, o.stream));
     HIPCHK(hipStreamSynchronize(o.stream));
-    if (st) {
-      st->iters_max = std::max(st->iters_max, (int32_t)it_block);
-      st->iters_total += it_block;
-      st->ir_steps = std::max(st->ir_steps, (int32_t)ir);
-      for (int k = 0; k < ncol; ++k) {
-        if (std::isfinite(pin.est[k])) st->est_max_rel_err = std::max(st->est_max_rel_err, pin.est[k]);
+    for (int i = 0; i < nb; ++i) {
+      BlockResult& r = br[j0 + (size_t)i];
+      const BlockJob& jb = jobs[j0 + (size_t)i];
+      r.iters = iters[(size_t)i];
+      r.ir = irs[(size_t)i];
+      r.conv = done[(size_t)i] != 0;
+      for (int k = 0; k < jb.ncol; ++k) {
+        const double e = hs[(size_t)i].est_rel[k];
+        if (std::isfinite(e)) r.est_max = std::max(r.est_max, e);
+        if (!r.conv && !(e <= CONV_SAFETY * o.tol)) r.n_unconv++;
       }
-      if (!conv) {
-        for (int k = 0; k < ncol; ++k)
-          if (!(pin.est[k] <= CONV_SAFETY * o.tol)) st->n_unconverged++;
-      }
+      if (!r.conv) any_unconv = true;
     }
-    if (!conv) any_unconv = true;
+    j0 = j1;
   }
   return any_unconv ? fail(REFF_ERR_NO_CONVERGENCE, "max_iters reached before the tolerance")
                     : REFF_OK;
+}
+
+void add_stats(reff_solve_stats* st, const std::vector<BlockResult>& br, size_t b0, size_t b1) {
+  if (!st) return;
+  for (size_t i = b0; i < b1; ++i) {
+    st->iters_max = std::max(st->iters_max, br[i].iters);
+    st->iters_total += br[i].iters;
+    st->ir_steps = std::max(st->ir_steps, br[i].ir);
+    st->est_max_rel_err = std::max(st->est_max_rel_err, br[i].est_max);
+    st->n_unconverged += br[i].n_unconv;
+  }
+}
+
+// Deal the free columns `cols` (distinct ids local to stack `stack`) to
+// blocks of S in a fixed pseudo-random order: right-hand sides that sit next
+// to each other span nearly the same block Krylov space, while spread-out
+// ones give every block independent directions.  Column i's result goes to
+// position pos0 + i.
+void deal_blocks(const std::vector<int64_t>& cols, int32_t stack, int64_t pos0,
+                 std::vector<BlockJob>& jobs) {
+  std::vector<int64_t> order(cols.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int64_t)i;
+  std::mt19937_64 rng(0x9e3779b97f4a7c15ull);
+  std::shuffle(order.begin(), order.end(), rng);
+  for (size_t j = 0; j < order.size(); j += S) {
+    BlockJob jb;
+    jb.stack = stack;
+    jb.ncol = (int)std::min<size_t>(S, order.size() - j);
+    for (int k = 0; k < jb.ncol; ++k) {
+      const int64_t i = order[j + (size_t)k];
+      jb.tgt[k] = cols[(size_t)i];
+      jb.pos[k] = pos0 + i;
+    }
+    jobs.push_back(jb);
+  }
+}
+
+// Device work tables for a single plan covering a whole stack (used by the
+// pair cross terms): returns buffers with part/W/act/work filled.
+reff_status single_work(Workspace& ws, const StackInfo& sk, SolveBuffers& b, hipStream_t stream,
+                        PinnedBuf& pin) {
+  std::vector<PlanDesc> in(1), plans;
+  in[0] = PlanDesc{};
+  in[0].cbase = sk.cbase;
+  in[0].vbase = 0;
+  in[0].n = sk.n;
+  in[0].plane = sk.plane;
+  in[0].nx = sk.nx;
+  std::vector<Unit> units;
+  make_units(in, plans, units);
+  const int nu = (int)units.size();
+  reff_status rs;
+  if ((rs = ensure(ws.part, (size_t)nu * NGRAM * S * S * sizeof(double))) != REFF_OK) return rs;
+  if ((rs = ensure(ws.W, (size_t)NGRAM * S * S * sizeof(double))) != REFF_OK) return rs;
+  if ((rs = ensure(ws.plans, sizeof(PlanDesc))) != REFF_OK) return rs;
+  if ((rs = ensure(ws.units, (size_t)nu * sizeof(Unit))) != REFF_OK) return rs;
+  if ((rs = ensure(ws.uid, (size_t)nu * sizeof(int32_t))) != REFF_OK) return rs;
+  if ((rs = ensure(ws.act, 2 * sizeof(int32_t))) != REFF_OK) return rs;
+  if ((rs = pin.ensure(sizeof(PlanDesc) + nu * (sizeof(Unit) + sizeof(int32_t)) + 16)) != REFF_OK)
+    return rs;
+  char* hp = (char*)pin.p;
+  std::memcpy(hp, plans.data(), sizeof(PlanDesc));
+  std::memcpy(hp + sizeof(PlanDesc), units.data(), nu * sizeof(Unit));
+  int32_t* uid = (int32_t*)(hp + sizeof(PlanDesc) + nu * sizeof(Unit));
+  for (int u = 0; u < nu; ++u) uid[u] = u;
+  uid[nu] = 0;
+  HIPCHK(hipMemcpyAsync(ws.plans.p, hp, sizeof(PlanDesc), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(ws.units.p, hp + sizeof(PlanDesc), nu * sizeof(Unit), hipMemcpyHostToDevice,
+                        stream));
+  HIPCHK(hipMemcpyAsync(ws.uid.p, uid, nu * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(ws.act.p, uid + nu, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  b = SolveBuffers{};
+  b.part = (double*)ws.part.p;
+  b.W = (double*)ws.W.p;
+  b.work.plans = (const PlanDesc*)ws.plans.p;
+  b.work.units = (const Unit*)ws.units.p;
+  b.work.uid = (const int32_t*)ws.uid.p;
+  b.act = (const int32_t*)ws.act.p;
+  b.n_act = 1;
+  b.n_units = nu;
+  b.rows = sk.n;
+  return REFF_OK;
 }
 
 }  // namespace
@@ -454,9 +774,15 @@ reff_status reff_build_pdn(const reff_pdn_desc* d, int32_t device, reff_pdn* out
   reff_status s = validate_desc(d);
   if (s != REFF_OK) return s;
   if (device < 0) return fail(REFF_ERR_INVALID_ARG, "device < 0");
-  HostCoef h;
-  s = build_host(d, h);
-  if (s != REFF_OK) return s;
+  std::vector<int64_t> pads;
+  for (int32_t j = 0; j < d->n_pads; ++j)
+    pads.push_back((int64_t)d->pad_xy[2 * j + 1] * d->nx + d->pad_xy[2 * j]);
+  {
+    // Connectivity check on the host, before any device work.
+    HostCoef h;
+    s = build_host(d, pads, h);
+    if (s != REFF_OK) return s;
+  }
   int ndev = 0;
   HIPCHK(hipGetDeviceCount(&ndev));
   if (device >= ndev) return fail(REFF_ERR_INVALID_ARG, "no such device");
@@ -469,36 +795,19 @@ reff_status reff_build_pdn(const reff_pdn_desc* d, int32_t device, reff_pdn* out
   p->ny = d->ny;
   p->plane = (int64_t)d->nx * d->ny;
   p->n = p->plane * d->n_tiers;
-  p->n_slots = (int64_t)h.up.size();
-  p->is_pad = h.is_pad;
-  p->n_free = 0;
-  for (uint8_t f : h.is_pad) p->n_free += f ? 0 : 1;
-  std::vector<double> dinv(h.d.size());
-  for (size_t i = 0; i < h.d.size(); ++i) dinv[i] = 1.0 / h.d[i];
-  reff_status rs = REFF_OK;
-  auto up = [&](const std::vector<double>& src, double** d64, float** d32) {
-    if (rs != REFF_OK) return;
-    rs = upload<double>(src, d64, p->extra);
-    if (rs == REFF_OK) rs = upload<float>(src, d32, p->extra);
-  };
-  up(h.d, &p->d64, &p->d32);
-  up(dinv, &p->dinv64, &p->dinv32);
-  up(h.cE, &p->cE64, &p->cE32);
-  up(h.cN, &p->cN64, &p->cN32);
-  up(h.up, &p->up64, &p->up32);
-  up(h.dn, &p->dn64, &p->dn32);
-  if (rs == REFF_OK) {
-    hipError_t e = hipMalloc((void**)&p->slot, h.slot.size() * sizeof(int32_t));
-    if (e == hipSuccess) {
-      p->extra.push_back(p->slot);
-      e = hipMemcpy(p->slot, h.slot.data(), h.slot.size() * sizeof(int32_t),
-                    hipMemcpyHostToDevice);
-    }
-    if (e != hipSuccess) rs = fail(REFF_ERR_DEVICE, std::string("slot upload: ") + hipGetErrorString(e));
-  }
-  if (rs != REFF_OK) {
+  const int64_t ngx = (int64_t)d->n_tiers * d->ny * (d->nx - 1);
+  const int64_t ngy = (int64_t)d->n_tiers * (d->ny - 1) * d->nx;
+  if (ngx > 0) p->gx.assign(d->gx, d->gx + ngx);
+  if (ngy > 0) p->gy.assign(d->gy, d->gy + ngy);
+  if (d->n_tsv > 0) p->tsv_xy.assign(d->tsv_xy, d->tsv_xy + 2 * (int64_t)d->n_tsv);
+  if (d->n_tiers > 1 && d->n_tsv > 0)
+    p->tsv_g.assign(d->tsv_g, d->tsv_g + (int64_t)d->n_tsv * (d->n_tiers - 1));
+  p->pad_xy.assign(d->pad_xy, d->pad_xy + 2 * (int64_t)d->n_pads);
+  s = make_coefset(p, pads, p->gnd);
+  if (s != REFF_OK) {
+    const std::string msg = g_err;
     reff_free_pdn(p);
-    return rs;
+    return fail(s, msg);
   }
   *out = p;
   return REFF_OK;
@@ -508,10 +817,61 @@ void reff_free_pdn(reff_pdn p) {
   if (!p) return;
   (void)hipSetDevice(p->device);
   for (void* q : p->extra) (void)hipFree(q);
-  for (DevBuf* b : {&p->ws_Y, &p->ws_P, &p->ws_Q, &p->ws_R, &p->ws_D, &p->ws_X, &p->ws_part, &p->ws_W,
-                    &p->ws_small, &p->ws_state, &p->ws_tgt, &p->ws_out})
-    if (b->p) (void)hipFree(b->p);
+  p->ws.release();
   delete p;
+}
+
+// Results of the distinct free nodes `cols` -> caller order (map[i] = index
+// into cols, -1 for grounded nodes), host or device output.
+static reff_status write_out(Workspace& ws, const double* res_dev, int64_t ncols,
+                             const std::vector<int64_t>& map, double* R_out, bool out_dev,
+                             hipStream_t stream) {
+  const int64_t count = (int64_t)map.size();
+  if (count == 0) return REFF_OK;
+  if (out_dev) {
+    reff_status rs = ensure(ws.map, (size_t)count * sizeof(int64_t));
+    if (rs != REFF_OK) return rs;
+    HIPCHK(hipMemcpyAsync(ws.map.p, map.data(), (size_t)count * sizeof(int64_t),
+                          hipMemcpyHostToDevice, stream));
+    HIPCHK(launch_gather_out(res_dev, (const int64_t*)ws.map.p, R_out, count, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+  } else {
+    std::vector<double> res((size_t)ncols);
+    if (ncols > 0)
+      HIPCHK(hipMemcpyAsync(res.data(), res_dev, (size_t)ncols * sizeof(double),
+                            hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int64_t i = 0; i < count; ++i)
+      R_out[i] = map[(size_t)i] >= 0 ? res[(size_t)map[(size_t)i]] : 0.0;
+  }
+  return REFF_OK;
+}
+
+// Distinct free ids of a request (sorted) and the caller-order map.
+static reff_status columns_of(const int64_t* nodes, int64_t count, int64_t n,
+                              const std::vector<uint8_t>& grounded, std::vector<int64_t>& cols,
+                              std::vector<int64_t>& map) {
+  cols.resize((size_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t v = nodes ? nodes[i] : i;
+    if (v < 0 || v >= n)
+      return fail(REFF_ERR_INVALID_ARG, "node id " + std::to_string(v) + " out of range");
+    cols[(size_t)i] = v;
+  }
+  std::vector<int64_t> ids = cols;
+  std::sort(cols.begin(), cols.end());
+  cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+  cols.erase(std::remove_if(cols.begin(), cols.end(),
+                            [&](int64_t v) { return grounded[(size_t)v] != 0; }),
+             cols.end());
+  map.resize((size_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t v = ids[(size_t)i];
+    map[(size_t)i] = grounded[(size_t)v]
+                         ? -1
+                         : (int64_t)(std::lower_bound(cols.begin(), cols.end(), v) - cols.begin());
+  }
+  return REFF_OK;
 }
 
 reff_status reff_solve_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, double* R_out,
@@ -522,71 +882,33 @@ reff_status reff_solve_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, d
   Opts o;
   reff_status s = parse_opts(opts, o);
   if (s != REFF_OK) return s;
-  const int64_t count = nodes ? n_nodes : p->n;
   if (nodes && n_nodes < 0) return fail(REFF_ERR_INVALID_ARG, "n_nodes < 0");
+  const int64_t count = nodes ? n_nodes : p->n;
   if (count > 0 && !R_out) return fail(REFF_ERR_INVALID_ARG, "R_out is NULL");
-  // Distinct free nodes in id order; map[i] = index of node i's result.
-  std::vector<int64_t> map((size_t)count);
-  std::vector<int64_t> cols;
-  {
-    std::vector<int64_t> ids((size_t)count);
-    for (int64_t i = 0; i < count; ++i) {
-      const int64_t v = nodes ? nodes[i] : i;
-      if (v < 0 || v >= p->n)
-        return fail(REFF_ERR_INVALID_ARG, "node id " + std::to_string(v) + " out of range");
-      ids[(size_t)i] = v;
-    }
-    cols = ids;
-    std::sort(cols.begin(), cols.end());
-    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-    cols.erase(std::remove_if(cols.begin(), cols.end(),
-                              [&](int64_t v) { return p->is_pad[(size_t)v] != 0; }),
-               cols.end());
-    for (int64_t i = 0; i < count; ++i) {
-      const int64_t v = ids[(size_t)i];
-      if (p->is_pad[(size_t)v]) {
-        map[(size_t)i] = -1;
-      } else {
-        map[(size_t)i] = std::lower_bound(cols.begin(), cols.end(), v) - cols.begin();
-      }
-    }
-  }
+  std::vector<int64_t> cols, map;
+  s = columns_of(nodes, count, p->n, p->gnd.grounded, cols, map);
+  if (s != REFF_OK) return s;
   if (st) {
     std::memset(st, 0, sizeof(*st));
     st->n_solved = (int64_t)cols.size();
   }
   HIPCHK(hipSetDevice(p->device));
-  reff_status rs;
-  if ((rs = ensure(p->ws_out, (cols.size() + count + 1) * sizeof(double) +
-                                  (count + 1) * sizeof(int64_t))) != REFF_OK)
-    return rs;
-  double* res_dev = (double*)p->ws_out.p;
-  int64_t* map_dev = (int64_t*)(res_dev + cols.size() + count + 1);
   // A block Krylov space of S columns exhausts a stack of only a few S free
   // nodes within a handful of iterations, where the block residual loses
   // column rank; such stacks use S independent PCGs instead.
-  if (p->n_free < 16 * (int64_t)S) o.indep = true;
-  reff_status solve_rs = REFF_OK;
-  if (!cols.empty()) {
-    solve_rs = solve_columns(p, cols, res_dev, o, st);
-    if (solve_rs != REFF_OK && solve_rs != REFF_ERR_NO_CONVERGENCE) return solve_rs;
-  }
-  if (count > 0) {
-    if (o.out_dev) {
-      HIPCHK(hipMemcpyAsync(map_dev, map.data(), count * sizeof(int64_t), hipMemcpyHostToDevice,
-                            o.stream));
-      HIPCHK(launch_gather_out(res_dev, map_dev, R_out, count, o.stream));
-      HIPCHK(hipStreamSynchronize(o.stream));
-    } else {
-      std::vector<double> res(cols.size());
-      if (!cols.empty())
-        HIPCHK(hipMemcpyAsync(res.data(), res_dev, cols.size() * sizeof(double),
-                              hipMemcpyDeviceToHost, o.stream));
-      HIPCHK(hipStreamSynchronize(o.stream));
-      for (int64_t i = 0; i < count; ++i)
-        R_out[i] = map[(size_t)i] >= 0 ? res[(size_t)map[(size_t)i]] : 0.0;
-    }
-  }
+  if (p->gnd.n_free < 16 * (int64_t)S) o.indep = true;
+  reff_status rs = ensure(p->ws.out, (cols.size() + 1) * sizeof(double));
+  if (rs != REFF_OK) return rs;
+  double* res_dev = (double*)p->ws.out.p;
+  std::vector<StackInfo> stacks{StackInfo{0, p->n, p->plane, p->nx}};
+  std::vector<BlockJob> jobs;
+  deal_blocks(cols, 0, 0, jobs);
+  std::vector<BlockResult> br;
+  reff_status solve_rs = run_blocks(p->ws, p->gnd, stacks, jobs, res_dev, o, br, st);
+  if (solve_rs != REFF_OK && solve_rs != REFF_ERR_NO_CONVERGENCE) return solve_rs;
+  add_stats(st, br, 0, br.size());
+  rs = write_out(p->ws, res_dev, (int64_t)cols.size(), map, R_out, o.out_dev, o.stream);
+  if (rs != REFF_OK) return rs;
   if (st)
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (solve_rs == REFF_ERR_NO_CONVERGENCE)
@@ -598,9 +920,146 @@ reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m, const int6
                              int64_t n, reff_pair_mode mode, double* R_out,
                              const reff_solve_opts* opts, reff_solve_stats* st) {
   g_err.clear();
-  (void)a; (void)m; (void)b; (void)n; (void)mode; (void)R_out; (void)opts; (void)st;
+  const auto t0 = std::chrono::steady_clock::now();
   if (!p) return fail(REFF_ERR_INVALID_ARG, "handle is NULL");
-  return fail(REFF_ERR_UNSUPPORTED, "reff_query_pairs: not available in this build");
+  if (m < 0 || n < 0) return fail(REFF_ERR_INVALID_ARG, "m, n must be >= 0");
+  if ((m > 0 && !a) || (n > 0 && !b)) return fail(REFF_ERR_INVALID_ARG, "NULL node list");
+  if (m * n > 0 && !R_out) return fail(REFF_ERR_INVALID_ARG, "R_out is NULL");
+  if (mode != REFF_PAIRS_GROUNDED && mode != REFF_PAIRS_FLOATING)
+    return fail(REFF_ERR_INVALID_ARG, "unknown pair mode");
+  Opts o;
+  reff_status s = parse_opts(opts, o);
+  if (s != REFF_OK) return s;
+  for (int64_t i = 0; i < m; ++i)
+    if (a[i] < 0 || a[i] >= p->n) return fail(REFF_ERR_INVALID_ARG, "node id out of range in a");
+  for (int64_t j = 0; j < n; ++j)
+    if (b[j] < 0 || b[j] >= p->n) return fail(REFF_ERR_INVALID_ARG, "node id out of range in b");
+  if (st) std::memset(st, 0, sizeof(*st));
+  HIPCHK(hipSetDevice(p->device));
+  // FLOATING: Eq. 2 on the whole stack; ground one reference node (the first
+  // pad) instead of every pad -- R(a,b) does not depend on that choice.
+  CoefSet* cs = &p->gnd;
+  if (mode == REFF_PAIRS_FLOATING) {
+    if (!p->flt.ready) {
+      p->flt_ref = (int64_t)p->pad_xy[1] * p->nx + p->pad_xy[0];
+      s = make_coefset(p, std::vector<int64_t>{p->flt_ref}, p->flt);
+      if (s != REFF_OK) return s;
+    }
+    cs = &p->flt;
+  }
+  if (cs->n_free < 16 * (int64_t)S) o.indep = true;
+  // Distinct non-grounded endpoints, each solved once (m + n solves).
+  std::vector<int64_t> cols(a, a + m);
+  cols.insert(cols.end(), b, b + n);
+  std::sort(cols.begin(), cols.end());
+  cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+  cols.erase(std::remove_if(cols.begin(), cols.end(),
+                            [&](int64_t v) { return cs->grounded[(size_t)v] != 0; }),
+             cols.end());
+  const int64_t U = (int64_t)cols.size();
+  std::vector<double> K((size_t)(U * U), 0.0);
+  reff_status solve_rs = REFF_OK;
+  if (U > 0) {
+    const int64_t nn = p->n;
+    std::vector<StackInfo> stacks{StackInfo{0, nn, p->plane, p->nx}};
+    std::vector<BlockJob> jobs;
+    deal_blocks(cols, 0, 0, jobs);
+    const int64_t nblk = (int64_t)jobs.size();
+    std::vector<int32_t> blk_of((size_t)U), col_of((size_t)U);
+    for (int64_t bb = 0; bb < nblk; ++bb)
+      for (int k = 0; k < jobs[(size_t)bb].ncol; ++k) {
+        blk_of[(size_t)jobs[(size_t)bb].pos[k]] = (int32_t)bb;
+        col_of[(size_t)jobs[(size_t)bb].pos[k]] = k;
+      }
+    reff_status rs;
+    if ((rs = ensure(p->ws.xs, (size_t)nblk * nn * S * sizeof(double))) != REFF_OK) return rs;
+    if ((rs = ensure(p->ws.rows, (size_t)(U * S + U) * sizeof(double))) != REFF_OK) return rs;
+    if ((rs = ensure(p->ws.out, (size_t)(U + 1) * sizeof(double))) != REFF_OK) return rs;
+    double* xs = (double*)p->ws.xs.p;
+    std::vector<int64_t> xoff((size_t)nblk);
+    for (int64_t bb = 0; bb < nblk; ++bb) xoff[(size_t)bb] = bb * nn * S;
+    std::vector<BlockResult> br;
+    solve_rs = run_blocks(p->ws, *cs, stacks, jobs, (double*)p->ws.out.p, o, br, st, xs, &xoff);
+    if (solve_rs != REFF_OK && solve_rs != REFF_ERR_NO_CONVERGENCE) return solve_rs;
+    add_stats(st, br, 0, br.size());
+    // x_u[v] for every endpoint pair: gather the endpoint rows of each block.
+    int64_t* node_dev = (int64_t*)((double*)p->ws.rows.p + U * S);
+    double* rows_dev = (double*)p->ws.rows.p;
+    HIPCHK(hipMemcpyAsync(node_dev, cols.data(), U * sizeof(int64_t), hipMemcpyHostToDevice,
+                          o.stream));
+    std::vector<double> rows((size_t)(nblk * U * S));
+    for (int64_t bb = 0; bb < nblk; ++bb) {
+      HIPCHK(launch_gather_rows(xs + bb * nn * S, node_dev, U, rows_dev, o.stream));
+      HIPCHK(hipMemcpyAsync(rows.data() + bb * U * S, rows_dev, U * S * sizeof(double),
+                            hipMemcpyDeviceToHost, o.stream));
+      HIPCHK(hipStreamSynchronize(o.stream));
+    }
+    // Cross terms x_u^T G x_v between (and within) solved blocks: the
+    // bilinear estimate K_uv = x_u[v] + x_v[u] - x_u^T G x_v has an error that
+    // is a product of the two solution errors (second order).
+    SolveBuffers sb;
+    PinnedBuf pin;
+    if ((rs = single_work(p->ws, stacks[0], sb, o.stream, pin)) != REFF_OK) return rs;
+    const Coef<double> c64 = coef64(*cs);
+    std::vector<double> C((size_t)(nblk * nblk * S * S));
+    std::vector<double> tmp(S * S);
+    for (int64_t b1 = 0; b1 < nblk; ++b1)
+      for (int64_t b2 = b1; b2 < nblk; ++b2) {
+        HIPCHK(launch_cross_gram(c64, xs + b1 * nn * S, xs + b2 * nn * S, sb, o.stream));
+        HIPCHK(hipMemcpyAsync(tmp.data(), sb.W, S * S * sizeof(double), hipMemcpyDeviceToHost,
+                              o.stream));
+        HIPCHK(hipStreamSynchronize(o.stream));
+        for (int i = 0; i < S; ++i)
+          for (int j = 0; j < S; ++j) {
+            C[(size_t)(((b1 * nblk + b2) * S + i) * S + j)] = tmp[(size_t)(i * S + j)];
+            C[(size_t)(((b2 * nblk + b1) * S + j) * S + i)] = tmp[(size_t)(i * S + j)];
+          }
+      }
+    for (int64_t u = 0; u < U; ++u)
+      for (int64_t v = 0; v < U; ++v) {
+        const int64_t bu = blk_of[(size_t)u], cu = col_of[(size_t)u];
+        const int64_t bv = blk_of[(size_t)v], cv = col_of[(size_t)v];
+        const double xuv = rows[(size_t)((bu * U + v) * S + cu)];
+        const double xvu = rows[(size_t)((bv * U + u) * S + cv)];
+        const double g = C[(size_t)(((bu * nblk + bv) * S + cu) * S + cv)];
+        K[(size_t)(u * U + v)] = xuv + xvu - g;
+      }
+  }
+  auto idx = [&](int64_t v) -> int64_t {
+    auto it = std::lower_bound(cols.begin(), cols.end(), v);
+    return (it != cols.end() && *it == v) ? (int64_t)(it - cols.begin()) : -1;
+  };
+  std::vector<double> R((size_t)(m * n));
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t ia = idx(a[i]);
+    for (int64_t j = 0; j < n; ++j) {
+      double r = 0.0;
+      if (a[i] != b[j]) {
+        const int64_t jb = idx(b[j]);
+        const double kaa = ia >= 0 ? K[(size_t)(ia * U + ia)] : 0.0;
+        const double kbb = jb >= 0 ? K[(size_t)(jb * U + jb)] : 0.0;
+        const double kab = (ia >= 0 && jb >= 0) ? K[(size_t)(ia * U + jb)] : 0.0;
+        r = kaa + kbb - 2.0 * kab;
+      }
+      R[(size_t)(i * n + j)] = r;
+    }
+  }
+  if (m * n > 0) {
+    if (o.out_dev) {
+      HIPCHK(hipMemcpyAsync(R_out, R.data(), (size_t)(m * n) * sizeof(double),
+                            hipMemcpyHostToDevice, o.stream));
+      HIPCHK(hipStreamSynchronize(o.stream));
+    } else {
+      std::memcpy(R_out, R.data(), (size_t)(m * n) * sizeof(double));
+    }
+  }
+  if (st) {
+    st->n_solved = U;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (solve_rs == REFF_ERR_NO_CONVERGENCE)
+    return fail(REFF_ERR_NO_CONVERGENCE, "max_iters reached before the tolerance");
+  return REFF_OK;
 }
 
 reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
@@ -608,24 +1067,109 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
                              double* const* R_out, const reff_batch_opts* opts,
                              reff_solve_stats* per_plan) {
   g_err.clear();
+  const auto t0 = std::chrono::steady_clock::now();
   if (n_plans < 0) return fail(REFF_ERR_INVALID_ARG, "n_plans < 0");
-  if (n_plans > 0 && (!plans || !R_out)) return fail(REFF_ERR_INVALID_ARG, "NULL plans/R_out");
+  if (n_plans == 0) return REFF_OK;
+  if (!plans || !R_out) return fail(REFF_ERR_INVALID_ARG, "NULL plans or R_out");
   if (opts && opts->surrogate) return fail(REFF_ERR_UNSUPPORTED, "surrogate screening not available");
+  Opts o;
+  reff_status s = parse_opts(opts ? &opts->solve : nullptr, o);
+  if (s != REFF_OK) return s;
+  // Validate every plan (and its node list) before any device work.
+  std::vector<const reff_pdn_desc*> ds((size_t)n_plans);
+  std::vector<std::vector<int64_t>> gnds((size_t)n_plans);
+  std::vector<StackInfo> stacks((size_t)n_plans);
   for (int32_t i = 0; i < n_plans; ++i) {
-    reff_status s = validate_desc(&plans[i]);
+    s = validate_desc(&plans[i]);
     if (s != REFF_OK) return fail(s, "plan " + std::to_string(i) + ": " + g_err);
+    ds[(size_t)i] = &plans[i];
+    for (int32_t j = 0; j < plans[i].n_pads; ++j)
+      gnds[(size_t)i].push_back((int64_t)plans[i].pad_xy[2 * j + 1] * plans[i].nx +
+                                plans[i].pad_xy[2 * j]);
+    const int64_t pl = (int64_t)plans[i].nx * plans[i].ny;
+    stacks[(size_t)i] = StackInfo{0, pl * plans[i].n_tiers, pl, plans[i].nx};
+    const bool given = nodes && nodes[i];
+    if (given && (!n_nodes || n_nodes[i] < 0))
+      return fail(REFF_ERR_INVALID_ARG, "plan " + std::to_string(i) + ": bad n_nodes");
+    const int64_t cnt = given ? n_nodes[i] : stacks[(size_t)i].n;
+    if (cnt > 0 && !R_out[i]) return fail(REFF_ERR_INVALID_ARG, "plan " + std::to_string(i) + ": R_out NULL");
+    if (given)
+      for (int64_t k = 0; k < cnt; ++k)
+        if (nodes[i][k] < 0 || nodes[i][k] >= stacks[(size_t)i].n)
+          return fail(REFF_ERR_INVALID_ARG, "plan " + std::to_string(i) + ": node id " +
+                                                std::to_string(nodes[i][k]) + " out of range");
   }
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
+  // Connectivity of every plan is checked (host breadth-first search) before
+  // the first upload.
+  // All plans' coefficients in one concatenated set (one upload).
+  CoefSet cs;
+  std::vector<void*> owned;
+  struct Free {
+    std::vector<void*>& v;
+    ~Free() {
+      for (void* q : v) (void)hipFree(q);
+    }
+  } free_owned{owned};
+  std::vector<int64_t> cbase;
+  s = make_coefset_multi(ds, gnds, cs, cbase, owned);
+  if (s != REFF_OK) return s;
+  std::vector<std::vector<int64_t>> cols((size_t)n_plans), maps((size_t)n_plans);
+  std::vector<BlockJob> jobs;
+  std::vector<size_t> job0((size_t)n_plans + 1);
+  int64_t pos0 = 0;
+  std::vector<int64_t> res0((size_t)n_plans);
+  bool any_small = false;
   for (int32_t i = 0; i < n_plans; ++i) {
-    reff_pdn h = nullptr;
-    reff_status s = reff_build_pdn(&plans[i], dev, &h);
+    stacks[(size_t)i].cbase = cbase[(size_t)i];
+    const bool given = nodes && nodes[i];
+    const int64_t cnt = given ? n_nodes[i] : stacks[(size_t)i].n;
+    std::vector<uint8_t> g(cs.grounded.begin() + cbase[(size_t)i],
+                           cs.grounded.begin() + cbase[(size_t)i] + stacks[(size_t)i].n);
+    s = columns_of(given ? nodes[i] : nullptr, cnt, stacks[(size_t)i].n, g, cols[(size_t)i],
+                   maps[(size_t)i]);
     if (s != REFF_OK) return fail(s, "plan " + std::to_string(i) + ": " + g_err);
-    s = reff_solve_diag(h, nodes ? nodes[i] : nullptr, nodes ? n_nodes[i] : 0, R_out[i],
-                        opts ? &opts->solve : nullptr, per_plan ? &per_plan[i] : nullptr);
-    reff_free_pdn(h);
-    if (s != REFF_OK) return fail(s, "plan " + std::to_string(i) + ": " + g_err);
+    int64_t nfree = 0;
+    for (uint8_t f : g) nfree += f ? 0 : 1;
+    if (nfree < 16 * (int64_t)S) any_small = true;
+    job0[(size_t)i] = jobs.size();
+    res0[(size_t)i] = pos0;
+    deal_blocks(cols[(size_t)i], i, pos0, jobs);
+    pos0 += (int64_t)cols[(size_t)i].size();
   }
+  job0[(size_t)n_plans] = jobs.size();
+  if (any_small) o.indep = true;
+  Workspace ws;
+  struct Rel {
+    Workspace& w;
+    ~Rel() { w.release(); }
+  } rel{ws};
+  reff_status rs = ensure(ws.out, (size_t)(pos0 + 1) * sizeof(double));
+  if (rs != REFF_OK) return rs;
+  std::vector<BlockResult> br;
+  reff_solve_stats agg;
+  std::memset(&agg, 0, sizeof(agg));
+  reff_status solve_rs = run_blocks(ws, cs, stacks, jobs, (double*)ws.out.p, o, br, &agg);
+  if (solve_rs != REFF_OK && solve_rs != REFF_ERR_NO_CONVERGENCE) return solve_rs;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int32_t i = 0; i < n_plans; ++i) {
+    rs = write_out(ws, (double*)ws.out.p + res0[(size_t)i], (int64_t)cols[(size_t)i].size(),
+                   maps[(size_t)i], R_out[i], o.out_dev, o.stream);
+    if (rs != REFF_OK) return rs;
+    if (per_plan) {
+      reff_solve_stats& ps = per_plan[i];
+      std::memset(&ps, 0, sizeof(ps));
+      ps.n_solved = (int64_t)cols[(size_t)i].size();
+      add_stats(&ps, br, job0[(size_t)i], job0[(size_t)i + 1]);
+      ps.seconds = secs;
+      if (i == 0)
+        for (int k = 0; k < 3; ++k) {
+          ps.kernel_ms[k] = agg.kernel_ms[k];
+          ps.kernel_launches[k] = agg.kernel_launches[k];
+        }
+    }
+  }
+  if (solve_rs == REFF_ERR_NO_CONVERGENCE)
+    return fail(REFF_ERR_NO_CONVERGENCE, "max_iters reached; R_out holds lower bounds");
   return REFF_OK;
 }
 

@@ -18,30 +18,59 @@ constexpr int WG = 512;      // threads per workgroup of the block kernels
 constexpr int NODES_PER_WAVE = CH / (WG / 64);  // 4
 constexpr int HIST = 16;     // convergence window (iterations)
 constexpr int MAX_GRID = 512;
+constexpr int NGRAM = 4;     // Gram partials per work unit
 // A column is converged once its estimated remaining relative error is
 // below CONV_SAFETY * rel_tol.
 constexpr double CONV_SAFETY = 0.25;
 
 // Per-node stencil coefficients of the grounded conductance matrix G, one
-// structure-of-arrays copy per precision.  For a node v (pads are identity
-// rows with all couplings zero):
+// structure-of-arrays copy per precision.  For a node v of a stack with row
+// length nx and tier size plane (pads and the other grounded nodes are
+// identity rows with all couplings zero):
 //   (G p)_v = d_v p_v - cE_v p_{v+1} - cE_{v-1} p_{v-1}
 //             - cN_v p_{v+nx} - cN_{v-nx} p_{v-nx}
 //             - up_v p_{v+plane} - dn_v p_{v-plane}
 // where up/dn come from the TSV side list (slot_v >= 0 only on nodes that
-// carry a TSV segment).
+// carry a TSV segment).  Several stacks may be concatenated (a batch).
 template <typename T>
 struct Coef {
   const T* d;
   const T* dinv;
   const T* cE;
   const T* cN;
-  const int32_t* slot;   // [n] index into up/dn, -1 if the node has no TSV
-  const T* up;           // [n_slots] coupling to v + plane
-  const T* dn;           // [n_slots] coupling to v - plane
+  const int32_t* slot;   // index into up/dn, -1 if the node has no TSV
+  const T* up;           // coupling to v + plane
+  const T* dn;           // coupling to v - plane
+};
+
+// One solve block: a stack (coefficients from node cbase on, n nodes, row
+// length nx, tier size plane) with its own S right-hand sides, whose vectors
+// occupy rows vbase .. vbase+n-1 of the n x S work arrays.  Its work units
+// are unit_begin .. unit_end-1.
+struct PlanDesc {
+  int64_t cbase;
+  int64_t vbase;
   int64_t n;
-  int32_t nx;
   int64_t plane;
+  int32_t nx;
+  int32_t unit_begin, unit_end;
+  int32_t pad_;
+};
+
+// A contiguous range of vector rows [begin, end) of one solve block,
+// processed by one workgroup of the vector kernels.
+struct Unit {
+  int64_t begin, end;
+  int32_t plan;
+  int32_t pad_;
+};
+
+// Argument bundle of the vector kernels: gridDim.x workgroups process the
+// units uid[0 .. gridDim.x) (the active ones).
+struct Work {
+  const PlanDesc* plans;
+  const Unit* units;
+  const int32_t* uid;
 };
 
 // Device-resident convergence state of one block solve.
@@ -62,66 +91,100 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Device work arrays of the block solver (grown on demand, reused).
+struct Workspace {
+  DevBuf Y, P, Q, R, D, X, part, W, small, state, tgt, pos, plans, units, uid, act, out, xs,
+      rows, map, flags;
+  void release();
+};
+
+}  // namespace reff
+
+namespace reff {
+
+// Stencil coefficients of one grounded system on the device, both
+// precisions.  `grounded` marks the Dirichlet nodes of this system (the pads
+// for node-to-supply resistance; one reference node for the floating
+// network of the whole stack).
+struct CoefSet {
+  bool ready = false;
+  double *d64 = nullptr, *dinv64 = nullptr, *cE64 = nullptr, *cN64 = nullptr,
+         *up64 = nullptr, *dn64 = nullptr;
+  float *d32 = nullptr, *dinv32 = nullptr, *cE32 = nullptr, *cN32 = nullptr,
+        *up32 = nullptr, *dn32 = nullptr;
+  int32_t* slot = nullptr;
+  std::vector<uint8_t> grounded;
+  int64_t n_free = 0;
+  int64_t n_slots = 0;
+};
+
 }  // namespace reff
 
 struct reff_pdn_t {
   int device = 0;
   int32_t nt = 0, nx = 0, ny = 0;
   int64_t n = 0, plane = 0;
-  int64_t n_slots = 0;
-  int64_t n_free = 0;
-  std::vector<uint8_t> is_pad;       // host copy
-  // device coefficient storage
-  double *d64 = nullptr, *dinv64 = nullptr, *cE64 = nullptr, *cN64 = nullptr,
-         *up64 = nullptr, *dn64 = nullptr;
-  float *d32 = nullptr, *dinv32 = nullptr, *cE32 = nullptr, *cN32 = nullptr,
-        *up32 = nullptr, *dn32 = nullptr;
-  int32_t* slot = nullptr;
-  // workspace (grown on demand)
-  reff::DevBuf ws_Y, ws_P, ws_Q, ws_R, ws_D, ws_X, ws_part, ws_W, ws_small, ws_state,
-      ws_tgt, ws_out;
-  std::vector<void*> extra;  // misc allocations freed with the handle
+  // host copy of the description (to build further coefficient sets)
+  std::vector<double> gx, gy, tsv_g;
+  std::vector<int32_t> tsv_xy, pad_xy;
+  reff::CoefSet gnd;   // pads grounded (node-to-supply resistance)
+  reff::CoefSet flt;   // one reference node grounded (floating pairs)
+  int64_t flt_ref = -1;
+  reff::Workspace ws;         // solver work arrays (grown on demand)
+  std::vector<void*> extra;  // coefficient allocations freed with the handle
 };
 
 namespace reff {
 
 // Kernel launchers (reff_kernels.hip).  All launch on `st` and return the
 // HIP error of the launch.
+// Work arrays of one solve (nb solve blocks at once).  Vectors are
+// rows x S; the S x S matrices and states are per solve block.
 struct SolveBuffers {
-  void* Y;       // n x S, T: search block before orthonormalisation
-  void* P;       // n x S, T: P = Y T
-  void* Q;       // n x S, T: Q = G P
-  void* R;       // n x S, T: residual block
-  void* D;       // n x S, T: accumulated solution (mixed path), may be null
-  double* X;     // n x S, float64 (mixed path accumulated solution), may be null
-  double* part;  // grid x 4 x S*S partial Grams
-  double* W;     // 4 x S*S reduced Grams
-  double* winv;  // S*S: W1^+
-  void* alpha;   // S*S in T
-  void* delta;   // S*S in T
-  void* Tm;      // S*S in T: orthonormalising map T
-  BlockState* state;
-  int64_t* tgt;  // S target node ids (-1 = empty column)
+  void* Y;       // rows x S, T: search block before orthonormalisation
+  void* P;       // rows x S, T: P = Y T
+  void* Q;       // rows x S, T: Q = G P
+  void* R;       // rows x S, T: residual block
+  void* D;       // rows x S, T: accumulated solution (mixed path / pairs), may be null
+  double* X;     // rows x S, float64 (mixed path accumulated solution), may be null
+  double* part;  // units x NGRAM x S*S partial Grams
+  double* W;     // nb x NGRAM x S*S reduced Grams
+  double* winv;  // nb x S*S: W1^+
+  void* alpha;   // nb x S*S in T
+  void* delta;   // nb x S*S in T
+  void* Tm;      // nb x S*S in T: orthonormalising map T
+  BlockState* state;  // nb
+  int64_t* tgt;  // nb x S target node ids, local to the stack (-1 = empty)
+  int64_t* pos;  // nb x S output positions (-1 = none)
+  Work work;     // device plan / unit tables
+  const int32_t* act;  // active solve blocks (small kernels, reductions)
+  int n_act;
+  int n_units;   // active units (grid of the vector kernels)
+  int64_t rows;  // vector rows covered by the active units' blocks
 };
 
 int grid_for(int64_t n);
 
-hipError_t launch_init_block(bool fp32, bool indep, const void* coef, const SolveBuffers& b,
-                             hipStream_t st);
-// ev (nullable): 6 events recorded around the three block kernels
+hipError_t launch_init_blocks(bool fp32, bool indep, const void* coef, const SolveBuffers& b,
+                              hipStream_t st);
+// ev (nullable): 6 events recorded around the three vector kernels
 // (before/after K1, K2, K3).
 hipError_t launch_iteration(bool fp32, bool indep, bool with_d, const void* coef,
-                            const SolveBuffers& b, int64_t n, double tol, hipStream_t st,
-                            hipEvent_t* ev);
+                            const SolveBuffers& b, double tol, hipStream_t st, hipEvent_t* ev);
 hipError_t launch_zero_x(double* X, int64_t cnt, hipStream_t st);
 hipError_t launch_mixed_residual(const Coef<double>& c, const Coef<float>& cf,
-                                 const SolveBuffers& b, double* out, const int64_t* pos,
-                                 hipStream_t st);
+                                 const SolveBuffers& b, double* out, hipStream_t st);
 hipError_t launch_restart(const Coef<float>& cf, const SolveBuffers& b, bool indep,
                           hipStream_t st);
-hipError_t launch_finalize_plain(const SolveBuffers& b, double* out, const int64_t* pos,
-                                 hipStream_t st);
+hipError_t launch_finalize_plain(const SolveBuffers& b, double* out, hipStream_t st);
 hipError_t launch_gather_out(const double* res, const int64_t* map, double* out,
                              int64_t count, hipStream_t st);
+// C = Xa^T (G Xb) for two solved blocks of the same stack (plan 0 of b.work;
+// partials + reduction; result in b.W[0 .. S*S)).
+hipError_t launch_cross_gram(const Coef<double>& c, const double* Xa, const double* Xb,
+                             const SolveBuffers& b, hipStream_t st);
+// rows[i*S + k] = X[nodes[i]*S + k] for i < count.
+hipError_t launch_gather_rows(const double* X, const int64_t* nodes, int64_t count,
+                              double* rows, hipStream_t st);
 
 }  // namespace reff

@@ -1,15 +1,18 @@
 // gfx950 kernels of the block-PCG effective-resistance solver.
 //
-// Vectors are n x S blocks stored node-major with the S = 64 right-hand
+// Vectors are rows x S blocks stored row-major with the S = 64 right-hand
 // sides contiguous (V[v*S + k]).  One wavefront owns one node at a time and
 // lane k owns column k, so every vector access of a wave is one coalesced
 // 64-element row and a node's stencil coefficients are wave-uniform (scalar
-// loads).
+// loads).  Several solve blocks (one per stack of a batch, each with its own
+// S right-hand sides) run in the same launches: the vector kernels walk a
+// table of work units (node ranges of one block each), the small S x S
+// kernels run one workgroup per block.
 //
 // Block PCG with rank-revealing orthonormalised search directions.  The
 // search block arrives as Y (any basis) plus an S x S upper-triangular map T
 // such that P = Y T has D-orthonormal kept columns (D = diag G) and zero
-// dropped ones.  One iteration for all S columns:
+// dropped ones.  One iteration for all S columns of every block:
 //   K1  Qt = G Y (stencil); P = Y T; Q = Qt T;  W1 = P^T Q, W2 = P^T R
 //   Ks1 W1^+ by a guarded sweep;  A = W1^+ W2;
 //       psi_k += sum_j P[tgt_k, j] A[j, k]  (= change of x_k at node tgt_k)
@@ -18,8 +21,8 @@
 //   K3  Y = Z - P B;  W4 = Y^T D Y
 //   Ks3 T from the guarded sweep of W4: directions whose pivot falls below
 //       eps are numerically dependent and are dropped
-// The S x S products and Grams of K1-K3 run on the matrix cores.
-// (the per-workgroup Gram partials are reduced by Kr first).  With x0 = 0
+// (the per-unit Gram partials are reduced per block by Kr first).  The
+// S x S products and Grams of K1-K3 run on the matrix cores.  With x0 = 0
 // and R0 = e_i, psi_k = e_i^T x_k is the Galerkin estimate of
 // R_i = (G^-1)_ii and rises to it from below.  The "independent" variant
 // keeps only the diagonals: S ordinary PCGs side by side.
@@ -32,7 +35,7 @@
 namespace reff {
 
 // Hardware dispatches workgroup b to XCD (b mod 8).  Give each XCD a
-// contiguous range of logical blocks so that neighbouring node ranges, which
+// contiguous range of logical units so that neighbouring node ranges, which
 // share stencil halo rows, are served by the same L2.
 __device__ __forceinline__ int logical_block(int b, int nb) {
   if ((nb & 7) != 0) return b;
@@ -40,19 +43,22 @@ __device__ __forceinline__ int logical_block(int b, int nb) {
   return (b & 7) * per + (b >> 3);
 }
 
-struct Range {
-  int64_t begin, end;
+// The unit, its block and the block's S x S matrices of this workgroup.
+struct UnitCtx {
+  int64_t begin, end;  // vector rows
+  PlanDesc pd;
+  int plan;
 };
 
-__device__ __forceinline__ Range block_range(int64_t n, int grid) {
-  const int lb = logical_block(blockIdx.x, grid);
-  const int64_t nch = (n + CH - 1) / CH;
-  const int64_t cpb = (nch + grid - 1) / grid;
-  Range r;
-  r.begin = (int64_t)lb * cpb * CH;
-  const int64_t e = (int64_t)(lb + 1) * cpb * CH;
-  r.end = e < n ? e : n;
-  return r;
+__device__ __forceinline__ UnitCtx unit_ctx(const Work& wk) {
+  const int lu = logical_block(blockIdx.x, gridDim.x);
+  const Unit u = wk.units[wk.uid[lu]];
+  UnitCtx c;
+  c.begin = u.begin;
+  c.end = u.end;
+  c.plan = u.plan;
+  c.pd = wk.plans[u.plan];
+  return c;
 }
 
 int grid_for(int64_t n) {
@@ -60,46 +66,47 @@ int grid_for(int64_t n) {
   return (int)(nch < MAX_GRID ? nch : MAX_GRID);
 }
 
-// (G y)_v for the lane's column.
+// (G y)_v for the lane's column; v is a vector row of block pd.
 template <typename T, typename U>
-__device__ __forceinline__ T stencil_row(const Coef<T>& c, const U* __restrict__ Y, int64_t v,
-                                         int lane) {
-  const int64_t n = c.n;
-  const T ce = c.cE[v];
-  const T cn = c.cN[v];
-  const T cw = v >= 1 ? c.cE[v - 1] : T(0);
-  const T cs = v >= c.nx ? c.cN[v - c.nx] : T(0);
-  // Clamped indices keep every load in range; the matching coefficient is
-  // zero whenever the neighbour does not exist (grid edge or pad).
-  const int64_t ve = v + 1 < n ? v + 1 : n - 1;
-  const int64_t vw = v >= 1 ? v - 1 : 0;
-  const int64_t vn = v + c.nx < n ? v + c.nx : n - 1;
-  const int64_t vs = v >= c.nx ? v - c.nx : 0;
+__device__ __forceinline__ T stencil_row(const Coef<T>& c, const U* __restrict__ Y,
+                                         const PlanDesc& pd, int64_t v, int lane) {
+  const int64_t lv = v - pd.vbase;      // node of the stack
+  const int64_t ci = pd.cbase + lv;     // its coefficient index
+  const int64_t nx = pd.nx;
+  const T ce = c.cE[ci];
+  const T cn = c.cN[ci];
+  const T cw = lv >= 1 ? c.cE[ci - 1] : T(0);
+  const T cs = lv >= nx ? c.cN[ci - nx] : T(0);
+  // Neighbour rows that do not exist fall back to v itself; their
+  // coefficient is zero (grid edge or grounded node).
+  const int64_t ve = lv + 1 < pd.n ? v + 1 : v;
+  const int64_t vw = lv >= 1 ? v - 1 : v;
+  const int64_t vn = lv + nx < pd.n ? v + nx : v;
+  const int64_t vs = lv >= nx ? v - nx : v;
   const T y = (T)Y[v * S + lane];
   const T ye = (T)Y[ve * S + lane];
   const T yw = (T)Y[vw * S + lane];
   const T yn = (T)Y[vn * S + lane];
   const T ys = (T)Y[vs * S + lane];
-  T q = c.d[v] * y - ce * ye - cw * yw - cn * yn - cs * ys;
-  const int sl = c.slot[v];
+  T q = c.d[ci] * y - ce * ye - cw * yw - cn * yn - cs * ys;
+  const int sl = c.slot[ci];
   if (sl >= 0) {
     const T gu = c.up[sl];
     const T gd = c.dn[sl];
-    if (gu != T(0)) q -= gu * (T)Y[(v + c.plane) * S + lane];
-    if (gd != T(0)) q -= gd * (T)Y[(v - c.plane) * S + lane];
+    if (gu != T(0)) q -= gu * (T)Y[(v + pd.plane) * S + lane];
+    if (gd != T(0)) q -= gd * (T)Y[(v - pd.plane) * S + lane];
   }
   return q;
 }
 
-// Partial Grams of one workgroup: part[g][m][S*S] (or the first S entries
-// for diagonal-only Grams).
-constexpr int NGRAM = 4;
+// Partial Grams of unit u: part[u][m][S*S] (or the first S entries for
+// diagonal-only Grams).
 // Padded LDS row (words).  A row offset of 4 words spreads the 16 rows read
 // by one product operand over distinct banks.
 constexpr int LDW = S + 4;
 
-__device__ __forceinline__ double* part_of(double* part, int m) {
-  return part + ((size_t)blockIdx.x * NGRAM + m) * S * S;
+__device__ __forceinline__ double* part_of(double* part, int unit, int m) {
+  return part + ((size_t)unit * NGRAM + m) * S * S;
 }
 
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -205,31 +212,34 @@ static_assert(CH == 32 && WG == 512, "tile ownership assumes 32-node chunks, 8 w
 // ---------------------------------------------------------------- K1
 // Qt = G Y;  P = Y T;  Q = Qt T;  W1 = P^T Q,  W2 = P^T R.
 template <typename T, bool DIAG>
-__global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, const T* __restrict__ Y,
-                                                     const T* __restrict__ Tm,
-                                                     const T* __restrict__ R, T* __restrict__ P,
-                                                     T* __restrict__ Q, double* __restrict__ part) {
+__global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, Work wk,
+                                                        const T* __restrict__ Y,
+                                                        const T* __restrict__ Tm,
+                                                        const T* __restrict__ R,
+                                                        T* __restrict__ P, T* __restrict__ Q,
+                                                        double* __restrict__ part) {
   __shared__ T sA[DIAG ? 1 : CH][LDW];  // Y rows, then P rows
   __shared__ T sB[DIAG ? 1 : CH][LDW];  // G Y rows, then Q rows
   __shared__ T sR[DIAG ? 1 : CH][LDW];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int nb = w >> 2, cb = w & 3;
-  const Range rg = block_range(c.n, gridDim.x);
+  const UnitCtx u = unit_ctx(wk);
+  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
   T breg[DIAG ? 1 : S / 4];
-  if (!DIAG) load_bcol<T>(Tm, cb, lane, breg);
+  if (!DIAG) load_bcol<T>(Tm + (size_t)u.plan * S * S, cb, lane, breg);
   double a1[2][4], a2[2][4];
   zero_acc(a1);
   zero_acc(a2);
   double d1 = 0.0, d2 = 0.0;
-  for (int64_t base = rg.begin; base < rg.end; base += CH) {
+  for (int64_t base = u.begin; base < u.end; base += CH) {
     if (DIAG) {
 #pragma unroll
       for (int i = 0; i < NODES_PER_WAVE; ++i) {
         const int64_t v = base + w * NODES_PER_WAVE + i;
-        if (v < rg.end) {
+        if (v < u.end) {
           const T y = Y[v * S + lane];
-          const T q = stencil_row<T, T>(c, Y, v, lane);
+          const T q = stencil_row<T, T>(c, Y, u.pd, v, lane);
           const T r = R[v * S + lane];
           P[v * S + lane] = y;
           Q[v * S + lane] = q;
@@ -244,10 +254,10 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, const T* __re
       const int row = w * NODES_PER_WAVE + i;
       const int64_t v = base + row;
       T y = 0, q = 0, r = 0;
-      if (v < rg.end) {
+      if (v < u.end) {
         y = Y[v * S + lane];
         r = R[v * S + lane];
-        q = stencil_row<T, T>(c, Y, v, lane);
+        q = stencil_row<T, T>(c, Y, u.pd, v, lane);
       }
       sA[row][lane] = y;
       sB[row][lane] = q;
@@ -270,7 +280,7 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, const T* __re
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
       const int64_t v = base + row;
-      if (v < rg.end) {
+      if (v < u.end) {
         P[v * S + lane] = sA[row][lane];
         Q[v * S + lane] = sB[row][lane];
       }
@@ -278,22 +288,24 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, const T* __re
     __syncthreads();
   }
   if (DIAG) {
-    diag_store(part_of(part, 0), d1, w, lane);
+    diag_store(part_of(part, uidx, 0), d1, w, lane);
     __syncthreads();
-    diag_store(part_of(part, 1), d2, w, lane);
+    diag_store(part_of(part, uidx, 1), d2, w, lane);
   } else {
-    gram_store<T>(part_of(part, 0), w, lane, a1);
-    gram_store<T>(part_of(part, 1), w, lane, a2);
+    gram_store<T>(part_of(part, uidx, 0), w, lane, a1);
+    gram_store<T>(part_of(part, uidx, 1), w, lane, a2);
   }
 }
 
 // ---------------------------------------------------------------- K2
 // R -= Q A;  (D += P A);  Z = Dinv R;  W3 = Q^T Z.
 template <typename T, bool DIAG, bool WITH_D>
-__global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, const T* __restrict__ alpha,
-                                                 const T* __restrict__ Q,
-                                                 const T* __restrict__ P, T* __restrict__ R,
-                                                 T* __restrict__ D, double* __restrict__ part) {
+__global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
+                                                    const T* __restrict__ alpha,
+                                                    const T* __restrict__ Q,
+                                                    const T* __restrict__ P, T* __restrict__ R,
+                                                    T* __restrict__ D,
+                                                    double* __restrict__ part) {
   __shared__ T sQ[DIAG ? 1 : CH][LDW];
   __shared__ T sP[DIAG ? 1 : CH][LDW];  // P rows, then Z rows
   __shared__ T sR[DIAG ? 1 : CH][LDW];
@@ -302,26 +314,29 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, const T* __restri
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int nb = w >> 2, cb = w & 3;
-  const Range rg = block_range(c.n, gridDim.x);
+  const UnitCtx u = unit_ctx(wk);
+  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
+  const T* al = alpha + (size_t)u.plan * S * S;
   T breg[DIAG ? 1 : S / 4];
   if (DIAG)
-    breg[0] = alpha[lane];
+    breg[0] = al[lane];
   else
-    load_bcol<T>(alpha, cb, lane, breg);
+    load_bcol<T>(al, cb, lane, breg);
   double a3[2][4];
   zero_acc(a3);
   double d3 = 0.0;
-  for (int64_t base = rg.begin; base < rg.end; base += CH) {
+  const int64_t cofs = u.pd.cbase - u.pd.vbase;  // vector row -> coefficient index
+  for (int64_t base = u.begin; base < u.end; base += CH) {
     if (DIAG) {
 #pragma unroll
       for (int i = 0; i < NODES_PER_WAVE; ++i) {
         const int64_t v = base + w * NODES_PER_WAVE + i;
-        if (v < rg.end) {
+        if (v < u.end) {
           const T q = Q[v * S + lane];
           const T r = R[v * S + lane] - breg[0] * q;
           R[v * S + lane] = r;
           if (WITH_D) D[v * S + lane] += breg[0] * P[v * S + lane];
-          d3 += (double)q * (double)(c.dinv[v] * r);
+          d3 += (double)q * (double)(c.dinv[v + cofs] * r);
         }
       }
       continue;
@@ -330,7 +345,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, const T* __restri
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
       const int64_t v = base + row;
-      const bool ok = v < rg.end;
+      const bool ok = v < u.end;
       sQ[row][lane] = ok ? Q[v * S + lane] : T(0);
       sR[row][lane] = ok ? R[v * S + lane] : T(0);
       if (WITH_D) {
@@ -340,7 +355,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, const T* __restri
     }
     if (threadIdx.x < CH) {
       const int64_t v = base + threadIdx.x;
-      sDinv[threadIdx.x] = v < rg.end ? c.dinv[v] : T(0);
+      sDinv[threadIdx.x] = v < u.end ? c.dinv[v + cofs] : T(0);
     }
     __syncthreads();
     const auto qa = prod_tile<T>(sQ, nb, breg, lane);
@@ -368,7 +383,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, const T* __restri
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
       const int64_t v = base + row;
-      if (v < rg.end) {
+      if (v < u.end) {
         R[v * S + lane] = sR[row][lane];
         if (WITH_D) D[v * S + lane] = sD[row][lane];
       }
@@ -376,38 +391,43 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, const T* __restri
     __syncthreads();
   }
   if (DIAG)
-    diag_store(part_of(part, 2), d3, w, lane);
+    diag_store(part_of(part, uidx, 2), d3, w, lane);
   else
-    gram_store<T>(part_of(part, 2), w, lane, a3);
+    gram_store<T>(part_of(part, uidx, 2), w, lane, a3);
 }
 
 // ---------------------------------------------------------------- K3
 // Y = Dinv R - P B;  W4 = Y^T D Y (block variant).
 template <typename T, bool DIAG>
-__global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, const T* __restrict__ delta,
-                                                 const T* __restrict__ R,
-                                                 const T* __restrict__ P, T* __restrict__ Y,
-                                                 double* __restrict__ part) {
+__global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
+                                                    const T* __restrict__ delta,
+                                                    const T* __restrict__ R,
+                                                    const T* __restrict__ P, T* __restrict__ Y,
+                                                    double* __restrict__ part) {
   __shared__ T sP[DIAG ? 1 : CH][LDW];  // P rows, then Y rows
   __shared__ T sR[DIAG ? 1 : CH][LDW];  // R rows, then D Y rows
   __shared__ T sDv[CH][2];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int nb = w >> 2, cb = w & 3;
-  const Range rg = block_range(c.n, gridDim.x);
+  const UnitCtx u = unit_ctx(wk);
+  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
+  const T* de = delta + (size_t)u.plan * S * S;
   T breg[DIAG ? 1 : S / 4];
   if (DIAG)
-    breg[0] = delta[lane];
+    breg[0] = de[lane];
   else
-    load_bcol<T>(delta, cb, lane, breg);
+    load_bcol<T>(de, cb, lane, breg);
   double a4[2][4];
   zero_acc(a4);
-  for (int64_t base = rg.begin; base < rg.end; base += CH) {
+  const int64_t cofs = u.pd.cbase - u.pd.vbase;
+  for (int64_t base = u.begin; base < u.end; base += CH) {
     if (DIAG) {
 #pragma unroll
       for (int i = 0; i < NODES_PER_WAVE; ++i) {
         const int64_t v = base + w * NODES_PER_WAVE + i;
-        if (v < rg.end) Y[v * S + lane] = c.dinv[v] * R[v * S + lane] - breg[0] * P[v * S + lane];
+        if (v < u.end)
+          Y[v * S + lane] = c.dinv[v + cofs] * R[v * S + lane] - breg[0] * P[v * S + lane];
       }
       continue;
     }
@@ -415,15 +435,15 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, const T* __restri
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
       const int64_t v = base + row;
-      const bool ok = v < rg.end;
+      const bool ok = v < u.end;
       sP[row][lane] = ok ? P[v * S + lane] : T(0);
       sR[row][lane] = ok ? R[v * S + lane] : T(0);
     }
     if (threadIdx.x < CH) {
       const int64_t v = base + threadIdx.x;
-      const bool ok = v < rg.end;
-      sDv[threadIdx.x][0] = ok ? c.dinv[v] : T(0);
-      sDv[threadIdx.x][1] = ok ? c.d[v] : T(0);
+      const bool ok = v < u.end;
+      sDv[threadIdx.x][0] = ok ? c.dinv[v + cofs] : T(0);
+      sDv[threadIdx.x][1] = ok ? c.d[v + cofs] : T(0);
     }
     __syncthreads();
     const auto pd = prod_tile<T>(sP, nb, breg, lane);
@@ -446,80 +466,110 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, const T* __restri
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
       const int64_t v = base + row;
-      if (v < rg.end) Y[v * S + lane] = sP[row][lane];
+      if (v < u.end) Y[v * S + lane] = sP[row][lane];
     }
     __syncthreads();
   }
-  if (!DIAG) gram_store<T>(part_of(part, 3), w, lane, a4);
+  if (!DIAG) gram_store<T>(part_of(part, uidx, 3), w, lane, a4);
 }
 
 // W4 = Y^T D Y alone (used when a refinement step restarts from a new Y).
 template <typename T>
-__global__ __launch_bounds__(WG) void k_gram_dy(Coef<T> c, const T* __restrict__ Y,
-                                                double* __restrict__ part) {
+__global__ __launch_bounds__(WG, 4) void k_gram_dy(Coef<T> c, Work wk, const T* __restrict__ Y,
+                                                   double* __restrict__ part) {
   __shared__ T sY[CH][LDW];
   __shared__ T sDY[CH][LDW];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const Range rg = block_range(c.n, gridDim.x);
+  const UnitCtx u = unit_ctx(wk);
+  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
+  const int64_t cofs = u.pd.cbase - u.pd.vbase;
   double a4[2][4];
   zero_acc(a4);
-  for (int64_t base = rg.begin; base < rg.end; base += CH) {
+  for (int64_t base = u.begin; base < u.end; base += CH) {
 #pragma unroll
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
       const int64_t v = base + row;
-      const T y = v < rg.end ? Y[v * S + lane] : T(0);
+      const T y = v < u.end ? Y[v * S + lane] : T(0);
       sY[row][lane] = y;
-      sDY[row][lane] = v < rg.end ? c.d[v] * y : T(0);
+      sDY[row][lane] = v < u.end ? c.d[v + cofs] * y : T(0);
     }
     __syncthreads();
     gram_chunk<T>(sY, sDY, w, lane, a4);
     __syncthreads();
   }
-  gram_store<T>(part_of(part, 3), w, lane, a4);
+  gram_store<T>(part_of(part, uidx, 3), w, lane, a4);
+}
+
+// C = Xa^T (G Xb) over all nodes of a block (pair resistances: the
+// bilinear cross terms x_u^T G x_v between two solved blocks of one stack).
+template <typename T>
+__global__ __launch_bounds__(WG, 4) void k_cross_gram(Coef<T> c, Work wk,
+                                                      const T* __restrict__ Xa,
+                                                      const T* __restrict__ Xb,
+                                                      double* __restrict__ part) {
+  __shared__ T sA[CH][LDW];
+  __shared__ T sB[CH][LDW];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const UnitCtx u = unit_ctx(wk);
+  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
+  double acc[2][4];
+  zero_acc(acc);
+  for (int64_t base = u.begin; base < u.end; base += CH) {
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int row = w * NODES_PER_WAVE + i;
+      const int64_t v = base + row;
+      const bool ok = v < u.end;
+      sA[row][lane] = ok ? Xa[v * S + lane] : T(0);
+      sB[row][lane] = ok ? stencil_row<T, T>(c, Xb, u.pd, v, lane) : T(0);
+    }
+    __syncthreads();
+    gram_chunk<T>(sA, sB, w, lane, acc);
+    __syncthreads();
+  }
+  gram_store<T>(part_of(part, uidx, 0), w, lane, acc);
 }
 
 // ---------------------------------------------------------------- Kr
-// W[m][e] = sum_g part[g][m][e] for m in [m0, m0+nmat), e < len, summed in
-// a fixed order (deterministic).  Eight independent partial sums per thread
-// keep many loads in flight.
+// W[p][m][e] = sum over the units of block p of part[unit][m][e], for the
+// active blocks p = act[blockIdx.y], m in [m0, m0+nmat), e < len, summed in
+// a fixed order (deterministic).
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
-                                                double* __restrict__ W, int G, int m0,
+                                                double* __restrict__ W,
+                                                const PlanDesc* __restrict__ plans,
+                                                const int32_t* __restrict__ act, int m0,
                                                 int nmat, int len) {
   __shared__ double red[4][64];
+  const int p = act[blockIdx.y];
   const int el = threadIdx.x & 63;
   const int grp = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + el;
   const int total = nmat * len;
   const int m = m0 + (e < total ? e / len : 0);
   const int off = e % len;
-  double acc[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  const int ub = plans[p].unit_begin, ue = plans[p].unit_end;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (e < total) {
-    int g = grp;
-    for (; g + 28 < G; g += 32) {
+    int g = ub + grp;
+    for (; g + 12 < ue; g += 16) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += part[((size_t)(g + 4 * u) * NGRAM + m) * S * S + off];
+      for (int q = 0; q < 4; ++q) acc[q] += part[((size_t)(g + 4 * q) * NGRAM + m) * S * S + off];
     }
-    for (; g < G; g += 4) acc[0] += part[((size_t)g * NGRAM + m) * S * S + off];
+    for (; g < ue; g += 4) acc[0] += part[((size_t)g * NGRAM + m) * S * S + off];
   }
-  double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-  red[grp][el] = s;
+  red[grp][el] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
   if (grp == 0 && e < total)
-    W[(size_t)m * S * S + off] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);
+    W[((size_t)p * NGRAM + m) * S * S + off] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);
 }
 
 // ---------------------------------------------------------------- small
-// Dense S x S work in one workgroup, float64 throughout.
+// Dense S x S work, one workgroup per solve block, float64 throughout.
 constexpr int SM_THREADS = 256;
 typedef double Mat[S][S + 1];
-
-
-
-
 
 __device__ void convergence_update(BlockState* st, const double* dpsi, double tol) {
   // Column k (thread k < S) adds its increment, keeps the last HIST
@@ -583,6 +633,22 @@ __device__ __forceinline__ void load_sym_regs(const double* __restrict__ M, Mat&
   __syncthreads();
 }
 
+// 1/x and 1/sqrt(x) for x > 0 from the hardware estimates plus two Newton
+// steps each (full float64 accuracy, without the long IEEE division and
+// square-root sequences, which dominate a latency-bound sweep step).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x, y * y, 1.5);
+  return y * fma(-0.5 * x, y * y, 1.5);
+}
+
 // Jacobi scaling: sc[i] = 1/sqrt(M_ii) for live columns, 0 otherwise (empty,
 // non-finite, or not above floor_[i]); a is scaled in place.
 __device__ void scale_regs(double (&a)[16], double* sc, const double* floor_) {
@@ -603,7 +669,7 @@ __device__ void scale_regs(double (&a)[16], double* sc, const double* floor_) {
     const double d = dg[threadIdx.x];
     const bool live = isfinite(d) && d > 1e-300 && d > 1e-28 * maxd &&
                       (floor_ == nullptr || d > floor_[threadIdx.x]);
-    sc[threadIdx.x] = live ? 1.0 / sqrt(d) : 0.0;
+    sc[threadIdx.x] = live ? rsqrt64(d) : 0.0;
   }
   __syncthreads();
   const double sk = sc[lane];
@@ -634,22 +700,30 @@ __device__ void sweep_regs(double (&a)[16], double eps, int* drop, const double*
     const bool dj = !(piv > eps);
     if (threadIdx.x == 0) drop[j] = dj ? 1 : 0;
     if (Tl != nullptr && lane == j) {
-      const double rs = dj ? 0.0 : 1.0 / sqrt(piv);
+      const double rs = dj ? 0.0 : rsqrt64(piv);
+      double tv[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = 16 * w + r;
+        const double c = cj[i], si = sc[i];
+        const int di = drop[i];
         double t = 0.0;
-        if (!dj) t = i < j ? (drop[i] ? 0.0 : -cj[i] * rs) : (i == j ? rs : 0.0);
-        (*Tl)[i][j] = sc[i] * t;
+        if (!dj) t = i < j ? (di ? 0.0 : -c * rs) : (i == j ? rs : 0.0);
+        tv[r] = si * t;
       }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) (*Tl)[16 * w + r][j] = tv[r];
     }
     if (!dj) {
-      const double inv = 1.0 / piv;
+      const double inv = rcp64(piv);
       const double ck = cj[lane];
+      double cv[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) cv[r] = cj[16 * w + r];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = 16 * w + r;
-        const double ci = cj[i];
+        const double ci = cv[r];
         if (i == j)
           a[r] = (lane == j) ? -inv : ck * inv;
         else if (lane == j)
@@ -675,24 +749,32 @@ __device__ __forceinline__ void mm_rows(const Mat& A, const Mat& B, double (&c)[
 }
 
 // Ks1: W1^+ by the guarded sweep (kept in winv), A = W1^+ W2, psi update
-// from the target rows of P, convergence.
+// from the target rows of P, convergence.  Block p = act[blockIdx.x].
 template <typename T>
-__global__ __launch_bounds__(SM_THREADS) void k_small1(const double* __restrict__ W,
+__global__ __launch_bounds__(SM_THREADS) void k_small1(const double* __restrict__ Wall,
                                                        const T* __restrict__ P,
-                                                       const int64_t* __restrict__ tgt,
-                                                       double* __restrict__ winv,
-                                                       T* __restrict__ alpha_out,
-                                                       BlockState* __restrict__ st, double tol,
-                                                       double eps, int diag) {
+                                                       const PlanDesc* __restrict__ plans,
+                                                       const int32_t* __restrict__ act,
+                                                       const int64_t* __restrict__ tgt_all,
+                                                       double* __restrict__ winv_all,
+                                                       T* __restrict__ alpha_all,
+                                                       BlockState* __restrict__ st_all,
+                                                       double tol, double eps, int diag) {
   __shared__ Mat Wi, B, PT;
   __shared__ double sc[S], dpsi[S];
   __shared__ int drop[S];
+  const int p = act[blockIdx.x];
+  const int64_t vbase = plans[p].vbase;
+  const double* W1 = Wall + (size_t)p * NGRAM * S * S;
+  const double* W2 = W1 + S * S;
+  const int64_t* tgt = tgt_all + (size_t)p * S;
+  double* winv = winv_all + (size_t)p * S * S;
+  T* alpha_out = alpha_all + (size_t)p * S * S;
+  BlockState* st = st_all + p;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const bool frozen = st->frozen != 0;
   // outputs are written at the end so that no barrier waits on global stores
-  const double* W1 = W;
-  const double* W2 = W + S * S;
   if (diag) {
     if (tid < S) {
       const double w1 = W1[tid];
@@ -700,7 +782,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small1(const double* __restrict_
       winv[tid] = w1 > 0.0 ? 1.0 / w1 : 0.0;
       alpha_out[tid] = (T)a;
       const int64_t v = tgt[tid];
-      dpsi[tid] = v >= 0 ? a * (double)P[v * S + tid] : 0.0;
+      dpsi[tid] = v >= 0 ? a * (double)P[(vbase + v) * S + tid] : 0.0;
     }
     __syncthreads();
     if (!frozen) convergence_update(st, dpsi, tol);
@@ -716,7 +798,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_small1(const double* __restrict_
     const int i = 16 * w + r;
     B[i][lane] = W2[i * S + lane];
     const int64_t v = tgt[i];
-    PT[i][lane] = v >= 0 ? (double)P[v * S + lane] : 0.0;
+    PT[i][lane] = v >= 0 ? (double)P[(vbase + v) * S + lane] : 0.0;
   }
   scale_regs(a, sc, nullptr);
   sweep_regs(a, eps, drop, sc, nullptr);
@@ -728,11 +810,11 @@ __global__ __launch_bounds__(SM_THREADS) void k_small1(const double* __restrict_
     Wi[i][lane] = (drop[i] || dk) ? 0.0 : -a[r] * sc[i] * sk;
   }
   __syncthreads();
-  double c[16];
-  mm_rows(Wi, B, c);  // alpha = W1^+ W2
+  double cc[16];
+  mm_rows(Wi, B, cc);  // alpha = W1^+ W2
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 16; ++r) B[16 * w + r][lane] = frozen ? 0.0 : c[r];
+  for (int r = 0; r < 16; ++r) B[16 * w + r][lane] = frozen ? 0.0 : cc[r];
   __syncthreads();
   // psi_k increment: row tgt_k of P times column k of alpha.
   if (tid < S) {
@@ -759,16 +841,20 @@ __global__ __launch_bounds__(SM_THREADS) void k_small1(const double* __restrict_
 
 // Ks2: B = W1^+ W3.
 template <typename T>
-__global__ __launch_bounds__(SM_THREADS) void k_small2(const double* __restrict__ W,
-                                                       const double* __restrict__ winv,
-                                                       T* __restrict__ delta_out,
-                                                       const BlockState* __restrict__ st,
+__global__ __launch_bounds__(SM_THREADS) void k_small2(const double* __restrict__ Wall,
+                                                       const int32_t* __restrict__ act,
+                                                       const double* __restrict__ winv_all,
+                                                       T* __restrict__ delta_all,
+                                                       const BlockState* __restrict__ st_all,
                                                        int diag) {
   __shared__ Mat A, B;
+  const int p = act[blockIdx.x];
+  const double* W3 = Wall + ((size_t)p * NGRAM + 2) * S * S;
+  const double* winv = winv_all + (size_t)p * S * S;
+  T* delta_out = delta_all + (size_t)p * S * S;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  const double* W3 = W + 2 * S * S;
-  const bool frozen = st->frozen != 0;
+  const bool frozen = st_all[p].frozen != 0;
   if (diag) {
     if (tid < S) delta_out[tid] = frozen ? (T)0 : (T)(W3[tid] * winv[tid]);
     return;
@@ -780,10 +866,10 @@ __global__ __launch_bounds__(SM_THREADS) void k_small2(const double* __restrict_
     B[i][lane] = W3[i * S + lane];
   }
   __syncthreads();
-  double c[16];
-  mm_rows(A, B, c);
+  double cc[16];
+  mm_rows(A, B, cc);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) delta_out[(16 * w + r) * S + lane] = frozen ? (T)0 : (T)c[r];
+  for (int r = 0; r < 16; ++r) delta_out[(16 * w + r) * S + lane] = frozen ? (T)0 : (T)cc[r];
 }
 
 // Ks3: T from the guarded sweep of W4 = Y^T D Y, so that the kept columns
@@ -792,15 +878,19 @@ __global__ __launch_bounds__(SM_THREADS) void k_small2(const double* __restrict_
 // (its residual has converged) and is dropped as well; the first call after
 // a (re)start records those reference norms.
 template <typename T>
-__global__ __launch_bounds__(SM_THREADS) void k_small3(const double* __restrict__ W,
-                                                       T* __restrict__ Tg,
-                                                       BlockState* __restrict__ st, double eps,
-                                                       double tau) {
+__global__ __launch_bounds__(SM_THREADS) void k_small3(const double* __restrict__ Wall,
+                                                       const int32_t* __restrict__ act,
+                                                       T* __restrict__ T_all,
+                                                       BlockState* __restrict__ st_all,
+                                                       double eps, double tau) {
   __shared__ Mat tmp, Tl;
   __shared__ double sc[S], floor_[S];
   __shared__ int drop[S];
+  const int p = act[blockIdx.x];
+  const double* W4 = Wall + ((size_t)p * NGRAM + 3) * S * S;
+  T* Tg = T_all + (size_t)p * S * S;
+  BlockState* st = st_all + p;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double* W4 = W + 3 * S * S;
   const bool first = st->it == 0;
   double djj = 0.0;
   if (threadIdx.x < S) {
@@ -817,6 +907,16 @@ __global__ __launch_bounds__(SM_THREADS) void k_small3(const double* __restrict_
 }
 
 // ---------------------------------------------------------------- init
+// Zero the rows of the active units (grid-stride over each unit's range).
+template <typename T>
+__global__ void k_zero_units(Work wk, T* __restrict__ a) {
+  const int uidx = wk.uid[blockIdx.x];
+  const Unit u = wk.units[uidx];
+  const int64_t cnt = (u.end - u.begin) * S;
+  T* base = a + u.begin * S;
+  for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) base[i] = T(0);
+}
+
 template <typename T>
 __global__ void k_zero(T* __restrict__ a, int64_t count) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
@@ -837,97 +937,114 @@ __device__ void reset_columns(BlockState* st, int k, bool clear_ref) {
   }
 }
 
-// R = E (unit column k at node tgt[k]), Y = Dinv E, T = diag(sqrt(d_tgt))
-// (so that P = Y T is D-orthonormal), state cleared.  R, Y (and D) were
+// Per block p = act[blockIdx.x]: R = E (unit column k at node tgt[k]),
+// Y = Dinv E, T = diag(sqrt(d_tgt)) (so that P = Y T is D-orthonormal; the
+// identity for the independent variant), state cleared.  R, Y (and D) were
 // zeroed before.
 template <typename T>
-__global__ void k_set_targets(const T* __restrict__ d, const T* __restrict__ dinv,
-                              const int64_t* __restrict__ tgt, T* __restrict__ R,
-                              T* __restrict__ Y, T* __restrict__ Tm, BlockState* st,
-                              int diag) {
+__global__ void k_set_targets(Coef<T> c, const PlanDesc* __restrict__ plans,
+                              const int32_t* __restrict__ act, const int64_t* __restrict__ tgt_all,
+                              T* __restrict__ R, T* __restrict__ Y, T* __restrict__ T_all,
+                              BlockState* __restrict__ st_all, int diag) {
+  const int p = act[blockIdx.x];
   const int k = threadIdx.x;
   if (k < S) {
-    const int64_t v = tgt[k];
+    const PlanDesc pd = plans[p];
+    const int64_t v = tgt_all[(size_t)p * S + k];
+    T* Tm = T_all + (size_t)p * S * S;
+    BlockState* st = st_all + p;
+    double dv = 1.0;
     if (v >= 0) {
-      R[v * S + k] = T(1);
-      Y[v * S + k] = dinv[v];
+      dv = (double)c.d[pd.cbase + v];
+      R[(pd.vbase + v) * S + k] = T(1);
+      Y[(pd.vbase + v) * S + k] = c.dinv[pd.cbase + v];
     }
     for (int j = 0; j < S; ++j)
-      Tm[j * S + k] = (T)((j == k && v >= 0) ? (diag ? 1.0 : sqrt((double)d[v])) : 0.0);
+      Tm[j * S + k] = (T)((j == k && v >= 0) ? (diag ? 1.0 : sqrt(dv)) : 0.0);
     reset_columns(st, k, true);
-    st->scale0[k] = v >= 0 ? (double)dinv[v] : 0.0;
+    st->scale0[k] = v >= 0 ? 1.0 / dv : 0.0;
   }
 }
 
 // ---------------------------------------------------------------- mixed path
-// X += D (float64 accumulation of the float32 correction).
-__global__ void k_accum(double* __restrict__ X, const float* __restrict__ D, int64_t count) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    X[i] += (double)D[i];
+// X += D over the active units (float64 accumulation of the float32
+// correction).
+__global__ void k_accum(Work wk, double* __restrict__ X, const float* __restrict__ D) {
+  const Unit u = wk.units[wk.uid[blockIdx.x]];
+  const int64_t cnt = (u.end - u.begin) * S;
+  double* xb = X + u.begin * S;
+  const float* db = D + u.begin * S;
+  for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) xb[i] += (double)db[i];
 }
 
 // r = E - G X in float64; partial sums of x_k . r_k per column.  r is also
 // stored (as float) into R for a further refinement step, with Y = Dinv r
 // and D = 0.
-__global__ __launch_bounds__(WG) void k_resid(Coef<double> c, Coef<float> cf,
+__global__ __launch_bounds__(WG) void k_resid(Coef<double> c, Coef<float> cf, Work wk,
                                               const double* __restrict__ X,
-                                              const int64_t* __restrict__ tgt,
+                                              const int64_t* __restrict__ tgt_all,
                                               float* __restrict__ Rf, float* __restrict__ Yf,
                                               float* __restrict__ Df,
                                               double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const Range rg = block_range(c.n, gridDim.x);
-  const int64_t my_t = tgt[lane];
+  const UnitCtx u = unit_ctx(wk);
+  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
+  const int64_t tl = tgt_all[(size_t)u.plan * S + lane];
+  const int64_t my_t = tl >= 0 ? u.pd.vbase + tl : -1;
+  const int64_t cofs = u.pd.cbase - u.pd.vbase;
   double acc = 0.0;
-  for (int64_t base = rg.begin; base < rg.end; base += CH) {
+  for (int64_t base = u.begin; base < u.end; base += CH) {
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int64_t v = base + w * NODES_PER_WAVE + i;
-      if (v < rg.end) {
-        const double gx = stencil_row<double, double>(c, X, v, lane);
+      if (v < u.end) {
+        const double gx = stencil_row<double, double>(c, X, u.pd, v, lane);
         const double r = (v == my_t ? 1.0 : 0.0) - gx;
         acc += X[v * S + lane] * r;
         Rf[v * S + lane] = (float)r;
-        Yf[v * S + lane] = cf.dinv[v] * (float)r;
+        Yf[v * S + lane] = cf.dinv[v + cofs] * (float)r;
         Df[v * S + lane] = 0.0f;
       }
     }
   }
-  __shared__ double red[WG / 64][S];
-  red[w][lane] = acc;
-  __syncthreads();
-  if (w == 0) {
-    double s = 0;
-    for (int u = 0; u < WG / 64; ++u) s += red[u][lane];
-    part_of(part, 0)[lane] = s;
-  }
+  diag_store(part_of(part, uidx, 0), acc, w, lane);
 }
 
 // Variational estimate R_k = e^T x + x^T r = 2 e^T x - x^T G x (float64),
 // whose error is the energy norm of the solution error (>= 0).
-__global__ void k_finalize_mixed(const double* __restrict__ X, const int64_t* __restrict__ tgt,
-                                 const double* __restrict__ W, BlockState* st,
-                                 double* __restrict__ out, const int64_t* __restrict__ pos) {
+__global__ void k_finalize_mixed(const double* __restrict__ X, const PlanDesc* __restrict__ plans,
+                                 const int32_t* __restrict__ act,
+                                 const int64_t* __restrict__ tgt_all,
+                                 const double* __restrict__ Wall, BlockState* st_all,
+                                 double* __restrict__ out, const int64_t* __restrict__ pos_all) {
+  const int p = act[blockIdx.x];
   const int k = threadIdx.x;
   if (k < S) {
-    const int64_t v = tgt[k];
+    const int64_t v = tgt_all[(size_t)p * S + k];
     double val = 0.0;
-    if (v >= 0) val = X[v * S + k] + W[k];
-    st->ref[k] = val;
-    if (pos[k] >= 0) out[pos[k]] = val;
+    if (v >= 0) val = X[(plans[p].vbase + v) * S + k] + Wall[(size_t)p * NGRAM * S * S + k];
+    st_all[p].ref[k] = val;
+    const int64_t q = pos_all[(size_t)p * S + k];
+    if (q >= 0) out[q] = val;
   }
 }
 
-__global__ void k_finalize_plain(const BlockState* st, double* __restrict__ out,
-                                 const int64_t* __restrict__ pos) {
+__global__ void k_finalize_plain(const int32_t* __restrict__ act, const BlockState* st_all,
+                                 double* __restrict__ out, const int64_t* __restrict__ pos_all) {
+  const int p = act[blockIdx.x];
   const int k = threadIdx.x;
-  if (k < S && pos[k] >= 0) out[pos[k]] = st->psi[k];
+  const int64_t q = k < S ? pos_all[(size_t)p * S + k] : -1;
+  if (q >= 0) out[q] = st_all[p].psi[k];
 }
 
-__global__ void k_reset_state(BlockState* st) {
+__global__ void k_reset_state(const int32_t* __restrict__ act, BlockState* st_all) {
   const int k = threadIdx.x;
-  if (k < S) reset_columns(st, k, false);
+  if (k < S) reset_columns(st_all + act[blockIdx.x], k, false);
+}
+
+__global__ void k_set_identity(const int32_t* __restrict__ act, float* __restrict__ T_all) {
+  float* Tm = T_all + (size_t)act[blockIdx.x] * S * S;
+  for (int e = threadIdx.x; e < S * S; e += blockDim.x) Tm[e] = (e / S == e % S) ? 1.0f : 0.0f;
 }
 
 // out_user[i] = res[map[i]] (map < 0 -> 0.0): solved values scattered into
@@ -941,11 +1058,22 @@ __global__ void k_gather_out(const double* __restrict__ res, const int64_t* __re
   }
 }
 
+__global__ void k_gather_rows(const double* __restrict__ X, const int64_t* __restrict__ nodes,
+                              int64_t count, double* __restrict__ rows) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count * S;
+       e += (int64_t)gridDim.x * blockDim.x)
+    rows[e] = X[nodes[e / S] * S + (e % S)];
+}
+
 // ---------------------------------------------------------------- launchers
+static void reduce(const SolveBuffers& b, int m0, int nmat, int len, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3((nmat * len + 63) / 64, b.n_act), dim3(256), 0, st, b.part,
+                     b.W, b.work.plans, b.act, m0, nmat, len);
+}
+
 template <typename T>
 static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const SolveBuffers& b,
                               double tol, hipStream_t st, hipEvent_t* ev) {
-  const int G = grid_for(c.n);
   T* Y = (T*)b.Y;
   T* P = (T*)b.P;
   T* Q = (T*)b.Q;
@@ -958,75 +1086,72 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
   const double tau = sizeof(T) == 8 ? 1e-26 : 1e-12;
   const int len = indep ? S : S * S;
   const int di = indep ? 1 : 0;
-  const dim3 g(G), blk(WG);
-  const T* Tm = (const T*)b.Tm;
+  const dim3 g(b.n_units), blk(WG), gs(b.n_act), bs(SM_THREADS);
+  const Work wk = b.work;
   if (ev) hipEventRecord(ev[0], st);
   if (indep)
-    hipLaunchKernelGGL((k_stencil_gram<T, true>), g, blk, 0, st, c, Y, Tm, R, P, Q, b.part);
+    hipLaunchKernelGGL((k_stencil_gram<T, true>), g, blk, 0, st, c, wk, Y, (const T*)b.Tm, R, P,
+                       Q, b.part);
   else
-    hipLaunchKernelGGL((k_stencil_gram<T, false>), g, blk, 0, st, c, Y, Tm, R, P, Q, b.part);
+    hipLaunchKernelGGL((k_stencil_gram<T, false>), g, blk, 0, st, c, wk, Y, (const T*)b.Tm, R,
+                       P, Q, b.part);
   if (ev) hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL(k_reduce, dim3((2 * len + 63) / 64), dim3(256), 0, st, b.part, b.W, G, 0,
-                     2, len);
-  hipLaunchKernelGGL((k_small1<T>), dim3(1), dim3(SM_THREADS), 0, st, b.W, (const T*)P, b.tgt,
+  reduce(b, 0, 2, len, st);
+  hipLaunchKernelGGL((k_small1<T>), gs, bs, 0, st, b.W, (const T*)P, wk.plans, b.act, b.tgt,
                      b.winv, (T*)b.alpha, b.state, tol, eps1, di);
   if (ev) hipEventRecord(ev[2], st);
   const T* al = (const T*)b.alpha;
   if (indep) {
     if (with_d)
-      hipLaunchKernelGGL((k_update_r<T, true, true>), g, blk, 0, st, c, al, Q, P, R, D, b.part);
+      hipLaunchKernelGGL((k_update_r<T, true, true>), g, blk, 0, st, c, wk, al, Q, P, R, D,
+                         b.part);
     else
-      hipLaunchKernelGGL((k_update_r<T, true, false>), g, blk, 0, st, c, al, Q, P, R, D, b.part);
+      hipLaunchKernelGGL((k_update_r<T, true, false>), g, blk, 0, st, c, wk, al, Q, P, R, D,
+                         b.part);
   } else {
     if (with_d)
-      hipLaunchKernelGGL((k_update_r<T, false, true>), g, blk, 0, st, c, al, Q, P, R, D, b.part);
+      hipLaunchKernelGGL((k_update_r<T, false, true>), g, blk, 0, st, c, wk, al, Q, P, R, D,
+                         b.part);
     else
-      hipLaunchKernelGGL((k_update_r<T, false, false>), g, blk, 0, st, c, al, Q, P, R, D,
+      hipLaunchKernelGGL((k_update_r<T, false, false>), g, blk, 0, st, c, wk, al, Q, P, R, D,
                          b.part);
   }
   if (ev) hipEventRecord(ev[3], st);
-  hipLaunchKernelGGL(k_reduce, dim3((len + 63) / 64), dim3(256), 0, st, b.part, b.W, G, 2, 1,
-                     len);
-  hipLaunchKernelGGL((k_small2<T>), dim3(1), dim3(SM_THREADS), 0, st, b.W, b.winv,
-                     (T*)b.delta, b.state, di);
+  reduce(b, 2, 1, len, st);
+  hipLaunchKernelGGL((k_small2<T>), gs, bs, 0, st, b.W, b.act, b.winv, (T*)b.delta, b.state, di);
   if (ev) hipEventRecord(ev[4], st);
   const T* de = (const T*)b.delta;
   if (indep) {
-    hipLaunchKernelGGL((k_update_y<T, true>), g, blk, 0, st, c, de, R, P, Y, b.part);
+    hipLaunchKernelGGL((k_update_y<T, true>), g, blk, 0, st, c, wk, de, R, P, Y, b.part);
     if (ev) hipEventRecord(ev[5], st);
   } else {
-    hipLaunchKernelGGL((k_update_y<T, false>), g, blk, 0, st, c, de, R, P, Y, b.part);
+    hipLaunchKernelGGL((k_update_y<T, false>), g, blk, 0, st, c, wk, de, R, P, Y, b.part);
     if (ev) hipEventRecord(ev[5], st);
-    hipLaunchKernelGGL(k_reduce, dim3((len + 63) / 64), dim3(256), 0, st, b.part, b.W, G, 3, 1,
-                       len);
-    hipLaunchKernelGGL((k_small3<T>), dim3(1), dim3(SM_THREADS), 0, st, b.W, (T*)b.Tm, b.state,
-                       eps4, tau);
+    reduce(b, 3, 1, len, st);
+    hipLaunchKernelGGL((k_small3<T>), gs, bs, 0, st, b.W, b.act, (T*)b.Tm, b.state, eps4, tau);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_iteration(bool fp32, bool indep, bool with_d, const void* coef,
-                            const SolveBuffers& b, int64_t n, double tol, hipStream_t st,
-                            hipEvent_t* ev) {
-  (void)n;
+                            const SolveBuffers& b, double tol, hipStream_t st, hipEvent_t* ev) {
   if (fp32) return iteration_t<float>(indep, with_d, *(const Coef<float>*)coef, b, tol, st, ev);
   return iteration_t<double>(indep, with_d, *(const Coef<double>*)coef, b, tol, st, ev);
 }
 
 template <typename T>
 static hipError_t init_t(const Coef<T>& c, const SolveBuffers& b, bool indep, hipStream_t st) {
-  const int64_t cnt = c.n * S;
-  const int blocks = (int)std::min<int64_t>((cnt + 255) / 256, 8192);
-  hipLaunchKernelGGL((k_zero<T>), dim3(blocks), dim3(256), 0, st, (T*)b.R, cnt);
-  hipLaunchKernelGGL((k_zero<T>), dim3(blocks), dim3(256), 0, st, (T*)b.Y, cnt);
-  if (b.D) hipLaunchKernelGGL((k_zero<T>), dim3(blocks), dim3(256), 0, st, (T*)b.D, cnt);
-  hipLaunchKernelGGL((k_set_targets<T>), dim3(1), dim3(S), 0, st, c.d, c.dinv, b.tgt, (T*)b.R,
-                     (T*)b.Y, (T*)b.Tm, b.state, indep ? 1 : 0);
+  const dim3 g(b.n_units), blk(256);
+  hipLaunchKernelGGL((k_zero_units<T>), g, blk, 0, st, b.work, (T*)b.R);
+  hipLaunchKernelGGL((k_zero_units<T>), g, blk, 0, st, b.work, (T*)b.Y);
+  if (b.D) hipLaunchKernelGGL((k_zero_units<T>), g, blk, 0, st, b.work, (T*)b.D);
+  hipLaunchKernelGGL((k_set_targets<T>), dim3(b.n_act), dim3(S), 0, st, c, b.work.plans, b.act,
+                     b.tgt, (T*)b.R, (T*)b.Y, (T*)b.Tm, b.state, indep ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_init_block(bool fp32, bool indep, const void* coef, const SolveBuffers& b,
-                             hipStream_t st) {
+hipError_t launch_init_blocks(bool fp32, bool indep, const void* coef, const SolveBuffers& b,
+                              hipStream_t st) {
   if (fp32) return init_t<float>(*(const Coef<float>*)coef, b, indep, st);
   return init_t<double>(*(const Coef<double>*)coef, b, indep, st);
 }
@@ -1038,45 +1163,51 @@ hipError_t launch_zero_x(double* X, int64_t cnt, hipStream_t st) {
 }
 
 hipError_t launch_mixed_residual(const Coef<double>& c, const Coef<float>& cf,
-                                 const SolveBuffers& b, double* out, const int64_t* pos,
-                                 hipStream_t st) {
-  const int64_t cnt = c.n * S;
-  const int blocks = (int)std::min<int64_t>((cnt + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_accum, dim3(blocks), dim3(256), 0, st, b.X, (const float*)b.D, cnt);
-  const int G = grid_for(c.n);
-  hipLaunchKernelGGL(k_resid, dim3(G), dim3(WG), 0, st, c, cf, b.X, b.tgt, (float*)b.R,
-                     (float*)b.Y, (float*)b.D, b.part);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, b.part, b.W, G, 0, 1, S);
-  hipLaunchKernelGGL(k_finalize_mixed, dim3(1), dim3(S), 0, st, b.X, b.tgt, b.W, b.state, out,
-                     pos);
+                                 const SolveBuffers& b, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_accum, dim3(b.n_units), dim3(256), 0, st, b.work, b.X,
+                     (const float*)b.D);
+  hipLaunchKernelGGL(k_resid, dim3(b.n_units), dim3(WG), 0, st, c, cf, b.work, b.X, b.tgt,
+                     (float*)b.R, (float*)b.Y, (float*)b.D, b.part);
+  reduce(b, 0, 1, S, st);
+  hipLaunchKernelGGL(k_finalize_mixed, dim3(b.n_act), dim3(S), 0, st, b.X, b.work.plans, b.act,
+                     b.tgt, b.W, b.state, out, b.pos);
   return hipGetLastError();
-}
-
-__global__ void k_set_identity(float* __restrict__ Tm) {
-  for (int e = threadIdx.x; e < S * S; e += blockDim.x) Tm[e] = (e / S == e % S) ? 1.0f : 0.0f;
 }
 
 hipError_t launch_restart(const Coef<float>& cf, const SolveBuffers& b, bool indep,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(S), 0, st, b.state);
-  const int G = grid_for(cf.n);
+  hipLaunchKernelGGL(k_reset_state, dim3(b.n_act), dim3(S), 0, st, b.act, b.state);
   if (indep) {
     // T = I: the independent variant needs no orthonormalisation.
-    hipLaunchKernelGGL(k_set_identity, dim3(1), dim3(256), 0, st, (float*)b.Tm);
+    hipLaunchKernelGGL(k_set_identity, dim3(b.n_act), dim3(256), 0, st, b.act, (float*)b.Tm);
   } else {
-    hipLaunchKernelGGL((k_gram_dy<float>), dim3(G), dim3(WG), 0, st, cf, (const float*)b.Y,
-                       b.part);
-    hipLaunchKernelGGL(k_reduce, dim3((S * S + 63) / 64), dim3(256), 0, st, b.part, b.W, G, 3,
-                       1, S * S);
-    hipLaunchKernelGGL((k_small3<float>), dim3(1), dim3(SM_THREADS), 0, st, b.W, (float*)b.Tm,
-                       b.state, 1e-6, 1e-12);
+    hipLaunchKernelGGL((k_gram_dy<float>), dim3(b.n_units), dim3(WG), 0, st, cf, b.work,
+                       (const float*)b.Y, b.part);
+    reduce(b, 3, 1, S * S, st);
+    hipLaunchKernelGGL((k_small3<float>), dim3(b.n_act), dim3(SM_THREADS), 0, st, b.W, b.act,
+                       (float*)b.Tm, b.state, 1e-6, 1e-12);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_plain(const SolveBuffers& b, double* out, const int64_t* pos,
-                                 hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_plain, dim3(1), dim3(S), 0, st, b.state, out, pos);
+hipError_t launch_finalize_plain(const SolveBuffers& b, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_plain, dim3(b.n_act), dim3(S), 0, st, b.act, b.state, out, b.pos);
+  return hipGetLastError();
+}
+
+hipError_t launch_cross_gram(const Coef<double>& c, const double* Xa, const double* Xb,
+                             const SolveBuffers& b, hipStream_t st) {
+  hipLaunchKernelGGL((k_cross_gram<double>), dim3(b.n_units), dim3(WG), 0, st, c, b.work, Xa, Xb,
+                     b.part);
+  reduce(b, 0, 1, S * S, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const double* X, const int64_t* nodes, int64_t count,
+                              double* rows, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((count * S + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_gather_rows, dim3(blocks), dim3(256), 0, st, X, nodes, count, rows);
   return hipGetLastError();
 }
 

@@ -87,3 +87,40 @@ def test_disconnected_tier_rejected():
         reff.reff_build_pdn(d)
     assert ei.value.status == reff.REFF_ERR_DISCONNECTED
     assert "no resistive path" in reff.reff_last_error()
+
+
+@pytest.mark.parametrize("case", ["bad_plan", "disconnected", "node_range", "surrogate"])
+def test_batch_rejected_on_host(case):
+    """reff_batch_plans validates every plan, node list and option before
+    any device work (so these run without a GPU)."""
+    from paper_2607_05818_amd import reff
+    good = gen.config1()
+    plans = [good, _bad(good)]
+    nodes = [np.array([3, 4], dtype=np.int64), np.array([5], dtype=np.int64)]
+    if case == "bad_plan":
+        plans[1]["gy"][0, 0, 0] = 0.0
+        want = reff.REFF_ERR_INVALID_ARG
+    elif case == "disconnected":
+        plans[1] = _bad(good, tsv_xy=np.zeros((0, 2), dtype=np.int32), tsv_g=np.zeros((0, 1)))
+        want = reff.REFF_ERR_DISCONNECTED
+    elif case == "node_range":
+        nodes[1] = np.array([gen.n_nodes(good)], dtype=np.int64)
+        want = reff.REFF_ERR_INVALID_ARG
+    else:
+        want = reff.REFF_ERR_UNSUPPORTED
+    if case == "surrogate":
+        structs = (reff.reff_pdn_desc * 1)()
+        s, keep = reff._desc_struct(good)
+        structs[0] = s
+        out = np.zeros(2)
+        nptr = (C.c_void_p * 1)(nodes[0].ctypes.data)
+        cnt = (C.c_int64 * 1)(2)
+        optr = (C.c_void_p * 1)(out.ctypes.data)
+        bo = reff.reff_batch_opts()
+        bo.surrogate = C.c_void_p(1)
+        st = reff._lib.reff_batch_plans(structs, 1, nptr, cnt, optr, C.byref(bo), None)
+        assert st == want
+        return
+    with pytest.raises(reff.ReffError) as ei:
+        reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_FP64)
+    assert ei.value.status == want

@@ -1,0 +1,109 @@
+"""Many TSV plans in one call (reff_batch_plans) against the oracle and
+against one-plan-at-a-time solves (design-option exploration, Sec. I and
+Sec. IV-B).
+
+Tolerances: 1e-6 relative in float64, 1e-3 mixed; pads give exactly 0."""
+import numpy as np
+import pytest
+
+from oracle import reff_oracle as ro
+from paper_2607_05818_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _reff():
+    from paper_2607_05818_amd import reff
+    return reff
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _rel(got, want):
+    got = np.asarray(got)
+    want = np.asarray(want)
+    zero = want == 0
+    assert np.all(got[zero] == 0.0)
+    m = ~zero
+    return float(np.max(np.abs(got[m] - want[m]) / want[m])) if m.any() else 0.0
+
+
+def _small_plans(k=5):
+    """Reduced-size plans of the batching recipe (2-4 tiers, sides 40-72,
+    U[0.5,2] S edges, 10 S TSV columns, pads at pitch 32 or 16)."""
+    return gen.config3_plans(seed=77, n_plans=k, side_lo=40, side_hi=72)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-3)], ids=["fp64", "mixed"])
+def test_batch_matches_oracle(prec, tol):
+    reff = _reff()
+    plans = _small_plans(5)
+    nodes = []
+    for i, d in enumerate(plans):
+        s = gen.sample_free_nodes(d, 150, 100 + i)
+        s = np.concatenate([s, gen.pad_ids(d)[:2], s[:3]])  # pads and duplicates
+        nodes.append(s)
+    _say("batch 5 plans prec", prec)
+    outs, stats = reff.reff_batch_plans(plans, nodes, precision=prec,
+                                        rel_tol=1e-9 if prec == 0 else 1e-5)
+    for i, d in enumerate(plans):
+        want = ro.diag(d, nodes[i])
+        err = _rel(outs[i], want)
+        print("plan", i, "n", gen.n_nodes(d), "err", err, stats[i]["iters_total"], flush=True)
+        assert err <= tol
+        assert stats[i]["n_solved"] == len(np.unique(nodes[i])) - 2
+
+
+def test_batch_equals_single_plan_solves():
+    """A plan solved inside a batch gives the single-plan result to within
+    the solver tolerance (blocks are dealt identically; only the launch
+    grouping differs)."""
+    reff = _reff()
+    plans = _small_plans(3)
+    nodes = [gen.sample_free_nodes(d, 64, 300 + i) for i, d in enumerate(plans)]
+    outs, _ = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_FP64,
+                                    rel_tol=1e-10)
+    for i, d in enumerate(plans):
+        h = reff.reff_build_pdn(d)
+        one, _ = reff.reff_solve_diag(h, nodes[i], precision=reff.REFF_PREC_FP64,
+                                      rel_tol=1e-10)
+        assert np.max(np.abs(outs[i] - one) / one) <= 1e-8
+
+
+def test_batch_edge_cases_and_device_output():
+    """An empty node list, an all-pads list, a whole tiny stack (independent
+    columns forced for small stacks) and device outputs."""
+    import torch
+    reff = _reff()
+    tiny = gen.small_random_desc(31, 2, 9, 7, 4, 3)
+    plans = _small_plans(2) + [tiny, tiny]
+    nodes = [np.array([], dtype=np.int64), gen.pad_ids(plans[1])[:3], None,
+             np.array([5, 5, 60, 0], dtype=np.int64)]
+    counts = [0, 3, gen.n_nodes(tiny), 4]
+    outs = [torch.full((c,), -1.0, dtype=torch.float64, device="cuda") for c in counts]
+    _say("batch edge cases")
+    reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_FP64, rel_tol=1e-10,
+                          R_out=outs)
+    torch.cuda.synchronize()
+    got = [o.cpu().numpy() for o in outs]
+    assert got[0].size == 0
+    assert np.all(got[1] == 0.0)
+    assert _rel(got[2], ro.diag(tiny, np.arange(gen.n_nodes(tiny)))) <= 1e-6
+    assert _rel(got[3], ro.diag(tiny, nodes[3])) <= 1e-6
+
+
+def test_batch_recipe_sizes_sampled():
+    """Eight plans drawn by the full batching recipe (sides 64-256), 64
+    sampled nodes each, mixed precision, against the oracle."""
+    reff = _reff()
+    plans = gen.config3_plans(n_plans=8)
+    nodes = [gen.sample_free_nodes(d, 64, 500 + i) for i, d in enumerate(plans)]
+    _say("batch recipe 8 plans")
+    outs, stats = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_MIXED,
+                                        rel_tol=1e-4)
+    for i, d in enumerate(plans):
+        err = _rel(outs[i], ro.diag(d, nodes[i]))
+        print("plan", i, gen.n_nodes(d), err, stats[i]["iters_total"], flush=True)
+        assert err <= 1e-3
