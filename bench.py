@@ -82,6 +82,75 @@ def cpu_baseline(desc, batch_nodes, n_timed=2):
     }
 
 
+def batched_compare(reff, gen, log, rel_tol, n_seq=16):
+    """The batching workload: 256 candidate TSV plans (2-4 tiers, sides
+    64-256, about 22M nodes in total) with one seeded 64-node block per
+    plan, solved in one reff_batch_plans call (mixed precision), against
+    one reff_build_pdn + reff_solve_diag per plan on the first n_seq plans
+    (extrapolated).  Accuracy is checked on the plans the stored oracle
+    fixture covers."""
+    import numpy as np
+    import torch
+    plans = gen.config3_plans()
+    nodes = gen.config3_samples(plans)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "config3_sample.json")))
+    total = sum(len(x) for x in nodes)
+    prec = reff.REFF_PREC_MIXED
+    # first call on a few plans: lazy runtime initialisation
+    reff.reff_batch_plans(plans[:4], nodes[:4], precision=prec, rel_tol=rel_tol)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    outs, stats = reff.reff_batch_plans(plans, nodes, precision=prec, rel_tol=rel_tol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - a
+    errs = []
+    for i in range(len(gold["nodes"])):
+        assert list(nodes[i]) == gold["nodes"][i], "batching sample drifted from the fixture"
+        want = np.array(gold["R"][i])
+        errs.append(float(np.max(np.abs(outs[i] - want) / want)))
+    a = time.perf_counter()
+    for i in range(n_seq):
+        h = reff.reff_build_pdn(plans[i])
+        reff.reff_solve_diag(h, nodes[i], precision=prec, rel_tol=rel_tol)
+        h.close()
+    torch.cuda.synchronize()
+    dseq = time.perf_counter() - a
+    seq_nodes = sum(len(nodes[i]) for i in range(n_seq))
+    rec = {
+        "workload": "256 TSV plans, 2-4 tiers x side 64-256 (%d nodes), 64 seeded nodes per plan"
+                    % sum(gen.n_nodes(d) for d in plans),
+        "nodes_per_s": total / dt, "seconds": dt, "nodes": total,
+        "iters_max": max(x["iters_max"] for x in stats),
+        "checked_plans": len(errs), "max_rel_err_checked": max(errs),
+        "est_max_rel_err": max(x["est_max_rel_err"] for x in stats),
+        "sequential_nodes_per_s": seq_nodes / dseq, "sequential_plans_timed": n_seq,
+        "rel_tol": rel_tol,
+    }
+    log(f"batched: {total / dt:.1f} nodes/s ({dt:.2f} s), sequential {seq_nodes / dseq:.1f} "
+        f"nodes/s, checked err {max(errs):.2e}")
+    return rec
+
+
+def measured_traffic():
+    """HBM bytes per node row of the block kernels from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "block_pcg_mixed_4x512x512_hbm_traffic.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"```json\n(.*?)```", text, re.S).group(1))
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+    except (OSError, AttributeError, ValueError, KeyError):
+        return None
+    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
+        return None
+    return rec["hbm_bytes_per_row"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,7 +162,22 @@ def main():
     ap.add_argument("--krylov", choices=["block", "indep"], default="block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy kernel 4 times (the "
+                         "reference point for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes,
+                          "launches": 4}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(solves shard by node blocks; see the design notes)", file=sys.stderr)
@@ -134,6 +218,7 @@ def main():
     torch.cuda.synchronize()
     kms = np.zeros(3)
     kl = np.zeros(3, dtype=np.int64)
+    krows = np.zeros(3, dtype=np.int64)
     iters = 0
     worst = 0.0
     n_ok = 0
@@ -142,6 +227,7 @@ def main():
         st = step(True)
         kms += np.array(st["kernel_ms"])
         kl += np.array(st["kernel_launches"], dtype=np.int64)
+        krows += np.array(st["kernel_rows"], dtype=np.int64)
         iters += st["iters_total"]
         log(f"step {k}: {st['iters_total']} iterations, {st['seconds']:.2f} s")
     torch.cuda.synchronize()
@@ -154,17 +240,26 @@ def main():
     value = n_ok * args.steps / elapsed
 
     fp32 = args.precision == "mixed"
-    kb = kernel_bytes(n, fp32=fp32, mixed_with_d=fp32)
+    kb = kernel_bytes(1, fp32=fp32, mixed_with_d=fp32)
     names = ["stencil_gram", "update_r", "update_y"]
     kern = {}
     for i, nm in enumerate(names):
         avg_ms = kms[i] / max(kl[i], 1)
+        # A launch streams every unconverged block of the group: bytes per
+        # launch = bytes per node row x rows streamed / launches.
+        per_launch = kb[i] * krows[i] / max(kl[i], 1)
         kern[nm] = {"avg_us": avg_ms * 1e3, "launches": int(kl[i]),
-                    "alg_bytes": int(kb[i]), "GBps": kb[i] / (avg_ms * 1e-3) / 1e9}
+                    "rows_per_launch": krows[i] / max(kl[i], 1),
+                    "alg_bytes_per_row": int(kb[i]), "alg_bytes_per_launch": per_launch,
+                    "GBps": per_launch / (avg_ms * 1e-3) / 1e9}
     dom = max(range(3), key=lambda i: kms[i])
     dk = kern[names[dom]]
+    mt = measured_traffic() if fp32 else None
+    traffic = None
+    if mt is not None:
+        traffic = mt[names[dom]] * krows[dom] / max(kl[dom], 1)
     roofline = {"bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dk["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                "frac": dk["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": names[dom]}
 
     compare = {}
@@ -185,6 +280,9 @@ def main():
             compare[tag] = {"nodes_per_s": S / dt, "iters": st2["iters_total"],
                             "max_rel_err": e2, "rel_tol": tol}
             log(f"{tag}: {S / dt:.1f} nodes/s, {st2['iters_total']} iterations, err {e2:.2e}")
+
+    if not args.no_batched and args.precision == "mixed":
+        compare["batched_plans"] = batched_compare(reff, gen, log, args.rel_tol)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -104,9 +104,12 @@ typedef struct {
   int64_t iters_total;    /* sum of block iterations over all blocks         */
   /* With opts->timing: summed device time (ms) and launch count of the
      stencil+Gram kernel [0], the residual-update kernel [1] and the
-     search-block kernel [2]. */
+     search-block kernel [2], and the node rows those launches streamed
+     (one row = one node of one 64-column block; a launch covers every
+     unconverged block of its group). */
   double kernel_ms[3];
   int64_t kernel_launches[3];
+  int64_t kernel_rows[3];
 } reff_solve_stats;
 
 /*

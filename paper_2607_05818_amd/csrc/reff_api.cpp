@@ -557,12 +557,18 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     std::vector<int32_t> irs((size_t)nb, 0);
     std::vector<int> active(nb);
     for (int i = 0; i < nb; ++i) active[(size_t)i] = i;
+    auto rows_of = [&](const std::vector<int>& a) {
+      int64_t r = 0;
+      for (int bi : a) r += plans[(size_t)bi].n;
+      return r;
+    };
     int ir = 0;
     while (true) {
       // ---- inner block-PCG iterations over the active blocks
       int it = 0;
       while (it < o.max_iters && !active.empty()) {
         const int k = std::min(poll, o.max_iters - it);
+        const int64_t act_rows = rows_of(active);
         for (int i = 0; i < k; ++i)
           HIPCHK(launch_iteration(fp32, o.indep, with_d, coef, b, o.tol, o.stream,
                                   o.timing ? &evp.ev[6 * i] : nullptr));
@@ -580,6 +586,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
               HIPCHK(hipEventElapsedTime(&ms, evp.ev[6 * i + 2 * kk], evp.ev[6 * i + 2 * kk + 1]));
               st->kernel_ms[kk] += ms;
               st->kernel_launches[kk] += 1;
+              st->kernel_rows[kk] += act_rows;
             }
         }
         // flags of every block (gathered into a small device array)
@@ -1165,6 +1172,7 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
         for (int k = 0; k < 3; ++k) {
           ps.kernel_ms[k] = agg.kernel_ms[k];
           ps.kernel_launches[k] = agg.kernel_launches[k];
+          ps.kernel_rows[k] = agg.kernel_rows[k];
         }
     }
   }

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "cell_centred", "make_desc", "config1", "config2", "config3_plans",
     "config4_plan", "config5", "sample_free_nodes", "pad_ids", "n_nodes",
-    "CONFIG_SEEDS", "small_random_desc",
+    "CONFIG_SEEDS", "small_random_desc", "config3_samples",
 ]
 
 CONFIG_SEEDS = {1: 1001, 2: 1002, 3: 1003, 4: 1004, 5: 1005}
@@ -175,7 +175,14 @@ def config5(seed: int = CONFIG_SEEDS[5], side: int = 2048, n_tiers: int = 8) -> 
     return make_desc(nt, nx, ny, gx, gy, tsv_xy, tsv_g, pad_xy)
 
 
-def sample_free_nodes(desc, count: int, seed: int) -> np.ndarray:
+def config3_samples(plans, per_plan: int = 64, seed: int = CONFIG_SEEDS[3]) -> list:
+    """One seeded block of per_plan free nodes for each batching plan
+    (plan i draws with the seed sequence [seed, i])."""
+    return [sample_free_nodes(d, per_plan, np.random.SeedSequence([seed, i]))
+            for i, d in enumerate(plans)]
+
+
+def sample_free_nodes(desc, count: int, seed) -> np.ndarray:
     """count distinct non-pad node ids drawn uniformly (seeded), in draw
     order, so that every prefix is itself a uniform sample."""
     rng = np.random.default_rng(seed)

@@ -72,7 +72,7 @@ class reff_solve_stats(C.Structure):
         ("n_solved", C.c_int64), ("n_unconverged", C.c_int64), ("iters_max", C.c_int32),
         ("ir_steps", C.c_int32), ("seconds", C.c_double), ("est_max_rel_err", C.c_double),
         ("iters_total", C.c_int64), ("kernel_ms", C.c_double * 3),
-        ("kernel_launches", C.c_int64 * 3),
+        ("kernel_launches", C.c_int64 * 3), ("kernel_rows", C.c_int64 * 3),
     ]
 
     def as_dict(self):
@@ -261,7 +261,8 @@ def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
 
 
 def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.0,
-                     max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None, R_out=None):
+                     max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None, R_out=None,
+                     timing=False):
     """Solve many plans in one call.  Returns (list of R arrays, list of stats)."""
     k = len(plans)
     structs = (reff_pdn_desc * k)()
@@ -296,7 +297,7 @@ def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.
             optrs[i] = o.ctypes.data
             outs.append(o)
     bo = reff_batch_opts()
-    bo.solve = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, 0)
+    bo.solve = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, 0, timing)
     stats = (reff_solve_stats * k)()
     _check(_lib.reff_batch_plans(structs, k, nptrs, ncount, optrs, C.byref(bo), stats))
     return outs, [stats[i].as_dict() for i in range(k)]

@@ -37,8 +37,31 @@ def config2_sample():
     }
 
 
+N_PLANS3 = 8
+
+
+def config3_sample():
+    plans = gen.config3_plans()
+    nodes = gen.config3_samples(plans)
+    t0 = time.time()
+    R = [ro.diag(plans[i], nodes=nodes[i]) for i in range(N_PLANS3)]
+    dt = time.time() - t0
+    return {
+        "what": "R_i = (G^-1)_ii, float64 oracle (sparse LU), first batching plans",
+        "inputs": ("plans = gen.config3_plans(seed=1003); nodes = gen.config3_samples(plans); "
+                   "plans 0..7"),
+        "oracle_seconds": dt,
+        "nodes": [[int(v) for v in nodes[i]] for i in range(N_PLANS3)],
+        "R": [[float(r) for r in R[i]] for i in range(N_PLANS3)],
+    }
+
+
 if __name__ == "__main__":
-    out = config2_sample()
-    with open(os.path.join(HERE, "config2_sample.json"), "w") as f:
-        json.dump(out, f, indent=0)
-    print("wrote config2_sample.json", out["oracle_seconds"])
+    which = sys.argv[1:] or ["config2", "config3"]
+    for name, fn in (("config2", config2_sample), ("config3", config3_sample)):
+        if name not in which:
+            continue
+        out = fn()
+        with open(os.path.join(HERE, name + "_sample.json"), "w") as f:
+            json.dump(out, f, indent=0)
+        print("wrote", name + "_sample.json", out["oracle_seconds"])
