@@ -110,6 +110,12 @@ typedef struct {
   double kernel_ms[3];
   int64_t kernel_launches[3];
   int64_t kernel_rows[3];
+  /* reff_batch_plans with a surrogate: 1 if the plan's results are the
+     model's predictions (solved values at the checked nodes), 0 if it fell
+     back to the solver; the largest relative error of the prediction over
+     the checked nodes. */
+  int32_t screened;
+  double spot_max_rel_err;
 } reff_solve_stats;
 
 /*
@@ -162,10 +168,15 @@ reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m,
 
 typedef struct {
   reff_solve_opts solve;   /* precision, tolerance, stream, out_on_device   */
-  const void* surrogate;   /* reserved; must be NULL                        */
-  double spot_frac;        /* reserved                                       */
-  double fallback_rel_err; /* reserved                                       */
-  const char* tune_db;     /* reserved                                       */
+  const void* surrogate;   /* NULL: solve every node.  A reff_surrogate
+                              (reff_surrogate.h) whose geometry every plan
+                              matches: screen the batch with it            */
+  double spot_frac;        /* screened: fraction of each plan's requested
+                              free nodes checked by the solver (seeded
+                              choice, at least one); 0 => 0.01             */
+  double fallback_rel_err; /* screened: a plan whose checked relative error
+                              exceeds this is solved in full; 0 => 1e-2    */
+  const char* tune_db;     /* reserved; must be NULL                        */
 } reff_batch_opts;
 
 /*
@@ -173,7 +184,10 @@ typedef struct {
  * and Sec. IV-B).  plans[i] is validated and solved like reff_build_pdn +
  * reff_solve_diag; nodes[i] (host, NULL => all) and n_nodes[i] select the
  * nodes of plan i and R_out[i] receives them.  per_plan (nullable) gets one
- * stats record per plan.
+ * stats record per plan.  The solve blocks of all plans advance together in
+ * the same kernel launches.  With opts->surrogate the batch is screened
+ * (see reff_batch_opts); results of screened plans carry the model's error,
+ * not the solver tolerance.
  */
 reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
                              const int64_t* const* nodes, const int64_t* n_nodes,

@@ -10,11 +10,13 @@
 #include <cstring>
 #include <deque>
 #include <new>
+#include <numeric>
 #include <random>
 #include <string>
 #include <vector>
 
 #include "reff_internal.h"
+#include "surrogate_internal.h"
 
 using namespace reff;
 
@@ -85,6 +87,15 @@ reff_status validate_desc(const reff_pdn_desc* d) {
   }
   return REFF_OK;
 }
+
+}  // namespace
+
+namespace reff {
+reff_status host_fail(reff_status s, const std::string& msg) { return fail(s, msg); }
+reff_status host_validate_desc(const reff_pdn_desc* d) { return validate_desc(d); }
+}  // namespace reff
+
+namespace {
 
 // Host-side stencil coefficients in float64 (see Coef in reff_internal.h).
 struct HostCoef {
@@ -1069,6 +1080,136 @@ reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m, const int6
   return REFF_OK;
 }
 
+// Screening of a batch with the learned model: predict every plan's map,
+// solve a seeded fraction of each plan's requested free nodes, and fall back
+// to solving all requested nodes of a plan whose checked relative error
+// exceeds fb_err.  Solved values replace predictions wherever they exist.
+static reff_status screen_plans(reff_surrogate sg, const reff_pdn_desc* plans, int32_t n_plans,
+                                Workspace& ws, const CoefSet& cs,
+                                const std::vector<StackInfo>& stacks,
+                                const std::vector<std::vector<int64_t>>& cols,
+                                const std::vector<std::vector<int64_t>>& maps,
+                                double* const* R_out, const Opts& o, double spot_frac,
+                                double fb_err, reff_solve_stats* per_plan,
+                                std::chrono::steady_clock::time_point t0) {
+  const int64_t per = stacks[0].n;  // every plan has the model's geometry
+  reff_status rs = ensure(ws.xs, (size_t)n_plans * per * sizeof(double));
+  if (rs != REFF_OK) return rs;
+  rs = reffsg::predict_device(sg, plans, n_plans, (double*)ws.xs.p, o.stream);
+  if (rs != REFF_OK) return rs;
+  std::vector<double> pred((size_t)(n_plans * per));
+  HIPCHK(hipMemcpyAsync(pred.data(), ws.xs.p, pred.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        o.stream));
+  HIPCHK(hipStreamSynchronize(o.stream));
+  // values[i][j] = result for cols[i][j]
+  std::vector<std::vector<double>> values((size_t)n_plans);
+  std::vector<std::vector<int64_t>> spot_idx((size_t)n_plans);  // indices into cols[i]
+  std::vector<BlockJob> sjobs;
+  std::vector<size_t> sjob0((size_t)n_plans + 1);
+  std::vector<int64_t> spos0((size_t)n_plans);
+  int64_t spos = 0;
+  for (int32_t i = 0; i < n_plans; ++i) {
+    const auto& c = cols[(size_t)i];
+    values[(size_t)i].resize(c.size());
+    for (size_t j = 0; j < c.size(); ++j)
+      values[(size_t)i][j] = pred[(size_t)(i * per + c[j])];
+    sjob0[(size_t)i] = sjobs.size();
+    spos0[(size_t)i] = spos;
+    if (c.empty()) continue;
+    const size_t k = std::max<size_t>(
+        1, std::min(c.size(), (size_t)std::ceil(spot_frac * (double)c.size() - 1e-9)));
+    std::vector<int64_t> order(c.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::mt19937_64 rng(0x5eedull * 1000003ull + (uint64_t)i);
+    std::shuffle(order.begin(), order.end(), rng);
+    order.resize(k);
+    spot_idx[(size_t)i] = order;
+    std::vector<int64_t> ids(k);
+    for (size_t j = 0; j < k; ++j) ids[j] = c[(size_t)order[j]];
+    deal_blocks(ids, i, spos, sjobs);
+    spos += (int64_t)k;
+  }
+  sjob0[(size_t)n_plans] = sjobs.size();
+  std::vector<BlockResult> sbr, fbr;
+  reff_solve_stats agg;
+  std::memset(&agg, 0, sizeof(agg));
+  if ((rs = ensure(ws.out, (size_t)(spos + 1) * sizeof(double))) != REFF_OK) return rs;
+  reff_status solve_rs = run_blocks(ws, cs, stacks, sjobs, (double*)ws.out.p, o, sbr, &agg);
+  if (solve_rs != REFF_OK && solve_rs != REFF_ERR_NO_CONVERGENCE) return solve_rs;
+  std::vector<double> spot((size_t)spos);
+  if (spos > 0)
+    HIPCHK(hipMemcpyAsync(spot.data(), ws.out.p, (size_t)spos * sizeof(double),
+                          hipMemcpyDeviceToHost, o.stream));
+  HIPCHK(hipStreamSynchronize(o.stream));
+  std::vector<double> err((size_t)n_plans, 0.0);
+  std::vector<char> fallback((size_t)n_plans, 0);
+  std::vector<BlockJob> fjobs;
+  std::vector<size_t> fjob0((size_t)n_plans + 1);
+  std::vector<int64_t> fpos0((size_t)n_plans, -1);
+  int64_t fpos = 0;
+  for (int32_t i = 0; i < n_plans; ++i) {
+    const auto& si = spot_idx[(size_t)i];
+    for (size_t j = 0; j < si.size(); ++j) {
+      const double r = spot[(size_t)(spos0[(size_t)i] + (int64_t)j)];
+      double& v = values[(size_t)i][(size_t)si[j]];
+      err[(size_t)i] = std::max(err[(size_t)i], std::fabs(v - r) / r);
+      v = r;
+    }
+    fallback[(size_t)i] = !(err[(size_t)i] <= fb_err);
+    fjob0[(size_t)i] = fjobs.size();
+    if (fallback[(size_t)i] && !cols[(size_t)i].empty()) {
+      fpos0[(size_t)i] = fpos;
+      deal_blocks(cols[(size_t)i], i, fpos, fjobs);
+      fpos += (int64_t)cols[(size_t)i].size();
+    }
+  }
+  fjob0[(size_t)n_plans] = fjobs.size();
+  if (!fjobs.empty()) {
+    if ((rs = ensure(ws.out, (size_t)(fpos + 1) * sizeof(double))) != REFF_OK) return rs;
+    reff_status frs = run_blocks(ws, cs, stacks, fjobs, (double*)ws.out.p, o, fbr, &agg);
+    if (frs != REFF_OK && frs != REFF_ERR_NO_CONVERGENCE) return frs;
+    if (frs == REFF_ERR_NO_CONVERGENCE) solve_rs = frs;
+    std::vector<double> fres((size_t)fpos);
+    HIPCHK(hipMemcpyAsync(fres.data(), ws.out.p, (size_t)fpos * sizeof(double),
+                          hipMemcpyDeviceToHost, o.stream));
+    HIPCHK(hipStreamSynchronize(o.stream));
+    for (int32_t i = 0; i < n_plans; ++i)
+      if (fpos0[(size_t)i] >= 0)
+        for (size_t j = 0; j < cols[(size_t)i].size(); ++j)
+          values[(size_t)i][j] = fres[(size_t)(fpos0[(size_t)i] + (int64_t)j)];
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int32_t i = 0; i < n_plans; ++i) {
+    const auto& mp = maps[(size_t)i];
+    std::vector<double> outv(mp.size());
+    for (size_t j = 0; j < mp.size(); ++j)
+      outv[j] = mp[j] >= 0 ? values[(size_t)i][(size_t)mp[j]] : 0.0;
+    if (!outv.empty()) {
+      if (o.out_dev) {
+        HIPCHK(hipMemcpyAsync(R_out[i], outv.data(), outv.size() * sizeof(double),
+                              hipMemcpyHostToDevice, o.stream));
+        HIPCHK(hipStreamSynchronize(o.stream));
+      } else {
+        std::memcpy(R_out[i], outv.data(), outv.size() * sizeof(double));
+      }
+    }
+    if (per_plan) {
+      reff_solve_stats& ps = per_plan[i];
+      std::memset(&ps, 0, sizeof(ps));
+      ps.n_solved = (int64_t)spot_idx[(size_t)i].size() +
+                    (fallback[(size_t)i] ? (int64_t)cols[(size_t)i].size() : 0);
+      add_stats(&ps, sbr, sjob0[(size_t)i], sjob0[(size_t)i + 1]);
+      add_stats(&ps, fbr, fjob0[(size_t)i], fjob0[(size_t)i + 1]);
+      ps.seconds = secs;
+      ps.screened = fallback[(size_t)i] ? 0 : 1;
+      ps.spot_max_rel_err = err[(size_t)i];
+    }
+  }
+  if (solve_rs == REFF_ERR_NO_CONVERGENCE)
+    return fail(REFF_ERR_NO_CONVERGENCE, "max_iters reached; R_out holds lower bounds");
+  return REFF_OK;
+}
+
 reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
                              const int64_t* const* nodes, const int64_t* n_nodes,
                              double* const* R_out, const reff_batch_opts* opts,
@@ -1078,10 +1219,20 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
   if (n_plans < 0) return fail(REFF_ERR_INVALID_ARG, "n_plans < 0");
   if (n_plans == 0) return REFF_OK;
   if (!plans || !R_out) return fail(REFF_ERR_INVALID_ARG, "NULL plans or R_out");
-  if (opts && opts->surrogate) return fail(REFF_ERR_UNSUPPORTED, "surrogate screening not available");
   Opts o;
   reff_status s = parse_opts(opts ? &opts->solve : nullptr, o);
   if (s != REFF_OK) return s;
+  if (opts && opts->tune_db) return fail(REFF_ERR_UNSUPPORTED, "tune_db is reserved and must be NULL");
+  reff_surrogate sg = opts ? (reff_surrogate)opts->surrogate : nullptr;
+  double spot_frac = 0.01, fb_err = 1e-2;
+  if (sg) {
+    if (opts->spot_frac != 0.0) spot_frac = opts->spot_frac;
+    if (opts->fallback_rel_err != 0.0) fb_err = opts->fallback_rel_err;
+    if (!(spot_frac > 0.0 && spot_frac <= 1.0))
+      return fail(REFF_ERR_INVALID_ARG, "spot_frac must be in (0, 1]");
+    if (!(fb_err > 0.0) || !std::isfinite(fb_err))
+      return fail(REFF_ERR_INVALID_ARG, "fallback_rel_err must be finite and > 0");
+  }
   // Validate every plan (and its node list) before any device work.
   std::vector<const reff_pdn_desc*> ds((size_t)n_plans);
   std::vector<std::vector<int64_t>> gnds((size_t)n_plans);
@@ -1100,6 +1251,9 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
       return fail(REFF_ERR_INVALID_ARG, "plan " + std::to_string(i) + ": bad n_nodes");
     const int64_t cnt = given ? n_nodes[i] : stacks[(size_t)i].n;
     if (cnt > 0 && !R_out[i]) return fail(REFF_ERR_INVALID_ARG, "plan " + std::to_string(i) + ": R_out NULL");
+    if (sg && !reffsg::geometry_matches(sg, &plans[i]))
+      return fail(REFF_ERR_INVALID_ARG,
+                  "plan " + std::to_string(i) + " does not match the surrogate's geometry");
     if (given)
       for (int64_t k = 0; k < cnt; ++k)
         if (nodes[i][k] < 0 || nodes[i][k] >= stacks[(size_t)i].n)
@@ -1150,6 +1304,9 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
     Workspace& w;
     ~Rel() { w.release(); }
   } rel{ws};
+  if (sg)
+    return screen_plans(sg, plans, n_plans, ws, cs, stacks, cols, maps, R_out, o, spot_frac,
+                        fb_err, per_plan, t0);
   reff_status rs = ensure(ws.out, (size_t)(pos0 + 1) * sizeof(double));
   if (rs != REFF_OK) return rs;
   std::vector<BlockResult> br;

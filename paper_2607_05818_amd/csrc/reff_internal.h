@@ -12,6 +12,11 @@
 
 namespace reff {
 
+// Set the calling thread's reff_last_error() text and return s.
+reff_status host_fail(reff_status s, const std::string& msg);
+// The stack validation every entry point performs before device work.
+reff_status host_validate_desc(const reff_pdn_desc* d);
+
 constexpr int S = 64;        // right-hand sides per block (one per lane)
 constexpr int CH = 32;       // nodes per LDS chunk in the block kernels
 constexpr int WG = 512;      // threads per workgroup of the block kernels

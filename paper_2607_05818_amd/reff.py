@@ -46,6 +46,10 @@ REFF_PAIRS_FLOATING = 1
 EXPORTED = [
     "reff_build_pdn", "reff_free_pdn", "reff_pdn_num_nodes", "reff_solve_diag",
     "reff_query_pairs", "reff_batch_plans", "reff_status_string", "reff_last_error",
+    "reff_surrogate_create", "reff_surrogate_free", "reff_surrogate_num_params",
+    "reff_surrogate_get_params", "reff_surrogate_set_params", "reff_surrogate_loss_grad",
+    "reff_surrogate_train", "reff_surrogate_predict", "reff_surrogate_save",
+    "reff_surrogate_load",
 ]
 
 
@@ -73,6 +77,7 @@ class reff_solve_stats(C.Structure):
         ("ir_steps", C.c_int32), ("seconds", C.c_double), ("est_max_rel_err", C.c_double),
         ("iters_total", C.c_int64), ("kernel_ms", C.c_double * 3),
         ("kernel_launches", C.c_int64 * 3), ("kernel_rows", C.c_int64 * 3),
+        ("screened", C.c_int32), ("spot_max_rel_err", C.c_double),
     ]
 
     def as_dict(self):
@@ -262,7 +267,7 @@ def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
 
 def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.0,
                      max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None, R_out=None,
-                     timing=False):
+                     timing=False, surrogate=None, spot_frac=0.0, fallback_rel_err=0.0):
     """Solve many plans in one call.  Returns (list of R arrays, list of stats)."""
     k = len(plans)
     structs = (reff_pdn_desc * k)()
@@ -298,6 +303,170 @@ def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.
             outs.append(o)
     bo = reff_batch_opts()
     bo.solve = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, 0, timing)
+    if surrogate is not None:
+        bo.surrogate = surrogate.handle
+        bo.spot_frac = spot_frac
+        bo.fallback_rel_err = fallback_rel_err
     stats = (reff_solve_stats * k)()
     _check(_lib.reff_batch_plans(structs, k, nptrs, ncount, optrs, C.byref(bo), stats))
     return outs, [stats[i].as_dict() for i in range(k)]
+
+
+# ---------------------------------------------------------------- surrogate
+
+class reff_surrogate_config(C.Structure):
+    _fields_ = [("n_tiers", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("base_channels", C.c_int32), ("seed", C.c_uint64)]
+
+
+class reff_labels(C.Structure):
+    _fields_ = [("nodes", C.c_void_p), ("n_nodes", C.c_int64), ("R", C.c_void_p)]
+
+
+class reff_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+_lib.reff_surrogate_create.argtypes = [C.POINTER(reff_surrogate_config), C.c_int32,
+                                       C.POINTER(C.c_void_p)]
+_lib.reff_surrogate_create.restype = C.c_int
+_lib.reff_surrogate_free.argtypes = [C.c_void_p]
+_lib.reff_surrogate_free.restype = None
+_lib.reff_surrogate_num_params.argtypes = [C.c_void_p]
+_lib.reff_surrogate_num_params.restype = C.c_int64
+_lib.reff_surrogate_get_params.argtypes = [C.c_void_p, C.c_void_p]
+_lib.reff_surrogate_get_params.restype = C.c_int
+_lib.reff_surrogate_set_params.argtypes = [C.c_void_p, C.c_void_p]
+_lib.reff_surrogate_set_params.restype = C.c_int
+_lib.reff_surrogate_loss_grad.argtypes = [C.c_void_p, C.POINTER(reff_pdn_desc),
+                                          C.POINTER(reff_labels), C.c_int32,
+                                          C.POINTER(C.c_double), C.c_void_p]
+_lib.reff_surrogate_loss_grad.restype = C.c_int
+_lib.reff_surrogate_train.argtypes = [C.c_void_p, C.POINTER(reff_pdn_desc),
+                                      C.POINTER(reff_labels), C.c_int32,
+                                      C.POINTER(reff_train_opts), C.c_void_p]
+_lib.reff_surrogate_train.restype = C.c_int
+_lib.reff_surrogate_predict.argtypes = [C.c_void_p, C.POINTER(reff_pdn_desc), C.c_int32,
+                                        C.POINTER(C.c_void_p), C.c_int32]
+_lib.reff_surrogate_predict.restype = C.c_int
+_lib.reff_surrogate_save.argtypes = [C.c_void_p, C.c_char_p]
+_lib.reff_surrogate_save.restype = C.c_int
+_lib.reff_surrogate_load.argtypes = [C.c_char_p, C.c_int32, C.POINTER(C.c_void_p)]
+_lib.reff_surrogate_load.restype = C.c_int
+
+
+class Surrogate:
+    """Owning wrapper of a reff_surrogate handle."""
+
+    def __init__(self, handle, geometry):
+        self.handle = handle
+        self.geometry = geometry
+
+    def close(self):
+        if self.handle:
+            _lib.reff_surrogate_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _plan_structs(plans):
+    structs = (reff_pdn_desc * max(len(plans), 1))()
+    keep = []
+    for i, d in enumerate(plans):
+        s, kp = _desc_struct(d)
+        structs[i] = s
+        keep.append(kp)
+    return structs, keep
+
+
+def _label_structs(labels):
+    arr = (reff_labels * max(len(labels), 1))()
+    keep = []
+    for i, (nodes, R) in enumerate(labels):
+        n = np.ascontiguousarray(nodes, dtype=np.int64)
+        r = np.ascontiguousarray(R, dtype=np.float64)
+        assert n.shape == r.shape
+        keep += [n, r]
+        arr[i] = reff_labels(n.ctypes.data, len(n), r.ctypes.data)
+    return arr, keep
+
+
+def reff_surrogate_create(n_tiers, nx, ny, base_channels=32, seed=0, device=0) -> Surrogate:
+    cfg = reff_surrogate_config(n_tiers, nx, ny, base_channels, seed)
+    h = C.c_void_p()
+    _check(_lib.reff_surrogate_create(C.byref(cfg), device, C.byref(h)))
+    return Surrogate(h, (n_tiers, nx, ny))
+
+
+def reff_surrogate_free(s: Surrogate) -> None:
+    s.close()
+
+
+def reff_surrogate_num_params(s: Surrogate) -> int:
+    return int(_lib.reff_surrogate_num_params(s.handle))
+
+
+def reff_surrogate_get_params(s: Surrogate) -> np.ndarray:
+    out = np.empty(reff_surrogate_num_params(s), dtype=np.float32)
+    _check(_lib.reff_surrogate_get_params(s.handle, out.ctypes.data))
+    return out
+
+
+def reff_surrogate_set_params(s: Surrogate, params) -> None:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.size == reff_surrogate_num_params(s)
+    _check(_lib.reff_surrogate_set_params(s.handle, p.ctypes.data))
+
+
+def reff_surrogate_loss_grad(s: Surrogate, plans, labels, grad=True):
+    """labels: list of (node ids, R values) per plan.  Returns (loss, grad)."""
+    structs, keep = _plan_structs(plans)
+    lab, keep2 = _label_structs(labels)
+    loss = C.c_double()
+    g = np.empty(reff_surrogate_num_params(s), dtype=np.float32) if grad else None
+    _check(_lib.reff_surrogate_loss_grad(s.handle, structs, lab, len(plans), C.byref(loss),
+                                         g.ctypes.data if grad else None))
+    return loss.value, g
+
+
+def reff_surrogate_train(s: Surrogate, plans, labels, *, epochs=1, batch=16, lr=1e-3, seed=0):
+    structs, keep = _plan_structs(plans)
+    lab, keep2 = _label_structs(labels)
+    o = reff_train_opts(epochs, batch, lr, seed)
+    hist = np.zeros(max(epochs, 1))
+    _check(_lib.reff_surrogate_train(s.handle, structs, lab, len(plans), C.byref(o),
+                                     hist.ctypes.data))
+    return hist
+
+
+def reff_surrogate_predict(s: Surrogate, plans, R_out=None):
+    structs, keep = _plan_structs(plans)
+    nt, nx, ny = s.geometry
+    if R_out is None:
+        R_out = [np.empty(nt * nx * ny, dtype=np.float64) for _ in plans]
+    dev = len(R_out) > 0 and _is_torch_cuda(R_out[0])
+    ptrs = (C.c_void_p * max(len(plans), 1))()
+    for i, o in enumerate(R_out):
+        ptrs[i] = o.data_ptr() if dev else o.ctypes.data
+    _check(_lib.reff_surrogate_predict(s.handle, structs, len(plans), ptrs, 1 if dev else 0))
+    return R_out
+
+
+def reff_surrogate_save(s: Surrogate, path: str) -> None:
+    _check(_lib.reff_surrogate_save(s.handle, os.fsencode(path)))
+
+
+def reff_surrogate_load(path: str, device: int = 0) -> Surrogate:
+    h = C.c_void_p()
+    _check(_lib.reff_surrogate_load(os.fsencode(path), device, C.byref(h)))
+    with open(path, "rb") as f:
+        hdr = f.read(20)
+    nt, nx, ny = (int.from_bytes(hdr[8 + 4 * i:12 + 4 * i], "little", signed=True)
+                  for i in range(3))
+    return Surrogate(h, (nt, nx, ny))

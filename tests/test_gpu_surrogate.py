@@ -1,0 +1,168 @@
+"""The screening model on the GPU (include/reff_surrogate.h) against its CPU
+float64 reference (oracle/surrogate_ref.py), and batch screening.
+
+Two comparisons, both on bf16-rounded weights and inputs (what the GPU
+model receives):
+* against the reference that rounds to bf16 exactly where the GPU stores
+  bf16 tensors (activations, their gradients): both sides then take the
+  same ReLU and max-pooling decisions, and what remains is float32 versus
+  float64 accumulation, which moves a value across a bf16 rounding boundary
+  only rarely: predictions and loss to 5e-3, gradient to 2e-2 relative
+  (L2), every layer's weight and bias gradient with cosine >= 0.999;
+  (measured: predictions 7e-4 / 1.3e-3, gradient 4.3e-3 / 5.2e-3, lowest
+  layer cosine 0.99996, for the two cases below);
+* against the plain float64 network: the GPU's bf16 storage (unit roundoff
+  2^-9) over 18 layers, with the ReLU and argmax decisions it flips near
+  ties, errors that grow along the backward path to the first layer:
+  predictions and loss to 2e-2, gradient to 1e-1 relative (L2), layer
+  cosines >= 0.98 (measured: predictions 3.7e-3 / 5.7e-3, gradient 5.5e-2 /
+  7.2e-2, lowest cosine 0.995 / 0.988, both at the first layer)."""
+import numpy as np
+import pytest
+
+from oracle import reff_oracle as ro
+from oracle import surrogate_ref as sr
+from paper_2607_05818_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _reff():
+    from paper_2607_05818_amd import reff
+    return reff
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _plans(k, nt=2, side=32, seed=300):
+    return [gen.small_random_desc(seed + i, nt, side, side, 24, 4) for i in range(k)]
+
+
+def _labels(plans, nt, side, count, seed, R=None):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, d in enumerate(plans):
+        nodes = rng.choice(nt * side * side, size=count, replace=False)
+        r = rng.uniform(0.2, 3.0, size=count) if R is None else R[i]
+        out.append((nodes, r))
+    return out
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("nt,side,C,B", [(2, 32, 8, 3), (3, 64, 16, 2)])
+def test_forward_loss_gradient_match_reference(nt, side, C, B):
+    reff = _reff()
+    _say("surrogate parity", nt, side, C, B)
+    s = reff.reff_surrogate_create(nt, side, side, C, seed=11)
+    p = reff.reff_surrogate_get_params(s)
+    assert p.size == sr.num_params(nt, C)
+    # nonzero biases as well
+    rng = np.random.default_rng(5)
+    mask = sr.weight_mask(nt, C)
+    p = np.where(mask, p, rng.normal(scale=0.1, size=p.size)).astype(np.float32)
+    reff.reff_surrogate_set_params(s, p)
+    plans = _plans(B, nt, side)
+    labels = _labels(plans, nt, side, 60, 9)
+    loss, g = reff.reff_surrogate_loss_grad(s, plans, labels)
+    pred = np.stack([np.log(np.where(r > 0, r, 1.0)) for r in reff.reff_surrogate_predict(s, plans)])
+    pads = np.stack([np.concatenate([sr.features(d, nt, side, side)[2 * nt + 1].ravel() > 0,
+                                     np.zeros((nt - 1) * side * side, dtype=bool)]) for d in plans])
+    for emulate, t_pred, t_grad, t_cos in ((True, 5e-3, 2e-2, 0.999), (False, 2e-2, 1e-1, 0.98)):
+        rloss, rg, rpred = sr.loss_and_grad(p, plans, labels, nt, side, side, C,
+                                            emulate_bf16=emulate)
+        rpred = rpred.reshape(B, -1)
+        e_pred = _rel_l2(pred[~pads], rpred[~pads])
+        e_loss = abs(loss - rloss) / rloss
+        e_grad = _rel_l2(g, rg)
+        cos = []
+        for name, (w, b) in sr.split(np.arange(p.size), nt, C).items():
+            for part in (w, b):
+                sl = np.asarray(part.numpy(), dtype=np.int64)
+                a, r = g[sl], rg[sl]
+                cos.append((float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r) + 1e-300)), name))
+        print("emulate", emulate, "pred", e_pred, "loss", e_loss, loss, rloss, "grad", e_grad,
+              "min cos", min(cos), flush=True)
+        assert e_pred <= t_pred
+        assert e_loss <= t_pred
+        assert e_grad <= t_grad
+        assert min(cos)[0] >= t_cos
+
+
+def test_config4_geometry_forward():
+    """3 tiers of 128 x 128 with C = 32 (the surrogate workload's model)."""
+    reff = _reff()
+    nt, side, C = 3, 128, 32
+    rng = np.random.default_rng(1004)
+    plans = [gen.config4_plan(rng) for _ in range(2)]
+    s = reff.reff_surrogate_create(nt, side, side, C, seed=3)
+    p = reff.reff_surrogate_get_params(s)
+    _say("surrogate 3x128x128 forward")
+    pred = np.stack([np.log(np.where(r > 0, r, 1.0)) for r in reff.reff_surrogate_predict(s, plans)])
+    _, _, rpred = sr.loss_and_grad(p, plans, [([], [])] * 2, nt, side, side, C)
+    rpred = rpred.reshape(2, -1)
+    pads = np.stack([np.concatenate([sr.features(d, nt, side, side)[2 * nt + 1].ravel() > 0,
+                                     np.zeros((nt - 1) * side * side, dtype=bool)]) for d in plans])
+    e = _rel_l2(pred[~pads], rpred[~pads])
+    print("pred rel l2", e, flush=True)
+    assert e <= 2e-2
+    assert np.all(np.exp(pred[pads]) == 1.0)  # pads were reported as R = 0
+
+
+def test_training_reduces_loss_and_save_load(tmp_path):
+    reff = _reff()
+    nt, side, C = 2, 32, 8
+    plans = _plans(16, nt, side, seed=500)
+    nodes = [gen.sample_free_nodes(d, 64, 600 + i) for i, d in enumerate(plans)]
+    _say("surrogate training")
+    R, _ = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_FP64, rel_tol=1e-8)
+    labels = list(zip(nodes, R))
+    s = reff.reff_surrogate_create(nt, side, side, C, seed=1)
+    l0, _ = reff.reff_surrogate_loss_grad(s, plans[:8], labels[:8], grad=False)
+    hist = reff.reff_surrogate_train(s, plans, labels, epochs=60, batch=8, lr=2e-3, seed=2)
+    l1, _ = reff.reff_surrogate_loss_grad(s, plans[:8], labels[:8], grad=False)
+    print("loss", l0, "->", l1, "epochs", hist[:3], hist[-3:], flush=True)
+    assert np.all(np.isfinite(hist))
+    assert l1 < 0.2 * l0
+    path = str(tmp_path / "model.bin")
+    reff.reff_surrogate_save(s, path)
+    t = reff.reff_surrogate_load(path)
+    assert np.array_equal(reff.reff_surrogate_get_params(t), reff.reff_surrogate_get_params(s))
+    a = reff.reff_surrogate_predict(s, plans[:3])
+    b = reff.reff_surrogate_predict(t, plans[:3])
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_batch_screening_fallback_and_accept():
+    """An untrained model fails its spot check, so every plan falls back to
+    the solver (results to the solver tolerance); with the threshold lifted
+    the predictions are returned, with solved values at the checked nodes."""
+    reff = _reff()
+    nt, side, C = 2, 32, 8
+    plans = _plans(3, nt, side, seed=700)
+    nodes = [gen.sample_free_nodes(d, 200, 800 + i) for i, d in enumerate(plans)]
+    s = reff.reff_surrogate_create(nt, side, side, C, seed=4)
+    _say("screening fallback")
+    out, st = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_MIXED, rel_tol=1e-5,
+                                    surrogate=s, spot_frac=0.05, fallback_rel_err=1e-2)
+    for i, d in enumerate(plans):
+        want = ro.diag(d, nodes[i])
+        assert st[i]["screened"] == 0 and st[i]["spot_max_rel_err"] > 1e-2
+        assert np.max(np.abs(out[i] - want) / want) <= 1e-3
+    _say("screening accept")
+    out2, st2 = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_MIXED, rel_tol=1e-5,
+                                      surrogate=s, spot_frac=0.05, fallback_rel_err=1e9)
+    pred = reff.reff_surrogate_predict(s, plans)
+    for i, d in enumerate(plans):
+        assert st2[i]["screened"] == 1
+        assert st2[i]["n_solved"] == 10  # ceil(0.05 * 200)
+        want = ro.diag(d, nodes[i])
+        solved = np.abs(out2[i] - want) / want <= 1e-3
+        from_model = out2[i] == pred[i][nodes[i]]
+        assert np.all(solved | from_model)
+        assert np.sum(solved & ~from_model) >= 1
