@@ -151,6 +151,76 @@ def measured_traffic():
     return rec["hbm_bytes_per_row"]
 
 
+def surrogate_compare(reff, gen, log, rel_tol, n_train=512, n_test=16, per_test=640,
+                      n_full=2, epochs=20):
+    """The surrogate workload (3 tiers of 128 x 128, TSV and pad densities
+    drawn per plan): labels for 64 seeded nodes of each of n_train plans
+    from one batched mixed-precision solve, Adam training of the BF16 U-Net,
+    then screening of n_test held-out plans (per_test requested nodes each,
+    1 % checked by the solver, fallback above 1e-2) against solving every
+    requested node.  The model's own contract is 1e-2: its errors are
+    reported as a distribution over the held-out requested nodes and over
+    the full maps of n_full held-out plans."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(gen.CONFIG_SEEDS[4])
+    plans = [gen.config4_plan(rng) for _ in range(n_train + n_test)]
+    train, test = plans[:n_train], plans[n_train:]
+    prec = reff.REFF_PREC_MIXED
+    lab_nodes = [gen.sample_free_nodes(d, 64, np.random.SeedSequence([4, i]))
+                 for i, d in enumerate(train)]
+    a = time.perf_counter()
+    lab_R, _ = reff.reff_batch_plans(train, lab_nodes, precision=prec, rel_tol=1e-5)
+    t_label = time.perf_counter() - a
+    s = reff.reff_surrogate_create(3, 128, 128, 32, seed=gen.CONFIG_SEEDS[4])
+    a = time.perf_counter()
+    hist = reff.reff_surrogate_train(s, train, list(zip(lab_nodes, lab_R)), epochs=epochs,
+                                     batch=16, lr=1e-3, seed=1)
+    t_train = time.perf_counter() - a
+    req = [gen.sample_free_nodes(d, per_test, np.random.SeedSequence([44, i]))
+           for i, d in enumerate(test)]
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    ref, _ = reff.reff_batch_plans(test, req, precision=prec, rel_tol=rel_tol)
+    t_solver = time.perf_counter() - a
+    a = time.perf_counter()
+    scr, st = reff.reff_batch_plans(test, req, precision=prec, rel_tol=rel_tol, surrogate=s,
+                                    spot_frac=0.01, fallback_rel_err=1e-2)
+    t_screen = time.perf_counter() - a
+    a = time.perf_counter()
+    pred = reff.reff_surrogate_predict(s, test)
+    t_pred = time.perf_counter() - a
+    e_req = np.concatenate([np.abs(pred[i][req[i]] - ref[i]) / ref[i] for i in range(n_test)])
+    e_scr = np.concatenate([np.abs(scr[i] - ref[i]) / ref[i] for i in range(n_test)])
+    full = reff.reff_batch_plans(test[:n_full], None, precision=prec, rel_tol=rel_tol)[0]
+    e_full = np.concatenate([np.abs(pred[i] - full[i])[full[i] > 0] / full[i][full[i] > 0]
+                             for i in range(n_full)])
+    total = n_test * per_test
+    q = lambda e: {"median": float(np.median(e)), "p90": float(np.quantile(e, 0.9)),
+                   "p99": float(np.quantile(e, 0.99)), "max": float(e.max()),
+                   "frac_le_1e-2": float(np.mean(e <= 1e-2))}
+    rec = {
+        "workload": ("3 tiers x 128 x 128 plans (TSV density U[0.5%,3%], pad density "
+                     f"U[0.2%,1%]); {n_train} training plans x 64 labelled nodes, {n_test} "
+                     f"held-out plans x {per_test} requested nodes"),
+        "label_seconds": t_label, "train_seconds": t_train, "epochs": epochs,
+        "train_loss_first_last": [float(hist[0]), float(hist[-1])],
+        "screened_nodes_per_s": total / t_screen,
+        "n_ok_1e-2": int(np.sum(e_scr <= 1e-2)), "nodes": total,
+        "solver_nodes_per_s": total / t_solver,
+        "predict_nodes_per_s": n_test * 3 * 128 * 128 / t_pred,
+        "plans_screened": int(sum(x["screened"] for x in st)), "plans": n_test,
+        "model_err_requested": q(e_req), "model_err_full_maps": q(e_full),
+        "screened_err": q(e_scr),
+    }
+    log(f"surrogate: train {t_train:.1f} s (labels {t_label:.1f} s), loss {hist[0]:.3g} -> "
+        f"{hist[-1]:.3g}; screened {rec['plans_screened']}/{n_test} plans, "
+        f"{total / t_screen:.0f} nodes/s vs solver {total / t_solver:.0f}; model median err "
+        f"{rec['model_err_requested']['median']:.3g}")
+    s.close()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +233,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy kernel 4 times (the "
                          "reference point for HBM byte counters)")
@@ -283,6 +354,8 @@ def main():
 
     if not args.no_batched and args.precision == "mixed":
         compare["batched_plans"] = batched_compare(reff, gen, log, args.rel_tol)
+    if not args.no_surrogate and args.precision == "mixed":
+        compare["surrogate_screened"] = surrogate_compare(reff, gen, log, args.rel_tol)
 
     cpu = None
     if not args.no_cpu_baseline:
