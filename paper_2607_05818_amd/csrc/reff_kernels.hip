@@ -88,15 +88,18 @@ __device__ __forceinline__ T stencil_row(const Coef<T>& c, const U* __restrict__
   const T yw = (T)Y[vw * S + lane];
   const T yn = (T)Y[vn * S + lane];
   const T ys = (T)Y[vs * S + lane];
-  T q = c.d[ci] * y - ce * ye - cw * yw - cn * yn - cs * ys;
+  // TSV segments: the rows above / below exist only where the coupling is
+  // nonzero; elsewhere the load repeats row v (an L1 hit) and is multiplied
+  // by zero, so that no load sits behind a branch.
   const int sl = c.slot[ci];
-  if (sl >= 0) {
-    const T gu = c.up[sl];
-    const T gd = c.dn[sl];
-    if (gu != T(0)) q -= gu * (T)Y[(v + pd.plane) * S + lane];
-    if (gd != T(0)) q -= gd * (T)Y[(v - pd.plane) * S + lane];
-  }
-  return q;
+  const int sc = sl >= 0 ? sl : 0;
+  const T gu = sl >= 0 ? c.up[sc] : T(0);
+  const T gd = sl >= 0 ? c.dn[sc] : T(0);
+  const int64_t vu = gu != T(0) ? v + pd.plane : v;
+  const int64_t vd = gd != T(0) ? v - pd.plane : v;
+  const T yu = (T)Y[vu * S + lane];
+  const T yd = (T)Y[vd * S + lane];
+  return c.d[ci] * y - ce * ye - cw * yw - cn * yn - cs * ys - gu * yu - gd * yd;
 }
 
 // Partial Grams of unit u: part[u][m][S*S] (or the first S entries for
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, Work wk,
   __shared__ T sB[DIAG ? 1 : CH][LDW];  // G Y rows, then Q rows
   __shared__ T sR[DIAG ? 1 : CH][LDW];
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int nb = w >> 2, cb = w & 3;
   const UnitCtx u = unit_ctx(wk);
   const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
@@ -234,34 +237,43 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, Work wk,
   double d1 = 0.0, d2 = 0.0;
   for (int64_t base = u.begin; base < u.end; base += CH) {
     if (DIAG) {
+      T yv[NODES_PER_WAVE], rv[NODES_PER_WAVE], qv[NODES_PER_WAVE];
+#pragma unroll
+      for (int i = 0; i < NODES_PER_WAVE; ++i) {
+        const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
+        yv[i] = Y[v * S + lane];
+        rv[i] = R[v * S + lane];
+        qv[i] = stencil_row<T, T>(c, Y, u.pd, v, lane);
+      }
 #pragma unroll
       for (int i = 0; i < NODES_PER_WAVE; ++i) {
         const int64_t v = base + w * NODES_PER_WAVE + i;
         if (v < u.end) {
-          const T y = Y[v * S + lane];
-          const T q = stencil_row<T, T>(c, Y, u.pd, v, lane);
-          const T r = R[v * S + lane];
-          P[v * S + lane] = y;
-          Q[v * S + lane] = q;
-          d1 += (double)y * (double)q;
-          d2 += (double)y * (double)r;
+          P[v * S + lane] = yv[i];
+          Q[v * S + lane] = qv[i];
+          d1 += (double)yv[i] * (double)qv[i];
+          d2 += (double)yv[i] * (double)rv[i];
         }
       }
       continue;
     }
+    // All loads of the chunk first (rows past the unit's end are clamped to
+    // its last row and zeroed afterwards), so none waits behind a branch.
+    T yv[NODES_PER_WAVE], rv[NODES_PER_WAVE], qv[NODES_PER_WAVE];
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
+      yv[i] = Y[v * S + lane];
+      rv[i] = R[v * S + lane];
+      qv[i] = stencil_row<T, T>(c, Y, u.pd, v, lane);
+    }
 #pragma unroll
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
-      const int64_t v = base + row;
-      T y = 0, q = 0, r = 0;
-      if (v < u.end) {
-        y = Y[v * S + lane];
-        r = R[v * S + lane];
-        q = stencil_row<T, T>(c, Y, u.pd, v, lane);
-      }
-      sA[row][lane] = y;
-      sB[row][lane] = q;
-      sR[row][lane] = r;
+      const bool ok = base + row < u.end;
+      sA[row][lane] = ok ? yv[i] : T(0);
+      sB[row][lane] = ok ? qv[i] : T(0);
+      sR[row][lane] = ok ? rv[i] : T(0);
     }
     __syncthreads();
     const auto pt = prod_tile<T>(sA, nb, breg, lane);
@@ -312,7 +324,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
   __shared__ T sD[(WITH_D && !DIAG) ? CH : 1][LDW];
   __shared__ T sDinv[CH];
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int nb = w >> 2, cb = w & 3;
   const UnitCtx u = unit_ctx(wk);
   const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
@@ -328,35 +340,54 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
   const int64_t cofs = u.pd.cbase - u.pd.vbase;  // vector row -> coefficient index
   for (int64_t base = u.begin; base < u.end; base += CH) {
     if (DIAG) {
+      T qv[NODES_PER_WAVE], rv[NODES_PER_WAVE], pv[NODES_PER_WAVE], dv[NODES_PER_WAVE];
+#pragma unroll
+      for (int i = 0; i < NODES_PER_WAVE; ++i) {
+        const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
+        qv[i] = Q[v * S + lane];
+        rv[i] = R[v * S + lane];
+        if (WITH_D) {
+          pv[i] = P[v * S + lane];
+          dv[i] = D[v * S + lane];
+        }
+      }
 #pragma unroll
       for (int i = 0; i < NODES_PER_WAVE; ++i) {
         const int64_t v = base + w * NODES_PER_WAVE + i;
         if (v < u.end) {
-          const T q = Q[v * S + lane];
-          const T r = R[v * S + lane] - breg[0] * q;
+          const T r = rv[i] - breg[0] * qv[i];
           R[v * S + lane] = r;
-          if (WITH_D) D[v * S + lane] += breg[0] * P[v * S + lane];
-          d3 += (double)q * (double)(c.dinv[v + cofs] * r);
+          if (WITH_D) D[v * S + lane] = dv[i] + breg[0] * pv[i];
+          d3 += (double)qv[i] * (double)(c.dinv[v + cofs] * r);
         }
       }
       continue;
     }
+    T qv[NODES_PER_WAVE], rv[NODES_PER_WAVE], pv[NODES_PER_WAVE], dv[NODES_PER_WAVE];
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
+      qv[i] = Q[v * S + lane];
+      rv[i] = R[v * S + lane];
+      if (WITH_D) {
+        pv[i] = P[v * S + lane];
+        dv[i] = D[v * S + lane];
+      }
+    }
+    T dinv_t = T(0);
+    if (threadIdx.x < CH) dinv_t = c.dinv[min(base + threadIdx.x, u.end - 1) + cofs];
 #pragma unroll
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
-      const int64_t v = base + row;
-      const bool ok = v < u.end;
-      sQ[row][lane] = ok ? Q[v * S + lane] : T(0);
-      sR[row][lane] = ok ? R[v * S + lane] : T(0);
+      const bool ok = base + row < u.end;
+      sQ[row][lane] = ok ? qv[i] : T(0);
+      sR[row][lane] = ok ? rv[i] : T(0);
       if (WITH_D) {
-        sP[row][lane] = ok ? P[v * S + lane] : T(0);
-        sD[row][lane] = ok ? D[v * S + lane] : T(0);
+        sP[row][lane] = ok ? pv[i] : T(0);
+        sD[row][lane] = ok ? dv[i] : T(0);
       }
     }
-    if (threadIdx.x < CH) {
-      const int64_t v = base + threadIdx.x;
-      sDinv[threadIdx.x] = v < u.end ? c.dinv[v + cofs] : T(0);
-    }
+    if (threadIdx.x < CH) sDinv[threadIdx.x] = base + threadIdx.x < u.end ? dinv_t : T(0);
     __syncthreads();
     const auto qa = prod_tile<T>(sQ, nb, breg, lane);
     typename Acc<T>::type pa = {0, 0, 0, 0};
@@ -408,7 +439,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
   __shared__ T sR[DIAG ? 1 : CH][LDW];  // R rows, then D Y rows
   __shared__ T sDv[CH][2];
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int nb = w >> 2, cb = w & 3;
   const UnitCtx u = unit_ctx(wk);
   const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
@@ -423,27 +454,44 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
   const int64_t cofs = u.pd.cbase - u.pd.vbase;
   for (int64_t base = u.begin; base < u.end; base += CH) {
     if (DIAG) {
+      T rv[NODES_PER_WAVE], pv[NODES_PER_WAVE];
+#pragma unroll
+      for (int i = 0; i < NODES_PER_WAVE; ++i) {
+        const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
+        rv[i] = R[v * S + lane];
+        pv[i] = P[v * S + lane];
+      }
 #pragma unroll
       for (int i = 0; i < NODES_PER_WAVE; ++i) {
         const int64_t v = base + w * NODES_PER_WAVE + i;
-        if (v < u.end)
-          Y[v * S + lane] = c.dinv[v + cofs] * R[v * S + lane] - breg[0] * P[v * S + lane];
+        if (v < u.end) Y[v * S + lane] = c.dinv[v + cofs] * rv[i] - breg[0] * pv[i];
       }
       continue;
+    }
+    T rv[NODES_PER_WAVE], pv[NODES_PER_WAVE];
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
+      pv[i] = P[v * S + lane];
+      rv[i] = R[v * S + lane];
+    }
+    T dinv_t = T(0), d_t = T(0);
+    if (threadIdx.x < CH) {
+      const int64_t v = min(base + threadIdx.x, u.end - 1) + cofs;
+      dinv_t = c.dinv[v];
+      d_t = c.d[v];
     }
 #pragma unroll
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
-      const int64_t v = base + row;
-      const bool ok = v < u.end;
-      sP[row][lane] = ok ? P[v * S + lane] : T(0);
-      sR[row][lane] = ok ? R[v * S + lane] : T(0);
+      const bool ok = base + row < u.end;
+      sP[row][lane] = ok ? pv[i] : T(0);
+      sR[row][lane] = ok ? rv[i] : T(0);
     }
     if (threadIdx.x < CH) {
-      const int64_t v = base + threadIdx.x;
-      const bool ok = v < u.end;
-      sDv[threadIdx.x][0] = ok ? c.dinv[v + cofs] : T(0);
-      sDv[threadIdx.x][1] = ok ? c.d[v + cofs] : T(0);
+      const bool ok = base + threadIdx.x < u.end;
+      sDv[threadIdx.x][0] = ok ? dinv_t : T(0);
+      sDv[threadIdx.x][1] = ok ? d_t : T(0);
     }
     __syncthreads();
     const auto pd = prod_tile<T>(sP, nb, breg, lane);
@@ -480,7 +528,7 @@ __global__ __launch_bounds__(WG, 4) void k_gram_dy(Coef<T> c, Work wk, const T* 
   __shared__ T sY[CH][LDW];
   __shared__ T sDY[CH][LDW];
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const UnitCtx u = unit_ctx(wk);
   const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
   const int64_t cofs = u.pd.cbase - u.pd.vbase;
@@ -512,7 +560,7 @@ __global__ __launch_bounds__(WG, 4) void k_cross_gram(Coef<T> c, Work wk,
   __shared__ T sA[CH][LDW];
   __shared__ T sB[CH][LDW];
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const UnitCtx u = unit_ctx(wk);
   const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
   double acc[2][4];
@@ -987,7 +1035,7 @@ __global__ __launch_bounds__(WG) void k_resid(Coef<double> c, Coef<float> cf, Wo
                                               float* __restrict__ Df,
                                               double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const UnitCtx u = unit_ctx(wk);
   const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
   const int64_t tl = tgt_all[(size_t)u.plan * S + lane];
