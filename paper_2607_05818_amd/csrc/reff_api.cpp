@@ -364,7 +364,7 @@ struct BlockResult {
 
 void reff::Workspace::release() {
   for (DevBuf* b : {&Y, &P, &Q, &R, &D, &X, &part, &W, &small, &state, &tgt, &pos, &plans, &units,
-                    &uid, &act, &out, &xs, &rows, &map, &flags})
+                    &uid, &act, &out, &xs, &rows, &map, &flags, &strips, &sid})
     if (b->p) {
       (void)hipFree(b->p);
       b->p = nullptr;
@@ -419,6 +419,37 @@ void make_units(const std::vector<PlanDesc>& in, std::vector<PlanDesc>& plans,
       units.push_back(u);
     }
     p.unit_end = (int32_t)units.size();
+  }
+}
+
+// Strips for the stencil kernel of a group (float32 block variant): every
+// block's tiers are cut into CH-wide x strips and, when that gives too few
+// workgroups, into y segments, about TARGET_UNITS strips in total.
+void make_strips(std::vector<PlanDesc>& plans, std::vector<Strip>& strips) {
+  int64_t rows = 0;
+  for (const PlanDesc& p : plans) rows += p.n;
+  strips.clear();
+  for (size_t i = 0; i < plans.size(); ++i) {
+    PlanDesc& p = plans[i];
+    const int64_t nx = p.nx, ny = p.plane / p.nx, nt = p.n / p.plane;
+    const int64_t nsx = (nx + CH - 1) / CH;
+    const int64_t want = std::max<int64_t>(1, (TARGET_UNITS * p.n + rows - 1) / std::max<int64_t>(rows, 1));
+    const int64_t ysegs = std::min<int64_t>(ny, std::max<int64_t>(1, (want + nt * nsx - 1) / (nt * nsx)));
+    const int64_t H = (ny + ysegs - 1) / ysegs;
+    p.strip_begin = (int32_t)strips.size();
+    for (int64_t t = 0; t < nt; ++t)
+      for (int64_t y0 = 0; y0 < ny; y0 += H)
+        for (int64_t x0 = 0; x0 < nx; x0 += CH) {
+          Strip s{};
+          s.lrow0 = t * p.plane + y0 * nx + x0;
+          s.plan = (int32_t)i;
+          s.nrows = (int32_t)std::min<int64_t>(H, ny - y0);
+          s.wdt = (int32_t)std::min<int64_t>(CH, nx - x0);
+          s.y0 = (int32_t)y0;
+          s.x0 = (int32_t)x0;
+          strips.push_back(s);
+        }
+    p.strip_end = (int32_t)strips.size();
   }
 }
 
@@ -485,6 +516,9 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     std::vector<Unit> units;
     make_units(pin, plans, units);
     const int nu = (int)units.size();
+    std::vector<Strip> strips;
+    if (fp32 && !o.indep) make_strips(plans, strips);
+    const int ns = (int)strips.size();
     // ---- buffers
     reff_status rs;
     const size_t vec = (size_t)rows * S * tsz;
@@ -494,9 +528,12 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     if ((rs = ensure(ws.R, vec)) != REFF_OK) return rs;
     if (with_d && (rs = ensure(ws.D, vec)) != REFF_OK) return rs;
     if (o.mixed && (rs = ensure(ws.X, (size_t)rows * S * sizeof(double))) != REFF_OK) return rs;
-    if ((rs = ensure(ws.part, (size_t)nu * NGRAM * S * S * sizeof(double))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.part, (size_t)std::max(nu, ns) * NGRAM * S * S * sizeof(double))) != REFF_OK)
+      return rs;
     if ((rs = ensure(ws.W, (size_t)nb * NGRAM * S * S * sizeof(double))) != REFF_OK) return rs;
     if ((rs = ensure(ws.small, (size_t)nb * 4 * S * S * sizeof(double))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.strips, (size_t)std::max(ns, 1) * sizeof(Strip))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.sid, (size_t)std::max(ns, 1) * sizeof(int32_t))) != REFF_OK) return rs;
     if ((rs = ensure(ws.state, (size_t)nb * sizeof(BlockState))) != REFF_OK) return rs;
     if ((rs = ensure(ws.tgt, (size_t)nb * S * sizeof(int64_t))) != REFF_OK) return rs;
     if ((rs = ensure(ws.pos, (size_t)nb * S * sizeof(int64_t))) != REFF_OK) return rs;
@@ -507,7 +544,8 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     if ((rs = ensure(ws.flags, (size_t)nb * 2 * sizeof(int32_t))) != REFF_OK) return rs;
     // ---- tables (one pinned staging area, uploaded asynchronously)
     const size_t tab_bytes = nb * sizeof(PlanDesc) + nu * sizeof(Unit) + nb * S * 16 +
-                             (nu + nb) * sizeof(int32_t) * 2 + 256;
+                             (nu + nb) * sizeof(int32_t) * 2 + ns * sizeof(Strip) +
+                             ns * sizeof(int32_t) + 256;
     if ((rs = pin_tab.ensure(tab_bytes)) != REFF_OK) return rs;
     if ((rs = pin_flags.ensure((size_t)nb * 2 * sizeof(int32_t))) != REFF_OK) return rs;
     char* hp = (char*)pin_tab.p;
@@ -517,6 +555,8 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     int64_t* h_pos = h_tgt + (size_t)nb * S;
     int32_t* h_uid = (int32_t*)(h_pos + (size_t)nb * S);
     int32_t* h_act = h_uid + nu;
+    Strip* h_strips = (Strip*)(((uintptr_t)(h_act + nb) + 15) & ~(uintptr_t)15);
+    int32_t* h_sid = (int32_t*)(h_strips + ns);
     std::memcpy(h_plans, plans.data(), nb * sizeof(PlanDesc));
     std::memcpy(h_units, units.data(), nu * sizeof(Unit));
     for (int i = 0; i < nb; ++i) {
@@ -528,6 +568,12 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       h_act[i] = i;
     }
     for (int u = 0; u < nu; ++u) h_uid[u] = u;
+    if (ns > 0) std::memcpy(h_strips, strips.data(), ns * sizeof(Strip));
+    for (int u = 0; u < ns; ++u) h_sid[u] = u;
+    if (ns > 0) {
+      HIPCHK(hipMemcpyAsync(ws.strips.p, h_strips, ns * sizeof(Strip), hipMemcpyHostToDevice, o.stream));
+      HIPCHK(hipMemcpyAsync(ws.sid.p, h_sid, ns * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
+    }
     HIPCHK(hipMemcpyAsync(ws.plans.p, h_plans, nb * sizeof(PlanDesc), hipMemcpyHostToDevice, o.stream));
     HIPCHK(hipMemcpyAsync(ws.units.p, h_units, nu * sizeof(Unit), hipMemcpyHostToDevice, o.stream));
     HIPCHK(hipMemcpyAsync(ws.tgt.p, h_tgt, (size_t)nb * S * sizeof(int64_t), hipMemcpyHostToDevice, o.stream));
@@ -554,9 +600,12 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     b.work.plans = (const PlanDesc*)ws.plans.p;
     b.work.units = (const Unit*)ws.units.p;
     b.work.uid = (const int32_t*)ws.uid.p;
+    b.work.strips = (const Strip*)ws.strips.p;
+    b.work.sid = (const int32_t*)ws.sid.p;
     b.act = (const int32_t*)ws.act.p;
     b.n_act = nb;
     b.n_units = nu;
+    b.n_strips = ns;
     b.rows = rows;
 
     HIPCHK(launch_init_blocks(fp32, o.indep, coef, b, o.stream));
@@ -614,18 +663,25 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
         if (still.size() != active.size() && !still.empty()) {
           // Compact: later launches cover only the unconverged blocks.
           active = still;
-          int na = 0, nuu = 0;
+          int na = 0, nuu = 0, nss = 0;
           for (int bi : active) {
             h_act[na++] = bi;
             for (int u = plans[(size_t)bi].unit_begin; u < plans[(size_t)bi].unit_end; ++u)
               h_uid[nuu++] = u;
+            if (ns > 0)
+              for (int u = plans[(size_t)bi].strip_begin; u < plans[(size_t)bi].strip_end; ++u)
+                h_sid[nss++] = u;
           }
           HIPCHK(hipMemcpyAsync(ws.uid.p, h_uid, nuu * sizeof(int32_t), hipMemcpyHostToDevice,
                                 o.stream));
           HIPCHK(hipMemcpyAsync(ws.act.p, h_act, na * sizeof(int32_t), hipMemcpyHostToDevice,
                                 o.stream));
+          if (ns > 0)
+            HIPCHK(hipMemcpyAsync(ws.sid.p, h_sid, nss * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  o.stream));
           b.n_act = na;
           b.n_units = nuu;
+          b.n_strips = nss;
         } else {
           active = still;
         }
@@ -635,10 +691,14 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       // ---- all blocks of the group again for the float64 step / results
       for (int i = 0; i < nb; ++i) h_act[i] = i;
       for (int u = 0; u < nu; ++u) h_uid[u] = u;
+      for (int u = 0; u < ns; ++u) h_sid[u] = u;
       HIPCHK(hipMemcpyAsync(ws.uid.p, h_uid, nu * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
       HIPCHK(hipMemcpyAsync(ws.act.p, h_act, nb * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
+      if (ns > 0)
+        HIPCHK(hipMemcpyAsync(ws.sid.p, h_sid, ns * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
       b.n_act = nb;
       b.n_units = nu;
+      b.n_strips = ns;
       if (!o.mixed) break;
       HIPCHK(launch_mixed_residual(c64, c32, b, res_dev, o.stream));
       // One float32 solve carried to the tolerance plus the float64

@@ -59,6 +59,7 @@ struct PlanDesc {
   int64_t plane;
   int32_t nx;
   int32_t unit_begin, unit_end;
+  int32_t strip_begin, strip_end;  // its strips (stencil kernel), if any
   int32_t pad_;
 };
 
@@ -70,12 +71,29 @@ struct Unit {
   int32_t pad_;
 };
 
+// A strip of one tier of a solve block for the stencil kernel: nodes
+// x0 .. x0+wdt-1 (wdt <= CH) of rows y0 .. y0+nrows-1; lrow0 is the
+// block-local id of node (x0, y0).  The kernel marches in +y keeping the
+// rows y-1, y, y+1 on chip, so each Y row is fetched once.
+struct Strip {
+  int64_t lrow0;
+  int32_t plan;
+  int32_t nrows;
+  int32_t wdt;
+  int32_t y0;
+  int32_t x0;
+  int32_t pad_;
+};
+
 // Argument bundle of the vector kernels: gridDim.x workgroups process the
-// units uid[0 .. gridDim.x) (the active ones).
+// units uid[0 .. gridDim.x) (the active ones); the strip stencil kernel
+// processes strips sid[0 .. gridDim.x).
 struct Work {
   const PlanDesc* plans;
   const Unit* units;
   const int32_t* uid;
+  const Strip* strips;
+  const int32_t* sid;
 };
 
 // Device-resident convergence state of one block solve.
@@ -99,7 +117,7 @@ struct DevBuf {
 // Device work arrays of the block solver (grown on demand, reused).
 struct Workspace {
   DevBuf Y, P, Q, R, D, X, part, W, small, state, tgt, pos, plans, units, uid, act, out, xs,
-      rows, map, flags;
+      rows, map, flags, strips, sid;
   void release();
 };
 
@@ -152,7 +170,7 @@ struct SolveBuffers {
   void* R;       // rows x S, T: residual block
   void* D;       // rows x S, T: accumulated solution (mixed path / pairs), may be null
   double* X;     // rows x S, float64 (mixed path accumulated solution), may be null
-  double* part;  // units x NGRAM x S*S partial Grams
+  double* part;  // max(units, strips) x NGRAM x S*S partial Grams
   double* W;     // nb x NGRAM x S*S reduced Grams
   double* winv;  // nb x S*S: W1^+
   void* alpha;   // nb x S*S in T
@@ -165,6 +183,7 @@ struct SolveBuffers {
   const int32_t* act;  // active solve blocks (small kernels, reductions)
   int n_act;
   int n_units;   // active units (grid of the vector kernels)
+  int n_strips;  // active strips (grid of the strip stencil kernel; 0 = not used)
   int64_t rows;  // vector rows covered by the active units' blocks
 };
 

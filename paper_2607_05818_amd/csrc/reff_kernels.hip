@@ -134,46 +134,151 @@ template <typename T> struct Acc;
 template <> struct Acc<float> { typedef f4v type; };
 template <> struct Acc<double> { typedef d4v type; };
 
-// Product tile: rows [16 nb, 16 nb + 16) of the CH x S block staged in sA
-// times an S x S matrix B, of which the lane holds column block cb as
-// breg[ks] = B[4 ks + l/16][16 cb + l%16].  Result as described above.
+// Product tiles: rows [16 nb, 16 nb + 16) of CH x S blocks staged in LDS
+// times an S x S matrix B, of which the lane holds column block cb.  The
+// 64-term contraction runs over k-blocks kb of 16 and steps st of 4, taking
+// k = 16 kb + 4 (l/16) + st at step (kb, st): a lane's A operands of one
+// k-block are 4 consecutive words of its row (one wide LDS read), and
+// breg[4 kb + st] = B[16 kb + 4 (l/16) + st][16 cb + l%16].  Only the first
+// kbn k-blocks are taken (B upper triangular: kbn = cb + 1).
+template <typename T>
+__device__ __forceinline__ void load_arow(const T (*sA)[LDW], int nb, int lane, int kbn,
+                                          T (&a)[S / 4]) {
+  const T* row = &sA[nb * 16 + (lane & 15)][4 * (lane >> 4)];
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    if (kb >= kbn) break;
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(row + 16 * kb);
+      a[4 * kb] = v.x;
+      a[4 * kb + 1] = v.y;
+      a[4 * kb + 2] = v.z;
+      a[4 * kb + 3] = v.w;
+    } else {
+      const double2 v0 = *reinterpret_cast<const double2*>(row + 16 * kb);
+      const double2 v1 = *reinterpret_cast<const double2*>(row + 16 * kb + 2);
+      a[4 * kb] = v0.x;
+      a[4 * kb + 1] = v0.y;
+      a[4 * kb + 2] = v1.x;
+      a[4 * kb + 3] = v1.y;
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ typename Acc<T>::type prod_tile(const T (*sA)[LDW], int nb,
-                                                           const T* breg, int lane) {
+                                                           const T* breg, int lane, int kbn = 4) {
   typename Acc<T>::type c = {0, 0, 0, 0};
-  const int rr = nb * 16 + (lane & 15), kq = lane >> 4;
+  if constexpr (sizeof(T) == 8) {  // float64: operands read step by step (registers)
+    const T* row = &sA[nb * 16 + (lane & 15)][4 * (lane >> 4)];
 #pragma unroll
-  for (int ks = 0; ks < S / 4; ++ks) c = mma(sA[rr][4 * ks + kq], breg[ks], c);
+    for (int kb = 0; kb < 4; ++kb) {
+      if (kb >= kbn) break;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) c = mma(row[16 * kb + st], breg[4 * kb + st], c);
+    }
+  } else {
+    T a[S / 4];
+    load_arow<T>(sA, nb, lane, kbn, a);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      if (kb >= kbn) break;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) c = mma(a[4 * kb + st], breg[4 * kb + st], c);
+    }
+  }
   return c;
+}
+
+// Two products with the same B, their matrix-core chains interleaved
+// (float64: one after the other, to stay within the register budget).
+template <typename T>
+__device__ __forceinline__ void prod_tile2(const T (*sA1)[LDW], const T (*sA2)[LDW], int nb,
+                                           const T* breg, int lane, typename Acc<T>::type& c1,
+                                           typename Acc<T>::type& c2, int kbn = 4) {
+  if constexpr (sizeof(T) == 8) {
+    c1 = prod_tile<T>(sA1, nb, breg, lane, kbn);
+    c2 = prod_tile<T>(sA2, nb, breg, lane, kbn);
+  } else {
+    // one k-block of both operands at a time (8 registers)
+    const float* r1 = &sA1[nb * 16 + (lane & 15)][4 * (lane >> 4)];
+    const float* r2 = &sA2[nb * 16 + (lane & 15)][4 * (lane >> 4)];
+    c1 = typename Acc<T>::type{0, 0, 0, 0};
+    c2 = typename Acc<T>::type{0, 0, 0, 0};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      if (kb >= kbn) break;
+      const float4 v1 = *reinterpret_cast<const float4*>(r1 + 16 * kb);
+      const float4 v2 = *reinterpret_cast<const float4*>(r2 + 16 * kb);
+      const float x1[4] = {v1.x, v1.y, v1.z, v1.w}, x2[4] = {v2.x, v2.y, v2.z, v2.w};
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        c1 = mma(x1[st], breg[4 * kb + st], c1);
+        c2 = mma(x2[st], breg[4 * kb + st], c2);
+      }
+    }
+  }
 }
 
 template <typename T>
 __device__ __forceinline__ void load_bcol(const T* __restrict__ B, int cb, int lane, T* breg) {
 #pragma unroll
-  for (int ks = 0; ks < S / 4; ++ks) breg[ks] = B[(4 * ks + (lane >> 4)) * S + 16 * cb + (lane & 15)];
+  for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+      breg[4 * kb + st] = B[(16 * kb + 4 * (lane >> 4) + st) * S + 16 * cb + (lane & 15)];
 }
 
-// Gram tile (ti, tj) of A^T B over the CH staged rows, added to acc (float64).
-// float32 products are summed over one chunk in float32 first.
-template <typename T>
-__device__ __forceinline__ void gram_tile(const T (*sA)[LDW], const T (*sB)[LDW], int ti, int tj,
-                                          int lane, double* acc) {
-  typename Acc<T>::type c = {0, 0, 0, 0};
-  const int kr = lane >> 4, cc = lane & 15;
-#pragma unroll
-  for (int kb = 0; kb < CH; kb += 4) c = mma(sA[kb + kr][ti * 16 + cc], sB[kb + kr][tj * 16 + cc], c);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) acc[r] += (double)c[r];
-}
-
-// Wave w owns Gram tiles 2w and 2w+1 of the 4 x 4 tiles of an S x S Gram.
+// Wave w owns Gram tiles 2w and 2w+1 of the 4 x 4 tiles of an S x S Gram
+// (same tile row ti = w / 2, columns 2 (w % 2) and 2 (w % 2) + 1): one A
+// operand read serves both, and the two matrix-core chains interleave.
 template <typename T>
 __device__ __forceinline__ void gram_chunk(const T (*sA)[LDW], const T (*sB)[LDW], int w,
                                            int lane, double (&acc)[2][4]) {
+  typename Acc<T>::type c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+  const int kr = lane >> 4, cc = lane & 15;
+  const int ti = (2 * w) >> 2, tj = (2 * w) & 3;
 #pragma unroll
-  for (int tt = 0; tt < 2; ++tt) {
-    const int t = 2 * w + tt;
-    gram_tile<T>(sA, sB, t >> 2, t & 3, lane, acc[tt]);
+  for (int kb = 0; kb < CH; kb += 4) {
+    const T a = sA[kb + kr][ti * 16 + cc];
+    c0 = mma(a, sB[kb + kr][tj * 16 + cc], c0);
+    c1 = mma(a, sB[kb + kr][(tj + 1) * 16 + cc], c1);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    acc[0][r] += (double)c0[r];
+    acc[1][r] += (double)c1[r];
+  }
+}
+
+// Two Grams A^T B1 and A^T B2 with the same tiles: four interleaved chains.
+template <typename T>
+__device__ __forceinline__ void gram_chunk2(const T (*sA)[LDW], const T (*sB1)[LDW],
+                                            const T (*sB2)[LDW], int w, int lane,
+                                            double (&acc1)[2][4], double (&acc2)[2][4]) {
+  if constexpr (sizeof(T) == 8) {  // float64: within the register budget
+    gram_chunk<T>(sA, sB1, w, lane, acc1);
+    gram_chunk<T>(sA, sB2, w, lane, acc2);
+    return;
+  }
+  typename Acc<T>::type c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0}, d0 = {0, 0, 0, 0},
+                        d1 = {0, 0, 0, 0};
+  const int kr = lane >> 4, cc = lane & 15;
+  const int ti = (2 * w) >> 2, tj = (2 * w) & 3;
+#pragma unroll
+  for (int kb = 0; kb < CH; kb += 4) {
+    const T a = sA[kb + kr][ti * 16 + cc];
+    c0 = mma(a, sB1[kb + kr][tj * 16 + cc], c0);
+    c1 = mma(a, sB1[kb + kr][(tj + 1) * 16 + cc], c1);
+    d0 = mma(a, sB2[kb + kr][tj * 16 + cc], d0);
+    d1 = mma(a, sB2[kb + kr][(tj + 1) * 16 + cc], d1);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    acc1[0][r] += (double)c0[r];
+    acc1[1][r] += (double)c1[r];
+    acc2[0][r] += (double)d0[r];
+    acc2[1][r] += (double)d1[r];
   }
 }
 
@@ -221,12 +326,15 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, Work wk,
                                                         const T* __restrict__ R,
                                                         T* __restrict__ P, T* __restrict__ Q,
                                                         double* __restrict__ part) {
-  __shared__ T sA[DIAG ? 1 : CH][LDW];  // Y rows, then P rows
-  __shared__ T sB[DIAG ? 1 : CH][LDW];  // G Y rows, then Q rows
-  __shared__ T sR[DIAG ? 1 : CH][LDW];
+  __shared__ __align__(16) T sA[DIAG ? 1 : CH][LDW];  // Y rows, then P rows
+  __shared__ __align__(16) T sB[DIAG ? 1 : CH][LDW];  // G Y rows, then Q rows
+  __shared__ __align__(16) T sR[DIAG ? 1 : CH][LDW];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const int nb = w >> 2, cb = w & 3;
+  // Product tile (nb, cb) of wave w; T is upper triangular, so tile column
+  // cb needs cb + 1 k-blocks: the two waves sharing a SIMD (w, w + 4) take
+  // cb and 3 - cb, five k-blocks per SIMD.
+  const int nb = w >> 2, cb = nb == 0 ? (w & 3) : 3 - (w & 3);
   const UnitCtx u = unit_ctx(wk);
   const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
   T breg[DIAG ? 1 : S / 4];
@@ -276,8 +384,8 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, Work wk,
       sR[row][lane] = ok ? rv[i] : T(0);
     }
     __syncthreads();
-    const auto pt = prod_tile<T>(sA, nb, breg, lane);
-    const auto qt = prod_tile<T>(sB, nb, breg, lane);
+    typename Acc<T>::type pt, qt;
+    prod_tile2<T>(sA, sB, nb, breg, lane, pt, qt, cb + 1);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -286,8 +394,7 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, Work wk,
       sB[row][col] = qt[r];
     }
     __syncthreads();
-    gram_chunk<T>(sA, sB, w, lane, a1);
-    gram_chunk<T>(sA, sR, w, lane, a2);
+    gram_chunk2<T>(sA, sB, sR, w, lane, a1, a2);
 #pragma unroll
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
@@ -309,6 +416,209 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, Work wk,
   }
 }
 
+// Read of an array that no kernel writes while a solve runs (stencil
+// coefficients): through the constant address space, so that a
+// wave-uniform index becomes a scalar-cache load that no vector store in
+// the kernel can be taken to clobber.
+template <typename T>
+__device__ __forceinline__ T ldc(const T* p, int64_t i) {
+  return ((const __attribute__((address_space(4))) T*)p)[i];
+}
+
+// K1 over strips (block variant): the same products and Grams, with the
+// stencil read from an on-chip window.  The workgroup marches its strip in
+// +y; the ring win[3] holds the Y rows y-1, y, y+1 of the strip plus one
+// halo node on each side (column 0 = x0-1, column j+1 = node x0+j), so
+// every Y row comes from HBM once.  The loads of row y+2 and of R row y+1
+// are issued before row y's matrix-core work and land in registers.
+template <typename T>
+__global__ __launch_bounds__(WG, 4) void k_stencil_gram_strip(Coef<T> c, Work wk,
+                                                              const T* __restrict__ Y,
+                                                              const T* __restrict__ Tm,
+                                                              const T* __restrict__ R,
+                                                              T* __restrict__ P,
+                                                              T* __restrict__ Q,
+                                                              double* __restrict__ part) {
+  constexpr int HWW = CH + 2;
+  __shared__ __align__(16) T win[3][HWW][LDW];
+  __shared__ __align__(16) T sR[CH][LDW];
+  __shared__ __align__(16) T sQ[CH][LDW];  // G Y rows, then Q rows
+  __shared__ __align__(16) T sP[CH][LDW];
+  // Stencil coefficients of row y (buffer s % 2): d, cE from node x0-1 on,
+  // cN (buffer s % 2 = row y, the other = row y-1), TSV slot.
+  __shared__ T cd[2][CH], ce[2][CH + 1], cn[2][CH];
+  __shared__ int cslot[2][CH];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  // Product tile (nb, cb): T is upper triangular (see k_stencil_gram).
+  const int nb = w >> 2, cb = nb == 0 ? (w & 3) : 3 - (w & 3);
+  const int sidx = wk.sid[logical_block(blockIdx.x, gridDim.x)];
+  const Strip st = wk.strips[sidx];
+  const PlanDesc pd = wk.plans[st.plan];
+  const int64_t nx = pd.nx;
+  const int ny = (int)(pd.plane / pd.nx);
+  const int wdt = st.wdt;
+  const bool has_w = st.x0 > 0;
+  const bool has_e = st.x0 + wdt < pd.nx;
+  T breg[S / 4];
+  load_bcol<T>(Tm + (size_t)st.plan * S * S, cb, lane, breg);
+  double a1[2][4], a2[2][4];
+  zero_acc(a1);
+  zero_acc(a2);
+  // Window row yy of the strip: this thread's nodes are j = 4w + i, plus the
+  // west halo (wave 0) and east halo (wave 1).  Rows outside the tier are 0.
+  auto load_row = [&](int yy, T (&v)[NODES_PER_WAVE], T& halo) {
+    const bool in = yy >= 0 && yy < ny;
+    const int64_t base = pd.vbase + st.lrow0 + (int64_t)(yy - st.y0) * nx;
+    const int64_t safe = in ? base : pd.vbase + st.lrow0;
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int j = min(w * NODES_PER_WAVE + i, wdt - 1);
+      v[i] = Y[(safe + j) * S + lane];
+      if (!in) v[i] = T(0);
+    }
+    halo = T(0);
+    if (w == 0) {
+      const T h = Y[(safe - (has_w ? 1 : 0)) * S + lane];
+      halo = (in && has_w) ? h : T(0);
+    } else if (w == 1) {
+      const T h = Y[(safe + (has_e ? wdt : 0)) * S + lane];
+      halo = (in && has_e) ? h : T(0);
+    }
+  };
+  auto store_row = [&](int slot, const T (&v)[NODES_PER_WAVE], T halo) {
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int j = w * NODES_PER_WAVE + i;
+      win[slot][j + 1][lane] = j < wdt ? v[i] : T(0);
+    }
+    if (w == 0) win[slot][0][lane] = halo;
+    if (w == 1 && wdt == CH) win[slot][CH + 1][lane] = halo;
+  };
+  auto load_r = [&](int s, T (&v)[NODES_PER_WAVE]) {
+    const int64_t base = pd.vbase + st.lrow0 + (int64_t)min(s, st.nrows - 1) * nx;
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int j = min(w * NODES_PER_WAVE + i, wdt - 1);
+      v[i] = R[(base + j) * S + lane];
+    }
+  };
+  // Coefficients of strip row s (one value per thread t < 4 CH + 1):
+  //   t < CH: d;  CH <= t <= 2 CH: cE of node x0 - 1 + (t - CH);
+  //   2 CH < t <= 3 CH: cN;  3 CH < t <= 4 CH: slot (as bits).
+  const int t = threadIdx.x;
+  auto load_coef = [&](int srow, T& val, int& sl) {
+    const int64_t base = pd.cbase + st.lrow0 + (int64_t)min(srow, st.nrows - 1) * nx;
+    val = T(0);
+    sl = -1;
+    if (t < CH) {
+      val = c.d[base + min(t, wdt - 1)];
+    } else if (t <= 2 * CH) {
+      const int e = t - CH;  // node x0 - 1 + e
+      const bool ok = (e > 0 || has_w) && e <= wdt;
+      const T v = c.cE[base + min(max(e - 1, has_w ? -1 : 0), wdt - 1)];
+      val = ok ? v : T(0);
+    } else if (t <= 3 * CH) {
+      val = c.cN[base + min(t - 2 * CH - 1, wdt - 1)];
+    } else if (t <= 4 * CH) {
+      sl = c.slot[base + min(t - 3 * CH - 1, wdt - 1)];
+    }
+  };
+  auto store_coef = [&](int b, T val, int sl) {
+    if (t < CH) {
+      cd[b][t] = val;
+    } else if (t <= 2 * CH) {
+      ce[b][t - CH] = val;
+    } else if (t <= 3 * CH) {
+      cn[b][t - 2 * CH - 1] = val;
+    } else if (t <= 4 * CH) {
+      cslot[b][t - 3 * CH - 1] = sl;
+    }
+  };
+  // Prologue: rows y0-1 and y0 into slots 0 and 1; cN of row y0-1 into
+  // buffer 1; row y0+1, R row y0 and the coefficients of row y0 in flight.
+  {
+    T v[NODES_PER_WAVE], h;
+    load_row(st.y0 - 1, v, h);
+    store_row(0, v, h);
+    load_row(st.y0, v, h);
+    store_row(1, v, h);
+    if (t > 2 * CH && t <= 3 * CH) {
+      const int j = t - 2 * CH - 1;
+      const int64_t ci = pd.cbase + st.lrow0 + min(j, wdt - 1) - nx;  // row y0 - 1
+      cn[1][j] = st.y0 > 0 ? c.cN[st.y0 > 0 ? ci : ci + nx] : T(0);
+    }
+  }
+  T ny_v[NODES_PER_WAVE], ny_h, r_v[NODES_PER_WAVE], c_v;
+  int c_sl;
+  load_row(st.y0 + 1, ny_v, ny_h);
+  load_r(0, r_v);
+  load_coef(0, c_v, c_sl);
+  for (int s = 0; s < st.nrows; ++s) {
+    const int y = st.y0 + s;
+    const int sc = (s + 1) % 3, sn = (s + 2) % 3, ss = s % 3;  // rows y, y+1, y-1
+    const int b = s & 1;
+    store_row(sn, ny_v, ny_h);
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int j = w * NODES_PER_WAVE + i;
+      sR[j][lane] = j < wdt ? r_v[i] : T(0);
+    }
+    store_coef(b, c_v, c_sl);
+    if (s + 1 < st.nrows) {
+      load_row(y + 2, ny_v, ny_h);
+      load_r(s + 1, r_v);
+      load_coef(s + 1, c_v, c_sl);
+    }
+    __syncthreads();
+    // (G Y)_v for this wave's nodes of row y.
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int j = w * NODES_PER_WAVE + i;
+      const int jc = min(j, wdt - 1);
+      T q = cd[b][jc] * win[sc][jc + 1][lane] - ce[b][jc + 1] * win[sc][jc + 2][lane] -
+            ce[b][jc] * win[sc][jc][lane] - cn[b][jc] * win[sn][jc + 1][lane] -
+            cn[b ^ 1][jc] * win[ss][jc + 1][lane];
+      const int sl = __builtin_amdgcn_readfirstlane(cslot[b][jc]);
+      if (sl >= 0) {  // wave-uniform: TSV segments to the tiers above / below
+        const T gu = ldc(c.up, sl);
+        const T gd = ldc(c.dn, sl);
+        const int64_t v = pd.vbase + st.lrow0 + (int64_t)s * nx + jc;
+        const T yu = Y[(gu != T(0) ? v + pd.plane : v) * S + lane];
+        const T yd = Y[(gd != T(0) ? v - pd.plane : v) * S + lane];
+        q -= gu * yu + gd * yd;
+      }
+      sQ[j][lane] = j < wdt ? q : T(0);
+    }
+    __syncthreads();
+    typename Acc<T>::type pt, qt;
+    prod_tile2<T>(&win[sc][1], sQ, nb, breg, lane, pt, qt, cb + 1);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = nb * 16 + tile_row<T>(lane, r), col = cb * 16 + (lane & 15);
+      sP[row][col] = pt[r];
+      sQ[row][col] = qt[r];
+    }
+    __syncthreads();
+    gram_chunk2<T>(sP, sQ, sR, w, lane, a1, a2);
+    {
+      const int64_t base = pd.vbase + st.lrow0 + (int64_t)s * nx;
+#pragma unroll
+      for (int i = 0; i < NODES_PER_WAVE; ++i) {
+        const int j = w * NODES_PER_WAVE + i;
+        if (j < wdt) {
+          P[(base + j) * S + lane] = sP[j][lane];
+          Q[(base + j) * S + lane] = sQ[j][lane];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  gram_store<T>(part_of(part, sidx, 0), w, lane, a1);
+  gram_store<T>(part_of(part, sidx, 1), w, lane, a2);
+}
+
 // ---------------------------------------------------------------- K2
 // R -= Q A;  (D += P A);  Z = Dinv R;  W3 = Q^T Z.
 template <typename T, bool DIAG, bool WITH_D>
@@ -318,11 +628,11 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
                                                     const T* __restrict__ P, T* __restrict__ R,
                                                     T* __restrict__ D,
                                                     double* __restrict__ part) {
-  __shared__ T sQ[DIAG ? 1 : CH][LDW];
-  __shared__ T sP[DIAG ? 1 : CH][LDW];  // P rows, then Z rows
-  __shared__ T sR[DIAG ? 1 : CH][LDW];
-  __shared__ T sD[(WITH_D && !DIAG) ? CH : 1][LDW];
-  __shared__ T sDinv[CH];
+  __shared__ __align__(16) T sQ[DIAG ? 1 : CH][LDW];
+  __shared__ __align__(16) T sP[DIAG ? 1 : CH][LDW];  // P rows, then Z rows
+  __shared__ __align__(16) T sR[DIAG ? 1 : CH][LDW];
+  __shared__ __align__(16) T sD[(WITH_D && !DIAG) ? CH : 1][LDW];
+  __shared__ __align__(16) T sDinv[CH];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int nb = w >> 2, cb = w & 3;
@@ -389,9 +699,11 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
     }
     if (threadIdx.x < CH) sDinv[threadIdx.x] = base + threadIdx.x < u.end ? dinv_t : T(0);
     __syncthreads();
-    const auto qa = prod_tile<T>(sQ, nb, breg, lane);
-    typename Acc<T>::type pa = {0, 0, 0, 0};
-    if (WITH_D) pa = prod_tile<T>(sP, nb, breg, lane);
+    typename Acc<T>::type qa, pa = {0, 0, 0, 0};
+    if (WITH_D)
+      prod_tile2<T>(sQ, sP, nb, breg, lane, qa, pa);
+    else
+      qa = prod_tile<T>(sQ, nb, breg, lane);
     T rn[4], zn[4], dn[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -435,9 +747,9 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
                                                     const T* __restrict__ R,
                                                     const T* __restrict__ P, T* __restrict__ Y,
                                                     double* __restrict__ part) {
-  __shared__ T sP[DIAG ? 1 : CH][LDW];  // P rows, then Y rows
-  __shared__ T sR[DIAG ? 1 : CH][LDW];  // R rows, then D Y rows
-  __shared__ T sDv[CH][2];
+  __shared__ __align__(16) T sP[DIAG ? 1 : CH][LDW];  // P rows, then Y rows
+  __shared__ __align__(16) T sR[DIAG ? 1 : CH][LDW];  // R rows, then D Y rows
+  __shared__ __align__(16) T sDv[CH][2];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int nb = w >> 2, cb = w & 3;
@@ -525,8 +837,8 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
 template <typename T>
 __global__ __launch_bounds__(WG, 4) void k_gram_dy(Coef<T> c, Work wk, const T* __restrict__ Y,
                                                    double* __restrict__ part) {
-  __shared__ T sY[CH][LDW];
-  __shared__ T sDY[CH][LDW];
+  __shared__ __align__(16) T sY[CH][LDW];
+  __shared__ __align__(16) T sDY[CH][LDW];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const UnitCtx u = unit_ctx(wk);
@@ -557,8 +869,8 @@ __global__ __launch_bounds__(WG, 4) void k_cross_gram(Coef<T> c, Work wk,
                                                       const T* __restrict__ Xa,
                                                       const T* __restrict__ Xb,
                                                       double* __restrict__ part) {
-  __shared__ T sA[CH][LDW];
-  __shared__ T sB[CH][LDW];
+  __shared__ __align__(16) T sA[CH][LDW];
+  __shared__ __align__(16) T sB[CH][LDW];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const UnitCtx u = unit_ctx(wk);
@@ -589,7 +901,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
                                                 double* __restrict__ W,
                                                 const PlanDesc* __restrict__ plans,
                                                 const int32_t* __restrict__ act, int m0,
-                                                int nmat, int len) {
+                                                int nmat, int len, int strips) {
   __shared__ double red[4][64];
   const int p = act[blockIdx.y];
   const int el = threadIdx.x & 63;
@@ -598,7 +910,8 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
   const int total = nmat * len;
   const int m = m0 + (e < total ? e / len : 0);
   const int off = e % len;
-  const int ub = plans[p].unit_begin, ue = plans[p].unit_end;
+  const int ub = strips ? plans[p].strip_begin : plans[p].unit_begin;
+  const int ue = strips ? plans[p].strip_end : plans[p].unit_end;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (e < total) {
     int g = ub + grp;
@@ -1114,9 +1427,10 @@ __global__ void k_gather_rows(const double* __restrict__ X, const int64_t* __res
 }
 
 // ---------------------------------------------------------------- launchers
-static void reduce(const SolveBuffers& b, int m0, int nmat, int len, hipStream_t st) {
+static void reduce(const SolveBuffers& b, int m0, int nmat, int len, hipStream_t st,
+                   bool strips = false) {
   hipLaunchKernelGGL(k_reduce, dim3((nmat * len + 63) / 64, b.n_act), dim3(256), 0, st, b.part,
-                     b.W, b.work.plans, b.act, m0, nmat, len);
+                     b.W, b.work.plans, b.act, m0, nmat, len, strips ? 1 : 0);
 }
 
 template <typename T>
@@ -1137,14 +1451,20 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
   const dim3 g(b.n_units), blk(WG), gs(b.n_act), bs(SM_THREADS);
   const Work wk = b.work;
   if (ev) hipEventRecord(ev[0], st);
+  const bool strips = !indep && b.n_strips > 0;
   if (indep)
     hipLaunchKernelGGL((k_stencil_gram<T, true>), g, blk, 0, st, c, wk, Y, (const T*)b.Tm, R, P,
                        Q, b.part);
-  else
+  else if (strips) {
+    // float32 only (the float64 window would not fit two workgroups per CU)
+    if constexpr (sizeof(T) == 4)
+      hipLaunchKernelGGL((k_stencil_gram_strip<T>), dim3(b.n_strips), blk, 0, st, c, wk, Y,
+                         (const T*)b.Tm, R, P, Q, b.part);
+  } else
     hipLaunchKernelGGL((k_stencil_gram<T, false>), g, blk, 0, st, c, wk, Y, (const T*)b.Tm, R,
                        P, Q, b.part);
   if (ev) hipEventRecord(ev[1], st);
-  reduce(b, 0, 2, len, st);
+  reduce(b, 0, 2, len, st, strips);
   hipLaunchKernelGGL((k_small1<T>), gs, bs, 0, st, b.W, (const T*)P, wk.plans, b.act, b.tgt,
                      b.winv, (T*)b.alpha, b.state, tol, eps1, di);
   if (ev) hipEventRecord(ev[2], st);
