@@ -1020,10 +1020,11 @@ __device__ void scale_regs(double (&a)[16], double* sc, const double* floor_) {
   for (int r = 0; r < 16; ++r)
     if (16 * w + r == lane) dg[lane] = a[r];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = 0.0;
-    for (int j = 0; j < S; ++j) m = fmax(m, dg[j]);
-    maxd = m;
+  if (threadIdx.x < 64) {  // max over the diagonal: one wave, butterfly
+    double m = fmax(dg[threadIdx.x], 0.0);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (threadIdx.x == 0) maxd = m;
   }
   __syncthreads();
   if (threadIdx.x < S) {
@@ -1038,6 +1039,14 @@ __device__ void scale_regs(double (&a)[16], double* sc, const double* floor_) {
   for (int r = 0; r < 16; ++r) a[r] *= sc[16 * w + r] * sk;
 }
 
+// Lane l's value of x (l wave-uniform), as a scalar.
+__device__ __forceinline__ double readlane64(double x, int l) {
+  const int64_t b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((int64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // Symmetric sweep of the Jacobi-scaled matrix held in registers, over every
 // index in order.  Index j is swept only if its current pivot (the Schur
 // complement with respect to the indices swept before it) is above eps;
@@ -1048,43 +1057,37 @@ __device__ void scale_regs(double (&a)[16], double* sc, const double* floor_) {
 // and T has zero columns for dropped j.
 __device__ void sweep_regs(double (&a)[16], double eps, int* drop, const double* sc,
                            Mat* Tl) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __shared__ double cjb[2][S];
-  for (int j = 0; j < S; ++j) {
-    double* cj = cjb[j & 1];
-    if (lane == j) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __shared__ double rowb[2][S];
+  // j = 16 jw + jr with jr unrolled, so that every register index is a
+  // compile-time constant (a dynamic index would move a[] out of registers).
+#pragma unroll 1
+  for (int jw = 0; jw < 4; ++jw)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) cj[16 * w + r] = a[r];
-    }
+  for (int jr = 0; jr < 16; ++jr) {
+    const int j = 16 * jw + jr;
+    // The matrix stays symmetric under the sweep, so row j (one full-wave
+    // store by the wave that holds it) also gives every wave column j.
+    double* rj = rowb[jr & 1];
+    if (w == jw) rj[lane] = a[jr];
     __syncthreads();
-    const double piv = cj[j];
+    const double piv = rj[j];
+    const double ck = rj[lane];  // M[j][lane] = M[lane][j]
     const bool dj = !(piv > eps);
     if (threadIdx.x == 0) drop[j] = dj ? 1 : 0;
-    if (Tl != nullptr && lane == j) {
+    if (Tl != nullptr && w == 0) {  // column j of T, one row per lane
       const double rs = dj ? 0.0 : rsqrt64(piv);
-      double tv[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = 16 * w + r;
-        const double c = cj[i], si = sc[i];
-        const int di = drop[i];
-        double t = 0.0;
-        if (!dj) t = i < j ? (di ? 0.0 : -c * rs) : (i == j ? rs : 0.0);
-        tv[r] = si * t;
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) (*Tl)[16 * w + r][j] = tv[r];
+      double t = 0.0;
+      if (!dj) t = lane < j ? (drop[lane] ? 0.0 : -ck * rs) : (lane == j ? rs : 0.0);
+      (*Tl)[lane][j] = sc[lane] * t;
     }
     if (!dj) {
       const double inv = rcp64(piv);
-      const double ck = cj[lane];
-      double cv[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) cv[r] = cj[16 * w + r];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = 16 * w + r;
-        const double ci = cv[r];
+        const double ci = readlane64(a[r], j);  // M[i][j]
         if (i == j)
           a[r] = (lane == j) ? -inv : ck * inv;
         else if (lane == j)
@@ -1183,10 +1186,9 @@ __global__ __launch_bounds__(SM_THREADS) void k_small1(const double* __restrict_
     for (int j = 0; j < S; ++j) acc += PT[tid][j] * B[j][tid];
     dpsi[tid] = acc;
   }
-  if (tid == 0) {
-    int nd = 0;
-    for (int j = 0; j < S; ++j) nd += drop[j];
-    st->n_drop = nd;
+  if (tid < 64) {
+    const uint64_t m = __ballot(drop[tid] != 0);
+    if (tid == 0) st->n_drop = __popcll(m);
   }
   __syncthreads();
   if (!frozen) convergence_update(st, dpsi, tol);
