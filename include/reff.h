@@ -91,6 +91,10 @@ typedef struct {
   int32_t max_ir_steps;  /* MIXED only: outer refinement steps; 0 => 3       */
   int32_t timing;        /* 1: time the three block kernels with HIP events on
                             `stream` (fills the kernel_* fields of stats)    */
+  int32_t graphs;        /* 1: replay chunks of iterations as HIP graphs when
+                            `stream` is a created (non-NULL) stream that is
+                            not itself being captured and timing is off
+                            (same results bitwise); 0: plain launches      */
 } reff_solve_opts;
 
 typedef struct {
@@ -176,7 +180,11 @@ typedef struct {
                               choice, at least one); 0 => 0.01             */
   double fallback_rel_err; /* screened: a plan whose checked relative error
                               exceeds this is solved in full; 0 => 1e-2    */
-  const char* tune_db;     /* reserved; must be NULL                        */
+  const char* tune_db;     /* NULL, or a tuning database file (created if
+                              absent): per size class of a launch group
+                              (precision, variant, rows, blocks) the work
+                              units per launch; a class not yet in it is
+                              timed on a few candidates first and added   */
 } reff_batch_opts;
 
 /*

@@ -306,6 +306,8 @@ struct Opts {
   hipStream_t stream;
   bool out_dev;
   bool timing;
+  bool graphs;  // replay iteration chunks as HIP graphs where possible
+  const char* tune_db = nullptr;  // tuning database path (batched solves)
 };
 
 reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
@@ -332,6 +334,8 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
   out.stream = (hipStream_t)o->stream;
   out.out_dev = o->out_on_device == 1;
   if (o->timing != 0 && o->timing != 1) return fail(REFF_ERR_INVALID_ARG, "timing must be 0 or 1");
+  if (o->graphs != 0 && o->graphs != 1) return fail(REFF_ERR_INVALID_ARG, "graphs must be 0 or 1");
+  out.graphs = o->graphs == 1;
   out.timing = o->timing == 1;
   return REFF_OK;
 }
@@ -398,7 +402,7 @@ constexpr int TARGET_UNITS = 1024;  // 4 workgroups of 512 threads per CU
 // is cut into chunk-aligned pieces, about TARGET_UNITS in total, in
 // proportion to the block sizes.
 void make_units(const std::vector<PlanDesc>& in, std::vector<PlanDesc>& plans,
-                std::vector<Unit>& units) {
+                std::vector<Unit>& units, int target = TARGET_UNITS) {
   int64_t rows = 0;
   for (const PlanDesc& p : in) rows += p.n;
   plans = in;
@@ -406,7 +410,7 @@ void make_units(const std::vector<PlanDesc>& in, std::vector<PlanDesc>& plans,
   for (size_t i = 0; i < plans.size(); ++i) {
     PlanDesc& p = plans[i];
     const int64_t nch = (p.n + CH - 1) / CH;
-    int64_t k = (TARGET_UNITS * p.n + rows - 1) / std::max<int64_t>(rows, 1);
+    int64_t k = (target * p.n + rows - 1) / std::max<int64_t>(rows, 1);
     k = std::max<int64_t>(1, std::min<int64_t>(k, nch));
     const int64_t cpu = (nch + k - 1) / k;  // chunks per unit
     p.unit_begin = (int32_t)units.size();
@@ -425,7 +429,8 @@ void make_units(const std::vector<PlanDesc>& in, std::vector<PlanDesc>& plans,
 // Strips for the stencil kernel of a group (float32 block variant): every
 // block's tiers are cut into CH-wide x strips and, when that gives too few
 // workgroups, into y segments, about TARGET_UNITS strips in total.
-void make_strips(std::vector<PlanDesc>& plans, std::vector<Strip>& strips) {
+void make_strips(std::vector<PlanDesc>& plans, std::vector<Strip>& strips,
+                 int target = TARGET_UNITS) {
   int64_t rows = 0;
   for (const PlanDesc& p : plans) rows += p.n;
   strips.clear();
@@ -433,7 +438,7 @@ void make_strips(std::vector<PlanDesc>& plans, std::vector<Strip>& strips) {
     PlanDesc& p = plans[i];
     const int64_t nx = p.nx, ny = p.plane / p.nx, nt = p.n / p.plane;
     const int64_t nsx = (nx + CH - 1) / CH;
-    const int64_t want = std::max<int64_t>(1, (TARGET_UNITS * p.n + rows - 1) / std::max<int64_t>(rows, 1));
+    const int64_t want = std::max<int64_t>(1, (target * p.n + rows - 1) / std::max<int64_t>(rows, 1));
     const int64_t ysegs = std::min<int64_t>(ny, std::max<int64_t>(1, (want + nt * nsx - 1) / (nt * nsx)));
     const int64_t H = (ny + ysegs - 1) / ysegs;
     p.strip_begin = (int32_t)strips.size();
@@ -458,6 +463,47 @@ __global__ void k_gather_flags(const BlockState* __restrict__ st, int nb, int32_
     out[2 * i] = st[i].it;
     out[2 * i + 1] = st[i].all_conv;
   }
+}
+
+// Tuning database: one line "<size class> <work units per launch>" per
+// entry.  The size class is the precision, the Krylov variant, log2 of the
+// rows of a launch group and the number of its blocks.
+struct TuneDb {
+  std::vector<std::pair<std::string, int>> e;
+  void load(const char* path) {
+    e.clear();
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[128];
+    int v = 0;
+    while (std::fscanf(f, "%127s %d", key, &v) == 2)
+      if (v >= 64 && v <= (1 << 16)) e.emplace_back(key, v);
+    std::fclose(f);
+  }
+  int get(const std::string& k) const {
+    for (const auto& kv : e)
+      if (kv.first == k) return kv.second;
+    return 0;
+  }
+  bool save(const char* path, const std::string& k, int v) {
+    load(path);
+    for (auto& kv : e)
+      if (kv.first == k) kv.second = v;
+    if (!get(k)) e.emplace_back(k, v);
+    FILE* f = std::fopen(path, "w");
+    if (!f) return false;
+    for (const auto& kv : e) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+    return std::fclose(f) == 0;
+  }
+};
+
+std::string tune_key(bool fp32, bool indep, int64_t rows, int nb) {
+  int lg = 0;
+  while ((int64_t(1) << (lg + 1)) <= rows) ++lg;
+  int bb = 1;
+  while (bb < nb && bb < 256) bb <<= 1;
+  return std::string(fp32 ? "f32" : "f64") + (indep ? "-indep" : "-block") + "-r" +
+         std::to_string(lg) + "-b" + std::to_string(bb);
 }
 
 // Solve every job (block of unit-current columns) with the block PCG,
@@ -492,6 +538,25 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
   }
   PinnedBuf pin_tab, pin_flags;
   bool any_unconv = false;
+  // Chunks of `poll` iterations are captured once and replayed as a HIP
+  // graph (the launch sequence of a chunk only changes with the active set),
+  // on a created stream that is not itself being captured, without timing.
+  struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    int k = -1, n_act = -1, n_units = -1, n_strips = -1;
+    void reset() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      exec = nullptr;
+      k = n_act = n_units = n_strips = -1;
+    }
+    ~GraphCache() { reset(); }
+  } gc;
+  bool use_graph = o.graphs && !o.timing && o.stream != nullptr;
+  if (use_graph) {
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(o.stream, &cst) != hipSuccess || cst != hipStreamCaptureStatusNone)
+      use_graph = false;
+  }
   size_t j0 = 0;
   while (j0 < jobs.size()) {
     // ---- group of jobs within the row budget
@@ -512,13 +577,42 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       ++j1;
     }
     const int nb = (int)(j1 - j0);
+    gc.reset();  // work arrays may be reallocated for this group
+    // Work units per launch: the tuning database's entry for this size
+    // class, or (new class) the fastest of a few candidates, each timed over
+    // one chunk of iterations from a fresh start.
+    int target = TARGET_UNITS;
+    std::vector<int> trials;
+    std::string tkey;
+    TuneDb tdb;
+    if (o.tune_db) {
+      tkey = tune_key(fp32, o.indep, rows, nb);
+      tdb.load(o.tune_db);
+      const int v = tdb.get(tkey);
+      if (v > 0)
+        target = v;
+      else
+        trials = {512, 1024, 2048};
+    }
+    std::vector<float> trial_ms;
     std::vector<PlanDesc> plans;
     std::vector<Unit> units;
-    make_units(pin, plans, units);
-    const int nu = (int)units.size();
     std::vector<Strip> strips;
-    if (fp32 && !o.indep) make_strips(plans, strips);
-    const int ns = (int)strips.size();
+    int nu = 0, ns = 0;
+    PlanDesc* h_plans = nullptr;
+    Unit* h_units = nullptr;
+    int64_t *h_tgt = nullptr, *h_pos = nullptr;
+    int32_t *h_uid = nullptr, *h_act = nullptr, *h_sid = nullptr;
+    Strip* h_strips = nullptr;
+    SolveBuffers b;
+    for (size_t attempt = 0; attempt <= trials.size(); ++attempt) {
+    const bool trial = attempt < trials.size();
+    const int tunits = trial ? trials[attempt] : target;
+    make_units(pin, plans, units, tunits);
+    nu = (int)units.size();
+    strips.clear();
+    if (fp32 && !o.indep) make_strips(plans, strips, tunits);
+    ns = (int)strips.size();
     // ---- buffers
     reff_status rs;
     const size_t vec = (size_t)rows * S * tsz;
@@ -549,14 +643,14 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     if ((rs = pin_tab.ensure(tab_bytes)) != REFF_OK) return rs;
     if ((rs = pin_flags.ensure((size_t)nb * 2 * sizeof(int32_t))) != REFF_OK) return rs;
     char* hp = (char*)pin_tab.p;
-    PlanDesc* h_plans = (PlanDesc*)hp;
-    Unit* h_units = (Unit*)(h_plans + nb);
-    int64_t* h_tgt = (int64_t*)(h_units + nu);
-    int64_t* h_pos = h_tgt + (size_t)nb * S;
-    int32_t* h_uid = (int32_t*)(h_pos + (size_t)nb * S);
-    int32_t* h_act = h_uid + nu;
-    Strip* h_strips = (Strip*)(((uintptr_t)(h_act + nb) + 15) & ~(uintptr_t)15);
-    int32_t* h_sid = (int32_t*)(h_strips + ns);
+    h_plans = (PlanDesc*)hp;
+    h_units = (Unit*)(h_plans + nb);
+    h_tgt = (int64_t*)(h_units + nu);
+    h_pos = h_tgt + (size_t)nb * S;
+    h_uid = (int32_t*)(h_pos + (size_t)nb * S);
+    h_act = h_uid + nu;
+    h_strips = (Strip*)(((uintptr_t)(h_act + nb) + 15) & ~(uintptr_t)15);
+    h_sid = (int32_t*)(h_strips + ns);
     std::memcpy(h_plans, plans.data(), nb * sizeof(PlanDesc));
     std::memcpy(h_units, units.data(), nu * sizeof(Unit));
     for (int i = 0; i < nb; ++i) {
@@ -581,7 +675,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     HIPCHK(hipMemcpyAsync(ws.uid.p, h_uid, nu * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
     HIPCHK(hipMemcpyAsync(ws.act.p, h_act, nb * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
 
-    SolveBuffers b;
+    b = SolveBuffers{};
     b.Y = ws.Y.p;
     b.P = ws.P.p;
     b.Q = ws.Q.p;
@@ -611,6 +705,32 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     HIPCHK(launch_init_blocks(fp32, o.indep, coef, b, o.stream));
     if (with_d && !fp32) HIPCHK(launch_zero_x((double*)b.D, rows * S, o.stream));
     if (o.mixed) HIPCHK(launch_zero_x(b.X, rows * S, o.stream));
+    if (trial) {
+      struct Ev {
+        hipEvent_t a = nullptr, z = nullptr;
+        ~Ev() {
+          if (a) (void)hipEventDestroy(a);
+          if (z) (void)hipEventDestroy(z);
+        }
+      } ev;
+      HIPCHK(hipEventCreate(&ev.a));
+      HIPCHK(hipEventCreate(&ev.z));
+      HIPCHK(hipEventRecord(ev.a, o.stream));
+      for (int i = 0; i < poll; ++i)
+        HIPCHK(launch_iteration(fp32, o.indep, with_d, coef, b, o.tol, o.stream, nullptr));
+      HIPCHK(hipEventRecord(ev.z, o.stream));
+      HIPCHK(hipEventSynchronize(ev.z));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.z));
+      trial_ms.push_back(ms);
+      if (attempt + 1 == trials.size()) {
+        const size_t best = (size_t)(std::min_element(trial_ms.begin(), trial_ms.end()) -
+                                     trial_ms.begin());
+        target = trials[best];
+        (void)tdb.save(o.tune_db, tkey, target);
+      }
+    }
+    }  // attempts
 
     std::vector<char> done((size_t)nb, 0);     // converged in the current step
     std::vector<int32_t> iters((size_t)nb, 0);
@@ -629,9 +749,39 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       while (it < o.max_iters && !active.empty()) {
         const int k = std::min(poll, o.max_iters - it);
         const int64_t act_rows = rows_of(active);
-        for (int i = 0; i < k; ++i)
-          HIPCHK(launch_iteration(fp32, o.indep, with_d, coef, b, o.tol, o.stream,
-                                  o.timing ? &evp.ev[6 * i] : nullptr));
+        if (use_graph) {
+          if (!gc.exec || gc.k != k || gc.n_act != b.n_act || gc.n_units != b.n_units ||
+              gc.n_strips != b.n_strips) {
+            gc.reset();
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(o.stream, hipStreamCaptureModeThreadLocal));
+            hipError_t le = hipSuccess;
+            for (int i = 0; i < k; ++i) {
+              const hipError_t e = launch_iteration(fp32, o.indep, with_d, coef, b, o.tol,
+                                                    o.stream, nullptr);
+              if (le == hipSuccess) le = e;
+            }
+            const hipError_t ee = hipStreamEndCapture(o.stream, &graph);
+            if (le != hipSuccess || ee != hipSuccess) {
+              if (graph) (void)hipGraphDestroy(graph);
+              HIPCHK(le);
+              HIPCHK(ee);
+            }
+            const hipError_t ie = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) gc.exec = nullptr;
+            HIPCHK(ie);
+            gc.k = k;
+            gc.n_act = b.n_act;
+            gc.n_units = b.n_units;
+            gc.n_strips = b.n_strips;
+          }
+          HIPCHK(hipGraphLaunch(gc.exec, o.stream));
+        } else {
+          for (int i = 0; i < k; ++i)
+            HIPCHK(launch_iteration(fp32, o.indep, with_d, coef, b, o.tol, o.stream,
+                                    o.timing ? &evp.ev[6 * i] : nullptr));
+        }
         it += k;
         hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(256), 0, o.stream, b.state, nb,
                            (int32_t*)ws.flags.p);
@@ -1282,7 +1432,7 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
   Opts o;
   reff_status s = parse_opts(opts ? &opts->solve : nullptr, o);
   if (s != REFF_OK) return s;
-  if (opts && opts->tune_db) return fail(REFF_ERR_UNSUPPORTED, "tune_db is reserved and must be NULL");
+  o.tune_db = opts ? opts->tune_db : nullptr;
   reff_surrogate sg = opts ? (reff_surrogate)opts->surrogate : nullptr;
   double spot_frac = 0.01, fb_err = 1e-2;
   if (sg) {

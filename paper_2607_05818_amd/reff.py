@@ -68,6 +68,7 @@ class reff_solve_opts(C.Structure):
         ("precision", C.c_int), ("rel_tol", C.c_double), ("max_iters", C.c_int32),
         ("block_rhs", C.c_int32), ("stream", C.c_void_p), ("out_on_device", C.c_int32),
         ("krylov", C.c_int), ("max_ir_steps", C.c_int32), ("timing", C.c_int32),
+        ("graphs", C.c_int32),
     ]
 
 
@@ -200,9 +201,11 @@ def _is_torch_cuda(x):
     return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
 
 
-def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing=False):
+def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing=False,
+          graphs=False):
     o = reff_solve_opts()
     o.timing = 1 if timing else 0
+    o.graphs = 1 if graphs else 0
     o.precision = int(precision)
     o.rel_tol = float(rel_tol)
     o.max_iters = int(max_iters)
@@ -219,7 +222,7 @@ def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, 
 
 def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP64,
                     rel_tol=0.0, max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None,
-                    max_ir_steps=0, allow_unconverged=False, timing=False):
+                    max_ir_steps=0, allow_unconverged=False, timing=False, graphs=False):
     """R_i = (G^-1)_ii for `nodes` (None = all).  Returns (R_out, stats)."""
     if nodes is None:
         count = pdn.num_nodes
@@ -239,7 +242,7 @@ def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP6
     else:
         assert R_out.dtype == np.float64 and R_out.flags.c_contiguous and len(R_out) >= count
         optr = R_out.ctypes.data
-    o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing)
+    o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing, graphs)
     st = reff_solve_stats()
     allow = (REFF_ERR_NO_CONVERGENCE,) if allow_unconverged else ()
     _check(_lib.reff_solve_diag(pdn.handle, nptr, count if nodes is not None else 0, optr,
@@ -267,7 +270,8 @@ def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
 
 def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.0,
                      max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None, R_out=None,
-                     timing=False, surrogate=None, spot_frac=0.0, fallback_rel_err=0.0):
+                     timing=False, surrogate=None, spot_frac=0.0, fallback_rel_err=0.0,
+                     graphs=False, tune_db=None):
     """Solve many plans in one call.  Returns (list of R arrays, list of stats)."""
     k = len(plans)
     structs = (reff_pdn_desc * k)()
@@ -302,7 +306,9 @@ def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.
             optrs[i] = o.ctypes.data
             outs.append(o)
     bo = reff_batch_opts()
-    bo.solve = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, 0, timing)
+    bo.solve = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, 0, timing, graphs)
+    if tune_db is not None:
+        bo.tune_db = os.fsencode(tune_db)
     if surrogate is not None:
         bo.surrogate = surrogate.handle
         bo.spot_frac = spot_frac

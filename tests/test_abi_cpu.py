@@ -89,7 +89,7 @@ def test_disconnected_tier_rejected():
     assert "no resistive path" in reff.reff_last_error()
 
 
-@pytest.mark.parametrize("case", ["bad_plan", "disconnected", "node_range", "tune_db"])
+@pytest.mark.parametrize("case", ["bad_plan", "disconnected", "node_range", "graphs_flag"])
 def test_batch_rejected_on_host(case):
     """reff_batch_plans validates every plan, node list and option before
     any device work (so these run without a GPU)."""
@@ -107,8 +107,8 @@ def test_batch_rejected_on_host(case):
         nodes[1] = np.array([gen.n_nodes(good)], dtype=np.int64)
         want = reff.REFF_ERR_INVALID_ARG
     else:
-        want = reff.REFF_ERR_UNSUPPORTED
-    if case == "tune_db":
+        want = reff.REFF_ERR_INVALID_ARG
+    if case == "graphs_flag":
         structs = (reff.reff_pdn_desc * 1)()
         s, keep = reff._desc_struct(good)
         structs[0] = s
@@ -117,7 +117,7 @@ def test_batch_rejected_on_host(case):
         cnt = (C.c_int64 * 1)(2)
         optr = (C.c_void_p * 1)(out.ctypes.data)
         bo = reff.reff_batch_opts()
-        bo.tune_db = b"tune.json"
+        bo.solve.graphs = 2
         st = reff._lib.reff_batch_plans(structs, 1, nptr, cnt, optr, C.byref(bo), None)
         assert st == want
         return

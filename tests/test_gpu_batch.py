@@ -107,3 +107,27 @@ def test_batch_recipe_sizes_sampled():
         err = _rel(outs[i], ro.diag(d, nodes[i]))
         print("plan", i, gen.n_nodes(d), err, stats[i]["iters_total"], flush=True)
         assert err <= 1e-3
+
+
+def test_tuning_database_created_and_reused(tmp_path):
+    """A batch with a tuning database times a few work-unit counts for its
+    size class, stores the fastest, and reuses it on the next call (same
+    launch layout, so bitwise the same results); results agree with the
+    untuned solve to the solver tolerance (only the summation order of the
+    Gram reductions differs)."""
+    reff = _reff()
+    plans = _small_plans(3)
+    nodes = [gen.sample_free_nodes(d, 64, 700 + i) for i, d in enumerate(plans)]
+    db = tmp_path / "tune.txt"
+    _say("tuning database")
+    a, _ = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_FP64, rel_tol=1e-10,
+                                 tune_db=str(db))
+    lines = db.read_text().split()
+    assert len(lines) == 2 and lines[0].startswith("f64-block-r") and int(lines[1]) in (512, 1024, 2048)
+    b, _ = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_FP64, rel_tol=1e-10,
+                                 tune_db=str(db))
+    c, _ = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_FP64, rel_tol=1e-10)
+    assert db.read_text().split() == lines
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y)
+        assert np.max(np.abs(x - z) / z) <= 1e-8
