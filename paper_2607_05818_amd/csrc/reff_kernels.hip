@@ -648,6 +648,23 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
   zero_acc(a3);
   double d3 = 0.0;
   const int64_t cofs = u.pd.cbase - u.pd.vbase;  // vector row -> coefficient index
+  // Rows of one chunk (clamped to the unit's last row; zeroed when staged).
+  T qv[NODES_PER_WAVE], rv[NODES_PER_WAVE], pv[NODES_PER_WAVE], dv[NODES_PER_WAVE];
+  T dinv_t = T(0);
+  auto load_chunk = [&](int64_t base) {
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
+      qv[i] = Q[v * S + lane];
+      rv[i] = R[v * S + lane];
+      if (WITH_D) {
+        pv[i] = P[v * S + lane];
+        dv[i] = D[v * S + lane];
+      }
+    }
+    if (threadIdx.x < CH) dinv_t = c.dinv[min(base + threadIdx.x, u.end - 1) + cofs];
+  };
+  if (!DIAG) load_chunk(u.begin);
   for (int64_t base = u.begin; base < u.end; base += CH) {
     if (DIAG) {
       T qv[NODES_PER_WAVE], rv[NODES_PER_WAVE], pv[NODES_PER_WAVE], dv[NODES_PER_WAVE];
@@ -673,19 +690,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
       }
       continue;
     }
-    T qv[NODES_PER_WAVE], rv[NODES_PER_WAVE], pv[NODES_PER_WAVE], dv[NODES_PER_WAVE];
-#pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
-      qv[i] = Q[v * S + lane];
-      rv[i] = R[v * S + lane];
-      if (WITH_D) {
-        pv[i] = P[v * S + lane];
-        dv[i] = D[v * S + lane];
-      }
-    }
-    T dinv_t = T(0);
-    if (threadIdx.x < CH) dinv_t = c.dinv[min(base + threadIdx.x, u.end - 1) + cofs];
+    // Stage this chunk (loaded one chunk ahead) and start loading the next.
 #pragma unroll
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
@@ -698,6 +703,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
       }
     }
     if (threadIdx.x < CH) sDinv[threadIdx.x] = base + threadIdx.x < u.end ? dinv_t : T(0);
+    if (base + CH < u.end) load_chunk(base + CH);
     __syncthreads();
     typename Acc<T>::type qa, pa = {0, 0, 0, 0};
     if (WITH_D)
@@ -764,9 +770,25 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
   double a4[2][4];
   zero_acc(a4);
   const int64_t cofs = u.pd.cbase - u.pd.vbase;
+  // Rows of one chunk (clamped to the unit's last row; zeroed when staged).
+  T rv[NODES_PER_WAVE], pv[NODES_PER_WAVE];
+  T dinv_t = T(0), d_t = T(0);
+  auto load_chunk = [&](int64_t base) {
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
+      pv[i] = P[v * S + lane];
+      rv[i] = R[v * S + lane];
+    }
+    if (threadIdx.x < CH) {
+      const int64_t v = min(base + threadIdx.x, u.end - 1) + cofs;
+      dinv_t = c.dinv[v];
+      d_t = c.d[v];
+    }
+  };
+  if (!DIAG) load_chunk(u.begin);
   for (int64_t base = u.begin; base < u.end; base += CH) {
     if (DIAG) {
-      T rv[NODES_PER_WAVE], pv[NODES_PER_WAVE];
 #pragma unroll
       for (int i = 0; i < NODES_PER_WAVE; ++i) {
         const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
@@ -780,19 +802,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
       }
       continue;
     }
-    T rv[NODES_PER_WAVE], pv[NODES_PER_WAVE];
-#pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
-      pv[i] = P[v * S + lane];
-      rv[i] = R[v * S + lane];
-    }
-    T dinv_t = T(0), d_t = T(0);
-    if (threadIdx.x < CH) {
-      const int64_t v = min(base + threadIdx.x, u.end - 1) + cofs;
-      dinv_t = c.dinv[v];
-      d_t = c.d[v];
-    }
+    // Stage this chunk (loaded one chunk ahead) and start loading the next.
 #pragma unroll
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
@@ -805,6 +815,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
       sDv[threadIdx.x][0] = ok ? dinv_t : T(0);
       sDv[threadIdx.x][1] = ok ? d_t : T(0);
     }
+    if (base + CH < u.end) load_chunk(base + CH);
     __syncthreads();
     const auto pd = prod_tile<T>(sP, nb, breg, lane);
     T yn[4];
