@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # dense matrix-core peaks
 S = 64
 
 
@@ -42,6 +43,15 @@ def kernel_bytes(n, fp32=True, mixed_with_d=True):
     k2 = n * ((6 if mixed_with_d else 3) * S * w + w)
     k3 = n * (3 * S * w + 2 * w)
     return [k1, k2, k3]
+
+
+def kernel_flops():
+    """Matrix-core flops per 64-column block row of the three block kernels
+    (2 S^2 per S x S product or Gram): K1 = P = Y T and Q = (G Y) T with T
+    upper triangular (10 of the 16 16 x 16 blocks of T are nonzero) plus the
+    Grams P^T Q and P^T R; K2 = Q A, P A and Q^T Z; K3 = P B and Y^T D Y."""
+    g = 2 * S * S
+    return [2 * g * 10 // 16 + 2 * g, 3 * g, 2 * g]
 
 
 def cpu_baseline(desc, batch_nodes, n_timed=2):
@@ -312,26 +322,41 @@ def main():
 
     fp32 = args.precision == "mixed"
     kb = kernel_bytes(1, fp32=fp32, mixed_with_d=fp32)
+    kf = kernel_flops()
+    mpeak = MFMA_PEAK_TFLOPS["f32" if fp32 else "f64"]
     names = ["stencil_gram", "update_r", "update_y"]
     kern = {}
     for i, nm in enumerate(names):
         avg_ms = kms[i] / max(kl[i], 1)
-        # A launch streams every unconverged block of the group: bytes per
-        # launch = bytes per node row x rows streamed / launches.
-        per_launch = kb[i] * krows[i] / max(kl[i], 1)
-        kern[nm] = {"avg_us": avg_ms * 1e3, "launches": int(kl[i]),
-                    "rows_per_launch": krows[i] / max(kl[i], 1),
+        # A launch streams every unconverged block of the group: bytes (and
+        # flops) per launch = per node row x rows streamed / launches.
+        rows = krows[i] / max(kl[i], 1)
+        per_launch = kb[i] * rows
+        flops = kf[i] * rows
+        # the binding ceiling: the larger of the two times at peak
+        t_hbm = per_launch / (HBM_PEAK_GBS * 1e9)
+        t_mfma = flops / (mpeak * 1e12)
+        kern[nm] = {"avg_us": avg_ms * 1e3, "launches": int(kl[i]), "rows_per_launch": rows,
                     "alg_bytes_per_row": int(kb[i]), "alg_bytes_per_launch": per_launch,
-                    "GBps": per_launch / (avg_ms * 1e-3) / 1e9}
+                    "alg_flops_per_row": int(kf[i]),
+                    "GBps": per_launch / (avg_ms * 1e-3) / 1e9,
+                    "TFLOPs": flops / (avg_ms * 1e-3) / 1e12,
+                    "hbm_frac": t_hbm / (avg_ms * 1e-3), "mfma_frac": t_mfma / (avg_ms * 1e-3),
+                    "bound": "mfma" if t_mfma > t_hbm else "hbm"}
     dom = max(range(3), key=lambda i: kms[i])
     dk = kern[names[dom]]
     mt = measured_traffic() if fp32 else None
     traffic = None
     if mt is not None:
         traffic = mt[names[dom]] * krows[dom] / max(kl[dom], 1)
-    roofline = {"bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dk["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": names[dom]}
+    if dk["bound"] == "mfma":
+        roofline = {"bound": "mfma", "achieved": dk["TFLOPs"], "peak": mpeak, "unit": "TFLOP/s",
+                    "frac": dk["TFLOPs"] / mpeak, "traffic": traffic, "kernel": names[dom],
+                    "hbm_frac": dk["hbm_frac"]}
+    else:
+        roofline = {"bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": dk["GBps"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": names[dom],
+                    "mfma_frac": dk["mfma_frac"]}
 
     compare = {}
     if not args.no_compare and args.precision == "mixed":
