@@ -95,6 +95,8 @@ typedef struct {
                             `stream` is a created (non-NULL) stream that is
                             not itself being captured and timing is off
                             (same results bitwise); 0: plain launches      */
+  int32_t progress;      /* 1: write a progress line (iterations, active
+                            blocks) to stderr at most every 10 s of a solve */
 } reff_solve_opts;
 
 typedef struct {

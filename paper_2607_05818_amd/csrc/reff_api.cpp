@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstddef>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <new>
@@ -308,6 +309,7 @@ struct Opts {
   bool timing;
   bool graphs;  // replay iteration chunks as HIP graphs where possible
   const char* tune_db = nullptr;  // tuning database path (batched solves)
+  bool progress = false;          // progress lines on stderr
 };
 
 reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
@@ -336,6 +338,8 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
   if (o->timing != 0 && o->timing != 1) return fail(REFF_ERR_INVALID_ARG, "timing must be 0 or 1");
   if (o->graphs != 0 && o->graphs != 1) return fail(REFF_ERR_INVALID_ARG, "graphs must be 0 or 1");
   out.graphs = o->graphs == 1;
+  if (o->progress != 0 && o->progress != 1) return fail(REFF_ERR_INVALID_ARG, "progress must be 0 or 1");
+  out.progress = o->progress == 1;
   out.timing = o->timing == 1;
   return REFF_OK;
 }
@@ -538,6 +542,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
   }
   PinnedBuf pin_tab, pin_flags;
   bool any_unconv = false;
+  auto last_report = std::chrono::steady_clock::now();
   // Chunks of `poll` iterations are captured once and replayed as a HIP
   // graph (the launch sequence of a chunk only changes with the active set),
   // on a created stream that is not itself being captured, without timing.
@@ -783,6 +788,15 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
                                     o.timing ? &evp.ev[6 * i] : nullptr));
         }
         it += k;
+        if (o.progress) {
+          const auto now = std::chrono::steady_clock::now();
+          if (std::chrono::duration<double>(now - last_report).count() >= 10.0) {
+            std::fprintf(stderr, "[reff] group of %d blocks: iteration %d, %zu blocks active\n", nb,
+                         it, active.size());
+            std::fflush(stderr);
+            last_report = now;
+          }
+        }
         hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(256), 0, o.stream, b.state, nb,
                            (int32_t*)ws.flags.p);
         HIPCHK(hipGetLastError());

@@ -68,7 +68,7 @@ class reff_solve_opts(C.Structure):
         ("precision", C.c_int), ("rel_tol", C.c_double), ("max_iters", C.c_int32),
         ("block_rhs", C.c_int32), ("stream", C.c_void_p), ("out_on_device", C.c_int32),
         ("krylov", C.c_int), ("max_ir_steps", C.c_int32), ("timing", C.c_int32),
-        ("graphs", C.c_int32),
+        ("graphs", C.c_int32), ("progress", C.c_int32),
     ]
 
 
@@ -202,8 +202,9 @@ def _is_torch_cuda(x):
 
 
 def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing=False,
-          graphs=False):
+          graphs=False, progress=False):
     o = reff_solve_opts()
+    o.progress = 1 if progress else 0
     o.timing = 1 if timing else 0
     o.graphs = 1 if graphs else 0
     o.precision = int(precision)
@@ -222,7 +223,8 @@ def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, 
 
 def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP64,
                     rel_tol=0.0, max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None,
-                    max_ir_steps=0, allow_unconverged=False, timing=False, graphs=False):
+                    max_ir_steps=0, allow_unconverged=False, timing=False, graphs=False,
+                    progress=False):
     """R_i = (G^-1)_ii for `nodes` (None = all).  Returns (R_out, stats)."""
     if nodes is None:
         count = pdn.num_nodes
@@ -242,7 +244,8 @@ def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP6
     else:
         assert R_out.dtype == np.float64 and R_out.flags.c_contiguous and len(R_out) >= count
         optr = R_out.ctypes.data
-    o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing, graphs)
+    o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing, graphs,
+              progress)
     st = reff_solve_stats()
     allow = (REFF_ERR_NO_CONVERGENCE,) if allow_unconverged else ()
     _check(_lib.reff_solve_diag(pdn.handle, nptr, count if nodes is not None else 0, optr,
