@@ -29,29 +29,38 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # dense matrix-core peaks
 S = 64
 
 
-def kernel_bytes(n, fp32=True, mixed_with_d=True):
-    """Algorithmic HBM bytes per launch of the three block kernels for an
-    n-node stack and S right-hand sides (w = bytes per word):
+def kernel_bytes(n, fp32=True, mixed_with_d=True, cheb=1):
+    """Algorithmic HBM bytes per launch of the block kernels for an n-node
+    stack and S right-hand sides (w = bytes per word):
       stencil+Gram (K1): read Y, R; write P = Y T, Q = (G Y) T -> 4 S w per node
                          + coefficients d, cE, cN (w each) and the TSV slot (4)
       residual update (K2): read Q, R (P, D); write R (D)       -> 3 (6) S w
-                         + Dinv
-      search block (K3): read P, R; write Y                     -> 3 S w + d, Dinv
+                         + Dinv; with the polynomial preconditioner it also
+                         writes z_1 = D^-1 R / theta            -> + S w
+      search block (K3): read P, R (or Z); write Y              -> 3 S w + d, Dinv
+      preconditioner (degree k > 1): step 1 reads z_1, R and writes z_2, each
+                         later step also reads z_{j-1}; then Q^T Z reads Q, Z
+                         -> (3 + 4 (k - 2)) S w + 2 S w + coefficients per step
     """
     w = 4 if fp32 else 8
     k1 = n * (4 * S * w + 3 * w + 4)
-    k2 = n * ((6 if mixed_with_d else 3) * S * w + w)
+    k2 = n * ((6 if mixed_with_d else 3) * S * w + w + (S * w if cheb > 1 else 0))
     k3 = n * (3 * S * w + 2 * w)
-    return [k1, k2, k3]
+    kp = n * ((3 + 4 * (cheb - 2)) * S * w + 2 * S * w + (cheb - 1) * (4 * w + 4)) if cheb > 1 else 0
+    return [k1, k2, k3, kp]
 
 
-def kernel_flops():
-    """Matrix-core flops per 64-column block row of the three block kernels
+def kernel_flops(cheb=1):
+    """Matrix-core flops per 64-column block row of the block kernels
     (2 S^2 per S x S product or Gram): K1 = P = Y T and Q = (G Y) T with T
     upper triangular (10 of the 16 16 x 16 blocks of T are nonzero) plus the
-    Grams P^T Q and P^T R; K2 = Q A, P A and Q^T Z; K3 = P B and Y^T D Y."""
+    Grams P^T Q and P^T R; K2 = Q A, P A and (Jacobi) Q^T Z; K3 = P B and
+    Y^T D Y; the polynomial preconditioner's Q^T Z Gram (its steps are
+    stencil arithmetic, not matrix-core work)."""
     g = 2 * S * S
-    return [2 * g * 10 // 16 + 2 * g, 3 * g, 2 * g]
+    if cheb > 1:
+        return [2 * g * 10 // 16 + 2 * g, 2 * g, 2 * g, g]
+    return [2 * g * 10 // 16 + 2 * g, 3 * g, 2 * g, 0]
 
 
 def cpu_baseline(desc, batch_nodes, n_timed=2):
@@ -142,9 +151,9 @@ def batched_compare(reff, gen, log, rel_tol, n_seq=16):
 
 
 def measured_traffic():
-    """HBM bytes per node row of the block kernels from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel
-    sources have changed since the counters were taken."""
+    """The committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (HBM bytes per
+    node row of the block kernels, and the preconditioner degree it was
+    taken with), or None when the kernel sources have changed since."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "block_pcg_mixed_4x512x512_hbm_traffic.md")
@@ -158,7 +167,7 @@ def measured_traffic():
         return None
     if h.hexdigest()[:16] != rec["sources_sha256_16"]:
         return None
-    return rec["hbm_bytes_per_row"]
+    return rec
 
 
 def surrogate_compare(reff, gen, log, rel_tol, n_train=512, n_test=16, per_test=640,
@@ -290,6 +299,8 @@ def main():
     ap.add_argument("--rel-tol", type=float, default=1e-4)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--krylov", choices=["block", "indep"], default="block")
+    ap.add_argument("--precond-degree", type=int, default=10,
+                    help="Chebyshev preconditioner degree (1 = Jacobi)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -347,15 +358,15 @@ def main():
     def step(timing):
         return reff.reff_solve_diag(h, batch, out, precision=prec, krylov=kry,
                                     rel_tol=args.rel_tol, stream=stream.cuda_stream,
-                                    timing=timing)[1]
+                                    timing=timing, precond_degree=args.precond_degree)[1]
 
     for w in range(args.warmup):
         st = step(False)
         log(f"warmup {w}: {st['iters_total']} iterations, {st['seconds']:.2f} s")
     torch.cuda.synchronize()
-    kms = np.zeros(3)
-    kl = np.zeros(3, dtype=np.int64)
-    krows = np.zeros(3, dtype=np.int64)
+    kms = np.zeros(4)
+    kl = np.zeros(4, dtype=np.int64)
+    krows = np.zeros(4, dtype=np.int64)
     iters = 0
     worst = 0.0
     n_ok = 0
@@ -377,12 +388,15 @@ def main():
     value = n_ok * args.steps / elapsed
 
     fp32 = args.precision == "mixed"
-    kb = kernel_bytes(1, fp32=fp32, mixed_with_d=fp32)
-    kf = kernel_flops()
+    cheb = args.precond_degree if args.krylov == "block" else 1
+    kb = kernel_bytes(1, fp32=fp32, mixed_with_d=fp32, cheb=cheb)
+    kf = kernel_flops(cheb)
     mpeak = MFMA_PEAK_TFLOPS["f32" if fp32 else "f64"]
-    names = ["stencil_gram", "update_r", "update_y"]
+    names = ["stencil_gram", "update_r", "update_y", "precond"]
     kern = {}
     for i, nm in enumerate(names):
+        if kl[i] == 0 or kms[i] == 0:
+            continue
         avg_ms = kms[i] / max(kl[i], 1)
         # A launch streams every unconverged block of the group: bytes (and
         # flops) per launch = per node row x rows streamed / launches.
@@ -399,12 +413,13 @@ def main():
                     "TFLOPs": flops / (avg_ms * 1e-3) / 1e12,
                     "hbm_frac": t_hbm / (avg_ms * 1e-3), "mfma_frac": t_mfma / (avg_ms * 1e-3),
                     "bound": "mfma" if t_mfma > t_hbm else "hbm"}
-    dom = max(range(3), key=lambda i: kms[i])
+    dom = max(range(4), key=lambda i: kms[i])
     dk = kern[names[dom]]
     mt = measured_traffic() if fp32 else None
     traffic = None
-    if mt is not None:
-        traffic = mt[names[dom]] * krows[dom] / max(kl[dom], 1)
+    if (mt is not None and names[dom] in mt["hbm_bytes_per_row"]
+            and mt.get("precond_degree", 1) == cheb):
+        traffic = mt["hbm_bytes_per_row"][names[dom]] * krows[dom] / max(kl[dom], 1)
     if dk["bound"] == "mfma":
         roofline = {"bound": "mfma", "achieved": dk["TFLOPs"], "peak": mpeak, "unit": "TFLOP/s",
                     "frac": dk["TFLOPs"] / mpeak, "traffic": traffic, "kernel": names[dom],
@@ -461,7 +476,7 @@ def main():
                                "lognormal(0,0.3) S edges, 1024 clustered TSVs at 5 S, 256 pads; "
                                f"{B} seeded sampled nodes per step",
                    "precision": args.precision, "krylov": args.krylov, "rel_tol": args.rel_tol,
-                   "block_rhs": S},
+                   "block_rhs": S, "precond_degree": cheb},
         "accuracy": {"max_rel_err": worst, "n_ok": n_ok, "n": B},
         "iters_per_step": iters / args.steps,
         "kernels": kern,

@@ -97,6 +97,12 @@ typedef struct {
                             (same results bitwise); 0: plain launches      */
   int32_t progress;      /* 1: write a progress line (iterations, active
                             blocks) to stderr at most every 10 s of a solve */
+  int32_t precond_degree;/* block Krylov variant: 1 = Jacobi (D^-1); 2..16 =
+                            Chebyshev polynomial preconditioner
+                            q(D^-1 G) D^-1 of that degree (SPD and fixed,
+                            so the results are those of PCG with a stronger
+                            preconditioner; fewer, costlier iterations);
+                            0 => 10.  The independent variant uses Jacobi. */
 } reff_solve_opts;
 
 typedef struct {
@@ -109,13 +115,14 @@ typedef struct {
                              error (not a bound)                             */
   int64_t iters_total;    /* sum of block iterations over all blocks         */
   /* With opts->timing: summed device time (ms) and launch count of the
-     stencil+Gram kernel [0], the residual-update kernel [1] and the
-     search-block kernel [2], and the node rows those launches streamed
-     (one row = one node of one 64-column block; a launch covers every
-     unconverged block of its group). */
-  double kernel_ms[3];
-  int64_t kernel_launches[3];
-  int64_t kernel_rows[3];
+     stencil+Gram kernel [0], the residual-update kernel [1], the
+     search-block kernel [2] and the polynomial preconditioner's kernels
+     (its steps and the Q^T Z Gram) [3], and the node rows those launches
+     streamed (one row = one node of one 64-column block; a launch covers
+     every unconverged block of its group). */
+  double kernel_ms[4];
+  int64_t kernel_launches[4];
+  int64_t kernel_rows[4];
   /* reff_batch_plans with a surrogate: 1 if the plan's results are the
      model's predictions (solved values at the checked nodes), 0 if it fell
      back to the solver; the largest relative error of the prediction over

@@ -310,6 +310,7 @@ struct Opts {
   bool graphs;  // replay iteration chunks as HIP graphs where possible
   const char* tune_db = nullptr;  // tuning database path (batched solves)
   bool progress = false;          // progress lines on stderr
+  int cheb = 10;                  // Chebyshev preconditioner degree (1 = Jacobi)
 };
 
 reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
@@ -340,6 +341,9 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
   out.graphs = o->graphs == 1;
   if (o->progress != 0 && o->progress != 1) return fail(REFF_ERR_INVALID_ARG, "progress must be 0 or 1");
   out.progress = o->progress == 1;
+  if (o->precond_degree < 0 || o->precond_degree > MAX_CHEB)
+    return fail(REFF_ERR_INVALID_ARG, "precond_degree must be in [0, 16]");
+  out.cheb = o->precond_degree == 0 ? 10 : o->precond_degree;
   out.timing = o->timing == 1;
   return REFF_OK;
 }
@@ -372,7 +376,7 @@ struct BlockResult {
 
 void reff::Workspace::release() {
   for (DevBuf* b : {&Y, &P, &Q, &R, &D, &X, &part, &W, &small, &state, &tgt, &pos, &plans, &units,
-                    &uid, &act, &out, &xs, &rows, &map, &flags, &strips, &sid})
+                    &uid, &act, &out, &xs, &rows, &map, &flags, &strips, &sid, &Za, &Zb})
     if (b->p) {
       (void)hipFree(b->p);
       b->p = nullptr;
@@ -528,7 +532,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
   const Coef<double> c64 = coef64(cs);
   const Coef<float> c32 = coef32(cs);
   const void* coef = fp32 ? (const void*)&c32 : (const void*)&c64;
-  const int poll = 8;
+  const int poll = 4;  // iterations between convergence checks
 
   struct EventPool {
     std::vector<hipEvent_t> ev;
@@ -537,7 +541,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     }
   } evp;
   if (o.timing) {
-    evp.ev.resize(6 * poll);
+    evp.ev.resize(8 * poll);
     for (auto& e : evp.ev) HIPCHK(hipEventCreate(&e));
   }
   PinnedBuf pin_tab, pin_flags;
@@ -616,7 +620,8 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     make_units(pin, plans, units, tunits);
     nu = (int)units.size();
     strips.clear();
-    if (fp32 && !o.indep) make_strips(plans, strips, tunits);
+    const bool cheb = !o.indep && o.cheb > 1;
+    if ((fp32 || cheb) && !o.indep) make_strips(plans, strips, tunits);
     ns = (int)strips.size();
     // ---- buffers
     reff_status rs;
@@ -627,6 +632,8 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     if ((rs = ensure(ws.R, vec)) != REFF_OK) return rs;
     if (with_d && (rs = ensure(ws.D, vec)) != REFF_OK) return rs;
     if (o.mixed && (rs = ensure(ws.X, (size_t)rows * S * sizeof(double))) != REFF_OK) return rs;
+    if (cheb && (rs = ensure(ws.Za, vec)) != REFF_OK) return rs;
+    if (cheb && (rs = ensure(ws.Zb, vec)) != REFF_OK) return rs;
     if ((rs = ensure(ws.part, (size_t)std::max(nu, ns) * NGRAM * S * S * sizeof(double))) != REFF_OK)
       return rs;
     if ((rs = ensure(ws.W, (size_t)nb * NGRAM * S * S * sizeof(double))) != REFF_OK) return rs;
@@ -706,6 +713,25 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     b.n_units = nu;
     b.n_strips = ns;
     b.rows = rows;
+    if (cheb) {
+      // Chebyshev semi-iteration for D^-1 G on [lmax / (6 k^2), lmax], lmax = 2
+      // (the spectrum of D^-1 G lies in (0, 2]): q > 0 on (0, 2], so
+      // M^-1 = q(D^-1 G) D^-1 is SPD.
+      const double lmax = 2.0, lmin = lmax / (6.0 * o.cheb * o.cheb);
+      const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+      const double sigma = theta / delta;
+      double rho = 1.0 / sigma;
+      b.cheb_k = o.cheb;
+      b.cheb_invtheta = 1.0 / theta;
+      for (int j = 1; j < o.cheb; ++j) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        b.cheb_a1[j] = rn * rho;
+        b.cheb_a2[j] = 2.0 * rn / delta;
+        rho = rn;
+      }
+      b.Za = ws.Za.p;
+      b.Zb = ws.Zb.p;
+    }
 
     HIPCHK(launch_init_blocks(fp32, o.indep, coef, b, o.stream));
     if (with_d && !fp32) HIPCHK(launch_zero_x((double*)b.D, rows * S, o.stream));
@@ -785,7 +811,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
         } else {
           for (int i = 0; i < k; ++i)
             HIPCHK(launch_iteration(fp32, o.indep, with_d, coef, b, o.tol, o.stream,
-                                    o.timing ? &evp.ev[6 * i] : nullptr));
+                                    o.timing ? &evp.ev[8 * i] : nullptr));
         }
         it += k;
         if (o.progress) {
@@ -805,9 +831,9 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
         HIPCHK(hipStreamSynchronize(o.stream));
         if (o.timing && st) {
           for (int i = 0; i < k; ++i)
-            for (int kk = 0; kk < 3; ++kk) {
+            for (int kk = 0; kk < 4; ++kk) {
               float ms = 0.f;
-              HIPCHK(hipEventElapsedTime(&ms, evp.ev[6 * i + 2 * kk], evp.ev[6 * i + 2 * kk + 1]));
+              HIPCHK(hipEventElapsedTime(&ms, evp.ev[8 * i + 2 * kk], evp.ev[8 * i + 2 * kk + 1]));
               st->kernel_ms[kk] += ms;
               st->kernel_launches[kk] += 1;
               st->kernel_rows[kk] += act_rows;
@@ -1550,7 +1576,7 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
       add_stats(&ps, br, job0[(size_t)i], job0[(size_t)i + 1]);
       ps.seconds = secs;
       if (i == 0)
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
           ps.kernel_ms[k] = agg.kernel_ms[k];
           ps.kernel_launches[k] = agg.kernel_launches[k];
           ps.kernel_rows[k] = agg.kernel_rows[k];

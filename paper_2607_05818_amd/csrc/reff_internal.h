@@ -24,6 +24,7 @@ constexpr int NODES_PER_WAVE = CH / (WG / 64);  // 4
 constexpr int HIST = 16;     // convergence window (iterations)
 constexpr int MAX_GRID = 512;
 constexpr int NGRAM = 4;     // Gram partials per work unit
+constexpr int MAX_CHEB = 16;  // largest Chebyshev preconditioner degree
 // A column is converged once its estimated remaining relative error is
 // below CONV_SAFETY * rel_tol.
 constexpr double CONV_SAFETY = 0.25;
@@ -117,7 +118,7 @@ struct DevBuf {
 // Device work arrays of the block solver (grown on demand, reused).
 struct Workspace {
   DevBuf Y, P, Q, R, D, X, part, W, small, state, tgt, pos, plans, units, uid, act, out, xs,
-      rows, map, flags, strips, sid;
+      rows, map, flags, strips, sid, Za, Zb;
   void release();
 };
 
@@ -185,6 +186,15 @@ struct SolveBuffers {
   int n_units;   // active units (grid of the vector kernels)
   int n_strips;  // active strips (grid of the strip stencil kernel; 0 = not used)
   int64_t rows;  // vector rows covered by the active units' blocks
+  // Chebyshev polynomial preconditioner of degree cheb_k (block variant;
+  // 1 = Jacobi): Z = q(D^-1 G) D^-1 R by cheb_k - 1 strip steps from
+  // z_1 = D^-1 R / theta, step j using cheb_a1[j], cheb_a2[j].
+  int cheb_k = 1;
+  double cheb_invtheta = 1.0;
+  double cheb_a1[MAX_CHEB] = {};
+  double cheb_a2[MAX_CHEB] = {};
+  void* Za = nullptr;  // rows x S, T: Chebyshev iterates (ping-pong)
+  void* Zb = nullptr;
 };
 
 int grid_for(int64_t n);

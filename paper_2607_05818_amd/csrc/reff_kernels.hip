@@ -621,13 +621,18 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram_strip(Coef<T> c, Work wk
 
 // ---------------------------------------------------------------- K2
 // R -= Q A;  (D += P A);  Z = Dinv R;  W3 = Q^T Z.
-template <typename T, bool DIAG, bool WITH_D>
+// With CHEB (polynomial preconditioner, block variant) the kernel writes
+// z_1 = D^-1 R / theta to Z1 (the Chebyshev steps' start) instead of
+// forming W3, which a Gram kernel takes from the finished Z.
+template <typename T, bool DIAG, bool WITH_D, bool CHEB = false>
 __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
                                                     const T* __restrict__ alpha,
                                                     const T* __restrict__ Q,
                                                     const T* __restrict__ P, T* __restrict__ R,
                                                     T* __restrict__ D,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part,
+                                                    T* __restrict__ Z1 = nullptr,
+                                                    T inv_theta = T(1)) {
   __shared__ __align__(16) T sQ[DIAG ? 1 : CH][LDW];
   __shared__ __align__(16) T sP[DIAG ? 1 : CH][LDW];  // P rows, then Z rows
   __shared__ __align__(16) T sR[DIAG ? 1 : CH][LDW];
@@ -716,6 +721,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
       const int row = nb * 16 + tile_row<T>(lane, r), col = cb * 16 + (lane & 15);
       rn[r] = sR[row][col] - qa[r];
       zn[r] = sDinv[row] * rn[r];
+      if (CHEB) zn[r] *= inv_theta;
       if (WITH_D) dn[r] = sD[row][col] + pa[r];
     }
     __syncthreads();
@@ -727,7 +733,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
       if (WITH_D) sD[row][col] = dn[r];
     }
     __syncthreads();
-    gram_chunk<T>(sQ, sP, w, lane, a3);
+    if (!CHEB) gram_chunk<T>(sQ, sP, w, lane, a3);
 #pragma unroll
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
@@ -735,19 +741,22 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
       if (v < u.end) {
         R[v * S + lane] = sR[row][lane];
         if (WITH_D) D[v * S + lane] = sD[row][lane];
+        if (CHEB) Z1[v * S + lane] = sP[row][lane];
       }
     }
     __syncthreads();
   }
   if (DIAG)
     diag_store(part_of(part, uidx, 2), d3, w, lane);
-  else
+  else if (!CHEB)
     gram_store<T>(part_of(part, uidx, 2), w, lane, a3);
 }
 
 // ---------------------------------------------------------------- K3
 // Y = Dinv R - P B;  W4 = Y^T D Y (block variant).
-template <typename T, bool DIAG>
+// With ZBUF the argument R is the preconditioned residual Z (polynomial
+// preconditioner) and Y = Z - P B.
+template <typename T, bool DIAG, bool ZBUF = false>
 __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
                                                     const T* __restrict__ delta,
                                                     const T* __restrict__ R,
@@ -822,7 +831,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = nb * 16 + tile_row<T>(lane, r), col = cb * 16 + (lane & 15);
-      yn[r] = sDv[row][0] * sR[row][col] - pd[r];
+      yn[r] = (ZBUF ? sR[row][col] : sDv[row][0] * sR[row][col]) - pd[r];
     }
     __syncthreads();
 #pragma unroll
@@ -844,33 +853,192 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
   if (!DIAG) gram_store<T>(part_of(part, uidx, 3), w, lane, a4);
 }
 
-// W4 = Y^T D Y alone (used when a refinement step restarts from a new Y).
-template <typename T>
-__global__ __launch_bounds__(WG, 4) void k_gram_dy(Coef<T> c, Work wk, const T* __restrict__ Y,
-                                                   double* __restrict__ part) {
-  __shared__ __align__(16) T sY[CH][LDW];
-  __shared__ __align__(16) T sDY[CH][LDW];
+// Gram m of each unit: A^T B (DSCALE: A^T D B) over its rows.  Used for
+// W4 = Y^T D Y when a solve starts from a new Y, and for W3 = Q^T Z when the
+// preconditioner is a polynomial (Z then comes from its own kernels).
+template <typename T, bool DSCALE>
+__global__ __launch_bounds__(WG, 4) void k_gram_ab(Coef<T> c, Work wk, const T* __restrict__ A,
+                                                   const T* __restrict__ B,
+                                                   double* __restrict__ part, int m) {
+  __shared__ __align__(16) T sA[CH][LDW];
+  __shared__ __align__(16) T sB[CH][LDW];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const UnitCtx u = unit_ctx(wk);
   const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
   const int64_t cofs = u.pd.cbase - u.pd.vbase;
-  double a4[2][4];
-  zero_acc(a4);
+  double acc[2][4];
+  zero_acc(acc);
   for (int64_t base = u.begin; base < u.end; base += CH) {
+    T av[NODES_PER_WAVE], bv[NODES_PER_WAVE];
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
+      av[i] = A[v * S + lane];
+      bv[i] = B[v * S + lane];
+      if (DSCALE) bv[i] *= ldc(c.d, v + cofs);
+    }
 #pragma unroll
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
-      const int64_t v = base + row;
-      const T y = v < u.end ? Y[v * S + lane] : T(0);
-      sY[row][lane] = y;
-      sDY[row][lane] = v < u.end ? c.d[v + cofs] * y : T(0);
+      const bool ok = base + row < u.end;
+      sA[row][lane] = ok ? av[i] : T(0);
+      sB[row][lane] = ok ? bv[i] : T(0);
     }
     __syncthreads();
-    gram_chunk<T>(sY, sDY, w, lane, a4);
+    gram_chunk<T>(sA, sB, w, lane, acc);
     __syncthreads();
   }
-  gram_store<T>(part_of(part, uidx, 3), w, lane, a4);
+  gram_store<T>(part_of(part, uidx, m), w, lane, acc);
+}
+
+// One step of the Chebyshev polynomial preconditioner Z = q(D^-1 G) D^-1 R
+// (block variant, over strips like the stencil kernel):
+//   zout = u + a1 (u - uprev) + a2 D^-1 (R - G u),   u = z_j, uprev = z_{j-1}
+// (uprev = 0 without HAS_PREV).  zout may be the uprev array: every row of it
+// is read, then written, by the same thread.
+template <typename T, bool HAS_PREV>
+__global__ __launch_bounds__(WG, 4) void k_cheb_strip(Coef<T> c, Work wk, const T* __restrict__ zin,
+                                                      const T* zprev, const T* __restrict__ R,
+                                                      T* zout, T a1, T a2) {
+  constexpr int HWW = CH + 2;
+  __shared__ __align__(16) T win[3][HWW][LDW];
+  __shared__ T cd[2][CH], ce[2][CH + 1], cn[2][CH], cdi[2][CH];
+  __shared__ int cslot[2][CH];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int sidx = wk.sid[logical_block(blockIdx.x, gridDim.x)];
+  const Strip st = wk.strips[sidx];
+  const PlanDesc pd = wk.plans[st.plan];
+  const int64_t nx = pd.nx;
+  const int ny = (int)(pd.plane / pd.nx);
+  const int wdt = st.wdt;
+  const bool has_w = st.x0 > 0;
+  const bool has_e = st.x0 + wdt < pd.nx;
+  auto load_row = [&](int yy, T (&v)[NODES_PER_WAVE], T& halo) {
+    const bool in = yy >= 0 && yy < ny;
+    const int64_t base = pd.vbase + st.lrow0 + (int64_t)(yy - st.y0) * nx;
+    const int64_t safe = in ? base : pd.vbase + st.lrow0;
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int j = min(w * NODES_PER_WAVE + i, wdt - 1);
+      v[i] = zin[(safe + j) * S + lane];
+      if (!in) v[i] = T(0);
+    }
+    halo = T(0);
+    if (w == 0) {
+      const T h = zin[(safe - (has_w ? 1 : 0)) * S + lane];
+      halo = (in && has_w) ? h : T(0);
+    } else if (w == 1) {
+      const T h = zin[(safe + (has_e ? wdt : 0)) * S + lane];
+      halo = (in && has_e) ? h : T(0);
+    }
+  };
+  auto store_row = [&](int slot, const T (&v)[NODES_PER_WAVE], T halo) {
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int j = w * NODES_PER_WAVE + i;
+      win[slot][j + 1][lane] = j < wdt ? v[i] : T(0);
+    }
+    if (w == 0) win[slot][0][lane] = halo;
+    if (w == 1 && wdt == CH) win[slot][CH + 1][lane] = halo;
+  };
+  // pointwise rows of strip row s: R and (HAS_PREV) uprev
+  auto load_pt = [&](int s, T (&rv)[NODES_PER_WAVE], T (&pv)[NODES_PER_WAVE]) {
+    const int64_t base = pd.vbase + st.lrow0 + (int64_t)min(s, st.nrows - 1) * nx;
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int j = min(w * NODES_PER_WAVE + i, wdt - 1);
+      rv[i] = R[(base + j) * S + lane];
+      pv[i] = HAS_PREV ? zprev[(base + j) * S + lane] : T(0);
+    }
+  };
+  // Coefficients of strip row s, one value per thread t < 5 CH + 1 (d, cE
+  // from node x0 - 1, cN, Dinv, slot as in the stencil kernel).
+  const int t = threadIdx.x;
+  auto load_coef = [&](int srow, T& val, int& sl) {
+    const int64_t base = pd.cbase + st.lrow0 + (int64_t)min(srow, st.nrows - 1) * nx;
+    val = T(0);
+    sl = -1;
+    if (t < CH) {
+      val = c.d[base + min(t, wdt - 1)];
+    } else if (t <= 2 * CH) {
+      const int e = t - CH;
+      const bool ok = (e > 0 || has_w) && e <= wdt;
+      const T v = c.cE[base + min(max(e - 1, has_w ? -1 : 0), wdt - 1)];
+      val = ok ? v : T(0);
+    } else if (t <= 3 * CH) {
+      val = c.cN[base + min(t - 2 * CH - 1, wdt - 1)];
+    } else if (t <= 4 * CH) {
+      sl = c.slot[base + min(t - 3 * CH - 1, wdt - 1)];
+    } else if (t <= 5 * CH) {
+      val = c.dinv[base + min(t - 4 * CH - 1, wdt - 1)];
+    }
+  };
+  auto store_coef = [&](int b, T val, int sl) {
+    if (t < CH) cd[b][t] = val;
+    else if (t <= 2 * CH) ce[b][t - CH] = val;
+    else if (t <= 3 * CH) cn[b][t - 2 * CH - 1] = val;
+    else if (t <= 4 * CH) cslot[b][t - 3 * CH - 1] = sl;
+    else if (t <= 5 * CH) cdi[b][t - 4 * CH - 1] = val;
+  };
+  {
+    T v[NODES_PER_WAVE], h;
+    load_row(st.y0 - 1, v, h);
+    store_row(0, v, h);
+    load_row(st.y0, v, h);
+    store_row(1, v, h);
+    if (t > 2 * CH && t <= 3 * CH) {
+      const int j = t - 2 * CH - 1;
+      const int64_t ci = pd.cbase + st.lrow0 + min(j, wdt - 1) - nx;  // row y0 - 1
+      cn[1][j] = st.y0 > 0 ? c.cN[st.y0 > 0 ? ci : ci + nx] : T(0);
+    }
+  }
+  T ny_v[NODES_PER_WAVE], ny_h, r_v[NODES_PER_WAVE], p_v[NODES_PER_WAVE], c_v;
+  int c_sl;
+  load_row(st.y0 + 1, ny_v, ny_h);
+  load_pt(0, r_v, p_v);
+  load_coef(0, c_v, c_sl);
+  for (int s = 0; s < st.nrows; ++s) {
+    const int y = st.y0 + s;
+    const int sc = (s + 1) % 3, sn = (s + 2) % 3, ss = s % 3;  // rows y, y+1, y-1
+    const int b = s & 1;
+    store_row(sn, ny_v, ny_h);
+    store_coef(b, c_v, c_sl);
+    T rc[NODES_PER_WAVE], pc[NODES_PER_WAVE];
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      rc[i] = r_v[i];
+      pc[i] = p_v[i];
+    }
+    if (s + 1 < st.nrows) {
+      load_row(y + 2, ny_v, ny_h);
+      load_pt(s + 1, r_v, p_v);
+      load_coef(s + 1, c_v, c_sl);
+    }
+    __syncthreads();
+    const int64_t obase = pd.vbase + st.lrow0 + (int64_t)s * nx;
+#pragma unroll
+    for (int i = 0; i < NODES_PER_WAVE; ++i) {
+      const int j = w * NODES_PER_WAVE + i;
+      const int jc = min(j, wdt - 1);
+      const T uc = win[sc][jc + 1][lane];
+      T g = cd[b][jc] * uc - ce[b][jc + 1] * win[sc][jc + 2][lane] - ce[b][jc] * win[sc][jc][lane] -
+            cn[b][jc] * win[sn][jc + 1][lane] - cn[b ^ 1][jc] * win[ss][jc + 1][lane];
+      const int sl = __builtin_amdgcn_readfirstlane(cslot[b][jc]);
+      if (sl >= 0) {  // wave-uniform: TSV segments to the tiers above / below
+        const T gu = ldc(c.up, sl);
+        const T gd = ldc(c.dn, sl);
+        const int64_t v = obase + jc;
+        const T yu = zin[(gu != T(0) ? v + pd.plane : v) * S + lane];
+        const T yd = zin[(gd != T(0) ? v - pd.plane : v) * S + lane];
+        g -= gu * yu + gd * yd;
+      }
+      const T zn = uc + a1 * (uc - pc[i]) + a2 * cdi[b][jc] * (rc[i] - g);
+      if (j < wdt) zout[(obase + j) * S + lane] = zn;
+    }
+    __syncthreads();
+  }
 }
 
 // C = Xa^T (G Xb) over all nodes of a block (pair resistances: the
@@ -1439,11 +1607,68 @@ __global__ void k_gather_rows(const double* __restrict__ X, const int64_t* __res
     rows[e] = X[nodes[e / S] * S + (e % S)];
 }
 
+// z_1 = D^-1 R / theta over the active units (start of the Chebyshev steps
+// when a solve starts from a new residual).
+template <typename T>
+__global__ void k_scale_units(Coef<T> c, Work wk, const T* __restrict__ R, T* __restrict__ Z,
+                              T inv_theta) {
+  const int uidx = wk.uid[blockIdx.x];
+  const Unit u = wk.units[uidx];
+  const PlanDesc pd = wk.plans[u.plan];
+  const int64_t cofs = pd.cbase - pd.vbase;
+  const int64_t cnt = (u.end - u.begin) * S;
+  for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int64_t v = u.begin + i / S;
+    Z[u.begin * S + i] = c.dinv[v + cofs] * R[u.begin * S + i] * inv_theta;
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 static void reduce(const SolveBuffers& b, int m0, int nmat, int len, hipStream_t st,
                    bool strips = false) {
   hipLaunchKernelGGL(k_reduce, dim3((nmat * len + 63) / 64, b.n_act), dim3(256), 0, st, b.part,
                      b.W, b.work.plans, b.act, m0, nmat, len, strips ? 1 : 0);
+}
+
+// Chebyshev steps j = 1 .. cheb_k - 1 from z_1 in Za; the iterates
+// alternate between Za and Zb (z_{j+1} overwrites z_{j-1}); the last step
+// writes to `last` if given.  Returns the array that holds Z.
+template <typename T>
+static T* cheb_steps(const Coef<T>& c, const SolveBuffers& b, hipStream_t st, T* last) {
+  const dim3 g(b.n_strips), blk(WG);
+  T* in = (T*)b.Za;
+  T* prev = nullptr;
+  const T* R = (const T*)b.R;
+  for (int j = 1; j < b.cheb_k; ++j) {
+    T* out = j == 1 ? (T*)b.Zb : prev;
+    if (j == b.cheb_k - 1 && last) out = last;
+    const T a1 = (T)b.cheb_a1[j], a2 = (T)b.cheb_a2[j];
+    if (j == 1)
+      hipLaunchKernelGGL((k_cheb_strip<T, false>), g, blk, 0, st, c, b.work, (const T*)in,
+                         (const T*)nullptr, R, out, a1, a2);
+    else
+      hipLaunchKernelGGL((k_cheb_strip<T, true>), g, blk, 0, st, c, b.work, (const T*)in,
+                         (const T*)prev, R, out, a1, a2);
+    prev = in;
+    in = out;
+  }
+  return in;
+}
+
+// Y = M^-1 R for a solve that starts from the residual in R, then T from
+// the guarded sweep of Y^T D Y (block variant, polynomial preconditioner).
+template <typename T>
+static void precond_start(const Coef<T>& c, const SolveBuffers& b, hipStream_t st) {
+  const double eps4 = sizeof(T) == 8 ? 1e-14 : 1e-6;
+  const double tau = sizeof(T) == 8 ? 1e-26 : 1e-12;
+  hipLaunchKernelGGL((k_scale_units<T>), dim3(b.n_units), dim3(256), 0, st, c, b.work,
+                     (const T*)b.R, (T*)b.Za, (T)b.cheb_invtheta);
+  cheb_steps<T>(c, b, st, (T*)b.Y);
+  hipLaunchKernelGGL((k_gram_ab<T, true>), dim3(b.n_units), dim3(WG), 0, st, c, b.work,
+                     (const T*)b.Y, (const T*)b.Y, b.part, 3);
+  reduce(b, 3, 1, S * S, st);
+  hipLaunchKernelGGL((k_small3<T>), dim3(b.n_act), dim3(SM_THREADS), 0, st, b.W, b.act,
+                     (T*)b.Tm, b.state, eps4, tau);
 }
 
 template <typename T>
@@ -1464,7 +1689,8 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
   const dim3 g(b.n_units), blk(WG), gs(b.n_act), bs(SM_THREADS);
   const Work wk = b.work;
   if (ev) hipEventRecord(ev[0], st);
-  const bool strips = !indep && b.n_strips > 0;
+  const bool strips = !indep && b.n_strips > 0 && sizeof(T) == 4;
+  const bool cheb = !indep && b.cheb_k > 1;
   if (indep)
     hipLaunchKernelGGL((k_stencil_gram<T, true>), g, blk, 0, st, c, wk, Y, (const T*)b.Tm, R, P,
                        Q, b.part);
@@ -1489,6 +1715,14 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
     else
       hipLaunchKernelGGL((k_update_r<T, true, false>), g, blk, 0, st, c, wk, al, Q, P, R, D,
                          b.part);
+  } else if (cheb) {
+    const T it = (T)b.cheb_invtheta;
+    if (with_d)
+      hipLaunchKernelGGL((k_update_r<T, false, true, true>), g, blk, 0, st, c, wk, al, Q, P, R, D,
+                         b.part, (T*)b.Za, it);
+    else
+      hipLaunchKernelGGL((k_update_r<T, false, false, true>), g, blk, 0, st, c, wk, al, Q, P, R,
+                         D, b.part, (T*)b.Za, it);
   } else {
     if (with_d)
       hipLaunchKernelGGL((k_update_r<T, false, true>), g, blk, 0, st, c, wk, al, Q, P, R, D,
@@ -1498,6 +1732,14 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
                          b.part);
   }
   if (ev) hipEventRecord(ev[3], st);
+  // Z = M^-1 R and W3 = Q^T Z (polynomial preconditioner)
+  if (ev) hipEventRecord(ev[6], st);
+  const T* Z = R;
+  if (cheb) {
+    Z = cheb_steps<T>(c, b, st, nullptr);
+    hipLaunchKernelGGL((k_gram_ab<T, false>), g, blk, 0, st, c, wk, (const T*)Q, Z, b.part, 2);
+  }
+  if (ev) hipEventRecord(ev[7], st);
   reduce(b, 2, 1, len, st);
   hipLaunchKernelGGL((k_small2<T>), gs, bs, 0, st, b.W, b.act, b.winv, (T*)b.delta, b.state, di);
   if (ev) hipEventRecord(ev[4], st);
@@ -1506,7 +1748,10 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
     hipLaunchKernelGGL((k_update_y<T, true>), g, blk, 0, st, c, wk, de, R, P, Y, b.part);
     if (ev) hipEventRecord(ev[5], st);
   } else {
-    hipLaunchKernelGGL((k_update_y<T, false>), g, blk, 0, st, c, wk, de, R, P, Y, b.part);
+    if (cheb)
+      hipLaunchKernelGGL((k_update_y<T, false, true>), g, blk, 0, st, c, wk, de, Z, P, Y, b.part);
+    else
+      hipLaunchKernelGGL((k_update_y<T, false>), g, blk, 0, st, c, wk, de, R, P, Y, b.part);
     if (ev) hipEventRecord(ev[5], st);
     reduce(b, 3, 1, len, st);
     hipLaunchKernelGGL((k_small3<T>), gs, bs, 0, st, b.W, b.act, (T*)b.Tm, b.state, eps4, tau);
@@ -1528,6 +1773,7 @@ static hipError_t init_t(const Coef<T>& c, const SolveBuffers& b, bool indep, hi
   if (b.D) hipLaunchKernelGGL((k_zero_units<T>), g, blk, 0, st, b.work, (T*)b.D);
   hipLaunchKernelGGL((k_set_targets<T>), dim3(b.n_act), dim3(S), 0, st, c, b.work.plans, b.act,
                      b.tgt, (T*)b.R, (T*)b.Y, (T*)b.Tm, b.state, indep ? 1 : 0);
+  if (!indep && b.cheb_k > 1) precond_start<T>(c, b, st);
   return hipGetLastError();
 }
 
@@ -1561,9 +1807,11 @@ hipError_t launch_restart(const Coef<float>& cf, const SolveBuffers& b, bool ind
   if (indep) {
     // T = I: the independent variant needs no orthonormalisation.
     hipLaunchKernelGGL(k_set_identity, dim3(b.n_act), dim3(256), 0, st, b.act, (float*)b.Tm);
+  } else if (b.cheb_k > 1) {
+    precond_start<float>(cf, b, st);  // Y = M^-1 r
   } else {
-    hipLaunchKernelGGL((k_gram_dy<float>), dim3(b.n_units), dim3(WG), 0, st, cf, b.work,
-                       (const float*)b.Y, b.part);
+    hipLaunchKernelGGL((k_gram_ab<float, true>), dim3(b.n_units), dim3(WG), 0, st, cf, b.work,
+                       (const float*)b.Y, (const float*)b.Y, b.part, 3);
     reduce(b, 3, 1, S * S, st);
     hipLaunchKernelGGL((k_small3<float>), dim3(b.n_act), dim3(SM_THREADS), 0, st, b.W, b.act,
                        (float*)b.Tm, b.state, 1e-6, 1e-12);

@@ -68,7 +68,7 @@ class reff_solve_opts(C.Structure):
         ("precision", C.c_int), ("rel_tol", C.c_double), ("max_iters", C.c_int32),
         ("block_rhs", C.c_int32), ("stream", C.c_void_p), ("out_on_device", C.c_int32),
         ("krylov", C.c_int), ("max_ir_steps", C.c_int32), ("timing", C.c_int32),
-        ("graphs", C.c_int32), ("progress", C.c_int32),
+        ("graphs", C.c_int32), ("progress", C.c_int32), ("precond_degree", C.c_int32),
     ]
 
 
@@ -76,8 +76,8 @@ class reff_solve_stats(C.Structure):
     _fields_ = [
         ("n_solved", C.c_int64), ("n_unconverged", C.c_int64), ("iters_max", C.c_int32),
         ("ir_steps", C.c_int32), ("seconds", C.c_double), ("est_max_rel_err", C.c_double),
-        ("iters_total", C.c_int64), ("kernel_ms", C.c_double * 3),
-        ("kernel_launches", C.c_int64 * 3), ("kernel_rows", C.c_int64 * 3),
+        ("iters_total", C.c_int64), ("kernel_ms", C.c_double * 4),
+        ("kernel_launches", C.c_int64 * 4), ("kernel_rows", C.c_int64 * 4),
         ("screened", C.c_int32), ("spot_max_rel_err", C.c_double),
     ]
 
@@ -202,9 +202,10 @@ def _is_torch_cuda(x):
 
 
 def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing=False,
-          graphs=False, progress=False):
+          graphs=False, progress=False, precond_degree=0):
     o = reff_solve_opts()
     o.progress = 1 if progress else 0
+    o.precond_degree = int(precond_degree)
     o.timing = 1 if timing else 0
     o.graphs = 1 if graphs else 0
     o.precision = int(precision)
@@ -224,7 +225,7 @@ def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, 
 def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP64,
                     rel_tol=0.0, max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None,
                     max_ir_steps=0, allow_unconverged=False, timing=False, graphs=False,
-                    progress=False):
+                    progress=False, precond_degree=0):
     """R_i = (G^-1)_ii for `nodes` (None = all).  Returns (R_out, stats)."""
     if nodes is None:
         count = pdn.num_nodes
@@ -245,7 +246,7 @@ def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP6
         assert R_out.dtype == np.float64 and R_out.flags.c_contiguous and len(R_out) >= count
         optr = R_out.ctypes.data
     o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing, graphs,
-              progress)
+              progress, precond_degree)
     st = reff_solve_stats()
     allow = (REFF_ERR_NO_CONVERGENCE,) if allow_unconverged else ()
     _check(_lib.reff_solve_diag(pdn.handle, nptr, count if nodes is not None else 0, optr,
@@ -255,7 +256,7 @@ def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP6
 
 def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
                      precision=REFF_PREC_FP64, rel_tol=0.0, max_iters=0,
-                     krylov=REFF_KRYLOV_BLOCK, stream=None, max_ir_steps=0):
+                     krylov=REFF_KRYLOV_BLOCK, stream=None, max_ir_steps=0, precond_degree=0):
     """m x n pair resistances R(a_i, b_j).  Returns (R_out, stats)."""
     a = np.ascontiguousarray(a, dtype=np.int64)
     b = np.ascontiguousarray(b, dtype=np.int64)
@@ -264,7 +265,8 @@ def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
         R_out = np.empty((m, n), dtype=np.float64)
     out_dev = _is_torch_cuda(R_out)
     optr = R_out.data_ptr() if out_dev else R_out.ctypes.data
-    o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps)
+    o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps,
+              precond_degree=precond_degree)
     st = reff_solve_stats()
     _check(_lib.reff_query_pairs(pdn.handle, a.ctypes.data, m, b.ctypes.data, n, int(mode),
                                  optr, C.byref(o), C.byref(st)))
@@ -274,7 +276,7 @@ def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
 def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.0,
                      max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None, R_out=None,
                      timing=False, surrogate=None, spot_frac=0.0, fallback_rel_err=0.0,
-                     graphs=False, tune_db=None):
+                     graphs=False, tune_db=None, precond_degree=0):
     """Solve many plans in one call.  Returns (list of R arrays, list of stats)."""
     k = len(plans)
     structs = (reff_pdn_desc * k)()
@@ -309,7 +311,8 @@ def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.
             optrs[i] = o.ctypes.data
             outs.append(o)
     bo = reff_batch_opts()
-    bo.solve = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, 0, timing, graphs)
+    bo.solve = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, 0, timing, graphs,
+                     precond_degree=precond_degree)
     if tune_db is not None:
         bo.tune_db = os.fsencode(tune_db)
     if surrogate is not None:

@@ -1,0 +1,45 @@
+"""The Chebyshev polynomial preconditioner is SPD and fixed, so every degree
+gives PCG's answer: results stay within the parity bars of the oracle while
+the block iterations fall with the degree (about proportionally)."""
+import numpy as np
+import pytest
+
+from oracle import reff_oracle as ro
+from paper_2607_05818_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _reff():
+    from paper_2607_05818_amd import reff
+    return reff
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.mark.parametrize("prec,tol,rel", [(0, 1e-6, 1e-9), (1, 1e-3, 1e-5)], ids=["fp64", "mixed"])
+def test_degrees_agree_with_oracle(prec, tol, rel):
+    reff = _reff()
+    d = gen.config2(side=128, n_tsv=64, sigma=10.0)
+    nodes = gen.sample_free_nodes(d, 128, 77)
+    want = ro.diag(d, nodes)
+    h = reff.reff_build_pdn(d)
+    iters = {}
+    for k in (1, 2, 4, 8):
+        _say("precond degree", k, "prec", prec)
+        got, st = reff.reff_solve_diag(h, nodes, precision=prec, rel_tol=rel, precond_degree=k)
+        err = float(np.max(np.abs(got - want) / want))
+        iters[k] = st["iters_total"]
+        print("degree", k, "iters", iters[k], "err", err, flush=True)
+        assert err <= tol
+    assert iters[4] < 0.5 * iters[1] and iters[8] < iters[4]
+
+
+def test_degree_out_of_range_rejected():
+    reff = _reff()
+    h = reff.reff_build_pdn(gen.config1())
+    with pytest.raises(reff.ReffError) as ei:
+        reff.reff_solve_diag(h, [5], precond_degree=17)
+    assert ei.value.status == reff.REFF_ERR_INVALID_ARG
