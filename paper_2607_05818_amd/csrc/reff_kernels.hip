@@ -895,13 +895,15 @@ __global__ __launch_bounds__(WG, 4) void k_gram_ab(Coef<T> c, Work wk, const T* 
 // One step of the Chebyshev polynomial preconditioner Z = q(D^-1 G) D^-1 R
 // (block variant, over strips like the stencil kernel):
 //   zout = u + a1 (u - uprev) + a2 D^-1 (R - G u),   u = z_j, uprev = z_{j-1}
-// (uprev = 0 without HAS_PREV).  zout may be the uprev array: every row of it
-// is read, then written, by the same thread.
+// (uprev = 0 without HAS_PREV).  zout may be the uprev array: each row of it
+// is read in the iteration before the one that writes it, and those reads
+// complete before the barrier that precedes the writes.
 template <typename T, bool HAS_PREV>
 __global__ __launch_bounds__(WG, 4) void k_cheb_strip(Coef<T> c, Work wk, const T* __restrict__ zin,
                                                       const T* zprev, const T* __restrict__ R,
                                                       T* zout, T a1, T a2) {
   constexpr int HWW = CH + 2;
+  constexpr int NPW = NODES_PER_WAVE;
   __shared__ __align__(16) T win[3][HWW][LDW];
   __shared__ T cd[2][CH], ce[2][CH + 1], cn[2][CH], cdi[2][CH];
   __shared__ int cslot[2][CH];
@@ -915,127 +917,150 @@ __global__ __launch_bounds__(WG, 4) void k_cheb_strip(Coef<T> c, Work wk, const 
   const int wdt = st.wdt;
   const bool has_w = st.x0 > 0;
   const bool has_e = st.x0 + wdt < pd.nx;
-  auto load_row = [&](int yy, T (&v)[NODES_PER_WAVE], T& halo) {
+  // Wave 0 reads the west halo column, wave 1 the east one (a strip
+  // narrower than CH ends at the east edge of the plane).
+  const int hoff = w == 0 ? (has_w ? -1 : 0) : (has_e ? wdt : 0);
+  // Every global load of the loop reads a valid address (rows and columns
+  // are clamped); values outside the plane or the strip are replaced by
+  // zero only when they are written to LDS.  The next row's loads are then
+  // never waited for before that point, and the loop body has no
+  // data-dependent branch around a load or a store, so the compiler can
+  // count outstanding loads exactly.
+  auto load_row = [&](int yy, T (&v)[NPW], T& halo) {
     const bool in = yy >= 0 && yy < ny;
-    const int64_t base = pd.vbase + st.lrow0 + (int64_t)(yy - st.y0) * nx;
-    const int64_t safe = in ? base : pd.vbase + st.lrow0;
+    const int64_t base = pd.vbase + st.lrow0 + (int64_t)((in ? yy : st.y0) - st.y0) * nx;
 #pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      const int j = min(w * NODES_PER_WAVE + i, wdt - 1);
-      v[i] = zin[(safe + j) * S + lane];
-      if (!in) v[i] = T(0);
-    }
-    halo = T(0);
-    if (w == 0) {
-      const T h = zin[(safe - (has_w ? 1 : 0)) * S + lane];
-      halo = (in && has_w) ? h : T(0);
-    } else if (w == 1) {
-      const T h = zin[(safe + (has_e ? wdt : 0)) * S + lane];
-      halo = (in && has_e) ? h : T(0);
-    }
+    for (int i = 0; i < NPW; ++i) v[i] = zin[(base + min(w * NPW + i, wdt - 1)) * S + lane];
+    if (w < 2) halo = zin[(base + hoff) * S + lane];
   };
-  auto store_row = [&](int slot, const T (&v)[NODES_PER_WAVE], T halo) {
+  auto store_row = [&](int slot, const T (&v)[NPW], T halo, int yy) {
+    const bool in = yy >= 0 && yy < ny;
 #pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      const int j = w * NODES_PER_WAVE + i;
-      win[slot][j + 1][lane] = j < wdt ? v[i] : T(0);
+    for (int i = 0; i < NPW; ++i) {
+      const int j = w * NPW + i;
+      win[slot][j + 1][lane] = (in && j < wdt) ? v[i] : T(0);
     }
-    if (w == 0) win[slot][0][lane] = halo;
-    if (w == 1 && wdt == CH) win[slot][CH + 1][lane] = halo;
+    if (w == 0) win[slot][0][lane] = (in && has_w) ? halo : T(0);
+    if (w == 1 && wdt == CH) win[slot][CH + 1][lane] = (in && has_e) ? halo : T(0);
   };
   // pointwise rows of strip row s: R and (HAS_PREV) uprev
-  auto load_pt = [&](int s, T (&rv)[NODES_PER_WAVE], T (&pv)[NODES_PER_WAVE]) {
+  auto load_pt = [&](int s, T (&rv)[NPW], T (&pv)[NPW]) {
     const int64_t base = pd.vbase + st.lrow0 + (int64_t)min(s, st.nrows - 1) * nx;
 #pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      const int j = min(w * NODES_PER_WAVE + i, wdt - 1);
-      rv[i] = R[(base + j) * S + lane];
-      pv[i] = HAS_PREV ? zprev[(base + j) * S + lane] : T(0);
+    for (int i = 0; i < NPW; ++i) {
+      const int64_t v = base + min(w * NPW + i, wdt - 1);
+      rv[i] = R[v * S + lane];
+      pv[i] = HAS_PREV ? zprev[v * S + lane] : T(0);
     }
   };
-  // Coefficients of strip row s, one value per thread t < 5 CH + 1 (d, cE
-  // from node x0 - 1, cN, Dinv, slot as in the stencil kernel).
+  // Coefficients of strip row s, one value per thread t <= 5 CH of waves
+  // 0 - 2: d (t < CH), cE from node x0 - 1 on (CH <= t <= 2 CH), cN, Dinv;
+  // every such thread also reads one slot entry (used by 3 CH < t <= 4 CH).
   const int t = threadIdx.x;
+  const int kc = t < CH ? t : t <= 2 * CH ? t - CH - 1 : t <= 3 * CH ? t - 2 * CH - 1 : t - 4 * CH - 1;
+  const int klo = (t == CH && has_w) ? -1 : 0;
+  const T* csrc = t < CH ? c.d : t <= 2 * CH ? c.cE : t <= 3 * CH ? c.cN : c.dinv;
+  const int ks = t - 3 * CH - 1;
   auto load_coef = [&](int srow, T& val, int& sl) {
-    const int64_t base = pd.cbase + st.lrow0 + (int64_t)min(srow, st.nrows - 1) * nx;
-    val = T(0);
-    sl = -1;
-    if (t < CH) {
-      val = c.d[base + min(t, wdt - 1)];
-    } else if (t <= 2 * CH) {
-      const int e = t - CH;
-      const bool ok = (e > 0 || has_w) && e <= wdt;
-      const T v = c.cE[base + min(max(e - 1, has_w ? -1 : 0), wdt - 1)];
-      val = ok ? v : T(0);
-    } else if (t <= 3 * CH) {
-      val = c.cN[base + min(t - 2 * CH - 1, wdt - 1)];
-    } else if (t <= 4 * CH) {
-      sl = c.slot[base + min(t - 3 * CH - 1, wdt - 1)];
-    } else if (t <= 5 * CH) {
-      val = c.dinv[base + min(t - 4 * CH - 1, wdt - 1)];
+    if (w < 3) {
+      const int64_t base = pd.cbase + st.lrow0 + (int64_t)min(srow, st.nrows - 1) * nx;
+      val = csrc[base + min(max(kc, klo), wdt - 1)];
+      sl = c.slot[base + min(max(ks, 0), wdt - 1)];
     }
   };
   auto store_coef = [&](int b, T val, int sl) {
-    if (t < CH) cd[b][t] = val;
-    else if (t <= 2 * CH) ce[b][t - CH] = val;
-    else if (t <= 3 * CH) cn[b][t - 2 * CH - 1] = val;
-    else if (t <= 4 * CH) cslot[b][t - 3 * CH - 1] = sl;
-    else if (t <= 5 * CH) cdi[b][t - 4 * CH - 1] = val;
+    if (t < CH) {
+      cd[b][t] = val;
+    } else if (t <= 2 * CH) {
+      const int e = t - CH;
+      ce[b][e] = ((e > 0 || has_w) && e <= wdt) ? val : T(0);
+    } else if (t <= 3 * CH) {
+      cn[b][t - 2 * CH - 1] = val;
+    } else if (t <= 4 * CH) {
+      cslot[b][t - 3 * CH - 1] = sl;
+    } else if (t <= 5 * CH) {
+      cdi[b][t - 4 * CH - 1] = val;
+    }
   };
   {
-    T v[NODES_PER_WAVE], h;
+    T v[NPW], h = T(0), cv = T(0);
+    int csl = -1;
     load_row(st.y0 - 1, v, h);
-    store_row(0, v, h);
+    store_row(0, v, h, st.y0 - 1);
     load_row(st.y0, v, h);
-    store_row(1, v, h);
+    store_row(1, v, h, st.y0);
+    load_row(st.y0 + 1, v, h);
+    store_row(2, v, h, st.y0 + 1);
+    load_coef(0, cv, csl);
+    store_coef(0, cv, csl);
     if (t > 2 * CH && t <= 3 * CH) {
       const int j = t - 2 * CH - 1;
       const int64_t ci = pd.cbase + st.lrow0 + min(j, wdt - 1) - nx;  // row y0 - 1
       cn[1][j] = st.y0 > 0 ? c.cN[st.y0 > 0 ? ci : ci + nx] : T(0);
     }
   }
-  T ny_v[NODES_PER_WAVE], ny_h, r_v[NODES_PER_WAVE], p_v[NODES_PER_WAVE], c_v;
-  int c_sl;
-  load_row(st.y0 + 1, ny_v, ny_h);
-  load_pt(0, r_v, p_v);
-  load_coef(0, c_v, c_sl);
+  T rc[NPW], pc[NPW];
+  load_pt(0, rc, pc);
+  __syncthreads();
+  // Iteration s: LDS holds window rows y - 1, y, y + 1 in slots s, s + 1,
+  // s + 2 (mod 3) and the coefficients of row s in buffer s & 1 (cN of row
+  // y - 1 in the other).  The loads of the next row are issued before the
+  // row's arithmetic and written to LDS after it, in the same iteration, so
+  // that their wait does not include this row's stores.
   for (int s = 0; s < st.nrows; ++s) {
     const int y = st.y0 + s;
-    const int sc = (s + 1) % 3, sn = (s + 2) % 3, ss = s % 3;  // rows y, y+1, y-1
+    const int ss = s % 3, sc = (s + 1) % 3, sn = (s + 2) % 3;  // rows y-1, y, y+1
     const int b = s & 1;
-    store_row(sn, ny_v, ny_h);
-    store_coef(b, c_v, c_sl);
-    T rc[NODES_PER_WAVE], pc[NODES_PER_WAVE];
-#pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      rc[i] = r_v[i];
-      pc[i] = p_v[i];
-    }
-    if (s + 1 < st.nrows) {
-      load_row(y + 2, ny_v, ny_h);
-      load_pt(s + 1, r_v, p_v);
-      load_coef(s + 1, c_v, c_sl);
-    }
-    __syncthreads();
     const int64_t obase = pd.vbase + st.lrow0 + (int64_t)s * nx;
+    // TSV partners (tiers above / below) of this row's nodes
+    int sl[NPW];
+    bool any = false;
 #pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      const int j = w * NODES_PER_WAVE + i;
-      const int jc = min(j, wdt - 1);
+    for (int i = 0; i < NPW; ++i) {
+      sl[i] = __builtin_amdgcn_readfirstlane(cslot[b][min(w * NPW + i, wdt - 1)]);
+      any |= sl[i] >= 0;
+    }
+    T gu[NPW], gd[NPW], yu[NPW], yd[NPW];
+    if (any) {  // wave-uniform
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        const int64_t v = obase + min(w * NPW + i, wdt - 1);
+        // slot 0 exists: some node of this wave has a TSV
+        const int q = max(sl[i], 0);
+        gu[i] = sl[i] >= 0 ? ldc(c.up, q) : T(0);
+        gd[i] = sl[i] >= 0 ? ldc(c.dn, q) : T(0);
+        yu[i] = zin[(gu[i] != T(0) ? v + pd.plane : v) * S + lane];
+        yd[i] = zin[(gd[i] != T(0) ? v - pd.plane : v) * S + lane];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) gu[i] = gd[i] = yu[i] = yd[i] = T(0);
+    }
+    // next row (the last iteration reads valid rows again and discards them)
+    T ny_v[NPW], ny_h = T(0), r_v[NPW], p_v[NPW], c_v = T(0);
+    int c_sl = -1;
+    load_row(y + 2, ny_v, ny_h);
+    load_pt(s + 1, r_v, p_v);
+    load_coef(s + 1, c_v, c_sl);
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      // nodes past the strip's width repeat the last node: same inputs, same
+      // value, same address
+      const int jc = min(w * NPW + i, wdt - 1);
       const T uc = win[sc][jc + 1][lane];
       T g = cd[b][jc] * uc - ce[b][jc + 1] * win[sc][jc + 2][lane] - ce[b][jc] * win[sc][jc][lane] -
             cn[b][jc] * win[sn][jc + 1][lane] - cn[b ^ 1][jc] * win[ss][jc + 1][lane];
-      const int sl = __builtin_amdgcn_readfirstlane(cslot[b][jc]);
-      if (sl >= 0) {  // wave-uniform: TSV segments to the tiers above / below
-        const T gu = ldc(c.up, sl);
-        const T gd = ldc(c.dn, sl);
-        const int64_t v = obase + jc;
-        const T yu = zin[(gu != T(0) ? v + pd.plane : v) * S + lane];
-        const T yd = zin[(gd != T(0) ? v - pd.plane : v) * S + lane];
-        g -= gu * yu + gd * yd;
-      }
+      g -= gu[i] * yu[i] + gd[i] * yd[i];
       const T zn = uc + a1 * (uc - pc[i]) + a2 * cdi[b][jc] * (rc[i] - g);
-      if (j < wdt) zout[(obase + j) * S + lane] = zn;
+      zout[(obase + jc) * S + lane] = zn;
+    }
+    __syncthreads();
+    store_row(ss, ny_v, ny_h, y + 2);  // row y + 2 replaces row y - 1
+    store_coef(b ^ 1, c_v, c_sl);
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      rc[i] = r_v[i];
+      pc[i] = p_v[i];
     }
     __syncthreads();
   }
