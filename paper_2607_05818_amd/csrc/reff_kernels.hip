@@ -429,8 +429,12 @@ __device__ __forceinline__ T ldc(const T* p, int64_t i) {
 // stencil read from an on-chip window.  The workgroup marches its strip in
 // +y; the ring win[3] holds the Y rows y-1, y, y+1 of the strip plus one
 // halo node on each side (column 0 = x0-1, column j+1 = node x0+j), so
-// every Y row comes from HBM once.  The loads of row y+2 and of R row y+1
-// are issued before row y's matrix-core work and land in registers.
+// every Y row comes from HBM once.  The loads of row y+2, of R row y+1 and
+// of the coefficients of row y+1 are issued before row y's work and written
+// to LDS after its products, in the same iteration: every load reads a
+// clamped, valid address, values outside the tier or the strip become zero
+// only when written to LDS, and no load or store sits under a data-dependent
+// branch, so no instruction waits for the next row before that point.
 template <typename T>
 __global__ __launch_bounds__(WG, 4) void k_stencil_gram_strip(Coef<T> c, Work wk,
                                                               const T* __restrict__ Y,
@@ -440,9 +444,10 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram_strip(Coef<T> c, Work wk
                                                               T* __restrict__ Q,
                                                               double* __restrict__ part) {
   constexpr int HWW = CH + 2;
+  constexpr int NPW = NODES_PER_WAVE;
   __shared__ __align__(16) T win[3][HWW][LDW];
-  __shared__ __align__(16) T sR[CH][LDW];
-  __shared__ __align__(16) T sQ[CH][LDW];  // G Y rows, then Q rows
+  __shared__ __align__(16) T sR[2][CH][LDW];  // R rows of row y in buffer s % 2
+  __shared__ __align__(16) T sQ[CH][LDW];     // G Y rows, then Q rows
   __shared__ __align__(16) T sP[CH][LDW];
   // Stencil coefficients of row y (buffer s % 2): d, cE from node x0-1 on,
   // cN (buffer s % 2 = row y, the other = row y-1), TSV slot.
@@ -466,128 +471,133 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram_strip(Coef<T> c, Work wk
   zero_acc(a1);
   zero_acc(a2);
   // Window row yy of the strip: this thread's nodes are j = 4w + i, plus the
-  // west halo (wave 0) and east halo (wave 1).  Rows outside the tier are 0.
-  auto load_row = [&](int yy, T (&v)[NODES_PER_WAVE], T& halo) {
+  // west halo (wave 0) and east halo (wave 1; a strip narrower than CH ends
+  // at the east edge of the tier).  Rows outside the tier are 0.
+  const int hoff = w == 0 ? (has_w ? -1 : 0) : (has_e ? wdt : 0);
+  auto load_row = [&](int yy, T (&v)[NPW], T& halo) {
     const bool in = yy >= 0 && yy < ny;
-    const int64_t base = pd.vbase + st.lrow0 + (int64_t)(yy - st.y0) * nx;
-    const int64_t safe = in ? base : pd.vbase + st.lrow0;
+    const int64_t base = pd.vbase + st.lrow0 + (int64_t)((in ? yy : st.y0) - st.y0) * nx;
 #pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      const int j = min(w * NODES_PER_WAVE + i, wdt - 1);
-      v[i] = Y[(safe + j) * S + lane];
-      if (!in) v[i] = T(0);
-    }
-    halo = T(0);
-    if (w == 0) {
-      const T h = Y[(safe - (has_w ? 1 : 0)) * S + lane];
-      halo = (in && has_w) ? h : T(0);
-    } else if (w == 1) {
-      const T h = Y[(safe + (has_e ? wdt : 0)) * S + lane];
-      halo = (in && has_e) ? h : T(0);
-    }
+    for (int i = 0; i < NPW; ++i) v[i] = Y[(base + min(w * NPW + i, wdt - 1)) * S + lane];
+    if (w < 2) halo = Y[(base + hoff) * S + lane];
   };
-  auto store_row = [&](int slot, const T (&v)[NODES_PER_WAVE], T halo) {
+  auto store_row = [&](int slot, const T (&v)[NPW], T halo, int yy) {
+    const bool in = yy >= 0 && yy < ny;
 #pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      const int j = w * NODES_PER_WAVE + i;
-      win[slot][j + 1][lane] = j < wdt ? v[i] : T(0);
+    for (int i = 0; i < NPW; ++i) {
+      const int j = w * NPW + i;
+      win[slot][j + 1][lane] = (in && j < wdt) ? v[i] : T(0);
     }
-    if (w == 0) win[slot][0][lane] = halo;
-    if (w == 1 && wdt == CH) win[slot][CH + 1][lane] = halo;
+    if (w == 0) win[slot][0][lane] = (in && has_w) ? halo : T(0);
+    if (w == 1 && wdt == CH) win[slot][CH + 1][lane] = (in && has_e) ? halo : T(0);
   };
-  auto load_r = [&](int s, T (&v)[NODES_PER_WAVE]) {
+  auto load_r = [&](int s, T (&v)[NPW]) {
     const int64_t base = pd.vbase + st.lrow0 + (int64_t)min(s, st.nrows - 1) * nx;
 #pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      const int j = min(w * NODES_PER_WAVE + i, wdt - 1);
-      v[i] = R[(base + j) * S + lane];
+    for (int i = 0; i < NPW; ++i) v[i] = R[(base + min(w * NPW + i, wdt - 1)) * S + lane];
+  };
+  auto store_r = [&](int b, const T (&v)[NPW]) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      const int j = w * NPW + i;
+      sR[b][j][lane] = j < wdt ? v[i] : T(0);
     }
   };
-  // Coefficients of strip row s (one value per thread t < 4 CH + 1):
-  //   t < CH: d;  CH <= t <= 2 CH: cE of node x0 - 1 + (t - CH);
-  //   2 CH < t <= 3 CH: cN;  3 CH < t <= 4 CH: slot (as bits).
+  // Coefficients of strip row s, one value per thread t <= 3 CH of waves
+  // 0 - 1 (t < CH: d;  CH <= t <= 2 CH: cE of node x0 - 1 + (t - CH);
+  // 2 CH < t <= 3 CH: cN), and one slot entry per thread t of waves 0 - 2
+  // (used by 3 CH < t <= 4 CH).
   const int t = threadIdx.x;
+  const int kc = t < CH ? t : t <= 2 * CH ? t - CH - 1 : t - 2 * CH - 1;
+  const int klo = (t == CH && has_w) ? -1 : 0;
+  const T* csrc = t < CH ? c.d : t <= 2 * CH ? c.cE : c.cN;
+  const int ks = t - 3 * CH - 1;
   auto load_coef = [&](int srow, T& val, int& sl) {
-    const int64_t base = pd.cbase + st.lrow0 + (int64_t)min(srow, st.nrows - 1) * nx;
-    val = T(0);
-    sl = -1;
-    if (t < CH) {
-      val = c.d[base + min(t, wdt - 1)];
-    } else if (t <= 2 * CH) {
-      const int e = t - CH;  // node x0 - 1 + e
-      const bool ok = (e > 0 || has_w) && e <= wdt;
-      const T v = c.cE[base + min(max(e - 1, has_w ? -1 : 0), wdt - 1)];
-      val = ok ? v : T(0);
-    } else if (t <= 3 * CH) {
-      val = c.cN[base + min(t - 2 * CH - 1, wdt - 1)];
-    } else if (t <= 4 * CH) {
-      sl = c.slot[base + min(t - 3 * CH - 1, wdt - 1)];
+    if (w < 3) {
+      const int64_t base = pd.cbase + st.lrow0 + (int64_t)min(srow, st.nrows - 1) * nx;
+      val = csrc[base + min(max(kc, klo), wdt - 1)];
+      sl = c.slot[base + min(max(ks, 0), wdt - 1)];
     }
   };
   auto store_coef = [&](int b, T val, int sl) {
     if (t < CH) {
       cd[b][t] = val;
     } else if (t <= 2 * CH) {
-      ce[b][t - CH] = val;
+      const int e = t - CH;  // node x0 - 1 + e
+      ce[b][e] = ((e > 0 || has_w) && e <= wdt) ? val : T(0);
     } else if (t <= 3 * CH) {
       cn[b][t - 2 * CH - 1] = val;
     } else if (t <= 4 * CH) {
       cslot[b][t - 3 * CH - 1] = sl;
     }
   };
-  // Prologue: rows y0-1 and y0 into slots 0 and 1; cN of row y0-1 into
-  // buffer 1; row y0+1, R row y0 and the coefficients of row y0 in flight.
+  // Prologue: rows y0-1, y0, y0+1 into slots 0, 1, 2; R row y0 and the
+  // coefficients of row y0 into buffer 0; cN of row y0-1 into buffer 1.
   {
-    T v[NODES_PER_WAVE], h;
+    T v[NPW], h = T(0), cv = T(0);
+    int csl = -1;
     load_row(st.y0 - 1, v, h);
-    store_row(0, v, h);
+    store_row(0, v, h, st.y0 - 1);
     load_row(st.y0, v, h);
-    store_row(1, v, h);
+    store_row(1, v, h, st.y0);
+    load_row(st.y0 + 1, v, h);
+    store_row(2, v, h, st.y0 + 1);
+    load_r(0, v);
+    store_r(0, v);
+    load_coef(0, cv, csl);
+    store_coef(0, cv, csl);
     if (t > 2 * CH && t <= 3 * CH) {
       const int j = t - 2 * CH - 1;
       const int64_t ci = pd.cbase + st.lrow0 + min(j, wdt - 1) - nx;  // row y0 - 1
       cn[1][j] = st.y0 > 0 ? c.cN[st.y0 > 0 ? ci : ci + nx] : T(0);
     }
   }
-  T ny_v[NODES_PER_WAVE], ny_h, r_v[NODES_PER_WAVE], c_v;
-  int c_sl;
-  load_row(st.y0 + 1, ny_v, ny_h);
-  load_r(0, r_v);
-  load_coef(0, c_v, c_sl);
+  __syncthreads();
   for (int s = 0; s < st.nrows; ++s) {
     const int y = st.y0 + s;
-    const int sc = (s + 1) % 3, sn = (s + 2) % 3, ss = s % 3;  // rows y, y+1, y-1
+    const int ss = s % 3, sc = (s + 1) % 3, sn = (s + 2) % 3;  // rows y-1, y, y+1
     const int b = s & 1;
-    store_row(sn, ny_v, ny_h);
+    const int64_t obase = pd.vbase + st.lrow0 + (int64_t)s * nx;
+    // TSV partners (tiers above / below) of this row's nodes, read before
+    // the next row so that waiting for them does not wait for that row.
+    int sl[NPW];
+    bool any = false;
 #pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      const int j = w * NODES_PER_WAVE + i;
-      sR[j][lane] = j < wdt ? r_v[i] : T(0);
+    for (int i = 0; i < NPW; ++i) {
+      sl[i] = __builtin_amdgcn_readfirstlane(cslot[b][min(w * NPW + i, wdt - 1)]);
+      any |= sl[i] >= 0;
     }
-    store_coef(b, c_v, c_sl);
-    if (s + 1 < st.nrows) {
-      load_row(y + 2, ny_v, ny_h);
-      load_r(s + 1, r_v);
-      load_coef(s + 1, c_v, c_sl);
+    T gu[NPW], gd[NPW], yu[NPW], yd[NPW];
+    if (any) {  // wave-uniform
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        const int64_t v = obase + min(w * NPW + i, wdt - 1);
+        // slot 0 exists: some node of this wave has a TSV
+        const int q = max(sl[i], 0);
+        gu[i] = sl[i] >= 0 ? ldc(c.up, q) : T(0);
+        gd[i] = sl[i] >= 0 ? ldc(c.dn, q) : T(0);
+        yu[i] = Y[(gu[i] != T(0) ? v + pd.plane : v) * S + lane];
+        yd[i] = Y[(gd[i] != T(0) ? v - pd.plane : v) * S + lane];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) gu[i] = gd[i] = yu[i] = yd[i] = T(0);
     }
-    __syncthreads();
+    // next row (the last iteration reads valid rows again and discards them)
+    T ny_v[NPW], ny_h = T(0), r_v[NPW], c_v = T(0);
+    int c_sl = -1;
+    load_row(y + 2, ny_v, ny_h);
+    load_r(s + 1, r_v);
+    load_coef(s + 1, c_v, c_sl);
     // (G Y)_v for this wave's nodes of row y.
 #pragma unroll
-    for (int i = 0; i < NODES_PER_WAVE; ++i) {
-      const int j = w * NODES_PER_WAVE + i;
+    for (int i = 0; i < NPW; ++i) {
+      const int j = w * NPW + i;
       const int jc = min(j, wdt - 1);
       T q = cd[b][jc] * win[sc][jc + 1][lane] - ce[b][jc + 1] * win[sc][jc + 2][lane] -
             ce[b][jc] * win[sc][jc][lane] - cn[b][jc] * win[sn][jc + 1][lane] -
             cn[b ^ 1][jc] * win[ss][jc + 1][lane];
-      const int sl = __builtin_amdgcn_readfirstlane(cslot[b][jc]);
-      if (sl >= 0) {  // wave-uniform: TSV segments to the tiers above / below
-        const T gu = ldc(c.up, sl);
-        const T gd = ldc(c.dn, sl);
-        const int64_t v = pd.vbase + st.lrow0 + (int64_t)s * nx + jc;
-        const T yu = Y[(gu != T(0) ? v + pd.plane : v) * S + lane];
-        const T yd = Y[(gd != T(0) ? v - pd.plane : v) * S + lane];
-        q -= gu * yu + gd * yd;
-      }
+      q -= gu[i] * yu[i] + gd[i] * yd[i];
       sQ[j][lane] = j < wdt ? q : T(0);
     }
     __syncthreads();
@@ -601,17 +611,18 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram_strip(Coef<T> c, Work wk
       sQ[row][col] = qt[r];
     }
     __syncthreads();
-    gram_chunk2<T>(sP, sQ, sR, w, lane, a1, a2);
-    {
-      const int64_t base = pd.vbase + st.lrow0 + (int64_t)s * nx;
+    gram_chunk2<T>(sP, sQ, sR[b], w, lane, a1, a2);
+    // Row y + 2 replaces row y - 1 (last read by the stencil above); the
+    // coefficients of row y + 1 replace those of row y - 1.
+    store_row(ss, ny_v, ny_h, y + 2);
+    store_r(b ^ 1, r_v);
+    store_coef(b ^ 1, c_v, c_sl);
+    // nodes past a ragged strip's width store the last node's row again
 #pragma unroll
-      for (int i = 0; i < NODES_PER_WAVE; ++i) {
-        const int j = w * NODES_PER_WAVE + i;
-        if (j < wdt) {
-          P[(base + j) * S + lane] = sP[j][lane];
-          Q[(base + j) * S + lane] = sQ[j][lane];
-        }
-      }
+    for (int i = 0; i < NPW; ++i) {
+      const int jc = min(w * NPW + i, wdt - 1);
+      P[(obase + jc) * S + lane] = sP[jc][lane];
+      Q[(obase + jc) * S + lane] = sQ[jc][lane];
     }
     __syncthreads();
   }
