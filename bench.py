@@ -29,6 +29,20 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # dense matrix-core peaks
 S = 64
 
 
+def cheb_words(cheb):
+    """S-wide vector words per node that the Chebyshev passes of one
+    preconditioner application read and write, and the number of passes:
+    steps run two per pass while two remain (a pass reads z_j, z_{j-1}, R and
+    writes z_{j+1}, z_{j+2}; the first pass has no z_{j-1}), a last odd step
+    reads z_j, z_{j-1}, R and writes z_{j+1}."""
+    steps = cheb - 1
+    pairs, single = steps // 2, steps % 2
+    words = sum(4 if i == 0 else 5 for i in range(pairs))
+    if single:
+        words += 3 if pairs == 0 else 4
+    return words, pairs + single
+
+
 def kernel_bytes(n, fp32=True, mixed_with_d=True, cheb=1):
     """Algorithmic HBM bytes per launch of the block kernels for an n-node
     stack and S right-hand sides (w = bytes per word):
@@ -38,15 +52,18 @@ def kernel_bytes(n, fp32=True, mixed_with_d=True, cheb=1):
                          + Dinv; with the polynomial preconditioner it also
                          writes z_1 = D^-1 R / theta            -> + S w
       search block (K3): read P, R (or Z); write Y              -> 3 S w + d, Dinv
-      preconditioner (degree k > 1): step 1 reads z_1, R and writes z_2, each
-                         later step also reads z_{j-1}; then Q^T Z reads Q, Z
-                         -> (3 + 4 (k - 2)) S w + 2 S w + coefficients per step
+      preconditioner (degree k > 1): the Chebyshev passes (cheb_words), each
+                         also reading d, cE, cN, Dinv and the slot, then
+                         Q^T Z reads Q, Z                       -> + 2 S w
     """
     w = 4 if fp32 else 8
     k1 = n * (4 * S * w + 3 * w + 4)
     k2 = n * ((6 if mixed_with_d else 3) * S * w + w + (S * w if cheb > 1 else 0))
     k3 = n * (3 * S * w + 2 * w)
-    kp = n * ((3 + 4 * (cheb - 2)) * S * w + 2 * S * w + (cheb - 1) * (4 * w + 4)) if cheb > 1 else 0
+    kp = 0
+    if cheb > 1:
+        words, passes = cheb_words(cheb)
+        kp = n * ((words + 2) * S * w + passes * (4 * w + 4))
     return [k1, k2, k3, kp]
 
 
@@ -299,7 +316,7 @@ def main():
     ap.add_argument("--rel-tol", type=float, default=1e-4)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--krylov", choices=["block", "indep"], default="block")
-    ap.add_argument("--precond-degree", type=int, default=10,
+    ap.add_argument("--precond-degree", type=int, default=19,
                     help="Chebyshev preconditioner degree (1 = Jacobi)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")

@@ -97,12 +97,12 @@ typedef struct {
                             (same results bitwise); 0: plain launches      */
   int32_t progress;      /* 1: write a progress line (iterations, active
                             blocks) to stderr at most every 10 s of a solve */
-  int32_t precond_degree;/* block Krylov variant: 1 = Jacobi (D^-1); 2..16 =
+  int32_t precond_degree;/* block Krylov variant: 1 = Jacobi (D^-1); 2..32 =
                             Chebyshev polynomial preconditioner
                             q(D^-1 G) D^-1 of that degree (SPD and fixed,
                             so the results are those of PCG with a stronger
                             preconditioner; fewer, costlier iterations);
-                            0 => 10.  The independent variant uses Jacobi. */
+                            0 => 19.  The independent variant uses Jacobi. */
 } reff_solve_opts;
 
 typedef struct {

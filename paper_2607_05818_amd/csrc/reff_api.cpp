@@ -310,7 +310,7 @@ struct Opts {
   bool graphs;  // replay iteration chunks as HIP graphs where possible
   const char* tune_db = nullptr;  // tuning database path (batched solves)
   bool progress = false;          // progress lines on stderr
-  int cheb = 10;                  // Chebyshev preconditioner degree (1 = Jacobi)
+  int cheb = 19;                  // Chebyshev preconditioner degree (1 = Jacobi)
 };
 
 reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
@@ -342,8 +342,8 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
   if (o->progress != 0 && o->progress != 1) return fail(REFF_ERR_INVALID_ARG, "progress must be 0 or 1");
   out.progress = o->progress == 1;
   if (o->precond_degree < 0 || o->precond_degree > MAX_CHEB)
-    return fail(REFF_ERR_INVALID_ARG, "precond_degree must be in [0, 16]");
-  out.cheb = o->precond_degree == 0 ? 10 : o->precond_degree;
+    return fail(REFF_ERR_INVALID_ARG, "precond_degree must be in [0, 32]");
+  out.cheb = o->precond_degree == 0 ? 19 : o->precond_degree;
   out.timing = o->timing == 1;
   return REFF_OK;
 }
@@ -376,7 +376,7 @@ struct BlockResult {
 
 void reff::Workspace::release() {
   for (DevBuf* b : {&Y, &P, &Q, &R, &D, &X, &part, &W, &small, &state, &tgt, &pos, &plans, &units,
-                    &uid, &act, &out, &xs, &rows, &map, &flags, &strips, &sid, &Za, &Zb})
+                    &uid, &act, &out, &xs, &rows, &map, &flags, &strips, &sid, &Za, &Zb, &Zc, &Zd})
     if (b->p) {
       (void)hipFree(b->p);
       b->p = nullptr;
@@ -527,12 +527,17 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
   const bool fp32 = o.mixed;
   const bool with_d = o.mixed || xstore != nullptr;
   const size_t tsz = fp32 ? sizeof(float) : sizeof(double);
-  const size_t row_bytes = S * (tsz * (5 + (with_d ? 1 : 0)) + (o.mixed ? sizeof(double) : 0));
+  const int ncheb = (!o.indep && o.cheb > 1) ? (o.cheb > 2 ? 4 : 2) : 0;  // iterate arrays
+  const size_t row_bytes =
+      S * (tsz * (5 + (with_d ? 1 : 0) + ncheb) + (o.mixed ? sizeof(double) : 0));
   const int64_t budget_rows = std::max<int64_t>(1, (int64_t)(48e9 / (double)row_bytes));
   const Coef<double> c64 = coef64(cs);
   const Coef<float> c32 = coef32(cs);
   const void* coef = fp32 ? (const void*)&c32 : (const void*)&c64;
-  const int poll = 4;  // iterations between convergence checks
+  // Iterations between convergence checks (each costs a host round trip):
+  // every iteration once the polynomial preconditioner makes iterations
+  // costly, every fourth with Jacobi.
+  const int poll = (!o.indep && o.cheb > 1) ? 1 : 4;
 
   struct EventPool {
     std::vector<hipEvent_t> ev;
@@ -634,6 +639,8 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     if (o.mixed && (rs = ensure(ws.X, (size_t)rows * S * sizeof(double))) != REFF_OK) return rs;
     if (cheb && (rs = ensure(ws.Za, vec)) != REFF_OK) return rs;
     if (cheb && (rs = ensure(ws.Zb, vec)) != REFF_OK) return rs;
+    if (cheb && o.cheb > 2 && (rs = ensure(ws.Zc, vec)) != REFF_OK) return rs;
+    if (cheb && o.cheb > 2 && (rs = ensure(ws.Zd, vec)) != REFF_OK) return rs;
     if ((rs = ensure(ws.part, (size_t)std::max(nu, ns) * NGRAM * S * S * sizeof(double))) != REFF_OK)
       return rs;
     if ((rs = ensure(ws.W, (size_t)nb * NGRAM * S * S * sizeof(double))) != REFF_OK) return rs;
@@ -731,6 +738,8 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       }
       b.Za = ws.Za.p;
       b.Zb = ws.Zb.p;
+      b.Zc = ws.Zc.p;
+      b.Zd = ws.Zd.p;
     }
 
     HIPCHK(launch_init_blocks(fp32, o.indep, coef, b, o.stream));

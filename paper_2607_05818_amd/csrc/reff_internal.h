@@ -21,10 +21,10 @@ constexpr int S = 64;        // right-hand sides per block (one per lane)
 constexpr int CH = 32;       // nodes per LDS chunk in the block kernels
 constexpr int WG = 512;      // threads per workgroup of the block kernels
 constexpr int NODES_PER_WAVE = CH / (WG / 64);  // 4
-constexpr int HIST = 16;     // convergence window (iterations)
+constexpr int HIST = 8;      // convergence window (iterations)
 constexpr int MAX_GRID = 512;
 constexpr int NGRAM = 4;     // Gram partials per work unit
-constexpr int MAX_CHEB = 16;  // largest Chebyshev preconditioner degree
+constexpr int MAX_CHEB = 32;  // largest Chebyshev preconditioner degree
 // A column is converged once its estimated remaining relative error is
 // below CONV_SAFETY * rel_tol.
 constexpr double CONV_SAFETY = 0.25;
@@ -118,7 +118,7 @@ struct DevBuf {
 // Device work arrays of the block solver (grown on demand, reused).
 struct Workspace {
   DevBuf Y, P, Q, R, D, X, part, W, small, state, tgt, pos, plans, units, uid, act, out, xs,
-      rows, map, flags, strips, sid, Za, Zb;
+      rows, map, flags, strips, sid, Za, Zb, Zc, Zd;
   void release();
 };
 
@@ -193,8 +193,10 @@ struct SolveBuffers {
   double cheb_invtheta = 1.0;
   double cheb_a1[MAX_CHEB] = {};
   double cheb_a2[MAX_CHEB] = {};
-  void* Za = nullptr;  // rows x S, T: Chebyshev iterates (ping-pong)
-  void* Zb = nullptr;
+  void* Za = nullptr;  // rows x S, T: Chebyshev iterates (z_1 in Za, then
+  void* Zb = nullptr;  // rotating over the four arrays)
+  void* Zc = nullptr;
+  void* Zd = nullptr;
 };
 
 int grid_for(int64_t n);

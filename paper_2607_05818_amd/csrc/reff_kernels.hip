@@ -31,6 +31,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace reff {
 
@@ -903,6 +904,24 @@ __global__ __launch_bounds__(WG, 4) void k_gram_ab(Coef<T> c, Work wk, const T* 
   gram_store<T>(part_of(part, uidx, m), w, lane, acc);
 }
 
+// One Chebyshev step at one node: u + a1 (u - up) + a2 Dinv (r - (G u)_v),
+// (G u)_v = d u - cE ue - cW uw - cN un - cS us - gU yu - gD yd.  Every
+// kernel that forms a Chebyshev iterate calls this, with explicit fused
+// multiply-adds, so a value recomputed by another workgroup (a strip halo,
+// a TSV partner) is bitwise the value its owner writes.
+template <typename T>
+__device__ __forceinline__ T cheb_node(T u, T ue, T uw, T un, T us, T yu, T yd, T d, T ce, T cw,
+                                       T cn, T cs, T gu, T gd, T up, T r, T dinv, T a1, T a2) {
+  T g = d * u;
+  g = fma(-ce, ue, g);
+  g = fma(-cw, uw, g);
+  g = fma(-cn, un, g);
+  g = fma(-cs, us, g);
+  g = fma(-gu, yu, g);
+  g = fma(-gd, yd, g);
+  return fma(a2 * dinv, r - g, fma(a1, u - up, u));
+}
+
 // One step of the Chebyshev polynomial preconditioner Z = q(D^-1 G) D^-1 R
 // (block variant, over strips like the stencil kernel):
 //   zout = u + a1 (u - uprev) + a2 D^-1 (R - G u),   u = z_j, uprev = z_{j-1}
@@ -1058,11 +1077,10 @@ __global__ __launch_bounds__(WG, 4) void k_cheb_strip(Coef<T> c, Work wk, const 
       // nodes past the strip's width repeat the last node: same inputs, same
       // value, same address
       const int jc = min(w * NPW + i, wdt - 1);
-      const T uc = win[sc][jc + 1][lane];
-      T g = cd[b][jc] * uc - ce[b][jc + 1] * win[sc][jc + 2][lane] - ce[b][jc] * win[sc][jc][lane] -
-            cn[b][jc] * win[sn][jc + 1][lane] - cn[b ^ 1][jc] * win[ss][jc + 1][lane];
-      g -= gu[i] * yu[i] + gd[i] * yd[i];
-      const T zn = uc + a1 * (uc - pc[i]) + a2 * cdi[b][jc] * (rc[i] - g);
+      const T zn = cheb_node(win[sc][jc + 1][lane], win[sc][jc + 2][lane], win[sc][jc][lane],
+                             win[sn][jc + 1][lane], win[ss][jc + 1][lane], yu[i], yd[i],
+                             cd[b][jc], ce[b][jc + 1], ce[b][jc], cn[b][jc], cn[b ^ 1][jc], gu[i],
+                             gd[i], pc[i], rc[i], cdi[b][jc], a1, a2);
       zout[(obase + jc) * S + lane] = zn;
     }
     __syncthreads();
@@ -1075,6 +1093,292 @@ __global__ __launch_bounds__(WG, 4) void k_cheb_strip(Coef<T> c, Work wk, const 
     }
     __syncthreads();
   }
+}
+
+// Two Chebyshev steps in one pass over a strip (block variant):
+//   z_{j+1} = step(z_j, z_{j-1}; a1, a2),   z_{j+2} = step(z_{j+1}, z_j; b1, b2)
+// (z_{j-1} = 0 without HAS_PREV).  The workgroup marches its strip in +y
+// with two levels one row apart: level 1 forms z_{j+1} on row y + 1 over the
+// strip and one halo column on each side (from z_j over two halo columns),
+// level 2 forms z_{j+2} on row y from the z_{j+1} rows y - 1 .. y + 1 held in
+// LDS.  z_{j+1} at the TSV partners of a row-y node (other tiers, other
+// workgroups) is recomputed from z_j, z_{j-1} and R.  All values come from
+// cheb_node, so each recomputed copy equals the owner's value bit for bit.
+// z_{j+1} goes to out1 (the next pair's z_{j-1}), z_{j+2} to out2; neither
+// may alias an input, since other workgroups read the inputs at halos and
+// TSV partners.
+template <typename T, bool HAS_PREV>
+__global__ __launch_bounds__(WG, sizeof(T) == 4 ? 4 : 2) void k_cheb2_strip(Coef<T> c, Work wk,
+                                                       const T* __restrict__ zin,
+                                                       const T* __restrict__ zprev,
+                                                       const T* __restrict__ R,
+                                                       T* __restrict__ out1,
+                                                       T* __restrict__ out2, T a1, T a2, T b1,
+                                                       T b2) {
+  constexpr int NPW = NODES_PER_WAVE;
+  constexpr int NC = CH + 2;  // level-1 columns -1 .. CH, index c + 1
+  // Ring of z_j rows (columns -2 .. CH + 1 at index c + 2): row y + k in
+  // slot (s + 2 + k) % 4.  Ring of z_{j+1} rows: row y + k in slot
+  // (s + 2 + k) % 3.  Coefficients of row y + k in slot (s + 2 + k) % 3,
+  // cN of row y + k in slot (s + 2 + k) % 4.
+  __shared__ __align__(16) T w1[4][CH + 4][LDW];
+  __shared__ __align__(16) T w2[3][NC][LDW];
+  __shared__ T cd[3][NC], cdi[3][NC], ce[3][NC + 1], cn[4][NC];  // ce: index c + 2
+  __shared__ int cslot[3][NC];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int sidx = wk.sid[logical_block(blockIdx.x, gridDim.x)];
+  const Strip st = wk.strips[sidx];
+  const PlanDesc pd = wk.plans[st.plan];
+  const int nx = pd.nx;
+  const int ny = (int)(pd.plane / pd.nx);
+  const int wdt = st.wdt;
+  const int x0 = st.x0;
+  const int64_t cofs = pd.cbase - pd.vbase;
+  auto col_ok = [&](int cc) { return x0 + cc >= 0 && x0 + cc < nx; };
+  auto row_ok = [&](int yy) { return yy >= 0 && yy < ny; };
+  // Vector row of strip node (yy, cc), clamped into the tier: every load
+  // reads a valid address; values of nodes outside the tier are replaced
+  // by zero when they are written to LDS or registers used later.
+  auto vidx = [&](int yy, int cc) -> int64_t {
+    yy = min(max(yy, 0), ny - 1);
+    cc = min(max(cc, -x0), nx - 1 - x0);
+    return pd.vbase + st.lrow0 + (int64_t)(yy - st.y0) * nx + cc;
+  };
+  // z_j row: nodes j = 4w + i, halo columns -2, -1, wdt, wdt + 1 (waves 0-3)
+  const int hc = w == 0 ? -2 : w == 1 ? -1 : wdt + (w - 2);
+  auto load_w1 = [&](int yy, T (&v)[NPW], T& h) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) v[i] = zin[vidx(yy, w * NPW + i) * S + lane];
+    if (w < 4) h = zin[vidx(yy, hc) * S + lane];
+  };
+  auto store_w1 = [&](int slot, const T (&v)[NPW], T h, int yy) {
+    const bool in = row_ok(yy);
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      const int j = w * NPW + i;
+      w1[slot][j + 2][lane] = (in && j < wdt) ? v[i] : T(0);
+    }
+    // east halo columns only for a full-width strip (a ragged strip ends at
+    // the tier's east edge, and the columns past it are zero above)
+    if (w < 2 || (w < 4 && wdt == CH)) w1[slot][hc + 2][lane] = (in && col_ok(hc)) ? h : T(0);
+  };
+  // pointwise rows on level-1 columns: nodes j, and -1 (wave 0), wdt (wave 1)
+  const int lc = w == 0 ? -1 : wdt;
+  auto load_pt = [&](const T* __restrict__ a, int yy, T (&v)[NPW], T& h) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) v[i] = a[vidx(yy, w * NPW + i) * S + lane];
+    if (w < 2) h = a[vidx(yy, lc) * S + lane];
+  };
+  // Coefficients of one row, one value per thread t < 5 NC + 1 (waves 0-2):
+  // d, cE (columns -2 .. CH), cN, Dinv on level-1 columns, and the TSV slot.
+  const int t = threadIdx.x;
+  const int kind = t < NC ? 0 : t < 2 * NC + 1 ? 1 : t < 3 * NC + 1 ? 2 : t < 4 * NC + 1 ? 3 : 4;
+  const int kcol = kind == 0   ? t - 1
+                   : kind == 1 ? t - NC - 2
+                   : kind == 2 ? t - (2 * NC + 1) - 1
+                   : kind == 3 ? t - (3 * NC + 1) - 1
+                               : t - (4 * NC + 1) - 1;
+  const T* csrc = kind == 0 ? c.d : kind == 1 ? c.cE : kind == 2 ? c.cN : c.dinv;
+  auto load_coef = [&](int yy, T& val, int& sl) {
+    if (w < 3) {
+      const int64_t ci = vidx(yy, kcol) + cofs;
+      val = csrc[ci];
+      sl = c.slot[ci];
+    }
+  };
+  auto store_coef = [&](int k, int kn, T val, int sl) {
+    const bool ok = col_ok(kcol);
+    if (kind == 0)
+      cd[k][kcol + 1] = ok ? val : T(0);
+    else if (kind == 1)
+      ce[k][kcol + 2] = ok ? val : T(0);
+    else if (kind == 2)
+      cn[kn][kcol + 1] = ok ? val : T(0);
+    else if (kind == 3)
+      cdi[k][kcol + 1] = ok ? val : T(0);
+    else if (t < 5 * NC + 1)
+      cslot[k][kcol + 1] = ok ? sl : -1;
+  };
+  // z_{j+1} at a node from global memory (a TSV partner of a level-2 node):
+  // the same arguments as level 1 passes from LDS.
+  auto point = [&](int64_t p, int xg, int yy) -> T {
+    const int64_t pc = p + cofs;
+    const bool he = xg + 1 < nx, hw = xg > 0, hn = yy + 1 < ny, hs = yy > 0;
+    const T u = zin[p * S + lane];
+    const T ue = zin[(he ? p + 1 : p) * S + lane];
+    const T uw = zin[(hw ? p - 1 : p) * S + lane];
+    const T un = zin[(hn ? p + nx : p) * S + lane];
+    const T us = zin[(hs ? p - nx : p) * S + lane];
+    const int sp = ldc(c.slot, pc);
+    const int q = max(sp, 0);
+    const T gu = sp >= 0 ? ldc(c.up, q) : T(0);
+    const T gd = sp >= 0 ? ldc(c.dn, q) : T(0);
+    const T yu = zin[(gu != T(0) ? p + pd.plane : p) * S + lane];
+    const T yd = zin[(gd != T(0) ? p - pd.plane : p) * S + lane];
+    const T up = HAS_PREV ? zprev[p * S + lane] : T(0);
+    const T r = R[p * S + lane];
+    const T cw = hw ? ldc(c.cE, hw ? pc - 1 : pc) : T(0);
+    const T cs = hs ? ldc(c.cN, hs ? pc - nx : pc) : T(0);
+    return cheb_node(u, he ? ue : T(0), hw ? uw : T(0), hn ? un : T(0), hs ? us : T(0), yu, yd,
+                     ldc(c.d, pc), ldc(c.cE, pc), cw, ldc(c.cN, pc), cs, gu, gd, up, r,
+                     ldc(c.dinv, pc), a1, a2);
+  };
+
+  // Prologue: z_j rows y0-2 .. y0 in slots 0 .. 2, coefficients of rows
+  // y0-2 (slot 0) and y0-1 (slot 1), R and z_{j-1} of row y0-1.
+  T rA[NPW], rAh = T(0), pA[NPW], pAh = T(0), rB[NPW];
+  {
+    T v[NPW], h = T(0), cv = T(0);
+    int csl = -1;
+    load_w1(st.y0 - 2, v, h);
+    store_w1(0, v, h, st.y0 - 2);
+    load_w1(st.y0 - 1, v, h);
+    store_w1(1, v, h, st.y0 - 1);
+    load_w1(st.y0, v, h);
+    store_w1(2, v, h, st.y0);
+    load_coef(st.y0 - 2, cv, csl);
+    store_coef(0, 0, cv, csl);
+    load_coef(st.y0 - 1, cv, csl);
+    store_coef(1, 1, cv, csl);
+    load_pt(R, st.y0 - 1, rA, rAh);
+    if (HAS_PREV) {
+      load_pt(zprev, st.y0 - 1, pA, pAh);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) pA[i] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) rB[i] = T(0);
+  }
+  __syncthreads();
+
+  // One row: level 1 on row y + 1, level 2 (L2) on row y.
+  auto row = [&](int s, auto L2) {
+    constexpr bool lvl2 = decltype(L2)::value;
+    const int y = st.y0 + s;
+    const int r0 = s + 2;
+    const int sw0 = r0 % 4, sw1 = (r0 + 1) % 4, sw2 = (r0 + 2) % 4, sw3 = (r0 + 3) % 4;
+    const int q0 = r0 % 3, q1 = (r0 + 1) % 3, qm = (r0 + 2) % 3;  // z_{j+1} rows y, y+1, y-1
+    const int k0 = r0 % 3, k1 = (r0 + 1) % 3, k2 = (r0 + 2) % 3;  // coefficients of y, y+1, y+2
+    const int n0 = r0 % 4, n1 = (r0 + 1) % 4, n2 = (r0 + 2) % 4, nm = (r0 + 3) % 4;  // cN
+    // [A] TSV partners: z_j of level-1 nodes (row y + 1), and z_{j+1} of
+    // level-2 nodes (row y), before the next row's loads.
+    int sl1[NPW + 1];
+    bool any1 = false;
+#pragma unroll
+    for (int i = 0; i <= NPW; ++i) {
+      const int cc = i < NPW ? min(w * NPW + i, wdt - 1) : lc;
+      sl1[i] = (i < NPW || w < 2) ? __builtin_amdgcn_readfirstlane(cslot[k1][cc + 1]) : -1;
+      any1 |= sl1[i] >= 0;
+    }
+    T gu1[NPW + 1], gd1[NPW + 1], yu1[NPW + 1], yd1[NPW + 1];
+    if (any1) {
+#pragma unroll
+      for (int i = 0; i <= NPW; ++i) {
+        const int cc = i < NPW ? min(w * NPW + i, wdt - 1) : lc;
+        const int64_t v = vidx(y + 1, cc);
+        const int q = max(sl1[i], 0);
+        gu1[i] = sl1[i] >= 0 ? ldc(c.up, q) : T(0);
+        gd1[i] = sl1[i] >= 0 ? ldc(c.dn, q) : T(0);
+        yu1[i] = zin[(gu1[i] != T(0) ? v + pd.plane : v) * S + lane];
+        yd1[i] = zin[(gd1[i] != T(0) ? v - pd.plane : v) * S + lane];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i <= NPW; ++i) gu1[i] = gd1[i] = yu1[i] = yd1[i] = T(0);
+    }
+    T gu2[NPW], gd2[NPW], zu2[NPW], zd2[NPW];
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) gu2[i] = gd2[i] = zu2[i] = zd2[i] = T(0);
+    if constexpr (lvl2) {
+      int sl2[NPW];
+      bool any2 = false;
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        sl2[i] = __builtin_amdgcn_readfirstlane(cslot[k0][min(w * NPW + i, wdt - 1) + 1]);
+        any2 |= sl2[i] >= 0;
+      }
+      if (any2) {
+        // one partner at a time (wave-uniform branches), to bound the
+        // registers of the loads in flight
+#pragma unroll
+        for (int i = 0; i < NPW; ++i) {
+          if (sl2[i] < 0) continue;
+          const int jc = min(w * NPW + i, wdt - 1);
+          const int64_t v = vidx(y, jc);
+          gu2[i] = ldc(c.up, sl2[i]);
+          gd2[i] = ldc(c.dn, sl2[i]);
+          if (gu2[i] != T(0)) zu2[i] = point(v + pd.plane, x0 + jc, y);
+          if (gd2[i] != T(0)) zd2[i] = point(v - pd.plane, x0 + jc, y);
+        }
+      }
+    }
+    // [B] next row: z_j row y + 3, coefficients, R and z_{j-1} of row y + 2
+    T v1n[NPW], h1n = T(0), rN[NPW], rNh = T(0), pN[NPW], pNh = T(0), cvN = T(0);
+    int cslN = -1;
+    load_w1(y + 3, v1n, h1n);
+    load_coef(y + 2, cvN, cslN);
+    load_pt(R, y + 2, rN, rNh);
+    if (HAS_PREV) load_pt(zprev, y + 2, pN, pNh);
+    // [C] level 1: z_{j+1} on row y + 1
+    const bool in1 = row_ok(y + 1);
+    T z1[NPW];
+#pragma unroll
+    for (int i = 0; i <= NPW; ++i) {
+      if (i == NPW && w >= 2) break;
+      const int j = i < NPW ? w * NPW + i : lc;
+      const int cc = i < NPW ? min(j, wdt - 1) : lc;
+      const T up = i < NPW ? pA[i] : pAh;
+      const T r = i < NPW ? rA[i] : rAh;
+      const T z = cheb_node(w1[sw1][cc + 2][lane], w1[sw1][cc + 3][lane], w1[sw1][cc + 1][lane],
+                            w1[sw2][cc + 2][lane], w1[sw0][cc + 2][lane], yu1[i], yd1[i],
+                            cd[k1][cc + 1], ce[k1][cc + 2], ce[k1][cc + 1], cn[n1][cc + 1],
+                            cn[n0][cc + 1], gu1[i], gd1[i], up, r, cdi[k1][cc + 1], a1, a2);
+      const bool ok = in1 && (i < NPW ? j < wdt : col_ok(lc));
+      // the east halo column exists only for a full-width strip
+      if (i < NPW || w == 0 || wdt == CH) w2[q1][(i < NPW ? j : lc) + 1][lane] = ok ? z : T(0);
+      if (i < NPW) z1[i] = z;
+    }
+    __syncthreads();
+    // [D] level 2: z_{j+2} on row y
+    if constexpr (lvl2) {
+      const int64_t obase = pd.vbase + st.lrow0 + (int64_t)s * nx;
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        // nodes past a ragged strip's width repeat the last node
+        const int jc = min(w * NPW + i, wdt - 1);
+        const T z = cheb_node(w2[q0][jc + 1][lane], w2[q0][jc + 2][lane], w2[q0][jc][lane],
+                              w2[q1][jc + 1][lane], w2[qm][jc + 1][lane], zu2[i], zd2[i],
+                              cd[k0][jc + 1], ce[k0][jc + 2], ce[k0][jc + 1], cn[n0][jc + 1],
+                              cn[nm][jc + 1], gu2[i], gd2[i], w1[sw0][jc + 2][lane], rB[i],
+                              cdi[k0][jc + 1], b1, b2);
+        out2[(obase + jc) * S + lane] = z;
+      }
+    }
+    // [E] the next row into the slots of rows y - 1 (z_j, coefficients) and
+    // y - 2 (cN), which no step of this row reads
+    store_w1(sw3, v1n, h1n, y + 3);
+    store_coef(k2, n2, cvN, cslN);
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      rB[i] = rA[i];
+      rA[i] = rN[i];
+      pA[i] = HAS_PREV ? pN[i] : T(0);
+    }
+    rAh = rNh;
+    pAh = pNh;
+    // z_{j+1} of row y + 1 if it is a row of this strip
+    if (s + 1 >= 0 && s + 1 < st.nrows) {
+      const int64_t b1row = pd.vbase + st.lrow0 + (int64_t)(s + 1) * nx;
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) out1[(b1row + min(w * NPW + i, wdt - 1)) * S + lane] = z1[i];
+    }
+    __syncthreads();
+  };
+  row(-2, std::false_type{});
+  row(-1, std::false_type{});
+  for (int s = 0; s < st.nrows; ++s) row(s, std::true_type{});
 }
 
 // C = Xa^T (G Xb) over all nodes of a block (pair resistances: the
@@ -1166,7 +1470,7 @@ __device__ void convergence_update(BlockState* st, const double* dpsi, double to
     st->hist[it % HIST][k] = d;
     const int itn = it + 1;
     double est = INFINITY;
-    if (itn >= 2 * HIST) {
+    if (itn >= HIST) {
       double A = 0.0, B = 0.0;
       for (int h = 0; h < HIST; ++h) {
         const double val = fabs(st->hist[(itn - HIST + h) % HIST][k]);
@@ -1666,29 +1970,50 @@ static void reduce(const SolveBuffers& b, int m0, int nmat, int len, hipStream_t
                      b.W, b.work.plans, b.act, m0, nmat, len, strips ? 1 : 0);
 }
 
-// Chebyshev steps j = 1 .. cheb_k - 1 from z_1 in Za; the iterates
-// alternate between Za and Zb (z_{j+1} overwrites z_{j-1}); the last step
-// writes to `last` if given.  Returns the array that holds Z.
+// Chebyshev steps j = 1 .. cheb_k - 1 from z_1 in Za, two per pass where
+// two remain (one pass reads z_j, z_{j-1} and writes z_{j+1}, z_{j+2} to
+// two arrays that hold neither); the iterates rotate over Za .. Zd.  The
+// last step writes to `last` if given.  Returns the array that holds Z.
 template <typename T>
 static T* cheb_steps(const Coef<T>& c, const SolveBuffers& b, hipStream_t st, T* last) {
   const dim3 g(b.n_strips), blk(WG);
-  T* in = (T*)b.Za;
-  T* prev = nullptr;
+  T* buf[4] = {(T*)b.Za, (T*)b.Zb, (T*)b.Zc, (T*)b.Zd};
   const T* R = (const T*)b.R;
-  for (int j = 1; j < b.cheb_k; ++j) {
-    T* out = j == 1 ? (T*)b.Zb : prev;
-    if (j == b.cheb_k - 1 && last) out = last;
+  int cur = 0, prev = -1;
+  auto free_slot = [&](int skip) {
+    for (int i = 0; i < 4; ++i)
+      if (i != cur && i != prev && i != skip) return i;
+    return -1;
+  };
+  int j = 1;
+  while (j + 1 < b.cheb_k) {
+    const int f1 = free_slot(-1), f2 = free_slot(f1);
+    T* o2 = (j + 2 == b.cheb_k && last) ? last : buf[f2];
     const T a1 = (T)b.cheb_a1[j], a2 = (T)b.cheb_a2[j];
-    if (j == 1)
-      hipLaunchKernelGGL((k_cheb_strip<T, false>), g, blk, 0, st, c, b.work, (const T*)in,
-                         (const T*)nullptr, R, out, a1, a2);
+    const T b1 = (T)b.cheb_a1[j + 1], b2 = (T)b.cheb_a2[j + 1];
+    if (prev < 0)
+      hipLaunchKernelGGL((k_cheb2_strip<T, false>), g, blk, 0, st, c, b.work, (const T*)buf[cur],
+                         (const T*)nullptr, R, buf[f1], o2, a1, a2, b1, b2);
     else
-      hipLaunchKernelGGL((k_cheb_strip<T, true>), g, blk, 0, st, c, b.work, (const T*)in,
-                         (const T*)prev, R, out, a1, a2);
-    prev = in;
-    in = out;
+      hipLaunchKernelGGL((k_cheb2_strip<T, true>), g, blk, 0, st, c, b.work, (const T*)buf[cur],
+                         (const T*)buf[prev], R, buf[f1], o2, a1, a2, b1, b2);
+    j += 2;
+    if (o2 == last) return last;
+    prev = f1;
+    cur = f2;
   }
-  return in;
+  if (j < b.cheb_k) {  // one step left
+    T* o = last ? last : buf[free_slot(-1)];
+    const T a1 = (T)b.cheb_a1[j], a2 = (T)b.cheb_a2[j];
+    if (prev < 0)
+      hipLaunchKernelGGL((k_cheb_strip<T, false>), g, blk, 0, st, c, b.work, (const T*)buf[cur],
+                         (const T*)nullptr, R, o, a1, a2);
+    else
+      hipLaunchKernelGGL((k_cheb_strip<T, true>), g, blk, 0, st, c, b.work, (const T*)buf[cur],
+                         (const T*)buf[prev], R, o, a1, a2);
+    return o;
+  }
+  return buf[cur];
 }
 
 // Y = M^-1 R for a solve that starts from the residual in R, then T from

@@ -41,5 +41,28 @@ def test_degree_out_of_range_rejected():
     reff = _reff()
     h = reff.reff_build_pdn(gen.config1())
     with pytest.raises(reff.ReffError) as ei:
-        reff.reff_solve_diag(h, [5], precond_degree=17)
+        reff.reff_solve_diag(h, [5], precond_degree=33)
     assert ei.value.status == reff.REFF_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("kind", ["ragged_square", "ragged_rect"])
+def test_paired_steps_on_ragged_strips(kind):
+    """Degrees whose steps run as fused pairs (3: one pair; 5: two pairs;
+    6: two pairs and a single step) on tiers whose width is not a multiple
+    of the strip width, with TSVs: every result within the mixed bar."""
+    reff = _reff()
+    if kind == "ragged_square":
+        d = gen.config2(side=100, n_tsv=64, sigma=10.0)
+    else:
+        d = gen.small_random_desc(41, 3, 45, 37, 40, 4)
+    nodes = gen.sample_free_nodes(d, 64, 5)
+    want = ro.diag(d, nodes)
+    h = reff.reff_build_pdn(d)
+    for k in (3, 5, 6):
+        _say("paired precond degree", k, kind)
+        got, st = reff.reff_solve_diag(h, nodes, precision=1, rel_tol=1e-5, precond_degree=k)
+        err = float(np.max(np.abs(got - want) / want))
+        print("degree", k, "iters", st["iters_total"], "err", err, flush=True)
+        assert err <= 1e-3
+    got, _ = reff.reff_solve_diag(h, nodes, precision=0, rel_tol=1e-9, precond_degree=3)
+    assert float(np.max(np.abs(got - want) / want)) <= 1e-6
