@@ -29,18 +29,28 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # dense matrix-core peaks
 S = 64
 
 
-def cheb_words(cheb):
+def cheb_passes(cheb, fp32=True):
+    """The Chebyshev passes of one preconditioner application, in order:
+    (steps, has z_{j-1}) per pass.  Steps run three per pass while three
+    remain (float32; two in float64), then two, then one."""
+    left, first, out = cheb - 1, True, []
+    top = 3 if fp32 else 2
+    while left > 0:
+        k = min(top, left)
+        out.append((k, not first))
+        left -= k
+        first = False
+    return out
+
+
+def cheb_words(cheb, fp32=True):
     """S-wide vector words per node that the Chebyshev passes of one
-    preconditioner application read and write, and the number of passes:
-    steps run two per pass while two remain (a pass reads z_j, z_{j-1}, R and
-    writes z_{j+1}, z_{j+2}; the first pass has no z_{j-1}), a last odd step
-    reads z_j, z_{j-1}, R and writes z_{j+1}."""
-    steps = cheb - 1
-    pairs, single = steps // 2, steps % 2
-    words = sum(4 if i == 0 else 5 for i in range(pairs))
-    if single:
-        words += 3 if pairs == 0 else 4
-    return words, pairs + single
+    application read and write, and the number of passes: a pass reads z_j,
+    R (and z_{j-1} after the first) and writes its last two iterates (one
+    for a single step)."""
+    passes = cheb_passes(cheb, fp32)
+    words = sum((3 if prev else 2) + min(k, 2) for k, prev in passes)
+    return words, len(passes)
 
 
 def kernel_bytes(n, fp32=True, mixed_with_d=True, cheb=1):
@@ -52,19 +62,21 @@ def kernel_bytes(n, fp32=True, mixed_with_d=True, cheb=1):
                          + Dinv; with the polynomial preconditioner it also
                          writes z_1 = D^-1 R / theta            -> + S w
       search block (K3): read P, R (or Z); write Y              -> 3 S w + d, Dinv
-      preconditioner (degree k > 1): the Chebyshev passes (cheb_words), each
-                         also reading d, cE, cN, Dinv and the slot, then
-                         Q^T Z reads Q, Z                       -> + 2 S w
+      Chebyshev passes (degree k > 1), all passes of one application: the
+                         vector words of cheb_words, each pass also reading
+                         d, cE, cN, Dinv and the slot
+      Q^T Z Gram (degree k > 1): read Q, Z                     -> 2 S w
     """
     w = 4 if fp32 else 8
     k1 = n * (4 * S * w + 3 * w + 4)
     k2 = n * ((6 if mixed_with_d else 3) * S * w + w + (S * w if cheb > 1 else 0))
     k3 = n * (3 * S * w + 2 * w)
-    kp = 0
+    kp = kg = 0
     if cheb > 1:
-        words, passes = cheb_words(cheb)
-        kp = n * ((words + 2) * S * w + passes * (4 * w + 4))
-    return [k1, k2, k3, kp]
+        words, passes = cheb_words(cheb, fp32)
+        kp = n * (words * S * w + passes * (4 * w + 4))
+        kg = n * 2 * S * w
+    return [k1, k2, k3, kp, kg]
 
 
 def kernel_flops(cheb=1):
@@ -72,12 +84,12 @@ def kernel_flops(cheb=1):
     (2 S^2 per S x S product or Gram): K1 = P = Y T and Q = (G Y) T with T
     upper triangular (10 of the 16 16 x 16 blocks of T are nonzero) plus the
     Grams P^T Q and P^T R; K2 = Q A, P A and (Jacobi) Q^T Z; K3 = P B and
-    Y^T D Y; the polynomial preconditioner's Q^T Z Gram (its steps are
-    stencil arithmetic, not matrix-core work)."""
+    Y^T D Y; the Chebyshev passes are stencil arithmetic (no matrix-core
+    work); the preconditioner's Q^T Z Gram."""
     g = 2 * S * S
     if cheb > 1:
-        return [2 * g * 10 // 16 + 2 * g, 2 * g, 2 * g, g]
-    return [2 * g * 10 // 16 + 2 * g, 3 * g, 2 * g, 0]
+        return [2 * g * 10 // 16 + 2 * g, 2 * g, 2 * g, 0, g]
+    return [2 * g * 10 // 16 + 2 * g, 3 * g, 2 * g, 0, 0]
 
 
 def cpu_baseline(desc, batch_nodes, n_timed=2):
@@ -381,9 +393,9 @@ def main():
         st = step(False)
         log(f"warmup {w}: {st['iters_total']} iterations, {st['seconds']:.2f} s")
     torch.cuda.synchronize()
-    kms = np.zeros(4)
-    kl = np.zeros(4, dtype=np.int64)
-    krows = np.zeros(4, dtype=np.int64)
+    kms = np.zeros(5)
+    kl = np.zeros(5, dtype=np.int64)
+    krows = np.zeros(5, dtype=np.int64)
     iters = 0
     worst = 0.0
     n_ok = 0
@@ -409,28 +421,32 @@ def main():
     kb = kernel_bytes(1, fp32=fp32, mixed_with_d=fp32, cheb=cheb)
     kf = kernel_flops(cheb)
     mpeak = MFMA_PEAK_TFLOPS["f32" if fp32 else "f64"]
-    names = ["stencil_gram", "update_r", "update_y", "precond"]
+    names = ["stencil_gram", "update_r", "update_y", "cheb_pass", "precond_gram"]
+    # one timed span of the Chebyshev entry covers all passes of an iteration
+    passes = cheb_words(cheb, fp32)[1] if cheb > 1 else 0
     kern = {}
     for i, nm in enumerate(names):
         if kl[i] == 0 or kms[i] == 0:
             continue
-        avg_ms = kms[i] / max(kl[i], 1)
+        per_span = passes if i == 3 else 1
+        launches = kl[i] * per_span
+        avg_ms = kms[i] / launches
         # A launch streams every unconverged block of the group: bytes (and
         # flops) per launch = per node row x rows streamed / launches.
         rows = krows[i] / max(kl[i], 1)
-        per_launch = kb[i] * rows
-        flops = kf[i] * rows
+        per_launch = kb[i] / per_span * rows
+        flops = kf[i] / per_span * rows
         # the binding ceiling: the larger of the two times at peak
         t_hbm = per_launch / (HBM_PEAK_GBS * 1e9)
         t_mfma = flops / (mpeak * 1e12)
-        kern[nm] = {"avg_us": avg_ms * 1e3, "launches": int(kl[i]), "rows_per_launch": rows,
-                    "alg_bytes_per_row": int(kb[i]), "alg_bytes_per_launch": per_launch,
-                    "alg_flops_per_row": int(kf[i]),
+        kern[nm] = {"avg_us": avg_ms * 1e3, "launches": int(launches), "rows_per_launch": rows,
+                    "alg_bytes_per_row": kb[i] / per_span, "alg_bytes_per_launch": per_launch,
+                    "alg_flops_per_row": kf[i] / per_span,
                     "GBps": per_launch / (avg_ms * 1e-3) / 1e9,
                     "TFLOPs": flops / (avg_ms * 1e-3) / 1e12,
                     "hbm_frac": t_hbm / (avg_ms * 1e-3), "mfma_frac": t_mfma / (avg_ms * 1e-3),
                     "bound": "mfma" if t_mfma > t_hbm else "hbm"}
-    dom = max(range(4), key=lambda i: kms[i])
+    dom = max(range(5), key=lambda i: kms[i])
     dk = kern[names[dom]]
     mt = measured_traffic() if fp32 else None
     traffic = None

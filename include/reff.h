@@ -114,15 +114,16 @@ typedef struct {
   double est_max_rel_err; /* solver's own estimate of the worst relative
                              error (not a bound)                             */
   int64_t iters_total;    /* sum of block iterations over all blocks         */
-  /* With opts->timing: summed device time (ms) and launch count of the
-     stencil+Gram kernel [0], the residual-update kernel [1], the
-     search-block kernel [2] and the polynomial preconditioner's kernels
-     (its steps and the Q^T Z Gram) [3], and the node rows those launches
-     streamed (one row = one node of one 64-column block; a launch covers
-     every unconverged block of its group). */
-  double kernel_ms[4];
-  int64_t kernel_launches[4];
-  int64_t kernel_rows[4];
+  /* With opts->timing, per block iteration: summed device time (ms) and
+     count of the stencil+Gram kernel [0], the residual-update kernel [1],
+     the search-block kernel [2], the polynomial preconditioner's Chebyshev
+     passes [3] (one entry covers all passes of an iteration) and its Q^T Z
+     Gram [4], and the node rows those launches streamed (one row = one
+     node of one 64-column block; a launch covers every unconverged block
+     of its group). */
+  double kernel_ms[5];
+  int64_t kernel_launches[5];
+  int64_t kernel_rows[5];
   /* reff_batch_plans with a surrogate: 1 if the plan's results are the
      model's predictions (solved values at the checked nodes), 0 if it fell
      back to the solver; the largest relative error of the prediction over

@@ -218,10 +218,10 @@ reff_status ensure(DevBuf& b, size_t bytes) {
 }
 
 Coef<double> coef64(const CoefSet& cs) {
-  return Coef<double>{cs.d64, cs.dinv64, cs.cE64, cs.cN64, cs.slot, cs.up64, cs.dn64};
+  return Coef<double>{cs.d64, cs.dinv64, cs.cE64, cs.cN64, cs.slot, cs.up64, cs.dn64, cs.tnode};
 }
 Coef<float> coef32(const CoefSet& cs) {
-  return Coef<float>{cs.d32, cs.dinv32, cs.cE32, cs.cN32, cs.slot, cs.up32, cs.dn32};
+  return Coef<float>{cs.d32, cs.dinv32, cs.cE32, cs.cN32, cs.slot, cs.up32, cs.dn32, cs.tnode};
 }
 
 // The handle's copy of its description, as a reff_pdn_desc view.
@@ -245,15 +245,23 @@ reff_pdn_desc desc_view(const reff_pdn_t* p) {
 // the first coefficient index of stack i.
 reff_status make_coefset_multi(const std::vector<const reff_pdn_desc*>& ds,
                                const std::vector<std::vector<int64_t>>& gnds, CoefSet& cs,
-                               std::vector<int64_t>& cbase, std::vector<void*>& extra) {
+                               std::vector<int64_t>& cbase, std::vector<void*>& extra,
+                               std::vector<int32_t>* slot0s = nullptr) {
   HostCoef h;
+  std::vector<int64_t> tnode;
   cbase.clear();
+  if (slot0s) slot0s->clear();
   for (size_t i = 0; i < ds.size(); ++i) {
     HostCoef hi;
     reff_status s = build_host(ds[i], gnds[i], hi);
     if (s != REFF_OK) return s;
-    cbase.push_back((int64_t)h.d.size());
+    const int64_t c0 = (int64_t)h.d.size();
+    cbase.push_back(c0);
     const int32_t slot0 = (int32_t)h.up.size();
+    if (slot0s) slot0s->push_back(slot0);
+    tnode.resize((size_t)slot0 + hi.up.size());
+    for (size_t v = 0; v < hi.slot.size(); ++v)
+      if (hi.slot[v] >= 0) tnode[(size_t)slot0 + (size_t)hi.slot[v]] = c0 + (int64_t)v;
     for (int32_t& sl : hi.slot)
       if (sl >= 0) sl += slot0;
     h.d.insert(h.d.end(), hi.d.begin(), hi.d.end());
@@ -283,6 +291,11 @@ reff_status make_coefset_multi(const std::vector<const reff_pdn_desc*>& ds,
   HIPCHK(hipMalloc((void**)&cs.slot, std::max<size_t>(1, h.slot.size()) * sizeof(int32_t)));
   owned.push_back(cs.slot);
   HIPCHK(hipMemcpy(cs.slot, h.slot.data(), h.slot.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc((void**)&cs.tnode, std::max<size_t>(1, tnode.size()) * sizeof(int64_t)));
+  owned.push_back(cs.tnode);
+  if (!tnode.empty())
+    HIPCHK(hipMemcpy(cs.tnode, tnode.data(), tnode.size() * sizeof(int64_t),
+                     hipMemcpyHostToDevice));
   cs.grounded = h.is_pad;
   cs.n_free = 0;
   for (uint8_t f : h.is_pad) cs.n_free += f ? 0 : 1;
@@ -353,6 +366,7 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
 struct StackInfo {
   int64_t cbase, n, plane;
   int32_t nx;
+  int32_t slot_begin = 0, slot_end = 0;  // its TSV slots in the coefficient set
 };
 
 // One block of up to S unit-current columns on one stack: local target node
@@ -546,7 +560,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     }
   } evp;
   if (o.timing) {
-    evp.ev.resize(8 * poll);
+    evp.ev.resize(NEV * poll);
     for (auto& e : evp.ev) HIPCHK(hipEventCreate(&e));
   }
   PinnedBuf pin_tab, pin_flags;
@@ -575,7 +589,8 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
   while (j0 < jobs.size()) {
     // ---- group of jobs within the row budget
     size_t j1 = j0;
-    int64_t rows = 0;
+    int64_t rows = 0, slot_rows = 0;
+    int max_slots = 0;
     std::vector<PlanDesc> pin;
     while (j1 < jobs.size()) {
       const StackInfo& sk = stacks[(size_t)jobs[j1].stack];
@@ -586,6 +601,11 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       pd.n = sk.n;
       pd.plane = sk.plane;
       pd.nx = sk.nx;
+      pd.slot_begin = sk.slot_begin;
+      pd.slot_end = sk.slot_end;
+      pd.sbase = slot_rows;
+      slot_rows += sk.slot_end - sk.slot_begin;
+      max_slots = std::max(max_slots, sk.slot_end - sk.slot_begin);
       pin.push_back(pd);
       rows += sk.n;
       ++j1;
@@ -641,6 +661,9 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     if (cheb && (rs = ensure(ws.Zb, vec)) != REFF_OK) return rs;
     if (cheb && o.cheb > 2 && (rs = ensure(ws.Zc, vec)) != REFF_OK) return rs;
     if (cheb && o.cheb > 2 && (rs = ensure(ws.Zd, vec)) != REFF_OK) return rs;
+    const bool triples = cheb && o.cheb > 3;
+    if (triples && (rs = ensure(ws.TA, (size_t)slot_rows * 5 * S * tsz)) != REFF_OK) return rs;
+    if (triples && (rs = ensure(ws.TB, (size_t)slot_rows * S * tsz)) != REFF_OK) return rs;
     if ((rs = ensure(ws.part, (size_t)std::max(nu, ns) * NGRAM * S * S * sizeof(double))) != REFF_OK)
       return rs;
     if ((rs = ensure(ws.W, (size_t)nb * NGRAM * S * S * sizeof(double))) != REFF_OK) return rs;
@@ -740,6 +763,9 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       b.Zb = ws.Zb.p;
       b.Zc = ws.Zc.p;
       b.Zd = ws.Zd.p;
+      b.TA = ws.TA.p;
+      b.TB = ws.TB.p;
+      b.max_slots = max_slots;
     }
 
     HIPCHK(launch_init_blocks(fp32, o.indep, coef, b, o.stream));
@@ -820,7 +846,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
         } else {
           for (int i = 0; i < k; ++i)
             HIPCHK(launch_iteration(fp32, o.indep, with_d, coef, b, o.tol, o.stream,
-                                    o.timing ? &evp.ev[8 * i] : nullptr));
+                                    o.timing ? &evp.ev[NEV * i] : nullptr));
         }
         it += k;
         if (o.progress) {
@@ -840,9 +866,10 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
         HIPCHK(hipStreamSynchronize(o.stream));
         if (o.timing && st) {
           for (int i = 0; i < k; ++i)
-            for (int kk = 0; kk < 4; ++kk) {
+            for (int kk = 0; kk < NEV / 2; ++kk) {
               float ms = 0.f;
-              HIPCHK(hipEventElapsedTime(&ms, evp.ev[8 * i + 2 * kk], evp.ev[8 * i + 2 * kk + 1]));
+              HIPCHK(hipEventElapsedTime(&ms, evp.ev[NEV * i + 2 * kk],
+                                         evp.ev[NEV * i + 2 * kk + 1]));
               st->kernel_ms[kk] += ms;
               st->kernel_launches[kk] += 1;
               st->kernel_rows[kk] += act_rows;
@@ -1177,7 +1204,8 @@ reff_status reff_solve_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, d
   reff_status rs = ensure(p->ws.out, (cols.size() + 1) * sizeof(double));
   if (rs != REFF_OK) return rs;
   double* res_dev = (double*)p->ws.out.p;
-  std::vector<StackInfo> stacks{StackInfo{0, p->n, p->plane, p->nx}};
+  std::vector<StackInfo> stacks{
+      StackInfo{0, p->n, p->plane, p->nx, 0, (int32_t)p->gnd.n_slots}};
   std::vector<BlockJob> jobs;
   deal_blocks(cols, 0, 0, jobs);
   std::vector<BlockResult> br;
@@ -1238,7 +1266,7 @@ reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m, const int6
   reff_status solve_rs = REFF_OK;
   if (U > 0) {
     const int64_t nn = p->n;
-    std::vector<StackInfo> stacks{StackInfo{0, nn, p->plane, p->nx}};
+    std::vector<StackInfo> stacks{StackInfo{0, nn, p->plane, p->nx, 0, (int32_t)cs->n_slots}};
     std::vector<BlockJob> jobs;
     deal_blocks(cols, 0, 0, jobs);
     const int64_t nblk = (int64_t)jobs.size();
@@ -1531,7 +1559,8 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
     }
   } free_owned{owned};
   std::vector<int64_t> cbase;
-  s = make_coefset_multi(ds, gnds, cs, cbase, owned);
+  std::vector<int32_t> slot0;
+  s = make_coefset_multi(ds, gnds, cs, cbase, owned, &slot0);
   if (s != REFF_OK) return s;
   std::vector<std::vector<int64_t>> cols((size_t)n_plans), maps((size_t)n_plans);
   std::vector<BlockJob> jobs;
@@ -1541,6 +1570,9 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
   bool any_small = false;
   for (int32_t i = 0; i < n_plans; ++i) {
     stacks[(size_t)i].cbase = cbase[(size_t)i];
+    stacks[(size_t)i].slot_begin = slot0[(size_t)i];
+    stacks[(size_t)i].slot_end =
+        i + 1 < n_plans ? slot0[(size_t)i + 1] : (int32_t)cs.n_slots;
     const bool given = nodes && nodes[i];
     const int64_t cnt = given ? n_nodes[i] : stacks[(size_t)i].n;
     std::vector<uint8_t> g(cs.grounded.begin() + cbase[(size_t)i],
@@ -1585,7 +1617,7 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
       add_stats(&ps, br, job0[(size_t)i], job0[(size_t)i + 1]);
       ps.seconds = secs;
       if (i == 0)
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < NEV / 2; ++k) {
           ps.kernel_ms[k] = agg.kernel_ms[k];
           ps.kernel_launches[k] = agg.kernel_launches[k];
           ps.kernel_rows[k] = agg.kernel_rows[k];

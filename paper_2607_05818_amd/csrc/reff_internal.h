@@ -25,6 +25,7 @@ constexpr int HIST = 8;      // convergence window (iterations)
 constexpr int MAX_GRID = 512;
 constexpr int NGRAM = 4;     // Gram partials per work unit
 constexpr int MAX_CHEB = 32;  // largest Chebyshev preconditioner degree
+constexpr int NEV = 10;       // timing events per block iteration (5 spans)
 // A column is converged once its estimated remaining relative error is
 // below CONV_SAFETY * rel_tol.
 constexpr double CONV_SAFETY = 0.25;
@@ -47,6 +48,7 @@ struct Coef {
   const int32_t* slot;   // index into up/dn, -1 if the node has no TSV
   const T* up;           // coupling to v + plane
   const T* dn;           // coupling to v - plane
+  const int64_t* tnode;  // slot -> coefficient index of its node
 };
 
 // One solve block: a stack (coefficients from node cbase on, n nodes, row
@@ -61,7 +63,8 @@ struct PlanDesc {
   int32_t nx;
   int32_t unit_begin, unit_end;
   int32_t strip_begin, strip_end;  // its strips (stencil kernel), if any
-  int32_t pad_;
+  int32_t slot_begin, slot_end;    // its stack's TSV slots (coefficient set indices)
+  int64_t sbase;                   // first row of its slots in the TSV side buffers
 };
 
 // A contiguous range of vector rows [begin, end) of one solve block,
@@ -118,7 +121,7 @@ struct DevBuf {
 // Device work arrays of the block solver (grown on demand, reused).
 struct Workspace {
   DevBuf Y, P, Q, R, D, X, part, W, small, state, tgt, pos, plans, units, uid, act, out, xs,
-      rows, map, flags, strips, sid, Za, Zb, Zc, Zd;
+      rows, map, flags, strips, sid, Za, Zb, Zc, Zd, TA, TB;
   void release();
 };
 
@@ -137,6 +140,7 @@ struct CoefSet {
   float *d32 = nullptr, *dinv32 = nullptr, *cE32 = nullptr, *cN32 = nullptr,
         *up32 = nullptr, *dn32 = nullptr;
   int32_t* slot = nullptr;
+  int64_t* tnode = nullptr;  // slot -> coefficient index of its node
   std::vector<uint8_t> grounded;
   int64_t n_free = 0;
   int64_t n_slots = 0;
@@ -197,14 +201,20 @@ struct SolveBuffers {
   void* Zb = nullptr;  // rotating over the four arrays)
   void* Zc = nullptr;
   void* Zd = nullptr;
+  // TSV side buffers of the three-step passes: z_{j+1} at every TSV node and
+  // its four in-plane neighbours ([slot row][5][S]) and z_{j+2} at every TSV
+  // node ([slot row][S]); max_slots = most slots of one block.
+  void* TA = nullptr;
+  void* TB = nullptr;
+  int max_slots = 0;
 };
 
 int grid_for(int64_t n);
 
 hipError_t launch_init_blocks(bool fp32, bool indep, const void* coef, const SolveBuffers& b,
                               hipStream_t st);
-// ev (nullable): 6 events recorded around the three vector kernels
-// (before/after K1, K2, K3).
+// ev (nullable): NEV events, before/after K1, K2, K3, the Chebyshev passes
+// and the Q^T Z Gram (ev[0..1], [2..3], [4..5], [6..7], [8..9]).
 hipError_t launch_iteration(bool fp32, bool indep, bool with_d, const void* coef,
                             const SolveBuffers& b, double tol, hipStream_t st, hipEvent_t* ev);
 hipError_t launch_zero_x(double* X, int64_t cnt, hipStream_t st);

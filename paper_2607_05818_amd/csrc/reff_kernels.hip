@@ -922,6 +922,40 @@ __device__ __forceinline__ T cheb_node(T u, T ue, T uw, T un, T us, T yu, T yd, 
   return fma(a2 * dinv, r - g, fma(a1, u - up, u));
 }
 
+// z_{j+1} at vector row p, node (xg, yy) of its tier, from global memory:
+// cheb_node with the arguments a strip kernel passes from LDS (neighbours
+// outside the tier are 0, with coupling 0 on the west and south side as
+// there; a missing TSV partner reads the node itself, with coupling 0).
+template <typename T, bool HAS_PREV>
+__device__ __forceinline__ T cheb_point(const Coef<T>& c, const PlanDesc& pd,
+                                        const T* __restrict__ zin, const T* __restrict__ zprev,
+                                        const T* __restrict__ R, int64_t p, int xg, int yy, T a1,
+                                        T a2) {
+  const int lane = threadIdx.x & 63;
+  const int nx = pd.nx;
+  const int ny = (int)(pd.plane / pd.nx);
+  const int64_t pc = p + (pd.cbase - pd.vbase);
+  const bool he = xg + 1 < nx, hw = xg > 0, hn = yy + 1 < ny, hs = yy > 0;
+  const T u = zin[p * S + lane];
+  const T ue = zin[(he ? p + 1 : p) * S + lane];
+  const T uw = zin[(hw ? p - 1 : p) * S + lane];
+  const T un = zin[(hn ? p + nx : p) * S + lane];
+  const T us = zin[(hs ? p - nx : p) * S + lane];
+  const int sp = ldc(c.slot, pc);
+  const int q = max(sp, 0);
+  const T gu = sp >= 0 ? ldc(c.up, q) : T(0);
+  const T gd = sp >= 0 ? ldc(c.dn, q) : T(0);
+  const T yu = zin[(gu != T(0) ? p + pd.plane : p) * S + lane];
+  const T yd = zin[(gd != T(0) ? p - pd.plane : p) * S + lane];
+  const T up = HAS_PREV ? zprev[p * S + lane] : T(0);
+  const T r = R[p * S + lane];
+  const T cw = hw ? ldc(c.cE, hw ? pc - 1 : pc) : T(0);
+  const T cs = hs ? ldc(c.cN, hs ? pc - nx : pc) : T(0);
+  return cheb_node(u, he ? ue : T(0), hw ? uw : T(0), hn ? un : T(0), hs ? us : T(0), yu, yd,
+                   ldc(c.d, pc), ldc(c.cE, pc), cw, ldc(c.cN, pc), cs, gu, gd, up, r,
+                   ldc(c.dinv, pc), a1, a2);
+}
+
 // One step of the Chebyshev polynomial preconditioner Z = q(D^-1 G) D^-1 R
 // (block variant, over strips like the stencil kernel):
 //   zout = u + a1 (u - uprev) + a2 D^-1 (R - G u),   u = z_j, uprev = z_{j-1}
@@ -1200,31 +1234,6 @@ __global__ __launch_bounds__(WG, sizeof(T) == 4 ? 4 : 2) void k_cheb2_strip(Coef
     else if (t < 5 * NC + 1)
       cslot[k][kcol + 1] = ok ? sl : -1;
   };
-  // z_{j+1} at a node from global memory (a TSV partner of a level-2 node):
-  // the same arguments as level 1 passes from LDS.
-  auto point = [&](int64_t p, int xg, int yy) -> T {
-    const int64_t pc = p + cofs;
-    const bool he = xg + 1 < nx, hw = xg > 0, hn = yy + 1 < ny, hs = yy > 0;
-    const T u = zin[p * S + lane];
-    const T ue = zin[(he ? p + 1 : p) * S + lane];
-    const T uw = zin[(hw ? p - 1 : p) * S + lane];
-    const T un = zin[(hn ? p + nx : p) * S + lane];
-    const T us = zin[(hs ? p - nx : p) * S + lane];
-    const int sp = ldc(c.slot, pc);
-    const int q = max(sp, 0);
-    const T gu = sp >= 0 ? ldc(c.up, q) : T(0);
-    const T gd = sp >= 0 ? ldc(c.dn, q) : T(0);
-    const T yu = zin[(gu != T(0) ? p + pd.plane : p) * S + lane];
-    const T yd = zin[(gd != T(0) ? p - pd.plane : p) * S + lane];
-    const T up = HAS_PREV ? zprev[p * S + lane] : T(0);
-    const T r = R[p * S + lane];
-    const T cw = hw ? ldc(c.cE, hw ? pc - 1 : pc) : T(0);
-    const T cs = hs ? ldc(c.cN, hs ? pc - nx : pc) : T(0);
-    return cheb_node(u, he ? ue : T(0), hw ? uw : T(0), hn ? un : T(0), hs ? us : T(0), yu, yd,
-                     ldc(c.d, pc), ldc(c.cE, pc), cw, ldc(c.cN, pc), cs, gu, gd, up, r,
-                     ldc(c.dinv, pc), a1, a2);
-  };
-
   // Prologue: z_j rows y0-2 .. y0 in slots 0 .. 2, coefficients of rows
   // y0-2 (slot 0) and y0-1 (slot 1), R and z_{j-1} of row y0-1.
   T rA[NPW], rAh = T(0), pA[NPW], pAh = T(0), rB[NPW];
@@ -1309,8 +1318,10 @@ __global__ __launch_bounds__(WG, sizeof(T) == 4 ? 4 : 2) void k_cheb2_strip(Coef
           const int64_t v = vidx(y, jc);
           gu2[i] = ldc(c.up, sl2[i]);
           gd2[i] = ldc(c.dn, sl2[i]);
-          if (gu2[i] != T(0)) zu2[i] = point(v + pd.plane, x0 + jc, y);
-          if (gd2[i] != T(0)) zd2[i] = point(v - pd.plane, x0 + jc, y);
+          if (gu2[i] != T(0))
+            zu2[i] = cheb_point<T, HAS_PREV>(c, pd, zin, zprev, R, v + pd.plane, x0 + jc, y, a1, a2);
+          if (gd2[i] != T(0))
+            zd2[i] = cheb_point<T, HAS_PREV>(c, pd, zin, zprev, R, v - pd.plane, x0 + jc, y, a1, a2);
         }
       }
     }
@@ -1379,6 +1390,401 @@ __global__ __launch_bounds__(WG, sizeof(T) == 4 ? 4 : 2) void k_cheb2_strip(Coef
   row(-2, std::false_type{});
   row(-1, std::false_type{});
   for (int s = 0; s < st.nrows; ++s) row(s, std::true_type{});
+}
+
+// TSV side buffers of a three-step pass (z_{j+1}, z_{j+2}, z_{j+3} from z_j,
+// z_{j-1}): the strip kernel's level 2 and level 3 need z_{j+1} and z_{j+2}
+// at the TSV partners of their nodes, in tiers other workgroups own.  Slot q
+// of block p has side row sbase + q - slot_begin.
+//   k_cheb_tsv1: z_{j+1} at every TSV node and its east, west, north and
+//                south neighbours (0 where the neighbour does not exist):
+//                TA[row][k][S], k = 0 (node), 1 (E), 2 (W), 3 (N), 4 (S);
+//   k_cheb_tsv2: z_{j+2} at every TSV node from TA: TB[row][S].
+// One wave per item, grid (items / 4, active blocks); no barriers.
+constexpr int TSV_WAVES = 4;
+
+template <typename T, bool HAS_PREV>
+__global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv1(Coef<T> c, Work wk,
+                                                             const int32_t* __restrict__ act,
+                                                             const T* __restrict__ zin,
+                                                             const T* __restrict__ zprev,
+                                                             const T* __restrict__ R,
+                                                             T* __restrict__ TA, T a1, T a2) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const PlanDesc pd = wk.plans[act[blockIdx.y]];
+  const int nsl = pd.slot_end - pd.slot_begin;
+  const int item = blockIdx.x * TSV_WAVES + w;
+  if (item >= 5 * nsl) return;
+  const int qi = item / 5, k = item % 5;
+  const int64_t loc = c.tnode[pd.slot_begin + qi] - pd.cbase;  // node within the stack
+  const int nx = pd.nx;
+  const int ny = (int)(pd.plane / pd.nx);
+  const int64_t rem = loc % pd.plane;
+  const int y = (int)(rem / nx), x = (int)(rem % nx);
+  const int dx = k == 1 ? 1 : k == 2 ? -1 : 0, dy = k == 3 ? 1 : k == 4 ? -1 : 0;
+  const int xn = x + dx, yn = y + dy;
+  T z = T(0);
+  if (xn >= 0 && xn < nx && yn >= 0 && yn < ny)
+    z = cheb_point<T, HAS_PREV>(c, pd, zin, zprev, R, pd.vbase + loc + dx + (int64_t)dy * nx, xn,
+                                yn, a1, a2);
+  TA[((pd.sbase + qi) * 5 + k) * S + lane] = z;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv2(Coef<T> c, Work wk,
+                                                             const int32_t* __restrict__ act,
+                                                             const T* __restrict__ zin,
+                                                             const T* __restrict__ R,
+                                                             const T* __restrict__ TA,
+                                                             T* __restrict__ TB, T b1, T b2) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const PlanDesc pd = wk.plans[act[blockIdx.y]];
+  const int nsl = pd.slot_end - pd.slot_begin;
+  const int qi = blockIdx.x * TSV_WAVES + w;
+  if (qi >= nsl) return;
+  const int q = pd.slot_begin + qi;
+  const int64_t u = c.tnode[q];  // coefficient index
+  const int64_t loc = u - pd.cbase;
+  const int64_t v = pd.vbase + loc;
+  const int nx = pd.nx;
+  const int64_t rem = loc % pd.plane;
+  const int y = (int)(rem / nx), x = (int)(rem % nx);
+  const int64_t a = (pd.sbase + qi) * 5;
+  const T gu = ldc(c.up, q), gd = ldc(c.dn, q);
+  // a partner's slot is the next / previous one (slots run over the tiers
+  // of a TSV column)
+  const T yu = gu != T(0) ? TA[(a + 5) * S + lane] : T(0);
+  const T yd = gd != T(0) ? TA[(a - 5) * S + lane] : T(0);
+  const T cw = x > 0 ? ldc(c.cE, x > 0 ? u - 1 : u) : T(0);
+  const T cs = y > 0 ? ldc(c.cN, y > 0 ? u - nx : u) : T(0);
+  TB[(pd.sbase + qi) * S + lane] =
+      cheb_node(TA[a * S + lane], TA[(a + 1) * S + lane], TA[(a + 2) * S + lane],
+                TA[(a + 3) * S + lane], TA[(a + 4) * S + lane], yu, yd, ldc(c.d, u),
+                ldc(c.cE, u), cw, ldc(c.cN, u), cs, gu, gd, zin[v * S + lane], R[v * S + lane],
+                ldc(c.dinv, u), b1, b2);
+}
+
+// Three Chebyshev steps in one pass over a strip (float32, block variant):
+//   z_{j+1} = step(z_j, z_{j-1}; a1, a2), z_{j+2} = step(z_{j+1}, z_j; b1, b2),
+//   z_{j+3} = step(z_{j+2}, z_{j+1}; c1, c2)
+// (z_{j-1} = 0 without HAS_PREV).  Three levels one row apart: level 1 forms
+// z_{j+1} on row y + 2 over the strip and two halo columns each side (from
+// z_j over three), level 2 forms z_{j+2} on row y + 1 over the strip and one
+// halo column each side, level 3 forms z_{j+3} on row y.  TSV partners:
+// z_j from global memory, z_{j+1} and z_{j+2} from the side buffers of
+// k_cheb_tsv1 / k_cheb_tsv2.  Writes z_{j+2} to outa and z_{j+3} to outb
+// (the next pass's z_{j-1} and z_j); neither may alias an input.  16 waves,
+// two nodes of a row each; about 96 KB of LDS, one workgroup per CU.
+constexpr int WG3 = 1024;
+constexpr int NPW3 = CH / (WG3 / 64);  // 2
+
+template <bool HAS_PREV>
+__global__ __launch_bounds__(WG3, 1) void k_cheb3_strip(Coef<float> c, Work wk,
+                                                        const float* __restrict__ zin,
+                                                        const float* __restrict__ zprev,
+                                                        const float* __restrict__ R,
+                                                        const float* __restrict__ TA,
+                                                        const float* __restrict__ TB,
+                                                        float* __restrict__ outa,
+                                                        float* __restrict__ outb, float a1,
+                                                        float a2, float b1, float b2, float c1,
+                                                        float c2) {
+  using T = float;
+  constexpr int NPW = NPW3;
+  constexpr int N1 = CH + 4;  // level-1 columns -2 .. CH + 1, index c + 2
+  constexpr int N2 = CH + 2;  // level-2 columns -1 .. CH, index c + 1
+  // z_j rows (columns -3 .. CH + 2 at index c + 3): row y + k in slot
+  // (s + 4 + k) % 4; z_{j+1} rows (index c + 2) and z_{j+2} rows (index
+  // c + 1): slot (s + 4 + k) % 3; coefficients of row y + k (index c + 2,
+  // cE c + 3): slot (s + 4 + k) % 4, cN: (s + 4 + k) % 5.  Accesses are one
+  // lane per column, so rows need no padding.
+  __shared__ T w1[4][CH + 6][S];
+  __shared__ T w2[3][N1][S];
+  __shared__ T w3[3][N2][S];
+  __shared__ T cd[4][N1], cdi[4][N1], ce[4][N1 + 1], cn[5][N1];
+  __shared__ int cslot[4][N1];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int sidx = wk.sid[logical_block(blockIdx.x, gridDim.x)];
+  const Strip st = wk.strips[sidx];
+  const PlanDesc pd = wk.plans[st.plan];
+  const int nx = pd.nx;
+  const int ny = (int)(pd.plane / pd.nx);
+  const int wdt = st.wdt;
+  const int x0 = st.x0;
+  const int64_t cofs = pd.cbase - pd.vbase;
+  auto col_ok = [&](int cc) { return x0 + cc >= 0 && x0 + cc < nx; };
+  auto row_ok = [&](int yy) { return yy >= 0 && yy < ny; };
+  auto vidx = [&](int yy, int cc) -> int64_t {
+    yy = min(max(yy, 0), ny - 1);
+    cc = min(max(cc, -x0), nx - 1 - x0);
+    return pd.vbase + st.lrow0 + (int64_t)(yy - st.y0) * nx + cc;
+  };
+  // side-buffer row of slot q (a slot of this block's stack)
+  auto srow = [&](int q) -> int64_t { return pd.sbase + (q - pd.slot_begin); };
+  // z_j row: nodes j = 2w + i; halo columns -3, -2, -1, wdt, wdt+1, wdt+2
+  // (waves 0-5; the east ones only for a full-width strip, which a ragged
+  // strip at the tier's east edge is not: its columns past wdt are zero)
+  const int hc1 = w < 3 ? w - 3 : wdt + (w - 3);
+  auto load_w1 = [&](int yy, T (&v)[NPW], T& h) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) v[i] = zin[vidx(yy, w * NPW + i) * S + lane];
+    if (w < 6) h = zin[vidx(yy, hc1) * S + lane];
+  };
+  auto store_w1 = [&](int slot, const T (&v)[NPW], T h, int yy) {
+    const bool in = row_ok(yy);
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      const int j = w * NPW + i;
+      w1[slot][j + 3][lane] = (in && j < wdt) ? v[i] : T(0);
+    }
+    if (w < 3 || (w < 6 && wdt == CH)) w1[slot][hc1 + 3][lane] = (in && col_ok(hc1)) ? h : T(0);
+  };
+  // level-1 halo node of waves 0-3: columns -2, -1, wdt, wdt + 1; level-2
+  // halo node of waves 1, 2: columns -1, wdt (the same waves, so R carries)
+  const int lc1 = w < 2 ? w - 2 : wdt + (w - 2);
+  auto load_pt = [&](const T* __restrict__ a, int yy, T (&v)[NPW], T& h) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) v[i] = a[vidx(yy, w * NPW + i) * S + lane];
+    if (w < 4) h = a[vidx(yy, lc1) * S + lane];
+  };
+  // Coefficients of one row, one value per thread t < 5 N1 + 1 (waves 0-2):
+  // d, cE (columns -3 .. CH + 1), cN, Dinv and the TSV slot on level-1 columns.
+  const int t = threadIdx.x;
+  const int kind = t < N1 ? 0 : t < 2 * N1 + 1 ? 1 : t < 3 * N1 + 1 ? 2 : t < 4 * N1 + 1 ? 3 : 4;
+  const int kcol = kind == 0   ? t - 2
+                   : kind == 1 ? t - N1 - 3
+                   : kind == 2 ? t - (2 * N1 + 1) - 2
+                   : kind == 3 ? t - (3 * N1 + 1) - 2
+                               : t - (4 * N1 + 1) - 2;
+  const T* csrc = kind == 0 ? c.d : kind == 1 ? c.cE : kind == 2 ? c.cN : c.dinv;
+  auto load_coef = [&](int yy, T& val, int& sl) {
+    if (w < 3) {
+      const int64_t ci = vidx(yy, kcol) + cofs;
+      val = csrc[ci];
+      sl = c.slot[ci];
+    }
+  };
+  auto store_coef = [&](int k, int kn, T val, int sl) {
+    const bool ok = col_ok(kcol);
+    if (kind == 0)
+      cd[k][kcol + 2] = ok ? val : T(0);
+    else if (kind == 1)
+      ce[k][kcol + 3] = ok ? val : T(0);
+    else if (kind == 2)
+      cn[kn][kcol + 2] = ok ? val : T(0);
+    else if (kind == 3)
+      cdi[k][kcol + 2] = ok ? val : T(0);
+    else if (t < 5 * N1 + 1)
+      cslot[k][kcol + 2] = ok ? sl : -1;
+  };
+
+  // Prologue: z_j rows y0-3 .. y0-1, coefficients of rows y0-3 and y0-2,
+  // R and z_{j-1} of row y0-2.
+  T rA[NPW], rAh = T(0), pA[NPW], pAh = T(0), rB[NPW], rBh = T(0), rC[NPW];
+  {
+    T v[NPW], h = T(0), cv = T(0);
+    int csl = -1;
+    for (int k = 1; k <= 3; ++k) {
+      load_w1(st.y0 - 4 + k, v, h);
+      store_w1(k % 4, v, h, st.y0 - 4 + k);
+    }
+    load_coef(st.y0 - 3, cv, csl);
+    store_coef(1, 1, cv, csl);
+    load_coef(st.y0 - 2, cv, csl);
+    store_coef(2, 2, cv, csl);
+    load_pt(R, st.y0 - 2, rA, rAh);
+    if (HAS_PREV) {
+      load_pt(zprev, st.y0 - 2, pA, pAh);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) pA[i] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) rB[i] = rC[i] = T(0);
+  }
+  __syncthreads();
+
+  // One row: level 1 on row y + 2, level 2 (L2) on row y + 1, level 3 (L3)
+  // on row y.
+  auto row = [&](int s, auto L2, auto L3) {
+    constexpr bool lvl2 = decltype(L2)::value;
+    constexpr bool lvl3 = decltype(L3)::value;
+    const int y = st.y0 + s;
+    const int r0 = s + 4;
+    const int sw1 = (r0 + 1) % 4, sw2 = (r0 + 2) % 4, sw3 = (r0 + 3) % 4, sw4 = r0 % 4;
+    const int q0 = r0 % 3, q1 = (r0 + 1) % 3, q2 = (r0 + 2) % 3;  // z_{j+1} rows y, y+1, y+2
+    const int e0 = r0 % 3, e1 = (r0 + 1) % 3, em = (r0 + 2) % 3;  // z_{j+2} rows y, y+1, y-1
+    const int k0 = r0 % 4, k1 = (r0 + 1) % 4, k2 = (r0 + 2) % 4, k3 = (r0 + 3) % 4;
+    const int n0 = r0 % 5, n1 = (r0 + 1) % 5, n2 = (r0 + 2) % 5, n3 = (r0 + 3) % 5,
+              nm = (r0 + 4) % 5;
+    // [A] TSV partner values of the three levels, before the next row's loads
+    T gu1[NPW + 1], gd1[NPW + 1], yu1[NPW + 1], yd1[NPW + 1];
+    {
+      int sl[NPW + 1];
+      bool any = false;
+#pragma unroll
+      for (int i = 0; i <= NPW; ++i) {
+        const int cc = i < NPW ? min(w * NPW + i, wdt - 1) : lc1;
+        sl[i] = (i < NPW || w < 4) ? __builtin_amdgcn_readfirstlane(cslot[k2][cc + 2]) : -1;
+        any |= sl[i] >= 0;
+      }
+      if (any) {
+#pragma unroll
+        for (int i = 0; i <= NPW; ++i) {
+          const int cc = i < NPW ? min(w * NPW + i, wdt - 1) : lc1;
+          const int64_t v = vidx(y + 2, cc);
+          const int q = max(sl[i], 0);
+          gu1[i] = sl[i] >= 0 ? ldc(c.up, q) : T(0);
+          gd1[i] = sl[i] >= 0 ? ldc(c.dn, q) : T(0);
+          yu1[i] = zin[(gu1[i] != T(0) ? v + pd.plane : v) * S + lane];
+          yd1[i] = zin[(gd1[i] != T(0) ? v - pd.plane : v) * S + lane];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i <= NPW; ++i) gu1[i] = gd1[i] = yu1[i] = yd1[i] = T(0);
+      }
+    }
+    T gu2[NPW + 1], gd2[NPW + 1], zu2[NPW + 1], zd2[NPW + 1];
+#pragma unroll
+    for (int i = 0; i <= NPW; ++i) gu2[i] = gd2[i] = zu2[i] = zd2[i] = T(0);
+    if constexpr (lvl2) {
+      const int lc2 = w == 1 ? -1 : wdt;
+      int sl[NPW + 1];
+      bool any = false;
+#pragma unroll
+      for (int i = 0; i <= NPW; ++i) {
+        const int cc = i < NPW ? min(w * NPW + i, wdt - 1) : lc2;
+        sl[i] = (i < NPW || w == 1 || w == 2) ? __builtin_amdgcn_readfirstlane(cslot[k1][cc + 2])
+                                              : -1;
+        any |= sl[i] >= 0;
+      }
+      if (any) {
+#pragma unroll
+        for (int i = 0; i <= NPW; ++i) {
+          if (sl[i] < 0) continue;
+          const int64_t a = srow(sl[i]) * 5;
+          gu2[i] = ldc(c.up, sl[i]);
+          gd2[i] = ldc(c.dn, sl[i]);
+          if (gu2[i] != T(0)) zu2[i] = TA[(a + 5) * S + lane];
+          if (gd2[i] != T(0)) zd2[i] = TA[(a - 5) * S + lane];
+        }
+      }
+    }
+    T gu3[NPW], gd3[NPW], zu3[NPW], zd3[NPW];
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) gu3[i] = gd3[i] = zu3[i] = zd3[i] = T(0);
+    if constexpr (lvl3) {
+      int sl[NPW];
+      bool any = false;
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        sl[i] = __builtin_amdgcn_readfirstlane(cslot[k0][min(w * NPW + i, wdt - 1) + 2]);
+        any |= sl[i] >= 0;
+      }
+      if (any) {
+#pragma unroll
+        for (int i = 0; i < NPW; ++i) {
+          if (sl[i] < 0) continue;
+          const int64_t a = srow(sl[i]);
+          gu3[i] = ldc(c.up, sl[i]);
+          gd3[i] = ldc(c.dn, sl[i]);
+          if (gu3[i] != T(0)) zu3[i] = TB[(a + 1) * S + lane];
+          if (gd3[i] != T(0)) zd3[i] = TB[(a - 1) * S + lane];
+        }
+      }
+    }
+    // [B] next row: z_j row y + 4, coefficients, R and z_{j-1} of row y + 3
+    T v1n[NPW], h1n = T(0), rN[NPW], rNh = T(0), pN[NPW], pNh = T(0), cvN = T(0);
+    int cslN = -1;
+    load_w1(y + 4, v1n, h1n);
+    load_coef(y + 3, cvN, cslN);
+    load_pt(R, y + 3, rN, rNh);
+    if (HAS_PREV) load_pt(zprev, y + 3, pN, pNh);
+    // [C] level 1: z_{j+1} on row y + 2 (columns -2 .. wdt + 1)
+    {
+      const bool in = row_ok(y + 2);
+#pragma unroll
+      for (int i = 0; i <= NPW; ++i) {
+        if (i == NPW && w >= 4) break;
+        const int j = i < NPW ? w * NPW + i : lc1;
+        const int cc = i < NPW ? min(j, wdt - 1) : lc1;
+        const T z = cheb_node(w1[sw2][cc + 3][lane], w1[sw2][cc + 4][lane], w1[sw2][cc + 2][lane],
+                              w1[sw3][cc + 3][lane], w1[sw1][cc + 3][lane], yu1[i], yd1[i],
+                              cd[k2][cc + 2], ce[k2][cc + 3], ce[k2][cc + 2], cn[n2][cc + 2],
+                              cn[n1][cc + 2], gu1[i], gd1[i], i < NPW ? pA[i] : pAh,
+                              i < NPW ? rA[i] : rAh, cdi[k2][cc + 2], a1, a2);
+        const bool ok = in && (i < NPW ? j < wdt : col_ok(lc1));
+        // east halo columns only for a full-width strip
+        if (i < NPW || w < 2 || wdt == CH) w2[q2][j + 2][lane] = ok ? z : T(0);
+      }
+    }
+    __syncthreads();
+    // [D] level 2: z_{j+2} on row y + 1 (columns -1 .. wdt)
+    T z2[NPW];
+    if constexpr (lvl2) {
+      const bool in = row_ok(y + 1);
+      const int lc2 = w == 1 ? -1 : wdt;
+#pragma unroll
+      for (int i = 0; i <= NPW; ++i) {
+        if (i == NPW && w != 1 && w != 2) break;
+        const int j = i < NPW ? w * NPW + i : lc2;
+        const int cc = i < NPW ? min(j, wdt - 1) : lc2;
+        const T z = cheb_node(w2[q1][cc + 2][lane], w2[q1][cc + 3][lane], w2[q1][cc + 1][lane],
+                              w2[q2][cc + 2][lane], w2[q0][cc + 2][lane], zu2[i], zd2[i],
+                              cd[k1][cc + 2], ce[k1][cc + 3], ce[k1][cc + 2], cn[n1][cc + 2],
+                              cn[n0][cc + 2], gu2[i], gd2[i], w1[sw1][cc + 3][lane],
+                              i < NPW ? rB[i] : rBh, cdi[k1][cc + 2], b1, b2);
+        const bool ok = in && (i < NPW ? j < wdt : col_ok(lc2));
+        if (i < NPW || w == 1 || wdt == CH) w3[e1][j + 1][lane] = ok ? z : T(0);
+        if (i < NPW) z2[i] = z;
+      }
+    }
+    __syncthreads();
+    // [E] level 3: z_{j+3} on row y
+    if constexpr (lvl3) {
+      const int64_t obase = pd.vbase + st.lrow0 + (int64_t)s * nx;
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        // nodes past a ragged strip's width repeat the last node
+        const int jc = min(w * NPW + i, wdt - 1);
+        const T z = cheb_node(w3[e0][jc + 1][lane], w3[e0][jc + 2][lane], w3[e0][jc][lane],
+                              w3[e1][jc + 1][lane], w3[em][jc + 1][lane], zu3[i], zd3[i],
+                              cd[k0][jc + 2], ce[k0][jc + 3], ce[k0][jc + 2], cn[n0][jc + 2],
+                              cn[nm][jc + 2], gu3[i], gd3[i], w2[q0][jc + 2][lane], rC[i],
+                              cdi[k0][jc + 2], c1, c2);
+        outb[(obase + jc) * S + lane] = z;
+      }
+    }
+    // the next row into the slots of rows y (z_j), y - 1 (coefficients) and
+    // y - 2 (cN), which no level of this row reads
+    store_w1(sw4, v1n, h1n, y + 4);
+    store_coef(k3, n3, cvN, cslN);
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      rC[i] = rB[i];
+      rB[i] = rA[i];
+      rA[i] = rN[i];
+      pA[i] = HAS_PREV ? pN[i] : T(0);
+    }
+    rBh = rAh;
+    rAh = rNh;
+    pAh = pNh;
+    // z_{j+2} of row y + 1 if it is a row of this strip
+    if (lvl2 && s + 1 >= 0 && s + 1 < st.nrows) {
+      const int64_t b1row = pd.vbase + st.lrow0 + (int64_t)(s + 1) * nx;
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) outa[(b1row + min(w * NPW + i, wdt - 1)) * S + lane] = z2[i];
+    }
+    __syncthreads();
+  };
+  row(-4, std::false_type{}, std::false_type{});
+  row(-3, std::false_type{}, std::false_type{});
+  row(-2, std::true_type{}, std::false_type{});
+  row(-1, std::true_type{}, std::false_type{});
+  for (int s = 0; s < st.nrows; ++s) row(s, std::true_type{}, std::true_type{});
 }
 
 // C = Xa^T (G Xb) over all nodes of a block (pair resistances: the
@@ -1970,10 +2376,11 @@ static void reduce(const SolveBuffers& b, int m0, int nmat, int len, hipStream_t
                      b.W, b.work.plans, b.act, m0, nmat, len, strips ? 1 : 0);
 }
 
-// Chebyshev steps j = 1 .. cheb_k - 1 from z_1 in Za, two per pass where
-// two remain (one pass reads z_j, z_{j-1} and writes z_{j+1}, z_{j+2} to
-// two arrays that hold neither); the iterates rotate over Za .. Zd.  The
-// last step writes to `last` if given.  Returns the array that holds Z.
+// Chebyshev steps j = 1 .. cheb_k - 1 from z_1 in Za: three per pass while
+// three remain (float32), then two per pass while two remain, then one.  A pass reads z_j, z_{j-1} and
+// writes its last two iterates (or one) to arrays that hold neither; the
+// iterates rotate over Za .. Zd.  The last step writes to `last` if given.
+// Returns the array that holds Z.
 template <typename T>
 static T* cheb_steps(const Coef<T>& c, const SolveBuffers& b, hipStream_t st, T* last) {
   const dim3 g(b.n_strips), blk(WG);
@@ -1985,12 +2392,52 @@ static T* cheb_steps(const Coef<T>& c, const SolveBuffers& b, hipStream_t st, T*
       if (i != cur && i != prev && i != skip) return i;
     return -1;
   };
+  auto coef = [&](int j, T& x1, T& x2) {
+    x1 = (T)b.cheb_a1[j];
+    x2 = (T)b.cheb_a2[j];
+  };
   int j = 1;
-  while (j + 1 < b.cheb_k) {
+  if constexpr (sizeof(T) == 4) {
+    while (j + 2 < b.cheb_k && b.TA) {
+      const int f1 = free_slot(-1), f2 = free_slot(f1);
+      T* o2 = (j + 3 == b.cheb_k && last) ? last : buf[f2];
+      T a1, a2, b1, b2, c1, c2;
+      coef(j, a1, a2);
+      coef(j + 1, b1, b2);
+      coef(j + 2, c1, c2);
+      const T* zp = prev < 0 ? nullptr : buf[prev];
+      if (b.max_slots > 0) {
+        const dim3 g1((5 * b.max_slots + TSV_WAVES - 1) / TSV_WAVES, b.n_act);
+        const dim3 g2((b.max_slots + TSV_WAVES - 1) / TSV_WAVES, b.n_act);
+        if (prev < 0)
+          hipLaunchKernelGGL((k_cheb_tsv1<T, false>), g1, dim3(64 * TSV_WAVES), 0, st, c, b.work,
+                             b.act, (const T*)buf[cur], zp, R, (T*)b.TA, a1, a2);
+        else
+          hipLaunchKernelGGL((k_cheb_tsv1<T, true>), g1, dim3(64 * TSV_WAVES), 0, st, c, b.work,
+                             b.act, (const T*)buf[cur], zp, R, (T*)b.TA, a1, a2);
+        hipLaunchKernelGGL((k_cheb_tsv2<T>), g2, dim3(64 * TSV_WAVES), 0, st, c, b.work, b.act,
+                           (const T*)buf[cur], R, (const T*)b.TA, (T*)b.TB, b1, b2);
+      }
+      if (prev < 0)
+        hipLaunchKernelGGL((k_cheb3_strip<false>), g, dim3(WG3), 0, st, c, b.work,
+                           (const T*)buf[cur], zp, R, (const T*)b.TA, (const T*)b.TB, buf[f1],
+                           o2, a1, a2, b1, b2, c1, c2);
+      else
+        hipLaunchKernelGGL((k_cheb3_strip<true>), g, dim3(WG3), 0, st, c, b.work,
+                           (const T*)buf[cur], zp, R, (const T*)b.TA, (const T*)b.TB, buf[f1],
+                           o2, a1, a2, b1, b2, c1, c2);
+      j += 3;
+      if (o2 == last) return last;
+      prev = f1;
+      cur = f2;
+    }
+  }
+  while (j + 1 < b.cheb_k) {  // two steps per pass (float64 throughout)
     const int f1 = free_slot(-1), f2 = free_slot(f1);
     T* o2 = (j + 2 == b.cheb_k && last) ? last : buf[f2];
-    const T a1 = (T)b.cheb_a1[j], a2 = (T)b.cheb_a2[j];
-    const T b1 = (T)b.cheb_a1[j + 1], b2 = (T)b.cheb_a2[j + 1];
+    T a1, a2, b1, b2;
+    coef(j, a1, a2);
+    coef(j + 1, b1, b2);
     if (prev < 0)
       hipLaunchKernelGGL((k_cheb2_strip<T, false>), g, blk, 0, st, c, b.work, (const T*)buf[cur],
                          (const T*)nullptr, R, buf[f1], o2, a1, a2, b1, b2);
@@ -2004,7 +2451,8 @@ static T* cheb_steps(const Coef<T>& c, const SolveBuffers& b, hipStream_t st, T*
   }
   if (j < b.cheb_k) {  // one step left
     T* o = last ? last : buf[free_slot(-1)];
-    const T a1 = (T)b.cheb_a1[j], a2 = (T)b.cheb_a2[j];
+    T a1, a2;
+    coef(j, a1, a2);
     if (prev < 0)
       hipLaunchKernelGGL((k_cheb_strip<T, false>), g, blk, 0, st, c, b.work, (const T*)buf[cur],
                          (const T*)nullptr, R, o, a1, a2);
@@ -2096,11 +2544,12 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
   // Z = M^-1 R and W3 = Q^T Z (polynomial preconditioner)
   if (ev) hipEventRecord(ev[6], st);
   const T* Z = R;
-  if (cheb) {
-    Z = cheb_steps<T>(c, b, st, nullptr);
-    hipLaunchKernelGGL((k_gram_ab<T, false>), g, blk, 0, st, c, wk, (const T*)Q, Z, b.part, 2);
-  }
+  if (cheb) Z = cheb_steps<T>(c, b, st, nullptr);
   if (ev) hipEventRecord(ev[7], st);
+  if (ev) hipEventRecord(ev[8], st);
+  if (cheb)
+    hipLaunchKernelGGL((k_gram_ab<T, false>), g, blk, 0, st, c, wk, (const T*)Q, Z, b.part, 2);
+  if (ev) hipEventRecord(ev[9], st);
   reduce(b, 2, 1, len, st);
   hipLaunchKernelGGL((k_small2<T>), gs, bs, 0, st, b.W, b.act, b.winv, (T*)b.delta, b.state, di);
   if (ev) hipEventRecord(ev[4], st);

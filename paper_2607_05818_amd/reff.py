@@ -76,8 +76,8 @@ class reff_solve_stats(C.Structure):
     _fields_ = [
         ("n_solved", C.c_int64), ("n_unconverged", C.c_int64), ("iters_max", C.c_int32),
         ("ir_steps", C.c_int32), ("seconds", C.c_double), ("est_max_rel_err", C.c_double),
-        ("iters_total", C.c_int64), ("kernel_ms", C.c_double * 4),
-        ("kernel_launches", C.c_int64 * 4), ("kernel_rows", C.c_int64 * 4),
+        ("iters_total", C.c_int64), ("kernel_ms", C.c_double * 5),
+        ("kernel_launches", C.c_int64 * 5), ("kernel_rows", C.c_int64 * 5),
         ("screened", C.c_int32), ("spot_max_rel_err", C.c_double),
     ]
 

@@ -46,10 +46,12 @@ def test_degree_out_of_range_rejected():
 
 
 @pytest.mark.parametrize("kind", ["ragged_square", "ragged_rect"])
-def test_paired_steps_on_ragged_strips(kind):
-    """Degrees whose steps run as fused pairs (3: one pair; 5: two pairs;
-    6: two pairs and a single step) on tiers whose width is not a multiple
-    of the strip width, with TSVs: every result within the mixed bar."""
+def test_fused_steps_on_ragged_strips(kind):
+    """Degrees whose steps run as fused passes (3: a pair; 4: a triple; 5: a
+    triple and a single step; 6: a triple and a pair; 7: two triples) on
+    tiers whose width is not a multiple of the strip width, with TSVs: every
+    result within the mixed bar.  Float64 runs pairs (3: one pair; 6: two
+    pairs and a single step)."""
     reff = _reff()
     if kind == "ragged_square":
         d = gen.config2(side=100, n_tsv=64, sigma=10.0)
@@ -58,11 +60,13 @@ def test_paired_steps_on_ragged_strips(kind):
     nodes = gen.sample_free_nodes(d, 64, 5)
     want = ro.diag(d, nodes)
     h = reff.reff_build_pdn(d)
-    for k in (3, 5, 6):
-        _say("paired precond degree", k, kind)
+    for k in (3, 4, 5, 6, 7):
+        _say("fused precond degree", k, kind)
         got, st = reff.reff_solve_diag(h, nodes, precision=1, rel_tol=1e-5, precond_degree=k)
         err = float(np.max(np.abs(got - want) / want))
         print("degree", k, "iters", st["iters_total"], "err", err, flush=True)
         assert err <= 1e-3
-    got, _ = reff.reff_solve_diag(h, nodes, precision=0, rel_tol=1e-9, precond_degree=3)
-    assert float(np.max(np.abs(got - want) / want)) <= 1e-6
+    for k in (3, 6):
+        _say("float64 precond degree", k, kind)
+        got, _ = reff.reff_solve_diag(h, nodes, precision=0, rel_tol=1e-9, precond_degree=k)
+        assert float(np.max(np.abs(got - want) / want)) <= 1e-6
