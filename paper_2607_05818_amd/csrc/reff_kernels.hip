@@ -905,21 +905,33 @@ __global__ __launch_bounds__(WG, 4) void k_gram_ab(Coef<T> c, Work wk, const T* 
 }
 
 // One Chebyshev step at one node: u + a1 (u - up) + a2 Dinv (r - (G u)_v),
-// (G u)_v = d u - cE ue - cW uw - cN un - cS us - gU yu - gD yd.  Every
-// kernel that forms a Chebyshev iterate calls this, with explicit fused
-// multiply-adds, so a value recomputed by another workgroup (a strip halo,
-// a TSV partner) is bitwise the value its owner writes.
+// (G u)_v = d u - cE ue - cW uw - cN un - cS us - t, where t = gU yu + gD yd
+// is the TSV term (tsv_term).  Every kernel that forms a Chebyshev iterate
+// goes through these two functions, with explicit fused multiply-adds, so a
+// value recomputed by another workgroup (a strip halo, a TSV partner) is
+// bitwise the value its owner writes.
 template <typename T>
-__device__ __forceinline__ T cheb_node(T u, T ue, T uw, T un, T us, T yu, T yd, T d, T ce, T cw,
-                                       T cn, T cs, T gu, T gd, T up, T r, T dinv, T a1, T a2) {
+__device__ __forceinline__ T tsv_term(T gu, T yu, T gd, T yd) {
+  return fma(gu, yu, gd * yd);
+}
+
+template <typename T>
+__device__ __forceinline__ T cheb_node_t(T u, T ue, T uw, T un, T us, T t, T d, T ce, T cw, T cn,
+                                         T cs, T up, T r, T dinv, T a1, T a2) {
   T g = d * u;
   g = fma(-ce, ue, g);
   g = fma(-cw, uw, g);
   g = fma(-cn, un, g);
   g = fma(-cs, us, g);
-  g = fma(-gu, yu, g);
-  g = fma(-gd, yd, g);
+  g = g - t;
   return fma(a2 * dinv, r - g, fma(a1, u - up, u));
+}
+
+template <typename T>
+__device__ __forceinline__ T cheb_node(T u, T ue, T uw, T un, T us, T yu, T yd, T d, T ce, T cw,
+                                       T cn, T cs, T gu, T gd, T up, T r, T dinv, T a1, T a2) {
+  return cheb_node_t(u, ue, uw, un, us, tsv_term(gu, yu, gd, yd), d, ce, cw, cn, cs, up, r, dinv,
+                     a1, a2);
 }
 
 // z_{j+1} at vector row p, node (xg, yy) of its tier, from global memory:
@@ -1472,16 +1484,20 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv2(Coef<T> c, Work wk
 // (z_{j-1} = 0 without HAS_PREV).  Three levels one row apart: level 1 forms
 // z_{j+1} on row y + 2 over the strip and two halo columns each side (from
 // z_j over three), level 2 forms z_{j+2} on row y + 1 over the strip and one
-// halo column each side, level 3 forms z_{j+3} on row y.  TSV partners:
+// halo column each side, level 3 forms z_{j+3} on row y.  A wave owns its
+// columns at every level (nodes 4w .. 4w+3; waves 0-3 also one halo column,
+// the same at levels 1 and 2), so the values above and below a node come
+// from the wave's own registers; LDS holds one row per level for the east
+// and west neighbours, double-buffered: each level reads the row written in
+// the previous iteration, and one barrier per row suffices.  TSV partners:
 // z_j from global memory, z_{j+1} and z_{j+2} from the side buffers of
 // k_cheb_tsv1 / k_cheb_tsv2.  Writes z_{j+2} to outa and z_{j+3} to outb
-// (the next pass's z_{j-1} and z_j); neither may alias an input.  16 waves,
-// two nodes of a row each; about 96 KB of LDS, one workgroup per CU.
-constexpr int WG3 = 1024;
-constexpr int NPW3 = CH / (WG3 / 64);  // 2
+// (the next pass's z_{j-1} and z_j); neither may alias an input.
+constexpr int WG3 = 512;
+constexpr int NPW3 = CH / (WG3 / 64);  // 4
 
 template <bool HAS_PREV>
-__global__ __launch_bounds__(WG3, 1) void k_cheb3_strip(Coef<float> c, Work wk,
+__global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
                                                         const float* __restrict__ zin,
                                                         const float* __restrict__ zprev,
                                                         const float* __restrict__ R,
@@ -1493,16 +1509,14 @@ __global__ __launch_bounds__(WG3, 1) void k_cheb3_strip(Coef<float> c, Work wk,
                                                         float c2) {
   using T = float;
   constexpr int NPW = NPW3;
-  constexpr int N1 = CH + 4;  // level-1 columns -2 .. CH + 1, index c + 2
-  constexpr int N2 = CH + 2;  // level-2 columns -1 .. CH, index c + 1
-  // z_j rows (columns -3 .. CH + 2 at index c + 3): row y + k in slot
-  // (s + 4 + k) % 4; z_{j+1} rows (index c + 2) and z_{j+2} rows (index
-  // c + 1): slot (s + 4 + k) % 3; coefficients of row y + k (index c + 2,
-  // cE c + 3): slot (s + 4 + k) % 4, cN: (s + 4 + k) % 5.  Accesses are one
-  // lane per column, so rows need no padding.
-  __shared__ T w1[4][CH + 6][S];
-  __shared__ T w2[3][N1][S];
-  __shared__ T w3[3][N2][S];
+  constexpr int N1 = CH + 4;  // coefficient columns -2 .. CH + 1, index c + 2 (cE: c + 3)
+  // East / west neighbour rows, slot (s + 4) & 1 read in iteration s: z_j
+  // row y + 2 (columns -3 .. CH + 2, index c + 3), z_{j+1} row y + 1 (index
+  // c + 2), z_{j+2} row y (index c + 1); one lane per column, no padding.
+  __shared__ T h1[2][CH + 6][S];
+  __shared__ T h2[2][CH + 4][S];
+  __shared__ T h3[2][CH + 2][S];
+  // coefficients of row y + k in slot (s + 4 + k) % 4, cN in (s + 4 + k) % 5
   __shared__ T cd[4][N1], cdi[4][N1], ce[4][N1 + 1], cn[5][N1];
   __shared__ int cslot[4][N1];
   const int lane = threadIdx.x & 63;
@@ -1522,36 +1536,44 @@ __global__ __launch_bounds__(WG3, 1) void k_cheb3_strip(Coef<float> c, Work wk,
     cc = min(max(cc, -x0), nx - 1 - x0);
     return pd.vbase + st.lrow0 + (int64_t)(yy - st.y0) * nx + cc;
   };
-  // side-buffer row of slot q (a slot of this block's stack)
   auto srow = [&](int q) -> int64_t { return pd.sbase + (q - pd.slot_begin); };
-  // z_j row: nodes j = 2w + i; halo columns -3, -2, -1, wdt, wdt+1, wdt+2
-  // (waves 0-5; the east ones only for a full-width strip, which a ragged
-  // strip at the tier's east edge is not: its columns past wdt are zero)
-  const int hc1 = w < 3 ? w - 3 : wdt + (w - 3);
-  auto load_w1 = [&](int yy, T (&v)[NPW], T& h) {
+  // halo column of waves 0-3 (levels 1 and 2; level 2 uses waves 1, 2):
+  // -2, -1, wdt, wdt + 1; outer z_j column of waves 4, 5: -3, wdt + 2.
+  // Columns east of a ragged strip (which ends at the tier's east edge) are
+  // outside the tier: only full-width strips write the east ones.
+  const bool has_h = w < 4;
+  const int hc = w < 2 ? w - 2 : wdt + (w - 2);
+  const bool has_o = w == 4 || w == 5;
+  const int oc = w == 4 ? -3 : wdt + 2;
+  const bool east_ok = wdt == CH;
+  // Node i of this wave at a level: column cc(i) (nodes past a ragged
+  // strip's width repeat the last node: same inputs, same value).
+  auto ccol = [&](int i) { return i < NPW ? min(w * NPW + i, wdt - 1) : hc; };
+  // z_j row yy on this wave's columns (raw loads; rows outside the tier are
+  // zeroed when the row enters the register history)
+  auto load_zj = [&](int yy, T (&v)[NPW + 1], T& o) {
 #pragma unroll
     for (int i = 0; i < NPW; ++i) v[i] = zin[vidx(yy, w * NPW + i) * S + lane];
-    if (w < 6) h = zin[vidx(yy, hc1) * S + lane];
+    if (has_h) v[NPW] = zin[vidx(yy, hc) * S + lane];
+    if (has_o) o = zin[vidx(yy, oc) * S + lane];
   };
-  auto store_w1 = [&](int slot, const T (&v)[NPW], T h, int yy) {
+  auto load_pt = [&](const T* __restrict__ a, int yy, T (&v)[NPW + 1]) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) v[i] = a[vidx(yy, w * NPW + i) * S + lane];
+    if (has_h) v[NPW] = a[vidx(yy, hc) * S + lane];
+  };
+  auto put_h1 = [&](int slot, const T (&v)[NPW + 1], T o, int yy) {
     const bool in = row_ok(yy);
 #pragma unroll
     for (int i = 0; i < NPW; ++i) {
       const int j = w * NPW + i;
-      w1[slot][j + 3][lane] = (in && j < wdt) ? v[i] : T(0);
+      h1[slot][j + 3][lane] = (in && j < wdt) ? v[i] : T(0);
     }
-    if (w < 3 || (w < 6 && wdt == CH)) w1[slot][hc1 + 3][lane] = (in && col_ok(hc1)) ? h : T(0);
-  };
-  // level-1 halo node of waves 0-3: columns -2, -1, wdt, wdt + 1; level-2
-  // halo node of waves 1, 2: columns -1, wdt (the same waves, so R carries)
-  const int lc1 = w < 2 ? w - 2 : wdt + (w - 2);
-  auto load_pt = [&](const T* __restrict__ a, int yy, T (&v)[NPW], T& h) {
-#pragma unroll
-    for (int i = 0; i < NPW; ++i) v[i] = a[vidx(yy, w * NPW + i) * S + lane];
-    if (w < 4) h = a[vidx(yy, lc1) * S + lane];
+    if (has_h && (w < 2 || east_ok)) h1[slot][hc + 3][lane] = (in && col_ok(hc)) ? v[NPW] : T(0);
+    if (has_o && (w == 4 || east_ok)) h1[slot][oc + 3][lane] = (in && col_ok(oc)) ? o : T(0);
   };
   // Coefficients of one row, one value per thread t < 5 N1 + 1 (waves 0-2):
-  // d, cE (columns -3 .. CH + 1), cN, Dinv and the TSV slot on level-1 columns.
+  // d, cE (columns -3 .. CH + 1), cN, Dinv and the TSV slot.
   const int t = threadIdx.x;
   const int kind = t < N1 ? 0 : t < 2 * N1 + 1 ? 1 : t < 3 * N1 + 1 ? 2 : t < 4 * N1 + 1 ? 3 : 4;
   const int kcol = kind == 0   ? t - 2
@@ -1581,84 +1603,83 @@ __global__ __launch_bounds__(WG3, 1) void k_cheb3_strip(Coef<float> c, Work wk,
       cslot[k][kcol + 2] = ok ? sl : -1;
   };
 
-  // Prologue: z_j rows y0-3 .. y0-1, coefficients of rows y0-3 and y0-2,
-  // R and z_{j-1} of row y0-2.
-  T rA[NPW], rAh = T(0), pA[NPW], pAh = T(0), rB[NPW], rBh = T(0), rC[NPW];
+  // Register history: z_j rows y+1, y+2, y+3 (zA[0..2]), z_{j+1} rows y,
+  // y+1 (z1h), z_{j+2} rows y-1, y (z2h), R rows y+2 (rA), y+1 (rB), y (rC),
+  // z_{j-1} row y+2 (pA); outer z_j column: row y+3 (oA).
+  T zA[3][NPW + 1], z1h[2][NPW + 1], z2h[2][NPW], rA[NPW + 1], rB[NPW + 1], rC[NPW],
+      pA[NPW + 1], oA = T(0);
+#pragma unroll
+  for (int i = 0; i <= NPW; ++i) {
+    z1h[0][i] = z1h[1][i] = rB[i] = pA[i] = T(0);
+    if (i < NPW) z2h[0][i] = z2h[1][i] = rC[i] = T(0);
+  }
+  // Prologue (iteration s = -4 reads row y0 - 2 as its row y + 2): z_j rows
+  // y0-3 .. y0-1, the east / west row y0-2, coefficients of rows y0-3 and
+  // y0-2, R and z_{j-1} of row y0-2.
   {
-    T v[NPW], h = T(0), cv = T(0);
+    T o = T(0), cv = T(0);
     int csl = -1;
-    for (int k = 1; k <= 3; ++k) {
-      load_w1(st.y0 - 4 + k, v, h);
-      store_w1(k % 4, v, h, st.y0 - 4 + k);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      load_zj(st.y0 - 3 + k, zA[k], o);
+      const bool in = row_ok(st.y0 - 3 + k);
+#pragma unroll
+      for (int i = 0; i <= NPW; ++i) zA[k][i] = in ? zA[k][i] : T(0);
+      if (k == 1) put_h1(0, zA[1], o, st.y0 - 2);
+      if (k == 2) oA = o;
     }
     load_coef(st.y0 - 3, cv, csl);
     store_coef(1, 1, cv, csl);
     load_coef(st.y0 - 2, cv, csl);
     store_coef(2, 2, cv, csl);
-    load_pt(R, st.y0 - 2, rA, rAh);
-    if (HAS_PREV) {
-      load_pt(zprev, st.y0 - 2, pA, pAh);
-    } else {
-#pragma unroll
-      for (int i = 0; i < NPW; ++i) pA[i] = T(0);
-    }
-#pragma unroll
-    for (int i = 0; i < NPW; ++i) rB[i] = rC[i] = T(0);
+    load_pt(R, st.y0 - 2, rA);
+    if (HAS_PREV) load_pt(zprev, st.y0 - 2, pA);
   }
   __syncthreads();
 
-  // One row: level 1 on row y + 2, level 2 (L2) on row y + 1, level 3 (L3)
-  // on row y.
   auto row = [&](int s, auto L2, auto L3) {
     constexpr bool lvl2 = decltype(L2)::value;
     constexpr bool lvl3 = decltype(L3)::value;
     const int y = st.y0 + s;
     const int r0 = s + 4;
-    const int sw1 = (r0 + 1) % 4, sw2 = (r0 + 2) % 4, sw3 = (r0 + 3) % 4, sw4 = r0 % 4;
-    const int q0 = r0 % 3, q1 = (r0 + 1) % 3, q2 = (r0 + 2) % 3;  // z_{j+1} rows y, y+1, y+2
-    const int e0 = r0 % 3, e1 = (r0 + 1) % 3, em = (r0 + 2) % 3;  // z_{j+2} rows y, y+1, y-1
+    const int hs = r0 & 1;  // neighbour rows read now; hs ^ 1 written now
     const int k0 = r0 % 4, k1 = (r0 + 1) % 4, k2 = (r0 + 2) % 4, k3 = (r0 + 3) % 4;
     const int n0 = r0 % 5, n1 = (r0 + 1) % 5, n2 = (r0 + 2) % 5, n3 = (r0 + 3) % 5,
               nm = (r0 + 4) % 5;
-    // [A] TSV partner values of the three levels, before the next row's loads
-    T gu1[NPW + 1], gd1[NPW + 1], yu1[NPW + 1], yd1[NPW + 1];
+    // [A] TSV terms of the three levels (rows y+2, y+1, y), before the next
+    // row's loads; a wave with a TSV node waits for its partners here.
+    T t1[NPW + 1], t2[NPW + 1], t3[NPW];
     {
       int sl[NPW + 1];
       bool any = false;
 #pragma unroll
       for (int i = 0; i <= NPW; ++i) {
-        const int cc = i < NPW ? min(w * NPW + i, wdt - 1) : lc1;
-        sl[i] = (i < NPW || w < 4) ? __builtin_amdgcn_readfirstlane(cslot[k2][cc + 2]) : -1;
+        sl[i] = (i < NPW || has_h) ? __builtin_amdgcn_readfirstlane(cslot[k2][ccol(i) + 2]) : -1;
         any |= sl[i] >= 0;
+        t1[i] = T(0);
       }
       if (any) {
 #pragma unroll
         for (int i = 0; i <= NPW; ++i) {
-          const int cc = i < NPW ? min(w * NPW + i, wdt - 1) : lc1;
-          const int64_t v = vidx(y + 2, cc);
-          const int q = max(sl[i], 0);
-          gu1[i] = sl[i] >= 0 ? ldc(c.up, q) : T(0);
-          gd1[i] = sl[i] >= 0 ? ldc(c.dn, q) : T(0);
-          yu1[i] = zin[(gu1[i] != T(0) ? v + pd.plane : v) * S + lane];
-          yd1[i] = zin[(gd1[i] != T(0) ? v - pd.plane : v) * S + lane];
+          if (sl[i] < 0) continue;
+          const int64_t v = vidx(y + 2, ccol(i));
+          const T gu = ldc(c.up, sl[i]), gd = ldc(c.dn, sl[i]);
+          const T yu = zin[(gu != T(0) ? v + pd.plane : v) * S + lane];
+          const T yd = zin[(gd != T(0) ? v - pd.plane : v) * S + lane];
+          t1[i] = tsv_term(gu, yu, gd, yd);
         }
-      } else {
-#pragma unroll
-        for (int i = 0; i <= NPW; ++i) gu1[i] = gd1[i] = yu1[i] = yd1[i] = T(0);
       }
     }
-    T gu2[NPW + 1], gd2[NPW + 1], zu2[NPW + 1], zd2[NPW + 1];
 #pragma unroll
-    for (int i = 0; i <= NPW; ++i) gu2[i] = gd2[i] = zu2[i] = zd2[i] = T(0);
+    for (int i = 0; i <= NPW; ++i) t2[i] = T(0);
     if constexpr (lvl2) {
-      const int lc2 = w == 1 ? -1 : wdt;
       int sl[NPW + 1];
       bool any = false;
 #pragma unroll
       for (int i = 0; i <= NPW; ++i) {
-        const int cc = i < NPW ? min(w * NPW + i, wdt - 1) : lc2;
-        sl[i] = (i < NPW || w == 1 || w == 2) ? __builtin_amdgcn_readfirstlane(cslot[k1][cc + 2])
-                                              : -1;
+        sl[i] = (i < NPW || w == 1 || w == 2)
+                    ? __builtin_amdgcn_readfirstlane(cslot[k1][ccol(i) + 2])
+                    : -1;
         any |= sl[i] >= 0;
       }
       if (any) {
@@ -1666,22 +1687,21 @@ __global__ __launch_bounds__(WG3, 1) void k_cheb3_strip(Coef<float> c, Work wk,
         for (int i = 0; i <= NPW; ++i) {
           if (sl[i] < 0) continue;
           const int64_t a = srow(sl[i]) * 5;
-          gu2[i] = ldc(c.up, sl[i]);
-          gd2[i] = ldc(c.dn, sl[i]);
-          if (gu2[i] != T(0)) zu2[i] = TA[(a + 5) * S + lane];
-          if (gd2[i] != T(0)) zd2[i] = TA[(a - 5) * S + lane];
+          const T gu = ldc(c.up, sl[i]), gd = ldc(c.dn, sl[i]);
+          const T zu = gu != T(0) ? TA[(a + 5) * S + lane] : T(0);
+          const T zd = gd != T(0) ? TA[(a - 5) * S + lane] : T(0);
+          t2[i] = tsv_term(gu, zu, gd, zd);
         }
       }
     }
-    T gu3[NPW], gd3[NPW], zu3[NPW], zd3[NPW];
 #pragma unroll
-    for (int i = 0; i < NPW; ++i) gu3[i] = gd3[i] = zu3[i] = zd3[i] = T(0);
+    for (int i = 0; i < NPW; ++i) t3[i] = T(0);
     if constexpr (lvl3) {
       int sl[NPW];
       bool any = false;
 #pragma unroll
       for (int i = 0; i < NPW; ++i) {
-        sl[i] = __builtin_amdgcn_readfirstlane(cslot[k0][min(w * NPW + i, wdt - 1) + 2]);
+        sl[i] = __builtin_amdgcn_readfirstlane(cslot[k0][ccol(i) + 2]);
         any |= sl[i] >= 0;
       }
       if (any) {
@@ -1689,94 +1709,111 @@ __global__ __launch_bounds__(WG3, 1) void k_cheb3_strip(Coef<float> c, Work wk,
         for (int i = 0; i < NPW; ++i) {
           if (sl[i] < 0) continue;
           const int64_t a = srow(sl[i]);
-          gu3[i] = ldc(c.up, sl[i]);
-          gd3[i] = ldc(c.dn, sl[i]);
-          if (gu3[i] != T(0)) zu3[i] = TB[(a + 1) * S + lane];
-          if (gd3[i] != T(0)) zd3[i] = TB[(a - 1) * S + lane];
+          const T gu = ldc(c.up, sl[i]), gd = ldc(c.dn, sl[i]);
+          const T zu = gu != T(0) ? TB[(a + 1) * S + lane] : T(0);
+          const T zd = gd != T(0) ? TB[(a - 1) * S + lane] : T(0);
+          t3[i] = tsv_term(gu, zu, gd, zd);
         }
       }
     }
-    // [B] next row: z_j row y + 4, coefficients, R and z_{j-1} of row y + 3
-    T v1n[NPW], h1n = T(0), rN[NPW], rNh = T(0), pN[NPW], pNh = T(0), cvN = T(0);
+    // [B] next row: coefficients of row y + 3 first (written to LDS at the
+    // end of this row), then z_j row y + 4, R and z_{j-1} of row y + 3
+    T cvN = T(0), v1n[NPW + 1], o1n = T(0), rN[NPW + 1], pN[NPW + 1];
     int cslN = -1;
-    load_w1(y + 4, v1n, h1n);
     load_coef(y + 3, cvN, cslN);
-    load_pt(R, y + 3, rN, rNh);
-    if (HAS_PREV) load_pt(zprev, y + 3, pN, pNh);
-    // [C] level 1: z_{j+1} on row y + 2 (columns -2 .. wdt + 1)
+    load_zj(y + 4, v1n, o1n);
+    load_pt(R, y + 3, rN);
+    if (HAS_PREV) load_pt(zprev, y + 3, pN);
+    // [C] level 1: z_{j+1} on row y + 2
+    T z1n[NPW + 1];
     {
       const bool in = row_ok(y + 2);
 #pragma unroll
       for (int i = 0; i <= NPW; ++i) {
-        if (i == NPW && w >= 4) break;
-        const int j = i < NPW ? w * NPW + i : lc1;
-        const int cc = i < NPW ? min(j, wdt - 1) : lc1;
-        const T z = cheb_node(w1[sw2][cc + 3][lane], w1[sw2][cc + 4][lane], w1[sw2][cc + 2][lane],
-                              w1[sw3][cc + 3][lane], w1[sw1][cc + 3][lane], yu1[i], yd1[i],
-                              cd[k2][cc + 2], ce[k2][cc + 3], ce[k2][cc + 2], cn[n2][cc + 2],
-                              cn[n1][cc + 2], gu1[i], gd1[i], i < NPW ? pA[i] : pAh,
-                              i < NPW ? rA[i] : rAh, cdi[k2][cc + 2], a1, a2);
-        const bool ok = in && (i < NPW ? j < wdt : col_ok(lc1));
-        // east halo columns only for a full-width strip
-        if (i < NPW || w < 2 || wdt == CH) w2[q2][j + 2][lane] = ok ? z : T(0);
+        if (i == NPW && !has_h) break;
+        const int cc = ccol(i);
+        const T z = cheb_node_t(zA[1][i], h1[hs][cc + 4][lane], h1[hs][cc + 2][lane], zA[2][i],
+                                zA[0][i], t1[i], cd[k2][cc + 2], ce[k2][cc + 3], ce[k2][cc + 2],
+                                cn[n2][cc + 2], cn[n1][cc + 2], pA[i], rA[i], cdi[k2][cc + 2],
+                                a1, a2);
+        if (i < NPW) {
+          const int j = w * NPW + i;
+          z1n[i] = in ? z : T(0);
+          h2[hs ^ 1][j + 2][lane] = (in && j < wdt) ? z : T(0);
+        } else {
+          const bool ok = in && col_ok(hc);
+          z1n[i] = ok ? z : T(0);
+          if (w < 2 || east_ok) h2[hs ^ 1][hc + 2][lane] = ok ? z : T(0);
+        }
       }
     }
-    __syncthreads();
-    // [D] level 2: z_{j+2} on row y + 1 (columns -1 .. wdt)
-    T z2[NPW];
+    // [D] level 2: z_{j+2} on row y + 1
+    T z2n[NPW + 1];
+#pragma unroll
+    for (int i = 0; i <= NPW; ++i) z2n[i] = T(0);
     if constexpr (lvl2) {
       const bool in = row_ok(y + 1);
-      const int lc2 = w == 1 ? -1 : wdt;
 #pragma unroll
       for (int i = 0; i <= NPW; ++i) {
         if (i == NPW && w != 1 && w != 2) break;
-        const int j = i < NPW ? w * NPW + i : lc2;
-        const int cc = i < NPW ? min(j, wdt - 1) : lc2;
-        const T z = cheb_node(w2[q1][cc + 2][lane], w2[q1][cc + 3][lane], w2[q1][cc + 1][lane],
-                              w2[q2][cc + 2][lane], w2[q0][cc + 2][lane], zu2[i], zd2[i],
-                              cd[k1][cc + 2], ce[k1][cc + 3], ce[k1][cc + 2], cn[n1][cc + 2],
-                              cn[n0][cc + 2], gu2[i], gd2[i], w1[sw1][cc + 3][lane],
-                              i < NPW ? rB[i] : rBh, cdi[k1][cc + 2], b1, b2);
-        const bool ok = in && (i < NPW ? j < wdt : col_ok(lc2));
-        if (i < NPW || w == 1 || wdt == CH) w3[e1][j + 1][lane] = ok ? z : T(0);
-        if (i < NPW) z2[i] = z;
+        const int cc = ccol(i);
+        const T z = cheb_node_t(z1h[1][i], h2[hs][cc + 3][lane], h2[hs][cc + 1][lane], z1n[i],
+                                z1h[0][i], t2[i], cd[k1][cc + 2], ce[k1][cc + 3], ce[k1][cc + 2],
+                                cn[n1][cc + 2], cn[n0][cc + 2], zA[0][i], rB[i], cdi[k1][cc + 2],
+                                b1, b2);
+        if (i < NPW) {
+          const int j = w * NPW + i;
+          z2n[i] = in ? z : T(0);
+          h3[hs ^ 1][j + 1][lane] = (in && j < wdt) ? z : T(0);
+        } else {
+          const bool ok = in && col_ok(hc);
+          z2n[i] = ok ? z : T(0);
+          if (w == 1 || east_ok) h3[hs ^ 1][hc + 1][lane] = ok ? z : T(0);
+        }
       }
     }
-    __syncthreads();
     // [E] level 3: z_{j+3} on row y
     if constexpr (lvl3) {
       const int64_t obase = pd.vbase + st.lrow0 + (int64_t)s * nx;
 #pragma unroll
       for (int i = 0; i < NPW; ++i) {
-        // nodes past a ragged strip's width repeat the last node
-        const int jc = min(w * NPW + i, wdt - 1);
-        const T z = cheb_node(w3[e0][jc + 1][lane], w3[e0][jc + 2][lane], w3[e0][jc][lane],
-                              w3[e1][jc + 1][lane], w3[em][jc + 1][lane], zu3[i], zd3[i],
-                              cd[k0][jc + 2], ce[k0][jc + 3], ce[k0][jc + 2], cn[n0][jc + 2],
-                              cn[nm][jc + 2], gu3[i], gd3[i], w2[q0][jc + 2][lane], rC[i],
-                              cdi[k0][jc + 2], c1, c2);
+        const int jc = ccol(i);
+        const T z = cheb_node_t(z2h[1][i], h3[hs][jc + 2][lane], h3[hs][jc][lane], z2n[i],
+                                z2h[0][i], t3[i], cd[k0][jc + 2], ce[k0][jc + 3], ce[k0][jc + 2],
+                                cn[n0][jc + 2], cn[nm][jc + 2], z1h[0][i], rC[i], cdi[k0][jc + 2],
+                                c1, c2);
         outb[(obase + jc) * S + lane] = z;
       }
     }
-    // the next row into the slots of rows y (z_j), y - 1 (coefficients) and
-    // y - 2 (cN), which no level of this row reads
-    store_w1(sw4, v1n, h1n, y + 4);
+    // [F] the east / west z_j row y + 3 and the coefficients of row y + 3
+    // for the next row; then the register histories move down one row.
+    put_h1(hs ^ 1, zA[2], oA, y + 3);
     store_coef(k3, n3, cvN, cslN);
+    {
+      const bool in4 = row_ok(y + 4);
 #pragma unroll
-    for (int i = 0; i < NPW; ++i) {
-      rC[i] = rB[i];
-      rB[i] = rA[i];
-      rA[i] = rN[i];
-      pA[i] = HAS_PREV ? pN[i] : T(0);
+      for (int i = 0; i <= NPW; ++i) {
+        zA[0][i] = zA[1][i];
+        zA[1][i] = zA[2][i];
+        zA[2][i] = in4 ? v1n[i] : T(0);
+        z1h[0][i] = z1h[1][i];
+        z1h[1][i] = z1n[i];
+        if (i < NPW) {
+          z2h[0][i] = z2h[1][i];
+          z2h[1][i] = z2n[i];
+          rC[i] = rB[i];
+        }
+        rB[i] = rA[i];
+        rA[i] = rN[i];
+        pA[i] = HAS_PREV ? pN[i] : T(0);
+      }
+      oA = o1n;
     }
-    rBh = rAh;
-    rAh = rNh;
-    pAh = pNh;
     // z_{j+2} of row y + 1 if it is a row of this strip
     if (lvl2 && s + 1 >= 0 && s + 1 < st.nrows) {
       const int64_t b1row = pd.vbase + st.lrow0 + (int64_t)(s + 1) * nx;
 #pragma unroll
-      for (int i = 0; i < NPW; ++i) outa[(b1row + min(w * NPW + i, wdt - 1)) * S + lane] = z2[i];
+      for (int i = 0; i < NPW; ++i) outa[(b1row + ccol(i)) * S + lane] = z2n[i];
     }
     __syncthreads();
   };
