@@ -47,9 +47,12 @@ def cheb_words(cheb, fp32=True):
     """S-wide vector words per node that the Chebyshev passes of one
     application read and write, and the number of passes: a pass reads z_j,
     R (and z_{j-1} after the first) and writes its last two iterates (one
-    for a single step)."""
+    for a single step; a last three-step pass writes only its last)."""
     passes = cheb_passes(cheb, fp32)
-    words = sum((3 if prev else 2) + min(k, 2) for k, prev in passes)
+    words = 0
+    for n, (k, prev) in enumerate(passes):
+        last = n == len(passes) - 1
+        words += (3 if prev else 2) + (1 if k == 1 or (k == 3 and last) else 2)
     return words, len(passes)
 
 

@@ -390,7 +390,8 @@ struct BlockResult {
 
 void reff::Workspace::release() {
   for (DevBuf* b : {&Y, &P, &Q, &R, &D, &X, &part, &W, &small, &state, &tgt, &pos, &plans, &units,
-                    &uid, &act, &out, &xs, &rows, &map, &flags, &strips, &sid, &Za, &Zb, &Zc, &Zd})
+                    &uid, &act, &out, &xs, &rows, &map, &flags, &strips, &sid, &Za, &Zb, &Zc, &Zd,
+                    &TA, &TB})
     if (b->p) {
       (void)hipFree(b->p);
       b->p = nullptr;

@@ -1491,8 +1491,9 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv2(Coef<T> c, Work wk
 // and west neighbours, double-buffered: each level reads the row written in
 // the previous iteration, and one barrier per row suffices.  TSV partners:
 // z_j from global memory, z_{j+1} and z_{j+2} from the side buffers of
-// k_cheb_tsv1 / k_cheb_tsv2.  Writes z_{j+2} to outa and z_{j+3} to outb
-// (the next pass's z_{j-1} and z_j); neither may alias an input.
+// k_cheb_tsv1 / k_cheb_tsv2.  Writes z_{j+2} to outa (null for the last
+// pass: nothing reads it) and z_{j+3} to outb (the next pass's z_{j-1} and
+// z_j); neither may alias an input.
 constexpr int WG3 = 512;
 constexpr int NPW3 = CH / (WG3 / 64);  // 4
 
@@ -1809,8 +1810,9 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
       }
       oA = o1n;
     }
-    // z_{j+2} of row y + 1 if it is a row of this strip
-    if (lvl2 && s + 1 >= 0 && s + 1 < st.nrows) {
+    // z_{j+2} of row y + 1 if it is a row of this strip (and a later pass
+    // needs it)
+    if (lvl2 && outa && s + 1 >= 0 && s + 1 < st.nrows) {
       const int64_t b1row = pd.vbase + st.lrow0 + (int64_t)(s + 1) * nx;
 #pragma unroll
       for (int i = 0; i < NPW; ++i) outa[(b1row + ccol(i)) * S + lane] = z2n[i];
@@ -2455,14 +2457,15 @@ static T* cheb_steps(const Coef<T>& c, const SolveBuffers& b, hipStream_t st, T*
         hipLaunchKernelGGL((k_cheb_tsv2<T>), g2, dim3(64 * TSV_WAVES), 0, st, c, b.work, b.act,
                            (const T*)buf[cur], R, (const T*)b.TA, (T*)b.TB, b1, b2);
       }
+      T* o1 = j + 3 == b.cheb_k ? nullptr : buf[f1];  // the last pass's z_{j+2} is not read
       if (prev < 0)
         hipLaunchKernelGGL((k_cheb3_strip<false>), g, dim3(WG3), 0, st, c, b.work,
-                           (const T*)buf[cur], zp, R, (const T*)b.TA, (const T*)b.TB, buf[f1],
-                           o2, a1, a2, b1, b2, c1, c2);
+                           (const T*)buf[cur], zp, R, (const T*)b.TA, (const T*)b.TB, o1, o2, a1,
+                           a2, b1, b2, c1, c2);
       else
         hipLaunchKernelGGL((k_cheb3_strip<true>), g, dim3(WG3), 0, st, c, b.work,
-                           (const T*)buf[cur], zp, R, (const T*)b.TA, (const T*)b.TB, buf[f1],
-                           o2, a1, a2, b1, b2, c1, c2);
+                           (const T*)buf[cur], zp, R, (const T*)b.TA, (const T*)b.TB, o1, o2, a1,
+                           a2, b1, b2, c1, c2);
       j += 3;
       if (o2 == last) return last;
       prev = f1;

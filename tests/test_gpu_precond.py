@@ -47,11 +47,12 @@ def test_degree_out_of_range_rejected():
 
 @pytest.mark.parametrize("kind", ["ragged_square", "ragged_rect"])
 def test_fused_steps_on_ragged_strips(kind):
-    """Degrees whose steps run as fused passes (3: a pair; 4: a triple; 5: a
-    triple and a single step; 6: a triple and a pair; 7: two triples) on
-    tiers whose width is not a multiple of the strip width, with TSVs: every
-    result within the mixed bar.  Float64 runs pairs (3: one pair; 6: two
-    pairs and a single step)."""
+    """Degrees whose steps run as fused passes (3: two steps; 4: three; 5:
+    three and one; 6: three and two; 7: two passes of three; 8: two of three
+    and one; 9: two of three and two) on tiers whose width is not a multiple
+    of the strip width, with TSVs: every result within the mixed bar.
+    Float64 runs two steps per pass (3: one pass; 6: two passes and a single
+    step)."""
     reff = _reff()
     if kind == "ragged_square":
         d = gen.config2(side=100, n_tsv=64, sigma=10.0)
@@ -60,7 +61,7 @@ def test_fused_steps_on_ragged_strips(kind):
     nodes = gen.sample_free_nodes(d, 64, 5)
     want = ro.diag(d, nodes)
     h = reff.reff_build_pdn(d)
-    for k in (3, 4, 5, 6, 7):
+    for k in (3, 4, 5, 6, 7, 8, 9):
         _say("fused precond degree", k, kind)
         got, st = reff.reff_solve_diag(h, nodes, precision=1, rel_tol=1e-5, precond_degree=k)
         err = float(np.max(np.abs(got - want) / want))
