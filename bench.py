@@ -43,16 +43,24 @@ def cheb_passes(cheb, fp32=True):
     return out
 
 
+def cheb_folds_z1(cheb, fp32=True):
+    """The first pass is a three-step pass that forms z_1 = D^-1 R / theta
+    from R itself (nothing writes z_1)."""
+    return fp32 and cheb > 3
+
+
 def cheb_words(cheb, fp32=True):
     """S-wide vector words per node that the Chebyshev passes of one
     application read and write, and the number of passes: a pass reads z_j,
-    R (and z_{j-1} after the first) and writes its last two iterates (one
-    for a single step; a last three-step pass writes only its last)."""
+    R (and z_{j-1} after the first; a first pass that forms z_1 from R reads
+    R alone) and writes its last two iterates (one for a single step; a last
+    three-step pass writes only its last)."""
     passes = cheb_passes(cheb, fp32)
     words = 0
     for n, (k, prev) in enumerate(passes):
         last = n == len(passes) - 1
-        words += (3 if prev else 2) + (1 if k == 1 or (k == 3 and last) else 2)
+        reads = 3 if prev else (1 if cheb_folds_z1(cheb, fp32) else 2)
+        words += reads + (1 if k == 1 or (k == 3 and last) else 2)
     return words, len(passes)
 
 
@@ -64,6 +72,7 @@ def kernel_bytes(n, fp32=True, mixed_with_d=True, cheb=1):
       residual update (K2): read Q, R (P, D); write R (D)       -> 3 (6) S w
                          + Dinv; with the polynomial preconditioner it also
                          writes z_1 = D^-1 R / theta            -> + S w
+                         unless the first pass forms z_1 itself
       search block (K3): read P, R (or Z); write Y              -> 3 S w + d, Dinv
       Chebyshev passes (degree k > 1), all passes of one application: the
                          vector words of cheb_words, each pass also reading
@@ -72,7 +81,8 @@ def kernel_bytes(n, fp32=True, mixed_with_d=True, cheb=1):
     """
     w = 4 if fp32 else 8
     k1 = n * (4 * S * w + 3 * w + 4)
-    k2 = n * ((6 if mixed_with_d else 3) * S * w + w + (S * w if cheb > 1 else 0))
+    z1 = cheb > 1 and not cheb_folds_z1(cheb, fp32)
+    k2 = n * ((6 if mixed_with_d else 3) * S * w + w + (S * w if z1 else 0))
     k3 = n * (3 * S * w + 2 * w)
     kp = kg = 0
     if cheb > 1:

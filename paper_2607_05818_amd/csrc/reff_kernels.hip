@@ -633,9 +633,10 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram_strip(Coef<T> c, Work wk
 
 // ---------------------------------------------------------------- K2
 // R -= Q A;  (D += P A);  Z = Dinv R;  W3 = Q^T Z.
-// With CHEB (polynomial preconditioner, block variant) the kernel writes
-// z_1 = D^-1 R / theta to Z1 (the Chebyshev steps' start) instead of
-// forming W3, which a Gram kernel takes from the finished Z.
+// With CHEB (polynomial preconditioner, block variant) the kernel does not
+// form W3 (a Gram kernel takes it from the finished Z) and writes z_1 =
+// D^-1 R / theta, the Chebyshev steps' start, to Z1 unless Z1 is null (the
+// first Chebyshev pass then forms z_1 from R itself).
 template <typename T, bool DIAG, bool WITH_D, bool CHEB = false>
 __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
                                                     const T* __restrict__ alpha,
@@ -753,7 +754,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
       if (v < u.end) {
         R[v * S + lane] = sR[row][lane];
         if (WITH_D) D[v * S + lane] = sD[row][lane];
-        if (CHEB) Z1[v * S + lane] = sP[row][lane];
+        if (CHEB && Z1) Z1[v * S + lane] = sP[row][lane];
       }
     }
     __syncthreads();
@@ -934,31 +935,43 @@ __device__ __forceinline__ T cheb_node(T u, T ue, T uw, T un, T us, T yu, T yd, 
                      a1, a2);
 }
 
+// z_1 = D^-1 R / theta at vector row v (coefficient index v + cofs), the
+// start of the Chebyshev steps, in the one order every kernel that forms it
+// uses.
+template <typename T>
+__device__ __forceinline__ T cheb_z1(const Coef<T>& c, const T* __restrict__ R, int64_t v,
+                                     int64_t cofs, T ith) {
+  return ldc(c.dinv, v + cofs) * R[v * S + (threadIdx.x & 63)] * ith;
+}
+
 // z_{j+1} at vector row p, node (xg, yy) of its tier, from global memory:
 // cheb_node with the arguments a strip kernel passes from LDS (neighbours
 // outside the tier are 0, with coupling 0 on the west and south side as
 // there; a missing TSV partner reads the node itself, with coupling 0).
-template <typename T, bool HAS_PREV>
+// With FIRST the z_j values are z_1, formed from R (zin unused).
+template <typename T, bool HAS_PREV, bool FIRST = false>
 __device__ __forceinline__ T cheb_point(const Coef<T>& c, const PlanDesc& pd,
                                         const T* __restrict__ zin, const T* __restrict__ zprev,
                                         const T* __restrict__ R, int64_t p, int xg, int yy, T a1,
-                                        T a2) {
+                                        T a2, T ith = T(1)) {
   const int lane = threadIdx.x & 63;
   const int nx = pd.nx;
   const int ny = (int)(pd.plane / pd.nx);
-  const int64_t pc = p + (pd.cbase - pd.vbase);
+  const int64_t cofs = pd.cbase - pd.vbase;
+  const int64_t pc = p + cofs;
+  auto zj = [&](int64_t q) { return FIRST ? cheb_z1(c, R, q, cofs, ith) : zin[q * S + lane]; };
   const bool he = xg + 1 < nx, hw = xg > 0, hn = yy + 1 < ny, hs = yy > 0;
-  const T u = zin[p * S + lane];
-  const T ue = zin[(he ? p + 1 : p) * S + lane];
-  const T uw = zin[(hw ? p - 1 : p) * S + lane];
-  const T un = zin[(hn ? p + nx : p) * S + lane];
-  const T us = zin[(hs ? p - nx : p) * S + lane];
+  const T u = zj(p);
+  const T ue = zj(he ? p + 1 : p);
+  const T uw = zj(hw ? p - 1 : p);
+  const T un = zj(hn ? p + nx : p);
+  const T us = zj(hs ? p - nx : p);
   const int sp = ldc(c.slot, pc);
   const int q = max(sp, 0);
   const T gu = sp >= 0 ? ldc(c.up, q) : T(0);
   const T gd = sp >= 0 ? ldc(c.dn, q) : T(0);
-  const T yu = zin[(gu != T(0) ? p + pd.plane : p) * S + lane];
-  const T yd = zin[(gd != T(0) ? p - pd.plane : p) * S + lane];
+  const T yu = zj(gu != T(0) ? p + pd.plane : p);
+  const T yd = zj(gd != T(0) ? p - pd.plane : p);
   const T up = HAS_PREV ? zprev[p * S + lane] : T(0);
   const T r = R[p * S + lane];
   const T cw = hw ? ldc(c.cE, hw ? pc - 1 : pc) : T(0);
@@ -1412,6 +1425,7 @@ __global__ __launch_bounds__(WG, sizeof(T) == 4 ? 4 : 2) void k_cheb2_strip(Coef
 //                south neighbours (0 where the neighbour does not exist):
 //                TA[row][k][S], k = 0 (node), 1 (E), 2 (W), 3 (N), 4 (S);
 //   k_cheb_tsv2: z_{j+2} at every TSV node from TA: TB[row][S].
+// In the first pass of an application (no z_{j-1}) z_j is z_1, formed from R.
 // One wave per item, grid (items / 4, active blocks); no barriers.
 constexpr int TSV_WAVES = 4;
 
@@ -1421,7 +1435,8 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv1(Coef<T> c, Work wk
                                                              const T* __restrict__ zin,
                                                              const T* __restrict__ zprev,
                                                              const T* __restrict__ R,
-                                                             T* __restrict__ TA, T a1, T a2) {
+                                                             T* __restrict__ TA, T a1, T a2,
+                                                             T ith) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const PlanDesc pd = wk.plans[act[blockIdx.y]];
@@ -1438,18 +1453,20 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv1(Coef<T> c, Work wk
   const int xn = x + dx, yn = y + dy;
   T z = T(0);
   if (xn >= 0 && xn < nx && yn >= 0 && yn < ny)
-    z = cheb_point<T, HAS_PREV>(c, pd, zin, zprev, R, pd.vbase + loc + dx + (int64_t)dy * nx, xn,
-                                yn, a1, a2);
+    z = cheb_point<T, HAS_PREV, !HAS_PREV>(c, pd, zin, zprev, R,
+                                           pd.vbase + loc + dx + (int64_t)dy * nx, xn, yn, a1, a2,
+                                           ith);
   TA[((pd.sbase + qi) * 5 + k) * S + lane] = z;
 }
 
-template <typename T>
+template <typename T, bool FIRST>
 __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv2(Coef<T> c, Work wk,
                                                              const int32_t* __restrict__ act,
                                                              const T* __restrict__ zin,
                                                              const T* __restrict__ R,
                                                              const T* __restrict__ TA,
-                                                             T* __restrict__ TB, T b1, T b2) {
+                                                             T* __restrict__ TB, T b1, T b2,
+                                                             T ith) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const PlanDesc pd = wk.plans[act[blockIdx.y]];
@@ -1474,8 +1491,9 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv2(Coef<T> c, Work wk
   TB[(pd.sbase + qi) * S + lane] =
       cheb_node(TA[a * S + lane], TA[(a + 1) * S + lane], TA[(a + 2) * S + lane],
                 TA[(a + 3) * S + lane], TA[(a + 4) * S + lane], yu, yd, ldc(c.d, u),
-                ldc(c.cE, u), cw, ldc(c.cN, u), cs, gu, gd, zin[v * S + lane], R[v * S + lane],
-                ldc(c.dinv, u), b1, b2);
+                ldc(c.cE, u), cw, ldc(c.cN, u), cs, gu, gd,
+                FIRST ? cheb_z1(c, R, v, pd.cbase - pd.vbase, ith) : zin[v * S + lane],
+                R[v * S + lane], ldc(c.dinv, u), b1, b2);
 }
 
 // Three Chebyshev steps in one pass over a strip (float32, block variant):
@@ -1507,7 +1525,7 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
                                                         float* __restrict__ outa,
                                                         float* __restrict__ outb, float a1,
                                                         float a2, float b1, float b2, float c1,
-                                                        float c2) {
+                                                        float c2, float ith) {
   using T = float;
   constexpr int NPW = NPW3;
   constexpr int N1 = CH + 4;  // coefficient columns -2 .. CH + 1, index c + 2 (cE: c + 3)
@@ -1552,12 +1570,34 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
   auto ccol = [&](int i) { return i < NPW ? min(w * NPW + i, wdt - 1) : hc; };
   // z_j row yy on this wave's columns (raw loads; rows outside the tier are
   // zeroed when the row enters the register history)
-  auto load_zj = [&](int yy, T (&v)[NPW + 1], T& o) {
-#pragma unroll
-    for (int i = 0; i < NPW; ++i) v[i] = zin[vidx(yy, w * NPW + i) * S + lane];
-    if (has_h) v[NPW] = zin[vidx(yy, hc) * S + lane];
-    if (has_o) o = zin[vidx(yy, oc) * S + lane];
+  // The first pass of an application (no z_{j-1}) forms z_j = z_1 from R:
+  // a row is loaded raw with the nodes' Dinv (scalar loads) and scaled where
+  // it enters the register history, so nothing waits for the load early.
+  constexpr bool FIRST = !HAS_PREV;
+  auto zj_at = [&](int64_t v) -> T {
+    return FIRST ? cheb_z1(c, R, v, cofs, ith) : zin[v * S + lane];
   };
+  const T* zsrc = FIRST ? R : zin;
+  auto load_zj = [&](int yy, T (&v)[NPW + 1], T& o, T (&dv)[NPW + 2]) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      const int64_t q = vidx(yy, w * NPW + i);
+      v[i] = zsrc[q * S + lane];
+      if (FIRST) dv[i] = ldc(c.dinv, q + cofs);
+    }
+    if (has_h) {
+      const int64_t q = vidx(yy, hc);
+      v[NPW] = zsrc[q * S + lane];
+      if (FIRST) dv[NPW] = ldc(c.dinv, q + cofs);
+    }
+    if (has_o) {
+      const int64_t q = vidx(yy, oc);
+      o = zsrc[q * S + lane];
+      if (FIRST) dv[NPW + 1] = ldc(c.dinv, q + cofs);
+    }
+  };
+  // z_1 = Dinv R / theta in the order of cheb_z1
+  auto scaled = [&](T raw, T d) -> T { return FIRST ? d * raw * ith : raw; };
   auto load_pt = [&](const T* __restrict__ a, int yy, T (&v)[NPW + 1]) {
 #pragma unroll
     for (int i = 0; i < NPW; ++i) v[i] = a[vidx(yy, w * NPW + i) * S + lane];
@@ -1618,14 +1658,17 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
   // y0-3 .. y0-1, the east / west row y0-2, coefficients of rows y0-3 and
   // y0-2, R and z_{j-1} of row y0-2.
   {
-    T o = T(0), cv = T(0);
+    T o = T(0), cv = T(0), dv[NPW + 2];
     int csl = -1;
 #pragma unroll
+    for (int i = 0; i < NPW + 2; ++i) dv[i] = T(1);
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-      load_zj(st.y0 - 3 + k, zA[k], o);
+      load_zj(st.y0 - 3 + k, zA[k], o, dv);
       const bool in = row_ok(st.y0 - 3 + k);
 #pragma unroll
-      for (int i = 0; i <= NPW; ++i) zA[k][i] = in ? zA[k][i] : T(0);
+      for (int i = 0; i <= NPW; ++i) zA[k][i] = in ? scaled(zA[k][i], dv[i]) : T(0);
+      o = scaled(o, dv[NPW + 1]);
       if (k == 1) put_h1(0, zA[1], o, st.y0 - 2);
       if (k == 2) oA = o;
     }
@@ -1665,8 +1708,8 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
           if (sl[i] < 0) continue;
           const int64_t v = vidx(y + 2, ccol(i));
           const T gu = ldc(c.up, sl[i]), gd = ldc(c.dn, sl[i]);
-          const T yu = zin[(gu != T(0) ? v + pd.plane : v) * S + lane];
-          const T yd = zin[(gd != T(0) ? v - pd.plane : v) * S + lane];
+          const T yu = zj_at(gu != T(0) ? v + pd.plane : v);
+          const T yd = zj_at(gd != T(0) ? v - pd.plane : v);
           t1[i] = tsv_term(gu, yu, gd, yd);
         }
       }
@@ -1719,10 +1762,12 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     }
     // [B] next row: coefficients of row y + 3 first (written to LDS at the
     // end of this row), then z_j row y + 4, R and z_{j-1} of row y + 3
-    T cvN = T(0), v1n[NPW + 1], o1n = T(0), rN[NPW + 1], pN[NPW + 1];
+    T cvN = T(0), v1n[NPW + 1], o1n = T(0), rN[NPW + 1], pN[NPW + 1], dvn[NPW + 2];
     int cslN = -1;
+#pragma unroll
+    for (int i = 0; i < NPW + 2; ++i) dvn[i] = T(1);
     load_coef(y + 3, cvN, cslN);
-    load_zj(y + 4, v1n, o1n);
+    load_zj(y + 4, v1n, o1n, dvn);
     load_pt(R, y + 3, rN);
     if (HAS_PREV) load_pt(zprev, y + 3, pN);
     // [C] level 1: z_{j+1} on row y + 2
@@ -1796,7 +1841,7 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
       for (int i = 0; i <= NPW; ++i) {
         zA[0][i] = zA[1][i];
         zA[1][i] = zA[2][i];
-        zA[2][i] = in4 ? v1n[i] : T(0);
+        zA[2][i] = in4 ? scaled(v1n[i], dvn[i]) : T(0);
         z1h[0][i] = z1h[1][i];
         z1h[1][i] = z1n[i];
         if (i < NPW) {
@@ -1808,7 +1853,7 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
         rA[i] = rN[i];
         pA[i] = HAS_PREV ? pN[i] : T(0);
       }
-      oA = o1n;
+      oA = scaled(o1n, dvn[NPW + 1]);
     }
     // z_{j+2} of row y + 1 if it is a row of this strip (and a later pass
     // needs it)
@@ -2415,8 +2460,17 @@ static void reduce(const SolveBuffers& b, int m0, int nmat, int len, hipStream_t
                      b.W, b.work.plans, b.act, m0, nmat, len, strips ? 1 : 0);
 }
 
-// Chebyshev steps j = 1 .. cheb_k - 1 from z_1 in Za: three per pass while
-// three remain (float32), then two per pass while two remain, then one.  A pass reads z_j, z_{j-1} and
+// True when the first Chebyshev pass of an application is a three-step pass
+// that forms z_1 from R itself, so that no kernel writes z_1.
+template <typename T>
+static bool cheb_folds_z1(const SolveBuffers& b) {
+  return sizeof(T) == 4 && b.cheb_k > 3 && b.TA != nullptr;
+}
+
+// Chebyshev steps j = 1 .. cheb_k - 1 from z_1: three per pass while three
+// remain (float32), then two per pass while two remain, then one.  z_1 =
+// D^-1 R / theta is in Za unless the first pass is a three-step pass, which
+// forms it from R (cheb_folds_z1).  A pass reads z_j, z_{j-1} and
 // writes its last two iterates (or one) to arrays that hold neither; the
 // iterates rotate over Za .. Zd.  The last step writes to `last` if given.
 // Returns the array that holds Z.
@@ -2435,6 +2489,7 @@ static T* cheb_steps(const Coef<T>& c, const SolveBuffers& b, hipStream_t st, T*
     x1 = (T)b.cheb_a1[j];
     x2 = (T)b.cheb_a2[j];
   };
+  const T ith = (T)b.cheb_invtheta;
   int j = 1;
   if constexpr (sizeof(T) == 4) {
     while (j + 2 < b.cheb_k && b.TA) {
@@ -2448,24 +2503,27 @@ static T* cheb_steps(const Coef<T>& c, const SolveBuffers& b, hipStream_t st, T*
       if (b.max_slots > 0) {
         const dim3 g1((5 * b.max_slots + TSV_WAVES - 1) / TSV_WAVES, b.n_act);
         const dim3 g2((b.max_slots + TSV_WAVES - 1) / TSV_WAVES, b.n_act);
-        if (prev < 0)
+        if (prev < 0) {
           hipLaunchKernelGGL((k_cheb_tsv1<T, false>), g1, dim3(64 * TSV_WAVES), 0, st, c, b.work,
-                             b.act, (const T*)buf[cur], zp, R, (T*)b.TA, a1, a2);
-        else
+                             b.act, (const T*)buf[cur], zp, R, (T*)b.TA, a1, a2, ith);
+          hipLaunchKernelGGL((k_cheb_tsv2<T, true>), g2, dim3(64 * TSV_WAVES), 0, st, c, b.work,
+                             b.act, (const T*)buf[cur], R, (const T*)b.TA, (T*)b.TB, b1, b2, ith);
+        } else {
           hipLaunchKernelGGL((k_cheb_tsv1<T, true>), g1, dim3(64 * TSV_WAVES), 0, st, c, b.work,
-                             b.act, (const T*)buf[cur], zp, R, (T*)b.TA, a1, a2);
-        hipLaunchKernelGGL((k_cheb_tsv2<T>), g2, dim3(64 * TSV_WAVES), 0, st, c, b.work, b.act,
-                           (const T*)buf[cur], R, (const T*)b.TA, (T*)b.TB, b1, b2);
+                             b.act, (const T*)buf[cur], zp, R, (T*)b.TA, a1, a2, ith);
+          hipLaunchKernelGGL((k_cheb_tsv2<T, false>), g2, dim3(64 * TSV_WAVES), 0, st, c, b.work,
+                             b.act, (const T*)buf[cur], R, (const T*)b.TA, (T*)b.TB, b1, b2, ith);
+        }
       }
       T* o1 = j + 3 == b.cheb_k ? nullptr : buf[f1];  // the last pass's z_{j+2} is not read
       if (prev < 0)
         hipLaunchKernelGGL((k_cheb3_strip<false>), g, dim3(WG3), 0, st, c, b.work,
                            (const T*)buf[cur], zp, R, (const T*)b.TA, (const T*)b.TB, o1, o2, a1,
-                           a2, b1, b2, c1, c2);
+                           a2, b1, b2, c1, c2, ith);
       else
         hipLaunchKernelGGL((k_cheb3_strip<true>), g, dim3(WG3), 0, st, c, b.work,
                            (const T*)buf[cur], zp, R, (const T*)b.TA, (const T*)b.TB, o1, o2, a1,
-                           a2, b1, b2, c1, c2);
+                           a2, b1, b2, c1, c2, ith);
       j += 3;
       if (o2 == last) return last;
       prev = f1;
@@ -2510,8 +2568,9 @@ template <typename T>
 static void precond_start(const Coef<T>& c, const SolveBuffers& b, hipStream_t st) {
   const double eps4 = sizeof(T) == 8 ? 1e-14 : 1e-6;
   const double tau = sizeof(T) == 8 ? 1e-26 : 1e-12;
-  hipLaunchKernelGGL((k_scale_units<T>), dim3(b.n_units), dim3(256), 0, st, c, b.work,
-                     (const T*)b.R, (T*)b.Za, (T)b.cheb_invtheta);
+  if (!cheb_folds_z1<T>(b))
+    hipLaunchKernelGGL((k_scale_units<T>), dim3(b.n_units), dim3(256), 0, st, c, b.work,
+                       (const T*)b.R, (T*)b.Za, (T)b.cheb_invtheta);
   cheb_steps<T>(c, b, st, (T*)b.Y);
   hipLaunchKernelGGL((k_gram_ab<T, true>), dim3(b.n_units), dim3(WG), 0, st, c, b.work,
                      (const T*)b.Y, (const T*)b.Y, b.part, 3);
@@ -2566,12 +2625,13 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
                          b.part);
   } else if (cheb) {
     const T it = (T)b.cheb_invtheta;
+    T* z1 = cheb_folds_z1<T>(b) ? nullptr : (T*)b.Za;  // z_1 = D^-1 R / theta
     if (with_d)
       hipLaunchKernelGGL((k_update_r<T, false, true, true>), g, blk, 0, st, c, wk, al, Q, P, R, D,
-                         b.part, (T*)b.Za, it);
+                         b.part, z1, it);
     else
       hipLaunchKernelGGL((k_update_r<T, false, false, true>), g, blk, 0, st, c, wk, al, Q, P, R,
-                         D, b.part, (T*)b.Za, it);
+                         D, b.part, z1, it);
   } else {
     if (with_d)
       hipLaunchKernelGGL((k_update_r<T, false, true>), g, blk, 0, st, c, wk, al, Q, P, R, D,
