@@ -591,7 +591,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     // ---- group of jobs within the row budget
     size_t j1 = j0;
     int64_t rows = 0, slot_rows = 0;
-    int max_slots = 0;
+    int max_cols = 0;  // most TSV columns of one block
     std::vector<PlanDesc> pin;
     while (j1 < jobs.size()) {
       const StackInfo& sk = stacks[(size_t)jobs[j1].stack];
@@ -606,7 +606,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       pd.slot_end = sk.slot_end;
       pd.sbase = slot_rows;
       slot_rows += sk.slot_end - sk.slot_begin;
-      max_slots = std::max(max_slots, sk.slot_end - sk.slot_begin);
+      max_cols = std::max(max_cols, (int)((sk.slot_end - sk.slot_begin) / (sk.n / sk.plane)));
       pin.push_back(pd);
       rows += sk.n;
       ++j1;
@@ -766,7 +766,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       b.Zd = ws.Zd.p;
       b.TA = ws.TA.p;
       b.TB = ws.TB.p;
-      b.max_slots = max_slots;
+      b.max_tsv_cols = max_cols;
     }
 
     HIPCHK(launch_init_blocks(fp32, o.indep, coef, b, o.stream));

@@ -71,3 +71,21 @@ def test_fused_steps_on_ragged_strips(kind):
         _say("float64 precond degree", k, kind)
         got, _ = reff.reff_solve_diag(h, nodes, precision=0, rel_tol=1e-9, precond_degree=k)
         assert float(np.max(np.abs(got - want) / want)) <= 1e-6
+
+
+def test_eight_tiers_with_clustered_tsvs():
+    """Eight tiers (the large stack's depth) on a small grid with many TSV
+    columns close together, so that TSV nodes neighbour each other: the
+    side-buffer values of the three-step passes at every tier, default
+    degree, against the oracle in both precisions."""
+    reff = _reff()
+    d = gen.small_random_desc(57, 8, 40, 36, 60, 6)
+    nodes = gen.sample_free_nodes(d, 64, 9)
+    want = ro.diag(d, nodes)
+    h = reff.reff_build_pdn(d)
+    _say("eight tiers, mixed")
+    got, st = reff.reff_solve_diag(h, nodes, precision=1, rel_tol=1e-5)
+    assert float(np.max(np.abs(got - want) / want)) <= 1e-3
+    _say("eight tiers, fp64")
+    got, st = reff.reff_solve_diag(h, nodes, precision=0, rel_tol=1e-9)
+    assert float(np.max(np.abs(got - want) / want)) <= 1e-6
