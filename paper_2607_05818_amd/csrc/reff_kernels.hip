@@ -1526,9 +1526,10 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
   __shared__ T h1[2][CH + 6][S];
   __shared__ T h2[2][CH + 4][S];
   __shared__ T h3[2][CH + 2][S];
-  // coefficients of row y + k in slot (s + 4 + k) % 4, cN in (s + 4 + k) % 5
-  __shared__ T cd[4][N1], cdi[4][N1], ce[4][N1 + 1], cn[5][N1];
-  __shared__ int cslot[4][N1];
+  // coefficients (and cN) of row y + k in slot (s + 4 + k) % 8 (a power of
+  // two: the slot indices are a mask away from the row number)
+  __shared__ T cd[8][N1], cdi[8][N1], ce[8][N1 + 1], cn[8][N1];
+  __shared__ int cslot[8][N1];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int sidx = wk.sid[logical_block(blockIdx.x, gridDim.x)];
@@ -1546,6 +1547,16 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     cc = min(max(cc, -x0), nx - 1 - x0);
     return pd.vbase + st.lrow0 + (int64_t)(yy - st.y0) * nx + cc;
   };
+  // Vector accesses go through strip-relative 32-bit element offsets from
+  // per-strip base pointers (a node's offset stays within the stack: at most
+  // a tier plus a strip's rows away, far below 2^31 elements).
+  const int64_t r0off = (pd.vbase + st.lrow0) * S;
+  auto voff = [&](int yy, int cc) -> int {
+    yy = min(max(yy, 0), ny - 1);
+    cc = min(max(cc, -x0), nx - 1 - x0);
+    return ((yy - st.y0) * nx + cc) * S + lane;
+  };
+  const int plS = (int)pd.plane * S;
   auto srow = [&](int q) -> int64_t { return pd.sbase + (q - pd.slot_begin); };
   // halo column of waves 0-3 (levels 1 and 2; level 2 uses waves 1, 2):
   // -2, -1, wdt, wdt + 1; outer z_j column of waves 4, 5: -3, wdt + 2.
@@ -1568,31 +1579,30 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
   auto zj_at = [&](int64_t v) -> T {
     return FIRST ? cheb_z1(c, R, v, cofs, ith) : zin[v * S + lane];
   };
-  const T* zsrc = FIRST ? R : zin;
+  const T* zsb = (FIRST ? R : zin) + r0off;
+  const T* Rb = R + r0off;
+  const T* pb = HAS_PREV ? zprev + r0off : nullptr;
   auto load_zj = [&](int yy, T (&v)[NPW + 1], T& o, T (&dv)[NPW + 2]) {
 #pragma unroll
     for (int i = 0; i < NPW; ++i) {
-      const int64_t q = vidx(yy, w * NPW + i);
-      v[i] = zsrc[q * S + lane];
-      if (FIRST) dv[i] = ldc(c.dinv, q + cofs);
+      v[i] = zsb[voff(yy, w * NPW + i)];
+      if (FIRST) dv[i] = ldc(c.dinv, vidx(yy, w * NPW + i) + cofs);
     }
     if (has_h) {
-      const int64_t q = vidx(yy, hc);
-      v[NPW] = zsrc[q * S + lane];
-      if (FIRST) dv[NPW] = ldc(c.dinv, q + cofs);
+      v[NPW] = zsb[voff(yy, hc)];
+      if (FIRST) dv[NPW] = ldc(c.dinv, vidx(yy, hc) + cofs);
     }
     if (has_o) {
-      const int64_t q = vidx(yy, oc);
-      o = zsrc[q * S + lane];
-      if (FIRST) dv[NPW + 1] = ldc(c.dinv, q + cofs);
+      o = zsb[voff(yy, oc)];
+      if (FIRST) dv[NPW + 1] = ldc(c.dinv, vidx(yy, oc) + cofs);
     }
   };
   // z_1 = Dinv R / theta in the order of cheb_z1
   auto scaled = [&](T raw, T d) -> T { return FIRST ? d * raw * ith : raw; };
-  auto load_pt = [&](const T* __restrict__ a, int yy, T (&v)[NPW + 1]) {
+  auto load_pt = [&](const T* __restrict__ ab, int yy, T (&v)[NPW + 1]) {
 #pragma unroll
-    for (int i = 0; i < NPW; ++i) v[i] = a[vidx(yy, w * NPW + i) * S + lane];
-    if (has_h) v[NPW] = a[vidx(yy, hc) * S + lane];
+    for (int i = 0; i < NPW; ++i) v[i] = ab[voff(yy, w * NPW + i)];
+    if (has_h) v[NPW] = ab[voff(yy, hc)];
   };
   auto put_h1 = [&](int slot, const T (&v)[NPW + 1], T o, int yy) {
     const bool in = row_ok(yy);
@@ -1667,8 +1677,8 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     store_coef(1, 1, cv, csl);
     load_coef(st.y0 - 2, cv, csl);
     store_coef(2, 2, cv, csl);
-    load_pt(R, st.y0 - 2, rA);
-    if (HAS_PREV) load_pt(zprev, st.y0 - 2, pA);
+    load_pt(Rb, st.y0 - 2, rA);
+    if (HAS_PREV) load_pt(pb, st.y0 - 2, pA);
   }
   __syncthreads();
 
@@ -1678,9 +1688,8 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     const int y = st.y0 + s;
     const int r0 = s + 4;
     const int hs = r0 & 1;  // neighbour rows read now; hs ^ 1 written now
-    const int k0 = r0 % 4, k1 = (r0 + 1) % 4, k2 = (r0 + 2) % 4, k3 = (r0 + 3) % 4;
-    const int n0 = r0 % 5, n1 = (r0 + 1) % 5, n2 = (r0 + 2) % 5, n3 = (r0 + 3) % 5,
-              nm = (r0 + 4) % 5;
+    const int k0 = r0 & 7, k1 = (r0 + 1) & 7, k2 = (r0 + 2) & 7, k3 = (r0 + 3) & 7;
+    const int n0 = k0, n1 = k1, n2 = k2, n3 = k3, nm = (r0 + 7) & 7;
     // [A] TSV terms of the three levels (rows y+2, y+1, y), before the next
     // row's loads; a wave with a TSV node waits for its partners here.
     T t1[NPW + 1], t2[NPW + 1], t3[NPW];
@@ -1699,8 +1708,15 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
           if (sl[i] < 0) continue;
           const int64_t v = vidx(y + 2, ccol(i));
           const T gu = ldc(c.up, sl[i]), gd = ldc(c.dn, sl[i]);
-          const T yu = zj_at(gu != T(0) ? v + pd.plane : v);
-          const T yd = zj_at(gd != T(0) ? v - pd.plane : v);
+          T yu, yd;
+          if (FIRST) {
+            yu = zj_at(gu != T(0) ? v + pd.plane : v);
+            yd = zj_at(gd != T(0) ? v - pd.plane : v);
+          } else {
+            const int o = voff(y + 2, ccol(i));
+            yu = zsb[gu != T(0) ? o + plS : o];
+            yd = zsb[gd != T(0) ? o - plS : o];
+          }
           t1[i] = tsv_term(gu, yu, gd, yd);
         }
       }
@@ -1759,8 +1775,8 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     for (int i = 0; i < NPW + 2; ++i) dvn[i] = T(1);
     load_coef(y + 3, cvN, cslN);
     load_zj(y + 4, v1n, o1n, dvn);
-    load_pt(R, y + 3, rN);
-    if (HAS_PREV) load_pt(zprev, y + 3, pN);
+    load_pt(Rb, y + 3, rN);
+    if (HAS_PREV) load_pt(pb, y + 3, pN);
     // [C] level 1: z_{j+1} on row y + 2
     T z1n[NPW + 1];
     {
@@ -1811,7 +1827,7 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     }
     // [E] level 3: z_{j+3} on row y
     if constexpr (lvl3) {
-      const int64_t obase = pd.vbase + st.lrow0 + (int64_t)s * nx;
+      T* ob = outb + r0off;
 #pragma unroll
       for (int i = 0; i < NPW; ++i) {
         const int jc = ccol(i);
@@ -1819,7 +1835,7 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
                                 z2h[0][i], t3[i], cd[k0][jc + 2], ce[k0][jc + 3], ce[k0][jc + 2],
                                 cn[n0][jc + 2], cn[nm][jc + 2], z1h[0][i], rC[i], cdi[k0][jc + 2],
                                 c1, c2);
-        outb[(obase + jc) * S + lane] = z;
+        ob[(s * nx + jc) * S + lane] = z;
       }
     }
     // [F] the east / west z_j row y + 3 and the coefficients of row y + 3
@@ -1849,9 +1865,9 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     // z_{j+2} of row y + 1 if it is a row of this strip (and a later pass
     // needs it)
     if (lvl2 && outa && s + 1 >= 0 && s + 1 < st.nrows) {
-      const int64_t b1row = pd.vbase + st.lrow0 + (int64_t)(s + 1) * nx;
+      T* oa = outa + r0off;
 #pragma unroll
-      for (int i = 0; i < NPW; ++i) outa[(b1row + ccol(i)) * S + lane] = z2n[i];
+      for (int i = 0; i < NPW; ++i) oa[((s + 1) * nx + ccol(i)) * S + lane] = z2n[i];
     }
     __syncthreads();
   };
