@@ -449,9 +449,18 @@ void make_units(const std::vector<PlanDesc>& in, std::vector<PlanDesc>& plans,
   }
 }
 
+// Most rows of one strip for the three-step Chebyshev pass, which addresses
+// a strip's rows through unsigned 32-bit byte offsets from a base three rows
+// before it: (rows + 8) x nx x S floats stay below 2^31 bytes.  0 when even
+// one row does not fit (the pass is then not used).
+int64_t max_strip_rows(int64_t nx) {
+  return std::max<int64_t>(0, (int64_t(1) << 31) / (nx * S * (int64_t)sizeof(float)) - 8);
+}
+
 // Strips for the stencil kernel of a group (float32 block variant): every
 // block's tiers are cut into CH-wide x strips and, when that gives too few
-// workgroups, into y segments, about TARGET_UNITS strips in total.
+// workgroups, into y segments, about TARGET_UNITS strips in total (and no
+// more than max_strip_rows rows each).
 void make_strips(std::vector<PlanDesc>& plans, std::vector<Strip>& strips,
                  int target = TARGET_UNITS) {
   int64_t rows = 0;
@@ -463,7 +472,8 @@ void make_strips(std::vector<PlanDesc>& plans, std::vector<Strip>& strips,
     const int64_t nsx = (nx + CH - 1) / CH;
     const int64_t want = std::max<int64_t>(1, (target * p.n + rows - 1) / std::max<int64_t>(rows, 1));
     const int64_t ysegs = std::min<int64_t>(ny, std::max<int64_t>(1, (want + nt * nsx - 1) / (nt * nsx)));
-    const int64_t H = (ny + ysegs - 1) / ysegs;
+    const int64_t hcap = max_strip_rows(nx);
+    const int64_t H = std::min<int64_t>((ny + ysegs - 1) / ysegs, std::max<int64_t>(hcap, 1));
     p.strip_begin = (int32_t)strips.size();
     for (int64_t t = 0; t < nt; ++t)
       for (int64_t y0 = 0; y0 < ny; y0 += H)
@@ -662,7 +672,8 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     if (cheb && (rs = ensure(ws.Zb, vec)) != REFF_OK) return rs;
     if (cheb && o.cheb > 2 && (rs = ensure(ws.Zc, vec)) != REFF_OK) return rs;
     if (cheb && o.cheb > 2 && (rs = ensure(ws.Zd, vec)) != REFF_OK) return rs;
-    const bool triples = cheb && o.cheb > 3;
+    bool triples = cheb && o.cheb > 3;
+    for (const PlanDesc& p : plans) triples = triples && max_strip_rows(p.nx) >= 1;
     if (triples && (rs = ensure(ws.TA, (size_t)slot_rows * 5 * S * tsz)) != REFF_OK) return rs;
     if (triples && (rs = ensure(ws.TB, (size_t)slot_rows * S * tsz)) != REFF_OK) return rs;
     if ((rs = ensure(ws.part, (size_t)std::max(nu, ns) * NGRAM * S * S * sizeof(double))) != REFF_OK)
@@ -764,8 +775,8 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       b.Zb = ws.Zb.p;
       b.Zc = ws.Zc.p;
       b.Zd = ws.Zd.p;
-      b.TA = ws.TA.p;
-      b.TB = ws.TB.p;
+      b.TA = triples ? ws.TA.p : nullptr;  // no three-step passes without them
+      b.TB = triples ? ws.TB.p : nullptr;
       b.max_tsv_cols = max_cols;
     }
 

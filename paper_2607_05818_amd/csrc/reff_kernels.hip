@@ -1547,16 +1547,22 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     cc = min(max(cc, -x0), nx - 1 - x0);
     return pd.vbase + st.lrow0 + (int64_t)(yy - st.y0) * nx + cc;
   };
-  // Vector accesses go through strip-relative 32-bit element offsets from
-  // per-strip base pointers (a node's offset stays within the stack: at most
-  // a tier plus a strip's rows away, far below 2^31 elements).
+  // The strip's own rows are read and written through unsigned 32-bit byte
+  // offsets from per-strip base pointers placed three rows and three columns
+  // before its first node, so that every offset is non-negative (the host
+  // keeps (nrows + 8) nx S sizeof(float) below 2^31); TSV partners, a tier
+  // away, use 64-bit indices.
   const int64_t r0off = (pd.vbase + st.lrow0) * S;
-  auto voff = [&](int yy, int cc) -> int {
+  const int64_t bias = (3 * (int64_t)nx + 3) * S;
+  const uint32_t lane4 = (uint32_t)lane * 4u;
+  auto boff = [&](int yy, int cc) -> uint32_t {
     yy = min(max(yy, 0), ny - 1);
     cc = min(max(cc, -x0), nx - 1 - x0);
-    return ((yy - st.y0) * nx + cc) * S + lane;
+    return (uint32_t)((yy - st.y0 + 3) * nx + cc + 3) * (uint32_t)(S * sizeof(T)) + lane4;
   };
-  const int plS = (int)pd.plane * S;
+  auto at = [](const T* base, uint32_t off) -> T {
+    return *(const T*)((const char*)base + off);
+  };
   auto srow = [&](int q) -> int64_t { return pd.sbase + (q - pd.slot_begin); };
   // halo column of waves 0-3 (levels 1 and 2; level 2 uses waves 1, 2):
   // -2, -1, wdt, wdt + 1; outer z_j column of waves 4, 5: -3, wdt + 2.
@@ -1579,21 +1585,21 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
   auto zj_at = [&](int64_t v) -> T {
     return FIRST ? cheb_z1(c, R, v, cofs, ith) : zin[v * S + lane];
   };
-  const T* zsb = (FIRST ? R : zin) + r0off;
-  const T* Rb = R + r0off;
-  const T* pb = HAS_PREV ? zprev + r0off : nullptr;
+  const T* zsb = (FIRST ? R : zin) + (r0off - bias);
+  const T* Rb = R + (r0off - bias);
+  const T* pb = HAS_PREV ? zprev + (r0off - bias) : nullptr;
   auto load_zj = [&](int yy, T (&v)[NPW + 1], T& o, T (&dv)[NPW + 2]) {
 #pragma unroll
     for (int i = 0; i < NPW; ++i) {
-      v[i] = zsb[voff(yy, w * NPW + i)];
+      v[i] = at(zsb, boff(yy, w * NPW + i));
       if (FIRST) dv[i] = ldc(c.dinv, vidx(yy, w * NPW + i) + cofs);
     }
     if (has_h) {
-      v[NPW] = zsb[voff(yy, hc)];
+      v[NPW] = at(zsb, boff(yy, hc));
       if (FIRST) dv[NPW] = ldc(c.dinv, vidx(yy, hc) + cofs);
     }
     if (has_o) {
-      o = zsb[voff(yy, oc)];
+      o = at(zsb, boff(yy, oc));
       if (FIRST) dv[NPW + 1] = ldc(c.dinv, vidx(yy, oc) + cofs);
     }
   };
@@ -1601,8 +1607,8 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
   auto scaled = [&](T raw, T d) -> T { return FIRST ? d * raw * ith : raw; };
   auto load_pt = [&](const T* __restrict__ ab, int yy, T (&v)[NPW + 1]) {
 #pragma unroll
-    for (int i = 0; i < NPW; ++i) v[i] = ab[voff(yy, w * NPW + i)];
-    if (has_h) v[NPW] = ab[voff(yy, hc)];
+    for (int i = 0; i < NPW; ++i) v[i] = at(ab, boff(yy, w * NPW + i));
+    if (has_h) v[NPW] = at(ab, boff(yy, hc));
   };
   auto put_h1 = [&](int slot, const T (&v)[NPW + 1], T o, int yy) {
     const bool in = row_ok(yy);
@@ -1708,15 +1714,8 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
           if (sl[i] < 0) continue;
           const int64_t v = vidx(y + 2, ccol(i));
           const T gu = ldc(c.up, sl[i]), gd = ldc(c.dn, sl[i]);
-          T yu, yd;
-          if (FIRST) {
-            yu = zj_at(gu != T(0) ? v + pd.plane : v);
-            yd = zj_at(gd != T(0) ? v - pd.plane : v);
-          } else {
-            const int o = voff(y + 2, ccol(i));
-            yu = zsb[gu != T(0) ? o + plS : o];
-            yd = zsb[gd != T(0) ? o - plS : o];
-          }
+          const T yu = zj_at(gu != T(0) ? v + pd.plane : v);
+          const T yd = zj_at(gd != T(0) ? v - pd.plane : v);
           t1[i] = tsv_term(gu, yu, gd, yd);
         }
       }
@@ -1827,7 +1826,7 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     }
     // [E] level 3: z_{j+3} on row y
     if constexpr (lvl3) {
-      T* ob = outb + r0off;
+      char* ob = (char*)(outb + r0off);
 #pragma unroll
       for (int i = 0; i < NPW; ++i) {
         const int jc = ccol(i);
@@ -1835,7 +1834,7 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
                                 z2h[0][i], t3[i], cd[k0][jc + 2], ce[k0][jc + 3], ce[k0][jc + 2],
                                 cn[n0][jc + 2], cn[nm][jc + 2], z1h[0][i], rC[i], cdi[k0][jc + 2],
                                 c1, c2);
-        ob[(s * nx + jc) * S + lane] = z;
+        *(T*)(ob + ((uint32_t)(s * nx + jc) * (uint32_t)(S * sizeof(T)) + lane4)) = z;
       }
     }
     // [F] the east / west z_j row y + 3 and the coefficients of row y + 3
@@ -1865,9 +1864,11 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     // z_{j+2} of row y + 1 if it is a row of this strip (and a later pass
     // needs it)
     if (lvl2 && outa && s + 1 >= 0 && s + 1 < st.nrows) {
-      T* oa = outa + r0off;
+      char* oa = (char*)(outa + r0off);
 #pragma unroll
-      for (int i = 0; i < NPW; ++i) oa[((s + 1) * nx + ccol(i)) * S + lane] = z2n[i];
+      for (int i = 0; i < NPW; ++i)
+        *(T*)(oa + ((uint32_t)((s + 1) * nx + ccol(i)) * (uint32_t)(S * sizeof(T)) + lane4)) =
+            z2n[i];
     }
     __syncthreads();
   };
