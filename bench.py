@@ -338,7 +338,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=128)
-    ap.add_argument("--rel-tol", type=float, default=1e-4)
+    ap.add_argument("--rel-tol", type=float, default=1e-3,
+                    help="solver tolerance (default: the metric's 1e-3 bar; every node is "
+                         "still checked against the oracle values)")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--krylov", choices=["block", "indep"], default="block")
     ap.add_argument("--precond-degree", type=int, default=19,

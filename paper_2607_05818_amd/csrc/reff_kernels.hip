@@ -882,23 +882,29 @@ __global__ __launch_bounds__(WG, 4) void k_gram_ab(Coef<T> c, Work wk, const T* 
   const int64_t cofs = u.pd.cbase - u.pd.vbase;
   double acc[2][4];
   zero_acc(acc);
-  for (int64_t base = u.begin; base < u.end; base += CH) {
-    T av[NODES_PER_WAVE], bv[NODES_PER_WAVE];
+  // Rows of the chunk at base (clamped to the unit's last row; zeroed when
+  // staged).  The next chunk's loads are issued before this chunk's Grams.
+  T av[NODES_PER_WAVE], bv[NODES_PER_WAVE], dv[NODES_PER_WAVE];
+  auto load = [&](int64_t base) {
 #pragma unroll
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
       av[i] = A[v * S + lane];
       bv[i] = B[v * S + lane];
-      if (DSCALE) bv[i] *= ldc(c.d, v + cofs);
+      if (DSCALE) dv[i] = ldc(c.d, v + cofs);
     }
+  };
+  load(u.begin);
+  for (int64_t base = u.begin; base < u.end; base += CH) {
 #pragma unroll
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
       const bool ok = base + row < u.end;
       sA[row][lane] = ok ? av[i] : T(0);
-      sB[row][lane] = ok ? bv[i] : T(0);
+      sB[row][lane] = ok ? (DSCALE ? bv[i] * dv[i] : bv[i]) : T(0);
     }
     __syncthreads();
+    load(min(base + CH, u.end - 1));  // the last chunk reads valid rows again
     gram_chunk<T>(sA, sB, w, lane, acc);
     __syncthreads();
   }
