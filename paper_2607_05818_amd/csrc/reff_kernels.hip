@@ -1525,17 +1525,23 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
                                                         float c2, float ith) {
   using T = float;
   constexpr int NPW = NPW3;
-  constexpr int N1 = CH + 4;  // coefficient columns -2 .. CH + 1, index c + 2 (cE: c + 3)
+  constexpr int N1 = CH + 4;  // coefficient columns -2 .. CH + 1, index c + 2
   // East / west neighbour rows, slot (s + 4) & 1 read in iteration s: z_j
   // row y + 2 (columns -3 .. CH + 2, index c + 3), z_{j+1} row y + 1 (index
   // c + 2), z_{j+2} row y (index c + 1); one lane per column, no padding.
   __shared__ T h1[2][CH + 6][S];
   __shared__ T h2[2][CH + 4][S];
   __shared__ T h3[2][CH + 2][S];
-  // coefficients (and cN) of row y + k in slot (s + 4 + k) % 8 (a power of
-  // two: the slot indices are a mask away from the row number)
-  __shared__ T cd[8][N1], cdi[8][N1], ce[8][N1 + 1], cn[8][N1];
-  __shared__ int cslot[8][N1];
+  // Everything a node's step reads besides the iterates, per row and column,
+  // in two 16-byte entries: cfa = {d, Dinv, cE (east coupling), cN (north
+  // coupling)}, cfb = {cW (west coupling, cE of column c - 1), cS (south
+  // coupling, cN of the row below), TSV slot (int bits), 0}.  Row yy is in
+  // ring slot (yy - y0 + 4) & 7 and again 8 slots on, so that the rows y - 1
+  // .. y + 2 read in iteration s sit in the consecutive slots b .. b + 3,
+  // b = (s + 3) & 7: one address per node column and row, the rest fixed
+  // offsets.
+  __shared__ f4v cfa[16][N1];
+  __shared__ f4v cfb[16][N1];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int sidx = wk.sid[logical_block(blockIdx.x, gridDim.x)];
@@ -1626,35 +1632,29 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     if (has_h && (w < 2 || east_ok)) h1[slot][hc + 3][lane] = (in && col_ok(hc)) ? v[NPW] : T(0);
     if (has_o && (w == 4 || east_ok)) h1[slot][oc + 3][lane] = (in && col_ok(oc)) ? o : T(0);
   };
-  // Coefficients of one row, one value per thread t < 5 N1 + 1 (waves 0-2):
-  // d, cE (columns -3 .. CH + 1), cN, Dinv and the TSV slot.
+  // The seven fields of a row's entries, one per thread t < 7 N1 (waves
+  // 0-3): field f = t / N1 of column kcol = t % N1 - 2.  Values outside the
+  // tier's columns are 0 (slot -1); rows are clamped as everywhere (a row
+  // outside the tier multiplies zero iterates).
   const int t = threadIdx.x;
-  const int kind = t < N1 ? 0 : t < 2 * N1 + 1 ? 1 : t < 3 * N1 + 1 ? 2 : t < 4 * N1 + 1 ? 3 : 4;
-  const int kcol = kind == 0   ? t - 2
-                   : kind == 1 ? t - N1 - 3
-                   : kind == 2 ? t - (2 * N1 + 1) - 2
-                   : kind == 3 ? t - (3 * N1 + 1) - 2
-                               : t - (4 * N1 + 1) - 2;
-  const T* csrc = kind == 0 ? c.d : kind == 1 ? c.cE : kind == 2 ? c.cN : c.dinv;
-  auto load_coef = [&](int yy, T& val, int& sl) {
-    if (w < 3) {
-      const int64_t ci = vidx(yy, kcol) + cofs;
-      val = csrc[ci];
-      sl = c.slot[ci];
+  const int kf = t / N1, kcol = t % N1 - 2;
+  const bool has_c = t < 7 * N1;
+  const T* csrc = kf == 0 ? c.d : kf == 1 ? c.dinv : (kf == 2 || kf == 4) ? c.cE : c.cN;
+  const int kc_src = kf == 4 ? kcol - 1 : kcol;  // cW is cE of the column to the west
+  const bool kc_ok = col_ok(kc_src);
+  auto load_coef = [&](int yy, T& val) {
+    if (has_c) {
+      const int64_t ci = vidx(kf == 5 ? yy - 1 : yy, kc_src) + cofs;  // cS: the row below
+      val = kf == 6 ? __int_as_float(c.slot[ci]) : csrc[ci];
     }
   };
-  auto store_coef = [&](int k, int kn, T val, int sl) {
-    const bool ok = col_ok(kcol);
-    if (kind == 0)
-      cd[k][kcol + 2] = ok ? val : T(0);
-    else if (kind == 1)
-      ce[k][kcol + 3] = ok ? val : T(0);
-    else if (kind == 2)
-      cn[kn][kcol + 2] = ok ? val : T(0);
-    else if (kind == 3)
-      cdi[k][kcol + 2] = ok ? val : T(0);
-    else if (t < 5 * N1 + 1)
-      cslot[k][kcol + 2] = ok ? sl : -1;
+  auto store_coef = [&](int k, T val) {
+    if (has_c) {
+      const T v = kf == 6 ? (kc_ok ? val : __int_as_float(-1)) : (kc_ok ? val : T(0));
+      T* e = kf < 4 ? (T*)&cfa[k][kcol + 2] + kf : (T*)&cfb[k][kcol + 2] + (kf - 4);
+      e[0] = v;
+      e[8 * N1 * 4] = v;  // the copy 8 slots on
+    }
   };
 
   // Register history: z_j rows y+1, y+2, y+3 (zA[0..2]), z_{j+1} rows y,
@@ -1672,7 +1672,6 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
   // y0-2, R and z_{j-1} of row y0-2.
   {
     T o = T(0), cv = T(0), dv[NPW + 2];
-    int csl = -1;
 #pragma unroll
     for (int i = 0; i < NPW + 2; ++i) dv[i] = T(1);
 #pragma unroll
@@ -1685,10 +1684,8 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
       if (k == 1) put_h1(0, zA[1], o, st.y0 - 2);
       if (k == 2) oA = o;
     }
-    load_coef(st.y0 - 3, cv, csl);
-    store_coef(1, 1, cv, csl);
-    load_coef(st.y0 - 2, cv, csl);
-    store_coef(2, 2, cv, csl);
+    load_coef(st.y0 - 2, cv);
+    store_coef(2, cv);
     load_pt(Rb, st.y0 - 2, rA);
     if (HAS_PREV) load_pt(pb, st.y0 - 2, pA);
   }
@@ -1700,8 +1697,9 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     const int y = st.y0 + s;
     const int r0 = s + 4;
     const int hs = r0 & 1;  // neighbour rows read now; hs ^ 1 written now
-    const int k0 = r0 & 7, k1 = (r0 + 1) & 7, k2 = (r0 + 2) & 7, k3 = (r0 + 3) & 7;
-    const int n0 = k0, n1 = k1, n2 = k2, n3 = k3, nm = (r0 + 7) & 7;
+    // coefficient slots: rows y - 1 + m at b + m (m = 0 .. 3); row y + 3
+    // is stored into k3 (and k3 + 8)
+    const int b = (r0 + 7) & 7, k3 = (r0 + 3) & 7;
     // [A] TSV terms of the three levels (rows y+2, y+1, y), before the next
     // row's loads; a wave with a TSV node waits for its partners here.
     T t1[NPW + 1], t2[NPW + 1], t3[NPW];
@@ -1710,7 +1708,9 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
       bool any = false;
 #pragma unroll
       for (int i = 0; i <= NPW; ++i) {
-        sl[i] = (i < NPW || has_h) ? __builtin_amdgcn_readfirstlane(cslot[k2][ccol(i) + 2]) : -1;
+        sl[i] = (i < NPW || has_h)
+                    ? __builtin_amdgcn_readfirstlane(__float_as_int(cfb[b + 3][ccol(i) + 2][2]))
+                    : -1;
         any |= sl[i] >= 0;
         t1[i] = T(0);
       }
@@ -1734,7 +1734,7 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
 #pragma unroll
       for (int i = 0; i <= NPW; ++i) {
         sl[i] = (i < NPW || w == 1 || w == 2)
-                    ? __builtin_amdgcn_readfirstlane(cslot[k1][ccol(i) + 2])
+                    ? __builtin_amdgcn_readfirstlane(__float_as_int(cfb[b + 2][ccol(i) + 2][2]))
                     : -1;
         any |= sl[i] >= 0;
       }
@@ -1757,7 +1757,7 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
       bool any = false;
 #pragma unroll
       for (int i = 0; i < NPW; ++i) {
-        sl[i] = __builtin_amdgcn_readfirstlane(cslot[k0][ccol(i) + 2]);
+        sl[i] = __builtin_amdgcn_readfirstlane(__float_as_int(cfb[b + 1][ccol(i) + 2][2]));
         any |= sl[i] >= 0;
       }
       if (any) {
@@ -1775,10 +1775,9 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
     // [B] next row: coefficients of row y + 3 first (written to LDS at the
     // end of this row), then z_j row y + 4, R and z_{j-1} of row y + 3
     T cvN = T(0), v1n[NPW + 1], o1n = T(0), rN[NPW + 1], pN[NPW + 1], dvn[NPW + 2];
-    int cslN = -1;
 #pragma unroll
     for (int i = 0; i < NPW + 2; ++i) dvn[i] = T(1);
-    load_coef(y + 3, cvN, cslN);
+    load_coef(y + 3, cvN);
     load_zj(y + 4, v1n, o1n, dvn);
     load_pt(Rb, y + 3, rN);
     if (HAS_PREV) load_pt(pb, y + 3, pN);
@@ -1790,10 +1789,10 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
       for (int i = 0; i <= NPW; ++i) {
         if (i == NPW && !has_h) break;
         const int cc = ccol(i);
+        const f4v A = cfa[b + 3][cc + 2], B = cfb[b + 3][cc + 2];
         const T z = cheb_node_t(zA[1][i], h1[hs][cc + 4][lane], h1[hs][cc + 2][lane], zA[2][i],
-                                zA[0][i], t1[i], cd[k2][cc + 2], ce[k2][cc + 3], ce[k2][cc + 2],
-                                cn[n2][cc + 2], cn[n1][cc + 2], pA[i], rA[i], cdi[k2][cc + 2],
-                                a1, a2);
+                                zA[0][i], t1[i], A[0], A[2], B[0], A[3], B[1], pA[i], rA[i],
+                                A[1], a1, a2);
         if (i < NPW) {
           const int j = w * NPW + i;
           z1n[i] = in ? z : T(0);
@@ -1815,10 +1814,10 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
       for (int i = 0; i <= NPW; ++i) {
         if (i == NPW && w != 1 && w != 2) break;
         const int cc = ccol(i);
+        const f4v A = cfa[b + 2][cc + 2], B = cfb[b + 2][cc + 2];
         const T z = cheb_node_t(z1h[1][i], h2[hs][cc + 3][lane], h2[hs][cc + 1][lane], z1n[i],
-                                z1h[0][i], t2[i], cd[k1][cc + 2], ce[k1][cc + 3], ce[k1][cc + 2],
-                                cn[n1][cc + 2], cn[n0][cc + 2], zA[0][i], rB[i], cdi[k1][cc + 2],
-                                b1, b2);
+                                z1h[0][i], t2[i], A[0], A[2], B[0], A[3], B[1], zA[0][i], rB[i],
+                                A[1], b1, b2);
         if (i < NPW) {
           const int j = w * NPW + i;
           z2n[i] = in ? z : T(0);
@@ -1836,17 +1835,17 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
 #pragma unroll
       for (int i = 0; i < NPW; ++i) {
         const int jc = ccol(i);
+        const f4v A = cfa[b + 1][jc + 2], B = cfb[b + 1][jc + 2];
         const T z = cheb_node_t(z2h[1][i], h3[hs][jc + 2][lane], h3[hs][jc][lane], z2n[i],
-                                z2h[0][i], t3[i], cd[k0][jc + 2], ce[k0][jc + 3], ce[k0][jc + 2],
-                                cn[n0][jc + 2], cn[nm][jc + 2], z1h[0][i], rC[i], cdi[k0][jc + 2],
-                                c1, c2);
+                                z2h[0][i], t3[i], A[0], A[2], B[0], A[3], B[1], z1h[0][i], rC[i],
+                                A[1], c1, c2);
         *(T*)(ob + ((uint32_t)(s * nx + jc) * (uint32_t)(S * sizeof(T)) + lane4)) = z;
       }
     }
     // [F] the east / west z_j row y + 3 and the coefficients of row y + 3
     // for the next row; then the register histories move down one row.
     put_h1(hs ^ 1, zA[2], oA, y + 3);
-    store_coef(k3, n3, cvN, cslN);
+    store_coef(k3, cvN);
     {
       const bool in4 = row_ok(y + 4);
 #pragma unroll
