@@ -601,7 +601,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     // ---- group of jobs within the row budget
     size_t j1 = j0;
     int64_t rows = 0, slot_rows = 0;
-    int max_cols = 0;  // most TSV columns of one block
+    int max_slots = 0;  // most TSV slots of one block
     std::vector<PlanDesc> pin;
     while (j1 < jobs.size()) {
       const StackInfo& sk = stacks[(size_t)jobs[j1].stack];
@@ -616,7 +616,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       pd.slot_end = sk.slot_end;
       pd.sbase = slot_rows;
       slot_rows += sk.slot_end - sk.slot_begin;
-      max_cols = std::max(max_cols, (int)((sk.slot_end - sk.slot_begin) / (sk.n / sk.plane)));
+      max_slots = std::max(max_slots, (int)(sk.slot_end - sk.slot_begin));
       pin.push_back(pd);
       rows += sk.n;
       ++j1;
@@ -777,7 +777,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       b.Zd = ws.Zd.p;
       b.TA = triples ? ws.TA.p : nullptr;  // no three-step passes without them
       b.TB = triples ? ws.TB.p : nullptr;
-      b.max_tsv_cols = max_cols;
+      b.max_tsv_slots = max_slots;
     }
 
     HIPCHK(launch_init_blocks(fp32, o.indep, coef, b, o.stream));

@@ -203,10 +203,10 @@ struct SolveBuffers {
   void* Zd = nullptr;
   // TSV side buffers of the three-step passes: z_{j+1} at every TSV node and
   // its four in-plane neighbours ([slot row][5][S]) and z_{j+2} at every TSV
-  // node ([slot row][S]); max_tsv_cols = most TSV columns of one block.
+  // node ([slot row][S]); max_tsv_slots = most TSV slots of one block.
   void* TA = nullptr;
   void* TB = nullptr;
-  int max_tsv_cols = 0;
+  int max_tsv_slots = 0;
 };
 
 int grid_for(int64_t n);

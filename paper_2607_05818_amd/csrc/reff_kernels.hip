@@ -1432,63 +1432,70 @@ __global__ __launch_bounds__(WG, sizeof(T) == 4 ? 4 : 2) void k_cheb2_strip(Coef
 //                  neighbour does not exist);
 //   TB[row][S]:    z_{j+2} at every TSV node, from TA.
 // In the first pass of an application (no z_{j-1}) z_j is z_1, formed from R.
-// The slots of a TSV column are consecutive over its tiers, and a node's
-// partners are the next and previous slot, so one workgroup per column forms
-// the column's TA entries, synchronises, then its TB entries.  Grid (columns,
-// active blocks); one wave per item.
-constexpr int TSV_WAVES = 8;
+// Two launches, one wave per item (4 waves per workgroup, no synchronisation
+// inside a launch): k_cheb_tsv_a forms TA item (slot, k), k_cheb_tsv_b then TB
+// item (slot); a node's TSV partners are the next and previous slot (the
+// slots of a TSV column are consecutive over its tiers).  Grid (items / 4,
+// active blocks).
+constexpr int TSV_WAVES = 4;
 
 template <typename T, bool HAS_PREV>
-__global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv(
+__global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv_a(
     Coef<T> c, Work wk, const int32_t* __restrict__ act, const T* __restrict__ zin,
-    const T* __restrict__ zprev, const T* __restrict__ R, T* __restrict__ TA,
-    T* __restrict__ TB, T a1, T a2, T b1, T b2, T ith) {
+    const T* __restrict__ zprev, const T* __restrict__ R, T* __restrict__ TA, T a1, T a2,
+    T ith) {
   constexpr bool FIRST = !HAS_PREV;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const PlanDesc pd = wk.plans[act[blockIdx.y]];
-  const int nt = (int)(pd.n / pd.plane);
-  const int col = blockIdx.x;
-  if (col * nt >= pd.slot_end - pd.slot_begin) return;  // the whole workgroup
+  const int item = blockIdx.x * TSV_WAVES + w;
+  if (item >= 5 * (pd.slot_end - pd.slot_begin)) return;  // the whole wave
   const int nx = pd.nx;
   const int ny = (int)(pd.plane / pd.nx);
+  const int qi = item / 5, k = item % 5;
+  const int64_t loc = c.tnode[pd.slot_begin + qi] - pd.cbase;  // node within the stack
+  const int64_t rem = loc % pd.plane;
+  const int y = (int)(rem / nx), x = (int)(rem % nx);
+  const int dx = k == 1 ? 1 : k == 2 ? -1 : 0, dy = k == 3 ? 1 : k == 4 ? -1 : 0;
+  const int xn = x + dx, yn = y + dy;
+  T z = T(0);
+  if (xn >= 0 && xn < nx && yn >= 0 && yn < ny)
+    z = cheb_point<T, HAS_PREV, FIRST>(c, pd, zin, zprev, R,
+                                       pd.vbase + loc + dx + (int64_t)dy * nx, xn, yn, a1, a2,
+                                       ith);
+  TA[((pd.sbase + qi) * 5 + k) * S + lane] = z;
+}
+
+template <typename T, bool HAS_PREV>
+__global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv_b(
+    Coef<T> c, Work wk, const int32_t* __restrict__ act, const T* __restrict__ zin,
+    const T* __restrict__ R, const T* __restrict__ TA, T* __restrict__ TB, T b1, T b2, T ith) {
+  constexpr bool FIRST = !HAS_PREV;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const PlanDesc pd = wk.plans[act[blockIdx.y]];
+  const int qi = blockIdx.x * TSV_WAVES + w;
+  if (qi >= pd.slot_end - pd.slot_begin) return;  // the whole wave
+  const int nx = pd.nx;
   const int64_t cofs = pd.cbase - pd.vbase;
-  for (int item = w; item < 5 * nt; item += TSV_WAVES) {
-    const int qi = col * nt + item / 5, k = item % 5;
-    const int64_t loc = c.tnode[pd.slot_begin + qi] - pd.cbase;  // node within the stack
-    const int64_t rem = loc % pd.plane;
-    const int y = (int)(rem / nx), x = (int)(rem % nx);
-    const int dx = k == 1 ? 1 : k == 2 ? -1 : 0, dy = k == 3 ? 1 : k == 4 ? -1 : 0;
-    const int xn = x + dx, yn = y + dy;
-    T z = T(0);
-    if (xn >= 0 && xn < nx && yn >= 0 && yn < ny)
-      z = cheb_point<T, HAS_PREV, FIRST>(c, pd, zin, zprev, R,
-                                         pd.vbase + loc + dx + (int64_t)dy * nx, xn, yn, a1, a2,
-                                         ith);
-    TA[((pd.sbase + qi) * 5 + k) * S + lane] = z;
-  }
-  __syncthreads();
-  for (int t = w; t < nt; t += TSV_WAVES) {
-    const int qi = col * nt + t;
-    const int q = pd.slot_begin + qi;
-    const int64_t u = c.tnode[q];  // coefficient index
-    const int64_t loc = u - pd.cbase;
-    const int64_t v = pd.vbase + loc;
-    const int64_t rem = loc % pd.plane;
-    const int y = (int)(rem / nx), x = (int)(rem % nx);
-    const int64_t a = (pd.sbase + qi) * 5;
-    const T gu = ldc(c.up, q), gd = ldc(c.dn, q);
-    const T yu = gu != T(0) ? TA[(a + 5) * S + lane] : T(0);
-    const T yd = gd != T(0) ? TA[(a - 5) * S + lane] : T(0);
-    const T cw = x > 0 ? ldc(c.cE, x > 0 ? u - 1 : u) : T(0);
-    const T cs = y > 0 ? ldc(c.cN, y > 0 ? u - nx : u) : T(0);
-    TB[(pd.sbase + qi) * S + lane] =
-        cheb_node(TA[a * S + lane], TA[(a + 1) * S + lane], TA[(a + 2) * S + lane],
-                  TA[(a + 3) * S + lane], TA[(a + 4) * S + lane], yu, yd, ldc(c.d, u),
-                  ldc(c.cE, u), cw, ldc(c.cN, u), cs, gu, gd,
-                  FIRST ? cheb_z1(c, R, v, cofs, ith) : zin[v * S + lane], R[v * S + lane],
-                  ldc(c.dinv, u), b1, b2);
-  }
+  const int q = pd.slot_begin + qi;
+  const int64_t u = c.tnode[q];  // coefficient index
+  const int64_t loc = u - pd.cbase;
+  const int64_t v = pd.vbase + loc;
+  const int64_t rem = loc % pd.plane;
+  const int y = (int)(rem / nx), x = (int)(rem % nx);
+  const int64_t a = (pd.sbase + qi) * 5;
+  const T gu = ldc(c.up, q), gd = ldc(c.dn, q);
+  const T yu = gu != T(0) ? TA[(a + 5) * S + lane] : T(0);
+  const T yd = gd != T(0) ? TA[(a - 5) * S + lane] : T(0);
+  const T cw = x > 0 ? ldc(c.cE, x > 0 ? u - 1 : u) : T(0);
+  const T cs = y > 0 ? ldc(c.cN, y > 0 ? u - nx : u) : T(0);
+  TB[(pd.sbase + qi) * S + lane] =
+      cheb_node(TA[a * S + lane], TA[(a + 1) * S + lane], TA[(a + 2) * S + lane],
+                TA[(a + 3) * S + lane], TA[(a + 4) * S + lane], yu, yd, ldc(c.d, u),
+                ldc(c.cE, u), cw, ldc(c.cN, u), cs, gu, gd,
+                FIRST ? cheb_z1(c, R, v, cofs, ith) : zin[v * S + lane], R[v * S + lane],
+                ldc(c.dinv, u), b1, b2);
 }
 
 // Three Chebyshev steps in one pass over a strip (float32, block variant):
@@ -1504,7 +1511,7 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv(
 // and west neighbours, double-buffered: each level reads the row written in
 // the previous iteration, and one barrier per row suffices.  TSV partners:
 // z_j from global memory, z_{j+1} and z_{j+2} from the side buffers of
-// k_cheb_tsv.  Without z_{j-1} (the first pass) z_j is z_1 = D^-1 R / theta,
+// k_cheb_tsv_a / _b.  Without z_{j-1} (the first pass) z_j is z_1 = D^-1 R / theta,
 // formed from R (ith = 1 / theta; zin unused), so that no kernel writes z_1.
 // Writes z_{j+2} to outa (null for the last pass: nothing reads it) and
 // z_{j+3} to outb (the next pass's z_{j-1} and z_j); neither may alias an
@@ -2513,16 +2520,22 @@ static T* cheb_steps(const Coef<T>& c, const SolveBuffers& b, hipStream_t st, T*
       coef(j + 1, b1, b2);
       coef(j + 2, c1, c2);
       const T* zp = prev < 0 ? nullptr : buf[prev];
-      if (b.max_tsv_cols > 0) {
-        const dim3 gt(b.max_tsv_cols, b.n_act);
-        if (prev < 0)
-          hipLaunchKernelGGL((k_cheb_tsv<T, false>), gt, dim3(64 * TSV_WAVES), 0, st, c, b.work,
-                             b.act, (const T*)buf[cur], zp, R, (T*)b.TA, (T*)b.TB, a1, a2, b1, b2,
-                             ith);
-        else
-          hipLaunchKernelGGL((k_cheb_tsv<T, true>), gt, dim3(64 * TSV_WAVES), 0, st, c, b.work,
-                             b.act, (const T*)buf[cur], zp, R, (T*)b.TA, (T*)b.TB, a1, a2, b1, b2,
-                             ith);
+      if (b.max_tsv_slots > 0) {
+        const dim3 ga((5 * b.max_tsv_slots + TSV_WAVES - 1) / TSV_WAVES, b.n_act);
+        const dim3 gb((b.max_tsv_slots + TSV_WAVES - 1) / TSV_WAVES, b.n_act);
+        const dim3 tb(64 * TSV_WAVES);
+        const T* zc = (const T*)buf[cur];
+        if (prev < 0) {
+          hipLaunchKernelGGL((k_cheb_tsv_a<T, false>), ga, tb, 0, st, c, b.work, b.act, zc, zp, R,
+                             (T*)b.TA, a1, a2, ith);
+          hipLaunchKernelGGL((k_cheb_tsv_b<T, false>), gb, tb, 0, st, c, b.work, b.act, zc, R,
+                             (const T*)b.TA, (T*)b.TB, b1, b2, ith);
+        } else {
+          hipLaunchKernelGGL((k_cheb_tsv_a<T, true>), ga, tb, 0, st, c, b.work, b.act, zc, zp, R,
+                             (T*)b.TA, a1, a2, ith);
+          hipLaunchKernelGGL((k_cheb_tsv_b<T, true>), gb, tb, 0, st, c, b.work, b.act, zc, R,
+                             (const T*)b.TA, (T*)b.TB, b1, b2, ith);
+        }
       }
       T* o1 = j + 3 == b.cheb_k ? nullptr : buf[f1];  // the last pass's z_{j+2} is not read
       if (prev < 0)
