@@ -143,6 +143,44 @@ def cpu_baseline(desc, batch_nodes, n_timed=2):
     }
 
 
+def grid_pairs_compare(reff, log, M=512, N=512, P=256, reps=3):
+    """Eq. 3 on one uniform tier (the intra-die step of the paper's pair
+    method, Sec. III-C/D): every pair of P seeded points on an M x N grid,
+    output to device memory, checked on sampled pairs against the closed form
+    summed directly in float64.  Each pair is a double sum over (M-1)(N-1)
+    terms of 16 float64 flops (two products, a fused difference, the square,
+    the denominator, a reciprocal by estimate and two Newton steps, the
+    accumulation)."""
+    import numpy as np
+    import torch
+    from tests import pins
+    rng = np.random.default_rng(3001)
+    r, s = (float(v) for v in rng.uniform(0.5, 2.0, size=2))
+    flat = rng.choice(M * N, size=P, replace=False)
+    xy = np.stack([flat % M, flat // M], axis=1).astype(np.int32)
+    out = torch.empty((P, P), dtype=torch.float64, device="cuda:0")
+    reff.reff_grid_pairs(M, N, r, s, xy, out)  # warm-up
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        reff.reff_grid_pairs(M, N, r, s, xy, out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - a) / reps
+    R = out.cpu().numpy()
+    pairs = P * (P - 1) // 2
+    terms = pairs * (M - 1) * (N - 1)
+    err = 0.0
+    for i, j in [(0, 1), (7, 200), (100, 255), (31, 32)]:
+        w = pins.wu_two_point(M, N, r, s, *xy[i], *xy[j])
+        err = max(err, abs(R[i, j] - w) / w)
+    tflops = 16.0 * terms / dt / 1e12
+    log(f"grid pairs (Eq. 3): {pairs / dt:.3g} pairs/s, {tflops:.1f} TFLOP/s float64, err {err:.1e}")
+    return {"workload": f"Eq. 3, all pairs of {P} seeded points on a uniform {M} x {N} grid",
+            "pairs_per_s": pairs / dt, "seconds": dt, "terms_per_s": terms / dt,
+            "fp64_tflops": tflops, "fp64_vector_peak_tflops": 78.6,
+            "frac": tflops / 78.6, "bound": "alu", "max_rel_err_sampled": err}
+
+
 def batched_compare(reff, gen, log, rel_tol, n_seq=16):
     """The batching workload: 256 candidate TSV plans (2-4 tiers, sides
     64-256, about 22M nodes in total) with one seeded 64-node block per
@@ -496,6 +534,8 @@ def main():
                             "max_rel_err": e2, "rel_tol": tol}
             log(f"{tag}: {S / dt:.1f} nodes/s, {st2['iters_total']} iterations, err {e2:.2e}")
 
+    if not args.no_compare:
+        compare["grid_pairs"] = grid_pairs_compare(reff, log)
     if not args.no_batched and args.precision == "mixed":
         compare["batched_plans"] = batched_compare(reff, gen, log, args.rel_tol)
     if not args.no_surrogate and args.precision == "mixed":

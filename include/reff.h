@@ -212,6 +212,26 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
                              double* const* R_out, const reff_batch_opts* opts,
                              reff_solve_stats* per_plan);
 
+/*
+ * Two-point resistances of every pair of P points on one uniform M x N
+ * resistor grid by the closed form of Eq. 3 (Sec. II-B): x in [0, M) along
+ * the edges of resistance r, y in [0, N) along those of resistance s.  It is
+ * the intra-die building block of the paper's divide-and-conquer pair method
+ * for uniformly meshed tiers (Sec. III-C/D, TSV-TSV and bump/load-TSV
+ * resistances of one die); each pair (i < j) is evaluated once and mirrored,
+ * the double sum with cosines of multiple angles from the multiple-angle
+ * recurrence (the GPU evaluation of Sec. III-D).
+ *   xy       host int32[2 P]: point k at (xy[2k], xy[2k+1]).
+ *   R_out    float64[P*P] row-major (host, or device if out_on_device);
+ *            R(k,k) = 0, R(i,j) = R(j,i).
+ *   stream   hipStream_t to run on; NULL => default stream.  The call
+ *            returns after R_out is written.
+ * Errors: INVALID_ARG (M, N < 1, r or s not finite and positive, P < 0, a
+ * point off the grid, NULL pointers with P > 0), OUT_OF_MEMORY, DEVICE.
+ */
+reff_status reff_grid_pairs(int32_t M, int32_t N, double r, double s, const int32_t* xy,
+                            int64_t P, double* R_out, int32_t out_on_device, void* stream);
+
 /* Static description of a status code. */
 const char* reff_status_string(reff_status s);
 

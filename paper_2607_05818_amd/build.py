@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libreff.so")
 
-SOURCES = ["reff_api.cpp", "reff_kernels.hip", "surrogate_api.cpp", "surrogate_kernels.hip"]
+SOURCES = ["reff_api.cpp", "reff_kernels.hip", "grid_pairs.hip", "surrogate_api.cpp",
+           "surrogate_kernels.hip"]
 
 # Packed FP32 arithmetic is disabled for every HIP translation unit.
 HIP_FLAGS = [

@@ -114,6 +114,9 @@ _lib.reff_batch_plans.argtypes = [C.POINTER(reff_pdn_desc), C.c_int32,
                                   C.POINTER(C.c_void_p), C.POINTER(reff_batch_opts),
                                   C.POINTER(reff_solve_stats)]
 _lib.reff_batch_plans.restype = C.c_int
+_lib.reff_grid_pairs.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_void_p,
+                                 C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]
+_lib.reff_grid_pairs.restype = C.c_int
 _lib.reff_status_string.argtypes = [C.c_int]
 _lib.reff_status_string.restype = C.c_char_p
 _lib.reff_last_error.argtypes = []
@@ -271,6 +274,31 @@ def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
     _check(_lib.reff_query_pairs(pdn.handle, a.ctypes.data, m, b.ctypes.data, n, int(mode),
                                  optr, C.byref(o), C.byref(st)))
     return R_out, st.as_dict()
+
+
+def reff_grid_pairs(M, N, r, s, xy, R_out=None, *, stream=None):
+    """Eq. 3 two-point resistances of every pair of points on a uniform
+    M x N grid (edges r along x, s along y).  xy: (P, 2) integer points.
+    Returns the P x P matrix (R_out if given: numpy or a torch CUDA tensor)."""
+    pts = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
+    P = len(pts)
+    if R_out is None:
+        R_out = np.empty((P, P), dtype=np.float64)
+    out_dev = _is_torch_cuda(R_out)
+    if out_dev:
+        assert R_out.dtype.__repr__().endswith("float64") and R_out.is_contiguous()
+        assert R_out.numel() >= P * P
+        optr = R_out.data_ptr()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+    else:
+        assert R_out.dtype == np.float64 and R_out.flags.c_contiguous and R_out.size >= P * P
+        optr = R_out.ctypes.data
+    _check(_lib.reff_grid_pairs(int(M), int(N), float(r), float(s), pts.ctypes.data, P, optr,
+                                1 if out_dev else 0,
+                                C.c_void_p(int(stream) if stream is not None else 0)))
+    return R_out
 
 
 def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.0,
