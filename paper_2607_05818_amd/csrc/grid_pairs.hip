@@ -7,12 +7,14 @@
 //       + 2 / (M N) sum_{m=1}^{M-1} sum_{n=1}^{N-1}
 //           (cos(m t xh1) cos(n u yh1) - cos(m t xh2) cos(n u yh2))^2
 //           / ((1 - cos(m t)) / r + (1 - cos(n u)) / s),
-// t = pi / M, u = pi / N.  One wave per pair (i < j; the mirror is written
-// by the same wave): lanes own n (WN values each per chunk of 64 WN), the m
-// loop runs in order and takes cos(m t xh) from the multiple-angle recurrence
-// cos((m+1) a) = 2 cos(a) cos(m a) - cos((m-1) a), as the paper's GPU
-// evaluation does (Sec. III-D); the m-dependent part of the denominator is a
-// per-workgroup LDS table.
+// t = pi / M, u = pi / N.  The denominator does not depend on the pair:
+// k_grid_weights stores its reciprocal W[m][n] once per call ((M-1)(N-1)
+// float64, cache-resident at the sizes of a tier).  k_grid_pairs then gives
+// each wave GP_PW pairs (i, j) with one i: lanes own n (GP_WN values each
+// per chunk of 64 GP_WN), the m loop runs in order and takes cos(m t xh)
+// from the multiple-angle recurrence cos((m+1) a) = 2 cos(a) cos(m a) -
+// cos((m-1) a), as the paper's GPU evaluation does (Sec. III-D), and each
+// W entry loaded serves the wave's GP_PW pairs.
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <stdint.h>
@@ -25,73 +27,117 @@
 namespace reff {
 namespace {
 
-constexpr int GP_WAVES = 4;      // pairs per workgroup (one wave each)
-constexpr int GP_WN = 8;         // n values per lane and chunk
-constexpr int GP_MMAX = 4096;    // LDS table of (1 - cos(m t)) / r
+constexpr int GP_WAVES = 4;   // waves per workgroup
+constexpr int GP_PW = 4;      // pairs per wave (one row point i, GP_PW columns j)
+constexpr int GP_WN = 8;      // n values per lane and chunk
 
-// 1/x for x > 0: hardware estimate and two Newton steps (float64 accuracy).
-__device__ __forceinline__ double grid_rcp(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
-  return fma(y, e, y);
+// W[(m-1)(N-1) + n-1] = 1 / ((1 - cos(m t)) / r + (1 - cos(n u)) / s).
+__global__ __launch_bounds__(256) void k_grid_weights(int M, int N, double r, double s,
+                                                      double* __restrict__ W) {
+  const int64_t total = (int64_t)(M - 1) * (N - 1);
+  const double t = M_PI / M, u = M_PI / N;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(q / (N - 1)) + 1, n = (int)(q % (N - 1)) + 1;
+    W[q] = 1.0 / ((1.0 - cos(m * t)) / r + (1.0 - cos(n * u)) / s);
+  }
 }
 
-// Grid (ceil(P / GP_WAVES), P): row i = blockIdx.y, column j = blockIdx.x *
-// GP_WAVES + wave; waves with j < i exit (their pair is the mirror of one
-// evaluated by another wave), j == i writes the zero diagonal.
+// Grid (ceil(P / (GP_WAVES GP_PW)), P): row point i = blockIdx.y; wave w
+// takes the columns j = (blockIdx.x GP_WAVES + w) GP_PW + q, q < GP_PW.
+// Pairs with j <= i or j >= P are formed with a valid stand-in column and
+// not written (their values come from the mirror pair); a wave with no
+// pair to write exits.  The diagonal is written as 0 by the wave of j = i.
 __global__ __launch_bounds__(64 * GP_WAVES) void k_grid_pairs(int M, int N, double r, double s,
                                                              const int32_t* __restrict__ xy,
+                                                             const double* __restrict__ W,
                                                              int64_t P, double* __restrict__ out) {
-  __shared__ double dm[GP_MMAX];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const double t = M_PI / M, u = M_PI / N;
-  for (int m = threadIdx.x; m < M && m < GP_MMAX; m += blockDim.x) dm[m] = (1.0 - cos(m * t)) / r;
-  __syncthreads();
   const int64_t i = blockIdx.y;
-  const int64_t j = (int64_t)blockIdx.x * GP_WAVES + w;
-  if (j < i || j >= P) return;  // the whole wave
-  if (j == i) {
-    if (lane == 0) out[i * P + i] = 0.0;
-    return;
+  const int64_t j0 = ((int64_t)blockIdx.x * GP_WAVES + w) * GP_PW;
+  if (j0 + GP_PW - 1 < i || j0 >= P) return;  // the whole wave: nothing to write
+  const double t = M_PI / M, u = M_PI / N;
+  const int x1 = xy[2 * i], y1 = xy[2 * i + 1];
+  const double xh1 = x1 + 0.5, yh1 = y1 + 0.5;
+  int x2[GP_PW], y2[GP_PW];
+  double xh2[GP_PW], yh2[GP_PW], c2[GP_PW];
+#pragma unroll
+  for (int q = 0; q < GP_PW; ++q) {
+    const int64_t j = min(j0 + q, P - 1);
+    x2[q] = xy[2 * j];
+    y2[q] = xy[2 * j + 1];
+    xh2[q] = x2[q] + 0.5;
+    yh2[q] = y2[q] + 0.5;
+    c2[q] = cos(xh2[q] * t);
   }
-  const int x1 = xy[2 * i], y1 = xy[2 * i + 1], x2 = xy[2 * j], y2 = xy[2 * j + 1];
-  const double xh1 = x1 + 0.5, xh2 = x2 + 0.5, yh1 = y1 + 0.5, yh2 = y2 + 0.5;
-  const double c1 = cos(xh1 * t), c2 = cos(xh2 * t);  // cos(a) of the two recurrences
-  double acc = 0.0;
+  const double c1 = cos(xh1 * t);
+  double acc[GP_PW];
+#pragma unroll
+  for (int q = 0; q < GP_PW; ++q) acc[q] = 0.0;
   for (int n0 = 1; n0 < N; n0 += 64 * GP_WN) {
-    double b1[GP_WN], b2[GP_WN], e[GP_WN];
+    double b1[GP_WN], b2[GP_PW][GP_WN];
+    int nw[GP_WN];  // column of this lane's n in W (clamped; b = 0 past N - 1)
 #pragma unroll
     for (int k = 0; k < GP_WN; ++k) {
       const int n = n0 + lane + 64 * k;
       const bool ok = n < N;
-      b1[k] = ok ? cos(n * u * yh1) : 0.0;  // a lane past N - 1 adds 0
-      b2[k] = ok ? cos(n * u * yh2) : 0.0;
-      e[k] = ok ? (1.0 - cos(n * u)) / s : 1.0;
+      nw[k] = ok ? n - 1 : 0;
+      b1[k] = ok ? cos(n * u * yh1) : 0.0;
+#pragma unroll
+      for (int q = 0; q < GP_PW; ++q) b2[q][k] = ok ? cos(n * u * yh2[q]) : 0.0;
     }
-    // cos(m a) for m = 1 (a1, a2) and m = 0 (p1, p2)
-    double a1 = c1, a2 = c2, p1 = 1.0, p2 = 1.0;
+    // cos(m a) at m = 1 (a*) and m = 0 (p*) for the row point and the columns
+    double a1 = c1, p1 = 1.0, a2[GP_PW], p2[GP_PW];
+#pragma unroll
+    for (int q = 0; q < GP_PW; ++q) a2[q] = c2[q], p2[q] = 1.0;
+    // W row m - 1, loaded one m ahead (the last row is loaded again at the end)
+    double wn[GP_WN];
+#pragma unroll
+    for (int k = 0; k < GP_WN; ++k) wn[k] = M > 1 ? W[nw[k]] : 0.0;
     for (int m = 1; m < M; ++m) {
-      const double d = m < GP_MMAX ? dm[m] : (1.0 - cos(m * t)) / r;
+      double wc[GP_WN];
+      const double* Wn = W + (int64_t)min(m, M - 2) * (N - 1);  // row of m + 1
 #pragma unroll
       for (int k = 0; k < GP_WN; ++k) {
-        const double num = fma(a1, b1[k], -a2 * b2[k]);
-        acc = fma(num * num, grid_rcp(d + e[k]), acc);
+        wc[k] = wn[k];
+        wn[k] = Wn[nw[k]];
       }
-      const double q1 = fma(2.0 * c1, a1, -p1), q2 = fma(2.0 * c2, a2, -p2);
-      p1 = a1, p2 = a2, a1 = q1, a2 = q2;
+#pragma unroll
+      for (int k = 0; k < GP_WN; ++k) {
+        const double wt = wc[k];
+        const double f1 = a1 * b1[k];
+#pragma unroll
+        for (int q = 0; q < GP_PW; ++q) {
+          const double num = fma(-a2[q], b2[q][k], f1);
+          acc[q] = fma(num * num, wt, acc[q]);
+        }
+      }
+      const double q1 = fma(2.0 * c1, a1, -p1);
+      p1 = a1, a1 = q1;
+#pragma unroll
+      for (int q = 0; q < GP_PW; ++q) {
+        const double qq = fma(2.0 * c2[q], a2[q], -p2[q]);
+        p2[q] = a2[q], a2[q] = qq;
+      }
     }
   }
-  // sum over the lanes
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (lane == 0) {
-    const double R = r * fabs((double)(x1 - x2)) / N + s * fabs((double)(y1 - y2)) / M +
-                     2.0 / ((double)M * N) * acc;
-    out[i * P + j] = R;
-    out[j * P + i] = R;
+  for (int q = 0; q < GP_PW; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int64_t j = j0 + q;
+    if (lane == 0 && j < P) {
+      if (j == i) {
+        out[i * P + i] = 0.0;
+      } else if (j > i) {
+        const double R = r * fabs((double)(x1 - x2[q])) / N + s * fabs((double)(y1 - y2[q])) / M +
+                         2.0 / ((double)M * N) * v;
+        out[i * P + j] = R;
+        out[j * P + i] = R;
+      }
+    }
   }
 }
 
@@ -119,28 +165,44 @@ extern "C" reff_status reff_grid_pairs(int32_t M, int32_t N, double r, double s,
   };
   int32_t* dxy = nullptr;
   double* dout = nullptr;
+  double* dW = nullptr;
+  const size_t nw = (size_t)(M - 1) * (N - 1);
   hipError_t e = hipMalloc((void**)&dxy, (size_t)P * 2 * sizeof(int32_t));
   if (e != hipSuccess) return dev_fail(e, "hipMalloc");
+  e = hipMalloc((void**)&dW, std::max<size_t>(nw, 1) * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipFree(dxy);
+    return dev_fail(e, "hipMalloc");
+  }
   const size_t obytes = (size_t)P * P * sizeof(double);
   if (!out_on_device) {
     e = hipMalloc((void**)&dout, obytes);
     if (e != hipSuccess) {
       (void)hipFree(dxy);
+      (void)hipFree(dW);
       return dev_fail(e, "hipMalloc");
     }
   }
   double* o = out_on_device ? R_out : dout;
   e = hipMemcpyAsync(dxy, xy, (size_t)P * 2 * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && nw > 0) {
+    const int64_t blocks = std::min<int64_t>((int64_t)((nw + 255) / 256), 4096);
+    hipLaunchKernelGGL(k_grid_weights, dim3((unsigned)blocks), dim3(256), 0, st, (int)M, (int)N,
+                       r, s, dW);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) {
-    const dim3 grid((unsigned)((P + GP_WAVES - 1) / GP_WAVES), (unsigned)P);
+    const int64_t per = (int64_t)GP_WAVES * GP_PW;
+    const dim3 grid((unsigned)((P + per - 1) / per), (unsigned)P);
     hipLaunchKernelGGL(k_grid_pairs, grid, dim3(64 * GP_WAVES), 0, st, (int)M, (int)N, r, s, dxy,
-                       P, o);
+                       (const double*)dW, P, o);
     e = hipGetLastError();
   }
   if (e == hipSuccess && !out_on_device)
     e = hipMemcpyAsync(R_out, dout, obytes, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(dxy);
+  (void)hipFree(dW);
   if (dout) (void)hipFree(dout);
   if (e != hipSuccess) return dev_fail(e, "grid pairs");
   return REFF_OK;
