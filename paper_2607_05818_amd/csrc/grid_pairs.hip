@@ -7,14 +7,14 @@
 //       + 2 / (M N) sum_{m=1}^{M-1} sum_{n=1}^{N-1}
 //           (cos(m t xh1) cos(n u yh1) - cos(m t xh2) cos(n u yh2))^2
 //           / ((1 - cos(m t)) / r + (1 - cos(n u)) / s),
-// t = pi / M, u = pi / N.  The denominator does not depend on the pair:
+// t = pi / M, u = pi / N.  The denominator does not depend on the pair, so
 // k_grid_weights stores its reciprocal W[m][n] once per call ((M-1)(N-1)
-// float64, cache-resident at the sizes of a tier).  k_grid_pairs then gives
-// each wave GP_PW pairs (i, j) with one i: lanes own n (GP_WN values each
-// per chunk of 64 GP_WN), the m loop runs in order and takes cos(m t xh)
-// from the multiple-angle recurrence cos((m+1) a) = 2 cos(a) cos(m a) -
-// cos((m-1) a), as the paper's GPU evaluation does (Sec. III-D), and each
-// W entry loaded serves the wave's GP_PW pairs.
+// float64, cache-resident at the sizes of a tier).  With X_i[m][n] =
+// cos(m t xh_i) cos(n u yh_i) the double sum of a pair is T_ii + T_jj -
+// 2 T_ij, T = X diag(W) X^T: a float64 product over K = (M-1)(N-1) that
+// runs on the matrix cores (k_grid_gram), its m factors from the
+// multiple-angle recurrence cos((m+1) a) = 2 cos(a) cos(m a) - cos((m-1) a)
+// as in the paper's GPU evaluation (Sec. III-D); k_grid_finish forms R.
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <stdint.h>
@@ -26,10 +26,6 @@
 
 namespace reff {
 namespace {
-
-constexpr int GP_WAVES = 4;   // waves per workgroup
-constexpr int GP_PW = 4;      // pairs per wave (one row point i, GP_PW columns j)
-constexpr int GP_WN = 8;      // n values per lane and chunk
 
 // W[(m-1)(N-1) + n-1] = 1 / ((1 - cos(m t)) / r + (1 - cos(n u)) / s).
 __global__ __launch_bounds__(256) void k_grid_weights(int M, int N, double r, double s,
@@ -43,101 +39,137 @@ __global__ __launch_bounds__(256) void k_grid_weights(int M, int N, double r, do
   }
 }
 
-// Grid (ceil(P / (GP_WAVES GP_PW)), P): row point i = blockIdx.y; wave w
-// takes the columns j = (blockIdx.x GP_WAVES + w) GP_PW + q, q < GP_PW.
-// Pairs with j <= i or j >= P are formed with a valid stand-in column and
-// not written (their values come from the mirror pair); a wave with no
-// pair to write exits.  The diagonal is written as 0 by the wave of j = i.
-__global__ __launch_bounds__(64 * GP_WAVES) void k_grid_pairs(int M, int N, double r, double s,
-                                                             const int32_t* __restrict__ xy,
-                                                             const double* __restrict__ W,
-                                                             int64_t P, double* __restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t i = blockIdx.y;
-  const int64_t j0 = ((int64_t)blockIdx.x * GP_WAVES + w) * GP_PW;
-  if (j0 + GP_PW - 1 < i || j0 >= P) return;  // the whole wave: nothing to write
-  const double t = M_PI / M, u = M_PI / N;
-  const int x1 = xy[2 * i], y1 = xy[2 * i + 1];
-  const double xh1 = x1 + 0.5, yh1 = y1 + 0.5;
-  int x2[GP_PW], y2[GP_PW];
-  double xh2[GP_PW], yh2[GP_PW], c2[GP_PW];
-#pragma unroll
-  for (int q = 0; q < GP_PW; ++q) {
-    const int64_t j = min(j0 + q, P - 1);
-    x2[q] = xy[2 * j];
-    y2[q] = xy[2 * j + 1];
-    xh2[q] = x2[q] + 0.5;
-    yh2[q] = y2[q] + 0.5;
-    c2[q] = cos(xh2[q] * t);
+// k_grid_gram computes 64 x 64 blocks of T (upper block pairs only) on the
+// float64 matrix cores (16x16x4), the K range split over workgroups by m
+// segment; its operands are formed on the fly: the n factor from a table C[p][n-1] =
+// cos(n u yh_p) staged in LDS per 64-wide chunk of n, the m factor from the
+// multiple-angle recurrence per lane, W from the weight table.  Each
+// segment writes its partial block; k_grid_finish sums them and forms R.
+constexpr int GG_B = 64;    // points per block
+constexpr int GG_NC = 64;   // n values per staged chunk
+
+__global__ __launch_bounds__(256) void k_grid_ncos(int N, const int32_t* __restrict__ xy,
+                                                   int64_t P, double* __restrict__ Cn) {
+  const int64_t total = P * (N - 1);
+  const double u = M_PI / N;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = q / (N - 1);
+    const int n = (int)(q % (N - 1)) + 1;
+    Cn[q] = cos(n * u * (xy[2 * p + 1] + 0.5));
   }
-  const double c1 = cos(xh1 * t);
-  double acc[GP_PW];
+}
+
+// Grid (block pairs, m segments).  Tpart[seg][i][j] for the block pair's
+// i, j (rows of block bi, columns of block bj, bi <= bj); points past P
+// are stand-ins (the last point) whose entries are not written.
+__global__ __launch_bounds__(256) void k_grid_gram(int M, int N, const int32_t* __restrict__ xy,
+                                                   const double* __restrict__ W,
+                                                   const double* __restrict__ Cn, int64_t P,
+                                                   int nb, int mseg, double* __restrict__ Tpart) {
+  __shared__ double BI[GG_B][GG_NC + 1], BJ[GG_B][GG_NC + 1];
+  int q = blockIdx.x, bi = 0;
+  while (q >= nb - bi) q -= nb - bi, ++bi;
+  const int bj = bi + q;
+  const int seg = blockIdx.y;
+  const int mlen = (M - 1 + mseg - 1) / mseg;
+  const int m0 = 1 + seg * mlen, m1 = min(M, m0 + mlen);  // m in [m0, m1)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cc = lane & 15, kr = lane >> 4;
+  const double t = M_PI / M;
+  const int64_t ia = min((int64_t)bi * GG_B + w * 16 + cc, P - 1);
+  int64_t jb[4];
 #pragma unroll
-  for (int q = 0; q < GP_PW; ++q) acc[q] = 0.0;
-  for (int n0 = 1; n0 < N; n0 += 64 * GP_WN) {
-    double b1[GP_WN], b2[GP_PW][GP_WN];
-    int nw[GP_WN];  // column of this lane's n in W (clamped; b = 0 past N - 1)
+  for (int tt = 0; tt < 4; ++tt) jb[tt] = min((int64_t)bj * GG_B + tt * 16 + cc, P - 1);
+  const double xi = xy[2 * ia] + 0.5;
+  double xj[4];
 #pragma unroll
-    for (int k = 0; k < GP_WN; ++k) {
-      const int n = n0 + lane + 64 * k;
+  for (int tt = 0; tt < 4; ++tt) xj[tt] = xy[2 * jb[tt]] + 0.5;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc[4];
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) acc[tt] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int n0 = 1; n0 < N; n0 += GG_NC) {
+    __syncthreads();  // the previous chunk is no longer read
+    for (int e = threadIdx.x; e < GG_B * GG_NC; e += blockDim.x) {
+      const int pt = e / GG_NC, k = e % GG_NC, n = n0 + k;
+      const int64_t pi = min((int64_t)bi * GG_B + pt, P - 1), pj = min((int64_t)bj * GG_B + pt, P - 1);
       const bool ok = n < N;
-      nw[k] = ok ? n - 1 : 0;
-      b1[k] = ok ? cos(n * u * yh1) : 0.0;
-#pragma unroll
-      for (int q = 0; q < GP_PW; ++q) b2[q][k] = ok ? cos(n * u * yh2[q]) : 0.0;
+      BI[pt][k] = ok ? Cn[pi * (N - 1) + (n - 1)] : 0.0;
+      BJ[pt][k] = ok ? Cn[pj * (N - 1) + (n - 1)] : 0.0;
     }
-    // cos(m a) at m = 1 (a*) and m = 0 (p*) for the row point and the columns
-    double a1 = c1, p1 = 1.0, a2[GP_PW], p2[GP_PW];
+    __syncthreads();
+    if (m0 >= m1) continue;
+    // cos(m a) at m = m0 and m0 - 1, then the recurrence
+    double ai = cos(m0 * t * xi), pi_ = cos((m0 - 1) * t * xi), ki = 2.0 * cos(t * xi);
+    double aj[4], pj_[4], kj[4];
 #pragma unroll
-    for (int q = 0; q < GP_PW; ++q) a2[q] = c2[q], p2[q] = 1.0;
-    // W row m - 1, loaded one m ahead (the last row is loaded again at the end)
-    double wn[GP_WN];
+    for (int tt = 0; tt < 4; ++tt) {
+      aj[tt] = cos(m0 * t * xj[tt]);
+      pj_[tt] = cos((m0 - 1) * t * xj[tt]);
+      kj[tt] = 2.0 * cos(t * xj[tt]);
+    }
+    for (int m = m0; m < m1; ++m) {
+      const double* Wm = W + (int64_t)(m - 1) * (N - 1);
 #pragma unroll
-    for (int k = 0; k < GP_WN; ++k) wn[k] = M > 1 ? W[nw[k]] : 0.0;
-    for (int m = 1; m < M; ++m) {
-      double wc[GP_WN];
-      const double* Wn = W + (int64_t)min(m, M - 2) * (N - 1);  // row of m + 1
+      for (int ks = 0; ks < GG_NC / 4; ++ks) {
+        const int k = 4 * ks + kr, n = n0 + k;
+        const double wv = Wm[min(n, N - 1) - 1];
+        const double A = ai * BI[w * 16 + cc][k];
+        const double wk = n < N ? wv : 0.0;
 #pragma unroll
-      for (int k = 0; k < GP_WN; ++k) {
-        wc[k] = wn[k];
-        wn[k] = Wn[nw[k]];
-      }
-#pragma unroll
-      for (int k = 0; k < GP_WN; ++k) {
-        const double wt = wc[k];
-        const double f1 = a1 * b1[k];
-#pragma unroll
-        for (int q = 0; q < GP_PW; ++q) {
-          const double num = fma(-a2[q], b2[q][k], f1);
-          acc[q] = fma(num * num, wt, acc[q]);
+        for (int tt = 0; tt < 4; ++tt) {
+          const double B = wk * aj[tt] * BJ[tt * 16 + cc][k];
+          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, B, acc[tt], 0, 0, 0);
         }
       }
-      const double q1 = fma(2.0 * c1, a1, -p1);
-      p1 = a1, a1 = q1;
+      const double qi = fma(ki, ai, -pi_);
+      pi_ = ai, ai = qi;
 #pragma unroll
-      for (int q = 0; q < GP_PW; ++q) {
-        const double qq = fma(2.0 * c2[q], a2[q], -p2[q]);
-        p2[q] = a2[q], a2[q] = qq;
+      for (int tt = 0; tt < 4; ++tt) {
+        const double qj = fma(kj[tt], aj[tt], -pj_[tt]);
+        pj_[tt] = aj[tt], aj[tt] = qj;
       }
     }
   }
+  double* Ts = Tpart + (int64_t)seg * P * P;
 #pragma unroll
-  for (int q = 0; q < GP_PW; ++q) {
-    double v = acc[q];
+  for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int64_t j = j0 + q;
-    if (lane == 0 && j < P) {
-      if (j == i) {
-        out[i * P + i] = 0.0;
-      } else if (j > i) {
-        const double R = r * fabs((double)(x1 - x2[q])) / N + s * fabs((double)(y1 - y2[q])) / M +
-                         2.0 / ((double)M * N) * v;
-        out[i * P + j] = R;
-        out[j * P + i] = R;
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = (int64_t)bi * GG_B + w * 16 + kr + 4 * r;
+      const int64_t j = (int64_t)bj * GG_B + tt * 16 + cc;
+      if (i < P && j < P) Ts[i * P + j] = acc[tt][r];
     }
+}
+
+// R(i,j) from the summed partial T (its upper blocks): r |dx| / N + s |dy| / M
+// + 2 / (M N) (T_ii + T_jj - 2 T_ij), i != j; R(i,i) = 0.  T_ij is read at
+// (min, max), so both halves of R are the same value.
+__global__ __launch_bounds__(256) void k_grid_finish(int M, int N, double r, double s,
+                                                     const int32_t* __restrict__ xy,
+                                                     const double* __restrict__ Tpart,
+                                                     int mseg, int64_t P,
+                                                     double* __restrict__ out) {
+  const int64_t total = P * P;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = q / P, j = q % P;
+    if (i == j) {
+      out[q] = 0.0;
+      continue;
+    }
+    const int64_t lo = min(i, j), hi = max(i, j);
+    double tii = 0.0, tjj = 0.0, tij = 0.0;
+    for (int g = 0; g < mseg; ++g) {
+      const double* Ts = Tpart + (int64_t)g * P * P;
+      tii += Ts[lo * P + lo];
+      tjj += Ts[hi * P + hi];
+      tij += Ts[lo * P + hi];
+    }
+    const int dx = xy[2 * lo] - xy[2 * hi], dy = xy[2 * lo + 1] - xy[2 * hi + 1];
+    out[q] = r * fabs((double)dx) / N + s * fabs((double)dy) / M +
+             2.0 / ((double)M * N) * (tii + tjj - 2.0 * tij);
   }
 }
 
@@ -163,47 +195,59 @@ extern "C" reff_status reff_grid_pairs(int32_t M, int32_t N, double r, double s,
     return host_fail(e == hipErrorOutOfMemory ? REFF_ERR_OUT_OF_MEMORY : REFF_ERR_DEVICE,
                      std::string(what) + ": " + hipGetErrorString(e));
   };
-  int32_t* dxy = nullptr;
-  double* dout = nullptr;
-  double* dW = nullptr;
+  // 64-point blocks, upper block pairs; the m range split into segments so
+  // that a launch has about 2048 workgroups.
+  const int64_t nb = (P + GG_B - 1) / GG_B;
+  const int64_t nbp = nb * (nb + 1) / 2;
+  const int mseg = (int)std::max<int64_t>(
+      1, std::min<int64_t>(std::max(M - 1, 1), (2048 + nbp - 1) / nbp));
   const size_t nw = (size_t)(M - 1) * (N - 1);
-  hipError_t e = hipMalloc((void**)&dxy, (size_t)P * 2 * sizeof(int32_t));
-  if (e != hipSuccess) return dev_fail(e, "hipMalloc");
-  e = hipMalloc((void**)&dW, std::max<size_t>(nw, 1) * sizeof(double));
-  if (e != hipSuccess) {
-    (void)hipFree(dxy);
-    return dev_fail(e, "hipMalloc");
-  }
+  const size_t ncos = (size_t)P * (N - 1);
+  const size_t tbytes = (size_t)mseg * P * P * sizeof(double);
   const size_t obytes = (size_t)P * P * sizeof(double);
-  if (!out_on_device) {
-    e = hipMalloc((void**)&dout, obytes);
-    if (e != hipSuccess) {
-      (void)hipFree(dxy);
-      (void)hipFree(dW);
-      return dev_fail(e, "hipMalloc");
-    }
+  int32_t* dxy = nullptr;
+  double *dW = nullptr, *dC = nullptr, *dT = nullptr, *dout = nullptr;
+  auto release = [&]() {
+    if (dxy) (void)hipFree(dxy);
+    if (dW) (void)hipFree(dW);
+    if (dC) (void)hipFree(dC);
+    if (dT) (void)hipFree(dT);
+    if (dout) (void)hipFree(dout);
+  };
+  hipError_t e = hipMalloc((void**)&dxy, (size_t)P * 2 * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&dW, std::max<size_t>(nw, 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&dC, std::max<size_t>(ncos, 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&dT, tbytes);
+  if (e == hipSuccess && !out_on_device) e = hipMalloc((void**)&dout, obytes);
+  if (e != hipSuccess) {
+    release();
+    return dev_fail(e, "hipMalloc");
   }
   double* o = out_on_device ? R_out : dout;
   e = hipMemcpyAsync(dxy, xy, (size_t)P * 2 * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  auto grid1 = [](size_t n) { return dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)); };
   if (e == hipSuccess && nw > 0) {
-    const int64_t blocks = std::min<int64_t>((int64_t)((nw + 255) / 256), 4096);
-    hipLaunchKernelGGL(k_grid_weights, dim3((unsigned)blocks), dim3(256), 0, st, (int)M, (int)N,
-                       r, s, dW);
+    hipLaunchKernelGGL(k_grid_weights, grid1(nw), dim3(256), 0, st, (int)M, (int)N, r, s, dW);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && ncos > 0) {
+    hipLaunchKernelGGL(k_grid_ncos, grid1(ncos), dim3(256), 0, st, (int)N, dxy, P, dC);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    const int64_t per = (int64_t)GP_WAVES * GP_PW;
-    const dim3 grid((unsigned)((P + per - 1) / per), (unsigned)P);
-    hipLaunchKernelGGL(k_grid_pairs, grid, dim3(64 * GP_WAVES), 0, st, (int)M, (int)N, r, s, dxy,
-                       (const double*)dW, P, o);
+    hipLaunchKernelGGL(k_grid_gram, dim3((unsigned)nbp, (unsigned)mseg), dim3(256), 0, st, (int)M,
+                       (int)N, dxy, (const double*)dW, (const double*)dC, P, (int)nb, mseg, dT);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_grid_finish, grid1((size_t)P * P), dim3(256), 0, st, (int)M, (int)N, r, s,
+                       dxy, (const double*)dT, mseg, P, o);
     e = hipGetLastError();
   }
   if (e == hipSuccess && !out_on_device)
     e = hipMemcpyAsync(R_out, dout, obytes, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(dxy);
-  (void)hipFree(dW);
-  if (dout) (void)hipFree(dout);
+  release();
   if (e != hipSuccess) return dev_fail(e, "grid pairs");
   return REFF_OK;
 }
