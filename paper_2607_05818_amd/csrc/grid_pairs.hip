@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_grid_gram(int M, int N, const int32_t* 
     }
     for (int m = m0; m < m1; ++m) {
       const double* Wm = W + (int64_t)(m - 1) * (N - 1);
-#pragma unroll
+#pragma unroll 4  // (full unrolling needs 305 registers: one wave per SIMD)
       for (int ks = 0; ks < GG_NC / 4; ++ks) {
         const int k = 4 * ks + kr, n = n0 + k;
         const double wv = Wm[min(n, N - 1) - 1];
