@@ -226,8 +226,13 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
  *            R(k,k) = 0, R(i,j) = R(j,i).
  *   stream   hipStream_t to run on; NULL => default stream.  The call
  *            returns after R_out is written.
- * Errors: INVALID_ARG (M, N < 1, r or s not finite and positive, P < 0, a
- * point off the grid, NULL pointers with P > 0), OUT_OF_MEMORY, DEVICE.
+ * The call allocates and frees its own device work memory: the weight table
+ * ((M-1)(N-1) doubles), a cosine table (P (N-1) doubles) and partial sums of
+ * up to about max(1, 2048 / (P/64)^2 * 2) P^2 doubles (one P^2 array from
+ * P = 4096 on), plus a P^2 staging array when R_out is a host pointer.
+ * Errors: INVALID_ARG (M, N < 1, r or s not finite and positive, P < 0 or
+ * P > 65535, a point off the grid, NULL pointers with P > 0),
+ * OUT_OF_MEMORY, DEVICE.
  */
 reff_status reff_grid_pairs(int32_t M, int32_t N, double r, double s, const int32_t* xy,
                             int64_t P, double* R_out, int32_t out_on_device, void* stream);
