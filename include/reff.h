@@ -227,9 +227,9 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
  *   stream   hipStream_t to run on; NULL => default stream.  The call
  *            returns after R_out is written.
  * The call allocates and frees its own device work memory: the weight table
- * ((M-1)(N-1) doubles), a cosine table (P (N-1) doubles) and partial sums of
- * up to about max(1, 2048 / (P/64)^2 * 2) P^2 doubles (one P^2 array from
- * P = 4096 on), plus a P^2 staging array when R_out is a host pointer.
+ * ((M-1)(N-1) doubles), a cosine table (P (N-1) doubles), partial sums of
+ * the larger of about 16.8M doubles (134 MB) and P^2 doubles, and a P^2
+ * staging array when R_out is a host pointer.
  * Errors: INVALID_ARG (M, N < 1, r or s not finite and positive, P < 0 or
  * P > 65535, a point off the grid, NULL pointers with P > 0),
  * OUT_OF_MEMORY, DEVICE.
