@@ -228,7 +228,7 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
  *            returns after R_out is written.
  * The call allocates and frees its own device work memory: the weight table
  * ((M-1)(N-1) doubles), a cosine table (P (N-1) doubles), partial sums of
- * the larger of about 16.8M doubles (134 MB) and P^2 doubles, and a P^2
+ * at most about 16.8M + P^2 doubles (134 MB + 8 P^2 bytes), and a P^2
  * staging array when R_out is a host pointer.
  * Errors: INVALID_ARG (M, N < 1, r or s not finite and positive, P < 0 or
  * P > 65535, a point off the grid, NULL pointers with P > 0),
