@@ -89,3 +89,33 @@ def test_eight_tiers_with_clustered_tsvs():
     _say("eight tiers, fp64")
     got, st = reff.reff_solve_diag(h, nodes, precision=0, rel_tol=1e-9)
     assert float(np.max(np.abs(got - want) / want)) <= 1e-6
+
+
+def test_wide_tier_falls_back_to_two_step_passes():
+    """A tier too wide for the three-step pass's 32-bit strip offsets (nine
+    rows of 932,100 nodes x 256 B exceed 2^31 B): the host cuts one-row
+    strips and runs two-step passes instead, and the float32 solve at the
+    default degree meets the mixed bar.  A stack with TSVs solved after it
+    on the same device (three-step passes again) does too."""
+    reff = _reff()
+    nx, ny = 932100, 2
+    rng = np.random.default_rng(77)
+    gx = rng.uniform(0.5, 2.0, size=(1, ny, nx - 1))
+    gy = rng.uniform(0.5, 2.0, size=(1, ny - 1, nx))
+    pads = [(x, 0) for x in range(0, nx, 50)]
+    d = gen.make_desc(1, nx, ny, gx, gy, np.zeros((0, 2)), np.zeros((0, 0)), pads)
+    nodes = gen.sample_free_nodes(d, 64, 78)
+    want = ro.diag(d, nodes)
+    _say("wide tier", nx, "x", ny)
+    h = reff.reff_build_pdn(d)
+    got, st = reff.reff_solve_diag(h, nodes, precision=1, rel_tol=1e-4)
+    err = float(np.max(np.abs(got - want) / want))
+    print("wide tier iters", st["iters_total"], "err", err, flush=True)
+    assert err <= 1e-3
+    del h
+    d2 = gen.config2(side=96, n_tsv=48, sigma=8.0)
+    nodes2 = gen.sample_free_nodes(d2, 64, 79)
+    want2 = ro.diag(d2, nodes2)
+    _say("stack after the wide tier")
+    got2, _ = reff.reff_solve_diag(reff.reff_build_pdn(d2), nodes2, precision=1, rel_tol=1e-4)
+    assert float(np.max(np.abs(got2 - want2) / want2)) <= 1e-3
