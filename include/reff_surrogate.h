@@ -21,8 +21,10 @@
  *   encoder 4 levels of two 3x3 convolutions + ReLU with C, 2C, 4C, 8C
  *          channels, 2x2 max pooling between levels;
  *   decoder 2x2 stride-2 transposed convolution (no activation), channel
- *          concatenation with the encoder output of that level, two 3x3
- *          convolutions + ReLU, for levels 3, 2, 1;
+ *          concatenation [transposed-convolution output, then the encoder
+ *          output of that level], two 3x3 convolutions + ReLU, for levels
+ *          3, 2, 1 (the encoder output is that of the level's second
+ *          convolution);
  *   head   1x1 convolution to nt channels = log R of the node (t, x, y).
  * Pads are reported as R = 0.
  *

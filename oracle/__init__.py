@@ -6,6 +6,7 @@ the oracle never imports the product package.
 """
 from .reff_oracle import (GROUNDED, FLOATING, laplacian, grounded, diag,
                           pairs, edge_list, edge_list_fast, pad_nodes)
+from . import selinv
 
 __all__ = ["GROUNDED", "FLOATING", "laplacian", "grounded", "diag", "pairs",
-           "edge_list", "edge_list_fast", "pad_nodes"]
+           "edge_list", "edge_list_fast", "pad_nodes", "selinv"]

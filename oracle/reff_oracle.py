@@ -31,7 +31,9 @@ What it computes (paper references are to arxiv 2607.05818):
   linearity to get m x n pairs from m + n solves (Sec. III-D).
 
 Solves use a dense inverse for small systems and SciPy's sparse LU
-(SuperLU) as a library primitive for larger ones.  Parity unpinned: none.
+(SuperLU) as a library primitive for larger ones.  Full maps of large
+stacks come from oracle/selinv.py (sparse Cholesky + selected inversion),
+which is pinned against this module.  Parity unpinned: none.
 """
 from __future__ import annotations
 

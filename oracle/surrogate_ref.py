@@ -12,8 +12,10 @@ with TSV placement and design-option exploration (Sec. I, Sec. IV-B), where
 many plans of one stack are compared.  The network is this library's
 design, so parity here means "the GPU implements the documented network";
 the pins in tests/test_surrogate_cpu.py tie this reference to brute-force
-loop definitions of each layer type and to finite differences of its own
-gradient.  Parity unpinned: none.
+loop definitions of each layer type, to a loop-written forward pass of the
+whole network as include/reff_surrogate.h documents it (which fails if the
+concatenation order, a pooling step or a skip tensor is wrong), and to
+finite differences of its own gradient.  Parity unpinned: none.
 
 Network (C base channels, nt tiers, input 2 nt + 2 channels):
   e1 = 2 x (3x3 conv + ReLU) to C      at full resolution

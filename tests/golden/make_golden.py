@@ -1,21 +1,26 @@
-"""Write the stored expected values used by the full-size parity tests.
+"""Write the stored expected values used by the full-size parity tests and
+the benchmark's accuracy checks.
 
 Calls only the CPU oracle (and the seeded input generators).  Each fixture
 records the generator call that rebuilds its inputs and the oracle's float64
 R_i = (G^-1)_ii (paper Sec. II-B, Eq. 2 with the bumps merged into the
-grounded supply) for a seeded sample of nodes.
+grounded supply) for a seeded sample of nodes, or for every node.
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py [config2] [config3] [config2_full]
 """
 import json
 import os
 import sys
 import time
+from multiprocessing import Pool
+
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import reff_oracle as ro  # noqa: E402
+from oracle import selinv  # noqa: E402
 from paper_2607_05818_amd import gen  # noqa: E402
 
 SAMPLE_SEED = 2002
@@ -37,27 +42,55 @@ def config2_sample():
     }
 
 
-N_PLANS3 = 8
+def _plan_sample(i):
+    from threadpoolctl import threadpool_limits
+    plans = gen.config3_plans()
+    nodes = gen.config3_samples(plans)
+    with threadpool_limits(1):
+        return selinv.solve_nodes(plans[i], nodes[i])
 
 
 def config3_sample():
+    """Every batching plan's seeded 64-node block: one factorisation and 64
+    unit solves per plan (oracle/selinv.py), plans spread over processes."""
     plans = gen.config3_plans()
     nodes = gen.config3_samples(plans)
     t0 = time.time()
-    R = [ro.diag(plans[i], nodes=nodes[i]) for i in range(N_PLANS3)]
+    with Pool(min(8, os.cpu_count() or 1)) as pool:
+        R = pool.map(_plan_sample, range(len(plans)))
     dt = time.time() - t0
     return {
-        "what": "R_i = (G^-1)_ii, float64 oracle (sparse LU), first batching plans",
-        "inputs": ("plans = gen.config3_plans(seed=1003); nodes = gen.config3_samples(plans); "
-                   "plans 0..7"),
+        "what": ("R_i = (G^-1)_ii, float64 oracle (sparse Cholesky, nested dissection, "
+                 "forward/backward substitution), every batching plan"),
+        "inputs": "plans = gen.config3_plans(seed=1003); nodes = gen.config3_samples(plans)",
         "oracle_seconds": dt,
-        "nodes": [[int(v) for v in nodes[i]] for i in range(N_PLANS3)],
-        "R": [[float(r) for r in R[i]] for i in range(N_PLANS3)],
+        "nodes": [[int(v) for v in nodes[i]] for i in range(len(plans))],
+        "R": [[float(r) for r in R[i]] for i in range(len(plans))],
     }
 
 
+def config2_full():
+    """R_i for all 1,048,576 node ids of the mixed-precision stack (pads 0)
+    by selected inversion, stored as float32 (relative rounding 6e-8, far
+    below the 1e-3 bar it is compared at).  Also checks the values against
+    the per-node SuperLU oracle on the stored sample."""
+    desc = gen.config2()
+    t0 = time.time()
+    R = selinv.diag_full(desc)
+    dt = time.time() - t0
+    with open(os.path.join(HERE, "config2_sample.json")) as f:
+        smp = json.load(f)
+    nodes = np.asarray(smp["nodes"])
+    err = float(np.max(np.abs(R[nodes] - np.asarray(smp["R"])) / np.asarray(smp["R"])))
+    assert err < 1e-12, err
+    np.save(os.path.join(HERE, "config2_fullmap_f32.npy"), R.astype(np.float32))
+    return dt
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["config2", "config3"]
+    which = sys.argv[1:] or ["config2", "config3", "config2_full"]
+    if "config2_full" in which:
+        print("wrote config2_fullmap_f32.npy", config2_full())
     for name, fn in (("config2", config2_sample), ("config3", config3_sample)):
         if name not in which:
             continue

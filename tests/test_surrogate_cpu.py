@@ -118,6 +118,123 @@ def test_reference_gradient_matches_finite_differences():
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
 
 
+# --- the network's composition, written with loops from the header ---------
+
+def _loop_conv(x, w, b, cin, cout, k, relu):
+    """x[Cin][H][W]; header layout W[(kh*K + kw)*Cin + ci][Cout]; output
+    (x, y) reads input (x + kw - (K-1)/2, y + kh - (K-1)/2), zero outside."""
+    _, H, W = x.shape
+    h = (k - 1) // 2
+    out = np.zeros((cout, H, W))
+    for co in range(cout):
+        for yy in range(H):
+            for xx in range(W):
+                s = b[co]
+                for kh in range(k):
+                    for kw in range(k):
+                        sy, sx = yy + kh - h, xx + kw - h
+                        if 0 <= sy < H and 0 <= sx < W:
+                            for ci in range(cin):
+                                s += w[((kh * k + kw) * cin + ci) * cout + co] * x[ci, sy, sx]
+                out[co, yy, xx] = max(s, 0.0) if relu else s
+    return out
+
+
+def _loop_pool(x):
+    c, H, W = x.shape
+    out = np.zeros((c, H // 2, W // 2))
+    for ch in range(c):
+        for yy in range(H // 2):
+            for xx in range(W // 2):
+                out[ch, yy, xx] = max(x[ch, 2 * yy, 2 * xx], x[ch, 2 * yy, 2 * xx + 1],
+                                      x[ch, 2 * yy + 1, 2 * xx], x[ch, 2 * yy + 1, 2 * xx + 1])
+    return out
+
+
+def _loop_up(x, w, b, cin, cout):
+    """Header layout W[ci][(a*2 + b)*Cout + co], bias [(a*2 + b)*Cout + co],
+    output pixel (2x + b, 2y + a)."""
+    _, H, W = x.shape
+    out = np.zeros((cout, 2 * H, 2 * W))
+    for co in range(cout):
+        for yy in range(H):
+            for xx in range(W):
+                for a in range(2):
+                    for c in range(2):
+                        s = b[(a * 2 + c) * cout + co]
+                        for ci in range(cin):
+                            s += w[ci * 4 * cout + (a * 2 + c) * cout + co] * x[ci, yy, xx]
+                        out[co, 2 * yy + a, 2 * xx + c] = s
+    return out
+
+
+def _loop_network(p, x, nt, C, variant=None):
+    """The network as include/reff_surrogate.h documents it, one plan
+    x[2nt+2][ny][nx] -> [nt][ny][nx].  variant plants one mistake."""
+    cin0 = 2 * nt + 2
+    convs = [("e1a", cin0, C), ("e1b", C, C), ("e2a", C, 2 * C), ("e2b", 2 * C, 2 * C),
+             ("e3a", 2 * C, 4 * C), ("e3b", 4 * C, 4 * C), ("b1", 4 * C, 8 * C),
+             ("b2", 8 * C, 8 * C), ("u3", 8 * C, 4 * C), ("d3a", 8 * C, 4 * C),
+             ("d3b", 4 * C, 4 * C), ("u2", 4 * C, 2 * C), ("d2a", 4 * C, 2 * C),
+             ("d2b", 2 * C, 2 * C), ("u1", 2 * C, C), ("d1a", 2 * C, C), ("d1b", C, C),
+             ("head", C, nt)]
+    P, off = {}, 0
+    for name, ci, co in convs:
+        if name.startswith("u"):
+            nw, nb = ci * 4 * co, 4 * co
+        else:
+            k = 1 if name == "head" else 3
+            nw, nb = k * k * ci * co, co
+        P[name] = (p[off:off + nw], p[off + nw:off + nw + nb], ci, co)
+        off += nw + nb
+    assert off == len(p)
+
+    def conv(name, h, relu=True):
+        w, b, ci, co = P[name]
+        return _loop_conv(h, w, b, ci, co, 1 if name == "head" else 3, relu)
+
+    def up(name, h):
+        w, b, ci, co = P[name]
+        return _loop_up(h, w, b, ci, co)
+
+    def cat(u, e):
+        return np.concatenate([e, u] if variant == "concat_swapped" else [u, e])
+
+    e1 = conv("e1b", conv("e1a", x))
+    if variant == "pool_between_convs":
+        e2 = conv("e2b", _loop_pool(conv("e2a", e1)))
+    else:
+        e2 = conv("e2b", conv("e2a", _loop_pool(e1)))
+    e3 = conv("e3b", conv("e3a", _loop_pool(e2)))
+    bt = conv("b2", conv("b1", _loop_pool(e3)))
+    d3 = conv("d3b", conv("d3a", cat(up("u3", bt), e3)))
+    d2 = conv("d2b", conv("d2a", cat(up("u2", d3), e2)))
+    skip1 = e1 if variant != "skip_from_first_conv" else conv("e1a", x)
+    d1 = conv("d1b", conv("d1a", cat(up("u1", d2), skip1)))
+    return conv("head", d1, relu=False)
+
+
+def test_network_composition_matches_loop_definition():
+    """forward() against the network written out with loops from the
+    header's documentation (nt = 1, C = 2, 8 x 8, float64), and each of
+    three plausible composition mistakes (concatenation order, a pooling
+    step in the wrong place, the wrong skip tensor) moves the output far
+    beyond the agreement bar."""
+    nt, C, H, W = 1, 2, 8, 8
+    rng = np.random.default_rng(21)
+    n = sr.num_params(nt, C)
+    p = rng.normal(scale=0.5, size=n)
+    x = rng.normal(size=(2, 2 * nt + 2, H, W))
+    got = sr.forward(torch.as_tensor(p), torch.as_tensor(x), nt, C).numpy()
+    assert got.shape == (2, nt, H, W)
+    for i in range(2):
+        want = _loop_network(p, x[i], nt, C)
+        assert np.allclose(got[i], want, rtol=1e-11, atol=1e-11)
+    for variant in ("concat_swapped", "pool_between_convs", "skip_from_first_conv"):
+        bad = _loop_network(p, x[0], nt, C, variant)
+        assert np.max(np.abs(bad - got[0])) > 1e-3, variant
+
+
 def test_loss_counts_labels_once_and_skips_pads():
     nt, nx, ny = 1, 4, 4
     pred = torch.zeros((1, nt, ny, nx), dtype=torch.float64)
