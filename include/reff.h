@@ -237,6 +237,28 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
 reff_status reff_grid_pairs(int32_t M, int32_t N, double r, double s, const int32_t* xy,
                             int64_t P, double* R_out, int32_t out_on_device, void* stream);
 
+/*
+ * reff_grid_pairs without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * reff_grid_pairs, which it shares its kernels with; its work memory (points,
+ * weights, cosine table, partial Gram blocks, and the staging of R_out when
+ * it is a host pointer) lives in one 64 MiB array per GPU that the library
+ * holds from the first call on that device until the process ends.  Inputs
+ * whose work memory does not fit (one m segment of P^2 doubles plus 8 (M-1)
+ * (N-1) + 8 P (N-1) + 8 P + (host output) 8 P^2 bytes, each part rounded up
+ * to 256 bytes, above 64 MiB; for example P above about 2,800 points) are
+ * rejected with REFF_ERR_INVALID_ARG before any device work.  When fewer m
+ * segments fit than the allocating call uses, the partial sums are grouped
+ * differently (results agree to rounding).  Calls on one GPU share the
+ * array: calls that overlap in time on the same GPU (two host threads, or
+ * two streams) race and must be serialised by the caller.  The call
+ * returns after R_out is written; it makes no hipMalloc or hipFree call.
+ */
+reff_status reff_grid_pairs_noalloc(int32_t M, int32_t N, double r, double s, const int32_t* xy,
+                                    int64_t P, double* R_out, int32_t out_on_device,
+                                    void* stream);
+
 /* Static description of a status code. */
 const char* reff_status_string(reff_status s);
 

@@ -19,6 +19,8 @@
 #include <cmath>
 #include <stdint.h>
 
+#include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -173,13 +175,46 @@ __global__ __launch_bounds__(256) void k_grid_finish(int M, int N, double r, dou
   }
 }
 
-}  // namespace
-}  // namespace reff
+// The four launches of one call: weights, cosine table, Gram blocks, R.
+hipError_t grid_pairs_launch(int M, int N, double r, double s, const int32_t* dxy, int64_t P,
+                             double* dW, double* dC, double* dT, int mseg, double* o,
+                             hipStream_t st) {
+  const int64_t nb = (P + GG_B - 1) / GG_B;
+  const int64_t nbp = nb * (nb + 1) / 2;
+  const size_t nw = (size_t)(M - 1) * (N - 1);
+  const size_t ncos = (size_t)P * (N - 1);
+  auto grid1 = [](size_t n) { return dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)); };
+  hipError_t e = hipSuccess;
+  if (nw > 0) {
+    hipLaunchKernelGGL(k_grid_weights, grid1(nw), dim3(256), 0, st, M, N, r, s, dW);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && ncos > 0) {
+    hipLaunchKernelGGL(k_grid_ncos, grid1(ncos), dim3(256), 0, st, N, dxy, P, dC);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_grid_gram, dim3((unsigned)nbp, (unsigned)mseg), dim3(256), 0, st, M, N,
+                       dxy, (const double*)dW, (const double*)dC, P, (int)nb, mseg, dT);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_grid_finish, grid1((size_t)P * P), dim3(256), 0, st, M, N, r, s, dxy,
+                       (const double*)dT, mseg, P, o);
+    e = hipGetLastError();
+  }
+  return e;
+}
 
-extern "C" reff_status reff_grid_pairs(int32_t M, int32_t N, double r, double s,
-                                       const int32_t* xy, int64_t P, double* R_out,
-                                       int32_t out_on_device, void* stream) {
-  using namespace reff;
+// Segments of the m range: about 2048 workgroups per launch.
+int grid_pairs_mseg(int M, int64_t P) {
+  const int64_t nb = (P + GG_B - 1) / GG_B;
+  const int64_t nbp = nb * (nb + 1) / 2;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(std::max(M - 1, 1), (2048 + nbp - 1) / nbp));
+}
+
+reff_status grid_pairs_validate(int32_t M, int32_t N, double r, double s, const int32_t* xy,
+                                int64_t P, const double* R_out) {
   if (M < 1 || N < 1) return host_fail(REFF_ERR_INVALID_ARG, "grid size must be at least 1 x 1");
   if (!std::isfinite(r) || !(r > 0.0) || !std::isfinite(s) || !(s > 0.0))
     return host_fail(REFF_ERR_INVALID_ARG, "edge resistances must be finite and positive");
@@ -190,17 +225,38 @@ extern "C" reff_status reff_grid_pairs(int32_t M, int32_t N, double r, double s,
   for (int64_t k = 0; k < P; ++k)
     if (xy[2 * k] < 0 || xy[2 * k] >= M || xy[2 * k + 1] < 0 || xy[2 * k + 1] >= N)
       return host_fail(REFF_ERR_INVALID_ARG, "point " + std::to_string(k) + " is off the grid");
+  return REFF_OK;
+}
+
+reff_status grid_dev_fail(hipError_t e, const char* what) {
+  return host_fail(e == hipErrorOutOfMemory ? REFF_ERR_OUT_OF_MEMORY : REFF_ERR_DEVICE,
+                   std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Work memory of reff_grid_pairs_noalloc: one array per GPU, resident until
+// the process ends.  Host code never passes `scratch` itself to a kernel or
+// a copy (on the host it is only a stand-in for the symbol); it uses the
+// device address looked up once per device below.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+}  // namespace reff
+
+extern "C" reff_status reff_grid_pairs(int32_t M, int32_t N, double r, double s,
+                                       const int32_t* xy, int64_t P, double* R_out,
+                                       int32_t out_on_device, void* stream) {
+  using namespace reff;
+  const reff_status v = grid_pairs_validate(M, N, r, s, xy, P, R_out);
+  if (v != REFF_OK || P == 0) return v;
   hipStream_t st = (hipStream_t)stream;
-  auto dev_fail = [&](hipError_t e, const char* what) {
-    return host_fail(e == hipErrorOutOfMemory ? REFF_ERR_OUT_OF_MEMORY : REFF_ERR_DEVICE,
-                     std::string(what) + ": " + hipGetErrorString(e));
-  };
-  // 64-point blocks, upper block pairs; the m range split into segments so
-  // that a launch has about 2048 workgroups.
-  const int64_t nb = (P + GG_B - 1) / GG_B;
-  const int64_t nbp = nb * (nb + 1) / 2;
-  const int mseg = (int)std::max<int64_t>(
-      1, std::min<int64_t>(std::max(M - 1, 1), (2048 + nbp - 1) / nbp));
+  const int mseg = grid_pairs_mseg(M, P);
   const size_t nw = (size_t)(M - 1) * (N - 1);
   const size_t ncos = (size_t)P * (N - 1);
   const size_t tbytes = (size_t)mseg * P * P * sizeof(double);
@@ -221,33 +277,68 @@ extern "C" reff_status reff_grid_pairs(int32_t M, int32_t N, double r, double s,
   if (e == hipSuccess && !out_on_device) e = hipMalloc((void**)&dout, obytes);
   if (e != hipSuccess) {
     release();
-    return dev_fail(e, "hipMalloc");
+    return grid_dev_fail(e, "hipMalloc");
   }
   double* o = out_on_device ? R_out : dout;
   e = hipMemcpyAsync(dxy, xy, (size_t)P * 2 * sizeof(int32_t), hipMemcpyHostToDevice, st);
-  auto grid1 = [](size_t n) { return dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)); };
-  if (e == hipSuccess && nw > 0) {
-    hipLaunchKernelGGL(k_grid_weights, grid1(nw), dim3(256), 0, st, (int)M, (int)N, r, s, dW);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess && ncos > 0) {
-    hipLaunchKernelGGL(k_grid_ncos, grid1(ncos), dim3(256), 0, st, (int)N, dxy, P, dC);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_grid_gram, dim3((unsigned)nbp, (unsigned)mseg), dim3(256), 0, st, (int)M,
-                       (int)N, dxy, (const double*)dW, (const double*)dC, P, (int)nb, mseg, dT);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_grid_finish, grid1((size_t)P * P), dim3(256), 0, st, (int)M, (int)N, r, s,
-                       dxy, (const double*)dT, mseg, P, o);
-    e = hipGetLastError();
-  }
+  if (e == hipSuccess) e = grid_pairs_launch(M, N, r, s, dxy, P, dW, dC, dT, mseg, o, st);
   if (e == hipSuccess && !out_on_device)
     e = hipMemcpyAsync(R_out, dout, obytes, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   release();
-  if (e != hipSuccess) return dev_fail(e, "grid pairs");
+  if (e != hipSuccess) return grid_dev_fail(e, "grid pairs");
+  return REFF_OK;
+}
+
+extern "C" reff_status reff_grid_pairs_noalloc(int32_t M, int32_t N, double r, double s,
+                                               const int32_t* xy, int64_t P, double* R_out,
+                                               int32_t out_on_device, void* stream) {
+  using namespace reff;
+  const reff_status v = grid_pairs_validate(M, N, r, s, xy, P, R_out);
+  if (v != REFF_OK || P == 0) return v;
+  // Layout of the work memory: points, weights, cosine table, host staging
+  // of R (host output only), then as many m segments of partial Gram blocks
+  // as fit, up to the count the allocating entry point uses.
+  const size_t b_xy = round256((size_t)P * 2 * sizeof(int32_t));
+  const size_t b_w = round256((size_t)(M - 1) * (N - 1) * sizeof(double));
+  const size_t b_c = round256((size_t)P * (N - 1) * sizeof(double));
+  const size_t b_o = out_on_device ? 0 : round256((size_t)P * P * sizeof(double));
+  const size_t b_seg = (size_t)P * P * sizeof(double);
+  const size_t fixed = b_xy + b_w + b_c + b_o;
+  if (fixed + b_seg > kScratchBytes)
+    return host_fail(REFF_ERR_INVALID_ARG,
+                     "grid pairs without allocation: " + std::to_string(M) + " x " +
+                         std::to_string(N) + " with " + std::to_string(P) + " points needs " +
+                         std::to_string(fixed + b_seg) + " bytes of work memory, more than the " +
+                         std::to_string(kScratchBytes) + " bytes it holds");
+  const int mseg = (int)std::min<size_t>(grid_pairs_mseg(M, P), (kScratchBytes - fixed) / b_seg);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return grid_dev_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return host_fail(REFF_ERR_UNSUPPORTED, "device index too large");
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return grid_dev_fail(e, "hipGetSymbolAddress(scratch)");
+      g_scratch_ptr[dev] = ptr;
+    }
+    base = (unsigned char*)g_scratch_ptr[dev];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int32_t* dxy = (int32_t*)base;
+  double* dW = (double*)(base + b_xy);
+  double* dC = (double*)(base + b_xy + b_w);
+  double* dout = (double*)(base + b_xy + b_w + b_c);
+  double* dT = (double*)(base + fixed);
+  double* o = out_on_device ? R_out : dout;
+  e = hipMemcpyAsync(dxy, xy, (size_t)P * 2 * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = grid_pairs_launch(M, N, r, s, dxy, P, dW, dC, dT, mseg, o, st);
+  if (e == hipSuccess && !out_on_device)
+    e = hipMemcpyAsync(R_out, dout, (size_t)P * P * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return grid_dev_fail(e, "grid pairs (no allocation)");
   return REFF_OK;
 }

@@ -49,7 +49,7 @@ EXPORTED = [
     "reff_surrogate_create", "reff_surrogate_free", "reff_surrogate_num_params",
     "reff_surrogate_get_params", "reff_surrogate_set_params", "reff_surrogate_loss_grad",
     "reff_surrogate_train", "reff_surrogate_predict", "reff_surrogate_save",
-    "reff_surrogate_load",
+    "reff_surrogate_load", "reff_grid_pairs", "reff_grid_pairs_noalloc",
 ]
 
 
@@ -117,6 +117,7 @@ _lib.reff_batch_plans.restype = C.c_int
 _lib.reff_grid_pairs.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_void_p,
                                  C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]
 _lib.reff_grid_pairs.restype = C.c_int
+_lib.reff_grid_pairs_noalloc.argtypes = _lib.reff_grid_pairs.argtypes
 _lib.reff_status_string.argtypes = [C.c_int]
 _lib.reff_status_string.restype = C.c_char_p
 _lib.reff_last_error.argtypes = []
@@ -276,10 +277,7 @@ def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
     return R_out, st.as_dict()
 
 
-def reff_grid_pairs(M, N, r, s, xy, R_out=None, *, stream=None):
-    """Eq. 3 two-point resistances of every pair of points on a uniform
-    M x N grid (edges r along x, s along y).  xy: (P, 2) integer points.
-    Returns the P x P matrix (R_out if given: numpy or a torch CUDA tensor)."""
+def _grid_pairs_call(fn, M, N, r, s, xy, R_out, stream):
     pts = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
     P = len(pts)
     if R_out is None:
@@ -295,10 +293,22 @@ def reff_grid_pairs(M, N, r, s, xy, R_out=None, *, stream=None):
     else:
         assert R_out.dtype == np.float64 and R_out.flags.c_contiguous and R_out.size >= P * P
         optr = R_out.ctypes.data
-    _check(_lib.reff_grid_pairs(int(M), int(N), float(r), float(s), pts.ctypes.data, P, optr,
-                                1 if out_dev else 0,
-                                C.c_void_p(int(stream) if stream is not None else 0)))
+    _check(fn(int(M), int(N), float(r), float(s), pts.ctypes.data, P, optr, 1 if out_dev else 0,
+              C.c_void_p(int(stream) if stream is not None else 0)))
     return R_out
+
+
+def reff_grid_pairs(M, N, r, s, xy, R_out=None, *, stream=None):
+    """Eq. 3 two-point resistances of every pair of points on a uniform
+    M x N grid (edges r along x, s along y).  xy: (P, 2) integer points.
+    Returns the P x P matrix (R_out if given: numpy or a torch CUDA tensor)."""
+    return _grid_pairs_call(_lib.reff_grid_pairs, M, N, r, s, xy, R_out, stream)
+
+
+def reff_grid_pairs_noalloc(M, N, r, s, xy, R_out=None, *, stream=None):
+    """reff_grid_pairs through the entry point that allocates no device
+    memory (the library's fixed per-GPU work array)."""
+    return _grid_pairs_call(_lib.reff_grid_pairs_noalloc, M, N, r, s, xy, R_out, stream)
 
 
 def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.0,
