@@ -180,6 +180,38 @@ reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m,
                              double* R_out, const reff_solve_opts* opts,
                              reff_solve_stats* st);
 
+/*
+ * IR drop and through-bump currents of load scenarios (Sec. II-B, Eq. 4;
+ * Sec. IV-B).  Bumps (pads) are ideal sources at the supply voltage, loads
+ * are ideal current sources (Sec. III-B).  Scenario c draws
+ * load_amps[c * n_loads + k] amperes at node load_nodes[k].  By Eq. 4 with
+ * every bump merged into the supply node, the drop below the supply at node
+ * j is sum_k I_k (R_j + R_{l_k} - R(j, l_k)) / 2 = sum_k I_k (G^-1 e_{l_k})_j:
+ * each distinct free load node is solved once with a unit current (block
+ * PCG, 64 loads per block) and the responses are superposed on the device,
+ * a bounded group of solved blocks at a time.
+ *   load_nodes  host int64[n_loads]; duplicates add; a load on a pad draws
+ *               straight from that pad (no drop).
+ *   load_amps   host double[n_scen][n_loads].
+ *   nodes       host int64[n_nodes] node ids to report, NULL = all nodes.
+ *   drop_out    double[n_scen][n_nodes] (host, or device if
+ *               opts->out_on_device): supply voltage minus node voltage, in
+ *               volts per ampere of load current; 0 on pads.
+ *   pad_amps_out  host double[n_scen][n_pads] (nullable): the current each
+ *               pad entry of the descriptor delivers; a position listed twice
+ *               reports its current at its first entry and 0 at the others.
+ *               The pad currents of a scenario sum to its total load current.
+ *   opts        rel_tol applies to the unit-load responses' R values; point
+ *               values are accurate to about its square root, so the default
+ *               (rel_tol 0) is 1e-12 in float64 and 1e-7 in mixed precision.
+ * Errors: INVALID_ARG (ids out of range, negative counts, non-finite
+ * currents, NULL pointers), NO_CONVERGENCE, OUT_OF_MEMORY, DEVICE.
+ */
+reff_status reff_ir_drop(reff_pdn p, const int64_t* load_nodes, int64_t n_loads,
+                         const double* load_amps, int32_t n_scen, const int64_t* nodes,
+                         int64_t n_nodes, double* drop_out, double* pad_amps_out,
+                         const reff_solve_opts* opts, reff_solve_stats* st);
+
 typedef struct {
   reff_solve_opts solve;   /* precision, tolerance, stream, out_on_device   */
   const void* surrogate;   /* NULL: solve every node.  A reff_surrogate
@@ -236,6 +268,45 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
  */
 reff_status reff_grid_pairs(int32_t M, int32_t N, double r, double s, const int32_t* xy,
                             int64_t P, double* R_out, int32_t out_on_device, void* stream);
+
+/*
+ * Bump-to-load pair resistances of a stack of uniformly meshed tiers by the
+ * paper's divide-and-conquer method (Sec. III-C and III-D): intra-die
+ * resistances from Eq. 3 (TSV-TSV on every tier, bump-TSV on tier 0,
+ * load-TSV on the last tier), the reduced system C x = b of size
+ * (p+1)(d-1) over the TSV currents of the d-1 tier interfaces and the
+ * supply-voltage differences, factorised once, m + n solves (one per bump
+ * and per load, the linearity of Sec. III-D), and
+ * R(i, j) = -(x^1_i + x^d_j)^T (b^1_i + b^d_j) with the m x n cross term as
+ * one matrix product.  The network is the floating stack (Eq. 2 with no
+ * other grounding), the same as reff_query_pairs in REFF_PAIRS_FLOATING mode
+ * on the equivalent reff_pdn_desc (gx = 1 / r_t, gy = 1 / s_t, tsv_g =
+ * 1 / tsv_r).
+ *   n_tiers  d >= 2 uniform tiers of nx x ny nodes; tier 0 carries the
+ *            bumps, tier d-1 the loads.
+ *   r_t,s_t  host double[d]: edge resistance along x and along y on tier t.
+ *   tsv_xy   host int32[2 p]: TSV columns (distinct), p >= 1.
+ *   tsv_r    host double[p][d-1]: segment resistance of TSV k between
+ *            tiers t and t+1.
+ *   bump_xy  host int32[2 m] on tier 0; load_xy host int32[2 n] on tier d-1.
+ *   R_out    double[m*n] row-major (host, or device if out_on_device):
+ *            R(bump i, load j).
+ *   stream   hipStream_t to run on; NULL => default stream.  The call
+ *            returns after R_out is written.
+ * The call allocates and frees its own device work memory (about
+ * 8 ((p-1)(d-1))^2 x 2 bytes for the reduced matrix and its factor, plus
+ * the intra-die tables).  Errors: INVALID_ARG (d < 2, p < 1, counts < 0,
+ * non-positive or non-finite resistances, a point off the grid, duplicate
+ * TSV columns, more than 65535 TSVs + bumps or TSVs + loads, NULL
+ * pointers), OUT_OF_MEMORY, DEVICE (also when the reduced matrix is not
+ * positive definite on the constrained currents, which a connected stack
+ * does not produce).
+ */
+reff_status reff_reduced_pairs(int32_t n_tiers, int32_t nx, int32_t ny, const double* r_t,
+                               const double* s_t, int32_t p, const int32_t* tsv_xy,
+                               const double* tsv_r, int64_t m, const int32_t* bump_xy, int64_t n,
+                               const int32_t* load_xy, double* R_out, int32_t out_on_device,
+                               void* stream);
 
 /*
  * reff_grid_pairs without any allocation, for callers that cannot allocate

@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libreff.so")
 
-SOURCES = ["reff_api.cpp", "reff_kernels.hip", "grid_pairs.hip", "surrogate_api.cpp",
-           "surrogate_kernels.hip"]
+SOURCES = ["reff_api.cpp", "reff_kernels.hip", "grid_pairs.hip", "reduced_pairs.hip", "ir_drop.hip",
+           "surrogate_api.cpp", "surrogate_kernels.hip"]
 
 # Packed FP32 arithmetic is disabled for every HIP translation unit.
 HIP_FLAGS = [
@@ -44,16 +44,21 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src in SOURCES:
+
+    def compile_one(src):
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"]
-        cmd = [hipcc(), *HIP_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc(), *HIP_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
+        return obj, subprocess.run(cmd, capture_output=True, text=True)
+
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        results = list(ex.map(compile_one, SOURCES))
+    objs = []
+    for src, (obj, r) in zip(SOURCES, results):
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)
             raise RuntimeError(f"hipcc failed on {src}")

@@ -249,6 +249,31 @@ size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 }  // namespace
 }  // namespace reff
 
+namespace reff {
+
+// All-pairs Eq. 3 resistances of P points already in device memory, into
+// device out[P * P]; the work memory is allocated here and released after
+// the stream has run the kernels (the call returns with them complete).
+hipError_t grid_pairs_device(int M, int N, double r, double s, const int32_t* dxy, int64_t P,
+                             double* dout, hipStream_t st) {
+  if (P <= 0) return hipSuccess;
+  const int mseg = grid_pairs_mseg(M, P);
+  double *dW = nullptr, *dC = nullptr, *dT = nullptr;
+  hipError_t e = hipMalloc((void**)&dW, std::max<size_t>((size_t)(M - 1) * (N - 1), 1) * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMalloc((void**)&dC, std::max<size_t>((size_t)P * (N - 1), 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&dT, (size_t)mseg * P * P * sizeof(double));
+  if (e == hipSuccess) e = grid_pairs_launch(M, N, r, s, dxy, P, dW, dC, dT, mseg, dout, st);
+  const hipError_t e2 = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = e2;
+  if (dW) (void)hipFree(dW);
+  if (dC) (void)hipFree(dC);
+  if (dT) (void)hipFree(dT);
+  return e;
+}
+
+}  // namespace reff
+
 extern "C" reff_status reff_grid_pairs(int32_t M, int32_t N, double r, double s,
                                        const int32_t* xy, int64_t P, double* R_out,
                                        int32_t out_on_device, void* stream) {

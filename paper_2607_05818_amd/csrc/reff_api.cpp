@@ -1379,6 +1379,208 @@ reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m, const int6
   return REFF_OK;
 }
 
+// IR drop and through-bump currents by superposition of unit-load responses
+// (Eq. 4 with every bump merged into the supply node: 1/2 (R_j + R_l -
+// R(j, l)) = (G^-1 e_l)_j).  The distinct free load nodes are solved 64 at a
+// time; each group of solved blocks is folded into the drop and pad-current
+// accumulators on the device and then dropped, so memory stays bounded by
+// the group size, not by the number of loads.
+reff_status reff_ir_drop(reff_pdn p, const int64_t* load_nodes, int64_t n_loads,
+                         const double* load_amps, int32_t n_scen, const int64_t* nodes,
+                         int64_t n_nodes, double* drop_out, double* pad_amps_out,
+                         const reff_solve_opts* opts, reff_solve_stats* st) {
+  g_err.clear();
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!p) return fail(REFF_ERR_INVALID_ARG, "handle is NULL");
+  if (n_loads < 0 || n_scen < 0) return fail(REFF_ERR_INVALID_ARG, "n_loads, n_scen must be >= 0");
+  if (n_loads > 0 && n_scen > 0 && (!load_nodes || !load_amps))
+    return fail(REFF_ERR_INVALID_ARG, "NULL load nodes or currents");
+  if (nodes && n_nodes < 0) return fail(REFF_ERR_INVALID_ARG, "n_nodes < 0");
+  const int64_t count = nodes ? n_nodes : p->n;
+  if (count * (int64_t)n_scen > 0 && !drop_out) return fail(REFF_ERR_INVALID_ARG, "drop_out is NULL");
+  for (int64_t i = 0; i < n_loads; ++i)
+    if (load_nodes[i] < 0 || load_nodes[i] >= p->n)
+      return fail(REFF_ERR_INVALID_ARG, "load node id out of range");
+  for (int64_t i = 0; i < n_loads * (int64_t)n_scen; ++i)
+    if (!std::isfinite(load_amps[i])) return fail(REFF_ERR_INVALID_ARG, "non-finite load current");
+  if (nodes)
+    for (int64_t i = 0; i < count; ++i)
+      if (nodes[i] < 0 || nodes[i] >= p->n) return fail(REFF_ERR_INVALID_ARG, "node id out of range");
+  Opts o;
+  reff_status s = parse_opts(opts, o);
+  if (s != REFF_OK) return s;
+  // Point values of a response are accurate to about the square root of the
+  // energy-norm error the solver controls; the defaults are tighter than
+  // those of reff_solve_diag accordingly.
+  if (!opts || opts->rel_tol == 0.0) o.tol = o.mixed ? 1e-7 : 1e-12;
+  if (st) std::memset(st, 0, sizeof(*st));
+  HIPCHK(hipSetDevice(p->device));
+  const CoefSet& cs = p->gnd;
+  if (cs.n_free < 16 * (int64_t)S) o.indep = true;
+  const int64_t nn = p->n;
+  // distinct free load columns; per column the summed currents per scenario
+  std::vector<int64_t> cols;
+  for (int64_t i = 0; i < n_loads; ++i)
+    if (!cs.grounded[(size_t)load_nodes[i]]) cols.push_back(load_nodes[i]);
+  std::sort(cols.begin(), cols.end());
+  cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+  const int64_t U = (int64_t)cols.size();
+  std::vector<double> colamp((size_t)(U * n_scen), 0.0);
+  // pad entries (descriptor order, first entry of a position only)
+  const int npad = (int)(p->pad_xy.size() / 2);
+  std::vector<int32_t> pad_first(npad, -1);
+  std::vector<double> pad_direct((size_t)npad * n_scen, 0.0);  // loads placed on pads
+  {
+    std::vector<int32_t> first_at((size_t)p->plane, -1);
+    for (int k = 0; k < npad; ++k) {
+      const int64_t v = (int64_t)p->pad_xy[2 * k + 1] * p->nx + p->pad_xy[2 * k];
+      if (first_at[(size_t)v] < 0) first_at[(size_t)v] = k;
+      pad_first[k] = first_at[(size_t)v];
+    }
+    for (int64_t i = 0; i < n_loads; ++i) {
+      const int64_t v = load_nodes[i];
+      if (cs.grounded[(size_t)v]) {
+        const int k = first_at[(size_t)v];
+        for (int c = 0; c < n_scen; ++c)
+          pad_direct[(size_t)c * npad + k] += load_amps[(size_t)c * n_loads + i];
+      } else {
+        const int64_t u = std::lower_bound(cols.begin(), cols.end(), v) - cols.begin();
+        for (int c = 0; c < n_scen; ++c)
+          colamp[(size_t)(u * n_scen + c)] += load_amps[(size_t)c * n_loads + i];
+      }
+    }
+  }
+  // weighted node rows: requested nodes (weight 1), then the pads' edges
+  std::vector<int32_t> rptr(1, 0);
+  std::vector<int64_t> rnode;
+  std::vector<double> rwt;
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t v = nodes ? nodes[i] : i;
+    if (!cs.grounded[(size_t)v]) rnode.push_back(v), rwt.push_back(1.0);
+    rptr.push_back((int32_t)rnode.size());
+  }
+  {
+    std::vector<int32_t> tsv_at((size_t)p->plane, -1);
+    for (size_t j = 0; j < p->tsv_xy.size() / 2; ++j)
+      tsv_at[(size_t)p->tsv_xy[2 * j + 1] * p->nx + p->tsv_xy[2 * j]] = (int32_t)j;
+    const int nx = p->nx, ny = p->ny;
+    for (int k = 0; k < npad; ++k) {
+      if (pad_first[k] == k) {
+        const int x = p->pad_xy[2 * k], y = p->pad_xy[2 * k + 1];
+        const int64_t v = (int64_t)y * nx + x;
+        auto edge = [&](int64_t u, double g) {
+          if (!cs.grounded[(size_t)u]) rnode.push_back(u), rwt.push_back(g);
+        };
+        if (x + 1 < nx) edge(v + 1, p->gx[(size_t)y * (nx - 1) + x]);
+        if (x > 0) edge(v - 1, p->gx[(size_t)y * (nx - 1) + x - 1]);
+        if (y + 1 < ny) edge(v + nx, p->gy[(size_t)y * nx + x]);
+        if (y > 0) edge(v - nx, p->gy[(size_t)(y - 1) * nx + x]);
+        const int32_t j = tsv_at[(size_t)v];
+        if (j >= 0 && p->nt > 1) edge(v + p->plane, p->tsv_g[(size_t)j * (p->nt - 1)]);
+      }
+      rptr.push_back((int32_t)rnode.size());
+    }
+  }
+  const int64_t nrows = count + npad;
+  // device buffers of this call
+  struct Local {
+    std::vector<void*> ptrs;
+    ~Local() {
+      for (void* q : ptrs) (void)hipFree(q);
+    }
+    hipError_t get(void** out, size_t bytes) {
+      hipError_t e = hipMalloc(out, std::max<size_t>(bytes, 8));
+      if (e == hipSuccess) ptrs.push_back(*out);
+      return e;
+    }
+  } loc;
+  void *d_rptr = nullptr, *d_rnode = nullptr, *d_rw = nullptr, *d_acc = nullptr, *d_amp = nullptr;
+  HIPCHK(loc.get(&d_rptr, rptr.size() * sizeof(int32_t)));
+  HIPCHK(loc.get(&d_rnode, rnode.size() * sizeof(int64_t)));
+  HIPCHK(loc.get(&d_rw, rwt.size() * sizeof(double)));
+  HIPCHK(loc.get(&d_acc, (size_t)nrows * n_scen * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(d_rptr, rptr.data(), rptr.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                        o.stream));
+  if (!rnode.empty()) {
+    HIPCHK(hipMemcpyAsync(d_rnode, rnode.data(), rnode.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice, o.stream));
+    HIPCHK(hipMemcpyAsync(d_rw, rwt.data(), rwt.size() * sizeof(double), hipMemcpyHostToDevice,
+                          o.stream));
+  }
+  HIPCHK(launch_zero_x((double*)d_acc, nrows * n_scen, o.stream));
+  reff_status solve_rs = REFF_OK;
+  if (U > 0 && n_scen > 0) {
+    std::vector<StackInfo> stacks{StackInfo{0, nn, p->plane, p->nx, 0, (int32_t)cs.n_slots}};
+    std::vector<BlockJob> jobs;
+    deal_blocks(cols, 0, 0, jobs);
+    const int64_t nblk = (int64_t)jobs.size();
+    // blocks per group: solution vectors of a group within 8 GB
+    const int64_t per = std::max<int64_t>(
+        1, std::min<int64_t>(nblk, (int64_t)(8e9 / ((double)nn * S * sizeof(double)))));
+    reff_status rs;
+    if ((rs = ensure(p->ws.xs, (size_t)per * nn * S * sizeof(double))) != REFF_OK) return rs;
+    if ((rs = ensure(p->ws.out, (size_t)(U + 1) * sizeof(double))) != REFF_OK) return rs;
+    HIPCHK(loc.get(&d_amp, (size_t)per * S * n_scen * sizeof(double)));
+    double* xs = (double*)p->ws.xs.p;
+    std::vector<double> hamp((size_t)per * S * n_scen);
+    for (int64_t g0 = 0; g0 < nblk; g0 += per) {
+      const int64_t g1 = std::min(nblk, g0 + per);
+      std::vector<BlockJob> gj(jobs.begin() + g0, jobs.begin() + g1);
+      std::vector<int64_t> xoff((size_t)(g1 - g0));
+      for (int64_t bb = 0; bb < g1 - g0; ++bb) xoff[(size_t)bb] = bb * nn * S;
+      std::vector<BlockResult> br;
+      rs = run_blocks(p->ws, cs, stacks, gj, (double*)p->ws.out.p, o, br, st, xs, &xoff);
+      if (rs != REFF_OK && rs != REFF_ERR_NO_CONVERGENCE) return rs;
+      if (rs == REFF_ERR_NO_CONVERGENCE) solve_rs = rs;
+      add_stats(st, br, 0, br.size());
+      std::fill(hamp.begin(), hamp.end(), 0.0);
+      for (int64_t bb = 0; bb < g1 - g0; ++bb) {
+        const BlockJob& jb = gj[(size_t)bb];
+        for (int k = 0; k < jb.ncol; ++k)
+          for (int c = 0; c < n_scen; ++c)
+            hamp[(size_t)((bb * S + k) * n_scen + c)] = colamp[(size_t)(jb.pos[k] * n_scen + c)];
+      }
+      HIPCHK(hipMemcpyAsync(d_amp, hamp.data(), (size_t)(g1 - g0) * S * n_scen * sizeof(double),
+                            hipMemcpyHostToDevice, o.stream));
+      for (int64_t bb = 0; bb < g1 - g0; ++bb)
+        HIPCHK(launch_rows_times_loads(xs + bb * nn * S, (const int32_t*)d_rptr,
+                                       (const int64_t*)d_rnode, (const double*)d_rw, nrows,
+                                       (const double*)d_amp + bb * S * n_scen, n_scen,
+                                       (double*)d_acc, nrows, o.stream));
+      HIPCHK(hipStreamSynchronize(o.stream));  // hamp is refilled by the next group
+    }
+  }
+  // drop: rows 0 .. count-1 of each scenario's accumulator row
+  if (count > 0 && n_scen > 0) {
+    if (o.out_dev) {
+      HIPCHK(hipMemcpy2DAsync(drop_out, count * sizeof(double), d_acc, nrows * sizeof(double),
+                              count * sizeof(double), n_scen, hipMemcpyDeviceToDevice, o.stream));
+    } else {
+      HIPCHK(hipMemcpy2DAsync(drop_out, count * sizeof(double), d_acc, nrows * sizeof(double),
+                              count * sizeof(double), n_scen, hipMemcpyDeviceToHost, o.stream));
+    }
+  }
+  if (pad_amps_out && npad > 0 && n_scen > 0) {
+    std::vector<double> pa((size_t)npad * n_scen);
+    HIPCHK(hipMemcpy2DAsync(pa.data(), npad * sizeof(double), (double*)d_acc + count,
+                            nrows * sizeof(double), npad * sizeof(double), n_scen,
+                            hipMemcpyDeviceToHost, o.stream));
+    HIPCHK(hipStreamSynchronize(o.stream));
+    for (int c = 0; c < n_scen; ++c)
+      for (int k = 0; k < npad; ++k)
+        pad_amps_out[(size_t)c * npad + k] =
+            pad_first[k] == k ? pa[(size_t)c * npad + k] + pad_direct[(size_t)c * npad + k] : 0.0;
+  }
+  HIPCHK(hipStreamSynchronize(o.stream));
+  if (st) {
+    st->n_solved = U;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (solve_rs == REFF_ERR_NO_CONVERGENCE)
+    return fail(REFF_ERR_NO_CONVERGENCE, "max_iters reached before the tolerance");
+  return REFF_OK;
+}
+
 // Screening of a batch with the learned model: predict every plan's map,
 // solve a seeded fraction of each plan's requested free nodes, and fall back
 // to solving all requested nodes of a plan whose checked relative error

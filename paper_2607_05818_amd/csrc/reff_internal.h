@@ -16,6 +16,11 @@ namespace reff {
 reff_status host_fail(reff_status s, const std::string& msg);
 // The stack validation every entry point performs before device work.
 reff_status host_validate_desc(const reff_pdn_desc* d);
+// Eq. 3 resistances of every pair of P points (device xy) on a uniform
+// M x N tier into device out[P * P] (grid_pairs.hip); returns once the
+// stream has run the kernels.
+hipError_t grid_pairs_device(int M, int N, double r, double s, const int32_t* dxy, int64_t P,
+                             double* dout, hipStream_t st);
 
 constexpr int S = 64;        // right-hand sides per block (one per lane)
 constexpr int CH = 32;       // nodes per LDS chunk in the block kernels
@@ -227,6 +232,12 @@ hipError_t launch_gather_out(const double* res, const int64_t* map, double* out,
                              int64_t count, hipStream_t st);
 // C = Xa^T (G Xb) for two solved blocks of the same stack (plan 0 of b.work;
 // partials + reduction; result in b.W[0 .. S*S)).
+// out[c * ld + r] += sum_k (sum_{e in row r} w_e X[node_e][k]) amps[k][c] for the
+// weighted node rows r < nrows (CSR rptr / rnode / rw, device) of a solved
+// float64 block X (n x S) and its S x n_scen load matrix (ir_drop.hip).
+hipError_t launch_rows_times_loads(const double* X, const int32_t* rptr, const int64_t* rnode,
+                                   const double* rw, int64_t nrows, const double* amps,
+                                   int n_scen, double* out, int64_t ld, hipStream_t st);
 hipError_t launch_cross_gram(const Coef<double>& c, const double* Xa, const double* Xb,
                              const SolveBuffers& b, hipStream_t st);
 // rows[i*S + k] = X[nodes[i]*S + k] for i < count.

@@ -26,7 +26,8 @@ import numpy as np
 __all__ = [
     "cell_centred", "make_desc", "config1", "config2", "config3_plans",
     "config4_plan", "config5", "sample_free_nodes", "pad_ids", "n_nodes",
-    "CONFIG_SEEDS", "small_random_desc", "config3_samples",
+    "CONFIG_SEEDS", "small_random_desc", "config3_samples", "tsv_planning_study",
+    "uniform_tier_stack",
 ]
 
 CONFIG_SEEDS = {1: 1001, 2: 1002, 3: 1003, 4: 1004, 5: 1005}
@@ -206,3 +207,65 @@ def small_random_desc(seed: int, n_tiers: int, nx: int, ny: int,
     tsv_g = rng.uniform(1.0, 10.0, size=(len(tsv_xy), max(n_tiers - 1, 0)))
     pad_xy = _uniform_distinct_xy(rng, nx, ny, min(n_pads, nx * ny))
     return make_desc(n_tiers, nx, ny, gx, gy, tsv_xy, tsv_g, pad_xy)
+
+
+def tsv_planning_study(seed: int = 1006, side: int = 128, n_tiers: int = 3, n_tsv: int = 256,
+                       bump_k: int = 16, block_w: int = 30, block_h: int = 15,
+                       amps_per_block: float = 6.1) -> dict:
+    """A synthetic analog of the TSV-planning comparison of Sec. IV-B: one
+    stack with two TSV plans of the same TSV count, band-like (every TSV
+    in a central vertical band, as in HBM-style stacks) and uniformly
+    distributed (a cell-centred array), bumps cell-centred bump_k x bump_k on
+    tier 0, and four functional blocks of block_w x block_h nodes on the last
+    tier, one per quadrant, each drawing amps_per_block spread evenly over
+    its nodes (the paper's blocks draw 220 A/cm^2 over 2.35 x 1.18 mm^2,
+    about 6.1 A).  Edges lognormal(0, 0.3) S, TSV segments 5 S.  Returns
+    {"band": desc, "uniform": desc, "loads": node ids, "amps": (1, n)}."""
+    rng = np.random.default_rng(seed)
+    nt, nx, ny = n_tiers, side, side
+    gx = rng.lognormal(0.0, 0.3, size=(nt, ny, nx - 1))
+    gy = rng.lognormal(0.0, 0.3, size=(nt, ny - 1, nx))
+    pad_xy = _grid_xy(nx, ny, bump_k, bump_k)
+    # uniform plan: a cell-centred array of about n_tsv columns
+    ku = max(1, int(round(np.sqrt(n_tsv))))
+    uni = _grid_xy(nx, ny, ku, max(1, n_tsv // ku))
+    # band plan: the same count packed in a band of columns at the centre
+    bw = max(1, int(np.ceil(len(uni) / ny)))
+    bx = np.arange(nx // 2 - bw // 2, nx // 2 - bw // 2 + bw)
+    band_all = np.stack(np.meshgrid(bx, np.arange(ny), indexing="xy"), axis=-1).reshape(-1, 2)
+    pick = np.sort(rng.choice(len(band_all), size=len(uni), replace=False))
+    band = band_all[pick].astype(np.int32)
+    tg = np.full((len(uni), nt - 1), 5.0)
+    loads, amps = [], []
+    plane = nx * ny
+    for qx, qy in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        x0 = (2 * qx + 1) * nx // 4 - block_w // 2
+        y0 = (2 * qy + 1) * ny // 4 - block_h // 2
+        xs, ys = np.meshgrid(np.arange(x0, x0 + block_w), np.arange(y0, y0 + block_h),
+                             indexing="xy")
+        ids = (nt - 1) * plane + ys.ravel() * nx + xs.ravel()
+        loads.append(ids)
+        amps.append(np.full(len(ids), amps_per_block / len(ids)))
+    return {
+        "band": make_desc(nt, nx, ny, gx, gy, band, tg, pad_xy),
+        "uniform": make_desc(nt, nx, ny, gx, gy, uni, tg, pad_xy),
+        "loads": np.concatenate(loads).astype(np.int64),
+        "amps": np.concatenate(amps)[None, :],
+    }
+
+
+def uniform_tier_stack(seed: int, n_tiers: int, side: int, n_tsv: int, m: int, n: int) -> dict:
+    """Inputs of the paper's pair method (Sec. III-C/D): n_tiers uniform
+    tiers of side x side nodes (per-tier edge resistances U[0.5, 2] Ohm along
+    x and y), n_tsv distinct uniform TSV columns with U[0.05, 1] Ohm segments,
+    m bumps on tier 0 and n loads on the last tier at distinct uniform
+    positions."""
+    rng = np.random.default_rng(seed)
+    r_t = rng.uniform(0.5, 2.0, n_tiers)
+    s_t = rng.uniform(0.5, 2.0, n_tiers)
+    tsv = _uniform_distinct_xy(rng, side, side, n_tsv)
+    tsv_r = rng.uniform(0.05, 1.0, (n_tsv, n_tiers - 1))
+    bumps = _uniform_distinct_xy(rng, side, side, m)
+    loads = _uniform_distinct_xy(rng, side, side, n)
+    return {"side": side, "r_t": r_t, "s_t": s_t, "tsv_xy": tsv, "tsv_r": tsv_r,
+            "bump_xy": bumps, "load_xy": loads}

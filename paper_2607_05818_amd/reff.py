@@ -49,7 +49,8 @@ EXPORTED = [
     "reff_surrogate_create", "reff_surrogate_free", "reff_surrogate_num_params",
     "reff_surrogate_get_params", "reff_surrogate_set_params", "reff_surrogate_loss_grad",
     "reff_surrogate_train", "reff_surrogate_predict", "reff_surrogate_save",
-    "reff_surrogate_load", "reff_grid_pairs", "reff_grid_pairs_noalloc",
+    "reff_surrogate_load", "reff_grid_pairs", "reff_grid_pairs_noalloc", "reff_reduced_pairs",
+    "reff_ir_drop",
 ]
 
 
@@ -118,6 +119,15 @@ _lib.reff_grid_pairs.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, C
                                  C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]
 _lib.reff_grid_pairs.restype = C.c_int
 _lib.reff_grid_pairs_noalloc.argtypes = _lib.reff_grid_pairs.argtypes
+_lib.reff_reduced_pairs.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                    C.c_int64, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+_lib.reff_reduced_pairs.restype = C.c_int
+_lib.reff_ir_drop.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
+                              C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                              C.POINTER(reff_solve_opts), C.POINTER(reff_solve_stats)]
+_lib.reff_ir_drop.restype = C.c_int
+_lib.reff_grid_pairs_noalloc.restype = C.c_int
 _lib.reff_status_string.argtypes = [C.c_int]
 _lib.reff_status_string.restype = C.c_char_p
 _lib.reff_last_error.argtypes = []
@@ -169,9 +179,10 @@ def _desc_struct(desc):
 class PDN:
     """Owner of a reff_pdn handle."""
 
-    def __init__(self, handle, device):
+    def __init__(self, handle, device, n_pads=0):
         self.handle = handle
         self.device = device
+        self.n_pads = int(n_pads)   # pad entries of the descriptor
 
     @property
     def num_nodes(self):
@@ -194,7 +205,7 @@ def reff_build_pdn(desc, device: int = 0) -> PDN:
     h = C.c_void_p()
     _check(_lib.reff_build_pdn(C.byref(s), int(device), C.byref(h)))
     del keep
-    return PDN(h, device)
+    return PDN(h, device, np.asarray(desc["pad_xy"]).reshape(-1, 2).shape[0])
 
 
 def reff_free_pdn(pdn: PDN) -> None:
@@ -277,6 +288,38 @@ def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
     return R_out, st.as_dict()
 
 
+def reff_ir_drop(pdn: PDN, load_nodes, load_amps, nodes=None, drop_out=None, *,
+                 precision=REFF_PREC_FP64, rel_tol=0.0, max_iters=0, stream=None,
+                 precond_degree=0, pad_amps=True):
+    """IR drop of load scenarios by superposition of unit-load responses
+    (Eq. 4) and the current each pad delivers.  load_amps: (n_scen, n_loads).
+    Returns (drop (n_scen, len(nodes) or n), pad currents (n_scen, n_pads) or
+    None, stats)."""
+    ln = np.ascontiguousarray(load_nodes, dtype=np.int64)
+    la = np.ascontiguousarray(np.atleast_2d(load_amps), dtype=np.float64)
+    assert la.shape[1] == len(ln)
+    n_scen = la.shape[0]
+    if nodes is None:
+        count, nptr, narr = pdn.num_nodes, None, None
+    else:
+        narr = np.ascontiguousarray(nodes, dtype=np.int64)
+        count, nptr = len(narr), narr.ctypes.data
+    if drop_out is None:
+        drop_out = np.empty((n_scen, count), dtype=np.float64)
+    out_dev = _is_torch_cuda(drop_out)
+    optr = drop_out.data_ptr() if out_dev else drop_out.ctypes.data
+    npad = pdn.n_pads
+    pa = np.empty((n_scen, npad), dtype=np.float64) if (pad_amps and npad) else None
+    o = _opts(precision, rel_tol, max_iters, REFF_KRYLOV_BLOCK, stream, out_dev, 0,
+              precond_degree=precond_degree)
+    st = reff_solve_stats()
+    _check(_lib.reff_ir_drop(pdn.handle, ln.ctypes.data, len(ln), la.ctypes.data, n_scen, nptr,
+                             count if nodes is not None else 0, optr,
+                             pa.ctypes.data if pa is not None else None, C.byref(o),
+                             C.byref(st)))
+    return drop_out, pa, st.as_dict()
+
+
 def _grid_pairs_call(fn, M, N, r, s, xy, R_out, stream):
     pts = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
     P = len(pts)
@@ -309,6 +352,42 @@ def reff_grid_pairs_noalloc(M, N, r, s, xy, R_out=None, *, stream=None):
     """reff_grid_pairs through the entry point that allocates no device
     memory (the library's fixed per-GPU work array)."""
     return _grid_pairs_call(_lib.reff_grid_pairs_noalloc, M, N, r, s, xy, R_out, stream)
+
+
+def reff_reduced_pairs(nx, ny, r_t, s_t, tsv_xy, tsv_r, bump_xy, load_xy, R_out=None, *,
+                       stream=None):
+    """Bump (tier 0) to load (last tier) pair resistances of a stack of
+    uniform tiers by the reduced system of Sec. III-C/D.  r_t, s_t: per-tier
+    edge resistances along x and y; tsv_xy (p, 2); tsv_r (p, d-1) segment
+    resistances; bump_xy (m, 2); load_xy (n, 2).  Returns the m x n matrix
+    (R_out if given: numpy or a torch CUDA tensor)."""
+    r_t = np.ascontiguousarray(r_t, dtype=np.float64)
+    s_t = np.ascontiguousarray(s_t, dtype=np.float64)
+    d = len(r_t)
+    assert len(s_t) == d
+    txy = np.ascontiguousarray(tsv_xy, dtype=np.int32).reshape(-1, 2)
+    p = len(txy)
+    tr = np.ascontiguousarray(tsv_r, dtype=np.float64).reshape(p, max(d - 1, 0))
+    bxy = np.ascontiguousarray(bump_xy, dtype=np.int32).reshape(-1, 2)
+    lxy = np.ascontiguousarray(load_xy, dtype=np.int32).reshape(-1, 2)
+    m, n = len(bxy), len(lxy)
+    if R_out is None:
+        R_out = np.empty((m, n), dtype=np.float64)
+    out_dev = _is_torch_cuda(R_out)
+    if out_dev:
+        assert R_out.is_contiguous() and R_out.numel() >= m * n
+        optr = R_out.data_ptr()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+    else:
+        assert R_out.dtype == np.float64 and R_out.flags.c_contiguous and R_out.size >= m * n
+        optr = R_out.ctypes.data
+    _check(_lib.reff_reduced_pairs(d, int(nx), int(ny), r_t.ctypes.data, s_t.ctypes.data, p,
+                                   txy.ctypes.data, tr.ctypes.data, m, bxy.ctypes.data, n,
+                                   lxy.ctypes.data, optr, 1 if out_dev else 0,
+                                   C.c_void_p(int(stream) if stream is not None else 0)))
+    return R_out
 
 
 def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.0,

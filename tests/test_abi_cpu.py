@@ -124,3 +124,26 @@ def test_batch_rejected_on_host(case):
     with pytest.raises(reff.ReffError) as ei:
         reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_FP64)
     assert ei.value.status == want
+
+
+@pytest.mark.parametrize("case", ["one_tier", "no_tsv", "dup_tsv", "off_grid", "neg_r"])
+def test_reduced_pairs_rejected_on_host(case):
+    from paper_2607_05818_amd import reff
+    r_t, s_t = np.ones(3), np.ones(3)
+    txy = np.array([[1, 1], [2, 3]], dtype=np.int32)
+    tr = np.ones((2, 2))
+    bxy = np.array([[0, 0]], dtype=np.int32)
+    lxy = np.array([[4, 4]], dtype=np.int32)
+    if case == "one_tier":
+        r_t, s_t, tr = np.ones(1), np.ones(1), np.ones((2, 0))
+    elif case == "no_tsv":
+        txy, tr = np.zeros((0, 2), dtype=np.int32), np.ones((0, 2))
+    elif case == "dup_tsv":
+        txy = np.array([[1, 1], [1, 1]], dtype=np.int32)
+    elif case == "off_grid":
+        lxy = np.array([[5, 0]], dtype=np.int32)
+    elif case == "neg_r":
+        tr = -np.ones((2, 2))
+    with pytest.raises(reff.ReffError) as ei:
+        reff.reff_reduced_pairs(5, 5, r_t, s_t, txy, tr, bxy, lxy)
+    assert ei.value.status == reff.REFF_ERR_INVALID_ARG

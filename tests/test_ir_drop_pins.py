@@ -148,3 +148,17 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(irl, "drop_full", lambda *a: -real_full(*a))
     pc = irl.pad_currents(d, loads, amps)
     assert not np.allclose(pc.sum(axis=1), amps.sum(axis=1), rtol=1e-6)
+
+
+def test_band_plan_concentrates_bump_current():
+    """Sec. IV-B's observation on the synthetic planning study: with every
+    TSV in a central band a small fraction of the bumps carries 95 % of the
+    current; spreading the same TSVs uniformly spreads it over many more."""
+    st = gen.tsv_planning_study(side=64, n_tsv=64, bump_k=8, block_w=14, block_h=7)
+    share = {}
+    for plan in ("band", "uniform"):
+        pc = irl.pad_currents(st[plan], st["loads"], st["amps"])
+        assert np.allclose(pc.sum(), st["amps"].sum(), rtol=1e-10)
+        share[plan] = irl.share_pads_for(pc[0])
+    print(share)
+    assert share["band"] < 0.6 * share["uniform"]
