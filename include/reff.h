@@ -84,7 +84,12 @@ typedef struct {
   double rel_tol;        /* target relative error per R_i; 0 => 1e-8 (FP64)
                             or 1e-5 (MIXED)                                 */
   int32_t max_iters;     /* per block-PCG solve; 0 => 20000                 */
-  int32_t block_rhs;     /* right-hand sides per block: 64 (0 => 64)        */
+  int32_t block_rhs;     /* right-hand sides dealt to one block: 32 or 64;
+                            0 => 64.  The kernels give every right-hand
+                            side one lane of a 64-wide wave, so a block
+                            streams 64 columns either way: 32 halves the
+                            columns per block (twice the bytes per node
+                            solved) and is never faster                  */
   void* stream;          /* hipStream_t to run on; NULL => default stream    */
   int32_t out_on_device; /* 1: R_out is a device pointer; 0: host pointer   */
   reff_krylov krylov;    /* 0 => block                                       */

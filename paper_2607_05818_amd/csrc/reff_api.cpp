@@ -324,6 +324,7 @@ struct Opts {
   const char* tune_db = nullptr;  // tuning database path (batched solves)
   bool progress = false;          // progress lines on stderr
   int cheb = 19;                  // Chebyshev preconditioner degree (1 = Jacobi)
+  int brhs = S;                   // right-hand sides dealt to one block (32 or 64)
 };
 
 reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
@@ -338,8 +339,8 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
     return fail(REFF_ERR_INVALID_ARG, "rel_tol must be in [0, 1)");
   if (o->max_iters < 0) return fail(REFF_ERR_INVALID_ARG, "max_iters < 0");
   if (o->max_ir_steps < 0) return fail(REFF_ERR_INVALID_ARG, "max_ir_steps < 0");
-  if (o->block_rhs != 0 && o->block_rhs != S)
-    return fail(REFF_ERR_UNSUPPORTED, "block_rhs must be 0 or 64");
+  if (o->block_rhs != 0 && o->block_rhs != 32 && o->block_rhs != S)
+    return fail(REFF_ERR_INVALID_ARG, "block_rhs must be 0, 32 or 64");
   if (o->out_on_device != 0 && o->out_on_device != 1)
     return fail(REFF_ERR_INVALID_ARG, "out_on_device must be 0 or 1");
   out.mixed = o->precision == REFF_PREC_MIXED;
@@ -357,6 +358,10 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
   if (o->precond_degree < 0 || o->precond_degree > MAX_CHEB)
     return fail(REFF_ERR_INVALID_ARG, "precond_degree must be in [0, 32]");
   out.cheb = o->precond_degree == 0 ? 19 : o->precond_degree;
+  // The kernels map one right-hand side to one lane of a 64-wide wave, so a
+  // block always streams 64 columns: 32 leaves half of them empty (no saving)
+  // and the automatic choice (0) is 64.
+  out.brhs = o->block_rhs == 32 ? 32 : S;
   out.timing = o->timing == 1;
   return REFF_OK;
 }
@@ -998,15 +1003,15 @@ void add_stats(reff_solve_stats* st, const std::vector<BlockResult>& br, size_t 
 // ones give every block independent directions.  Column i's result goes to
 // position pos0 + i.
 void deal_blocks(const std::vector<int64_t>& cols, int32_t stack, int64_t pos0,
-                 std::vector<BlockJob>& jobs) {
+                 std::vector<BlockJob>& jobs, int per = S) {
   std::vector<int64_t> order(cols.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int64_t)i;
   std::mt19937_64 rng(0x9e3779b97f4a7c15ull);
   std::shuffle(order.begin(), order.end(), rng);
-  for (size_t j = 0; j < order.size(); j += S) {
+  for (size_t j = 0; j < order.size(); j += (size_t)per) {
     BlockJob jb;
     jb.stack = stack;
-    jb.ncol = (int)std::min<size_t>(S, order.size() - j);
+    jb.ncol = (int)std::min<size_t>((size_t)per, order.size() - j);
     for (int k = 0; k < jb.ncol; ++k) {
       const int64_t i = order[j + (size_t)k];
       jb.tgt[k] = cols[(size_t)i];
@@ -1219,7 +1224,7 @@ reff_status reff_solve_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, d
   std::vector<StackInfo> stacks{
       StackInfo{0, p->n, p->plane, p->nx, 0, (int32_t)p->gnd.n_slots}};
   std::vector<BlockJob> jobs;
-  deal_blocks(cols, 0, 0, jobs);
+  deal_blocks(cols, 0, 0, jobs, o.brhs);
   std::vector<BlockResult> br;
   reff_status solve_rs = run_blocks(p->ws, p->gnd, stacks, jobs, res_dev, o, br, st);
   if (solve_rs != REFF_OK && solve_rs != REFF_ERR_NO_CONVERGENCE) return solve_rs;
@@ -1280,7 +1285,7 @@ reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m, const int6
     const int64_t nn = p->n;
     std::vector<StackInfo> stacks{StackInfo{0, nn, p->plane, p->nx, 0, (int32_t)cs->n_slots}};
     std::vector<BlockJob> jobs;
-    deal_blocks(cols, 0, 0, jobs);
+    deal_blocks(cols, 0, 0, jobs, o.brhs);
     const int64_t nblk = (int64_t)jobs.size();
     std::vector<int32_t> blk_of((size_t)U), col_of((size_t)U);
     for (int64_t bb = 0; bb < nblk; ++bb)
@@ -1512,7 +1517,7 @@ reff_status reff_ir_drop(reff_pdn p, const int64_t* load_nodes, int64_t n_loads,
   if (U > 0 && n_scen > 0) {
     std::vector<StackInfo> stacks{StackInfo{0, nn, p->plane, p->nx, 0, (int32_t)cs.n_slots}};
     std::vector<BlockJob> jobs;
-    deal_blocks(cols, 0, 0, jobs);
+    deal_blocks(cols, 0, 0, jobs, o.brhs);
     const int64_t nblk = (int64_t)jobs.size();
     // blocks per group: solution vectors of a group within 8 GB
     const int64_t per = std::max<int64_t>(
@@ -1627,7 +1632,7 @@ static reff_status screen_plans(reff_surrogate sg, const reff_pdn_desc* plans, i
     spot_idx[(size_t)i] = order;
     std::vector<int64_t> ids(k);
     for (size_t j = 0; j < k; ++j) ids[j] = c[(size_t)order[j]];
-    deal_blocks(ids, i, spos, sjobs);
+    deal_blocks(ids, i, spos, sjobs, o.brhs);
     spos += (int64_t)k;
   }
   sjob0[(size_t)n_plans] = sjobs.size();
@@ -1660,7 +1665,7 @@ static reff_status screen_plans(reff_surrogate sg, const reff_pdn_desc* plans, i
     fjob0[(size_t)i] = fjobs.size();
     if (fallback[(size_t)i] && !cols[(size_t)i].empty()) {
       fpos0[(size_t)i] = fpos;
-      deal_blocks(cols[(size_t)i], i, fpos, fjobs);
+      deal_blocks(cols[(size_t)i], i, fpos, fjobs, o.brhs);
       fpos += (int64_t)cols[(size_t)i].size();
     }
   }
@@ -1799,7 +1804,7 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
     if (nfree < 16 * (int64_t)S) any_small = true;
     job0[(size_t)i] = jobs.size();
     res0[(size_t)i] = pos0;
-    deal_blocks(cols[(size_t)i], i, pos0, jobs);
+    deal_blocks(cols[(size_t)i], i, pos0, jobs, o.brhs);
     pos0 += (int64_t)cols[(size_t)i].size();
   }
   job0[(size_t)n_plans] = jobs.size();

@@ -217,7 +217,7 @@ def _is_torch_cuda(x):
 
 
 def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing=False,
-          graphs=False, progress=False, precond_degree=0):
+          graphs=False, progress=False, precond_degree=0, block_rhs=0):
     o = reff_solve_opts()
     o.progress = 1 if progress else 0
     o.precond_degree = int(precond_degree)
@@ -226,7 +226,7 @@ def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, 
     o.precision = int(precision)
     o.rel_tol = float(rel_tol)
     o.max_iters = int(max_iters)
-    o.block_rhs = 0
+    o.block_rhs = int(block_rhs)
     o.krylov = int(krylov)
     o.max_ir_steps = int(max_ir_steps)
     o.out_on_device = 1 if out_dev else 0
@@ -240,7 +240,7 @@ def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, 
 def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP64,
                     rel_tol=0.0, max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None,
                     max_ir_steps=0, allow_unconverged=False, timing=False, graphs=False,
-                    progress=False, precond_degree=0):
+                    progress=False, precond_degree=0, block_rhs=0):
     """R_i = (G^-1)_ii for `nodes` (None = all).  Returns (R_out, stats)."""
     if nodes is None:
         count = pdn.num_nodes
@@ -261,7 +261,7 @@ def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP6
         assert R_out.dtype == np.float64 and R_out.flags.c_contiguous and len(R_out) >= count
         optr = R_out.ctypes.data
     o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing, graphs,
-              progress, precond_degree)
+              progress, precond_degree, block_rhs)
     st = reff_solve_stats()
     allow = (REFF_ERR_NO_CONVERGENCE,) if allow_unconverged else ()
     _check(_lib.reff_solve_diag(pdn.handle, nptr, count if nodes is not None else 0, optr,

@@ -147,3 +147,22 @@ def test_reduced_pairs_rejected_on_host(case):
     with pytest.raises(reff.ReffError) as ei:
         reff.reff_reduced_pairs(5, 5, r_t, s_t, txy, tr, bxy, lxy)
     assert ei.value.status == reff.REFF_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("brhs", [16, 48, 128, -1])
+def test_block_rhs_other_than_0_32_64_rejected(brhs):
+    """Options are parsed on the host before any device work (a batch call
+    parses them before touching its plans' device state)."""
+    from paper_2607_05818_amd import reff
+    d = gen.config1()
+    s, keep = reff._desc_struct(d)
+    plans = (reff.reff_pdn_desc * 1)(s)
+    nptrs = (C.c_void_p * 1)(None)
+    ncount = (C.c_int64 * 1)(gen.n_nodes(d))
+    out = np.zeros(gen.n_nodes(d))
+    optrs = (C.c_void_p * 1)(out.ctypes.data)
+    bo = reff.reff_batch_opts()
+    bo.solve = reff._opts(reff.REFF_PREC_FP64, 0.0, 0, 0, None, False, 0, block_rhs=brhs)
+    rc = reff._lib.reff_batch_plans(plans, 1, nptrs, ncount, optrs, C.byref(bo), None)
+    assert rc == reff.REFF_ERR_INVALID_ARG
+    assert "block_rhs" in reff.reff_last_error()

@@ -167,3 +167,26 @@ def test_config2_full_size_sampled_golden():
     got, st = reff.reff_solve_diag(h, nodes, precision=reff.REFF_PREC_MIXED, rel_tol=1e-4)
     print("mixed", _max_rel(got, want), st, flush=True)
     assert _max_rel(got, want) <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_block_rhs_32(prec):
+    """Blocks of 32 right-hand sides (half of the 64 lanes of a block
+    empty) give the same results: plain stack (float64, 1e-6) and the
+    mixed-precision recipe at side 128 (1e-3), 200 nodes = 7 blocks of 32."""
+    reff = _reff()
+    if prec == "fp64":
+        d = gen.config1()
+        p, tol, bar = reff.REFF_PREC_FP64, 1e-9, 1e-6
+    else:
+        d = gen.config2(side=128, n_tsv=64, sigma=10.0)
+        p, tol, bar = reff.REFF_PREC_MIXED, 1e-4, 1e-3
+    nodes = gen.sample_free_nodes(d, 200, 21)
+    want = ro.diag(d, nodes=nodes)
+    _say("block_rhs 32", prec)
+    h = reff.reff_build_pdn(d)
+    got, st = reff.reff_solve_diag(h, nodes, precision=p, rel_tol=tol, block_rhs=32)
+    err = _max_rel(got, want)
+    print("max rel err", err, st["iters_total"], flush=True)
+    assert err <= bar
+    assert st["n_unconverged"] == 0
