@@ -105,53 +105,93 @@ def kernel_flops(cheb=1):
     return [2 * g * 10 // 16 + 2 * g, 3 * g, 2 * g, 0, 0]
 
 
-def cpu_baseline(desc, batch_nodes, n_timed=2):
-    """The CPU oracle as it stands, on a bounded sample: assembly + sparse
-    LU factorisation of G, then n_timed single-column solves; the time for
-    the whole batch is extrapolated as fixed + len(batch) * per-solve."""
+def host_info():
+    """Logical CPUs this process may run on, the CPU model and the RAM of the
+    host (from /proc)."""
+    info = {"nproc": len(os.sched_getaffinity(0)), "cpu_model": None, "ram_gb": None}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["ram_gb"] = round(int(line.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
+    return info
+
+
+def oracle_threads():
+    """Threads for the CPU oracle: every CPU this process may use, capped by
+    OMP_NUM_THREADS when the host sets it (a share of a larger machine)."""
+    n = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return n
+
+
+def cpu_baseline(desc, batch_nodes, want, full_map=True):
+    """The CPU oracle as it stands, timed on the host's cores: its
+    sparse-Cholesky factorisation of G (nested dissection, multifrontal)
+    followed by one unit-current solve per node of the batch, measured (not
+    extrapolated), and checked against the stored oracle values of the
+    batch.  With full_map, the selected inversion that then yields every
+    diagonal entry is timed as well (the oracle's full-map rate)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
-    from oracle import reff_oracle as ro
-    with threadpool_limits(limits=1):
+    from oracle import selinv
+    threads = oracle_threads()
+    n = int(desc["n_tiers"]) * int(desc["nx"]) * int(desc["ny"])
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
-        G, free = ro.grounded(desc)
+        F, free = selinv.factor(desc)
         t1 = time.perf_counter()
-        solver = ro._Solver(G)
-        t2 = time.perf_counter()
-        pos = np.full(int(desc["n_tiers"]) * int(desc["nx"]) * int(desc["ny"]), -1)
+        pos = np.full(n, -1, dtype=np.int64)
         pos[free] = np.arange(len(free))
-        ts = []
-        for v in batch_nodes[:n_timed]:
-            e = np.zeros(G.shape[0])
-            e[pos[v]] = 1.0
-            a = time.perf_counter()
-            solver.solve(e[:, None])
-            ts.append(time.perf_counter() - a)
-    per_solve = sum(ts) / len(ts)
-    fixed = (t1 - t0) + (t2 - t1)
-    t_batch = fixed + len(batch_nodes) * per_solve
-    return {
+        rows = pos[np.asarray(batch_nodes, dtype=np.int64)]
+        E = np.zeros((len(free), len(rows)))
+        E[rows, np.arange(len(rows))] = 1.0
+        X = F.solve(E)
+        got = X[rows, np.arange(len(rows))]
+        t2 = time.perf_counter()
+        t_sel = None
+        if full_map:
+            F.selected_inverse()
+            t_sel = time.perf_counter() - t2
+    err = float(np.max(np.abs(got - want) / want))
+    t_batch = t2 - t0
+    rec = {
         "value": len(batch_nodes) / t_batch,
         "unit": "nodes/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"float64 sparse-LU oracle on the same stack: assembly {t1 - t0:.1f} s + "
-                   f"factorisation {t2 - t1:.1f} s, {n_timed} timed unit-current solves "
-                   f"({per_solve:.2f} s each); batch of {len(batch_nodes)} nodes "
-                   f"extrapolated to {t_batch:.0f} s; BLAS limited to 1 thread"),
+        "sample": (f"the batch of {len(batch_nodes)} nodes on the same stack: float64 sparse "
+                   f"Cholesky of G (nested dissection, multifrontal; assembly included) "
+                   f"{t1 - t0:.1f} s + {len(batch_nodes)} unit-current solves {t2 - t1:.1f} s, "
+                   f"measured, {threads} threads; max rel diff to the stored values {err:.1e}"),
+        "host": host_info(),
     }
+    if full_map:
+        rec["full_map"] = {"nodes": int(len(free)), "seconds": (t1 - t0) + t_sel,
+                           "nodes_per_s": len(free) / ((t1 - t0) + t_sel),
+                           "factor_seconds": t1 - t0, "selected_inversion_seconds": t_sel}
+    return rec
 
 
-def grid_pairs_compare(reff, log, M=512, N=512, P=256, reps=3):
+def grid_pairs_compare(reff, log, M=512, N=512, P=256, reps=5):
     """Eq. 3 on one uniform tier (the intra-die step of the paper's pair
     method, Sec. III-C/D): every pair of P seeded points on an M x N grid,
     output to device memory, checked on sampled pairs against the closed form
-    summed directly in float64.  The work is counted in the direct form:
-    each pair is a double sum over (M-1)(N-1) terms of 6 float64 flops (two
-    products and their difference, the square, the weight, the
-    accumulation); the library evaluates it as a float64 matrix-core product
-    (T = X diag(W) X^T)."""
+    summed directly in float64.  The library evaluates the double sums as
+    T = X diag(W) X^T on the float64 matrix cores: 64 x 64 blocks of T for the
+    upper block pairs, each a product over K = (M-1)(N-1), i.e.
+    2 * 64 * 64 * K flops per block pair; that issued work is the roofline
+    figure.  The direct form (6 flops per term and pair) is reported beside
+    it as an equivalent rate only."""
     import numpy as np
     import torch
     from tests import pins
@@ -174,60 +214,152 @@ def grid_pairs_compare(reff, log, M=512, N=512, P=256, reps=3):
     for i, j in [(0, 1), (7, 200), (100, 255), (31, 32)]:
         w = pins.wu_two_point(M, N, r, s, *xy[i], *xy[j])
         err = max(err, abs(R[i, j] - w) / w)
-    tflops = 6.0 * terms / dt / 1e12
-    log(f"grid pairs (Eq. 3): {pairs / dt:.3g} pairs/s, {tflops:.1f} TFLOP/s float64, err {err:.1e}")
+    nb = (P + 63) // 64
+    issued = nb * (nb + 1) // 2 * 2 * 64 * 64 * (M - 1) * (N - 1)
+    tflops = issued / dt / 1e12
+    direct = 6.0 * terms / dt / 1e12
+    log(f"grid pairs (Eq. 3): {pairs / dt:.3g} pairs/s, {tflops:.1f} TFLOP/s issued float64 "
+        f"matrix-core work, err {err:.1e}")
     return {"workload": f"Eq. 3, all pairs of {P} seeded points on a uniform {M} x {N} grid",
-            "pairs_per_s": pairs / dt, "seconds": dt, "terms_per_s": terms / dt,
-            "fp64_tflops": tflops, "fp64_vector_peak_tflops": 78.6,
-            "frac": tflops / 78.6, "bound": "mfma", "max_rel_err_sampled": err}
+            "pairs_per_s": pairs / dt, "seconds": dt, "reps": reps, "terms_per_s": terms / dt,
+            "issued_flops": issued, "fp64_tflops": tflops, "peak_tflops": 78.6,
+            "frac": tflops / 78.6, "bound": "mfma",
+            "direct_form_equiv_tflops": direct, "max_rel_err_sampled": err}
 
 
-def batched_compare(reff, gen, log, rel_tol, n_seq=16):
+def batched_compare(reff, gen, log, rel_tol, n_seq=16, reps=3):
     """The batching workload: 256 candidate TSV plans (2-4 tiers, sides
     64-256, about 22M nodes in total) with one seeded 64-node block per
-    plan, solved in one reff_batch_plans call (mixed precision), against
-    one reff_build_pdn + reff_solve_diag per plan on the first n_seq plans
-    (extrapolated).  Accuracy is checked on the plans the stored oracle
-    fixture covers."""
+    plan, solved in one reff_batch_plans call (mixed precision; the median
+    of `reps` calls), and in float64 in one call, against one
+    reff_build_pdn + reff_solve_diag per plan on the first n_seq plans
+    (mixed, and the plain float64 block PCG).  Every plan's results are
+    checked against the stored oracle values and only nodes within 1e-3
+    count."""
     import numpy as np
     import torch
     plans = gen.config3_plans()
     nodes = gen.config3_samples(plans)
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "config3_sample.json")))
-    total = sum(len(x) for x in nodes)
-    prec = reff.REFF_PREC_MIXED
-    # first call on a few plans: lazy runtime initialisation
-    reff.reff_batch_plans(plans[:4], nodes[:4], precision=prec, rel_tol=rel_tol)
-    torch.cuda.synchronize()
-    a = time.perf_counter()
-    outs, stats = reff.reff_batch_plans(plans, nodes, precision=prec, rel_tol=rel_tol)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - a
-    errs = []
-    for i in range(len(gold["nodes"])):
+    assert len(gold["nodes"]) == len(plans)
+    for i in range(len(plans)):
         assert list(nodes[i]) == gold["nodes"][i], "batching sample drifted from the fixture"
-        want = np.array(gold["R"][i])
-        errs.append(float(np.max(np.abs(outs[i] - want) / want)))
-    a = time.perf_counter()
-    for i in range(n_seq):
-        h = reff.reff_build_pdn(plans[i])
-        reff.reff_solve_diag(h, nodes[i], precision=prec, rel_tol=rel_tol)
-        h.close()
+    want = [np.array(g) for g in gold["R"]]
+    total = sum(len(x) for x in nodes)
+
+    def check(outs):
+        rel = np.concatenate([np.abs(outs[i] - want[i]) / want[i] for i in range(len(plans))])
+        return int(np.sum(rel <= 1e-3)), float(rel.max())
+
+    # first call on a few plans: lazy runtime initialisation
+    reff.reff_batch_plans(plans[:4], nodes[:4], precision=reff.REFF_PREC_MIXED, rel_tol=rel_tol)
     torch.cuda.synchronize()
-    dseq = time.perf_counter() - a
-    seq_nodes = sum(len(nodes[i]) for i in range(n_seq))
-    rec = {
-        "workload": "256 TSV plans, 2-4 tiers x side 64-256 (%d nodes), 64 seeded nodes per plan"
-                    % sum(gen.n_nodes(d) for d in plans),
-        "nodes_per_s": total / dt, "seconds": dt, "nodes": total,
-        "iters_max": max(x["iters_max"] for x in stats),
-        "checked_plans": len(errs), "max_rel_err_checked": max(errs),
-        "est_max_rel_err": max(x["est_max_rel_err"] for x in stats),
-        "sequential_nodes_per_s": seq_nodes / dseq, "sequential_plans_timed": n_seq,
-        "rel_tol": rel_tol,
-    }
-    log(f"batched: {total / dt:.1f} nodes/s ({dt:.2f} s), sequential {seq_nodes / dseq:.1f} "
-        f"nodes/s, checked err {max(errs):.2e}")
+    rec = {"workload": "256 TSV plans, 2-4 tiers x side 64-256 (%d nodes), 64 seeded nodes per plan"
+                       % sum(gen.n_nodes(d) for d in plans), "nodes": total, "rel_tol": rel_tol}
+    for tag, prec, nrep in (("mixed", reff.REFF_PREC_MIXED, reps), ("fp64", reff.REFF_PREC_FP64, 1)):
+        dts = []
+        for _ in range(nrep):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            outs, stats = reff.reff_batch_plans(plans, nodes, precision=prec, rel_tol=rel_tol)
+            torch.cuda.synchronize()
+            dts.append(time.perf_counter() - a)
+        dt = float(np.median(dts))
+        n_ok, worst = check(outs)
+        rec["batched_" + tag] = {"nodes_per_s": n_ok / dt, "seconds": dt, "seconds_all": dts,
+                                 "n_ok": n_ok, "max_rel_err": worst,
+                                 "iters_max": max(x["iters_max"] for x in stats)}
+        log(f"batched {tag}: {n_ok / dt:.1f} nodes/s ({dt:.2f} s), {n_ok}/{total} within 1e-3, "
+            f"max err {worst:.2e}")
+    for tag, prec in (("sequential_mixed", reff.REFF_PREC_MIXED),
+                      ("sequential_fp64", reff.REFF_PREC_FP64)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        n_ok = 0
+        worst = 0.0
+        for i in range(n_seq):
+            h = reff.reff_build_pdn(plans[i])
+            got = reff.reff_solve_diag(h, nodes[i], precision=prec, rel_tol=rel_tol)[0]
+            h.close()
+            rel = np.abs(got - want[i]) / want[i]
+            n_ok += int(np.sum(rel <= 1e-3))
+            worst = max(worst, float(rel.max()))
+        torch.cuda.synchronize()
+        dseq = time.perf_counter() - a
+        rec[tag] = {"nodes_per_s": n_ok / dseq, "seconds": dseq, "plans_timed": n_seq,
+                    "n_ok": n_ok, "max_rel_err": worst}
+        log(f"{tag}: {n_ok / dseq:.1f} nodes/s over {n_seq} plans (build + solve per plan)")
+    rec["nodes_per_s"] = rec["batched_mixed"]["nodes_per_s"]
+    return rec
+
+
+def reduced_pairs_compare(reff, gen, log, d=4, side=512, p=512, m=128, n=2048, reps=3):
+    """The paper's own pair method (Sec. III-C/D) on uniform tiers: m bumps
+    on tier 0 to n loads on the last tier through the reduced system
+    (reff_reduced_pairs), pairs/s; four sampled pairs cross-checked against
+    the block PCG on the whole stack (reff_query_pairs, floating mode,
+    float64), an independent device path."""
+    import numpy as np
+    w = gen.uniform_tier_stack(3101, d, side, p, m, n)
+    args = (side, side, w["r_t"], w["s_t"], w["tsv_xy"], w["tsv_r"], w["bump_xy"], w["load_xy"])
+    reff.reff_reduced_pairs(*args)   # warm-up
+    dts = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        R = reff.reff_reduced_pairs(*args)
+        dts.append(time.perf_counter() - a)
+    dt = float(np.median(dts))
+    nx = side
+    gx = np.concatenate([np.full(nx * (nx - 1), 1.0 / w["r_t"][t]) for t in range(d)])
+    gy = np.concatenate([np.full((nx - 1) * nx, 1.0 / w["s_t"][t]) for t in range(d)])
+    desc = gen.make_desc(d, nx, nx, gx, gy, w["tsv_xy"], 1.0 / w["tsv_r"],
+                         np.array([[0, 0]], dtype=np.int32))
+    bi, lj = np.array([0, m - 1]), np.array([0, n - 1])
+    a_ids = w["bump_xy"][bi, 1].astype(np.int64) * nx + w["bump_xy"][bi, 0]
+    b_ids = (d - 1) * nx * nx + w["load_xy"][lj, 1].astype(np.int64) * nx + w["load_xy"][lj, 0]
+    h = reff.reff_build_pdn(desc)
+    a = time.perf_counter()
+    ref = reff.reff_query_pairs(h, a_ids, b_ids, mode=reff.REFF_PAIRS_FLOATING,
+                                precision=reff.REFF_PREC_FP64, rel_tol=1e-12)[0]
+    t_pcg = time.perf_counter() - a
+    h.close()
+    err = float(np.max(np.abs(R[np.ix_(bi, lj)] - ref) / ref))
+    log(f"reduced pairs (Sec. III-C/D): {m * n / dt:.3g} pairs/s ({dt * 1e3:.1f} ms), "
+        f"max rel diff to block PCG {err:.1e}")
+    return {"workload": f"{d} uniform tiers of {side} x {side}, {p} TSV columns, {m} bumps x "
+                        f"{n} loads", "pairs_per_s": m * n / dt, "seconds": dt,
+            "seconds_all": dts, "reduced_size": (p + 1) * (d - 1),
+            "max_rel_diff_vs_block_pcg_floating": err, "block_pcg_seconds_4_pairs": t_pcg}
+
+
+def tsv_planning_compare(reff, gen, log):
+    """Sec. IV-B's TSV-planning comparison on a synthetic analog: band-like
+    and uniformly spread TSV plans of one stack, four functional blocks on
+    the last tier; through-bump currents by superposition of unit-load
+    responses (reff_ir_drop, Eq. 4) and the share of bumps that carries 95 %
+    of the current."""
+    import numpy as np
+
+    def share(c, frac=0.95):
+        # fraction of the bumps that, largest first, carry frac of the current
+        c = np.sort(np.asarray(c))[::-1]
+        return (int(np.searchsorted(np.cumsum(c), frac * c.sum())) + 1) / len(c)
+
+    st = gen.tsv_planning_study()
+    rec = {"workload": "3 tiers x 128 x 128, 256 bumps (16 x 16), 256 TSV columns per plan, "
+                       f"4 functional blocks = {len(st['loads'])} load nodes on the last tier"}
+    for plan in ("band", "uniform"):
+        h = reff.reff_build_pdn(st[plan])
+        a = time.perf_counter()
+        drop, pads, s2 = reff.reff_ir_drop(h, st["loads"], st["amps"], precision=reff.REFF_PREC_MIXED)
+        dt = time.perf_counter() - a
+        h.close()
+        rec[plan] = {"share_of_bumps_for_95pct": share(pads[0]),
+                     "max_drop_V": float(drop.max()), "seconds": dt,
+                     "unit_load_solves": int(s2["n_solved"]),
+                     "kirchhoff_rel": float(abs(pads.sum() - st["amps"].sum()) / st["amps"].sum())}
+        log(f"TSV planning, {plan}: {100 * rec[plan]['share_of_bumps_for_95pct']:.1f}% of bumps carry "
+            f"95% of the current, max drop {drop.max():.3f} V, {dt:.2f} s")
     return rec
 
 
@@ -371,6 +503,50 @@ def large_run(args, reff, gen, log):
     print(json.dumps(rec), flush=True)
 
 
+def full_map_run(args, reff, gen, log):
+    """The full map of the mixed-precision stack (all 1,048,576 node ids) in
+    mixed precision, one part of `parts` contiguous id ranges per run (a whole
+    map takes about 20 minutes), compared node by node with the stored oracle
+    map (selected inversion, float32 storage); pads must come out exactly 0.
+    The part's results are saved under gpurun_out/ for a later merge."""
+    import numpy as np
+    import torch
+    desc = gen.config2()
+    n = gen.n_nodes(desc)
+    k, i = args.parts, args.part
+    assert 0 <= i < k
+    lo, hi = i * n // k, (i + 1) * n // k
+    ids = np.arange(lo, hi, dtype=np.int64)
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "config2_fullmap_f32.npy")).astype(np.float64)
+    want = gold[lo:hi]
+    log(f"full map part {i}/{k}: node ids [{lo}, {hi})")
+    h = reff.reff_build_pdn(desc, device=0)
+    out = torch.empty(hi - lo, dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    st = reff.reff_solve_diag(h, ids, out, precision=reff.REFF_PREC_MIXED, rel_tol=args.rel_tol,
+                              stream=stream.cuda_stream, progress=True)[1]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - a
+    got = out.cpu().numpy()
+    free = want > 0
+    rel = np.abs(got[free] - want[free]) / want[free]
+    n_ok = int(np.sum(rel <= 1e-3))
+    pads_zero = bool(np.all(got[~free] == 0.0))
+    odir = os.path.join(ROOT, "gpurun_out")
+    os.makedirs(odir, exist_ok=True)
+    np.save(os.path.join(odir, f"fullmap_config2_part{i}of{k}.npy"), got)
+    rec = {"full_map_part": i, "parts": k, "ids": [lo, hi], "free_nodes": int(free.sum()),
+           "n_ok": n_ok, "max_rel_err": float(rel.max()), "pads_exactly_zero": pads_zero,
+           "seconds": dt, "nodes_per_s": n_ok / dt, "iters_total": st["iters_total"],
+           "iters_max": st["iters_max"], "rel_tol": args.rel_tol,
+           "workload": "mixed-precision stack 4 x 512 x 512, full map"}
+    log(f"full map part {i}/{k}: {n_ok}/{int(free.sum())} within 1e-3, max err {rel.max():.2e}, "
+        f"{dt:.1f} s, {n_ok / dt:.1f} nodes/s")
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,6 +567,11 @@ def main():
     ap.add_argument("--large", action="store_true",
                     help="only the large-stack subset measurement (8 x 2048 x 2048)")
     ap.add_argument("--large-blocks", type=int, default=1)
+    ap.add_argument("--full-map", action="store_true",
+                    help="only the full map of the mixed-precision stack, one part of --parts "
+                         "contiguous node-id ranges, against the stored oracle map")
+    ap.add_argument("--part", type=int, default=0)
+    ap.add_argument("--parts", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy kernel 4 times (the "
                          "reference point for HBM byte counters)")
@@ -421,6 +602,9 @@ def main():
 
     if args.large:
         large_run(args, reff, gen, log)
+        return
+    if args.full_map:
+        full_map_run(args, reff, gen, log)
         return
     desc = gen.config2()
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "config2_sample.json")))
@@ -518,25 +702,39 @@ def main():
 
     compare = {}
     if not args.no_compare and args.precision == "mixed":
-        # The plain float64 block-PCG and the independent-column variant on
-        # one 64-node block of the same batch, same GPU.
-        for tag, p, kk, tol in (("plain_fp64_block", reff.REFF_PREC_FP64, reff.REFF_KRYLOV_BLOCK, 1e-6),
-                                ("mixed_independent", reff.REFF_PREC_MIXED,
-                                 reff.REFF_KRYLOV_INDEPENDENT, args.rel_tol)):
-            o2 = torch.empty(S, dtype=torch.float64, device="cuda:0")
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            st2 = reff.reff_solve_diag(h, batch[:S], o2, precision=p, krylov=kk, rel_tol=tol,
-                                       stream=stream.cuda_stream)[1]
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - a
-            e2 = float(np.max(np.abs(o2.cpu().numpy() - want[:S]) / want[:S]))
-            compare[tag] = {"nodes_per_s": S / dt, "iters": st2["iters_total"],
-                            "max_rel_err": e2, "rel_tol": tol}
-            log(f"{tag}: {S / dt:.1f} nodes/s, {st2['iters_total']} iterations, err {e2:.2e}")
+        # The plain float64 block PCG (at the metric's 1e-3 bar and at the
+        # float64 path's 1e-6 parity bar) and the independent-column mixed
+        # variant on the same batch, same GPU: one warm-up call, then the
+        # median of three timed calls.
+        o2 = torch.empty(B, dtype=torch.float64, device="cuda:0")
+        for tag, p, kk, tol in (
+                ("plain_fp64_block", reff.REFF_PREC_FP64, reff.REFF_KRYLOV_BLOCK, args.rel_tol),
+                ("plain_fp64_block_1e-6", reff.REFF_PREC_FP64, reff.REFF_KRYLOV_BLOCK, 1e-6),
+                ("mixed_independent", reff.REFF_PREC_MIXED, reff.REFF_KRYLOV_INDEPENDENT,
+                 args.rel_tol)):
+            dts = []
+            for rep in range(4):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                st2 = reff.reff_solve_diag(h, batch, o2, precision=p, krylov=kk, rel_tol=tol,
+                                           stream=stream.cuda_stream)[1]
+                torch.cuda.synchronize()
+                if rep:
+                    dts.append(time.perf_counter() - a)
+            dt = float(np.median(dts))
+            rel2 = np.abs(o2.cpu().numpy() - want) / want
+            ok2 = int(np.sum(rel2 <= 1e-3))
+            compare[tag] = {"nodes_per_s": ok2 / dt, "seconds": dt, "seconds_all": dts,
+                            "iters": st2["iters_total"], "n_ok": ok2, "n": B,
+                            "max_rel_err": float(rel2.max()), "rel_tol": tol}
+            log(f"{tag}: {ok2 / dt:.1f} nodes/s, {st2['iters_total']} iterations, "
+                f"err {rel2.max():.2e}")
 
     if not args.no_compare:
         compare["grid_pairs"] = grid_pairs_compare(reff, log)
+    if not args.no_compare:
+        compare["reduced_pairs"] = reduced_pairs_compare(reff, gen, log)
+        compare["tsv_planning"] = tsv_planning_compare(reff, gen, log)
     if not args.no_batched and args.precision == "mixed":
         compare["batched_plans"] = batched_compare(reff, gen, log, args.rel_tol)
     if not args.no_surrogate and args.precision == "mixed":
@@ -545,7 +743,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(desc, batch)
+        cpu = cpu_baseline(desc, batch, want)
         log(f"cpu baseline {cpu['value']:.4f} nodes/s")
 
     rec = {
