@@ -230,8 +230,11 @@ typedef struct {
   const char* tune_db;     /* NULL, or a tuning database file (created if
                               absent): per size class of a launch group
                               (precision, variant, rows, blocks) the work
-                              units per launch; a class not yet in it is
-                              timed on a few candidates first and added   */
+                              units per launch of the row-range kernels and
+                              the strips per launch of the stencil passes
+                              (which sets the strip height, i.e. the tile
+                              shape); a class not yet in it is timed on 12
+                              candidate pairs first and added             */
 } reff_batch_opts;
 
 /*

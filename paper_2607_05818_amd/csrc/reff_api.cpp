@@ -503,34 +503,43 @@ __global__ void k_gather_flags(const BlockState* __restrict__ st, int nb, int32_
   }
 }
 
-// Tuning database: one line "<size class> <work units per launch>" per
-// entry.  The size class is the precision, the Krylov variant, log2 of the
-// rows of a launch group and the number of its blocks.
+// Tuning database: one line "<size class> <work units> <strips>" per entry:
+// the work units per launch of the row-range kernels and the strips per
+// launch of the stencil passes (which fixes the strips' height, the tile
+// shape of those passes: CH nodes wide, H rows tall).  The size class is the
+// precision, the Krylov variant, log2 of the rows of a launch group and the
+// number of its blocks.
+struct TuneChoice {
+  int units = 0, strips = 0;
+};
 struct TuneDb {
-  std::vector<std::pair<std::string, int>> e;
+  std::vector<std::pair<std::string, TuneChoice>> e;
+  static bool ok(int v) { return v >= 64 && v <= (1 << 16); }
   void load(const char* path) {
     e.clear();
     FILE* f = std::fopen(path, "r");
     if (!f) return;
     char key[128];
-    int v = 0;
-    while (std::fscanf(f, "%127s %d", key, &v) == 2)
-      if (v >= 64 && v <= (1 << 16)) e.emplace_back(key, v);
+    TuneChoice c;
+    while (std::fscanf(f, "%127s %d %d", key, &c.units, &c.strips) == 3)
+      if (ok(c.units) && ok(c.strips)) e.emplace_back(key, c);
     std::fclose(f);
   }
-  int get(const std::string& k) const {
+  TuneChoice get(const std::string& k) const {
     for (const auto& kv : e)
       if (kv.first == k) return kv.second;
-    return 0;
+    return TuneChoice{};
   }
-  bool save(const char* path, const std::string& k, int v) {
+  bool save(const char* path, const std::string& k, TuneChoice v) {
     load(path);
+    bool found = false;
     for (auto& kv : e)
-      if (kv.first == k) kv.second = v;
-    if (!get(k)) e.emplace_back(k, v);
+      if (kv.first == k) kv.second = v, found = true;
+    if (!found) e.emplace_back(k, v);
     FILE* f = std::fopen(path, "w");
     if (!f) return false;
-    for (const auto& kv : e) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+    for (const auto& kv : e)
+      std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.units, kv.second.strips);
     return std::fclose(f) == 0;
   }
 };
@@ -631,18 +640,20 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     // Work units per launch: the tuning database's entry for this size
     // class, or (new class) the fastest of a few candidates, each timed over
     // one chunk of iterations from a fresh start.
-    int target = TARGET_UNITS;
-    std::vector<int> trials;
+    TuneChoice target{TARGET_UNITS, TARGET_UNITS};
+    std::vector<TuneChoice> trials;
     std::string tkey;
     TuneDb tdb;
     if (o.tune_db) {
       tkey = tune_key(fp32, o.indep, rows, nb);
       tdb.load(o.tune_db);
-      const int v = tdb.get(tkey);
-      if (v > 0)
+      const TuneChoice v = tdb.get(tkey);
+      if (v.units > 0) {
         target = v;
-      else
-        trials = {512, 1024, 2048};
+      } else {
+        for (int u : {512, 1024, 2048})
+          for (int sp : {256, 512, 1024, 2048}) trials.push_back(TuneChoice{u, sp});
+      }
     }
     std::vector<float> trial_ms;
     std::vector<PlanDesc> plans;
@@ -657,12 +668,12 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     SolveBuffers b;
     for (size_t attempt = 0; attempt <= trials.size(); ++attempt) {
     const bool trial = attempt < trials.size();
-    const int tunits = trial ? trials[attempt] : target;
-    make_units(pin, plans, units, tunits);
+    const TuneChoice tc = trial ? trials[attempt] : target;
+    make_units(pin, plans, units, tc.units);
     nu = (int)units.size();
     strips.clear();
     const bool cheb = !o.indep && o.cheb > 1;
-    if ((fp32 || cheb) && !o.indep) make_strips(plans, strips, tunits);
+    if ((fp32 || cheb) && !o.indep) make_strips(plans, strips, tc.strips);
     ns = (int)strips.size();
     // ---- buffers
     reff_status rs;
@@ -1279,23 +1290,62 @@ reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m, const int6
                             [&](int64_t v) { return cs->grounded[(size_t)v] != 0; }),
              cols.end());
   const int64_t U = (int64_t)cols.size();
-  std::vector<double> K((size_t)(U * U), 0.0);
   reff_status solve_rs = REFF_OK;
+  // Endpoint index of every a_i / b_j (-1: grounded, K row and column 0).
+  auto idx = [&](int64_t v) -> int64_t {
+    auto it = std::lower_bound(cols.begin(), cols.end(), v);
+    return (it != cols.end() && *it == v) ? (int64_t)(it - cols.begin()) : -1;
+  };
+  std::vector<int64_t> ia((size_t)m), ib((size_t)n);
+  for (int64_t i = 0; i < m; ++i) ia[(size_t)i] = idx(a[i]);
+  for (int64_t j = 0; j < n; ++j) ib[(size_t)j] = idx(b[j]);
+  const int64_t nn = p->n;
+  std::vector<StackInfo> stacks{StackInfo{0, nn, p->plane, p->nx, 0, (int32_t)cs->n_slots}};
+  std::vector<BlockJob> jobs;
+  if (U > 0) deal_blocks(cols, 0, 0, jobs, o.brhs);
+  const int64_t nblk = (int64_t)jobs.size();
+  std::vector<int32_t> blk_of((size_t)std::max<int64_t>(U, 1)), col_of((size_t)std::max<int64_t>(U, 1));
+  for (int64_t bb = 0; bb < nblk; ++bb)
+    for (int k = 0; k < jobs[(size_t)bb].ncol; ++k) {
+      blk_of[(size_t)jobs[(size_t)bb].pos[k]] = (int32_t)bb;
+      col_of[(size_t)jobs[(size_t)bb].pos[k]] = k;
+    }
+  // device tables: endpoint nodes, maps, gathered rows, cross Grams, output
+  struct Local {
+    std::vector<void*> ptrs;
+    ~Local() {
+      for (void* q : ptrs) (void)hipFree(q);
+    }
+    hipError_t get(void** out, size_t bytes) {
+      hipError_t e = hipMalloc(out, std::max<size_t>(bytes, 8));
+      if (e == hipSuccess) ptrs.push_back(*out);
+      return e;
+    }
+  } loc;
+  void *d_nodes, *d_ia, *d_ib, *d_aid, *d_bid, *d_blk, *d_col, *d_rows, *d_cg, *d_out;
+  HIPCHK(loc.get(&d_nodes, (size_t)U * sizeof(int64_t)));
+  HIPCHK(loc.get(&d_ia, (size_t)m * sizeof(int64_t)));
+  HIPCHK(loc.get(&d_ib, (size_t)n * sizeof(int64_t)));
+  HIPCHK(loc.get(&d_aid, (size_t)m * sizeof(int64_t)));
+  HIPCHK(loc.get(&d_bid, (size_t)n * sizeof(int64_t)));
+  HIPCHK(loc.get(&d_blk, (size_t)U * sizeof(int32_t)));
+  HIPCHK(loc.get(&d_col, (size_t)U * sizeof(int32_t)));
+  HIPCHK(loc.get(&d_rows, (size_t)nblk * U * S * sizeof(double)));
+  HIPCHK(loc.get(&d_cg, (size_t)nblk * nblk * S * S * sizeof(double)));
+  HIPCHK(loc.get(&d_out, o.out_dev ? 8 : (size_t)(m * n) * sizeof(double)));
+  auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, o.stream) : hipSuccess;
+  };
+  HIPCHK(up(d_nodes, cols.data(), (size_t)U * sizeof(int64_t)));
+  HIPCHK(up(d_ia, ia.data(), (size_t)m * sizeof(int64_t)));
+  HIPCHK(up(d_ib, ib.data(), (size_t)n * sizeof(int64_t)));
+  HIPCHK(up(d_aid, a, (size_t)m * sizeof(int64_t)));
+  HIPCHK(up(d_bid, b, (size_t)n * sizeof(int64_t)));
+  HIPCHK(up(d_blk, blk_of.data(), (size_t)U * sizeof(int32_t)));
+  HIPCHK(up(d_col, col_of.data(), (size_t)U * sizeof(int32_t)));
   if (U > 0) {
-    const int64_t nn = p->n;
-    std::vector<StackInfo> stacks{StackInfo{0, nn, p->plane, p->nx, 0, (int32_t)cs->n_slots}};
-    std::vector<BlockJob> jobs;
-    deal_blocks(cols, 0, 0, jobs, o.brhs);
-    const int64_t nblk = (int64_t)jobs.size();
-    std::vector<int32_t> blk_of((size_t)U), col_of((size_t)U);
-    for (int64_t bb = 0; bb < nblk; ++bb)
-      for (int k = 0; k < jobs[(size_t)bb].ncol; ++k) {
-        blk_of[(size_t)jobs[(size_t)bb].pos[k]] = (int32_t)bb;
-        col_of[(size_t)jobs[(size_t)bb].pos[k]] = k;
-      }
     reff_status rs;
     if ((rs = ensure(p->ws.xs, (size_t)nblk * nn * S * sizeof(double))) != REFF_OK) return rs;
-    if ((rs = ensure(p->ws.rows, (size_t)(U * S + U) * sizeof(double))) != REFF_OK) return rs;
     if ((rs = ensure(p->ws.out, (size_t)(U + 1) * sizeof(double))) != REFF_OK) return rs;
     double* xs = (double*)p->ws.xs.p;
     std::vector<int64_t> xoff((size_t)nblk);
@@ -1304,76 +1354,37 @@ reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m, const int6
     solve_rs = run_blocks(p->ws, *cs, stacks, jobs, (double*)p->ws.out.p, o, br, st, xs, &xoff);
     if (solve_rs != REFF_OK && solve_rs != REFF_ERR_NO_CONVERGENCE) return solve_rs;
     add_stats(st, br, 0, br.size());
-    // x_u[v] for every endpoint pair: gather the endpoint rows of each block.
-    int64_t* node_dev = (int64_t*)((double*)p->ws.rows.p + U * S);
-    double* rows_dev = (double*)p->ws.rows.p;
-    HIPCHK(hipMemcpyAsync(node_dev, cols.data(), U * sizeof(int64_t), hipMemcpyHostToDevice,
-                          o.stream));
-    std::vector<double> rows((size_t)(nblk * U * S));
-    for (int64_t bb = 0; bb < nblk; ++bb) {
-      HIPCHK(launch_gather_rows(xs + bb * nn * S, node_dev, U, rows_dev, o.stream));
-      HIPCHK(hipMemcpyAsync(rows.data() + bb * U * S, rows_dev, U * S * sizeof(double),
-                            hipMemcpyDeviceToHost, o.stream));
-      HIPCHK(hipStreamSynchronize(o.stream));
-    }
+    // x_u[v] for every endpoint pair: the endpoint rows of each block
+    for (int64_t bb = 0; bb < nblk; ++bb)
+      HIPCHK(launch_gather_rows(xs + bb * nn * S, (const int64_t*)d_nodes, U,
+                                (double*)d_rows + bb * U * S, o.stream));
     // Cross terms x_u^T G x_v between (and within) solved blocks: the
     // bilinear estimate K_uv = x_u[v] + x_v[u] - x_u^T G x_v has an error that
-    // is a product of the two solution errors (second order).
+    // is a product of the two solution errors (second order).  All block
+    // pairs are queued on the stream; nothing waits on the host.
     SolveBuffers sb;
     PinnedBuf pin;
     if ((rs = single_work(p->ws, stacks[0], sb, o.stream, pin)) != REFF_OK) return rs;
     const Coef<double> c64 = coef64(*cs);
-    std::vector<double> C((size_t)(nblk * nblk * S * S));
-    std::vector<double> tmp(S * S);
     for (int64_t b1 = 0; b1 < nblk; ++b1)
       for (int64_t b2 = b1; b2 < nblk; ++b2) {
         HIPCHK(launch_cross_gram(c64, xs + b1 * nn * S, xs + b2 * nn * S, sb, o.stream));
-        HIPCHK(hipMemcpyAsync(tmp.data(), sb.W, S * S * sizeof(double), hipMemcpyDeviceToHost,
-                              o.stream));
-        HIPCHK(hipStreamSynchronize(o.stream));
-        for (int i = 0; i < S; ++i)
-          for (int j = 0; j < S; ++j) {
-            C[(size_t)(((b1 * nblk + b2) * S + i) * S + j)] = tmp[(size_t)(i * S + j)];
-            C[(size_t)(((b2 * nblk + b1) * S + j) * S + i)] = tmp[(size_t)(i * S + j)];
-          }
+        HIPCHK(hipMemcpyAsync((double*)d_cg + (b1 * nblk + b2) * S * S, sb.W,
+                              S * S * sizeof(double), hipMemcpyDeviceToDevice, o.stream));
       }
-    for (int64_t u = 0; u < U; ++u)
-      for (int64_t v = 0; v < U; ++v) {
-        const int64_t bu = blk_of[(size_t)u], cu = col_of[(size_t)u];
-        const int64_t bv = blk_of[(size_t)v], cv = col_of[(size_t)v];
-        const double xuv = rows[(size_t)((bu * U + v) * S + cu)];
-        const double xvu = rows[(size_t)((bv * U + u) * S + cv)];
-        const double g = C[(size_t)(((bu * nblk + bv) * S + cu) * S + cv)];
-        K[(size_t)(u * U + v)] = xuv + xvu - g;
-      }
-  }
-  auto idx = [&](int64_t v) -> int64_t {
-    auto it = std::lower_bound(cols.begin(), cols.end(), v);
-    return (it != cols.end() && *it == v) ? (int64_t)(it - cols.begin()) : -1;
-  };
-  std::vector<double> R((size_t)(m * n));
-  for (int64_t i = 0; i < m; ++i) {
-    const int64_t ia = idx(a[i]);
-    for (int64_t j = 0; j < n; ++j) {
-      double r = 0.0;
-      if (a[i] != b[j]) {
-        const int64_t jb = idx(b[j]);
-        const double kaa = ia >= 0 ? K[(size_t)(ia * U + ia)] : 0.0;
-        const double kbb = jb >= 0 ? K[(size_t)(jb * U + jb)] : 0.0;
-        const double kab = (ia >= 0 && jb >= 0) ? K[(size_t)(ia * U + jb)] : 0.0;
-        r = kaa + kbb - 2.0 * kab;
-      }
-      R[(size_t)(i * n + j)] = r;
-    }
+    HIPCHK(hipStreamSynchronize(o.stream));  // the pinned tables of single_work
   }
   if (m * n > 0) {
-    if (o.out_dev) {
-      HIPCHK(hipMemcpyAsync(R_out, R.data(), (size_t)(m * n) * sizeof(double),
-                            hipMemcpyHostToDevice, o.stream));
-      HIPCHK(hipStreamSynchronize(o.stream));
-    } else {
-      std::memcpy(R_out, R.data(), (size_t)(m * n) * sizeof(double));
-    }
+    double* dst = o.out_dev ? R_out : (double*)d_out;
+    HIPCHK(launch_pairs_finish(m, n, (const int64_t*)d_ia, (const int64_t*)d_ib,
+                               (const int64_t*)d_aid, (const int64_t*)d_bid,
+                               (const int32_t*)d_blk, (const int32_t*)d_col,
+                               (const double*)d_rows, (const double*)d_cg, U, nblk, dst,
+                               o.stream));
+    if (!o.out_dev)
+      HIPCHK(hipMemcpyAsync(R_out, d_out, (size_t)(m * n) * sizeof(double),
+                            hipMemcpyDeviceToHost, o.stream));
+    HIPCHK(hipStreamSynchronize(o.stream));
   }
   if (st) {
     st->n_solved = U;

@@ -2764,6 +2764,48 @@ hipError_t launch_cross_gram(const Coef<double>& c, const double* Xa, const doub
   return hipGetLastError();
 }
 
+// Pair resistances from the solved endpoint blocks, on the device: with
+// x_u the solution for endpoint u (block blk[u], column col[u]),
+//   K(u, v) = x_u[v] + x_v[u] - x_u^T G x_v   (bilinear estimate),
+//   R(a, b) = K(a, a) + K(b, b) - 2 K(a, b),  R = 0 when a and b coincide.
+// rows[bb][w][k] = x of block bb, column k, at endpoint w's node;
+// cg[b1][b2][i][j] = x_{b1,i}^T G x_{b2,j} for b1 <= b2 (the transpose
+// serves b1 > b2).  ia / ib: endpoint index of a_i / b_j (-1: grounded).
+__global__ void k_pairs_finish(int64_t m, int64_t n, const int64_t* __restrict__ ia,
+                               const int64_t* __restrict__ ib, const int64_t* __restrict__ aid,
+                               const int64_t* __restrict__ bid, const int32_t* __restrict__ blk,
+                               const int32_t* __restrict__ col, const double* __restrict__ rows,
+                               const double* __restrict__ cg, int64_t U, int64_t nblk,
+                               double* __restrict__ out) {
+  auto K = [&](int64_t u, int64_t v) -> double {
+    if (u < 0 || v < 0) return 0.0;
+    const int64_t bu = blk[u], cu = col[u], bv = blk[v], cv = col[v];
+    const double xuv = rows[(bu * U + v) * S + cu];
+    const double xvu = rows[(bv * U + u) * S + cv];
+    const double g = bu <= bv ? cg[((bu * nblk + bv) * S + cu) * S + cv]
+                              : cg[((bv * nblk + bu) * S + cv) * S + cu];
+    return xuv + xvu - g;
+  };
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < m * n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = q / n, j = q % n;
+    double r = 0.0;
+    if (aid[i] != bid[j]) r = K(ia[i], ia[i]) + K(ib[j], ib[j]) - 2.0 * K(ia[i], ib[j]);
+    out[q] = r;
+  }
+}
+
+hipError_t launch_pairs_finish(int64_t m, int64_t n, const int64_t* ia, const int64_t* ib,
+                               const int64_t* aid, const int64_t* bid, const int32_t* blk,
+                               const int32_t* col, const double* rows, const double* cg, int64_t U,
+                               int64_t nblk, double* out, hipStream_t st) {
+  if (m * n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((m * n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pairs_finish, dim3((unsigned)blocks), dim3(256), 0, st, m, n, ia, ib, aid,
+                     bid, blk, col, rows, cg, U, nblk, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_rows(const double* X, const int64_t* nodes, int64_t count,
                               double* rows, hipStream_t st) {
   if (count <= 0) return hipSuccess;

@@ -110,8 +110,10 @@ def test_batch_recipe_sizes_sampled():
 
 
 def test_tuning_database_created_and_reused(tmp_path):
-    """A batch with a tuning database times a few work-unit counts for its
-    size class, stores the fastest, and reuses it on the next call (same
+    """A batch with a tuning database times a few (work units, strips) per
+    launch for its size class -- the strip count sets the strip height, the
+    tile shape of the stencil passes -- stores the fastest, and reuses it on
+    the next call (same
     launch layout, so bitwise the same results); results agree with the
     untuned solve to the solver tolerance (only the summation order of the
     Gram reductions differs)."""
@@ -123,7 +125,8 @@ def test_tuning_database_created_and_reused(tmp_path):
     a, _ = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_FP64, rel_tol=1e-10,
                                  tune_db=str(db))
     lines = db.read_text().split()
-    assert len(lines) == 2 and lines[0].startswith("f64-block-r") and int(lines[1]) in (512, 1024, 2048)
+    assert len(lines) == 3 and lines[0].startswith("f64-block-r")
+    assert int(lines[1]) in (512, 1024, 2048) and int(lines[2]) in (256, 512, 1024, 2048)
     b, _ = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_FP64, rel_tol=1e-10,
                                  tune_db=str(db))
     c, _ = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_FP64, rel_tol=1e-10)

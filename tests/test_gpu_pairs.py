@@ -112,3 +112,34 @@ def test_config2_recipe_pairs():
     err = _rel(got, want)
     print("max rel err", err, st, flush=True)
     assert err <= 1e-6
+
+
+def test_thousand_endpoints_recipe_side_256():
+    """1,000 distinct endpoints (500 x 500 pairs, 16 solve blocks and 136
+    block cross terms) on the mixed-precision recipe at side 256
+    (4 x 256 x 256 = 262,144 nodes), float64, against the oracle at 1e-6;
+    output in device memory, pads and coinciding endpoints included."""
+    import time
+
+    import torch
+    reff = _reff()
+    d = gen.config2(side=256, n_tsv=256, sigma=20.0)
+    nodes = gen.sample_free_nodes(d, 1000, 77)
+    a, b = nodes[:500].copy(), nodes[500:].copy()
+    a[0] = gen.pad_ids(d)[0]
+    b[1] = a[2]
+    want = ro.pairs(d, a, b, mode=ro.GROUNDED)
+    _say("1000 endpoints, side 256, fp64, device output")
+    h = reff.reff_build_pdn(d)
+    out = torch.full((500, 500), float("nan"), dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reff.reff_query_pairs(h, a, b, mode=reff.REFF_PAIRS_GROUNDED, R_out=out,
+                          precision=reff.REFF_PREC_FP64, rel_tol=1e-10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    got = out.cpu().numpy()
+    err = _rel(got, want)
+    print(f"max rel err {err:.3e}; {500 * 500 / dt:.3g} pairs/s ({dt:.2f} s)", flush=True)
+    assert got[2, 1] == 0.0
+    assert err <= 1e-6
