@@ -6,7 +6,7 @@ records the generator call that rebuilds its inputs and the oracle's float64
 R_i = (G^-1)_ii (paper Sec. II-B, Eq. 2 with the bumps merged into the
 grounded supply) for a seeded sample of nodes, or for every node.
 
-    python tests/golden/make_golden.py [config2] [config3] [config2_full]
+    python tests/golden/make_golden.py [config2] [config3] [config2_full] [config5_quarter]
 """
 import json
 import os
@@ -87,11 +87,33 @@ def config2_full():
     return dt
 
 
+def config5_quarter():
+    """The large workload's recipe (8 tiers, anisotropic edges, clustered
+    TSVs, pads at pitch 32) on a quarter of its area: 8 tiers of 1024 x 1024
+    (8,388,608 nodes), 64 seeded free nodes, by one sparse Cholesky
+    factorisation and 64 unit solves (oracle/selinv.py).  The full 2048 x
+    2048 stack's factor does not fit this host's memory."""
+    desc = gen.config5(side=1024)
+    nodes = gen.sample_free_nodes(desc, 64, 5005)
+    t0 = time.time()
+    R = selinv.solve_nodes(desc, nodes)
+    dt = time.time() - t0
+    return {
+        "what": ("R_i = (G^-1)_ii, float64 oracle (sparse Cholesky, nested dissection, "
+                 "forward/backward substitution), large-workload recipe at 8 x 1024 x 1024"),
+        "inputs": "gen.config5(seed=1005, side=1024); nodes = gen.sample_free_nodes(desc, 64, 5005)",
+        "oracle_seconds": dt,
+        "nodes": [int(v) for v in nodes],
+        "R": [float(r) for r in R],
+    }
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["config2", "config3", "config2_full"]
+    which = sys.argv[1:] or ["config2", "config3", "config2_full", "config5_quarter"]
     if "config2_full" in which:
         print("wrote config2_fullmap_f32.npy", config2_full())
-    for name, fn in (("config2", config2_sample), ("config3", config3_sample)):
+    for name, fn in (("config2", config2_sample), ("config3", config3_sample),
+                     ("config5_quarter", config5_quarter)):
         if name not in which:
             continue
         out = fn()

@@ -61,3 +61,24 @@ def test_config2_fullmap_sample_fp64(stack):
     err = _max_rel(got, full[ids])
     print("fp64", err, st["iters_total"], flush=True)
     assert err <= 1e-6
+
+
+def test_large_recipe_quarter_area_against_oracle():
+    """The large workload's recipe (8 tiers, anisotropic edges, clustered
+    TSVs, pads at pitch 32) on a quarter of its area, 8 x 1024 x 1024
+    (8,388,608 nodes): 64 seeded nodes against the stored oracle values
+    (tests/golden/config5_quarter_sample.json), mixed precision at the 1e-3
+    bar in the launch configuration of the large bench line."""
+    import json
+    from paper_2607_05818_amd import reff
+    g = json.load(open(os.path.join(HERE, "golden", "config5_quarter_sample.json")))
+    d = gen.config5(side=1024)
+    nodes = np.array(g["nodes"], dtype=np.int64)
+    assert np.array_equal(nodes, gen.sample_free_nodes(d, 64, 5005))
+    want = np.array(g["R"])
+    print("[case] large recipe 8 x 1024 x 1024, 64 nodes, mixed rel_tol 1e-3", flush=True)
+    h = reff.reff_build_pdn(d)
+    got, st = reff.reff_solve_diag(h, nodes, precision=reff.REFF_PREC_MIXED, rel_tol=1e-3)
+    err = _max_rel(got, want)
+    print("mixed", err, st["iters_total"], st["seconds"], flush=True)
+    assert err <= 1e-3
