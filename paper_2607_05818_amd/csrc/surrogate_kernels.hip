@@ -24,63 +24,96 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 32, LDT = BK + 8;
 
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// Eight consecutive bf16 of one tile row, from global memory: one 16-byte
+// load when the run is in range and 16-byte aligned, element loads (zero
+// outside [0, lim)) otherwise.
+__device__ __forceinline__ u4v load8(const uint16_t* __restrict__ base, int64_t first,
+                                     int64_t stride, int idx0, int lim, bool vec_ok) {
+  if (vec_ok && idx0 + 8 <= lim) return *reinterpret_cast<const u4v*>(base + first);
+  uint16_t h[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) h[e] = idx0 + e < lim ? base[first + e * stride] : (uint16_t)0;
+  return u4v{(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16),
+             (uint32_t)h[4] | ((uint32_t)h[5] << 16), (uint32_t)h[6] | ((uint32_t)h[7] << 16)};
+}
+
 // 64 x 64 output tile (blockIdx.x along M, blockIdx.y along N, blockIdx.z
 // the K slice) per 256-thread workgroup; wave w owns the 32 x 32
 // quarter (w / 2, w % 2) as 2 x 2 tiles of v_mfma_f32_16x16x16bf16 (A lane
 // l holds A[l%16][4(l/16) .. +3], B lane l holds B[4(l/16) .. +3][l%16],
-// result row 4(l/16) + r, column l%16 in register r).
+// result row 4(l/16) + r, column l%16 in register r).  Every thread moves
+// eight consecutive bf16 of A and of B per 32-wide K step with one 16-byte
+// global load each; the next step's loads are in flight while the current
+// step's products run, and the LDS tiles are double-buffered, so one
+// barrier per step suffices.  A with unit K stride (im2col rows) lands in
+// LDS as one 16-byte store; the K-strided A (weight gradients) and B are
+// scattered into the transposed [n][k] layout the matrix-core operands read.
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  __shared__ uint16_t sA[BM][LDT];
-  __shared__ uint16_t sB[BN][LDT];  // transposed: sB[n][k]
+  __shared__ __align__(16) uint16_t sA[2][BM][LDT];
+  __shared__ __align__(16) uint16_t sB[2][BN][LDT];  // transposed: sB[n][k]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int kbeg = blockIdx.z * g.kchunk;
   const int kend = min(g.K, kbeg + g.kchunk);
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const bool arow = g.sAk == 1;
+  // this thread's slice of a K step: A row-major: row t/4, k (t%4)*8;
+  // A K-strided: k t/8, rows (t%8)*8; B: k t/8, columns (t%8)*8
+  const int ar = arow ? t >> 2 : (t & 7) * 8, ak = arow ? (t & 3) * 8 : t >> 3;
+  const int bk = t >> 3, bn = (t & 7) * 8;
+  const bool a_vec = arow ? (g.sAm % 8 == 0 && ((uintptr_t)g.A & 15) == 0)
+                          : (g.sAm == 1 && g.sAk % 8 == 0 && ((uintptr_t)g.A & 15) == 0);
+  const bool b_vec = g.sBk % 8 == 0 && ((uintptr_t)g.B & 15) == 0;
+  auto load_step = [&](int k0, u4v& va, u4v& vb) {
+    if (arow) {
+      const int gm = m0 + ar;
+      va = gm < g.M ? load8(g.A, (int64_t)gm * g.sAm + k0 + ak, 1, k0 + ak, kend, a_vec)
+                    : u4v{0u, 0u, 0u, 0u};
+    } else {
+      const int gk = k0 + ak;
+      va = gk < kend ? load8(g.A, (int64_t)(m0 + ar) * g.sAm + (int64_t)gk * g.sAk, g.sAm, m0 + ar,
+                             g.M, a_vec)
+                     : u4v{0u, 0u, 0u, 0u};
+    }
+    const int gk = k0 + bk;
+    vb = gk < kend ? load8(g.B, (int64_t)gk * g.sBk + n0 + bn, 1, n0 + bn, g.N, b_vec)
+                   : u4v{0u, 0u, 0u, 0u};
+  };
+  auto store_step = [&](int buf, const u4v& va, const u4v& vb) {
+    if (arow) {
+      *reinterpret_cast<u4v*>(&sA[buf][ar][ak]) = va;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sA[buf][ar + e][ak] = (uint16_t)(va[e >> 1] >> (16 * (e & 1)));
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sB[buf][bn + e][bk] = (uint16_t)(vb[e >> 1] >> (16 * (e & 1)));
+  };
   f4v acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+  u4v va, vb;
+  if (kbeg < kend) {
+    load_step(kbeg, va, vb);
+    store_step(0, va, vb);
+  }
+  __syncthreads();
+  int buf = 0;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    if (g.sAk == 1) {
-      const int m = t >> 2, kq = (t & 3) * 8;
-      const int gm = m0 + m;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gk = k0 + kq + e;
-        sA[m][kq + e] = (gm < g.M && gk < kend) ? g.A[(int64_t)gm * g.sAm + gk] : (uint16_t)0;
-      }
-    } else {
-      const int k = t >> 3, mq = (t & 7) * 8;
-      const int gk = k0 + k;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gm = m0 + mq + e;
-        sA[mq + e][k] = (gm < g.M && gk < kend) ? g.A[(int64_t)gm * g.sAm + (int64_t)gk * g.sAk]
-                                                : (uint16_t)0;
-      }
-    }
-    {
-      const int k = t >> 3, nq = (t & 7) * 8;
-      const int gk = k0 + k;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gn = n0 + nq + e;
-        sB[nq + e][k] = (gn < g.N && gk < kend) ? g.B[(int64_t)gk * g.sBk + gn] : (uint16_t)0;
-      }
-    }
-    __syncthreads();
+    const bool more = k0 + BK < kend;
+    if (more) load_step(k0 + BK, va, vb);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       s4v af[2], bfr[2];
       const int kc = kk + 4 * (lane >> 4);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const uint16_t* pa = &sA[wm + 16 * i + (lane & 15)][kc];
-        const uint16_t* pb = &sB[wn + 16 * i + (lane & 15)][kc];
-        af[i] = s4v{(short)pa[0], (short)pa[1], (short)pa[2], (short)pa[3]};
-        bfr[i] = s4v{(short)pb[0], (short)pb[1], (short)pb[2], (short)pb[3]};
+        af[i] = *reinterpret_cast<const s4v*>(&sA[buf][wm + 16 * i + (lane & 15)][kc]);
+        bfr[i] = *reinterpret_cast<const s4v*>(&sB[buf][wn + 16 * i + (lane & 15)][kc]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -88,7 +121,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
+    if (more) store_step(buf ^ 1, va, vb);
     __syncthreads();
+    buf ^= 1;
   }
   const bool split = gridDim.z > 1;
 #pragma unroll
