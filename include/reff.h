@@ -96,10 +96,14 @@ typedef struct {
   int32_t max_ir_steps;  /* MIXED only: outer refinement steps; 0 => 3       */
   int32_t timing;        /* 1: time the three block kernels with HIP events on
                             `stream` (fills the kernel_* fields of stats)    */
-  int32_t graphs;        /* 1: replay chunks of iterations as HIP graphs when
-                            `stream` is a created (non-NULL) stream that is
-                            not itself being captured and timing is off
-                            (same results bitwise); 0: plain launches      */
+  int32_t graphs;        /* 0 (automatic) or 1: replay chunks of four
+                            iterations as HIP graphs unless timing is on or
+                            `stream` is itself being captured; on the NULL
+                            stream the solve then runs on a stream of its
+                            own (drained before the call returns).  Blocks
+                            that converge leave device-resident work lists,
+                            so a captured chunk stays valid.  Same results
+                            bitwise as plain launches.  2: plain launches  */
   int32_t progress;      /* 1: write a progress line (iterations, active
                             blocks) to stderr at most every 10 s of a solve */
   int32_t precond_degree;/* block Krylov variant: 1 = Jacobi (D^-1); 2..32 =
@@ -235,6 +239,12 @@ typedef struct {
                               (which sets the strip height, i.e. the tile
                               shape); a class not yet in it is timed on 12
                               candidate pairs first and added             */
+  int32_t calibrate;       /* screened: 0 = every checked node checks the
+                              prediction; 1 = the checked nodes at even
+                              positions of the seeded order fit one log
+                              offset per tier (mean of log(solved /
+                              predicted)), every prediction of the plan is
+                              scaled by it, and the odd positions check it */
 } reff_batch_opts;
 
 /*

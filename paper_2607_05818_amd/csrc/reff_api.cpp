@@ -351,8 +351,9 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
   out.stream = (hipStream_t)o->stream;
   out.out_dev = o->out_on_device == 1;
   if (o->timing != 0 && o->timing != 1) return fail(REFF_ERR_INVALID_ARG, "timing must be 0 or 1");
-  if (o->graphs != 0 && o->graphs != 1) return fail(REFF_ERR_INVALID_ARG, "graphs must be 0 or 1");
-  out.graphs = o->graphs == 1;
+  if (o->graphs < 0 || o->graphs > 2)
+    return fail(REFF_ERR_INVALID_ARG, "graphs must be 0 (automatic), 1 (replay) or 2 (plain)");
+  out.graphs = o->graphs != 2;
   if (o->progress != 0 && o->progress != 1) return fail(REFF_ERR_INVALID_ARG, "progress must be 0 or 1");
   out.progress = o->progress == 1;
   if (o->precond_degree < 0 || o->precond_degree > MAX_CHEB)
@@ -396,7 +397,7 @@ struct BlockResult {
 void reff::Workspace::release() {
   for (DevBuf* b : {&Y, &P, &Q, &R, &D, &X, &part, &W, &small, &state, &tgt, &pos, &plans, &units,
                     &uid, &act, &out, &xs, &rows, &map, &flags, &strips, &sid, &Za, &Zb, &Zc, &Zd,
-                    &TA, &TB})
+                    &TA, &TB, &cnt})
     if (b->p) {
       (void)hipFree(b->p);
       b->p = nullptr;
@@ -558,11 +559,29 @@ std::string tune_key(bool fp32, bool indep, int64_t rows, int nb) {
 // j of block b to res_dev[b.pos[j]].  With xstore, the float64 solution of
 // job i is copied to xstore + xoff[i] (stack n x S).
 reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<StackInfo>& stacks,
-                       const std::vector<BlockJob>& jobs, double* res_dev, const Opts& o,
+                       const std::vector<BlockJob>& jobs, double* res_dev, const Opts& o_in,
                        std::vector<BlockResult>& br, reff_solve_stats* st,
                        double* xstore = nullptr, const std::vector<int64_t>* xoff = nullptr) {
   br.assign(jobs.size(), BlockResult());
   if (jobs.empty()) return REFF_OK;
+  // Iteration chunks are replayed as HIP graphs unless plain launches were
+  // asked for or the kernels are being timed.  On the legacy default stream
+  // (NULL) the solve runs on a stream of its own, which orders itself with
+  // the default stream both ways and is drained before returning.
+  Opts o = o_in;
+  struct OwnStream {
+    hipStream_t s = nullptr;
+    ~OwnStream() {
+      if (s) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+      }
+    }
+  } own;
+  if (o.graphs && !o.timing && o.stream == nullptr) {
+    HIPCHK(hipStreamCreate(&own.s));
+    o.stream = own.s;
+  }
   const bool fp32 = o.mixed;
   const bool with_d = o.mixed || xstore != nullptr;
   const size_t tsz = fp32 ? sizeof(float) : sizeof(double);
@@ -576,7 +595,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
   // Iterations between convergence checks (each costs a host round trip):
   // every iteration once the polynomial preconditioner makes iterations
   // costly, every fourth with Jacobi.
-  const int poll = (!o.indep && o.cheb > 1) ? 1 : 4;
+  int poll = (!o.indep && o.cheb > 1) ? 1 : 4;
 
   struct EventPool {
     std::vector<hipEvent_t> ev;
@@ -596,11 +615,11 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
   // on a created stream that is not itself being captured, without timing.
   struct GraphCache {
     hipGraphExec_t exec = nullptr;
-    int k = -1, n_act = -1, n_units = -1, n_strips = -1;
+    int k = -1;
     void reset() {
       if (exec) (void)hipGraphExecDestroy(exec);
       exec = nullptr;
-      k = n_act = n_units = n_strips = -1;
+      k = -1;
     }
     ~GraphCache() { reset(); }
   } gc;
@@ -610,6 +629,10 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     if (hipStreamIsCapturing(o.stream, &cst) != hipSuccess || cst != hipStreamCaptureStatusNone)
       use_graph = false;
   }
+  // A replayed chunk stays valid while blocks converge (they leave the
+  // device-resident active lists), so chunks can span several iterations
+  // with one host round trip each.
+  if (use_graph) poll = 4;
   size_t j0 = 0;
   while (j0 < jobs.size()) {
     // ---- group of jobs within the row budget
@@ -663,7 +686,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     PlanDesc* h_plans = nullptr;
     Unit* h_units = nullptr;
     int64_t *h_tgt = nullptr, *h_pos = nullptr;
-    int32_t *h_uid = nullptr, *h_act = nullptr, *h_sid = nullptr;
+    int32_t *h_uid = nullptr, *h_act = nullptr, *h_sid = nullptr, *h_cnt = nullptr;
     Strip* h_strips = nullptr;
     SolveBuffers b;
     for (size_t attempt = 0; attempt <= trials.size(); ++attempt) {
@@ -706,10 +729,11 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     if ((rs = ensure(ws.uid, (size_t)nu * sizeof(int32_t))) != REFF_OK) return rs;
     if ((rs = ensure(ws.act, (size_t)nb * sizeof(int32_t))) != REFF_OK) return rs;
     if ((rs = ensure(ws.flags, (size_t)nb * 2 * sizeof(int32_t))) != REFF_OK) return rs;
+    if ((rs = ensure(ws.cnt, 4 * sizeof(int32_t))) != REFF_OK) return rs;
     // ---- tables (one pinned staging area, uploaded asynchronously)
     const size_t tab_bytes = nb * sizeof(PlanDesc) + nu * sizeof(Unit) + nb * S * 16 +
                              (nu + nb) * sizeof(int32_t) * 2 + ns * sizeof(Strip) +
-                             ns * sizeof(int32_t) + 256;
+                             ns * sizeof(int32_t) + 256 + 64;
     if ((rs = pin_tab.ensure(tab_bytes)) != REFF_OK) return rs;
     if ((rs = pin_flags.ensure((size_t)nb * 2 * sizeof(int32_t))) != REFF_OK) return rs;
     char* hp = (char*)pin_tab.p;
@@ -721,6 +745,11 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     h_act = h_uid + nu;
     h_strips = (Strip*)(((uintptr_t)(h_act + nb) + 15) & ~(uintptr_t)15);
     h_sid = (int32_t*)(h_strips + ns);
+    h_cnt = (int32_t*)(((uintptr_t)(h_sid + ns) + 15) & ~(uintptr_t)15);
+    h_cnt[0] = nu;
+    h_cnt[1] = ns;
+    h_cnt[2] = nb;
+    h_cnt[3] = 0;
     std::memcpy(h_plans, plans.data(), nb * sizeof(PlanDesc));
     std::memcpy(h_units, units.data(), nu * sizeof(Unit));
     for (int i = 0; i < nb; ++i) {
@@ -744,6 +773,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     HIPCHK(hipMemcpyAsync(ws.pos.p, h_pos, (size_t)nb * S * sizeof(int64_t), hipMemcpyHostToDevice, o.stream));
     HIPCHK(hipMemcpyAsync(ws.uid.p, h_uid, nu * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
     HIPCHK(hipMemcpyAsync(ws.act.p, h_act, nb * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
+    HIPCHK(hipMemcpyAsync(ws.cnt.p, h_cnt, 4 * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
 
     b = SolveBuffers{};
     b.Y = ws.Y.p;
@@ -767,6 +797,11 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     b.work.strips = (const Strip*)ws.strips.p;
     b.work.sid = (const int32_t*)ws.sid.p;
     b.act = (const int32_t*)ws.act.p;
+    b.act_w = (int32_t*)ws.act.p;
+    b.uid_w = (int32_t*)ws.uid.p;
+    b.sid_w = (int32_t*)ws.sid.p;
+    b.cnt = (int32_t*)ws.cnt.p;
+    b.work.cnt = b.cnt;
     b.n_act = nb;
     b.n_units = nu;
     b.n_strips = ns;
@@ -827,7 +862,8 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     }  // attempts
 
     std::vector<char> done((size_t)nb, 0);     // converged in the current step
-    std::vector<int32_t> iters((size_t)nb, 0);
+    std::vector<int32_t> iters((size_t)nb, 0);   // block iterations over all inner solves
+    std::vector<int32_t> cur_it((size_t)nb, 0);  // of the current inner solve (device count)
     std::vector<int32_t> irs((size_t)nb, 0);
     std::vector<int> active(nb);
     for (int i = 0; i < nb; ++i) active[(size_t)i] = i;
@@ -844,8 +880,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
         const int k = std::min(poll, o.max_iters - it);
         const int64_t act_rows = rows_of(active);
         if (use_graph) {
-          if (!gc.exec || gc.k != k || gc.n_act != b.n_act || gc.n_units != b.n_units ||
-              gc.n_strips != b.n_strips) {
+          if (!gc.exec || gc.k != k) {
             gc.reset();
             hipGraph_t graph = nullptr;
             HIPCHK(hipStreamBeginCapture(o.stream, hipStreamCaptureModeThreadLocal));
@@ -866,9 +901,6 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
             if (ie != hipSuccess) gc.exec = nullptr;
             HIPCHK(ie);
             gc.k = k;
-            gc.n_act = b.n_act;
-            gc.n_units = b.n_units;
-            gc.n_strips = b.n_strips;
           }
           HIPCHK(hipGraphLaunch(gc.exec, o.stream));
         } else {
@@ -903,42 +935,24 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
               st->kernel_rows[kk] += act_rows;
             }
         }
-        // flags of every block (gathered into a small device array)
+        // flags of every block (gathered into a small device array); the
+        // device has already dropped converged blocks from its active lists
+        // (k_compact at the end of every iteration), this is bookkeeping
         const int32_t* fl = (const int32_t*)pin_flags.p;
         std::vector<int> still;
         for (int bi : active) {
-          iters[(size_t)bi] += k;
+          cur_it[(size_t)bi] = fl[(size_t)bi * 2];
           if (fl[(size_t)bi * 2 + 1]) {
             done[(size_t)bi] = 1;
           } else {
             still.push_back(bi);
           }
         }
-        if (still.size() != active.size() && !still.empty()) {
-          // Compact: later launches cover only the unconverged blocks.
-          active = still;
-          int na = 0, nuu = 0, nss = 0;
-          for (int bi : active) {
-            h_act[na++] = bi;
-            for (int u = plans[(size_t)bi].unit_begin; u < plans[(size_t)bi].unit_end; ++u)
-              h_uid[nuu++] = u;
-            if (ns > 0)
-              for (int u = plans[(size_t)bi].strip_begin; u < plans[(size_t)bi].strip_end; ++u)
-                h_sid[nss++] = u;
-          }
-          HIPCHK(hipMemcpyAsync(ws.uid.p, h_uid, nuu * sizeof(int32_t), hipMemcpyHostToDevice,
-                                o.stream));
-          HIPCHK(hipMemcpyAsync(ws.act.p, h_act, na * sizeof(int32_t), hipMemcpyHostToDevice,
-                                o.stream));
-          if (ns > 0)
-            HIPCHK(hipMemcpyAsync(ws.sid.p, h_sid, nss * sizeof(int32_t), hipMemcpyHostToDevice,
-                                  o.stream));
-          b.n_act = na;
-          b.n_units = nuu;
-          b.n_strips = nss;
-        } else {
-          active = still;
-        }
+        active = still;
+      }
+      for (int i = 0; i < nb; ++i) {
+        iters[(size_t)i] += cur_it[(size_t)i];
+        cur_it[(size_t)i] = 0;
       }
       ++ir;
       for (int i = 0; i < nb; ++i) irs[(size_t)i] = ir;
@@ -950,9 +964,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
       HIPCHK(hipMemcpyAsync(ws.act.p, h_act, nb * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
       if (ns > 0)
         HIPCHK(hipMemcpyAsync(ws.sid.p, h_sid, ns * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
-      b.n_act = nb;
-      b.n_units = nu;
-      b.n_strips = ns;
+      HIPCHK(hipMemcpyAsync(ws.cnt.p, h_cnt, 4 * sizeof(int32_t), hipMemcpyHostToDevice, o.stream));
       if (!o.mixed) break;
       HIPCHK(launch_mixed_residual(c64, c32, b, res_dev, o.stream));
       // One float32 solve carried to the tolerance plus the float64
@@ -1053,7 +1065,8 @@ reff_status single_work(Workspace& ws, const StackInfo& sk, SolveBuffers& b, hip
   if ((rs = ensure(ws.units, (size_t)nu * sizeof(Unit))) != REFF_OK) return rs;
   if ((rs = ensure(ws.uid, (size_t)nu * sizeof(int32_t))) != REFF_OK) return rs;
   if ((rs = ensure(ws.act, 2 * sizeof(int32_t))) != REFF_OK) return rs;
-  if ((rs = pin.ensure(sizeof(PlanDesc) + nu * (sizeof(Unit) + sizeof(int32_t)) + 16)) != REFF_OK)
+  if ((rs = ensure(ws.cnt, 4 * sizeof(int32_t))) != REFF_OK) return rs;
+  if ((rs = pin.ensure(sizeof(PlanDesc) + nu * (sizeof(Unit) + sizeof(int32_t)) + 64)) != REFF_OK)
     return rs;
   char* hp = (char*)pin.p;
   std::memcpy(hp, plans.data(), sizeof(PlanDesc));
@@ -1066,6 +1079,12 @@ reff_status single_work(Workspace& ws, const StackInfo& sk, SolveBuffers& b, hip
                         stream));
   HIPCHK(hipMemcpyAsync(ws.uid.p, uid, nu * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   HIPCHK(hipMemcpyAsync(ws.act.p, uid + nu, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  int32_t* cnt = (int32_t*)(((uintptr_t)(uid + nu + 1) + 15) & ~(uintptr_t)15);
+  cnt[0] = nu;
+  cnt[1] = 0;
+  cnt[2] = 1;
+  cnt[3] = 0;
+  HIPCHK(hipMemcpyAsync(ws.cnt.p, cnt, 4 * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   b = SolveBuffers{};
   b.part = (double*)ws.part.p;
   b.W = (double*)ws.W.p;
@@ -1073,6 +1092,8 @@ reff_status single_work(Workspace& ws, const StackInfo& sk, SolveBuffers& b, hip
   b.work.units = (const Unit*)ws.units.p;
   b.work.uid = (const int32_t*)ws.uid.p;
   b.act = (const int32_t*)ws.act.p;
+  b.cnt = (int32_t*)ws.cnt.p;
+  b.work.cnt = b.cnt;
   b.n_act = 1;
   b.n_units = nu;
   b.rows = sk.n;
@@ -1607,9 +1628,10 @@ static reff_status screen_plans(reff_surrogate sg, const reff_pdn_desc* plans, i
                                 const std::vector<std::vector<int64_t>>& cols,
                                 const std::vector<std::vector<int64_t>>& maps,
                                 double* const* R_out, const Opts& o, double spot_frac,
-                                double fb_err, reff_solve_stats* per_plan,
+                                double fb_err, int calibrate, reff_solve_stats* per_plan,
                                 std::chrono::steady_clock::time_point t0) {
   const int64_t per = stacks[0].n;  // every plan has the model's geometry
+  const int64_t plane = stacks[0].plane;
   reff_status rs = ensure(ws.xs, (size_t)n_plans * per * sizeof(double));
   if (rs != REFF_OK) return rs;
   rs = reffsg::predict_device(sg, plans, n_plans, (double*)ws.xs.p, o.stream);
@@ -1664,12 +1686,40 @@ static reff_status screen_plans(reff_surrogate sg, const reff_pdn_desc* plans, i
   std::vector<size_t> fjob0((size_t)n_plans + 1);
   std::vector<int64_t> fpos0((size_t)n_plans, -1);
   int64_t fpos = 0;
+  const int nt = (int)(per / plane);
   for (int32_t i = 0; i < n_plans; ++i) {
     const auto& si = spot_idx[(size_t)i];
+    const auto& c = cols[(size_t)i];
+    // With calibration, the checked nodes at even positions of the seeded
+    // order fit one log-offset per tier (the mean of log(solved / predicted)
+    // there; the overall mean on a tier with none), the prediction of every
+    // requested node is scaled by it, and the odd positions check the
+    // scaled prediction.  Without, every checked node checks.
+    const bool cal = calibrate && si.size() >= 2;
+    if (cal) {
+      std::vector<double> sum((size_t)nt, 0.0);
+      std::vector<int> num((size_t)nt, 0);
+      double all = 0.0;
+      int nall = 0;
+      for (size_t j = 0; j < si.size(); j += 2) {
+        const double r = spot[(size_t)(spos0[(size_t)i] + (int64_t)j)];
+        const double v = values[(size_t)i][(size_t)si[j]];
+        if (!(r > 0.0) || !(v > 0.0)) continue;
+        const int t = (int)(c[(size_t)si[j]] / plane);
+        const double d = std::log(r / v);
+        sum[(size_t)t] += d, num[(size_t)t] += 1;
+        all += d, nall += 1;
+      }
+      std::vector<double> scale((size_t)nt, 1.0);
+      for (int t = 0; t < nt; ++t)
+        scale[(size_t)t] = std::exp(num[(size_t)t] ? sum[(size_t)t] / num[(size_t)t]
+                                                   : (nall ? all / nall : 0.0));
+      for (size_t j = 0; j < c.size(); ++j) values[(size_t)i][j] *= scale[(size_t)(c[j] / plane)];
+    }
     for (size_t j = 0; j < si.size(); ++j) {
       const double r = spot[(size_t)(spos0[(size_t)i] + (int64_t)j)];
       double& v = values[(size_t)i][(size_t)si[j]];
-      err[(size_t)i] = std::max(err[(size_t)i], std::fabs(v - r) / r);
+      if (!cal || (j & 1)) err[(size_t)i] = std::max(err[(size_t)i], std::fabs(v - r) / r);
       v = r;
     }
     fallback[(size_t)i] = !(err[(size_t)i] <= fb_err);
@@ -1742,7 +1792,11 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
   o.tune_db = opts ? opts->tune_db : nullptr;
   reff_surrogate sg = opts ? (reff_surrogate)opts->surrogate : nullptr;
   double spot_frac = 0.01, fb_err = 1e-2;
+  int calibrate = 0;
   if (sg) {
+    if (opts->calibrate != 0 && opts->calibrate != 1)
+      return fail(REFF_ERR_INVALID_ARG, "calibrate must be 0 or 1");
+    calibrate = opts->calibrate;
     if (opts->spot_frac != 0.0) spot_frac = opts->spot_frac;
     if (opts->fallback_rel_err != 0.0) fb_err = opts->fallback_rel_err;
     if (!(spot_frac > 0.0 && spot_frac <= 1.0))
@@ -1827,7 +1881,7 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
   } rel{ws};
   if (sg)
     return screen_plans(sg, plans, n_plans, ws, cs, stacks, cols, maps, R_out, o, spot_frac,
-                        fb_err, per_plan, t0);
+                        fb_err, calibrate, per_plan, t0);
   reff_status rs = ensure(ws.out, (size_t)(pos0 + 1) * sizeof(double));
   if (rs != REFF_OK) return rs;
   std::vector<BlockResult> br;

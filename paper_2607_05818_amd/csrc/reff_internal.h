@@ -94,15 +94,19 @@ struct Strip {
   int32_t pad_;
 };
 
-// Argument bundle of the vector kernels: gridDim.x workgroups process the
-// units uid[0 .. gridDim.x) (the active ones); the strip stencil kernel
-// processes strips sid[0 .. gridDim.x).
+// Argument bundle of the vector kernels.  The active work lives on the
+// device: cnt[0] units uid[0 .. cnt[0]), cnt[1] strips sid[0 .. cnt[1]) and
+// cnt[2] solve blocks (act[]), rewritten by k_compact at the end of every
+// iteration as blocks converge.  Launch grids cover the whole group; a
+// workgroup whose logical item is not active returns at once, so a captured
+// sequence of launches stays valid while the active set shrinks.
 struct Work {
   const PlanDesc* plans;
   const Unit* units;
   const int32_t* uid;
   const Strip* strips;
   const int32_t* sid;
+  const int32_t* cnt;
 };
 
 // Device-resident convergence state of one block solve.
@@ -126,7 +130,7 @@ struct DevBuf {
 // Device work arrays of the block solver (grown on demand, reused).
 struct Workspace {
   DevBuf Y, P, Q, R, D, X, part, W, small, state, tgt, pos, plans, units, uid, act, out, xs,
-      rows, map, flags, strips, sid, Za, Zb, Zc, Zd, TA, TB;
+      rows, map, flags, strips, sid, Za, Zb, Zc, Zd, TA, TB, cnt;
   void release();
 };
 
@@ -191,9 +195,13 @@ struct SolveBuffers {
   int64_t* pos;  // nb x S output positions (-1 = none)
   Work work;     // device plan / unit tables
   const int32_t* act;  // active solve blocks (small kernels, reductions)
-  int n_act;
-  int n_units;   // active units (grid of the vector kernels)
-  int n_strips;  // active strips (grid of the strip stencil kernel; 0 = not used)
+  int32_t* act_w;      // the same lists, writable (k_compact)
+  int32_t* uid_w;
+  int32_t* sid_w;
+  int32_t* cnt;        // device active counts (= work.cnt)
+  int n_act;     // solve blocks of the group (grid of the small kernels)
+  int n_units;   // units of the group (grid of the vector kernels)
+  int n_strips;  // strips of the group (grid of the strip kernels; 0 = not used)
   int64_t rows;  // vector rows covered by the active units' blocks
   // Chebyshev polynomial preconditioner of degree cheb_k (block variant;
   // 1 = Jacobi): Z = q(D^-1 G) D^-1 R by cheb_k - 1 strip steps from
@@ -223,6 +231,9 @@ hipError_t launch_init_blocks(bool fp32, bool indep, const void* coef, const Sol
 hipError_t launch_iteration(bool fp32, bool indep, bool with_d, const void* coef,
                             const SolveBuffers& b, double tol, hipStream_t st, hipEvent_t* ev);
 hipError_t launch_zero_x(double* X, int64_t cnt, hipStream_t st);
+// Rebuild the active lists and counts of a group from its blocks'
+// convergence flags (blocks 0 .. nb-1, all of them, in order).
+hipError_t launch_compact(const SolveBuffers& b, int nb, hipStream_t st);
 hipError_t launch_mixed_residual(const Coef<double>& c, const Coef<float>& cf,
                                  const SolveBuffers& b, double* out, hipStream_t st);
 hipError_t launch_restart(const Coef<float>& cf, const SolveBuffers& b, bool indep,

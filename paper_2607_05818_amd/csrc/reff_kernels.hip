@@ -44,6 +44,20 @@ __device__ __forceinline__ int logical_block(int b, int nb) {
   return (b & 7) * per + (b >> 3);
 }
 
+// This workgroup's logical item among the n active ones of a kind (0 units,
+// 1 strips; n read from device memory), or -1 when it has none.  With a grid
+// that is a multiple of 8 the active items are spread evenly over the XCDs,
+// each XCD taking a contiguous range.
+__device__ __forceinline__ int active_item(const Work& wk, int kind) {
+  const int n = wk.cnt[kind];
+  const int b = (int)blockIdx.x;
+  if ((gridDim.x & 7) != 0) return b < n ? b : -1;
+  const int np = (n + 7) & ~7;
+  if (b >= np) return -1;
+  const int l = logical_block(b, np);
+  return l < n ? l : -1;
+}
+
 // The unit, its block and the block's S x S matrices of this workgroup.
 struct UnitCtx {
   int64_t begin, end;  // vector rows
@@ -51,8 +65,7 @@ struct UnitCtx {
   int plan;
 };
 
-__device__ __forceinline__ UnitCtx unit_ctx(const Work& wk) {
-  const int lu = logical_block(blockIdx.x, gridDim.x);
+__device__ __forceinline__ UnitCtx unit_ctx(const Work& wk, int lu) {
   const Unit u = wk.units[wk.uid[lu]];
   UnitCtx c;
   c.begin = u.begin;
@@ -336,8 +349,10 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram(Coef<T> c, Work wk,
   // cb needs cb + 1 k-blocks: the two waves sharing a SIMD (w, w + 4) take
   // cb and 3 - cb, five k-blocks per SIMD.
   const int nb = w >> 2, cb = nb == 0 ? (w & 3) : 3 - (w & 3);
-  const UnitCtx u = unit_ctx(wk);
-  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
+  const int lu = active_item(wk, 0);
+  if (lu < 0) return;
+  const UnitCtx u = unit_ctx(wk, lu);
+  const int uidx = wk.uid[lu];
   T breg[DIAG ? 1 : S / 4];
   if (!DIAG) load_bcol<T>(Tm + (size_t)u.plan * S * S, cb, lane, breg);
   double a1[2][4], a2[2][4];
@@ -458,7 +473,9 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram_strip(Coef<T> c, Work wk
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   // Product tile (nb, cb): T is upper triangular (see k_stencil_gram).
   const int nb = w >> 2, cb = nb == 0 ? (w & 3) : 3 - (w & 3);
-  const int sidx = wk.sid[logical_block(blockIdx.x, gridDim.x)];
+  const int ls = active_item(wk, 1);
+  if (ls < 0) return;
+  const int sidx = wk.sid[ls];
   const Strip st = wk.strips[sidx];
   const PlanDesc pd = wk.plans[st.plan];
   const int64_t nx = pd.nx;
@@ -654,8 +671,10 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int nb = w >> 2, cb = w & 3;
-  const UnitCtx u = unit_ctx(wk);
-  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
+  const int lu = active_item(wk, 0);
+  if (lu < 0) return;
+  const UnitCtx u = unit_ctx(wk, lu);
+  const int uidx = wk.uid[lu];
   const T* al = alpha + (size_t)u.plan * S * S;
   T breg[DIAG ? 1 : S / 4];
   if (DIAG)
@@ -781,8 +800,10 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int nb = w >> 2, cb = w & 3;
-  const UnitCtx u = unit_ctx(wk);
-  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
+  const int lu = active_item(wk, 0);
+  if (lu < 0) return;
+  const UnitCtx u = unit_ctx(wk, lu);
+  const int uidx = wk.uid[lu];
   const T* de = delta + (size_t)u.plan * S * S;
   T breg[DIAG ? 1 : S / 4];
   if (DIAG)
@@ -877,8 +898,10 @@ __global__ __launch_bounds__(WG, 4) void k_gram_ab(Coef<T> c, Work wk, const T* 
   __shared__ __align__(16) T sB[CH][LDW];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const UnitCtx u = unit_ctx(wk);
-  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
+  const int lu = active_item(wk, 0);
+  if (lu < 0) return;
+  const UnitCtx u = unit_ctx(wk, lu);
+  const int uidx = wk.uid[lu];
   const int64_t cofs = u.pd.cbase - u.pd.vbase;
   double acc[2][4];
   zero_acc(acc);
@@ -1004,7 +1027,9 @@ __global__ __launch_bounds__(WG, 4) void k_cheb_strip(Coef<T> c, Work wk, const 
   __shared__ int cslot[2][CH];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const int sidx = wk.sid[logical_block(blockIdx.x, gridDim.x)];
+  const int ls = active_item(wk, 1);
+  if (ls < 0) return;
+  const int sidx = wk.sid[ls];
   const Strip st = wk.strips[sidx];
   const PlanDesc pd = wk.plans[st.plan];
   const int64_t nx = pd.nx;
@@ -1192,7 +1217,9 @@ __global__ __launch_bounds__(WG, sizeof(T) == 4 ? 4 : 2) void k_cheb2_strip(Coef
   __shared__ int cslot[3][NC];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const int sidx = wk.sid[logical_block(blockIdx.x, gridDim.x)];
+  const int ls = active_item(wk, 1);
+  if (ls < 0) return;
+  const int sidx = wk.sid[ls];
   const Strip st = wk.strips[sidx];
   const PlanDesc pd = wk.plans[st.plan];
   const int nx = pd.nx;
@@ -1447,6 +1474,7 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv_a(
   constexpr bool FIRST = !HAS_PREV;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if ((int)blockIdx.y >= wk.cnt[2]) return;
   const PlanDesc pd = wk.plans[act[blockIdx.y]];
   const int item = blockIdx.x * TSV_WAVES + w;
   if (item >= 5 * (pd.slot_end - pd.slot_begin)) return;  // the whole wave
@@ -1473,6 +1501,7 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv_b(
   constexpr bool FIRST = !HAS_PREV;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if ((int)blockIdx.y >= wk.cnt[2]) return;
   const PlanDesc pd = wk.plans[act[blockIdx.y]];
   const int qi = blockIdx.x * TSV_WAVES + w;
   if (qi >= pd.slot_end - pd.slot_begin) return;  // the whole wave
@@ -1551,7 +1580,9 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
   __shared__ f4v cfb[16][N1];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const int sidx = wk.sid[logical_block(blockIdx.x, gridDim.x)];
+  const int ls = active_item(wk, 1);
+  if (ls < 0) return;
+  const int sidx = wk.sid[ls];
   const Strip st = wk.strips[sidx];
   const PlanDesc pd = wk.plans[st.plan];
   const int nx = pd.nx;
@@ -1902,8 +1933,10 @@ __global__ __launch_bounds__(WG, 4) void k_cross_gram(Coef<T> c, Work wk,
   __shared__ __align__(16) T sB[CH][LDW];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const UnitCtx u = unit_ctx(wk);
-  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
+  const int lu = active_item(wk, 0);
+  if (lu < 0) return;
+  const UnitCtx u = unit_ctx(wk, lu);
+  const int uidx = wk.uid[lu];
   double acc[2][4];
   zero_acc(acc);
   for (int64_t base = u.begin; base < u.end; base += CH) {
@@ -1930,8 +1963,10 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
                                                 double* __restrict__ W,
                                                 const PlanDesc* __restrict__ plans,
                                                 const int32_t* __restrict__ act, int m0,
-                                                int nmat, int len, int strips) {
+                                                int nmat, int len, int strips,
+                                                const int32_t* __restrict__ cnt) {
   __shared__ double red[4][64];
+  if ((int)blockIdx.y >= cnt[2]) return;
   const int p = act[blockIdx.y];
   const int el = threadIdx.x & 63;
   const int grp = threadIdx.x >> 6;
@@ -2152,10 +2187,12 @@ __global__ __launch_bounds__(SM_THREADS) void k_small1(const double* __restrict_
                                                        double* __restrict__ winv_all,
                                                        T* __restrict__ alpha_all,
                                                        BlockState* __restrict__ st_all,
-                                                       double tol, double eps, int diag) {
+                                                       double tol, double eps, int diag,
+                                                       const int32_t* __restrict__ cnt) {
   __shared__ Mat Wi, B, PT;
   __shared__ double sc[S], dpsi[S];
   __shared__ int drop[S];
+  if ((int)blockIdx.x >= cnt[2]) return;
   const int p = act[blockIdx.x];
   const int64_t vbase = plans[p].vbase;
   const double* W1 = Wall + (size_t)p * NGRAM * S * S;
@@ -2238,8 +2275,9 @@ __global__ __launch_bounds__(SM_THREADS) void k_small2(const double* __restrict_
                                                        const double* __restrict__ winv_all,
                                                        T* __restrict__ delta_all,
                                                        const BlockState* __restrict__ st_all,
-                                                       int diag) {
+                                                       int diag, const int32_t* __restrict__ cnt) {
   __shared__ Mat A, B;
+  if ((int)blockIdx.x >= cnt[2]) return;
   const int p = act[blockIdx.x];
   const double* W3 = Wall + ((size_t)p * NGRAM + 2) * S * S;
   const double* winv = winv_all + (size_t)p * S * S;
@@ -2274,10 +2312,12 @@ __global__ __launch_bounds__(SM_THREADS) void k_small3(const double* __restrict_
                                                        const int32_t* __restrict__ act,
                                                        T* __restrict__ T_all,
                                                        BlockState* __restrict__ st_all,
-                                                       double eps, double tau) {
+                                                       double eps, double tau,
+                                                       const int32_t* __restrict__ cnt) {
   __shared__ Mat tmp, Tl;
   __shared__ double sc[S], floor_[S];
   __shared__ int drop[S];
+  if ((int)blockIdx.x >= cnt[2]) return;
   const int p = act[blockIdx.x];
   const double* W4 = Wall + ((size_t)p * NGRAM + 3) * S * S;
   T* Tg = T_all + (size_t)p * S * S;
@@ -2380,8 +2420,10 @@ __global__ __launch_bounds__(WG) void k_resid(Coef<double> c, Coef<float> cf, Wo
                                               double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const UnitCtx u = unit_ctx(wk);
-  const int uidx = wk.uid[logical_block(blockIdx.x, gridDim.x)];
+  const int lu = active_item(wk, 0);
+  if (lu < 0) return;
+  const UnitCtx u = unit_ctx(wk, lu);
+  const int uidx = wk.uid[lu];
   const int64_t tl = tgt_all[(size_t)u.plan * S + lane];
   const int64_t my_t = tl >= 0 ? u.pd.vbase + tl : -1;
   const int64_t cofs = u.pd.cbase - u.pd.vbase;
@@ -2473,11 +2515,68 @@ __global__ void k_scale_units(Coef<T> c, Work wk, const T* __restrict__ R, T* __
   }
 }
 
+// ---------------------------------------------------------------- compaction
+// Active lists of a group from its blocks' convergence flags: blocks
+// 0 .. nb-1 in order, a block staying active until every column met the
+// tolerance (all_conv); its units and strips follow it.  One workgroup;
+// 256 blocks per round, placed by block-wide exclusive scans of the active
+// flag and of the unit and strip counts.
+__global__ __launch_bounds__(256) void k_compact(const PlanDesc* __restrict__ plans, int nb,
+                                                 const BlockState* __restrict__ st,
+                                                 int32_t* __restrict__ act,
+                                                 int32_t* __restrict__ uid,
+                                                 int32_t* __restrict__ sid,
+                                                 int32_t* __restrict__ cnt) {
+  __shared__ int sa[256], su[256], ss[256];
+  const int t = threadIdx.x;
+  int ta = 0, tu = 0, ts = 0;  // totals of the rounds before
+  for (int base = 0; base < nb; base += 256) {
+    const int p = base + t;
+    const bool on = p < nb && st[p].all_conv == 0;
+    const int nu = on ? plans[p].unit_end - plans[p].unit_begin : 0;
+    const int ns = on ? plans[p].strip_end - plans[p].strip_begin : 0;
+    sa[t] = on ? 1 : 0;
+    su[t] = nu;
+    ss[t] = ns;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {  // inclusive scans
+      const int a = t >= d ? sa[t - d] : 0, u = t >= d ? su[t - d] : 0,
+                v = t >= d ? ss[t - d] : 0;
+      __syncthreads();
+      sa[t] += a;
+      su[t] += u;
+      ss[t] += v;
+      __syncthreads();
+    }
+    if (on) {
+      act[ta + sa[t] - 1] = p;
+      const int u0 = tu + su[t] - nu, s0 = ts + ss[t] - ns;
+      for (int i = 0; i < nu; ++i) uid[u0 + i] = plans[p].unit_begin + i;
+      for (int i = 0; i < ns; ++i) sid[s0 + i] = plans[p].strip_begin + i;
+    }
+    ta += sa[255];
+    tu += su[255];
+    ts += ss[255];
+    __syncthreads();
+  }
+  if (t == 0) {
+    cnt[0] = tu;
+    cnt[1] = ts;
+    cnt[2] = ta;
+  }
+}
+
+hipError_t launch_compact(const SolveBuffers& b, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(256), 0, st, b.work.plans, nb, b.state, b.act_w,
+                     b.uid_w, b.sid_w, b.cnt);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launchers
 static void reduce(const SolveBuffers& b, int m0, int nmat, int len, hipStream_t st,
                    bool strips = false) {
   hipLaunchKernelGGL(k_reduce, dim3((nmat * len + 63) / 64, b.n_act), dim3(256), 0, st, b.part,
-                     b.W, b.work.plans, b.act, m0, nmat, len, strips ? 1 : 0);
+                     b.W, b.work.plans, b.act, m0, nmat, len, strips ? 1 : 0, b.work.cnt);
 }
 
 // True when the first Chebyshev pass of an application is a three-step pass
@@ -2598,7 +2697,7 @@ static void precond_start(const Coef<T>& c, const SolveBuffers& b, hipStream_t s
                      (const T*)b.Y, (const T*)b.Y, b.part, 3);
   reduce(b, 3, 1, S * S, st);
   hipLaunchKernelGGL((k_small3<T>), dim3(b.n_act), dim3(SM_THREADS), 0, st, b.W, b.act,
-                     (T*)b.Tm, b.state, eps4, tau);
+                     (T*)b.Tm, b.state, eps4, tau, b.work.cnt);
 }
 
 template <typename T>
@@ -2635,7 +2734,7 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
   if (ev) hipEventRecord(ev[1], st);
   reduce(b, 0, 2, len, st, strips);
   hipLaunchKernelGGL((k_small1<T>), gs, bs, 0, st, b.W, (const T*)P, wk.plans, b.act, b.tgt,
-                     b.winv, (T*)b.alpha, b.state, tol, eps1, di);
+                     b.winv, (T*)b.alpha, b.state, tol, eps1, di, wk.cnt);
   if (ev) hipEventRecord(ev[2], st);
   const T* al = (const T*)b.alpha;
   if (indep) {
@@ -2673,7 +2772,8 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
     hipLaunchKernelGGL((k_gram_ab<T, false>), g, blk, 0, st, c, wk, (const T*)Q, Z, b.part, 2);
   if (ev) hipEventRecord(ev[9], st);
   reduce(b, 2, 1, len, st);
-  hipLaunchKernelGGL((k_small2<T>), gs, bs, 0, st, b.W, b.act, b.winv, (T*)b.delta, b.state, di);
+  hipLaunchKernelGGL((k_small2<T>), gs, bs, 0, st, b.W, b.act, b.winv, (T*)b.delta, b.state, di,
+                     wk.cnt);
   if (ev) hipEventRecord(ev[4], st);
   const T* de = (const T*)b.delta;
   if (indep) {
@@ -2686,8 +2786,12 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
       hipLaunchKernelGGL((k_update_y<T, false>), g, blk, 0, st, c, wk, de, R, P, Y, b.part);
     if (ev) hipEventRecord(ev[5], st);
     reduce(b, 3, 1, len, st);
-    hipLaunchKernelGGL((k_small3<T>), gs, bs, 0, st, b.W, b.act, (T*)b.Tm, b.state, eps4, tau);
+    hipLaunchKernelGGL((k_small3<T>), gs, bs, 0, st, b.W, b.act, (T*)b.Tm, b.state, eps4, tau,
+                       wk.cnt);
   }
+  // blocks that converged in this iteration leave the active lists
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(256), 0, st, wk.plans, b.n_act, b.state, b.act_w,
+                     b.uid_w, b.sid_w, b.cnt);
   return hipGetLastError();
 }
 
@@ -2746,7 +2850,7 @@ hipError_t launch_restart(const Coef<float>& cf, const SolveBuffers& b, bool ind
                        (const float*)b.Y, (const float*)b.Y, b.part, 3);
     reduce(b, 3, 1, S * S, st);
     hipLaunchKernelGGL((k_small3<float>), dim3(b.n_act), dim3(SM_THREADS), 0, st, b.W, b.act,
-                       (float*)b.Tm, b.state, 1e-6, 1e-12);
+                       (float*)b.Tm, b.state, 1e-6, 1e-12, b.work.cnt);
   }
   return hipGetLastError();
 }

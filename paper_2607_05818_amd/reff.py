@@ -93,7 +93,7 @@ class reff_solve_stats(C.Structure):
 class reff_batch_opts(C.Structure):
     _fields_ = [
         ("solve", reff_solve_opts), ("surrogate", C.c_void_p), ("spot_frac", C.c_double),
-        ("fallback_rel_err", C.c_double), ("tune_db", C.c_char_p),
+        ("fallback_rel_err", C.c_double), ("tune_db", C.c_char_p), ("calibrate", C.c_int32),
     ]
 
 
@@ -217,12 +217,13 @@ def _is_torch_cuda(x):
 
 
 def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, timing=False,
-          graphs=False, progress=False, precond_degree=0, block_rhs=0):
+          graphs=None, progress=False, precond_degree=0, block_rhs=0):
     o = reff_solve_opts()
     o.progress = 1 if progress else 0
     o.precond_degree = int(precond_degree)
     o.timing = 1 if timing else 0
-    o.graphs = 1 if graphs else 0
+    # None: automatic (graph replay where possible); True: replay; False: plain
+    o.graphs = 0 if graphs is None else (1 if graphs else 2)
     o.precision = int(precision)
     o.rel_tol = float(rel_tol)
     o.max_iters = int(max_iters)
@@ -239,7 +240,7 @@ def _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps, 
 
 def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP64,
                     rel_tol=0.0, max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None,
-                    max_ir_steps=0, allow_unconverged=False, timing=False, graphs=False,
+                    max_ir_steps=0, allow_unconverged=False, timing=False, graphs=None,
                     progress=False, precond_degree=0, block_rhs=0):
     """R_i = (G^-1)_ii for `nodes` (None = all).  Returns (R_out, stats)."""
     if nodes is None:
@@ -393,7 +394,7 @@ def reff_reduced_pairs(nx, ny, r_t, s_t, tsv_xy, tsv_r, bump_xy, load_xy, R_out=
 def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.0,
                      max_iters=0, krylov=REFF_KRYLOV_BLOCK, stream=None, R_out=None,
                      timing=False, surrogate=None, spot_frac=0.0, fallback_rel_err=0.0,
-                     graphs=False, tune_db=None, precond_degree=0):
+                     graphs=None, tune_db=None, precond_degree=0, calibrate=False):
     """Solve many plans in one call.  Returns (list of R arrays, list of stats)."""
     k = len(plans)
     structs = (reff_pdn_desc * k)()
@@ -436,6 +437,7 @@ def reff_batch_plans(plans, nodes=None, *, precision=REFF_PREC_MIXED, rel_tol=0.
         bo.surrogate = surrogate.handle
         bo.spot_frac = spot_frac
         bo.fallback_rel_err = fallback_rel_err
+        bo.calibrate = 1 if calibrate else 0
     stats = (reff_solve_stats * k)()
     _check(_lib.reff_batch_plans(structs, k, nptrs, ncount, optrs, C.byref(bo), stats))
     return outs, [stats[i].as_dict() for i in range(k)]

@@ -117,7 +117,7 @@ def test_batch_rejected_on_host(case):
         cnt = (C.c_int64 * 1)(2)
         optr = (C.c_void_p * 1)(out.ctypes.data)
         bo = reff.reff_batch_opts()
-        bo.solve.graphs = 2
+        bo.solve.graphs = 3
         st = reff._lib.reff_batch_plans(structs, 1, nptr, cnt, optr, C.byref(bo), None)
         assert st == want
         return

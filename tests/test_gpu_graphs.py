@@ -1,8 +1,10 @@
 """Iteration chunks replayed as HIP graphs give bitwise the results of plain
 launches (same kernels in the same order; the solver's reductions are
-deterministic).  Each solve replays its graphs many times with host-side
-convergence checks in between, and a batch whose blocks converge at
-different iterations re-captures after every compaction."""
+deterministic).  Each solve replays a captured chunk of four iterations
+many times with host-side convergence checks in between, and in a batch
+whose blocks converge at different iterations the same chunk stays valid
+while converged blocks leave the device-resident work lists.  Graph replay
+is the default; the NULL stream path runs on a stream of its own."""
 import numpy as np
 import pytest
 
@@ -33,7 +35,7 @@ def test_solve_graph_replay_matches_plain_launches(prec):
         out_g = torch.empty(len(nodes), dtype=torch.float64, device="cuda")
         reff.reff_solve_diag(h, nodes, out_g, precision=prec, stream=s.cuda_stream, graphs=True)
         out_p = torch.empty(len(nodes), dtype=torch.float64, device="cuda")
-        reff.reff_solve_diag(h, nodes, out_p, precision=prec, stream=s.cuda_stream)
+        reff.reff_solve_diag(h, nodes, out_p, precision=prec, stream=s.cuda_stream, graphs=False)
     s.synchronize()
     assert torch.equal(out_g, out_p)
 
@@ -48,7 +50,11 @@ def test_batch_graph_replay_with_compaction():
     g, st_g = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_MIXED,
                                     stream=s.cuda_stream, graphs=True)
     p, st_p = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_MIXED,
-                                    stream=s.cuda_stream)
+                                    stream=s.cuda_stream, graphs=False)
+    q, st_q = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_MIXED)  # NULL stream
+    for a, b in zip(q, p):
+        assert np.array_equal(a, b)
+    assert [x["iters_max"] for x in st_q] == [x["iters_max"] for x in st_p]
     iters = [x["iters_max"] for x in st_p]
     assert len(set(iters)) > 1  # blocks converged at different iterations
     for a, b in zip(g, p):
