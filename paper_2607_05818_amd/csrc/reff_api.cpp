@@ -9,8 +9,9 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
-#include <deque>
+#include <atomic>
 #include <new>
+#include <thread>
 #include <numeric>
 #include <random>
 #include <string>
@@ -105,103 +106,182 @@ struct HostCoef {
   std::vector<uint8_t> is_pad;
 };
 
+// Destination of one stack's coefficients inside (possibly concatenated)
+// arrays: node v of the stack is entry off + v, its TSV slots are entries
+// soff .. soff + n_tsv * n_tiers - 1 (global slot ids), and tnode maps a
+// global slot back to its global node entry.
+struct CoefOut {
+  double *d, *cE, *cN, *up, *dn;
+  int32_t* slot;
+  uint8_t* is_pad;
+  int64_t* tnode;  // may be null
+  int64_t off, soff;
+};
+
 // Coefficients of G = L[F, F] for the grounded (Dirichlet) node set `gnd`
-// and a breadth-first connectivity check from those nodes.
-reff_status build_host(const reff_pdn_desc* ds, const std::vector<int64_t>& gnd, HostCoef& h) {
+// and a breadth-first connectivity check from those nodes.  Thread-safe:
+// touches only its own entries of `o`; on failure `msg` says why.
+reff_status build_into(const reff_pdn_desc* ds, const std::vector<int64_t>& gnd, const CoefOut& o,
+                       std::string& msg) {
   const int64_t nt = ds->n_tiers, nx = ds->nx, ny = ds->ny;
   const int64_t plane = nx * ny, n = nt * plane;
-  h.d.assign((size_t)n, 0.0);
-  h.cE.assign((size_t)n, 0.0);
-  h.cN.assign((size_t)n, 0.0);
-  h.slot.assign((size_t)n, -1);
-  h.is_pad.assign((size_t)n, 0);
-  for (int64_t v : gnd) h.is_pad[(size_t)v] = 1;
-  auto edge = [&](int64_t u, int64_t v, double g, double* cu) {
-    const bool fu = !h.is_pad[(size_t)u], fv = !h.is_pad[(size_t)v];
-    if (fu) h.d[(size_t)u] += g;
-    if (fv) h.d[(size_t)v] += g;
-    if (fu && fv && cu) *cu = g;
-  };
+  double* d = o.d + o.off;
+  double* cE = o.cE + o.off;
+  double* cN = o.cN + o.off;
+  int32_t* slot = o.slot + o.off;
+  uint8_t* is_pad = o.is_pad + o.off;
+  std::fill(d, d + n, 0.0);
+  std::fill(cE, cE + n, 0.0);
+  std::fill(cN, cN + n, 0.0);
+  std::fill(slot, slot + n, -1);
+  std::fill(is_pad, is_pad + n, (uint8_t)0);
+  for (int64_t v : gnd) is_pad[v] = 1;
   for (int64_t t = 0; t < nt; ++t)
-    for (int64_t y = 0; y < ny; ++y)
+    for (int64_t y = 0; y < ny; ++y) {
+      const double* gx = ds->gx + (t * ny + y) * (nx - 1);
+      const double* gy = y + 1 < ny ? ds->gy + (t * (ny - 1) + y) * nx : nullptr;
       for (int64_t x = 0; x < nx; ++x) {
         const int64_t v = t * plane + y * nx + x;
-        if (x + 1 < nx) edge(v, v + 1, ds->gx[(t * ny + y) * (nx - 1) + x], &h.cE[(size_t)v]);
-        if (y + 1 < ny) edge(v, v + nx, ds->gy[(t * (ny - 1) + y) * nx + x], &h.cN[(size_t)v]);
+        const bool fv = !is_pad[v];
+        if (x + 1 < nx) {
+          const double g = gx[x];
+          const bool fu = !is_pad[v + 1];
+          if (fv) d[v] += g;
+          if (fu) d[v + 1] += g;
+          if (fu && fv) cE[v] = g;
+        }
+        if (gy) {
+          const double g = gy[x];
+          const bool fu = !is_pad[v + nx];
+          if (fv) d[v] += g;
+          if (fu) d[v + nx] += g;
+          if (fu && fv) cN[v] = g;
+        }
       }
+    }
   // TSV side list: one slot per (column, tier) node.
-  h.up.clear();
-  h.dn.clear();
+  int64_t k = 0;
   for (int32_t j = 0; j < ds->n_tsv; ++j) {
     const int64_t x = ds->tsv_xy[2 * j], y = ds->tsv_xy[2 * j + 1];
-    for (int64_t t = 0; t < nt; ++t) {
+    for (int64_t t = 0; t < nt; ++t, ++k) {
       const int64_t v = t * plane + y * nx + x;
       double gu = 0.0, gd = 0.0;
       if (t + 1 < nt) {
         const double g = ds->tsv_g[j * (nt - 1) + t];
-        const bool fu = !h.is_pad[(size_t)v], fv = !h.is_pad[(size_t)(v + plane)];
-        if (fu) h.d[(size_t)v] += g;
+        const bool fu = !is_pad[v], fv = !is_pad[v + plane];
+        if (fu) d[v] += g;
         if (fu && fv) gu = g;
       }
       if (t > 0) {
         const double g = ds->tsv_g[j * (nt - 1) + t - 1];
-        const bool fu = !h.is_pad[(size_t)v], fv = !h.is_pad[(size_t)(v - plane)];
-        if (fu) h.d[(size_t)v] += g;
+        const bool fu = !is_pad[v], fv = !is_pad[v - plane];
+        if (fu) d[v] += g;
         if (fu && fv) gd = g;
       }
-      h.slot[(size_t)v] = (int32_t)h.up.size();
-      h.up.push_back(gu);
-      h.dn.push_back(gd);
+      slot[v] = (int32_t)(o.soff + k);
+      o.up[o.soff + k] = gu;
+      o.dn[o.soff + k] = gd;
+      if (o.tnode) o.tnode[o.soff + k] = o.off + v;
     }
   }
   for (int64_t v = 0; v < n; ++v)
-    if (h.is_pad[(size_t)v]) h.d[(size_t)v] = 1.0;
-  // Connectivity: breadth-first search from the pads over all resistors.
+    if (is_pad[v]) d[v] = 1.0;
+  // Connectivity: breadth-first search from the pads over all resistors
+  // (the queue is a plain array: every node enters it at most once).
   std::vector<uint8_t> seen((size_t)n, 0);
-  std::vector<int32_t> col((size_t)plane, -1);
-  for (int32_t j = 0; j < ds->n_tsv; ++j) col[(size_t)(ds->tsv_xy[2 * j + 1] * nx + ds->tsv_xy[2 * j])] = j;
-  std::deque<int64_t> q;
+  std::vector<uint8_t> has_tsv((size_t)plane, 0);
+  for (int32_t j = 0; j < ds->n_tsv; ++j)
+    has_tsv[(size_t)(ds->tsv_xy[2 * j + 1] * nx + ds->tsv_xy[2 * j])] = 1;
+  std::vector<int64_t> q;
+  q.reserve((size_t)n);
   for (int64_t v : gnd)
     if (!seen[(size_t)v]) {
       seen[(size_t)v] = 1;
       q.push_back(v);
     }
-  int64_t reached = (int64_t)q.size();
-  while (!q.empty()) {
-    const int64_t v = q.front();
-    q.pop_front();
+  for (size_t h = 0; h < q.size(); ++h) {
+    const int64_t v = q[h];
     const int64_t t = v / plane, rem = v % plane, y = rem / nx, x = rem % nx;
     int64_t nb[6];
-    int k = 0;
-    if (x > 0) nb[k++] = v - 1;
-    if (x + 1 < nx) nb[k++] = v + 1;
-    if (y > 0) nb[k++] = v - nx;
-    if (y + 1 < ny) nb[k++] = v + nx;
-    if (col[(size_t)rem] >= 0) {
-      if (t > 0) nb[k++] = v - plane;
-      if (t + 1 < nt) nb[k++] = v + plane;
+    int c = 0;
+    if (x > 0) nb[c++] = v - 1;
+    if (x + 1 < nx) nb[c++] = v + 1;
+    if (y > 0) nb[c++] = v - nx;
+    if (y + 1 < ny) nb[c++] = v + nx;
+    if (has_tsv[(size_t)rem]) {
+      if (t > 0) nb[c++] = v - plane;
+      if (t + 1 < nt) nb[c++] = v + plane;
     }
-    for (int i = 0; i < k; ++i)
+    for (int i = 0; i < c; ++i)
       if (!seen[(size_t)nb[i]]) {
         seen[(size_t)nb[i]] = 1;
-        ++reached;
         q.push_back(nb[i]);
       }
   }
-  if (reached != n)
-    return fail(REFF_ERR_DISCONNECTED, std::to_string(n - reached) +
-                                           " node(s) have no resistive path to a pad");
+  if ((int64_t)q.size() != n) {
+    msg = std::to_string(n - (int64_t)q.size()) + " node(s) have no resistive path to a pad";
+    return REFF_ERR_DISCONNECTED;
+  }
   return REFF_OK;
+}
+
+reff_status build_host(const reff_pdn_desc* ds, const std::vector<int64_t>& gnd, HostCoef& h) {
+  const int64_t n = (int64_t)ds->n_tiers * ds->nx * ds->ny;
+  const int64_t ns = (int64_t)ds->n_tsv * ds->n_tiers;
+  h.d.resize((size_t)n);
+  h.cE.resize((size_t)n);
+  h.cN.resize((size_t)n);
+  h.slot.resize((size_t)n);
+  h.is_pad.resize((size_t)n);
+  h.up.resize((size_t)ns);
+  h.dn.resize((size_t)ns);
+  const CoefOut o{h.d.data(), h.cE.data(), h.cN.data(), h.up.data(), h.dn.data(),
+                  h.slot.data(), h.is_pad.data(), nullptr, 0, 0};
+  std::string msg;
+  const reff_status s = build_into(ds, gnd, o, msg);
+  return s == REFF_OK ? s : fail(s, msg);
+}
+
+// Run body(i) for i < count on up to 16 host threads (dynamic assignment).
+template <typename F>
+void parallel_for(size_t count, F body) {
+  const size_t hw = std::max<unsigned>(1, std::thread::hardware_concurrency());
+  const size_t nthr = std::min<size_t>({hw, (size_t)16, count});
+  if (nthr <= 1) {
+    for (size_t i = 0; i < count; ++i) body(i);
+    return;
+  }
+  std::atomic<size_t> next{0};
+  std::vector<std::thread> pool;
+  for (size_t t = 0; t < nthr; ++t)
+    pool.emplace_back([&]() {
+      for (size_t i = next++; i < count; i = next++) body(i);
+    });
+  for (auto& th : pool) th.join();
+}
+
+// Apply body(lo, hi) to [0, n) in chunks spread over parallel_for.
+template <typename F>
+void parallel_chunks(size_t n, F body) {
+  constexpr size_t CH = size_t(1) << 20;
+  parallel_for((n + CH - 1) / CH, [&](size_t c) { body(c * CH, std::min(n, (c + 1) * CH)); });
 }
 
 template <typename T>
 reff_status upload(const std::vector<double>& src, T** dst, std::vector<void*>& owned) {
-  std::vector<T> tmp(src.size());
-  for (size_t i = 0; i < src.size(); ++i) tmp[i] = (T)src[i];
-  const size_t bytes = std::max<size_t>(1, tmp.size()) * sizeof(T);
+  const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
   HIPCHK(hipMalloc((void**)dst, bytes));
   owned.push_back(*dst);
-  if (!tmp.empty()) HIPCHK(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (src.empty()) return REFF_OK;
+  if (sizeof(T) == sizeof(double)) {
+    HIPCHK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return REFF_OK;
+  }
+  std::vector<T> tmp(src.size());
+  parallel_chunks(src.size(), [&](size_t lo, size_t hi) {
+    for (size_t i = lo; i < hi; ++i) tmp[i] = (T)src[i];
+  });
+  HIPCHK(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
   return REFF_OK;
 }
 
@@ -247,33 +327,41 @@ reff_status make_coefset_multi(const std::vector<const reff_pdn_desc*>& ds,
                                const std::vector<std::vector<int64_t>>& gnds, CoefSet& cs,
                                std::vector<int64_t>& cbase, std::vector<void*>& extra,
                                std::vector<int32_t>* slot0s = nullptr) {
-  HostCoef h;
-  std::vector<int64_t> tnode;
-  cbase.clear();
-  if (slot0s) slot0s->clear();
-  for (size_t i = 0; i < ds.size(); ++i) {
-    HostCoef hi;
-    reff_status s = build_host(ds[i], gnds[i], hi);
-    if (s != REFF_OK) return s;
-    const int64_t c0 = (int64_t)h.d.size();
-    cbase.push_back(c0);
-    const int32_t slot0 = (int32_t)h.up.size();
-    if (slot0s) slot0s->push_back(slot0);
-    tnode.resize((size_t)slot0 + hi.up.size());
-    for (size_t v = 0; v < hi.slot.size(); ++v)
-      if (hi.slot[v] >= 0) tnode[(size_t)slot0 + (size_t)hi.slot[v]] = c0 + (int64_t)v;
-    for (int32_t& sl : hi.slot)
-      if (sl >= 0) sl += slot0;
-    h.d.insert(h.d.end(), hi.d.begin(), hi.d.end());
-    h.cE.insert(h.cE.end(), hi.cE.begin(), hi.cE.end());
-    h.cN.insert(h.cN.end(), hi.cN.begin(), hi.cN.end());
-    h.up.insert(h.up.end(), hi.up.begin(), hi.up.end());
-    h.dn.insert(h.dn.end(), hi.dn.begin(), hi.dn.end());
-    h.slot.insert(h.slot.end(), hi.slot.begin(), hi.slot.end());
-    h.is_pad.insert(h.is_pad.end(), hi.is_pad.begin(), hi.is_pad.end());
+  // Every stack's entries go straight into the concatenated arrays; the
+  // stacks are built on parallel host threads.
+  const size_t np = ds.size();
+  std::vector<int64_t> off(np + 1, 0), soff(np + 1, 0);
+  for (size_t i = 0; i < np; ++i) {
+    off[i + 1] = off[i] + (int64_t)ds[i]->n_tiers * ds[i]->nx * ds[i]->ny;
+    soff[i + 1] = soff[i] + (int64_t)ds[i]->n_tsv * ds[i]->n_tiers;
   }
+  HostCoef h;
+  std::vector<int64_t> tnode((size_t)soff[np]);
+  h.d.resize((size_t)off[np]);
+  h.cE.resize((size_t)off[np]);
+  h.cN.resize((size_t)off[np]);
+  h.slot.resize((size_t)off[np]);
+  h.is_pad.resize((size_t)off[np]);
+  h.up.resize((size_t)soff[np]);
+  h.dn.resize((size_t)soff[np]);
+  cbase.assign(off.begin(), off.end() - 1);
+  if (slot0s) {
+    slot0s->clear();
+    for (size_t i = 0; i < np; ++i) slot0s->push_back((int32_t)soff[i]);
+  }
+  std::vector<reff_status> st(np, REFF_OK);
+  std::vector<std::string> msg(np);
+  parallel_for(np, [&](size_t i) {
+    const CoefOut o{h.d.data(), h.cE.data(), h.cN.data(), h.up.data(), h.dn.data(),
+                    h.slot.data(), h.is_pad.data(), tnode.data(), off[i], soff[i]};
+    st[i] = build_into(ds[i], gnds[i], o, msg[i]);
+  });
+  for (size_t i = 0; i < np; ++i)
+    if (st[i] != REFF_OK) return fail(st[i], "plan " + std::to_string(i) + ": " + msg[i]);
   std::vector<double> dinv(h.d.size());
-  for (size_t i = 0; i < h.d.size(); ++i) dinv[i] = 1.0 / h.d[i];
+  parallel_chunks(h.d.size(), [&](size_t lo, size_t hi) {
+    for (size_t i = lo; i < hi; ++i) dinv[i] = 1.0 / h.d[i];
+  });
   reff_status rs = REFF_OK;
   auto& owned = extra;
   auto upload_owned = [&](const std::vector<double>& src, double** d64, float** d32) {
