@@ -169,6 +169,51 @@ reff_status reff_solve_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes,
                             double* R_out, const reff_solve_opts* opts,
                             reff_solve_stats* st);
 
+/*
+ * Statistics of a sparse-direct selected inversion (reff_selinv_diag), or of
+ * its plan alone (reff_selinv_info: the timing fields stay 0).
+ */
+typedef struct {
+  int64_t n_fronts;       /* supernodes of the nested-dissection tree         */
+  int32_t n_levels;       /* depth of the tree + 1                            */
+  int32_t reserved;
+  int64_t max_front;      /* rows of the largest dense front                  */
+  int64_t device_bytes;   /* device memory one call allocates                 */
+  double flops_factor;    /* float64 flops of the factorisation               */
+  double flops_selinv;    /* float64 flops of the selected inversion          */
+  double seconds;         /* wall time of the call                            */
+  double seconds_plan;    /* symbolic analysis (on a handle's first use only) */
+  double seconds_factor;  /* allocation, table upload and factorisation       */
+  double seconds_selinv;  /* selected inversion and output                    */
+} reff_selinv_stats;
+
+/*
+ * R_i = (G^-1)_ii (Eq. 2 with all bumps merged into the grounded supply,
+ * Sec. II-B / III-B) by sparse-direct selected inversion: nested dissection
+ * of the stacked grid (walls of columns through every tier), a multifrontal
+ * float64 Cholesky factorisation G = L L^T and the Takahashi recurrence for
+ * the entries of G^-1 on the structure of L, all numeric work on the GPU.
+ * The definition itself, to float64 rounding: there is no tolerance and no
+ * iteration.  The cost does not depend on how many nodes are asked for, so
+ * it is the method for full maps; block PCG (reff_solve_diag) is the method
+ * for samples.  The plan (ordering and front structure) is built on the
+ * handle's first use and kept with it.
+ *   nodes, n_nodes, R_out   as reff_solve_diag (pads give 0.0).
+ *   opts     NULL => defaults; only stream and out_on_device are read.
+ *   st       nullable.
+ * Errors: INVALID_ARG (bad id or option), OUT_OF_MEMORY (the fronts need
+ * reff_selinv_info().device_bytes of device memory), DEVICE (HIP error, or
+ * a Cholesky pivot that is not positive).
+ */
+reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes,
+                             double* R_out, const reff_solve_opts* opts,
+                             reff_selinv_stats* st);
+
+/* The plan reff_selinv_diag would use for a stack (host only, no device
+ * needed): fronts, levels, largest front, device bytes and flop counts.
+ * Errors: INVALID_ARG (as reff_build_pdn's validation). */
+reff_status reff_selinv_info(const reff_pdn_desc* d, reff_selinv_stats* info);
+
 typedef enum {
   REFF_PAIRS_GROUNDED = 0, /* pads merged into the grounded supply:
                               R(a,b) = K_aa + K_bb - 2 K_ab with K = G^-1   */

@@ -5,12 +5,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/reff.h"
 
 namespace reff {
+
+struct SelinvPlan;  // selinv_plan.h
 
 // Set the calling thread's reff_last_error() text and return s.
 reff_status host_fail(reff_status s, const std::string& msg);
@@ -169,6 +172,7 @@ struct reff_pdn_t {
   int64_t flt_ref = -1;
   reff::Workspace ws;         // solver work arrays (grown on demand)
   std::vector<void*> extra;  // coefficient allocations freed with the handle
+  std::shared_ptr<reff::SelinvPlan> sel_plan;  // sparse-direct plan, built on first use
 };
 
 namespace reff {

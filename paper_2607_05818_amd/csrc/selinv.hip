@@ -1,0 +1,687 @@
+// Full maps R_i = (G^-1)_ii by sparse-direct selected inversion.
+//
+// Block PCG pays one block solve per 64 nodes; a full map of a large stack
+// needs every diagonal entry of G^-1, which a sparse Cholesky factorisation
+// and the Takahashi recurrence give at the cost of a few factorisations.
+// The symbolic part (nested dissection of the stacked grid, fronts, maps)
+// is host code (selinv_plan.cpp); everything numeric runs here, in float64,
+// level by level of the dissection tree (all fronts of one depth together).
+//
+// Factorisation (deepest level first): each front is a dense F x F
+// column-major block over [pivots, update set Q].  It is cleared, receives
+// the entries of G in its pivot columns, and the update matrices of its
+// children (extend-add, children of rank 0 then 1, so no two writers meet).
+// Its k pivot columns are then factored 64 at a time, right-looking:
+//   L_jj = chol(A_jj), L_Rj = A_Rj L_jj^-T, A_RR -= L_Rj L_Rj^T  (lower),
+// where R is every front row after the panel; after the last panel the
+// trailing Q x Q block is the update matrix passed to the parent.
+//
+// Selected inversion (roots first; Z = G^-1): a front first gathers Z_QQ
+// from its parent's finished block, then takes its panels last to first.
+// For a panel P with the rows R after it (the later pivots of the front and
+// Q, all of whose Z entries are known by then):
+//   Lhat = L_RP L_PP^-1,  Z_RP = -Z_RR Lhat,
+//   Z_PP = L_PP^-T L_PP^-1 - Lhat^T Z_RP,
+// the block form of the Takahashi identities (L^T Z = L^-1, whose upper
+// part is known and whose lower part is the identity's inverse on the
+// diagonal), written over Z_RP / Z_PR / Z_PP in place.  The dense front
+// makes the structure of every column the whole of R, so the supernodal
+// block form applies to any panel split.  diag(Z_PP) is R_i for the panel's
+// nodes.
+//
+// The dense work is 64 x 64 output tiles on the float64 matrix cores
+// (v_mfma_f64_16x16x4); tiles of all fronts of a level share one launch
+// (grid.y walks the fronts).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "reff_internal.h"
+#include "selinv_plan.h"
+
+namespace reff {
+namespace {
+
+constexpr int PT = 64;  // panel width and output tile edge
+constexpr int LEAF_AREA = 16;
+constexpr unsigned MAX_GY = 65535;
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// Device copy of a front (see SnFront), plus its per-level scratch slots.
+struct DFront {
+  int64_t off;   // arena offset of the F x F block
+  int64_t poff;  // parent's arena offset, -1 at a root
+  int64_t rel;   // into rel[]: F - k parent positions of Q
+  int64_t piv;   // into piv_node[]: k node ids
+  int64_t ybuf;  // offset of its F x 64 block in the level's Y buffer
+  int64_t part;  // offset of its nsplit x 64 x 64 partial products
+  int32_t F, k, pF, rank, nsplit, pad_;
+};
+
+// C(i, j) = alpha sum_{kk in [kb, ke)} A(i, kk) B(kk, j) [+ beta C(i, j)] on the
+// 64 x 64 tile at (i0, j0) of an M x N column-major C (ldc).
+//   A(i, kk) = ta ? A[i lda + kk] : A[kk lda + i]
+//   B(kk, j) = tb ? B[kk ldb + j] : B[j ldb + kk]
+// With `lower`, entries above the diagonal are not written.  Four waves;
+// wave w owns tile rows 16 w .. 16 w + 15 as four 16 x 16 accumulators;
+// K is staged through LDS 16 at a time.  The whole K range is read before
+// the tile is written, so C may alias the rows of A it covers.
+__device__ __forceinline__ void gemm_tile(int i0, int j0, int M, int N, int kb, int ke,
+                                          double alpha, const double* __restrict__ A, int64_t lda,
+                                          bool ta, const double* __restrict__ B, int64_t ldb,
+                                          bool tb, double beta, double* C, int64_t ldc,
+                                          bool lower, double (*sA)[17], double (*sB)[PT + 1]) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int cc = lane & 15, kr = lane >> 4;
+  d4v acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = d4v{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = t + 256 * e;  // 0 .. 1023
+      const int ai = ta ? idx >> 4 : idx & 63, ak = ta ? idx & 15 : idx >> 6;
+      const int gi = i0 + ai, gk = k0 + ak;
+      double va = 0.0;
+      if (gi < M && gk < ke) va = ta ? A[(int64_t)gi * lda + gk] : A[(int64_t)gk * lda + gi];
+      sA[ai][ak] = va;
+      const int bj = tb ? idx & 63 : idx >> 4, bk = tb ? idx >> 6 : idx & 15;
+      const int gj = j0 + bj, gk2 = k0 + bk;
+      double vb = 0.0;
+      if (gj < N && gk2 < ke) vb = tb ? B[(int64_t)gk2 * ldb + gj] : B[(int64_t)gj * ldb + gk2];
+      sB[bk][bj] = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const double a = sA[16 * w + cc][4 * ks + kr];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sB[4 * ks + kr][16 * q + cc], acc[q], 0,
+                                                      0, 0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gi = i0 + 16 * w + kr + 4 * r, gj = j0 + 16 * q + cc;
+      if (gi < M && gj < N && (!lower || gi >= gj)) {
+        double* c = &C[(int64_t)gj * ldc + gi];
+        *c = alpha * acc[q][r] + (beta != 0.0 ? beta * *c : 0.0);
+      }
+    }
+}
+
+__global__ void k_zero(double* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// Entries of G into the cleared fronts (each position occurs once).
+__global__ void k_scatter(const int64_t* __restrict__ idx, const double* __restrict__ val,
+                          int64_t n, double* __restrict__ ar) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    ar[idx[e]] = val[e];
+}
+
+// Extend-add: the lower triangle of each rank-`rank` child's update matrix
+// (its trailing (F-k) x (F-k) block) into its parent at rel x rel.
+__global__ __launch_bounds__(256) void k_extend_add(const DFront* __restrict__ fr,
+                                                    const int32_t* __restrict__ list, int nf,
+                                                    int rank, const int32_t* __restrict__ rel,
+                                                    double* ar) {
+  for (int fi = blockIdx.y; fi < nf; fi += gridDim.y) {
+    const DFront f = fr[list[fi]];
+    if (f.poff < 0 || f.rank != rank) continue;
+    const int64_t q = f.F - f.k;
+    const int32_t* rl = rel + f.rel;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < q * q;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t b = e / q, a = e % q;
+      if (a < b) continue;
+      ar[f.poff + (int64_t)rl[b] * f.pF + rl[a]] +=
+          ar[f.off + (f.k + b) * (int64_t)f.F + f.k + a];
+    }
+  }
+}
+
+// Z_QQ of each front (full square) from its parent's finished block.
+__global__ __launch_bounds__(256) void k_gather(const DFront* __restrict__ fr,
+                                                const int32_t* __restrict__ list, int nf,
+                                                const int32_t* __restrict__ rel, double* ar) {
+  for (int fi = blockIdx.y; fi < nf; fi += gridDim.y) {
+    const DFront f = fr[list[fi]];
+    if (f.poff < 0) continue;
+    const int64_t q = f.F - f.k;
+    const int32_t* rl = rel + f.rel;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < q * q;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t b = e / q, a = e % q;
+      ar[f.off + (f.k + b) * (int64_t)f.F + f.k + a] =
+          ar[f.poff + (int64_t)rl[b] * f.pF + rl[a]];
+    }
+  }
+}
+
+// Diagonal tile of panel jp of every front.  FACTOR: Cholesky of A_jj in
+// place (lower) and L_jj^-1 into Li; a pivot that is not positive sets
+// *bad.  Otherwise (selected inversion): L_jj^-1 into Li and
+// L_jj^-T L_jj^-1 into Z0.  Li, Z0: 64 x 64 column-major per list slot,
+// identity-padded past the panel width.
+template <bool FACTOR>
+__global__ __launch_bounds__(256) void k_tile(const DFront* __restrict__ fr,
+                                              const int32_t* __restrict__ list, int nf, int jp,
+                                              double* ar, double* __restrict__ Li,
+                                              double* __restrict__ Z0, int* bad) {
+  __shared__ double T[PT][PT + 1], X[PT][PT + 1];
+  const int t = threadIdx.x;
+  for (int fi = blockIdx.x; fi < nf; fi += gridDim.x) {
+    const DFront f = fr[list[fi]];
+    const int j0 = PT * jp;
+    if (f.k <= j0) continue;
+    const int w = min(PT, f.k - j0);
+    double* a = ar + f.off + (int64_t)j0 * f.F + j0;
+    __syncthreads();
+    for (int e = t; e < PT * PT; e += 256) {
+      const int c = e >> 6, r = e & 63;
+      T[r][c] = (r < w && c < w) ? (r >= c ? a[(int64_t)c * f.F + r] : 0.0) : (r == c ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    if (FACTOR) {
+      for (int c = 0; c < PT; ++c) {
+        if (t == 0) {
+          const double piv = T[c][c];
+          if (!(piv > 0.0) || !std::isfinite(piv)) atomicOr(bad, 1);
+          T[c][c] = sqrt(fmax(piv, 1e-300));
+        }
+        __syncthreads();
+        const double dc = T[c][c];
+        for (int r = c + 1 + t; r < PT; r += 256) T[r][c] /= dc;
+        __syncthreads();
+        for (int e = t; e < PT * PT; e += 256) {
+          const int cc = e >> 6, r = e & 63;
+          if (cc > c && r >= cc) T[r][cc] -= T[r][c] * T[cc][c];
+        }
+        __syncthreads();
+      }
+    }
+    // L^-1 by forward substitution, one column per thread
+    if (t < PT) {
+      const int c = t;
+      for (int i = 0; i < PT; ++i) {
+        double v = (i == c) ? 1.0 : 0.0;
+        for (int k = c; k < i; ++k) v -= T[i][k] * X[k][c];
+        X[i][c] = (i < c) ? 0.0 : v / T[i][i];
+      }
+    }
+    __syncthreads();
+    double* li = Li + (size_t)fi * PT * PT;
+    for (int e = t; e < PT * PT; e += 256) {
+      const int c = e >> 6, r = e & 63;
+      li[e] = X[r][c];
+      if (FACTOR && r < w && c < w && r >= c) a[(int64_t)c * f.F + r] = T[r][c];
+    }
+    if (!FACTOR) {
+      double* z0 = Z0 + (size_t)fi * PT * PT;
+      for (int e = t; e < PT * PT; e += 256) {
+        const int c = e >> 6, r = e & 63;
+        double v = 0.0;
+        for (int k = max(r, c); k < PT; ++k) v += X[k][r] * X[k][c];
+        z0[e] = v;
+      }
+    }
+  }
+}
+
+enum GemmOp { OP_TRSM = 0, OP_SYRK = 1, OP_LHAT = 2, OP_Y = 3, OP_PART = 4 };
+
+__device__ __forceinline__ void lower_tile(int t, int& ti, int& tj) {
+  ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  tj = t - ti * (ti + 1) / 2;
+}
+
+// The panel products of step jp for every front of a level (see the file
+// comment); blockIdx.x is the tile (or, for OP_PART, the K split).
+template <int OP>
+__global__ __launch_bounds__(256) void k_front_gemm(const DFront* __restrict__ fr,
+                                                    const int32_t* __restrict__ list, int nf,
+                                                    int jp, double* ar,
+                                                    const double* __restrict__ Li,
+                                                    double* __restrict__ Ybuf,
+                                                    double* __restrict__ part) {
+  __shared__ double sA[PT][17], sB[16][PT + 1];
+  for (int fi = blockIdx.y; fi < nf; fi += gridDim.y) {
+    const DFront f = fr[list[fi]];
+    const int j0 = PT * jp;
+    if (f.k <= j0) continue;
+    const int w = min(PT, f.k - j0), r0 = j0 + w, m = f.F - r0;
+    const int64_t F = f.F;
+    double* base = ar + f.off;
+    const double* li = Li + (size_t)fi * PT * PT;
+    const int ntile = (m + PT - 1) / PT;
+    if (OP == OP_TRSM || OP == OP_LHAT) {
+      // rows R of the panel, in place: times L_jj^-T (factor) or L_jj^-1
+      if ((int)blockIdx.x >= ntile) continue;
+      double* c = base + (int64_t)j0 * F + r0;
+      gemm_tile(blockIdx.x * PT, 0, m, w, 0, w, 1.0, c, F, false, li, PT, OP == OP_TRSM, 0.0, c,
+                F, false, sA, sB);
+    } else if (OP == OP_SYRK) {
+      if ((int)blockIdx.x >= ntile * (ntile + 1) / 2) continue;
+      int ti, tj;
+      lower_tile(blockIdx.x, ti, tj);
+      const double* l = base + (int64_t)j0 * F + r0;
+      gemm_tile(ti * PT, tj * PT, m, m, 0, w, -1.0, l, F, false, l, F, true, 1.0,
+                base + (int64_t)r0 * F + r0, F, true, sA, sB);
+    } else if (OP == OP_Y) {
+      // Y = -Z_RR Lhat
+      if ((int)blockIdx.x >= ntile) continue;
+      gemm_tile(blockIdx.x * PT, 0, m, w, 0, m, -1.0, base + (int64_t)r0 * F + r0, F, false,
+                base + (int64_t)j0 * F + r0, F, false, 0.0, Ybuf + f.ybuf, F, false, sA, sB);
+    } else {
+      // partial -Lhat^T Y over split blockIdx.x of the rows R
+      if ((int)blockIdx.x >= f.nsplit) continue;
+      const int ks = (m + f.nsplit - 1) / f.nsplit;
+      const int kb = min(m, (int)blockIdx.x * ks), ke = min(m, kb + ks);
+      gemm_tile(0, 0, w, w, kb, ke, -1.0, base + (int64_t)j0 * F + r0, F, true, Ybuf + f.ybuf, F,
+                false, 0.0, part + f.part + (size_t)blockIdx.x * PT * PT, PT, false, sA, sB);
+    }
+  }
+}
+
+// End of a selected-inversion panel step: Z_PP = Z0 + sum of the partials
+// (blockIdx.x == 0, also writing diag(Z_PP) to Rfull), and Z_RP = Y,
+// Z_PR = Y^T (blockIdx.x = 1 + row tile).
+__global__ __launch_bounds__(256) void k_finish(const DFront* __restrict__ fr,
+                                                const int32_t* __restrict__ list, int nf, int jp,
+                                                double* ar, const double* __restrict__ Z0,
+                                                const double* __restrict__ Ybuf,
+                                                const double* __restrict__ part,
+                                                const int64_t* __restrict__ piv_node,
+                                                double* __restrict__ Rfull) {
+  __shared__ double Ts[PT][PT + 1];
+  const int t = threadIdx.x;
+  for (int fi = blockIdx.y; fi < nf; fi += gridDim.y) {
+    const DFront f = fr[list[fi]];
+    const int j0 = PT * jp;
+    if (f.k <= j0) continue;
+    const int w = min(PT, f.k - j0), r0 = j0 + w, m = f.F - r0;
+    const int64_t F = f.F;
+    double* base = ar + f.off;
+    if (blockIdx.x == 0) {
+      const double* z0 = Z0 + (size_t)fi * PT * PT;
+      const int ns = m > 0 ? f.nsplit : 0;
+      for (int e = t; e < PT * PT; e += 256) {
+        const int c = e >> 6, r = e & 63;
+        if (r >= w || c >= w) continue;
+        double v = z0[e];
+        for (int s = 0; s < ns; ++s) v += part[f.part + (size_t)s * PT * PT + e];
+        base[(int64_t)(j0 + c) * F + j0 + r] = v;
+        if (r == c) Rfull[piv_node[f.piv + j0 + r]] = v;
+      }
+      continue;
+    }
+    const int rt = (int)blockIdx.x - 1;
+    if (rt * PT >= m) continue;
+    const int rows = min(PT, m - rt * PT);
+    const double* y = Ybuf + f.ybuf + rt * PT;
+    __syncthreads();
+    for (int e = t; e < PT * PT; e += 256) {
+      const int c = e >> 6, r = e & 63;
+      if (r < rows && c < w) {
+        const double v = y[(int64_t)c * F + r];
+        base[(int64_t)(j0 + c) * F + r0 + rt * PT + r] = v;  // Z_RP
+        Ts[c][r] = v;
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < PT * PT; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      if (r < rows && c < w) base[(int64_t)(r0 + rt * PT + r) * F + j0 + c] = Ts[c][r];  // Z_PR
+    }
+  }
+}
+
+__global__ void k_pick(const double* __restrict__ Rfull, const int64_t* __restrict__ nodes,
+                       int64_t n, double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = Rfull[nodes[i]];
+}
+
+dim3 flat(int64_t n) { return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192))); }
+
+struct Bufs {
+  std::vector<void*> ptrs;
+  ~Bufs() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  hipError_t get(T** out, size_t count) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back(p);
+    *out = (T*)p;
+    return e;
+  }
+};
+
+template <typename T>
+hipError_t put(Bufs& b, T** out, const std::vector<T>& v, hipStream_t st) {
+  hipError_t e = b.get(out, v.size());
+  if (e == hipSuccess && !v.empty())
+    e = hipMemcpyAsync(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+  return e;
+}
+
+// Per level: the largest tile counts of each launch of a panel step.
+struct LevelDev {
+  int64_t list_off = 0;
+  int nf = 0;
+  int max_panels = 0;
+  int max_rowtiles = 0;  // over fronts, for panel 0 (the largest m)
+  int max_split = 0;
+  int64_t ent_off = 0, ent_n = 0;
+};
+
+reff_status dev_status(hipError_t e, const char* what) {
+  return host_fail(e == hipErrorOutOfMemory ? REFF_ERR_OUT_OF_MEMORY : REFF_ERR_DEVICE,
+                   std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+std::shared_ptr<SelinvPlan> selinv_plan_of(reff_pdn_t* p, reff_status& s) {
+  s = REFF_OK;
+  if (p->sel_plan) return p->sel_plan;
+  auto plan = std::make_shared<SelinvPlan>();
+  std::string err;
+  if (!build_selinv_plan(p->nt, p->nx, p->ny, p->gx.data(), p->gy.data(),
+                         (int32_t)(p->tsv_xy.size() / 2), p->tsv_xy.data(), p->tsv_g.data(),
+                         (int32_t)(p->pad_xy.size() / 2), p->pad_xy.data(), LEAF_AREA, *plan,
+                         err)) {
+    s = host_fail(REFF_ERR_DEVICE, "selected inversion plan: " + err);
+    return nullptr;
+  }
+  p->sel_plan = plan;
+  return plan;
+}
+
+// Scratch sizes of a plan on the device, in doubles / bytes.
+struct SelinvSizes {
+  int64_t tiles = 0, ybuf = 0, part = 0;
+  int64_t bytes = 0;
+};
+
+SelinvSizes selinv_sizes(const SelinvPlan& P) {
+  SelinvSizes z;
+  for (const SelinvLevel& L : P.levels) {
+    int64_t yb = 0, pa = 0;
+    for (int32_t i : L.fronts) {
+      const SnFront& f = P.fronts[(size_t)i];
+      yb += (int64_t)f.F * PT;
+      pa += (int64_t)std::min(16, std::max(1, (f.F + 255) / 256)) * PT * PT;
+    }
+    z.tiles = std::max<int64_t>(z.tiles, (int64_t)L.fronts.size() * PT * PT);
+    z.ybuf = std::max(z.ybuf, yb);
+    z.part = std::max(z.part, pa);
+  }
+  int64_t ent = 0;
+  for (const SelinvLevel& L : P.levels) ent += (int64_t)L.ent_idx.size();
+  z.bytes = 8 * (P.arena + 2 * z.tiles + z.ybuf + z.part + P.n) + 16 * ent +
+            (int64_t)sizeof(DFront) * (int64_t)P.fronts.size() + 4 * (int64_t)P.rel.size() +
+            8 * (int64_t)P.piv_node.size();
+  return z;
+}
+
+}  // namespace reff
+
+extern "C" {
+
+reff_status reff_selinv_info(const reff_pdn_desc* d, reff_selinv_stats* info) {
+  using namespace reff;
+  if (!d || !info) return host_fail(REFF_ERR_INVALID_ARG, "NULL descriptor or info");
+  reff_status s = host_validate_desc(d);
+  if (s != REFF_OK) return s;
+  SelinvPlan plan;
+  std::string err;
+  if (!build_selinv_plan(d->n_tiers, d->nx, d->ny, d->gx, d->gy, d->n_tsv, d->tsv_xy, d->tsv_g,
+                         d->n_pads, d->pad_xy, LEAF_AREA, plan, err))
+    return host_fail(REFF_ERR_INVALID_ARG, "selected inversion plan: " + err);
+  std::memset(info, 0, sizeof(*info));
+  info->n_fronts = (int64_t)plan.fronts.size();
+  info->n_levels = (int32_t)plan.levels.size();
+  for (const SnFront& f : plan.fronts) info->max_front = std::max<int64_t>(info->max_front, f.F);
+  info->device_bytes = selinv_sizes(plan).bytes;
+  info->flops_factor = plan.flops_factor;
+  info->flops_selinv = plan.flops_selinv;
+  return REFF_OK;
+}
+
+reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, double* R_out,
+                             const reff_solve_opts* opts, reff_selinv_stats* st) {
+  using namespace reff;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!p) return host_fail(REFF_ERR_INVALID_ARG, "handle is NULL");
+  if (nodes && n_nodes < 0) return host_fail(REFF_ERR_INVALID_ARG, "n_nodes < 0");
+  const int64_t count = nodes ? n_nodes : p->n;
+  if (count > 0 && !R_out) return host_fail(REFF_ERR_INVALID_ARG, "R_out is NULL");
+  for (int64_t i = 0; nodes && i < count; ++i)
+    if (nodes[i] < 0 || nodes[i] >= p->n)
+      return host_fail(REFF_ERR_INVALID_ARG, "node id " + std::to_string(nodes[i]) + " out of range");
+  hipStream_t st_ = opts ? (hipStream_t)opts->stream : nullptr;
+  const bool out_dev = opts && opts->out_on_device;
+  if (opts && opts->out_on_device != 0 && opts->out_on_device != 1)
+    return host_fail(REFF_ERR_INVALID_ARG, "out_on_device must be 0 or 1");
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return dev_status(e, "hipSetDevice");
+  reff_status s;
+  auto plan_sp = selinv_plan_of(p, s);
+  if (!plan_sp) return s;
+  const SelinvPlan& P = *plan_sp;
+  const auto t_plan = std::chrono::steady_clock::now();
+
+  // host tables
+  std::vector<DFront> dfr(P.fronts.size());
+  std::vector<int32_t> lists;
+  std::vector<LevelDev> lv(P.levels.size());
+  std::vector<int64_t> ent_idx;
+  std::vector<double> ent_val;
+  const SelinvSizes sz = selinv_sizes(P);
+  for (size_t d = 0; d < P.levels.size(); ++d) {
+    const SelinvLevel& L = P.levels[d];
+    LevelDev& D = lv[d];
+    D.list_off = (int64_t)lists.size();
+    D.nf = (int)L.fronts.size();
+    D.max_panels = L.max_panels;
+    D.ent_off = (int64_t)ent_idx.size();
+    D.ent_n = (int64_t)L.ent_idx.size();
+    ent_idx.insert(ent_idx.end(), L.ent_idx.begin(), L.ent_idx.end());
+    ent_val.insert(ent_val.end(), L.ent_val.begin(), L.ent_val.end());
+    int64_t yb = 0, pa = 0;
+    for (int32_t i : L.fronts) {
+      const SnFront& f = P.fronts[(size_t)i];
+      DFront& g = dfr[(size_t)i];
+      g.off = f.off;
+      g.poff = f.parent >= 0 ? P.fronts[(size_t)f.parent].off : -1;
+      g.rel = f.rel;
+      g.piv = f.piv;
+      g.F = f.F;
+      g.k = f.k;
+      g.pF = f.parent >= 0 ? P.fronts[(size_t)f.parent].F : 0;
+      g.rank = f.rank;
+      g.nsplit = std::min(16, std::max(1, (f.F + 255) / 256));
+      g.pad_ = 0;
+      g.ybuf = yb;
+      g.part = pa;
+      yb += (int64_t)f.F * PT;
+      pa += (int64_t)g.nsplit * PT * PT;
+      lists.push_back(i);
+      const int m0 = f.F - std::min(PT, f.k);
+      D.max_rowtiles = std::max(D.max_rowtiles, (m0 + PT - 1) / PT);
+      D.max_split = std::max(D.max_split, g.nsplit);
+    }
+  }
+
+  Bufs b;
+  double *ar = nullptr, *Li = nullptr, *Z0 = nullptr, *Yb = nullptr, *part = nullptr;
+  double *Rfull = nullptr, *vals = nullptr, *dout = nullptr;
+  int64_t *idx = nullptr, *piv = nullptr, *dnodes = nullptr;
+  int32_t *rel = nullptr, *dl = nullptr;
+  DFront* dF = nullptr;
+  int* bad = nullptr;
+  e = b.get(&ar, (size_t)P.arena);
+  if (e == hipSuccess) e = b.get(&Li, (size_t)sz.tiles);
+  if (e == hipSuccess) e = b.get(&Z0, (size_t)sz.tiles);
+  if (e == hipSuccess) e = b.get(&Yb, (size_t)sz.ybuf);
+  if (e == hipSuccess) e = b.get(&part, (size_t)sz.part);
+  if (e == hipSuccess) e = b.get(&Rfull, (size_t)P.n);
+  if (e == hipSuccess) e = b.get(&bad, 1);
+  if (e == hipSuccess) e = put(b, &idx, ent_idx, st_);
+  if (e == hipSuccess) e = put(b, &vals, ent_val, st_);
+  if (e == hipSuccess) e = put(b, &piv, P.piv_node, st_);
+  if (e == hipSuccess) e = put(b, &rel, P.rel, st_);
+  if (e == hipSuccess) e = put(b, &dl, lists, st_);
+  if (e == hipSuccess) e = put(b, &dF, dfr, st_);
+  if (e == hipSuccess && nodes && count > 0) {
+    std::vector<int64_t> nv(nodes, nodes + count);
+    e = put(b, &dnodes, nv, st_);
+    // the staged host vector must outlive the copy
+    if (e == hipSuccess) e = hipStreamSynchronize(st_);
+  }
+  if (e == hipSuccess && !out_dev && count > 0) e = b.get(&dout, (size_t)count);
+  if (e != hipSuccess) return dev_status(e, "selected inversion: allocation / upload");
+  hipLaunchKernelGGL(k_zero, flat(P.n), dim3(256), 0, st_, Rfull, P.n);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), st_);
+
+  auto gy = [](int nf) { return (unsigned)std::min<int64_t>(nf, MAX_GY); };
+  const int nlev = (int)P.levels.size();
+  // factorisation, deepest level first
+  for (int d = nlev - 1; d >= 0 && e == hipSuccess; --d) {
+    const SelinvLevel& L = P.levels[(size_t)d];
+    const LevelDev& D = lv[(size_t)d];
+    const int32_t* l = dl + D.list_off;
+    if (D.nf == 0) continue;
+    const int64_t span = L.arena_end - L.arena_begin;
+    if (span > 0) hipLaunchKernelGGL(k_zero, flat(span), dim3(256), 0, st_, ar + L.arena_begin, span);
+    if (D.ent_n > 0)
+      hipLaunchKernelGGL(k_scatter, flat(D.ent_n), dim3(256), 0, st_, idx + D.ent_off,
+                         vals + D.ent_off, D.ent_n, ar);
+    if (d + 1 < nlev && lv[(size_t)d + 1].nf > 0) {
+      const LevelDev& C = lv[(size_t)d + 1];
+      int64_t maxq = 0;
+      for (int32_t i : P.levels[(size_t)d + 1].fronts)
+        maxq = std::max<int64_t>(maxq, (int64_t)(P.fronts[(size_t)i].F - P.fronts[(size_t)i].k));
+      const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((maxq * maxq + 255) / 256, 1024));
+      for (int rank = 0; rank < 2; ++rank)
+        hipLaunchKernelGGL(k_extend_add, dim3(gx, gy(C.nf)), dim3(256), 0, st_, dF,
+                           dl + C.list_off, C.nf, rank, rel, ar);
+    }
+    for (int jp = 0; jp < D.max_panels; ++jp) {
+      hipLaunchKernelGGL(k_tile<true>, dim3(gy(D.nf)), dim3(256), 0, st_, dF, l, D.nf, jp, ar,
+                         Li, Z0, bad);
+      // rows after this panel in the largest front of the level
+      int mt = 0;
+      for (int32_t i : L.fronts) {
+        const SnFront& f = P.fronts[(size_t)i];
+        if (f.k > PT * jp) mt = std::max(mt, (f.F - PT * jp - std::min(PT, f.k - PT * jp) + PT - 1) / PT);
+      }
+      if (mt == 0) continue;
+      hipLaunchKernelGGL(k_front_gemm<OP_TRSM>, dim3((unsigned)mt, gy(D.nf)), dim3(256), 0, st_,
+                         dF, l, D.nf, jp, ar, Li, Yb, part);
+      hipLaunchKernelGGL(k_front_gemm<OP_SYRK>, dim3((unsigned)(mt * (mt + 1) / 2), gy(D.nf)),
+                         dim3(256), 0, st_, dF, l, D.nf, jp, ar, Li, Yb, part);
+    }
+    e = hipGetLastError();
+  }
+  int hbad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st_);
+  if (e == hipSuccess) e = hipStreamSynchronize(st_);
+  if (e != hipSuccess) return dev_status(e, "selected inversion: factorisation");
+  if (hbad) return host_fail(REFF_ERR_DEVICE, "sparse Cholesky: a pivot was not positive");
+  const auto t_fact = std::chrono::steady_clock::now();
+  // selected inversion, roots first
+  for (int d = 0; d < nlev && e == hipSuccess; ++d) {
+    const SelinvLevel& L = P.levels[(size_t)d];
+    const LevelDev& D = lv[(size_t)d];
+    const int32_t* l = dl + D.list_off;
+    if (D.nf == 0) continue;
+    if (d > 0) {
+      int64_t maxq = 0;
+      for (int32_t i : L.fronts)
+        maxq = std::max<int64_t>(maxq, (int64_t)(P.fronts[(size_t)i].F - P.fronts[(size_t)i].k));
+      if (maxq > 0) {
+        const unsigned gx = (unsigned)std::min<int64_t>((maxq * maxq + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_gather, dim3(gx, gy(D.nf)), dim3(256), 0, st_, dF, l, D.nf, rel, ar);
+      }
+    }
+    for (int jp = D.max_panels - 1; jp >= 0; --jp) {
+      int mt = 0, ms = 0;
+      for (int32_t i : L.fronts) {
+        const SnFront& f = P.fronts[(size_t)i];
+        if (f.k > PT * jp) {
+          mt = std::max(mt, (f.F - PT * jp - std::min(PT, f.k - PT * jp) + PT - 1) / PT);
+          ms = std::max(ms, dfr[(size_t)i].nsplit);
+        }
+      }
+      hipLaunchKernelGGL(k_tile<false>, dim3(gy(D.nf)), dim3(256), 0, st_, dF, l, D.nf, jp, ar,
+                         Li, Z0, bad);
+      if (mt > 0) {
+        hipLaunchKernelGGL(k_front_gemm<OP_LHAT>, dim3((unsigned)mt, gy(D.nf)), dim3(256), 0,
+                           st_, dF, l, D.nf, jp, ar, Li, Yb, part);
+        hipLaunchKernelGGL(k_front_gemm<OP_Y>, dim3((unsigned)mt, gy(D.nf)), dim3(256), 0, st_,
+                           dF, l, D.nf, jp, ar, Li, Yb, part);
+        hipLaunchKernelGGL(k_front_gemm<OP_PART>, dim3((unsigned)ms, gy(D.nf)), dim3(256), 0,
+                           st_, dF, l, D.nf, jp, ar, Li, Yb, part);
+      }
+      hipLaunchKernelGGL(k_finish, dim3((unsigned)(1 + mt), gy(D.nf)), dim3(256), 0, st_, dF, l,
+                         D.nf, jp, ar, Z0, Yb, part, piv, Rfull);
+    }
+    e = hipGetLastError();
+  }
+  // output
+  if (e == hipSuccess && count > 0) {
+    double* out = out_dev ? R_out : dout;
+    if (nodes) {
+      hipLaunchKernelGGL(k_pick, flat(count), dim3(256), 0, st_, Rfull, dnodes, count, out);
+      e = hipGetLastError();
+    } else {
+      e = hipMemcpyAsync(out, Rfull, sizeof(double) * count, hipMemcpyDeviceToDevice, st_);
+    }
+    if (e == hipSuccess && !out_dev)
+      e = hipMemcpyAsync(R_out, dout, sizeof(double) * count, hipMemcpyDeviceToHost, st_);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st_);
+  if (e != hipSuccess) return dev_status(e, "selected inversion");
+  const auto t1 = std::chrono::steady_clock::now();
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->n_fronts = (int64_t)P.fronts.size();
+    st->n_levels = (int32_t)P.levels.size();
+    for (const SnFront& f : P.fronts) st->max_front = std::max<int64_t>(st->max_front, f.F);
+    st->device_bytes = sz.bytes;
+    st->flops_factor = P.flops_factor;
+    st->flops_selinv = P.flops_selinv;
+    st->seconds = std::chrono::duration<double>(t1 - t0).count();
+    st->seconds_plan = std::chrono::duration<double>(t_plan - t0).count();
+    st->seconds_factor = std::chrono::duration<double>(t_fact - t_plan).count();
+    st->seconds_selinv = std::chrono::duration<double>(t1 - t_fact).count();
+  }
+  return REFF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+// Symbolic analysis of the sparse-direct full map (see selinv_plan.h).
+#include "selinv_plan.h"
+
+#include <algorithm>
+#include <functional>
+
+namespace reff {
+
+namespace {
+
+struct Builder {
+  int32_t nt, nx, ny;
+  int64_t plane;
+  const double *gx, *gy, *tsv_g;
+  std::vector<int32_t> tsv_of;  // column -> TSV index, -1 if none
+  std::vector<uint8_t> pad;     // tier-0 column is a pad
+  int32_t leaf;
+  SelinvPlan& P;
+  std::vector<int64_t> ord;     // elimination position of a node, -1 = pad
+  std::vector<std::vector<int32_t>> kids;
+  int64_t next_ord = 0;
+
+  bool is_free(int64_t v) const { return !(v < plane && pad[(size_t)v]); }
+
+  void add_pivot(int64_t v) {
+    if (!is_free(v)) return;
+    ord[(size_t)v] = next_ord++;
+    P.piv_node.push_back(v);
+  }
+
+  // Build the subtree of the box; returns its front index, -1 if empty.
+  int32_t rec(int32_t x0, int32_t x1, int32_t y0, int32_t y1, int32_t depth) {
+    const int32_t w = x1 - x0, h = y1 - y0;
+    if (w <= 0 || h <= 0) return -1;
+    std::vector<int32_t> ch;
+    SnFront f;
+    f.x0 = x0, f.x1 = x1, f.y0 = y0, f.y1 = y1, f.depth = depth;
+    if ((int64_t)w * h <= leaf) {
+      f.piv = (int64_t)P.piv_node.size();
+      for (int32_t t = 0; t < nt; ++t)
+        for (int32_t y = y0; y < y1; ++y)
+          for (int32_t x = x0; x < x1; ++x) add_pivot(t * plane + (int64_t)y * nx + x);
+    } else if (w >= h) {
+      const int32_t m = x0 + w / 2;
+      for (int32_t c : {rec(x0, m, y0, y1, depth + 1), rec(m + 1, x1, y0, y1, depth + 1)})
+        if (c >= 0) ch.push_back(c);
+      f.piv = (int64_t)P.piv_node.size();
+      for (int32_t t = 0; t < nt; ++t)
+        for (int32_t y = y0; y < y1; ++y) add_pivot(t * plane + (int64_t)y * nx + m);
+    } else {
+      const int32_t m = y0 + h / 2;
+      for (int32_t c : {rec(x0, x1, y0, m, depth + 1), rec(x0, x1, m + 1, y1, depth + 1)})
+        if (c >= 0) ch.push_back(c);
+      f.piv = (int64_t)P.piv_node.size();
+      for (int32_t t = 0; t < nt; ++t)
+        for (int32_t x = x0; x < x1; ++x) add_pivot(t * plane + (int64_t)m * nx + x);
+    }
+    f.k = (int32_t)((int64_t)P.piv_node.size() - f.piv);
+    const int32_t id = (int32_t)P.fronts.size();
+    for (size_t r = 0; r < ch.size(); ++r) {
+      P.fronts[(size_t)ch[r]].parent = id;
+      P.fronts[(size_t)ch[r]].rank = (int32_t)r;
+    }
+    P.fronts.push_back(f);
+    kids.push_back(ch);
+    return id;
+  }
+
+  // Free nodes just outside the box, all tiers, in elimination order.
+  void boundary(const SnFront& f, std::vector<int64_t>& q) const {
+    q.clear();
+    for (int32_t t = 0; t < nt; ++t) {
+      const int64_t tb = t * plane;
+      if (f.x0 > 0)
+        for (int32_t y = f.y0; y < f.y1; ++y) q.push_back(tb + (int64_t)y * nx + f.x0 - 1);
+      if (f.x1 < nx)
+        for (int32_t y = f.y0; y < f.y1; ++y) q.push_back(tb + (int64_t)y * nx + f.x1);
+      if (f.y0 > 0)
+        for (int32_t x = f.x0; x < f.x1; ++x) q.push_back(tb + (int64_t)(f.y0 - 1) * nx + x);
+      if (f.y1 < ny)
+        for (int32_t x = f.x0; x < f.x1; ++x) q.push_back(tb + (int64_t)f.y1 * nx + x);
+    }
+    q.erase(std::remove_if(q.begin(), q.end(), [&](int64_t v) { return !is_free(v); }),
+            q.end());
+    std::sort(q.begin(), q.end(),
+              [&](int64_t a, int64_t b) { return ord[(size_t)a] < ord[(size_t)b]; });
+  }
+
+  // Conductances of the edges at node v: calls fn(u, g) for every neighbour
+  // u (pads included) and returns the sum.
+  template <typename Fn>
+  double edges(int64_t v, Fn fn) const {
+    const int64_t t = v / plane, rem = v % plane, y = rem / nx, x = rem % nx;
+    double s = 0.0;
+    auto e = [&](int64_t u, double g) {
+      s += g;
+      fn(u, g);
+    };
+    const double* gxt = gx + t * (int64_t)ny * (nx - 1);
+    const double* gyt = gy + t * (int64_t)(ny - 1) * nx;
+    if (x > 0) e(v - 1, gxt[y * (nx - 1) + x - 1]);
+    if (x + 1 < nx) e(v + 1, gxt[y * (nx - 1) + x]);
+    if (y > 0) e(v - nx, gyt[(y - 1) * nx + x]);
+    if (y + 1 < ny) e(v + nx, gyt[y * nx + x]);
+    const int32_t j = tsv_of[(size_t)rem];
+    if (j >= 0) {
+      if (t > 0) e(v - plane, tsv_g[(int64_t)j * (nt - 1) + t - 1]);
+      if (t + 1 < nt) e(v + plane, tsv_g[(int64_t)j * (nt - 1) + t]);
+    }
+    return s;
+  }
+};
+
+}  // namespace
+
+bool build_selinv_plan(int32_t nt, int32_t nx, int32_t ny, const double* gx, const double* gy,
+                       int32_t n_tsv, const int32_t* tsv_xy, const double* tsv_g, int32_t n_pads,
+                       const int32_t* pad_xy, int32_t leaf_area, SelinvPlan& plan,
+                       std::string& err) {
+  plan = SelinvPlan();
+  plan.nt = nt, plan.nx = nx, plan.ny = ny;
+  Builder b{nt, nx, ny, (int64_t)nx * ny, gx, gy, tsv_g, {}, {}, std::max(1, leaf_area), plan,
+            {}, {}, 0};
+  const int64_t n = b.plane * nt;
+  plan.n = n;
+  b.tsv_of.assign((size_t)b.plane, -1);
+  for (int32_t j = 0; j < n_tsv; ++j)
+    b.tsv_of[(size_t)((int64_t)tsv_xy[2 * j + 1] * nx + tsv_xy[2 * j])] = j;
+  b.pad.assign((size_t)b.plane, 0);
+  for (int32_t j = 0; j < n_pads; ++j) b.pad[(size_t)((int64_t)pad_xy[2 * j + 1] * nx + pad_xy[2 * j])] = 1;
+  b.ord.assign((size_t)n, -1);
+  b.rec(0, nx, 0, ny, 0);
+  plan.n_free = b.next_ord;
+
+  // update sets, sizes, levels
+  std::vector<std::vector<int64_t>> Q(plan.fronts.size());
+  int32_t max_depth = 0;
+  for (size_t i = 0; i < plan.fronts.size(); ++i) {
+    b.boundary(plan.fronts[i], Q[i]);
+    SnFront& f = plan.fronts[i];
+    const int64_t F = (int64_t)f.k + (int64_t)Q[i].size();
+    if (F > (int64_t)1 << 30) {
+      err = "front too large";
+      return false;
+    }
+    f.F = (int32_t)F;
+    max_depth = std::max(max_depth, f.depth);
+  }
+  plan.levels.assign((size_t)max_depth + 1, SelinvLevel());
+  for (size_t i = 0; i < plan.fronts.size(); ++i)
+    plan.levels[(size_t)plan.fronts[i].depth].fronts.push_back((int32_t)i);
+  int64_t off = 0;
+  for (SelinvLevel& L : plan.levels) {
+    L.arena_begin = off;
+    for (int32_t i : L.fronts) {
+      SnFront& f = plan.fronts[(size_t)i];
+      f.off = off;
+      off += (int64_t)f.F * f.F;
+      L.max_panels = std::max<int32_t>(L.max_panels, (f.k + 63) / 64);
+      L.max_F = std::max<int64_t>(L.max_F, f.F);
+      const double k = f.k, q = f.F - f.k;
+      plan.flops_factor += k * k * k / 3.0 + k * k * q + k * q * q;
+      for (int32_t j0 = 0; j0 < f.k; j0 += 64) {
+        const double w = std::min(64, f.k - j0), m = f.F - j0 - w;
+        plan.flops_selinv += 2.0 * m * w * w + 2.0 * m * m * w + 2.0 * m * w * w + w * w * w;
+      }
+    }
+    L.arena_end = off;
+  }
+  plan.arena = off;
+
+  // positions inside a front's index set; child maps and original entries
+  std::vector<int32_t> pos((size_t)n, -1);
+  for (size_t s = 0; s < plan.fronts.size(); ++s) {
+    const SnFront& f = plan.fronts[s];
+    for (int32_t a = 0; a < f.k; ++a) pos[(size_t)plan.piv_node[(size_t)(f.piv + a)]] = a;
+    for (size_t a = 0; a < Q[s].size(); ++a) pos[(size_t)Q[s][a]] = f.k + (int32_t)a;
+    for (int32_t c : b.kids[s]) {
+      SnFront& cf = plan.fronts[(size_t)c];
+      cf.rel = (int64_t)plan.rel.size();
+      int32_t prev = -1;
+      for (int64_t u : Q[(size_t)c]) {
+        const int32_t p = pos[(size_t)u];
+        if (p < 0 || p <= prev) {
+          err = "update set of a child outside its parent's front";
+          return false;
+        }
+        prev = p;
+        plan.rel.push_back(p);
+      }
+    }
+    SelinvLevel& L = plan.levels[(size_t)f.depth];
+    for (int32_t a = 0; a < f.k; ++a) {
+      const int64_t v = plan.piv_node[(size_t)(f.piv + a)];
+      bool bad = false;
+      const double dv = b.edges(v, [&](int64_t u, double g) {
+        if (!b.is_free(u) || b.ord[(size_t)u] < b.ord[(size_t)v]) return;
+        const int32_t p = pos[(size_t)u];
+        if (p < 0) {
+          bad = true;
+          return;
+        }
+        L.ent_idx.push_back(f.off + (int64_t)a * f.F + p);
+        L.ent_val.push_back(-g);
+      });
+      if (bad) {
+        err = "neighbour outside the front of its pivot";
+        return false;
+      }
+      L.ent_idx.push_back(f.off + (int64_t)a * f.F + a);
+      L.ent_val.push_back(dv);
+    }
+    for (int32_t a = 0; a < f.k; ++a) pos[(size_t)plan.piv_node[(size_t)(f.piv + a)]] = -1;
+    for (int64_t u : Q[s]) pos[(size_t)u] = -1;
+  }
+  return true;
+}
+
+}  // namespace reff

@@ -90,6 +90,18 @@ class reff_solve_stats(C.Structure):
         return out
 
 
+class reff_selinv_stats(C.Structure):
+    _fields_ = [
+        ("n_fronts", C.c_int64), ("n_levels", C.c_int32), ("reserved", C.c_int32),
+        ("max_front", C.c_int64), ("device_bytes", C.c_int64), ("flops_factor", C.c_double),
+        ("flops_selinv", C.c_double), ("seconds", C.c_double), ("seconds_plan", C.c_double),
+        ("seconds_factor", C.c_double), ("seconds_selinv", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class reff_batch_opts(C.Structure):
     _fields_ = [
         ("solve", reff_solve_opts), ("surrogate", C.c_void_p), ("spot_frac", C.c_double),
@@ -128,6 +140,11 @@ _lib.reff_ir_drop.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c
                               C.POINTER(reff_solve_opts), C.POINTER(reff_solve_stats)]
 _lib.reff_ir_drop.restype = C.c_int
 _lib.reff_grid_pairs_noalloc.restype = C.c_int
+_lib.reff_selinv_diag.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                  C.POINTER(reff_solve_opts), C.POINTER(reff_selinv_stats)]
+_lib.reff_selinv_diag.restype = C.c_int
+_lib.reff_selinv_info.argtypes = [C.POINTER(reff_pdn_desc), C.POINTER(reff_selinv_stats)]
+_lib.reff_selinv_info.restype = C.c_int
 _lib.reff_status_string.argtypes = [C.c_int]
 _lib.reff_status_string.restype = C.c_char_p
 _lib.reff_last_error.argtypes = []
@@ -268,6 +285,41 @@ def reff_solve_diag(pdn: PDN, nodes=None, R_out=None, *, precision=REFF_PREC_FP6
     _check(_lib.reff_solve_diag(pdn.handle, nptr, count if nodes is not None else 0, optr,
                                 C.byref(o), C.byref(st)), allow)
     return R_out, st.as_dict()
+
+
+def reff_selinv_diag(pdn: PDN, nodes=None, R_out=None, *, stream=None):
+    """R_i = (G^-1)_ii for `nodes` (None = all) by sparse-direct selected
+    inversion on the GPU.  Returns (R_out, stats)."""
+    if nodes is None:
+        count, nptr = pdn.num_nodes, None
+    else:
+        nodes_arr = np.ascontiguousarray(nodes, dtype=np.int64)
+        count, nptr = len(nodes_arr), nodes_arr.ctypes.data
+    if R_out is None:
+        R_out = np.empty(count, dtype=np.float64)
+    out_dev = _is_torch_cuda(R_out)
+    if out_dev:
+        assert R_out.dtype.__repr__().endswith("float64") and R_out.is_contiguous()
+        assert R_out.numel() >= count
+        optr = R_out.data_ptr()
+    else:
+        assert R_out.dtype == np.float64 and R_out.flags.c_contiguous and len(R_out) >= count
+        optr = R_out.ctypes.data
+    o = _opts(REFF_PREC_FP64, 0.0, 0, REFF_KRYLOV_BLOCK, stream, out_dev, 0)
+    st = reff_selinv_stats()
+    _check(_lib.reff_selinv_diag(pdn.handle, nptr, count if nodes is not None else 0, optr,
+                                 C.byref(o), C.byref(st)))
+    return R_out, st.as_dict()
+
+
+def reff_selinv_info(desc):
+    """Plan of reff_selinv_diag for a stack descriptor (host only): fronts,
+    levels, largest front, device bytes, flop counts."""
+    ds, keep = _desc_struct(desc)
+    st = reff_selinv_stats()
+    _check(_lib.reff_selinv_info(C.byref(ds), C.byref(st)))
+    del keep
+    return st.as_dict()
 
 
 def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
