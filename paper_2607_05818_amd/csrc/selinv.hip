@@ -66,48 +66,61 @@ struct DFront {
   int32_t F, k, pF, rank, nsplit, pad_;
 };
 
+constexpr int KS = 32;  // K slice staged through LDS
+
 // C(i, j) = alpha sum_{kk in [kb, ke)} A(i, kk) B(kk, j) [+ beta C(i, j)] on the
 // 64 x 64 tile at (i0, j0) of an M x N column-major C (ldc).
 //   A(i, kk) = ta ? A[i lda + kk] : A[kk lda + i]
 //   B(kk, j) = tb ? B[kk ldb + j] : B[j ldb + kk]
 // With `lower`, entries above the diagonal are not written.  Four waves;
-// wave w owns tile rows 16 w .. 16 w + 15 as four 16 x 16 accumulators;
-// K is staged through LDS 16 at a time.  The whole K range is read before
-// the tile is written, so C may alias the rows of A it covers.
+// wave w owns tile rows 16 w .. 16 w + 15 as four 16 x 16 accumulators.
+// K goes through LDS 32 at a time, the next slice's loads in flight (in
+// registers) while the matrix cores work on the current one.  The whole K
+// range is read before the tile is written, so C may alias the rows of A
+// it covers.
 __device__ __forceinline__ void gemm_tile(int i0, int j0, int M, int N, int kb, int ke,
-                                          double alpha, const double* __restrict__ A, int64_t lda,
-                                          bool ta, const double* __restrict__ B, int64_t ldb,
-                                          bool tb, double beta, double* C, int64_t ldc,
-                                          bool lower, double (*sA)[17], double (*sB)[PT + 1]) {
+                                          double alpha, const double* A, int64_t lda, bool ta,
+                                          const double* B, int64_t ldb, bool tb, double beta,
+                                          double* C, int64_t ldc, bool lower,
+                                          double (*sA)[KS + 1], double (*sB)[PT + 1]) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int cc = lane & 15, kr = lane >> 4;
   d4v acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = d4v{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kb; k0 < ke; k0 += 16) {
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int idx = t + 256 * e;  // 0 .. 2047
+      const int ai = ta ? idx >> 5 : idx & 63, ak = ta ? idx & 31 : idx >> 6;
+      const int gi = i0 + ai, gk = k0 + ak;
+      ra[e] = (gi < M && gk < ke) ? (ta ? A[(int64_t)gi * lda + gk] : A[(int64_t)gk * lda + gi])
+                                  : 0.0;
+      const int bj = tb ? idx & 63 : idx >> 5, bk = tb ? idx >> 6 : idx & 31;
+      const int gj = j0 + bj, gk2 = k0 + bk;
+      rb[e] = (gj < N && gk2 < ke) ? (tb ? B[(int64_t)gk2 * ldb + gj] : B[(int64_t)gj * ldb + gk2])
+                                   : 0.0;
+    }
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += KS) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = t + 256 * e;  // 0 .. 1023
-      const int ai = ta ? idx >> 4 : idx & 63, ak = ta ? idx & 15 : idx >> 6;
-      const int gi = i0 + ai, gk = k0 + ak;
-      double va = 0.0;
-      if (gi < M && gk < ke) va = ta ? A[(int64_t)gi * lda + gk] : A[(int64_t)gk * lda + gi];
-      sA[ai][ak] = va;
-      const int bj = tb ? idx & 63 : idx >> 4, bk = tb ? idx >> 6 : idx & 15;
-      const int gj = j0 + bj, gk2 = k0 + bk;
-      double vb = 0.0;
-      if (gj < N && gk2 < ke) vb = tb ? B[(int64_t)gk2 * ldb + gj] : B[(int64_t)gj * ldb + gk2];
-      sB[bk][bj] = vb;
+    for (int e = 0; e < 8; ++e) {
+      const int idx = t + 256 * e;
+      sA[ta ? idx >> 5 : idx & 63][ta ? idx & 31 : idx >> 6] = ra[e];
+      sB[tb ? idx >> 6 : idx & 31][tb ? idx & 63 : idx >> 5] = rb[e];
     }
     __syncthreads();
+    if (k0 + KS < ke) load(k0 + KS);
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const double a = sA[16 * w + cc][4 * ks + kr];
+    for (int ks = 0; ks < KS / 4; ++ks) {
+      const double av = sA[16 * w + cc][4 * ks + kr];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sB[4 * ks + kr][16 * q + cc], acc[q], 0,
-                                                      0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sB[4 * ks + kr][16 * q + cc], acc[q],
+                                                      0, 0, 0);
     }
   }
 #pragma unroll
@@ -180,67 +193,95 @@ __global__ __launch_bounds__(256) void k_gather(const DFront* __restrict__ fr,
 // *bad.  Otherwise (selected inversion): L_jj^-1 into Li and
 // L_jj^-T L_jj^-1 into Z0.  Li, Z0: 64 x 64 column-major per list slot,
 // identity-padded past the panel width.
+//
+// The tile lives in registers: lane r of wave g holds row r of columns
+// g, g+4, .., g+60 (Cholesky), then column r of rows g, g+4, .. of the
+// inverse (forward elimination).  Each of the 64 steps publishes one
+// column (one row) through a double-buffered LDS vector, so a step costs
+// one barrier, a few LDS broadcasts and 16 fused multiply-adds per lane.
 template <bool FACTOR>
 __global__ __launch_bounds__(256) void k_tile(const DFront* __restrict__ fr,
                                               const int32_t* __restrict__ list, int nf, int jp,
                                               double* ar, double* __restrict__ Li,
                                               double* __restrict__ Z0, int* bad) {
   __shared__ double T[PT][PT + 1], X[PT][PT + 1];
-  const int t = threadIdx.x;
+  __shared__ double buf[2][PT];
+  const int t = threadIdx.x, r = t & 63, g = t >> 6;
   for (int fi = blockIdx.x; fi < nf; fi += gridDim.x) {
     const DFront f = fr[list[fi]];
     const int j0 = PT * jp;
     if (f.k <= j0) continue;
     const int w = min(PT, f.k - j0);
     double* a = ar + f.off + (int64_t)j0 * f.F + j0;
-    __syncthreads();
-    for (int e = t; e < PT * PT; e += 256) {
-      const int c = e >> 6, r = e & 63;
-      T[r][c] = (r < w && c < w) ? (r >= c ? a[(int64_t)c * f.F + r] : 0.0) : (r == c ? 1.0 : 0.0);
+    double v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int cc = g + 4 * j;
+      v[j] = (r < w && cc < w) ? (r >= cc ? a[(int64_t)cc * f.F + r] : 0.0) : (r == cc ? 1.0 : 0.0);
     }
-    __syncthreads();
+    __syncthreads();  // the previous front's LDS reads are done
     if (FACTOR) {
+#pragma unroll
       for (int c = 0; c < PT; ++c) {
-        if (t == 0) {
-          const double piv = T[c][c];
-          if (!(piv > 0.0) || !std::isfinite(piv)) atomicOr(bad, 1);
-          T[c][c] = sqrt(fmax(piv, 1e-300));
+        double* bf = buf[c & 1];
+        if (g == (c & 3)) bf[r] = v[c >> 2];
+        __syncthreads();
+        const double piv = bf[c];
+        if (t == 0 && !(piv > 0.0 && std::isfinite(piv))) atomicOr(bad, 1);
+        const double sq = sqrt(fmax(piv, 1e-300)), inv = 1.0 / sq;
+        const double lr = bf[r] * inv;
+        if (g == (c & 3)) v[c >> 2] = r > c ? lr : (r == c ? sq : 0.0);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int cc = g + 4 * j;
+          if (cc > c && r >= cc) v[j] -= lr * (bf[cc] * inv);
         }
-        __syncthreads();
-        const double dc = T[c][c];
-        for (int r = c + 1 + t; r < PT; r += 256) T[r][c] /= dc;
-        __syncthreads();
-        for (int e = t; e < PT * PT; e += 256) {
-          const int cc = e >> 6, r = e & 63;
-          if (cc > c && r >= cc) T[r][cc] -= T[r][c] * T[cc][c];
-        }
-        __syncthreads();
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int cc = g + 4 * j;
+        if (r < w && cc < w && r >= cc) a[(int64_t)cc * f.F + r] = v[j];
       }
     }
-    // L^-1 by forward substitution, one column per thread
-    if (t < PT) {
-      const int c = t;
-      for (int i = 0; i < PT; ++i) {
-        double v = (i == c) ? 1.0 : 0.0;
-        for (int k = c; k < i; ++k) v -= T[i][k] * X[k][c];
-        X[i][c] = (i < c) ? 0.0 : v / T[i][i];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) T[r][g + 4 * j] = v[j];
+    __syncthreads();
+    // X = L^-1: lane r holds column r of rows g + 4 j
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = (g + 4 * j == r) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      double* bk = buf[k & 1];
+      if (g == (k & 3)) {
+        v[k >> 2] /= T[k][k];
+        bk[r] = v[k >> 2];
+      }
+      __syncthreads();
+      const double xk = bk[r];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int i = g + 4 * j;
+        if (i > k) v[j] -= T[i][k] * xk;
       }
     }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) X[g + 4 * j][r] = v[j];
     __syncthreads();
     double* li = Li + (size_t)fi * PT * PT;
-    for (int e = t; e < PT * PT; e += 256) {
-      const int c = e >> 6, r = e & 63;
-      li[e] = X[r][c];
-      if (FACTOR && r < w && c < w && r >= c) a[(int64_t)c * f.F + r] = T[r][c];
-    }
+    for (int e = t; e < PT * PT; e += 256) li[e] = X[e & 63][e >> 6];
     if (!FACTOR) {
-      double* z0 = Z0 + (size_t)fi * PT * PT;
-      for (int e = t; e < PT * PT; e += 256) {
-        const int c = e >> 6, r = e & 63;
-        double v = 0.0;
-        for (int k = max(r, c); k < PT; ++k) v += X[k][r] * X[k][c];
-        z0[e] = v;
+      // Z0(r, b) = sum_k X(k, r) X(k, b), b = g + 4 j
+      double z[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) z[j] = 0.0;
+      for (int k = 0; k < PT; ++k) {
+        const double xr = X[k][r];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) z[j] += xr * X[k][g + 4 * j];
       }
+      double* z0 = Z0 + (size_t)fi * PT * PT;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) z0[(g + 4 * j) * PT + r] = z[j];
     }
   }
 }
@@ -262,8 +303,10 @@ __global__ __launch_bounds__(256) void k_front_gemm(const DFront* __restrict__ f
                                                     int jp, double* ar,
                                                     const double* __restrict__ Li,
                                                     double* __restrict__ Ybuf,
-                                                    double* __restrict__ part) {
-  __shared__ double sA[PT][17], sB[16][PT + 1];
+                                                    double* __restrict__ part, int tiles,
+                                                    int ysplit, double* __restrict__ Ysp,
+                                                    int64_t ylev) {
+  __shared__ double sA[PT][KS + 1], sB[KS][PT + 1];
   for (int fi = blockIdx.y; fi < nf; fi += gridDim.y) {
     const DFront f = fr[list[fi]];
     const int j0 = PT * jp;
@@ -287,10 +330,20 @@ __global__ __launch_bounds__(256) void k_front_gemm(const DFront* __restrict__ f
       gemm_tile(ti * PT, tj * PT, m, m, 0, w, -1.0, l, F, false, l, F, true, 1.0,
                 base + (int64_t)r0 * F + r0, F, true, sA, sB);
     } else if (OP == OP_Y) {
-      // Y = -Z_RR Lhat
-      if ((int)blockIdx.x >= ntile) continue;
-      gemm_tile(blockIdx.x * PT, 0, m, w, 0, m, -1.0, base + (int64_t)r0 * F + r0, F, false,
-                base + (int64_t)j0 * F + r0, F, false, 0.0, Ybuf + f.ybuf, F, false, sA, sB);
+      // Y = -Z_RR Lhat; with ysplit > 1, the K range in ysplit parts, each
+      // into its own copy of the level's Y buffer (summed by k_ysum)
+      const int tile = (int)blockIdx.x % tiles, sp = (int)blockIdx.x / tiles;
+      if (tile >= ntile) continue;
+      int kb = 0, ke = m;
+      double* y = Ybuf + f.ybuf;
+      if (ysplit > 1) {
+        const int ks = ((m + ysplit - 1) / ysplit + KS - 1) / KS * KS;
+        kb = min(m, sp * ks);
+        ke = min(m, kb + ks);
+        y = Ysp + (size_t)sp * ylev + f.ybuf;
+      }
+      gemm_tile(tile * PT, 0, m, w, kb, ke, -1.0, base + (int64_t)r0 * F + r0, F, false,
+                base + (int64_t)j0 * F + r0, F, false, 0.0, y, F, false, sA, sB);
     } else {
       // partial -Lhat^T Y over split blockIdx.x of the rows R
       if ((int)blockIdx.x >= f.nsplit) continue;
@@ -298,6 +351,29 @@ __global__ __launch_bounds__(256) void k_front_gemm(const DFront* __restrict__ f
       const int kb = min(m, (int)blockIdx.x * ks), ke = min(m, kb + ks);
       gemm_tile(0, 0, w, w, kb, ke, -1.0, base + (int64_t)j0 * F + r0, F, true, Ybuf + f.ybuf, F,
                 false, 0.0, part + f.part + (size_t)blockIdx.x * PT * PT, PT, false, sA, sB);
+    }
+  }
+}
+
+// Y = sum of the ysplit partial products (rows of row tile blockIdx.x).
+__global__ __launch_bounds__(256) void k_ysum(const DFront* __restrict__ fr,
+                                              const int32_t* __restrict__ list, int nf, int jp,
+                                              int ysplit, const double* __restrict__ Ysp,
+                                              int64_t ylev, double* __restrict__ Ybuf) {
+  for (int fi = blockIdx.y; fi < nf; fi += gridDim.y) {
+    const DFront f = fr[list[fi]];
+    const int j0 = PT * jp;
+    if (f.k <= j0) continue;
+    const int w = min(PT, f.k - j0), m = f.F - j0 - w;
+    const int i0 = blockIdx.x * PT;
+    if (i0 >= m) continue;
+    for (int e = threadIdx.x; e < PT * PT; e += 256) {
+      const int c = e >> 6, i = i0 + (e & 63);
+      if (i >= m || c >= w) continue;
+      const int64_t o = f.ybuf + (int64_t)c * f.F + i;
+      double v = 0.0;
+      for (int s = 0; s < ysplit; ++s) v += Ysp[(size_t)s * ylev + o];
+      Ybuf[o] = v;
     }
   }
 }
@@ -395,6 +471,8 @@ struct LevelDev {
   int max_rowtiles = 0;  // over fronts, for panel 0 (the largest m)
   int max_split = 0;
   int64_t ent_off = 0, ent_n = 0;
+  int ysplit = 1;     // K parts of the Y product
+  int64_t ylev = 0;   // doubles of the level's Y buffer
 };
 
 reff_status dev_status(hipError_t e, const char* what) {
@@ -420,9 +498,28 @@ std::shared_ptr<SelinvPlan> selinv_plan_of(reff_pdn_t* p, reff_status& s) {
   return plan;
 }
 
+// Parts the K range of a level's Y products is split into: enough
+// workgroups to fill the chip where a level has few fronts, at least 128
+// rows of K per part, and at most 1 GiB of partial products.
+int level_ysplit(const SelinvPlan& P, const SelinvLevel& L, int64_t yb) {
+  int64_t tiles0 = 0, maxm = 0;
+  for (int32_t i : L.fronts) {
+    const SnFront& f = P.fronts[(size_t)i];
+    if (f.k == 0) continue;
+    const int64_t m0 = f.F - std::min(PT, f.k);
+    tiles0 += (m0 + PT - 1) / PT;
+    maxm = std::max(maxm, m0);
+  }
+  if (tiles0 == 0) return 1;
+  int64_t s = std::min<int64_t>((2048 + tiles0 - 1) / tiles0, 16);
+  s = std::min<int64_t>(s, std::max<int64_t>(1, maxm / 128));
+  while (s > 1 && s * yb > ((int64_t)1 << 27)) --s;
+  return (int)std::max<int64_t>(1, s);
+}
+
 // Scratch sizes of a plan on the device, in doubles / bytes.
 struct SelinvSizes {
-  int64_t tiles = 0, ybuf = 0, part = 0;
+  int64_t tiles = 0, ybuf = 0, part = 0, ysp = 0;
   int64_t bytes = 0;
 };
 
@@ -438,10 +535,12 @@ SelinvSizes selinv_sizes(const SelinvPlan& P) {
     z.tiles = std::max<int64_t>(z.tiles, (int64_t)L.fronts.size() * PT * PT);
     z.ybuf = std::max(z.ybuf, yb);
     z.part = std::max(z.part, pa);
+    const int ys = level_ysplit(P, L, yb);
+    if (ys > 1) z.ysp = std::max(z.ysp, ys * yb);
   }
   int64_t ent = 0;
   for (const SelinvLevel& L : P.levels) ent += (int64_t)L.ent_idx.size();
-  z.bytes = 8 * (P.arena + 2 * z.tiles + z.ybuf + z.part + P.n) + 16 * ent +
+  z.bytes = 8 * (P.arena + 2 * z.tiles + z.ybuf + z.part + z.ysp + P.n) + 16 * ent +
             (int64_t)sizeof(DFront) * (int64_t)P.fronts.size() + 4 * (int64_t)P.rel.size() +
             8 * (int64_t)P.piv_node.size();
   return z;
@@ -534,11 +633,13 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
       D.max_rowtiles = std::max(D.max_rowtiles, (m0 + PT - 1) / PT);
       D.max_split = std::max(D.max_split, g.nsplit);
     }
+    D.ylev = yb;
+    D.ysplit = level_ysplit(P, L, yb);
   }
 
   Bufs b;
   double *ar = nullptr, *Li = nullptr, *Z0 = nullptr, *Yb = nullptr, *part = nullptr;
-  double *Rfull = nullptr, *vals = nullptr, *dout = nullptr;
+  double *Rfull = nullptr, *vals = nullptr, *dout = nullptr, *Ysp = nullptr;
   int64_t *idx = nullptr, *piv = nullptr, *dnodes = nullptr;
   int32_t *rel = nullptr, *dl = nullptr;
   DFront* dF = nullptr;
@@ -548,6 +649,7 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
   if (e == hipSuccess) e = b.get(&Z0, (size_t)sz.tiles);
   if (e == hipSuccess) e = b.get(&Yb, (size_t)sz.ybuf);
   if (e == hipSuccess) e = b.get(&part, (size_t)sz.part);
+  if (e == hipSuccess) e = b.get(&Ysp, (size_t)sz.ysp);
   if (e == hipSuccess) e = b.get(&Rfull, (size_t)P.n);
   if (e == hipSuccess) e = b.get(&bad, 1);
   if (e == hipSuccess) e = put(b, &idx, ent_idx, st_);
@@ -602,9 +704,10 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
       }
       if (mt == 0) continue;
       hipLaunchKernelGGL(k_front_gemm<OP_TRSM>, dim3((unsigned)mt, gy(D.nf)), dim3(256), 0, st_,
-                         dF, l, D.nf, jp, ar, Li, Yb, part);
+                         dF, l, D.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
       hipLaunchKernelGGL(k_front_gemm<OP_SYRK>, dim3((unsigned)(mt * (mt + 1) / 2), gy(D.nf)),
-                         dim3(256), 0, st_, dF, l, D.nf, jp, ar, Li, Yb, part);
+                         dim3(256), 0, st_, dF, l, D.nf, jp, ar, Li, Yb, part, mt, 1, Ysp,
+                         (int64_t)0);
     }
     e = hipGetLastError();
   }
@@ -642,11 +745,15 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
                          Li, Z0, bad);
       if (mt > 0) {
         hipLaunchKernelGGL(k_front_gemm<OP_LHAT>, dim3((unsigned)mt, gy(D.nf)), dim3(256), 0,
-                           st_, dF, l, D.nf, jp, ar, Li, Yb, part);
-        hipLaunchKernelGGL(k_front_gemm<OP_Y>, dim3((unsigned)mt, gy(D.nf)), dim3(256), 0, st_,
-                           dF, l, D.nf, jp, ar, Li, Yb, part);
+                           st_, dF, l, D.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
+        hipLaunchKernelGGL(k_front_gemm<OP_Y>, dim3((unsigned)(mt * D.ysplit), gy(D.nf)),
+                           dim3(256), 0, st_, dF, l, D.nf, jp, ar, Li, Yb, part, mt, D.ysplit,
+                           Ysp, D.ylev);
+        if (D.ysplit > 1)
+          hipLaunchKernelGGL(k_ysum, dim3((unsigned)mt, gy(D.nf)), dim3(256), 0, st_, dF, l,
+                             D.nf, jp, D.ysplit, (const double*)Ysp, D.ylev, Yb);
         hipLaunchKernelGGL(k_front_gemm<OP_PART>, dim3((unsigned)ms, gy(D.nf)), dim3(256), 0,
-                           st_, dF, l, D.nf, jp, ar, Li, Yb, part);
+                           st_, dF, l, D.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
       }
       hipLaunchKernelGGL(k_finish, dim3((unsigned)(1 + mt), gy(D.nf)), dim3(256), 0, st_, dF, l,
                          D.nf, jp, ar, Z0, Yb, part, piv, Rfull);
