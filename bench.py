@@ -590,6 +590,42 @@ def surrogate_scale_run(reff, gen, log, n_train=4000, labels=1024, epochs=24, n_
     return rec
 
 
+def stream_probe_run(gib=1, reps=5):
+    """HBM bandwidth of plain streaming kernels (reff_stream_probe), the
+    practical ceiling for the bandwidth-bound kernels: per kind, the best
+    over grid sizes of the median of `reps` launches timed with events on
+    the launch stream.  Bytes counted = bytes read + bytes written."""
+    import numpy as np
+    import torch
+    from paper_2607_05818_amd import reff
+    nb = gib << 30
+    src = torch.ones(3 * nb // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty(2 * nb // 4, dtype=torch.float32, device="cuda:0")
+    moved = {0: 2 * nb, 1: nb, 2: nb, 3: 5 * nb, 4: 2 * nb}
+    names = {0: "copy", 1: "read", 2: "write", 3: "read3_write2", 4: "copy_nontemporal"}
+    stream = torch.cuda.current_stream()
+    out = {"bytes_per_array": nb, "peak_GBps": HBM_PEAK_GBS}
+    for kind in range(5):
+        best = None
+        for blocks in (1024, 2048, 4096, 8192, 16384, 32768):
+            ts = []
+            for r in range(reps + 2):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                reff.reff_stream_probe(kind, src, dst, nb, blocks, stream.cuda_stream)
+                b.record(stream)
+                b.synchronize()
+                if r >= 2:
+                    ts.append(a.elapsed_time(b) * 1e-3)
+            gbps = moved[kind] / float(np.median(ts)) / 1e9
+            if best is None or gbps > best["GBps"]:
+                best = {"GBps": gbps, "blocks": blocks, "frac_of_peak": gbps / HBM_PEAK_GBS}
+        out[names[kind]] = best
+        print(f"[bench] probe {names[kind]}: {best['GBps']:.0f} GB/s ({best['frac_of_peak']:.3f} "
+              f"of peak) at {best['blocks']} workgroups", file=sys.stderr, flush=True)
+    return out
+
+
 def large_run(args, reff, gen, log):
     """The large stack (8 tiers of 2048 x 2048, 33,554,432 nodes): a full
     map is out of reach on one GPU, so the first `large_blocks` 64-node
@@ -715,6 +751,9 @@ def main():
     ap.add_argument("--direct-only", action="store_true",
                     help="only the sparse-direct all-node map of the 4 x 512 x 512 stack "
                          "(reff_selinv_diag); prints that leg's record")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only the HBM bandwidth probes (copy, read, write, 3-read/2-write, "
+                         "non-temporal copy) over grid sizes; prints one JSON record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy kernel 4 times (the "
                          "reference point for HBM byte counters)")
@@ -729,6 +768,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes,
                           "launches": 4}), flush=True)
+        return
+    if args.stream_probe:
+        print(json.dumps(stream_probe_run()), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "

@@ -196,8 +196,10 @@ typedef struct {
  * The definition itself, to float64 rounding: there is no tolerance and no
  * iteration.  The cost does not depend on how many nodes are asked for, so
  * it is the method for full maps; block PCG (reff_solve_diag) is the method
- * for samples.  The plan (ordering and front structure) is built on the
- * handle's first use and kept with it.
+ * for samples.  The plan (ordering and front structure), its device tables
+ * and the work buffers (reff_selinv_info().device_bytes) are set up on the
+ * handle's first call and kept with it until reff_free_pdn; calls on one
+ * handle must not overlap.
  *   nodes, n_nodes, R_out   as reff_solve_diag (pads give 0.0).
  *   opts     NULL => defaults; only stream and out_on_device are read.
  *   st       nullable.
@@ -213,6 +215,23 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes,
  * needed): fronts, levels, largest front, device bytes and flop counts.
  * Errors: INVALID_ARG (as reff_build_pdn's validation). */
 reff_status reff_selinv_info(const reff_pdn_desc* d, reff_selinv_stats* info);
+
+/*
+ * HBM bandwidth probe (a measurement helper; no part of any result): one
+ * launch of a plain streaming kernel with 16-byte accesses, `blocks`
+ * workgroups of 256 threads walking the data grid-stride, on `stream`.
+ *   kind 0  copy src -> dst (bytes each)
+ *        1  read src; dst receives blocks x 256 floats (partial sums)
+ *        2  write dst
+ *        3  read three arrays, write two (the Chebyshev pass's mix): src
+ *           holds 3 x bytes, dst 2 x bytes, element-wise sums
+ *        4  copy with non-temporal loads and stores
+ * src, dst: device pointers.  bytes: per array, a positive multiple of 16.
+ * Errors: INVALID_ARG, DEVICE (launch error).  Asynchronous: time it with
+ * events on `stream`.
+ */
+reff_status reff_stream_probe(int32_t kind, const void* src, void* dst, int64_t bytes,
+                              int32_t blocks, void* stream);
 
 typedef enum {
   REFF_PAIRS_GROUNDED = 0, /* pads merged into the grounded supply:

@@ -13,7 +13,8 @@
 
 namespace reff {
 
-struct SelinvPlan;  // selinv_plan.h
+struct SelinvPlan;    // selinv_plan.h
+struct SelinvDevice;  // selinv.hip
 
 // Set the calling thread's reff_last_error() text and return s.
 reff_status host_fail(reff_status s, const std::string& msg);
@@ -173,6 +174,7 @@ struct reff_pdn_t {
   reff::Workspace ws;         // solver work arrays (grown on demand)
   std::vector<void*> extra;  // coefficient allocations freed with the handle
   std::shared_ptr<reff::SelinvPlan> sel_plan;  // sparse-direct plan, built on first use
+  std::shared_ptr<reff::SelinvDevice> sel_dev;  // its device tables and work buffers
 };
 
 namespace reff {

@@ -1877,7 +1877,9 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
         const T z = cheb_node_t(z2h[1][i], h3[hs][jc + 2][lane], h3[hs][jc][lane], z2n[i],
                                 z2h[0][i], t3[i], A[0], A[2], B[0], A[3], B[1], z1h[0][i], rC[i],
                                 A[1], c1, c2);
-        *(T*)(ob + ((uint32_t)(s * nx + jc) * (uint32_t)(S * sizeof(T)) + lane4)) = z;
+        // non-temporal: the iterates are streamed back by the next pass
+        __builtin_nontemporal_store(
+            z, (T*)(ob + ((uint32_t)(s * nx + jc) * (uint32_t)(S * sizeof(T)) + lane4)));
       }
     }
     // [F] the east / west z_j row y + 3 and the coefficients of row y + 3
@@ -1910,8 +1912,9 @@ __global__ __launch_bounds__(WG3, 4) void k_cheb3_strip(Coef<float> c, Work wk,
       char* oa = (char*)(outa + r0off);
 #pragma unroll
       for (int i = 0; i < NPW; ++i)
-        *(T*)(oa + ((uint32_t)((s + 1) * nx + ccol(i)) * (uint32_t)(S * sizeof(T)) + lane4)) =
-            z2n[i];
+        __builtin_nontemporal_store(
+            z2n[i],
+            (T*)(oa + ((uint32_t)((s + 1) * nx + ccol(i)) * (uint32_t)(S * sizeof(T)) + lane4)));
     }
     __syncthreads();
   };

@@ -196,7 +196,8 @@ __global__ __launch_bounds__(256) void k_gather(const DFront* __restrict__ fr,
 //
 // The tile lives in registers: lane r of wave g holds row r of columns
 // g, g+4, .., g+60 (Cholesky), then column r of rows g, g+4, .. of the
-// inverse (forward elimination).  Each of the 64 steps publishes one
+// inverse (forward elimination); one LDS tile holds L for the elimination
+// and then the inverse.  Each of the 64 steps publishes one
 // column (one row) through a double-buffered LDS vector, so a step costs
 // one barrier, a few LDS broadcasts and 16 fused multiply-adds per lane.
 template <bool FACTOR>
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(256) void k_tile(const DFront* __restrict__ fr,
                                               const int32_t* __restrict__ list, int nf, int jp,
                                               double* ar, double* __restrict__ Li,
                                               double* __restrict__ Z0, int* bad) {
-  __shared__ double T[PT][PT + 1], X[PT][PT + 1];
+  __shared__ double T[PT][PT + 1];  // the tile, then its inverse
   __shared__ double buf[2][PT];
   const int t = threadIdx.x, r = t & 63, g = t >> 6;
   for (int fi = blockIdx.x; fi < nf; fi += gridDim.x) {
@@ -264,20 +265,21 @@ __global__ __launch_bounds__(256) void k_tile(const DFront* __restrict__ fr,
         if (i > k) v[j] -= T[i][k] * xk;
       }
     }
+    __syncthreads();  // every step's reads of L are done
 #pragma unroll
-    for (int j = 0; j < 16; ++j) X[g + 4 * j][r] = v[j];
+    for (int j = 0; j < 16; ++j) T[g + 4 * j][r] = v[j];
     __syncthreads();
     double* li = Li + (size_t)fi * PT * PT;
-    for (int e = t; e < PT * PT; e += 256) li[e] = X[e & 63][e >> 6];
+    for (int e = t; e < PT * PT; e += 256) li[e] = T[e & 63][e >> 6];
     if (!FACTOR) {
       // Z0(r, b) = sum_k X(k, r) X(k, b), b = g + 4 j
       double z[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) z[j] = 0.0;
       for (int k = 0; k < PT; ++k) {
-        const double xr = X[k][r];
+        const double xr = T[k][r];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) z[j] += xr * X[k][g + 4 * j];
+        for (int j = 0; j < 16; ++j) z[j] += xr * T[k][g + 4 * j];
       }
       double* z0 = Z0 + (size_t)fi * PT * PT;
 #pragma unroll
@@ -468,11 +470,11 @@ struct LevelDev {
   int64_t list_off = 0;
   int nf = 0;
   int max_panels = 0;
-  int max_rowtiles = 0;  // over fronts, for panel 0 (the largest m)
-  int max_split = 0;
   int64_t ent_off = 0, ent_n = 0;
   int ysplit = 1;     // K parts of the Y product
   int64_t ylev = 0;   // doubles of the level's Y buffer
+  int64_t maxq = 0;   // largest update set of the level
+  std::vector<int> mt, ms;  // per panel: row tiles after it, K parts of its partials
 };
 
 reff_status dev_status(hipError_t e, const char* what) {
@@ -546,6 +548,112 @@ SelinvSizes selinv_sizes(const SelinvPlan& P) {
   return z;
 }
 
+// Device state of a handle's plan: the uploaded tables and every work
+// buffer, allocated on the first call and kept with the handle.
+struct SelinvDevice {
+  std::vector<LevelDev> lv;
+  SelinvSizes sz;
+  double *ar = nullptr, *Li = nullptr, *Z0 = nullptr, *Yb = nullptr, *part = nullptr;
+  double *Ysp = nullptr, *Rfull = nullptr, *vals = nullptr;
+  int64_t *idx = nullptr, *piv = nullptr;
+  int32_t *rel = nullptr, *dl = nullptr;
+  DFront* dF = nullptr;
+  int* bad = nullptr;
+  std::vector<void*> ptrs;
+  ~SelinvDevice() {
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+  template <typename T>
+  hipError_t get(T** out, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back(q);
+    *out = (T*)q;
+    return e;
+  }
+  template <typename T>
+  hipError_t put(T** out, const std::vector<T>& v) {
+    hipError_t e = get(out, v.size());
+    if (e == hipSuccess && !v.empty())
+      e = hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+  }
+};
+
+std::shared_ptr<SelinvDevice> selinv_device_of(reff_pdn_t* p, const SelinvPlan& P,
+                                               reff_status& s) {
+  s = REFF_OK;
+  if (p->sel_dev) return p->sel_dev;
+  auto D = std::make_shared<SelinvDevice>();
+  std::vector<DFront> dfr(P.fronts.size());
+  std::vector<int32_t> lists;
+  std::vector<int64_t> ent_idx;
+  std::vector<double> ent_val;
+  D->sz = selinv_sizes(P);
+  D->lv.resize(P.levels.size());
+  for (size_t d = 0; d < P.levels.size(); ++d) {
+    const SelinvLevel& L = P.levels[d];
+    LevelDev& V = D->lv[d];
+    V.list_off = (int64_t)lists.size();
+    V.nf = (int)L.fronts.size();
+    V.max_panels = L.max_panels;
+    V.ent_off = (int64_t)ent_idx.size();
+    V.ent_n = (int64_t)L.ent_idx.size();
+    ent_idx.insert(ent_idx.end(), L.ent_idx.begin(), L.ent_idx.end());
+    ent_val.insert(ent_val.end(), L.ent_val.begin(), L.ent_val.end());
+    V.mt.assign((size_t)V.max_panels, 0);
+    V.ms.assign((size_t)V.max_panels, 0);
+    int64_t yb = 0, pa = 0;
+    for (int32_t i : L.fronts) {
+      const SnFront& f = P.fronts[(size_t)i];
+      DFront& g = dfr[(size_t)i];
+      g.off = f.off;
+      g.poff = f.parent >= 0 ? P.fronts[(size_t)f.parent].off : -1;
+      g.rel = f.rel;
+      g.piv = f.piv;
+      g.F = f.F;
+      g.k = f.k;
+      g.pF = f.parent >= 0 ? P.fronts[(size_t)f.parent].F : 0;
+      g.rank = f.rank;
+      g.nsplit = std::min(16, std::max(1, (f.F + 255) / 256));
+      g.pad_ = 0;
+      g.ybuf = yb;
+      g.part = pa;
+      yb += (int64_t)f.F * PT;
+      pa += (int64_t)g.nsplit * PT * PT;
+      lists.push_back(i);
+      V.maxq = std::max<int64_t>(V.maxq, (int64_t)(f.F - f.k));
+      for (int jp = 0; PT * jp < f.k; ++jp) {
+        const int m = f.F - PT * jp - std::min(PT, f.k - PT * jp);
+        V.mt[(size_t)jp] = std::max(V.mt[(size_t)jp], (m + PT - 1) / PT);
+        V.ms[(size_t)jp] = std::max(V.ms[(size_t)jp], g.nsplit);
+      }
+    }
+    V.ylev = yb;
+    V.ysplit = level_ysplit(P, L, yb);
+  }
+  hipError_t e = D->get(&D->ar, (size_t)P.arena);
+  if (e == hipSuccess) e = D->get(&D->Li, (size_t)D->sz.tiles);
+  if (e == hipSuccess) e = D->get(&D->Z0, (size_t)D->sz.tiles);
+  if (e == hipSuccess) e = D->get(&D->Yb, (size_t)D->sz.ybuf);
+  if (e == hipSuccess) e = D->get(&D->part, (size_t)D->sz.part);
+  if (e == hipSuccess) e = D->get(&D->Ysp, (size_t)D->sz.ysp);
+  if (e == hipSuccess) e = D->get(&D->Rfull, (size_t)P.n);
+  if (e == hipSuccess) e = D->get(&D->bad, 1);
+  if (e == hipSuccess) e = D->put(&D->idx, ent_idx);
+  if (e == hipSuccess) e = D->put(&D->vals, ent_val);
+  if (e == hipSuccess) e = D->put(&D->piv, P.piv_node);
+  if (e == hipSuccess) e = D->put(&D->rel, P.rel);
+  if (e == hipSuccess) e = D->put(&D->dl, lists);
+  if (e == hipSuccess) e = D->put(&D->dF, dfr);
+  if (e != hipSuccess) {
+    s = dev_status(e, "selected inversion: allocation / upload");
+    return nullptr;
+  }
+  p->sel_dev = D;
+  return D;
+}
+
 }  // namespace reff
 
 extern "C" {
@@ -593,79 +701,25 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
   const SelinvPlan& P = *plan_sp;
   const auto t_plan = std::chrono::steady_clock::now();
 
-  // host tables
-  std::vector<DFront> dfr(P.fronts.size());
-  std::vector<int32_t> lists;
-  std::vector<LevelDev> lv(P.levels.size());
-  std::vector<int64_t> ent_idx;
-  std::vector<double> ent_val;
-  const SelinvSizes sz = selinv_sizes(P);
-  for (size_t d = 0; d < P.levels.size(); ++d) {
-    const SelinvLevel& L = P.levels[d];
-    LevelDev& D = lv[d];
-    D.list_off = (int64_t)lists.size();
-    D.nf = (int)L.fronts.size();
-    D.max_panels = L.max_panels;
-    D.ent_off = (int64_t)ent_idx.size();
-    D.ent_n = (int64_t)L.ent_idx.size();
-    ent_idx.insert(ent_idx.end(), L.ent_idx.begin(), L.ent_idx.end());
-    ent_val.insert(ent_val.end(), L.ent_val.begin(), L.ent_val.end());
-    int64_t yb = 0, pa = 0;
-    for (int32_t i : L.fronts) {
-      const SnFront& f = P.fronts[(size_t)i];
-      DFront& g = dfr[(size_t)i];
-      g.off = f.off;
-      g.poff = f.parent >= 0 ? P.fronts[(size_t)f.parent].off : -1;
-      g.rel = f.rel;
-      g.piv = f.piv;
-      g.F = f.F;
-      g.k = f.k;
-      g.pF = f.parent >= 0 ? P.fronts[(size_t)f.parent].F : 0;
-      g.rank = f.rank;
-      g.nsplit = std::min(16, std::max(1, (f.F + 255) / 256));
-      g.pad_ = 0;
-      g.ybuf = yb;
-      g.part = pa;
-      yb += (int64_t)f.F * PT;
-      pa += (int64_t)g.nsplit * PT * PT;
-      lists.push_back(i);
-      const int m0 = f.F - std::min(PT, f.k);
-      D.max_rowtiles = std::max(D.max_rowtiles, (m0 + PT - 1) / PT);
-      D.max_split = std::max(D.max_split, g.nsplit);
-    }
-    D.ylev = yb;
-    D.ysplit = level_ysplit(P, L, yb);
-  }
-
+  auto dev_sp = selinv_device_of(p, P, s);
+  if (!dev_sp) return s;
+  const SelinvDevice& D = *dev_sp;
+  double *ar = D.ar, *Li = D.Li, *Z0 = D.Z0, *Yb = D.Yb, *part = D.part, *Ysp = D.Ysp;
+  double* Rfull = D.Rfull;
+  const int32_t *rel = D.rel, *dl = D.dl;
+  const DFront* dF = D.dF;
+  int* bad = D.bad;
   Bufs b;
-  double *ar = nullptr, *Li = nullptr, *Z0 = nullptr, *Yb = nullptr, *part = nullptr;
-  double *Rfull = nullptr, *vals = nullptr, *dout = nullptr, *Ysp = nullptr;
-  int64_t *idx = nullptr, *piv = nullptr, *dnodes = nullptr;
-  int32_t *rel = nullptr, *dl = nullptr;
-  DFront* dF = nullptr;
-  int* bad = nullptr;
-  e = b.get(&ar, (size_t)P.arena);
-  if (e == hipSuccess) e = b.get(&Li, (size_t)sz.tiles);
-  if (e == hipSuccess) e = b.get(&Z0, (size_t)sz.tiles);
-  if (e == hipSuccess) e = b.get(&Yb, (size_t)sz.ybuf);
-  if (e == hipSuccess) e = b.get(&part, (size_t)sz.part);
-  if (e == hipSuccess) e = b.get(&Ysp, (size_t)sz.ysp);
-  if (e == hipSuccess) e = b.get(&Rfull, (size_t)P.n);
-  if (e == hipSuccess) e = b.get(&bad, 1);
-  if (e == hipSuccess) e = put(b, &idx, ent_idx, st_);
-  if (e == hipSuccess) e = put(b, &vals, ent_val, st_);
-  if (e == hipSuccess) e = put(b, &piv, P.piv_node, st_);
-  if (e == hipSuccess) e = put(b, &rel, P.rel, st_);
-  if (e == hipSuccess) e = put(b, &dl, lists, st_);
-  if (e == hipSuccess) e = put(b, &dF, dfr, st_);
-  if (e == hipSuccess && nodes && count > 0) {
+  double* dout = nullptr;
+  int64_t* dnodes = nullptr;
+  if (nodes && count > 0) {
     std::vector<int64_t> nv(nodes, nodes + count);
     e = put(b, &dnodes, nv, st_);
     // the staged host vector must outlive the copy
     if (e == hipSuccess) e = hipStreamSynchronize(st_);
   }
   if (e == hipSuccess && !out_dev && count > 0) e = b.get(&dout, (size_t)count);
-  if (e != hipSuccess) return dev_status(e, "selected inversion: allocation / upload");
+  if (e != hipSuccess) return dev_status(e, "selected inversion: output buffers");
   hipLaunchKernelGGL(k_zero, flat(P.n), dim3(256), 0, st_, Rfull, P.n);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), st_);
@@ -675,38 +729,31 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
   // factorisation, deepest level first
   for (int d = nlev - 1; d >= 0 && e == hipSuccess; --d) {
     const SelinvLevel& L = P.levels[(size_t)d];
-    const LevelDev& D = lv[(size_t)d];
-    const int32_t* l = dl + D.list_off;
-    if (D.nf == 0) continue;
+    const LevelDev& V = D.lv[(size_t)d];
+    const int32_t* l = dl + V.list_off;
+    if (V.nf == 0) continue;
     const int64_t span = L.arena_end - L.arena_begin;
     if (span > 0) hipLaunchKernelGGL(k_zero, flat(span), dim3(256), 0, st_, ar + L.arena_begin, span);
-    if (D.ent_n > 0)
-      hipLaunchKernelGGL(k_scatter, flat(D.ent_n), dim3(256), 0, st_, idx + D.ent_off,
-                         vals + D.ent_off, D.ent_n, ar);
-    if (d + 1 < nlev && lv[(size_t)d + 1].nf > 0) {
-      const LevelDev& C = lv[(size_t)d + 1];
-      int64_t maxq = 0;
-      for (int32_t i : P.levels[(size_t)d + 1].fronts)
-        maxq = std::max<int64_t>(maxq, (int64_t)(P.fronts[(size_t)i].F - P.fronts[(size_t)i].k));
-      const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((maxq * maxq + 255) / 256, 1024));
+    if (V.ent_n > 0)
+      hipLaunchKernelGGL(k_scatter, flat(V.ent_n), dim3(256), 0, st_, D.idx + V.ent_off,
+                         D.vals + V.ent_off, V.ent_n, ar);
+    if (d + 1 < nlev && D.lv[(size_t)d + 1].nf > 0) {
+      const LevelDev& C = D.lv[(size_t)d + 1];
+      const unsigned gx = (unsigned)std::max<int64_t>(
+          1, std::min<int64_t>((C.maxq * C.maxq + 255) / 256, 1024));
       for (int rank = 0; rank < 2; ++rank)
         hipLaunchKernelGGL(k_extend_add, dim3(gx, gy(C.nf)), dim3(256), 0, st_, dF,
                            dl + C.list_off, C.nf, rank, rel, ar);
     }
-    for (int jp = 0; jp < D.max_panels; ++jp) {
-      hipLaunchKernelGGL(k_tile<true>, dim3(gy(D.nf)), dim3(256), 0, st_, dF, l, D.nf, jp, ar,
+    for (int jp = 0; jp < V.max_panels; ++jp) {
+      hipLaunchKernelGGL(k_tile<true>, dim3(gy(V.nf)), dim3(256), 0, st_, dF, l, V.nf, jp, ar,
                          Li, Z0, bad);
-      // rows after this panel in the largest front of the level
-      int mt = 0;
-      for (int32_t i : L.fronts) {
-        const SnFront& f = P.fronts[(size_t)i];
-        if (f.k > PT * jp) mt = std::max(mt, (f.F - PT * jp - std::min(PT, f.k - PT * jp) + PT - 1) / PT);
-      }
+      const int mt = V.mt[(size_t)jp];
       if (mt == 0) continue;
-      hipLaunchKernelGGL(k_front_gemm<OP_TRSM>, dim3((unsigned)mt, gy(D.nf)), dim3(256), 0, st_,
-                         dF, l, D.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
-      hipLaunchKernelGGL(k_front_gemm<OP_SYRK>, dim3((unsigned)(mt * (mt + 1) / 2), gy(D.nf)),
-                         dim3(256), 0, st_, dF, l, D.nf, jp, ar, Li, Yb, part, mt, 1, Ysp,
+      hipLaunchKernelGGL(k_front_gemm<OP_TRSM>, dim3((unsigned)mt, gy(V.nf)), dim3(256), 0, st_,
+                         dF, l, V.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
+      hipLaunchKernelGGL(k_front_gemm<OP_SYRK>, dim3((unsigned)(mt * (mt + 1) / 2), gy(V.nf)),
+                         dim3(256), 0, st_, dF, l, V.nf, jp, ar, Li, Yb, part, mt, 1, Ysp,
                          (int64_t)0);
     }
     e = hipGetLastError();
@@ -719,44 +766,31 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
   const auto t_fact = std::chrono::steady_clock::now();
   // selected inversion, roots first
   for (int d = 0; d < nlev && e == hipSuccess; ++d) {
-    const SelinvLevel& L = P.levels[(size_t)d];
-    const LevelDev& D = lv[(size_t)d];
-    const int32_t* l = dl + D.list_off;
-    if (D.nf == 0) continue;
-    if (d > 0) {
-      int64_t maxq = 0;
-      for (int32_t i : L.fronts)
-        maxq = std::max<int64_t>(maxq, (int64_t)(P.fronts[(size_t)i].F - P.fronts[(size_t)i].k));
-      if (maxq > 0) {
-        const unsigned gx = (unsigned)std::min<int64_t>((maxq * maxq + 255) / 256, 1024);
-        hipLaunchKernelGGL(k_gather, dim3(gx, gy(D.nf)), dim3(256), 0, st_, dF, l, D.nf, rel, ar);
-      }
+    const LevelDev& V = D.lv[(size_t)d];
+    const int32_t* l = dl + V.list_off;
+    if (V.nf == 0) continue;
+    if (d > 0 && V.maxq > 0) {
+      const unsigned gx = (unsigned)std::min<int64_t>((V.maxq * V.maxq + 255) / 256, 1024);
+      hipLaunchKernelGGL(k_gather, dim3(gx, gy(V.nf)), dim3(256), 0, st_, dF, l, V.nf, rel, ar);
     }
-    for (int jp = D.max_panels - 1; jp >= 0; --jp) {
-      int mt = 0, ms = 0;
-      for (int32_t i : L.fronts) {
-        const SnFront& f = P.fronts[(size_t)i];
-        if (f.k > PT * jp) {
-          mt = std::max(mt, (f.F - PT * jp - std::min(PT, f.k - PT * jp) + PT - 1) / PT);
-          ms = std::max(ms, dfr[(size_t)i].nsplit);
-        }
-      }
-      hipLaunchKernelGGL(k_tile<false>, dim3(gy(D.nf)), dim3(256), 0, st_, dF, l, D.nf, jp, ar,
+    for (int jp = V.max_panels - 1; jp >= 0; --jp) {
+      const int mt = V.mt[(size_t)jp], ms = V.ms[(size_t)jp];
+      hipLaunchKernelGGL(k_tile<false>, dim3(gy(V.nf)), dim3(256), 0, st_, dF, l, V.nf, jp, ar,
                          Li, Z0, bad);
       if (mt > 0) {
-        hipLaunchKernelGGL(k_front_gemm<OP_LHAT>, dim3((unsigned)mt, gy(D.nf)), dim3(256), 0,
-                           st_, dF, l, D.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
-        hipLaunchKernelGGL(k_front_gemm<OP_Y>, dim3((unsigned)(mt * D.ysplit), gy(D.nf)),
-                           dim3(256), 0, st_, dF, l, D.nf, jp, ar, Li, Yb, part, mt, D.ysplit,
-                           Ysp, D.ylev);
-        if (D.ysplit > 1)
-          hipLaunchKernelGGL(k_ysum, dim3((unsigned)mt, gy(D.nf)), dim3(256), 0, st_, dF, l,
-                             D.nf, jp, D.ysplit, (const double*)Ysp, D.ylev, Yb);
-        hipLaunchKernelGGL(k_front_gemm<OP_PART>, dim3((unsigned)ms, gy(D.nf)), dim3(256), 0,
-                           st_, dF, l, D.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
+        hipLaunchKernelGGL(k_front_gemm<OP_LHAT>, dim3((unsigned)mt, gy(V.nf)), dim3(256), 0,
+                           st_, dF, l, V.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
+        hipLaunchKernelGGL(k_front_gemm<OP_Y>, dim3((unsigned)(mt * V.ysplit), gy(V.nf)),
+                           dim3(256), 0, st_, dF, l, V.nf, jp, ar, Li, Yb, part, mt, V.ysplit,
+                           Ysp, V.ylev);
+        if (V.ysplit > 1)
+          hipLaunchKernelGGL(k_ysum, dim3((unsigned)mt, gy(V.nf)), dim3(256), 0, st_, dF, l,
+                             V.nf, jp, V.ysplit, (const double*)Ysp, V.ylev, Yb);
+        hipLaunchKernelGGL(k_front_gemm<OP_PART>, dim3((unsigned)ms, gy(V.nf)), dim3(256), 0,
+                           st_, dF, l, V.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
       }
-      hipLaunchKernelGGL(k_finish, dim3((unsigned)(1 + mt), gy(D.nf)), dim3(256), 0, st_, dF, l,
-                         D.nf, jp, ar, Z0, Yb, part, piv, Rfull);
+      hipLaunchKernelGGL(k_finish, dim3((unsigned)(1 + mt), gy(V.nf)), dim3(256), 0, st_, dF, l,
+                         V.nf, jp, ar, Z0, Yb, part, D.piv, Rfull);
     }
     e = hipGetLastError();
   }
@@ -780,7 +814,7 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
     st->n_fronts = (int64_t)P.fronts.size();
     st->n_levels = (int32_t)P.levels.size();
     for (const SnFront& f : P.fronts) st->max_front = std::max<int64_t>(st->max_front, f.F);
-    st->device_bytes = sz.bytes;
+    st->device_bytes = D.sz.bytes;
     st->flops_factor = P.flops_factor;
     st->flops_selinv = P.flops_selinv;
     st->seconds = std::chrono::duration<double>(t1 - t0).count();

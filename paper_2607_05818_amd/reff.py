@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libreff.so")
+# REFF_LIBRARY names another build of the library (A/B timing of variants)
+LIB_PATH = os.environ.get("REFF_LIBRARY") or os.path.join(_HERE, "libreff.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -145,6 +146,9 @@ _lib.reff_selinv_diag.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
 _lib.reff_selinv_diag.restype = C.c_int
 _lib.reff_selinv_info.argtypes = [C.POINTER(reff_pdn_desc), C.POINTER(reff_selinv_stats)]
 _lib.reff_selinv_info.restype = C.c_int
+_lib.reff_stream_probe.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                                   C.c_void_p]
+_lib.reff_stream_probe.restype = C.c_int
 _lib.reff_status_string.argtypes = [C.c_int]
 _lib.reff_status_string.restype = C.c_char_p
 _lib.reff_last_error.argtypes = []
@@ -310,6 +314,17 @@ def reff_selinv_diag(pdn: PDN, nodes=None, R_out=None, *, stream=None):
     _check(_lib.reff_selinv_diag(pdn.handle, nptr, count if nodes is not None else 0, optr,
                                  C.byref(o), C.byref(st)))
     return R_out, st.as_dict()
+
+
+def reff_stream_probe(kind, src, dst, nbytes, blocks, stream=None):
+    """One launch of an HBM bandwidth probe kernel on device tensors (see
+    include/reff.h); asynchronous on `stream` (default: torch's current)."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(_lib.reff_stream_probe(int(kind), src.data_ptr() if src is not None else None,
+                                  dst.data_ptr(), int(nbytes), int(blocks),
+                                  C.c_void_p(int(stream))))
 
 
 def reff_selinv_info(desc):

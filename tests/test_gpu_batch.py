@@ -109,6 +109,31 @@ def test_batch_recipe_sizes_sampled():
         assert err <= 1e-3
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_all_256_recipe_plans_against_stored_oracle_values(prec):
+    """The whole batching workload in one call, in the benchmark's launch
+    configuration: 256 plans (2-4 tiers, sides 64-256, 21.1M nodes), the
+    seeded 64-node block of every plan, against the oracle's values stored
+    in tests/golden/config3_sample.json (written by make_golden.py from the
+    oracle alone).  Every node must be within 1e-3 (the metric's bar) at the
+    benchmark's rel_tol 1e-3, in mixed precision and in float64."""
+    import json
+    import os
+    reff = _reff()
+    plans = gen.config3_plans()
+    nodes = gen.config3_samples(plans)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "config3_sample.json")))
+    assert [list(x) for x in nodes] == gold["nodes"], "sample drifted from the fixture"
+    _say("batch all 256 recipe plans", prec)
+    p = reff.REFF_PREC_MIXED if prec == "mixed" else reff.REFF_PREC_FP64
+    outs, stats = reff.reff_batch_plans(plans, nodes, precision=p, rel_tol=1e-3)
+    worst = max(_rel(outs[i], np.array(gold["R"][i])) for i in range(len(plans)))
+    print("worst relative error over 16,384 nodes", worst, flush=True)
+    assert worst <= 1e-3
+    assert all(s["n_unconverged"] == 0 for s in stats)
+
+
 def test_tuning_database_created_and_reused(tmp_path):
     """A batch with a tuning database times a few (work units, strips) per
     launch for its size class -- the strip count sets the strip height, the
