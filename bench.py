@@ -415,6 +415,10 @@ def surrogate_compare(reff, gen, log, rel_tol, n_train=512, n_test=16, per_test=
     a = time.perf_counter()
     ref, _ = reff.reff_batch_plans(test, req, precision=prec, rel_tol=rel_tol)
     t_solver = time.perf_counter() - a
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    reff.reff_batch_plans(test, req, precision=reff.REFF_PREC_FP64, rel_tol=rel_tol)
+    t_solver64 = time.perf_counter() - a
     a = time.perf_counter()
     scr, st = reff.reff_batch_plans(test, req, precision=prec, rel_tol=rel_tol, surrogate=s,
                                     spot_frac=0.01, fallback_rel_err=1e-2)
@@ -454,6 +458,7 @@ def surrogate_compare(reff, gen, log, rel_tol, n_train=512, n_test=16, per_test=
         "screened_nodes_per_s": total / t_screen,
         "n_ok_1e-2": int(np.sum(e_scr <= 1e-2)), "nodes": total,
         "solver_nodes_per_s": total / t_solver,
+        "solver_fp64_nodes_per_s": total / t_solver64,
         "predict_nodes_per_s": n_test * 3 * 128 * 128 / t_pred,
         "plans_screened": int(sum(x["screened"] for x in st)), "plans": n_test,
         "model_err_requested": q(e_req), "model_err_full_maps": q(e_full),
@@ -626,6 +631,50 @@ def stream_probe_run(gib=1, reps=5):
     return out
 
 
+def direct_large_run(reff, gen, log, side, reps=2):
+    """The sparse-direct all-node map of a 4 x side x side stack drawn by the
+    mixed-precision recipe (TSV and pad counts scaled with the area), timed
+    (first call, then the median of `reps`), with 32 nodes checked against
+    float64 block-PCG solves (rel_tol 1e-10) on the same stack."""
+    import numpy as np
+    import torch
+    scale = (side / 512) ** 2
+    d = gen.config2(side=side, n_tsv=int(1024 * scale), sigma=40.0 * side / 512)
+    n = gen.n_nodes(d)
+    info = reff.reff_selinv_info(d)
+    log(f"direct {side}: {n} nodes, {info['n_fronts']} fronts, largest {info['max_front']}, "
+        f"{info['device_bytes'] / 1e9:.1f} GB, "
+        f"{(info['flops_factor'] + info['flops_selinv']) / 1e12:.2f} TFLOP")
+    h = reff.reff_build_pdn(d, device=0)
+    out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    reff.reff_selinv_diag(h, None, out)
+    torch.cuda.synchronize()
+    first = time.perf_counter() - a
+    dts = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        _, st = reff.reff_selinv_diag(h, None, out)
+        torch.cuda.synchronize()
+        dts.append(time.perf_counter() - a)
+    dt = float(np.median(dts))
+    got = out.cpu().numpy()
+    ids = gen.sample_free_nodes(d, 32, 4242)
+    want, _ = reff.reff_solve_diag(h, ids, precision=reff.REFF_PREC_FP64, rel_tol=1e-10)
+    err = float(np.max(np.abs(got[ids] - want) / want))
+    flops = st["flops_factor"] + st["flops_selinv"]
+    free = int(np.sum(got > 0))
+    rec = {"workload": f"all {free} free nodes of a 4 x {side} x {side} stack", "nodes": n,
+           "seconds": dt, "seconds_first_call": first, "nodes_per_s": free / dt,
+           "TFLOPs": flops / dt / 1e12, "flops": flops, "device_bytes": st["device_bytes"],
+           "max_front": st["max_front"], "fronts": st["n_fronts"],
+           "max_rel_diff_vs_fp64_pcg_32_nodes": err}
+    log(f"direct {side}: {dt:.3f} s per map ({free / dt:.3g} nodes/s), first {first:.2f} s, "
+        f"{flops / dt / 1e12:.1f} TFLOP/s, 32-node check {err:.1e}")
+    return rec
+
+
 def large_run(args, reff, gen, log):
     """The large stack (8 tiers of 2048 x 2048, 33,554,432 nodes): a full
     map is out of reach on one GPU, so the first `large_blocks` 64-node
@@ -751,6 +800,10 @@ def main():
     ap.add_argument("--direct-only", action="store_true",
                     help="only the sparse-direct all-node map of the 4 x 512 x 512 stack "
                          "(reff_selinv_diag); prints that leg's record")
+    ap.add_argument("--direct-side", type=int, default=512,
+                    help="--direct-only: tier side of the 4-tier stack (512: the benchmark "
+                         "stack, checked against the stored oracle map; larger sides draw "
+                         "the same recipe and check 32 nodes against block-PCG solves)")
     ap.add_argument("--stream-probe", action="store_true",
                     help="only the HBM bandwidth probes (copy, read, write, 3-read/2-write, "
                          "non-temporal copy) over grid sizes; prints one JSON record")
@@ -795,9 +848,12 @@ def main():
         print(json.dumps(surrogate_scale_run(reff, gen, log)), flush=True)
         return
     if args.direct_only:
-        d2 = gen.config2()
-        h2 = reff.reff_build_pdn(d2, device=0)
-        print(json.dumps(direct_full_map_compare(reff, log, h2, gen.n_nodes(d2))), flush=True)
+        if args.direct_side == 512:
+            d2 = gen.config2()
+            h2 = reff.reff_build_pdn(d2, device=0)
+            print(json.dumps(direct_full_map_compare(reff, log, h2, gen.n_nodes(d2))), flush=True)
+        else:
+            print(json.dumps(direct_large_run(reff, gen, log, args.direct_side)), flush=True)
         return
     desc = gen.config2()
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "config2_sample.json")))
