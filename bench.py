@@ -289,6 +289,35 @@ def batched_compare(reff, gen, log, rel_tol, n_seq=16, reps=3):
         rec[tag] = {"nodes_per_s": n_ok / dseq, "seconds": dseq, "plans_timed": n_seq,
                     "n_ok": n_ok, "max_rel_err": worst}
         log(f"{tag}: {n_ok / dseq:.1f} nodes/s over {n_seq} plans (build + solve per plan)")
+    # the sparse-direct path on the same plans in one call: the same requests,
+    # then every node of every plan
+    for tag, req in (("batched_direct", nodes), ("batched_direct_all_nodes", None)):
+        dts = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            outs, st = reff.reff_selinv_batch(plans, req)
+            torch.cuda.synchronize()
+            dts.append(time.perf_counter() - a)
+        dt = float(np.median(dts))
+        if req is None:
+            cnt = sum(int(np.sum(o > 0)) for o in outs)
+            n_ok = cnt  # every free node, all exact to float64 rounding
+            outs_req = [outs[i][nodes[i]] for i in range(len(plans))]
+        else:
+            outs_req = outs
+            cnt = total
+        n_req_ok, worst = check(outs_req)
+        if req is not None:
+            n_ok = n_req_ok
+        rec[tag] = {"nodes_per_s": n_ok / dt, "seconds": dt, "seconds_all": dts, "n_ok": n_ok,
+                    "nodes": cnt, "max_rel_err_requested": worst,
+                    "seconds_plan": st["seconds_plan"], "seconds_factor": st["seconds_factor"],
+                    "seconds_selinv": st["seconds_selinv"], "fronts": st["n_fronts"],
+                    "device_bytes": st["device_bytes"],
+                    "TFLOPs": (st["flops_factor"] + st["flops_selinv"]) / dt / 1e12}
+        log(f"{tag}: {n_ok / dt:.4g} nodes/s ({dt:.2f} s, plan {st['seconds_plan']:.2f} s), "
+            f"{n_ok} nodes, requested max err {worst:.2e}")
     rec["nodes_per_s"] = rec["batched_mixed"]["nodes_per_s"]
     return rec
 

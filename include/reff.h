@@ -183,8 +183,10 @@ typedef struct {
   double flops_selinv;    /* float64 flops of the selected inversion          */
   double seconds;         /* wall time of the call                            */
   double seconds_plan;    /* symbolic analysis (on a handle's first use only) */
-  double seconds_factor;  /* allocation, table upload and factorisation       */
+  double seconds_factor;  /* factorisation (device set-up included)          */
   double seconds_selinv;  /* selected inversion and output                    */
+  double seconds_setup;   /* of seconds_factor: device allocation and upload of
+                             the plan's tables (0 when a handle reuses them) */
 } reff_selinv_stats;
 
 /*
@@ -211,9 +213,30 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes,
                              double* R_out, const reff_solve_opts* opts,
                              reff_selinv_stats* st);
 
+/*
+ * reff_selinv_diag for many stacks (candidate TSV plans, Sec. I and IV-B) in
+ * one call, with no handle: the plans' dissection trees are analysed on
+ * host threads and merged by depth, so every plan's fronts of one tree
+ * level share the same launches; device memory is allocated for the call
+ * and released before it returns (the sum of the plans'
+ * reff_selinv_info().device_bytes).  Inputs as reff_batch_plans:
+ *   plans    host array of n_plans stack descriptions (validated as
+ *            reff_build_pdn does, and checked for connectivity).
+ *   nodes    NULL, or host array of n_plans node-id arrays (an entry NULL =
+ *            all nodes of that plan); n_nodes their lengths.
+ *   R_out    n_plans output arrays (host, or device if opts->out_on_device).
+ *   opts     NULL => defaults; only stream and out_on_device are read.  Runs
+ *            on the current device.
+ * Errors: INVALID_ARG (naming the plan), DISCONNECTED, OUT_OF_MEMORY, DEVICE.
+ */
+reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
+                              const int64_t* const* nodes, const int64_t* n_nodes,
+                              double* const* R_out, const reff_solve_opts* opts,
+                              reff_selinv_stats* st);
+
 /* The plan reff_selinv_diag would use for a stack (host only, no device
  * needed): fronts, levels, largest front, device bytes and flop counts.
- * Errors: INVALID_ARG (as reff_build_pdn's validation). */
+ * Errors: INVALID_ARG (as reff_build_pdn's validation), DISCONNECTED. */
 reff_status reff_selinv_info(const reff_pdn_desc* d, reff_selinv_stats* info);
 
 /*

@@ -465,16 +465,27 @@ hipError_t put(Bufs& b, T** out, const std::vector<T>& v, hipStream_t st) {
   return e;
 }
 
-// Per level: the largest tile counts of each launch of a panel step.
-struct LevelDev {
-  int64_t list_off = 0;
+// The fronts of a level are launched in groups of at most GROUP fronts, so
+// that the per-front scratch of a panel step (tile inverses, Y blocks,
+// partial products) is sized by a group, not by a level of a large forest.
+constexpr size_t GROUP = 16384;
+
+// One launch group: a contiguous range of a level's front list.
+struct GroupDev {
+  int64_t list_off = 0;  // into the device front lists
   int nf = 0;
   int max_panels = 0;
-  int64_t ent_off = 0, ent_n = 0;
-  int ysplit = 1;     // K parts of the Y product
-  int64_t ylev = 0;   // doubles of the level's Y buffer
-  int64_t maxq = 0;   // largest update set of the level
+  int ysplit = 1;        // K parts of the Y product
+  int64_t ylev = 0;      // doubles of the group's Y buffer
+  int64_t part = 0;      // doubles of its partial products
+  int64_t maxq = 0;      // largest update set
   std::vector<int> mt, ms;  // per panel: row tiles after it, K parts of its partials
+};
+
+struct LevelDev {
+  int64_t ent_off = 0, ent_n = 0;
+  int nf = 0;
+  std::vector<GroupDev> groups;
 };
 
 reff_status dev_status(hipError_t e, const char* what) {
@@ -500,23 +511,58 @@ std::shared_ptr<SelinvPlan> selinv_plan_of(reff_pdn_t* p, reff_status& s) {
   return plan;
 }
 
-// Parts the K range of a level's Y products is split into: enough
-// workgroups to fill the chip where a level has few fronts, at least 128
+// Parts the K range of a group's Y products is split into: enough
+// workgroups to fill the chip where a group has few fronts, at least 128
 // rows of K per part, and at most 1 GiB of partial products.
-int level_ysplit(const SelinvPlan& P, const SelinvLevel& L, int64_t yb) {
+int group_ysplit(const SelinvPlan& P, const int32_t* fronts, size_t nf, int64_t yb) {
   int64_t tiles0 = 0, maxm = 0;
-  for (int32_t i : L.fronts) {
-    const SnFront& f = P.fronts[(size_t)i];
+  for (size_t j = 0; j < nf; ++j) {
+    const SnFront& f = P.fronts[(size_t)fronts[j]];
     if (f.k == 0) continue;
     const int64_t m0 = f.F - std::min(PT, f.k);
     tiles0 += (m0 + PT - 1) / PT;
     maxm = std::max(maxm, m0);
   }
   if (tiles0 == 0) return 1;
-  int64_t s = std::min<int64_t>((2048 + tiles0 - 1) / tiles0, 16);
-  s = std::min<int64_t>(s, std::max<int64_t>(1, maxm / 128));
-  while (s > 1 && s * yb > ((int64_t)1 << 27)) --s;
-  return (int)std::max<int64_t>(1, s);
+  int64_t sp = std::min<int64_t>((2048 + tiles0 - 1) / tiles0, 16);
+  sp = std::min<int64_t>(sp, std::max<int64_t>(1, maxm / 128));
+  while (sp > 1 && sp * yb > ((int64_t)1 << 27)) --sp;
+  return (int)std::max<int64_t>(1, sp);
+}
+
+int front_nsplit(const SnFront& f) { return std::min(16, std::max(1, (f.F + 255) / 256)); }
+
+// The launch groups of every level, with their scratch sizes.
+std::vector<std::vector<GroupDev>> plan_groups(const SelinvPlan& P) {
+  std::vector<std::vector<GroupDev>> out(P.levels.size());
+  for (size_t d = 0; d < P.levels.size(); ++d) {
+    const SelinvLevel& L = P.levels[d];
+    for (size_t b = 0; b < L.fronts.size(); b += GROUP) {
+      GroupDev g;
+      g.list_off = (int64_t)b;  // within the level; made absolute by the device build
+      g.nf = (int)std::min(GROUP, L.fronts.size() - b);
+      for (int j = 0; j < g.nf; ++j) {
+        const SnFront& f = P.fronts[(size_t)L.fronts[b + (size_t)j]];
+        g.max_panels = std::max(g.max_panels, (f.k + PT - 1) / PT);
+        g.ylev += (int64_t)f.F * PT;
+        g.part += (int64_t)front_nsplit(f) * PT * PT;
+        g.maxq = std::max<int64_t>(g.maxq, (int64_t)(f.F - f.k));
+      }
+      g.mt.assign((size_t)g.max_panels, 0);
+      g.ms.assign((size_t)g.max_panels, 0);
+      for (int j = 0; j < g.nf; ++j) {
+        const SnFront& f = P.fronts[(size_t)L.fronts[b + (size_t)j]];
+        for (int jp = 0; PT * jp < f.k; ++jp) {
+          const int m = f.F - PT * jp - std::min(PT, f.k - PT * jp);
+          g.mt[(size_t)jp] = std::max(g.mt[(size_t)jp], (m + PT - 1) / PT);
+          g.ms[(size_t)jp] = std::max(g.ms[(size_t)jp], front_nsplit(f));
+        }
+      }
+      g.ysplit = group_ysplit(P, L.fronts.data() + b, (size_t)g.nf, g.ylev);
+      out[d].push_back(std::move(g));
+    }
+  }
+  return out;
 }
 
 // Scratch sizes of a plan on the device, in doubles / bytes.
@@ -527,19 +573,13 @@ struct SelinvSizes {
 
 SelinvSizes selinv_sizes(const SelinvPlan& P) {
   SelinvSizes z;
-  for (const SelinvLevel& L : P.levels) {
-    int64_t yb = 0, pa = 0;
-    for (int32_t i : L.fronts) {
-      const SnFront& f = P.fronts[(size_t)i];
-      yb += (int64_t)f.F * PT;
-      pa += (int64_t)std::min(16, std::max(1, (f.F + 255) / 256)) * PT * PT;
+  for (const auto& lev : plan_groups(P))
+    for (const GroupDev& g : lev) {
+      z.tiles = std::max<int64_t>(z.tiles, (int64_t)g.nf * PT * PT);
+      z.ybuf = std::max(z.ybuf, g.ylev);
+      z.part = std::max(z.part, g.part);
+      if (g.ysplit > 1) z.ysp = std::max(z.ysp, g.ysplit * g.ylev);
     }
-    z.tiles = std::max<int64_t>(z.tiles, (int64_t)L.fronts.size() * PT * PT);
-    z.ybuf = std::max(z.ybuf, yb);
-    z.part = std::max(z.part, pa);
-    const int ys = level_ysplit(P, L, yb);
-    if (ys > 1) z.ysp = std::max(z.ysp, ys * yb);
-  }
   int64_t ent = 0;
   for (const SelinvLevel& L : P.levels) ent += (int64_t)L.ent_idx.size();
   z.bytes = 8 * (P.arena + 2 * z.tiles + z.ybuf + z.part + z.ysp + P.n) + 16 * ent +
@@ -580,57 +620,48 @@ struct SelinvDevice {
   }
 };
 
-std::shared_ptr<SelinvDevice> selinv_device_of(reff_pdn_t* p, const SelinvPlan& P,
-                                               reff_status& s) {
+std::shared_ptr<SelinvDevice> selinv_device_build(const SelinvPlan& P, reff_status& s) {
   s = REFF_OK;
-  if (p->sel_dev) return p->sel_dev;
   auto D = std::make_shared<SelinvDevice>();
   std::vector<DFront> dfr(P.fronts.size());
   std::vector<int32_t> lists;
-  std::vector<int64_t> ent_idx;
-  std::vector<double> ent_val;
+  int64_t n_ent = 0;
   D->sz = selinv_sizes(P);
+  auto groups = plan_groups(P);
   D->lv.resize(P.levels.size());
   for (size_t d = 0; d < P.levels.size(); ++d) {
     const SelinvLevel& L = P.levels[d];
     LevelDev& V = D->lv[d];
-    V.list_off = (int64_t)lists.size();
     V.nf = (int)L.fronts.size();
-    V.max_panels = L.max_panels;
-    V.ent_off = (int64_t)ent_idx.size();
+    V.ent_off = n_ent;
     V.ent_n = (int64_t)L.ent_idx.size();
-    ent_idx.insert(ent_idx.end(), L.ent_idx.begin(), L.ent_idx.end());
-    ent_val.insert(ent_val.end(), L.ent_val.begin(), L.ent_val.end());
-    V.mt.assign((size_t)V.max_panels, 0);
-    V.ms.assign((size_t)V.max_panels, 0);
-    int64_t yb = 0, pa = 0;
-    for (int32_t i : L.fronts) {
-      const SnFront& f = P.fronts[(size_t)i];
-      DFront& g = dfr[(size_t)i];
-      g.off = f.off;
-      g.poff = f.parent >= 0 ? P.fronts[(size_t)f.parent].off : -1;
-      g.rel = f.rel;
-      g.piv = f.piv;
-      g.F = f.F;
-      g.k = f.k;
-      g.pF = f.parent >= 0 ? P.fronts[(size_t)f.parent].F : 0;
-      g.rank = f.rank;
-      g.nsplit = std::min(16, std::max(1, (f.F + 255) / 256));
-      g.pad_ = 0;
-      g.ybuf = yb;
-      g.part = pa;
-      yb += (int64_t)f.F * PT;
-      pa += (int64_t)g.nsplit * PT * PT;
-      lists.push_back(i);
-      V.maxq = std::max<int64_t>(V.maxq, (int64_t)(f.F - f.k));
-      for (int jp = 0; PT * jp < f.k; ++jp) {
-        const int m = f.F - PT * jp - std::min(PT, f.k - PT * jp);
-        V.mt[(size_t)jp] = std::max(V.mt[(size_t)jp], (m + PT - 1) / PT);
-        V.ms[(size_t)jp] = std::max(V.ms[(size_t)jp], g.nsplit);
+    n_ent += V.ent_n;
+    const int64_t lbase = (int64_t)lists.size();
+    for (GroupDev& g : groups[d]) {
+      int64_t yb = 0, pa = 0;
+      for (int j = 0; j < g.nf; ++j) {
+        const int32_t i = L.fronts[(size_t)(g.list_off + j)];
+        const SnFront& f = P.fronts[(size_t)i];
+        DFront& x = dfr[(size_t)i];
+        x.off = f.off;
+        x.poff = f.parent >= 0 ? P.fronts[(size_t)f.parent].off : -1;
+        x.rel = f.rel;
+        x.piv = f.piv;
+        x.F = f.F;
+        x.k = f.k;
+        x.pF = f.parent >= 0 ? P.fronts[(size_t)f.parent].F : 0;
+        x.rank = f.rank;
+        x.nsplit = front_nsplit(f);
+        x.pad_ = 0;
+        x.ybuf = yb;
+        x.part = pa;
+        yb += (int64_t)f.F * PT;
+        pa += (int64_t)x.nsplit * PT * PT;
       }
+      g.list_off += lbase;
     }
-    V.ylev = yb;
-    V.ysplit = level_ysplit(P, L, yb);
+    lists.insert(lists.end(), L.fronts.begin(), L.fronts.end());
+    V.groups = std::move(groups[d]);
   }
   hipError_t e = D->get(&D->ar, (size_t)P.arena);
   if (e == hipSuccess) e = D->get(&D->Li, (size_t)D->sz.tiles);
@@ -640,8 +671,19 @@ std::shared_ptr<SelinvDevice> selinv_device_of(reff_pdn_t* p, const SelinvPlan& 
   if (e == hipSuccess) e = D->get(&D->Ysp, (size_t)D->sz.ysp);
   if (e == hipSuccess) e = D->get(&D->Rfull, (size_t)P.n);
   if (e == hipSuccess) e = D->get(&D->bad, 1);
-  if (e == hipSuccess) e = D->put(&D->idx, ent_idx);
-  if (e == hipSuccess) e = D->put(&D->vals, ent_val);
+  // G's entries, level by level straight from the plan
+  if (e == hipSuccess) e = D->get(&D->idx, (size_t)n_ent);
+  if (e == hipSuccess) e = D->get(&D->vals, (size_t)n_ent);
+  for (size_t d = 0; d < P.levels.size() && e == hipSuccess; ++d) {
+    const SelinvLevel& L = P.levels[d];
+    const LevelDev& V = D->lv[d];
+    if (V.ent_n == 0) continue;
+    e = hipMemcpy(D->idx + V.ent_off, L.ent_idx.data(), sizeof(int64_t) * V.ent_n,
+                  hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(D->vals + V.ent_off, L.ent_val.data(), sizeof(double) * V.ent_n,
+                    hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = D->put(&D->piv, P.piv_node);
   if (e == hipSuccess) e = D->put(&D->rel, P.rel);
   if (e == hipSuccess) e = D->put(&D->dl, lists);
@@ -650,8 +692,109 @@ std::shared_ptr<SelinvDevice> selinv_device_of(reff_pdn_t* p, const SelinvPlan& 
     s = dev_status(e, "selected inversion: allocation / upload");
     return nullptr;
   }
-  p->sel_dev = D;
   return D;
+}
+
+std::shared_ptr<SelinvDevice> selinv_device_of(reff_pdn_t* p, const SelinvPlan& P,
+                                               reff_status& s) {
+  s = REFF_OK;
+  if (p->sel_dev) return p->sel_dev;
+  auto D = selinv_device_build(P, s);
+  if (D) p->sel_dev = D;
+  return D;
+}
+
+// The numeric work of a plan on its device state, on `st`: factorisation
+// (deepest level first) then selected inversion (roots first); D.Rfull
+// receives R for every pivot node (0 elsewhere).  t_fact: when the
+// factorisation finished (the call synchronises there to read the pivot
+// flag).
+reff_status selinv_run(const SelinvPlan& P, const SelinvDevice& D, hipStream_t st_,
+                       std::chrono::steady_clock::time_point& t_fact) {
+  double *ar = D.ar, *Li = D.Li, *Z0 = D.Z0, *Yb = D.Yb, *part = D.part, *Ysp = D.Ysp;
+  double* Rfull = D.Rfull;
+  const int32_t *rel = D.rel, *dl = D.dl;
+  const DFront* dF = D.dF;
+  int* bad = D.bad;
+  hipLaunchKernelGGL(k_zero, flat(P.n), dim3(256), 0, st_, Rfull, P.n);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), st_);
+  auto gy = [](int nf) { return (unsigned)std::min<int64_t>(nf, MAX_GY); };
+  const int nlev = (int)P.levels.size();
+  // factorisation, deepest level first
+  for (int d = nlev - 1; d >= 0 && e == hipSuccess; --d) {
+    const SelinvLevel& L = P.levels[(size_t)d];
+    const LevelDev& V = D.lv[(size_t)d];
+    if (V.nf == 0) continue;
+    const int64_t span = L.arena_end - L.arena_begin;
+    if (span > 0) hipLaunchKernelGGL(k_zero, flat(span), dim3(256), 0, st_, ar + L.arena_begin, span);
+    if (V.ent_n > 0)
+      hipLaunchKernelGGL(k_scatter, flat(V.ent_n), dim3(256), 0, st_, D.idx + V.ent_off,
+                         D.vals + V.ent_off, V.ent_n, ar);
+    if (d + 1 < nlev)
+      for (int rank = 0; rank < 2; ++rank)
+        for (const GroupDev& C : D.lv[(size_t)d + 1].groups) {
+          const unsigned gx = (unsigned)std::max<int64_t>(
+              1, std::min<int64_t>((C.maxq * C.maxq + 255) / 256, 1024));
+          hipLaunchKernelGGL(k_extend_add, dim3(gx, gy(C.nf)), dim3(256), 0, st_, dF,
+                             dl + C.list_off, C.nf, rank, rel, ar);
+        }
+    for (const GroupDev& G : V.groups) {
+      const int32_t* l = dl + G.list_off;
+      for (int jp = 0; jp < G.max_panels; ++jp) {
+        hipLaunchKernelGGL(k_tile<true>, dim3(gy(G.nf)), dim3(256), 0, st_, dF, l, G.nf, jp, ar,
+                           Li, Z0, bad);
+        const int mt = G.mt[(size_t)jp];
+        if (mt == 0) continue;
+        hipLaunchKernelGGL(k_front_gemm<OP_TRSM>, dim3((unsigned)mt, gy(G.nf)), dim3(256), 0,
+                           st_, dF, l, G.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
+        hipLaunchKernelGGL(k_front_gemm<OP_SYRK>, dim3((unsigned)(mt * (mt + 1) / 2), gy(G.nf)),
+                           dim3(256), 0, st_, dF, l, G.nf, jp, ar, Li, Yb, part, mt, 1, Ysp,
+                           (int64_t)0);
+      }
+    }
+    e = hipGetLastError();
+  }
+  int hbad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st_);
+  if (e == hipSuccess) e = hipStreamSynchronize(st_);
+  if (e != hipSuccess) return dev_status(e, "selected inversion: factorisation");
+  if (hbad) return host_fail(REFF_ERR_DEVICE, "sparse Cholesky: a pivot was not positive");
+  t_fact = std::chrono::steady_clock::now();
+  // selected inversion, roots first
+  for (int d = 0; d < nlev && e == hipSuccess; ++d) {
+    const LevelDev& V = D.lv[(size_t)d];
+    for (const GroupDev& G : V.groups) {
+      const int32_t* l = dl + G.list_off;
+      if (d > 0 && G.maxq > 0) {
+        const unsigned gx = (unsigned)std::min<int64_t>((G.maxq * G.maxq + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_gather, dim3(gx, gy(G.nf)), dim3(256), 0, st_, dF, l, G.nf, rel,
+                           ar);
+      }
+      for (int jp = G.max_panels - 1; jp >= 0; --jp) {
+        const int mt = G.mt[(size_t)jp], ms = G.ms[(size_t)jp];
+        hipLaunchKernelGGL(k_tile<false>, dim3(gy(G.nf)), dim3(256), 0, st_, dF, l, G.nf, jp, ar,
+                           Li, Z0, bad);
+        if (mt > 0) {
+          hipLaunchKernelGGL(k_front_gemm<OP_LHAT>, dim3((unsigned)mt, gy(G.nf)), dim3(256), 0,
+                             st_, dF, l, G.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
+          hipLaunchKernelGGL(k_front_gemm<OP_Y>, dim3((unsigned)(mt * G.ysplit), gy(G.nf)),
+                             dim3(256), 0, st_, dF, l, G.nf, jp, ar, Li, Yb, part, mt, G.ysplit,
+                             Ysp, G.ylev);
+          if (G.ysplit > 1)
+            hipLaunchKernelGGL(k_ysum, dim3((unsigned)mt, gy(G.nf)), dim3(256), 0, st_, dF, l,
+                               G.nf, jp, G.ysplit, (const double*)Ysp, G.ylev, Yb);
+          hipLaunchKernelGGL(k_front_gemm<OP_PART>, dim3((unsigned)ms, gy(G.nf)), dim3(256), 0,
+                             st_, dF, l, G.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
+        }
+        hipLaunchKernelGGL(k_finish, dim3((unsigned)(1 + mt), gy(G.nf)), dim3(256), 0, st_, dF,
+                           l, G.nf, jp, ar, Z0, Yb, part, D.piv, Rfull);
+      }
+    }
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return dev_status(e, "selected inversion");
+  return REFF_OK;
 }
 
 }  // namespace reff
@@ -665,9 +808,11 @@ reff_status reff_selinv_info(const reff_pdn_desc* d, reff_selinv_stats* info) {
   if (s != REFF_OK) return s;
   SelinvPlan plan;
   std::string err;
+  bool dis = false;
   if (!build_selinv_plan(d->n_tiers, d->nx, d->ny, d->gx, d->gy, d->n_tsv, d->tsv_xy, d->tsv_g,
-                         d->n_pads, d->pad_xy, LEAF_AREA, plan, err))
-    return host_fail(REFF_ERR_INVALID_ARG, "selected inversion plan: " + err);
+                         d->n_pads, d->pad_xy, LEAF_AREA, plan, err, &dis))
+    return host_fail(dis ? REFF_ERR_DISCONNECTED : REFF_ERR_INVALID_ARG,
+                     "selected inversion plan: " + err);
   std::memset(info, 0, sizeof(*info));
   info->n_fronts = (int64_t)plan.fronts.size();
   info->n_levels = (int32_t)plan.levels.size();
@@ -704,11 +849,8 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
   auto dev_sp = selinv_device_of(p, P, s);
   if (!dev_sp) return s;
   const SelinvDevice& D = *dev_sp;
-  double *ar = D.ar, *Li = D.Li, *Z0 = D.Z0, *Yb = D.Yb, *part = D.part, *Ysp = D.Ysp;
+  const auto t_setup = std::chrono::steady_clock::now();
   double* Rfull = D.Rfull;
-  const int32_t *rel = D.rel, *dl = D.dl;
-  const DFront* dF = D.dF;
-  int* bad = D.bad;
   Bufs b;
   double* dout = nullptr;
   int64_t* dnodes = nullptr;
@@ -720,80 +862,9 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
   }
   if (e == hipSuccess && !out_dev && count > 0) e = b.get(&dout, (size_t)count);
   if (e != hipSuccess) return dev_status(e, "selected inversion: output buffers");
-  hipLaunchKernelGGL(k_zero, flat(P.n), dim3(256), 0, st_, Rfull, P.n);
-  e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), st_);
-
-  auto gy = [](int nf) { return (unsigned)std::min<int64_t>(nf, MAX_GY); };
-  const int nlev = (int)P.levels.size();
-  // factorisation, deepest level first
-  for (int d = nlev - 1; d >= 0 && e == hipSuccess; --d) {
-    const SelinvLevel& L = P.levels[(size_t)d];
-    const LevelDev& V = D.lv[(size_t)d];
-    const int32_t* l = dl + V.list_off;
-    if (V.nf == 0) continue;
-    const int64_t span = L.arena_end - L.arena_begin;
-    if (span > 0) hipLaunchKernelGGL(k_zero, flat(span), dim3(256), 0, st_, ar + L.arena_begin, span);
-    if (V.ent_n > 0)
-      hipLaunchKernelGGL(k_scatter, flat(V.ent_n), dim3(256), 0, st_, D.idx + V.ent_off,
-                         D.vals + V.ent_off, V.ent_n, ar);
-    if (d + 1 < nlev && D.lv[(size_t)d + 1].nf > 0) {
-      const LevelDev& C = D.lv[(size_t)d + 1];
-      const unsigned gx = (unsigned)std::max<int64_t>(
-          1, std::min<int64_t>((C.maxq * C.maxq + 255) / 256, 1024));
-      for (int rank = 0; rank < 2; ++rank)
-        hipLaunchKernelGGL(k_extend_add, dim3(gx, gy(C.nf)), dim3(256), 0, st_, dF,
-                           dl + C.list_off, C.nf, rank, rel, ar);
-    }
-    for (int jp = 0; jp < V.max_panels; ++jp) {
-      hipLaunchKernelGGL(k_tile<true>, dim3(gy(V.nf)), dim3(256), 0, st_, dF, l, V.nf, jp, ar,
-                         Li, Z0, bad);
-      const int mt = V.mt[(size_t)jp];
-      if (mt == 0) continue;
-      hipLaunchKernelGGL(k_front_gemm<OP_TRSM>, dim3((unsigned)mt, gy(V.nf)), dim3(256), 0, st_,
-                         dF, l, V.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
-      hipLaunchKernelGGL(k_front_gemm<OP_SYRK>, dim3((unsigned)(mt * (mt + 1) / 2), gy(V.nf)),
-                         dim3(256), 0, st_, dF, l, V.nf, jp, ar, Li, Yb, part, mt, 1, Ysp,
-                         (int64_t)0);
-    }
-    e = hipGetLastError();
-  }
-  int hbad = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st_);
-  if (e == hipSuccess) e = hipStreamSynchronize(st_);
-  if (e != hipSuccess) return dev_status(e, "selected inversion: factorisation");
-  if (hbad) return host_fail(REFF_ERR_DEVICE, "sparse Cholesky: a pivot was not positive");
-  const auto t_fact = std::chrono::steady_clock::now();
-  // selected inversion, roots first
-  for (int d = 0; d < nlev && e == hipSuccess; ++d) {
-    const LevelDev& V = D.lv[(size_t)d];
-    const int32_t* l = dl + V.list_off;
-    if (V.nf == 0) continue;
-    if (d > 0 && V.maxq > 0) {
-      const unsigned gx = (unsigned)std::min<int64_t>((V.maxq * V.maxq + 255) / 256, 1024);
-      hipLaunchKernelGGL(k_gather, dim3(gx, gy(V.nf)), dim3(256), 0, st_, dF, l, V.nf, rel, ar);
-    }
-    for (int jp = V.max_panels - 1; jp >= 0; --jp) {
-      const int mt = V.mt[(size_t)jp], ms = V.ms[(size_t)jp];
-      hipLaunchKernelGGL(k_tile<false>, dim3(gy(V.nf)), dim3(256), 0, st_, dF, l, V.nf, jp, ar,
-                         Li, Z0, bad);
-      if (mt > 0) {
-        hipLaunchKernelGGL(k_front_gemm<OP_LHAT>, dim3((unsigned)mt, gy(V.nf)), dim3(256), 0,
-                           st_, dF, l, V.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
-        hipLaunchKernelGGL(k_front_gemm<OP_Y>, dim3((unsigned)(mt * V.ysplit), gy(V.nf)),
-                           dim3(256), 0, st_, dF, l, V.nf, jp, ar, Li, Yb, part, mt, V.ysplit,
-                           Ysp, V.ylev);
-        if (V.ysplit > 1)
-          hipLaunchKernelGGL(k_ysum, dim3((unsigned)mt, gy(V.nf)), dim3(256), 0, st_, dF, l,
-                             V.nf, jp, V.ysplit, (const double*)Ysp, V.ylev, Yb);
-        hipLaunchKernelGGL(k_front_gemm<OP_PART>, dim3((unsigned)ms, gy(V.nf)), dim3(256), 0,
-                           st_, dF, l, V.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
-      }
-      hipLaunchKernelGGL(k_finish, dim3((unsigned)(1 + mt), gy(V.nf)), dim3(256), 0, st_, dF, l,
-                         V.nf, jp, ar, Z0, Yb, part, D.piv, Rfull);
-    }
-    e = hipGetLastError();
-  }
+  std::chrono::steady_clock::time_point t_fact;
+  s = selinv_run(P, D, st_, t_fact);
+  if (s != REFF_OK) return s;
   // output
   if (e == hipSuccess && count > 0) {
     double* out = out_dev ? R_out : dout;
@@ -821,6 +892,121 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
     st->seconds_plan = std::chrono::duration<double>(t_plan - t0).count();
     st->seconds_factor = std::chrono::duration<double>(t_fact - t_plan).count();
     st->seconds_selinv = std::chrono::duration<double>(t1 - t_fact).count();
+    st->seconds_setup = std::chrono::duration<double>(t_setup - t_plan).count();
+  }
+  return REFF_OK;
+}
+
+reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
+                              const int64_t* const* nodes, const int64_t* n_nodes,
+                              double* const* R_out, const reff_solve_opts* opts,
+                              reff_selinv_stats* st) {
+  using namespace reff;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (st) std::memset(st, 0, sizeof(*st));
+  if (n_plans < 0) return host_fail(REFF_ERR_INVALID_ARG, "n_plans < 0");
+  if (n_plans == 0) return REFF_OK;
+  if (!plans || !R_out) return host_fail(REFF_ERR_INVALID_ARG, "NULL plans or R_out");
+  if (opts && opts->out_on_device != 0 && opts->out_on_device != 1)
+    return host_fail(REFF_ERR_INVALID_ARG, "out_on_device must be 0 or 1");
+  const bool out_dev = opts && opts->out_on_device;
+  hipStream_t st_ = opts ? (hipStream_t)opts->stream : nullptr;
+  const size_t np = (size_t)n_plans;
+  std::vector<int64_t> cnt(np);
+  for (size_t i = 0; i < np; ++i) {
+    const std::string who = "plan " + std::to_string(i) + ": ";
+    reff_status v = host_validate_desc(&plans[i]);
+    if (v != REFF_OK) return host_fail(v, who + reff_last_error());
+    const int64_t n = (int64_t)plans[i].n_tiers * plans[i].nx * plans[i].ny;
+    const bool given = nodes && nodes[i];
+    if (given && (!n_nodes || n_nodes[i] < 0)) return host_fail(REFF_ERR_INVALID_ARG, who + "bad n_nodes");
+    cnt[i] = given ? n_nodes[i] : n;
+    if (cnt[i] > 0 && !R_out[i]) return host_fail(REFF_ERR_INVALID_ARG, who + "R_out NULL");
+    for (int64_t k = 0; given && k < cnt[i]; ++k)
+      if (nodes[i][k] < 0 || nodes[i][k] >= n)
+        return host_fail(REFF_ERR_INVALID_ARG,
+                         who + "node id " + std::to_string(nodes[i][k]) + " out of range");
+  }
+  // symbolic analysis of every plan on host threads, then one forest
+  std::vector<SelinvPlan> sp(np);
+  std::vector<std::string> err(np);
+  std::vector<char> ok(np, 0), disc(np, 0);
+  selinv_parallel_for(np, [&](size_t i) {
+    const reff_pdn_desc& d = plans[i];
+    bool dis = false;
+    ok[i] = build_selinv_plan(d.n_tiers, d.nx, d.ny, d.gx, d.gy, d.n_tsv, d.tsv_xy, d.tsv_g,
+                              d.n_pads, d.pad_xy, LEAF_AREA, sp[i], err[i], &dis);
+    disc[i] = dis;
+  });
+  for (size_t i = 0; i < np; ++i)
+    if (!ok[i])
+      return host_fail(disc[i] ? REFF_ERR_DISCONNECTED : REFF_ERR_INVALID_ARG,
+                       "plan " + std::to_string(i) + ": " + err[i]);
+  std::vector<int64_t> base;
+  const SelinvPlan P = merge_selinv_plans(sp, base);
+  sp.clear();
+  const auto t_plan = std::chrono::steady_clock::now();
+  reff_status s;
+  auto dev_sp = selinv_device_build(P, s);
+  if (!dev_sp) return s;
+  const SelinvDevice& D = *dev_sp;
+  const auto t_setup = std::chrono::steady_clock::now();
+  std::chrono::steady_clock::time_point t_fact;
+  s = selinv_run(P, D, st_, t_fact);
+  if (s != REFF_OK) return s;
+  // requested nodes of every plan, in plan order, picked into one array
+  std::vector<int64_t> ids;
+  int64_t total = 0;
+  for (size_t i = 0; i < np; ++i) total += cnt[i];
+  ids.reserve((size_t)total);
+  for (size_t i = 0; i < np; ++i) {
+    const bool given = nodes && nodes[i];
+    for (int64_t k = 0; k < cnt[i]; ++k) ids.push_back(base[i] + (given ? nodes[i][k] : k));
+  }
+  Bufs b;
+  int64_t* dids = nullptr;
+  double* dres = nullptr;
+  hipError_t e = put(b, &dids, ids, st_);
+  if (e == hipSuccess) e = b.get(&dres, (size_t)total);
+  if (e == hipSuccess && total > 0) {
+    hipLaunchKernelGGL(k_pick, flat(total), dim3(256), 0, st_, D.Rfull, dids, total, dres);
+    e = hipGetLastError();
+  }
+  std::vector<double> host;
+  if (e == hipSuccess && !out_dev) {
+    host.resize((size_t)total);
+    if (total > 0)
+      e = hipMemcpyAsync(host.data(), dres, sizeof(double) * total, hipMemcpyDeviceToHost, st_);
+  }
+  int64_t at = 0;
+  for (size_t i = 0; i < np && e == hipSuccess; ++i) {
+    if (cnt[i] > 0 && out_dev)
+      e = hipMemcpyAsync(R_out[i], dres + at, sizeof(double) * cnt[i], hipMemcpyDeviceToDevice,
+                         st_);
+    at += cnt[i];
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st_);
+  if (e != hipSuccess) return dev_status(e, "selected inversion batch");
+  if (!out_dev) {
+    at = 0;
+    for (size_t i = 0; i < np; ++i) {
+      if (cnt[i] > 0) std::memcpy(R_out[i], host.data() + at, sizeof(double) * cnt[i]);
+      at += cnt[i];
+    }
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  if (st) {
+    st->n_fronts = (int64_t)P.fronts.size();
+    st->n_levels = (int32_t)P.levels.size();
+    for (const SnFront& f : P.fronts) st->max_front = std::max<int64_t>(st->max_front, f.F);
+    st->device_bytes = D.sz.bytes;
+    st->flops_factor = P.flops_factor;
+    st->flops_selinv = P.flops_selinv;
+    st->seconds = std::chrono::duration<double>(t1 - t0).count();
+    st->seconds_plan = std::chrono::duration<double>(t_plan - t0).count();
+    st->seconds_factor = std::chrono::duration<double>(t_fact - t_plan).count();
+    st->seconds_selinv = std::chrono::duration<double>(t1 - t_fact).count();
+    st->seconds_setup = std::chrono::duration<double>(t_setup - t_plan).count();
   }
   return REFF_OK;
 }

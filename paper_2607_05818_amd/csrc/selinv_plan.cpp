@@ -2,7 +2,9 @@
 #include "selinv_plan.h"
 
 #include <algorithm>
+#include <atomic>
 #include <functional>
+#include <thread>
 
 namespace reff {
 
@@ -116,8 +118,9 @@ struct Builder {
 bool build_selinv_plan(int32_t nt, int32_t nx, int32_t ny, const double* gx, const double* gy,
                        int32_t n_tsv, const int32_t* tsv_xy, const double* tsv_g, int32_t n_pads,
                        const int32_t* pad_xy, int32_t leaf_area, SelinvPlan& plan,
-                       std::string& err) {
+                       std::string& err, bool* disconnected) {
   plan = SelinvPlan();
+  if (disconnected) *disconnected = false;
   plan.nt = nt, plan.nx = nx, plan.ny = ny;
   Builder b{nt, nx, ny, (int64_t)nx * ny, gx, gy, tsv_g, {}, {}, std::max(1, leaf_area), plan,
             {}, {}, 0};
@@ -131,6 +134,29 @@ bool build_selinv_plan(int32_t nt, int32_t nx, int32_t ny, const double* gx, con
   b.ord.assign((size_t)n, -1);
   b.rec(0, nx, 0, ny, 0);
   plan.n_free = b.next_ord;
+  {
+    // every free node must reach a pad (breadth-first search over the edges)
+    std::vector<uint8_t> seen((size_t)n, 0);
+    std::vector<int64_t> q;
+    q.reserve((size_t)n);
+    for (int64_t v = 0; v < b.plane; ++v)
+      if (b.pad[(size_t)v]) {
+        seen[(size_t)v] = 1;
+        q.push_back(v);
+      }
+    for (size_t h = 0; h < q.size(); ++h)
+      b.edges(q[h], [&](int64_t u, double) {
+        if (!seen[(size_t)u]) {
+          seen[(size_t)u] = 1;
+          q.push_back(u);
+        }
+      });
+    if ((int64_t)q.size() != n) {
+      err = std::to_string(n - (int64_t)q.size()) + " node(s) have no resistive path to a pad";
+      if (disconnected) *disconnected = true;
+      return false;
+    }
+  }
 
   // update sets, sizes, levels
   std::vector<std::vector<int64_t>> Q(plan.fronts.size());
@@ -214,6 +240,112 @@ bool build_selinv_plan(int32_t nt, int32_t nx, int32_t ny, const double* gx, con
     for (int64_t u : Q[s]) pos[(size_t)u] = -1;
   }
   return true;
+}
+
+SelinvPlan merge_selinv_plans(const std::vector<SelinvPlan>& plans, std::vector<int64_t>& base) {
+  SelinvPlan M;
+  const size_t np = plans.size();
+  base.assign(np, 0);
+  size_t nlev = 0;
+  for (const SelinvPlan& P : plans) nlev = std::max(nlev, P.levels.size());
+  M.levels.assign(nlev, SelinvLevel());
+  // offsets of every plan's fronts, maps, pivots and node ids
+  std::vector<int32_t> f0(np);
+  std::vector<int64_t> r0(np), p0(np);
+  int64_t nf = 0, nr = 0, npv = 0;
+  for (size_t i = 0; i < np; ++i) {
+    base[i] = M.n;
+    f0[i] = (int32_t)nf;
+    r0[i] = nr;
+    p0[i] = npv;
+    nf += (int64_t)plans[i].fronts.size();
+    nr += (int64_t)plans[i].rel.size();
+    npv += (int64_t)plans[i].piv_node.size();
+    M.n += plans[i].n;
+    M.n_free += plans[i].n_free;
+    M.flops_factor += plans[i].flops_factor;
+    M.flops_selinv += plans[i].flops_selinv;
+  }
+  // per level, plan-major: where each plan's fronts, entries and arena start
+  std::vector<std::vector<int64_t>> lf(nlev, std::vector<int64_t>(np + 1, 0)),
+      le(nlev, std::vector<int64_t>(np + 1, 0)), la(nlev, std::vector<int64_t>(np + 1, 0));
+  int64_t off = 0;
+  for (size_t d = 0; d < nlev; ++d) {
+    SelinvLevel& L = M.levels[d];
+    L.arena_begin = off;
+    la[d][0] = off;
+    for (size_t i = 0; i < np; ++i) {
+      int64_t cf = 0, ce = 0, ca = 0;
+      if (d < plans[i].levels.size()) {
+        const SelinvLevel& PL = plans[i].levels[d];
+        cf = (int64_t)PL.fronts.size();
+        ce = (int64_t)PL.ent_idx.size();
+        ca = PL.arena_end - PL.arena_begin;
+        L.max_panels = std::max(L.max_panels, PL.max_panels);
+        L.max_F = std::max(L.max_F, PL.max_F);
+      }
+      lf[d][i + 1] = lf[d][i] + cf;
+      le[d][i + 1] = le[d][i] + ce;
+      la[d][i + 1] = la[d][i] + ca;
+    }
+    off = la[d][np];
+    L.arena_end = off;
+    L.fronts.resize((size_t)lf[d][np]);
+    L.ent_idx.resize((size_t)le[d][np]);
+    L.ent_val.resize((size_t)le[d][np]);
+  }
+  M.arena = off;
+  M.fronts.resize((size_t)nf);
+  M.rel.resize((size_t)nr);
+  M.piv_node.resize((size_t)npv);
+  // every plan fills its own slices
+  selinv_parallel_for(np, [&](size_t i) {
+    const SelinvPlan& P = plans[i];
+    for (size_t j = 0; j < P.fronts.size(); ++j) {
+      SnFront f = P.fronts[j];
+      if (f.parent >= 0) f.parent += f0[i];
+      f.rel += r0[i];
+      f.piv += p0[i];
+      M.fronts[(size_t)f0[i] + j] = f;
+    }
+    std::copy(P.rel.begin(), P.rel.end(), M.rel.begin() + r0[i]);
+    for (size_t j = 0; j < P.piv_node.size(); ++j)
+      M.piv_node[(size_t)p0[i] + j] = P.piv_node[j] + base[i];
+    for (size_t d = 0; d < P.levels.size(); ++d) {
+      const SelinvLevel& PL = P.levels[d];
+      SelinvLevel& L = M.levels[d];
+      // the level's arena moves from PL.arena_begin to la[d][i]; fronts keep
+      // their order, so every front and entry shifts by the same amount
+      const int64_t shift = la[d][i] - PL.arena_begin;
+      for (size_t j = 0; j < PL.fronts.size(); ++j) {
+        const int32_t fi = f0[i] + PL.fronts[j];
+        L.fronts[(size_t)lf[d][i] + j] = fi;
+        M.fronts[(size_t)fi].off = P.fronts[(size_t)PL.fronts[j]].off + shift;
+      }
+      const size_t e0 = (size_t)le[d][i];
+      for (size_t e = 0; e < PL.ent_idx.size(); ++e) {
+        L.ent_idx[e0 + e] = PL.ent_idx[e] + shift;
+        L.ent_val[e0 + e] = PL.ent_val[e];
+      }
+    }
+  });
+  return M;
+}
+
+void selinv_parallel_for(size_t count, const std::function<void(size_t)>& body) {
+  const size_t hw = std::max<unsigned>(1, std::thread::hardware_concurrency());
+  const size_t nthr = std::min<size_t>({hw, (size_t)16, count});
+  if (nthr <= 1) {
+    for (size_t i = 0; i < count; ++i) body(i);
+    return;
+  }
+  std::atomic<size_t> next{0};
+  std::vector<std::thread> pool;
+  for (size_t t = 0; t < nthr; ++t)
+    pool.emplace_back([&]() {
+      for (size_t i = next++; i < count; i = next++) body(i);
+    });
+  for (auto& th : pool) th.join();
 }
 
 }  // namespace reff

@@ -23,6 +23,7 @@
 
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -61,13 +62,23 @@ struct SelinvPlan {
   double flops_factor = 0.0, flops_selinv = 0.0;
 };
 
+// Several plans as one (a forest): fronts, maps and node ids offset plan by
+// plan (plan i's node v becomes base[i] + v), levels merged by depth, the
+// arena laid out again level by level.  base receives each plan's first
+// node id.
+SelinvPlan merge_selinv_plans(const std::vector<SelinvPlan>& plans, std::vector<int64_t>& base);
+
+// Run body(i) for i < count on up to 16 host threads.
+void selinv_parallel_for(size_t count, const std::function<void(size_t)>& body);
+
 // Build the plan from the stack description (arrays as in reff_pdn_desc:
 // gx [nt][ny][nx-1], gy [nt][ny-1][nx], tsv_xy [n_tsv][2], tsv_g
 // [n_tsv][nt-1], pads on tier 0).  Returns false with `err` set on
-// inconsistent input (a node without conductance to anything).
+// inconsistent input, or when some node has no resistive path to a pad
+// (G singular; breadth-first search from the pads).
 bool build_selinv_plan(int32_t nt, int32_t nx, int32_t ny, const double* gx, const double* gy,
                        int32_t n_tsv, const int32_t* tsv_xy, const double* tsv_g, int32_t n_pads,
                        const int32_t* pad_xy, int32_t leaf_area, SelinvPlan& plan,
-                       std::string& err);
+                       std::string& err, bool* disconnected = nullptr);
 
 }  // namespace reff

@@ -97,6 +97,7 @@ class reff_selinv_stats(C.Structure):
         ("max_front", C.c_int64), ("device_bytes", C.c_int64), ("flops_factor", C.c_double),
         ("flops_selinv", C.c_double), ("seconds", C.c_double), ("seconds_plan", C.c_double),
         ("seconds_factor", C.c_double), ("seconds_selinv", C.c_double),
+        ("seconds_setup", C.c_double),
     ]
 
     def as_dict(self):
@@ -146,6 +147,11 @@ _lib.reff_selinv_diag.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
 _lib.reff_selinv_diag.restype = C.c_int
 _lib.reff_selinv_info.argtypes = [C.POINTER(reff_pdn_desc), C.POINTER(reff_selinv_stats)]
 _lib.reff_selinv_info.restype = C.c_int
+_lib.reff_selinv_batch.argtypes = [C.POINTER(reff_pdn_desc), C.c_int32,
+                                   C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_void_p), C.POINTER(reff_solve_opts),
+                                   C.POINTER(reff_selinv_stats)]
+_lib.reff_selinv_batch.restype = C.c_int
 _lib.reff_stream_probe.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                    C.c_void_p]
 _lib.reff_stream_probe.restype = C.c_int
@@ -314,6 +320,46 @@ def reff_selinv_diag(pdn: PDN, nodes=None, R_out=None, *, stream=None):
     _check(_lib.reff_selinv_diag(pdn.handle, nptr, count if nodes is not None else 0, optr,
                                  C.byref(o), C.byref(st)))
     return R_out, st.as_dict()
+
+
+def reff_selinv_batch(plans, nodes=None, R_out=None, *, stream=None):
+    """reff_selinv_diag for many stack descriptors in one call (no handle).
+    Returns (list of R arrays, stats)."""
+    k = len(plans)
+    structs = (reff_pdn_desc * k)()
+    keep = []
+    for i, d in enumerate(plans):
+        st_, kp = _desc_struct(d)
+        structs[i] = st_
+        keep.append(kp)
+    nptrs = (C.c_void_p * k)()
+    ncount = (C.c_int64 * k)()
+    optrs = (C.c_void_p * k)()
+    outs, node_arrs = [], []
+    out_dev = False
+    for i, d in enumerate(plans):
+        if nodes is None or nodes[i] is None:
+            nptrs[i] = None
+            cnt = int(d["n_tiers"]) * int(d["nx"]) * int(d["ny"])
+        else:
+            arr = np.ascontiguousarray(nodes[i], dtype=np.int64)
+            node_arrs.append(arr)
+            nptrs[i] = arr.ctypes.data
+            cnt = len(arr)
+        ncount[i] = cnt
+        if R_out is not None:
+            o = R_out[i]
+            out_dev = _is_torch_cuda(o)
+            optrs[i] = o.data_ptr() if out_dev else o.ctypes.data
+        else:
+            o = np.empty(cnt, dtype=np.float64)
+            optrs[i] = o.ctypes.data
+        outs.append(o)
+    o = _opts(REFF_PREC_FP64, 0.0, 0, REFF_KRYLOV_BLOCK, stream, out_dev, 0)
+    st = reff_selinv_stats()
+    _check(_lib.reff_selinv_batch(structs, k, nptrs, ncount, optrs, C.byref(o), C.byref(st)))
+    del keep, node_arrs
+    return outs, st.as_dict()
 
 
 def reff_stream_probe(kind, src, dst, nbytes, blocks, stream=None):

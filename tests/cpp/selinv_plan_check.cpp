@@ -22,38 +22,53 @@ static void chk(bool c, const char* m) {
   }
 }
 
-int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
+struct Stack {
+  int nt, nx, ny, ntsv, npad;
+  std::vector<double> gx, gy, tg;
+  std::vector<int32_t> txy, pxy;
+};
+
+static Stack make_stack(int seed, int nt, int nx, int ny, int ntsv, int npad) {
+  Stack S{nt, nx, ny, ntsv, npad, {}, {}, {}, {}, {}};
   std::mt19937_64 rng(seed);
   std::uniform_real_distribution<double> U(0.5, 2.0);
-  std::vector<double> gx((size_t)nt * ny * std::max(nx - 1, 0)), gy((size_t)nt * std::max(ny - 1, 0) * nx);
-  for (auto& v : gx) v = U(rng);
-  for (auto& v : gy) v = U(rng);
-  std::vector<int32_t> txy, pxy;
+  S.gx.resize((size_t)nt * ny * std::max(nx - 1, 0));
+  S.gy.resize((size_t)nt * std::max(ny - 1, 0) * nx);
+  for (auto& v : S.gx) v = U(rng);
+  for (auto& v : S.gy) v = U(rng);
   std::vector<char> used((size_t)nx * ny, 0);
   for (int j = 0; j < ntsv; ++j) {
     int x, y;
     do { x = rng() % nx; y = rng() % ny; } while (used[(size_t)y * nx + x]);
     used[(size_t)y * nx + x] = 1;
-    txy.push_back(x); txy.push_back(y);
+    S.txy.push_back(x); S.txy.push_back(y);
   }
-  if (nt > 1 && ntsv == 0) { txy = {0, 0}; ntsv = 1; }
-  std::vector<double> tg((size_t)ntsv * std::max(nt - 1, 0));
-  for (auto& v : tg) v = U(rng) * 3;
-  for (int j = 0; j < npad; ++j) { pxy.push_back(rng() % nx); pxy.push_back(rng() % ny); }
-  SelinvPlan P;
+  if (nt > 1 && ntsv == 0) { S.txy = {0, 0}; S.ntsv = 1; }
+  S.tg.resize((size_t)S.ntsv * std::max(nt - 1, 0));
+  for (auto& v : S.tg) v = U(rng) * 3;
+  for (int j = 0; j < npad; ++j) { S.pxy.push_back(rng() % nx); S.pxy.push_back(rng() % ny); }
+  return S;
+}
+
+static bool plan_of(const Stack& S, int leaf, SelinvPlan& P) {
   std::string err;
-  if (!build_selinv_plan(nt, nx, ny, gx.data(), gy.data(), ntsv, txy.data(), tg.data(), npad, pxy.data(), leaf, P, err)) {
+  if (!build_selinv_plan(S.nt, S.nx, S.ny, S.gx.data(), S.gy.data(), S.ntsv, S.txy.data(),
+                         S.tg.data(), S.npad, S.pxy.data(), leaf, P, err)) {
     fprintf(stderr, "plan error %s\n", err.c_str());
-    return 1;
+    return false;
   }
-  const int64_t n = P.n, plane = (int64_t)nx * ny;
-  // dense G over free nodes
+  return true;
+}
+
+// diag(G^-1) by Gauss-Jordan on the dense grounded matrix; 0 on pads.
+static std::vector<double> dense_diag(const Stack& S) {
+  const int nt = S.nt, nx = S.nx, ny = S.ny;
+  const int64_t plane = (int64_t)nx * ny, n = plane * nt;
   std::vector<char> pad((size_t)n, 0);
-  for (int j = 0; j < npad; ++j) pad[(size_t)(pxy[2 * j + 1] * nx + pxy[2 * j])] = 1;
+  for (int j = 0; j < S.npad; ++j) pad[(size_t)(S.pxy[2 * j + 1] * nx + S.pxy[2 * j])] = 1;
   std::vector<int64_t> fid((size_t)n, -1);
   int64_t nf = 0;
   for (int64_t v = 0; v < n; ++v) if (!pad[v]) fid[v] = nf++;
-  chk(nf == P.n_free, "n_free");
   std::vector<double> G((size_t)(nf * nf), 0.0);
   auto add = [&](int64_t a, int64_t b, double g) {
     if (fid[a] >= 0) G[fid[a] * nf + fid[a]] += g;
@@ -64,15 +79,14 @@ int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         int64_t v = t * plane + (int64_t)y * nx + x;
-        if (x + 1 < nx) add(v, v + 1, gx[(size_t)(t * ny + y) * (nx - 1) + x]);
-        if (y + 1 < ny) add(v, v + nx, gy[(size_t)(t * (ny - 1) + y) * nx + x]);
+        if (x + 1 < nx) add(v, v + 1, S.gx[(size_t)(t * ny + y) * (nx - 1) + x]);
+        if (y + 1 < ny) add(v, v + nx, S.gy[(size_t)(t * (ny - 1) + y) * nx + x]);
       }
-  for (int j = 0; j < ntsv; ++j)
+  for (int j = 0; j < S.ntsv; ++j)
     for (int t = 0; t + 1 < nt; ++t) {
-      int64_t v = t * plane + (int64_t)txy[2 * j + 1] * nx + txy[2 * j];
-      add(v, v + plane, tg[(size_t)j * (nt - 1) + t]);
+      int64_t v = t * plane + (int64_t)S.txy[2 * j + 1] * nx + S.txy[2 * j];
+      add(v, v + plane, S.tg[(size_t)j * (nt - 1) + t]);
     }
-  // dense inverse via Gauss-Jordan
   std::vector<double> A = G, Inv((size_t)(nf * nf), 0.0);
   for (int64_t i = 0; i < nf; ++i) Inv[i * nf + i] = 1;
   for (int64_t c = 0; c < nf; ++c) {
@@ -85,10 +99,18 @@ int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
       for (int64_t j = 0; j < nf; ++j) { A[r * nf + j] -= f * A[c * nf + j]; Inv[r * nf + j] -= f * Inv[c * nf + j]; }
     }
   }
-  // numeric multifrontal on host arena
+  std::vector<double> R((size_t)n, 0.0);
+  for (int64_t v = 0; v < n; ++v) if (fid[v] >= 0) R[v] = Inv[fid[v] * nf + fid[v]];
+  return R;
+}
+
+// The panel factorisation and block Takahashi recurrence of the device
+// kernels, as plain loops over a plan (any forest); R per node id.
+static std::vector<double> numeric(const SelinvPlan& P) {
   std::vector<double> ar((size_t)P.arena, 0.0);
   auto at = [&](const SnFront& f, int64_t r, int64_t c) -> double& {
     chk(r >= 0 && r < f.F && c >= 0 && c < f.F, "front index");
+    chk(f.off + c * f.F + r < P.arena, "arena index");
     return ar[(size_t)(f.off + c * f.F + r)];
   };
   for (int d = (int)P.levels.size() - 1; d >= 0; --d) {
@@ -97,7 +119,6 @@ int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
       chk(L.ent_idx[e] >= L.arena_begin && L.ent_idx[e] < L.arena_end, "entry range");
       ar[(size_t)L.ent_idx[e]] += L.ent_val[e];
     }
-    // extend-add from children (next level)
     if (d + 1 < (int)P.levels.size())
       for (int32_t ci : P.levels[(size_t)d + 1].fronts) {
         const SnFront& c = P.fronts[(size_t)ci];
@@ -116,24 +137,21 @@ int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
       const SnFront& f = P.fronts[(size_t)fi];
       for (int j0 = 0; j0 < f.k; j0 += 64) {
         int w = std::min(64, f.k - j0);
-        // potrf tile
         for (int c = j0; c < j0 + w; ++c) {
           double piv = at(f, c, c);
           chk(piv > 0, "front pivot");
-          double s = std::sqrt(piv);
-          at(f, c, c) = s;
-          for (int r = c + 1; r < j0 + w; ++r) at(f, r, c) /= s;
+          double sq = std::sqrt(piv);
+          at(f, c, c) = sq;
+          for (int r = c + 1; r < j0 + w; ++r) at(f, r, c) /= sq;
           for (int cc = c + 1; cc < j0 + w; ++cc)
             for (int r = cc; r < j0 + w; ++r) at(f, r, cc) -= at(f, r, c) * at(f, cc, c);
         }
-        // trsm rows below: X Ljj^T = A
         for (int r = j0 + w; r < f.F; ++r)
           for (int c = j0; c < j0 + w; ++c) {
             double v = at(f, r, c);
             for (int t = j0; t < c; ++t) v -= at(f, r, t) * at(f, c, t);
             at(f, r, c) = v / at(f, c, c);
           }
-        // syrk trailing lower
         for (int c = j0 + w; c < f.F; ++c)
           for (int r = c; r < f.F; ++r) {
             double v = 0;
@@ -143,11 +161,9 @@ int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
       }
     }
   }
-  // selinv top-down
-  std::vector<double> R((size_t)n, 0.0);
+  std::vector<double> R((size_t)P.n, 0.0);
   for (size_t d = 0; d < P.levels.size(); ++d) {
-    const SelinvLevel& L = P.levels[d];
-    for (int32_t fi : L.fronts) {
+    for (int32_t fi : P.levels[d].fronts) {
       const SnFront& f = P.fronts[(size_t)fi];
       const int32_t q = f.F - f.k;
       if (f.parent >= 0) {
@@ -156,10 +172,8 @@ int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
           for (int a = 0; a < q; ++a)
             at(f, f.k + a, f.k + b) = at(p, P.rel[(size_t)(f.rel + a)], P.rel[(size_t)(f.rel + b)]);
       } else chk(q == 0, "root with update set");
-      int np = (f.k + 63) / 64;
-      for (int jp = np - 1; jp >= 0; --jp) {
+      for (int jp = (f.k + 63) / 64 - 1; jp >= 0; --jp) {
         int j0 = 64 * jp, w = std::min(64, f.k - j0), r0 = j0 + w, m = f.F - r0;
-        // Linv
         std::vector<double> Li(64 * 64, 0.0), Z0(64 * 64, 0.0);
         for (int c = 0; c < w; ++c)
           for (int i = 0; i < w; ++i) {
@@ -173,7 +187,6 @@ int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
             for (int c = std::max(a, bb); c < w; ++c) v += Li[c * 64 + a] * Li[c * 64 + bb];
             Z0[a * 64 + bb] = v;
           }
-        // Lhat = L[R,P] Linv
         std::vector<double> Lh((size_t)m * w), Y((size_t)m * w, 0.0);
         for (int r = 0; r < m; ++r)
           for (int c = 0; c < w; ++c) {
@@ -184,7 +197,7 @@ int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
         for (int r = 0; r < m; ++r)
           for (int c = 0; c < w; ++c) {
             double v = 0;
-            for (int s = 0; s < m; ++s) v -= at(f, r0 + r, r0 + s) * Lh[(size_t)s * w + c];
+            for (int t = 0; t < m; ++t) v -= at(f, r0 + r, r0 + t) * Lh[(size_t)t * w + c];
             Y[(size_t)r * w + c] = v;
           }
         for (int a = 0; a < w; ++a)
@@ -202,14 +215,49 @@ int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
       }
     }
   }
+  return R;
+}
+
+static double worst_rel(const std::vector<double>& got, const double* want, int64_t n) {
   double worst = 0;
   for (int64_t v = 0; v < n; ++v) {
-    if (fid[v] < 0) { chk(R[v] == 0, "pad zero"); continue; }
-    double want = Inv[fid[v] * nf + fid[v]];
-    worst = std::max(worst, std::fabs(R[v] - want) / want);
+    if (want[v] == 0) { chk(got[v] == 0, "pad zero"); continue; }
+    worst = std::max(worst, std::fabs(got[v] - want[v]) / want[v]);
   }
-  printf("seed %d %dx%dx%d tsv %d pads %d leaf %d: fronts %zu levels %zu arena %lld worst %.3e\n", seed, nt, nx, ny, ntsv, npad, leaf,
-         P.fronts.size(), P.levels.size(), (long long)P.arena, worst);
+  return worst;
+}
+
+int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
+  const Stack S = make_stack(seed, nt, nx, ny, ntsv, npad);
+  SelinvPlan P;
+  if (!plan_of(S, leaf, P)) return 1;
+  const std::vector<double> want = dense_diag(S);
+  const double worst = worst_rel(numeric(P), want.data(), P.n);
+  printf("seed %d %dx%dx%d tsv %d pads %d leaf %d: fronts %zu levels %zu arena %lld worst %.3e\n",
+         seed, nt, nx, ny, ntsv, npad, leaf, P.fronts.size(), P.levels.size(),
+         (long long)P.arena, worst);
+  return worst < 1e-10 ? 0 : 1;
+}
+
+// Several stacks merged into one forest (the batched path): each plan's
+// segment of the merged result against its own dense inverse.
+int run_merged() {
+  const Stack S[3] = {make_stack(21, 2, 17, 9, 6, 2), make_stack(22, 3, 6, 13, 4, 1),
+                      make_stack(23, 1, 30, 20, 0, 3)};
+  std::vector<SelinvPlan> plans(3);
+  for (int i = 0; i < 3; ++i)
+    if (!plan_of(S[i], 16, plans[i])) return 1;
+  std::vector<int64_t> base;
+  const SelinvPlan M = merge_selinv_plans(plans, base);
+  const std::vector<double> R = numeric(M);
+  double worst = 0;
+  for (int i = 0; i < 3; ++i) {
+    const std::vector<double> want = dense_diag(S[i]);
+    std::vector<double> seg(R.begin() + base[i], R.begin() + base[i] + plans[i].n);
+    worst = std::max(worst, worst_rel(seg, want.data(), plans[i].n));
+  }
+  printf("merged forest of 3 stacks: fronts %zu levels %zu worst %.3e\n", M.fronts.size(),
+         M.levels.size(), worst);
   return worst < 1e-10 ? 0 : 1;
 }
 
@@ -228,6 +276,7 @@ int main() {
   bad |= run(11, 3, 30, 1, 5, 1, 4);
   bad |= run(12, 2, 70, 20, 30, 4, 16);
   bad |= run(14, 8, 16, 14, 12, 2, 16);
+  bad |= run_merged();
   printf(bad ? "FAILED\n" : "all ok\n");
   return bad;
 }

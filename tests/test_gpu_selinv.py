@@ -128,3 +128,64 @@ def test_config2_full_map():
     want = osel.solve_nodes(d, ids)
     assert _max_rel(got[ids], want) <= TOL
     h.close()
+
+
+def test_batch_of_ragged_plans_matches_unit_solves_and_single_calls():
+    """reff_selinv_batch over plans of different shapes and depths (their
+    dissection trees merged by depth): all nodes of some plans, subsets
+    with duplicates and pads of others, host and device output; every value
+    against the oracle's unit solves (1e-10) and against reff_selinv_diag of
+    the plan alone (1e-12: the batch may split products differently)."""
+    import torch
+    reff = _reff()
+    shapes = [(201, 2, 17, 19, 9, 5), (202, 1, 7, 5, 0, 1), (203, 4, 10, 10, 6, 3),
+              (204, 3, 40, 33, 30, 6), (205, 1, 1, 1, 0, 1), (206, 8, 9, 7, 12, 3)]
+    plans = [gen.small_random_desc(s, nt, nx, ny, max(k, 1 if nt > 1 else 0), p)
+             for s, nt, nx, ny, k, p in shapes]
+    rng = np.random.default_rng(77)
+    nodes = []
+    for i, d in enumerate(plans):
+        if i % 2 == 0:
+            nodes.append(None)
+        else:
+            ids = rng.integers(0, gen.n_nodes(d), size=50)
+            ids[:2] = ro.pad_nodes(d)[:1].repeat(2)
+            nodes.append(ids)
+    _say("selinv batch of 6 ragged plans")
+    outs, st = reff.reff_selinv_batch(plans, nodes)
+    print(st, flush=True)
+    dev = [torch.empty(gen.n_nodes(d) if nodes[i] is None else len(nodes[i]),
+                       dtype=torch.float64, device="cuda") for i, d in enumerate(plans)]
+    reff.reff_selinv_batch(plans, nodes, dev)
+    torch.cuda.synchronize()
+    for i, d in enumerate(plans):
+        want = ro.diag(d, nodes[i])
+        assert _max_rel(outs[i], want) <= TOL
+        assert np.array_equal(dev[i].cpu().numpy(), outs[i])
+        h = reff.reff_build_pdn(d)
+        alone, _ = reff.reff_selinv_diag(h, nodes[i])
+        h.close()
+        m = alone > 0
+        assert np.all(outs[i][~m] == 0.0)
+        if m.any():  # a 1 x 1 x 1 stack is all pad
+            assert np.max(np.abs(outs[i][m] - alone[m]) / alone[m]) <= 1e-12
+
+
+def test_batch_all_256_recipe_plans_against_stored_oracle_values():
+    """The batching workload (256 plans, 2-4 tiers, sides 64-256, 21.1M
+    nodes) in one reff_selinv_batch call: the seeded 64-node block of every
+    plan against the oracle's float64 values stored in
+    tests/golden/config3_sample.json, at the float64 bar."""
+    import json
+    import os
+    reff = _reff()
+    plans = gen.config3_plans()
+    nodes = gen.config3_samples(plans)
+    gold = json.load(open(os.path.join(HERE, "golden", "config3_sample.json")))
+    assert [list(x) for x in nodes] == gold["nodes"], "sample drifted from the fixture"
+    _say("selinv batch, all 256 recipe plans")
+    outs, st = reff.reff_selinv_batch(plans, nodes)
+    print({k: v for k, v in st.items()}, flush=True)
+    worst = max(_max_rel(outs[i], np.array(gold["R"][i])) for i in range(len(plans)))
+    print("worst relative error over 16,384 nodes", worst, flush=True)
+    assert worst <= TOL

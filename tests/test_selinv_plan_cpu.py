@@ -1,7 +1,9 @@
 """Host-side checks of the sparse-direct full map (no GPU): the plan query
-of the C ABI, and tests/cpp/selinv_plan_check.cpp, which drives the
-library's symbolic plan through the panel factorisation and Takahashi
-recurrence as plain loops against a dense inverse of G."""
+of the C ABI, the batch entry point's host-side rejections, and
+tests/cpp/selinv_plan_check.cpp, which drives the library's symbolic plan
+(single stacks, and several stacks merged into one forest as the batch
+does) through the panel factorisation and Takahashi recurrence as plain
+loops against dense inverses of G."""
 import os
 import shutil
 import subprocess
@@ -20,7 +22,7 @@ def test_plan_and_panel_algorithm_match_dense_inverse(tmp_path):
     subprocess.run(["g++", "-O2", "-std=c++17", "-o", exe,
                     os.path.join(HERE, "cpp", "selinv_plan_check.cpp"),
                     os.path.join(CSRC, "selinv_plan.cpp")], check=True)
-    r = subprocess.run([exe], capture_output=True, text=True, timeout=600)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=900)
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "all ok" in r.stdout
@@ -47,3 +49,33 @@ def test_plan_query_rejects_bad_descriptors():
     d["pad_xy"] = [[9, 9]]
     with pytest.raises(reff.ReffError):
         reff.reff_selinv_info(d)
+
+
+@pytest.mark.parametrize("case", ["disconnected", "node_range", "bad_plan", "empty"])
+def test_batch_rejections_on_the_host(case):
+    """reff_selinv_batch validates and analyses every plan on the host before
+    any device work: a plan whose second tier has no TSV column (G
+    singular), a node id out of range and an invalid descriptor are
+    refused with the plan named; an empty batch is a no-op."""
+    import numpy as np
+    from paper_2607_05818_amd import reff
+    good = gen.small_random_desc(31, 2, 6, 5, 3, 2)
+    if case == "empty":
+        outs, st = reff.reff_selinv_batch([])
+        assert outs == [] and st["n_fronts"] == 0
+        return
+    other = dict(good)
+    nodes = None
+    want = reff.REFF_ERR_INVALID_ARG
+    if case == "disconnected":
+        other["tsv_xy"] = np.zeros((0, 2), dtype=np.int32)
+        other["tsv_g"] = np.zeros((0, 1))
+        want = reff.REFF_ERR_DISCONNECTED
+    elif case == "node_range":
+        nodes = [None, [0, gen.n_nodes(good)]]
+    else:
+        other["pad_xy"] = [[99, 0]]
+    with pytest.raises(reff.ReffError) as ei:
+        reff.reff_selinv_batch([good, other], nodes)
+    assert ei.value.status == want
+    assert "plan 1" in reff.reff_last_error()
