@@ -546,7 +546,8 @@ def direct_full_map_compare(reff, log, h, n, reps=3):
     return rec
 
 
-def surrogate_scale_run(reff, gen, log, n_train=4000, labels=1024, epochs=24, n_test=32):
+def surrogate_scale_run(reff, gen, log, n_train=4000, labels=1024, epochs=24, n_test=32,
+                        label_source="pcg"):
     """The learned screen at its full training scale (3 tiers of 128 x 128):
     labels for `labels` seeded nodes of each of n_train plans from batched
     mixed solves (rel_tol 1e-4, 500 plans per call), Adam with a step
@@ -560,15 +561,25 @@ def surrogate_scale_run(reff, gen, log, n_train=4000, labels=1024, epochs=24, n_
     rng = np.random.default_rng(gen.CONFIG_SEEDS[4])
     plans = [gen.config4_plan(rng) for _ in range(n_train + n_test)]
     train, test = plans[:n_train], plans[n_train:]
-    lab_nodes = [gen.sample_free_nodes(d, labels, np.random.SeedSequence([4, i]))
-                 for i, d in enumerate(train)]
     a = time.perf_counter()
-    lab_R = []
-    for c0 in range(0, n_train, 500):
-        r, _ = reff.reff_batch_plans(train[c0:c0 + 500], lab_nodes[c0:c0 + 500],
-                                     precision=reff.REFF_PREC_MIXED, rel_tol=1e-4)
-        lab_R += r
-        log(f"labels {min(c0 + 500, n_train)}/{n_train}, {time.perf_counter() - a:.0f} s")
+    lab_nodes, lab_R = [], []
+    if label_source == "direct":
+        # every free node of every training plan, exact (sparse-direct maps)
+        for c0 in range(0, n_train, 500):
+            maps, _ = reff.reff_selinv_batch(train[c0:c0 + 500])
+            for m in maps:
+                free = np.flatnonzero(m > 0)
+                lab_nodes.append(free)
+                lab_R.append(m[free])
+            log(f"labels {min(c0 + 500, n_train)}/{n_train}, {time.perf_counter() - a:.0f} s")
+    else:
+        lab_nodes = [gen.sample_free_nodes(d, labels, np.random.SeedSequence([4, i]))
+                     for i, d in enumerate(train)]
+        for c0 in range(0, n_train, 500):
+            r, _ = reff.reff_batch_plans(train[c0:c0 + 500], lab_nodes[c0:c0 + 500],
+                                         precision=reff.REFF_PREC_MIXED, rel_tol=1e-4)
+            lab_R += r
+            log(f"labels {min(c0 + 500, n_train)}/{n_train}, {time.perf_counter() - a:.0f} s")
     t_label = time.perf_counter() - a
     # exact held-out maps by the direct method
     exact, t_direct = [], []
@@ -613,8 +624,10 @@ def surrogate_scale_run(reff, gen, log, n_train=4000, labels=1024, epochs=24, n_
             "plans_accepted": int(sum(x["screened"] for x in st)), "seconds": t,
             "gain_vs_solver": t_solver / t, "spot_err_min": spot[0],
             "spot_err_median": spot[len(spot) // 2]}
-    rec = {"workload": f"3 x 128 x 128 plans: {n_train} training plans x {labels} labelled "
-                       f"nodes, {n_test} held-out plans (all nodes)",
+    nl = "every free node (sparse-direct maps)" if label_source == "direct" else \
+        f"{labels} block-PCG"
+    rec = {"workload": f"3 x 128 x 128 plans: {n_train} training plans x {nl} labelled "
+                       f"nodes, {n_test} held-out plans (all nodes)", "labels": label_source,
            "label_seconds": t_label, "train_seconds": t_train, "epochs": epochs,
            "loss_first_last": [float(hist[0]), float(hist[-1])],
            "model_err_held_out_full_maps": q, "solver_full_maps_seconds": t_solver,
@@ -826,6 +839,9 @@ def main():
     ap.add_argument("--surrogate-scale", action="store_true",
                     help="the learned screen at 4000 training plans x 1024 labels, "
                          "32 held-out exact maps; prints that record (several minutes)")
+    ap.add_argument("--surrogate-labels", choices=["pcg", "direct"], default="pcg",
+                    help="--surrogate-scale: labels from 1024 block-PCG nodes per plan, or "
+                         "every node of each plan's sparse-direct map")
     ap.add_argument("--direct-only", action="store_true",
                     help="only the sparse-direct all-node map of the 4 x 512 x 512 stack "
                          "(reff_selinv_diag); prints that leg's record")
@@ -874,7 +890,8 @@ def main():
         full_map_run(args, reff, gen, log)
         return
     if args.surrogate_scale:
-        print(json.dumps(surrogate_scale_run(reff, gen, log)), flush=True)
+        print(json.dumps(surrogate_scale_run(reff, gen, log,
+                                             label_source=args.surrogate_labels)), flush=True)
         return
     if args.direct_only:
         if args.direct_side == 512:
