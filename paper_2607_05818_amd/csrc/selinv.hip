@@ -150,40 +150,43 @@ __global__ void k_scatter(const int64_t* __restrict__ idx, const double* __restr
 }
 
 // Extend-add: the lower triangle of each rank-`rank` child's update matrix
-// (its trailing (F-k) x (F-k) block) into its parent at rel x rel.
+// (its trailing (F-k) x (F-k) block) into its parent at rel x rel.  One wave
+// per column b of the update matrix (four per workgroup, blockIdx.x walks
+// the columns), its lanes down the rows a >= b: the child's column is read
+// contiguously and the parent's rows rel[a] are increasing.
 __global__ __launch_bounds__(256) void k_extend_add(const DFront* __restrict__ fr,
                                                     const int32_t* __restrict__ list, int nf,
                                                     int rank, const int32_t* __restrict__ rel,
                                                     double* ar) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int fi = blockIdx.y; fi < nf; fi += gridDim.y) {
     const DFront f = fr[list[fi]];
     if (f.poff < 0 || f.rank != rank) continue;
-    const int64_t q = f.F - f.k;
+    const int q = f.F - f.k;
     const int32_t* rl = rel + f.rel;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < q * q;
-         e += (int64_t)gridDim.x * blockDim.x) {
-      const int64_t b = e / q, a = e % q;
-      if (a < b) continue;
-      ar[f.poff + (int64_t)rl[b] * f.pF + rl[a]] +=
-          ar[f.off + (f.k + b) * (int64_t)f.F + f.k + a];
+    for (int b = blockIdx.x * 4 + w; b < q; b += gridDim.x * 4) {
+      const double* src = ar + f.off + (int64_t)(f.k + b) * f.F + f.k;
+      double* dst = ar + f.poff + (int64_t)rl[b] * f.pF;
+      for (int a = b + lane; a < q; a += 64) dst[rl[a]] += src[a];
     }
   }
 }
 
-// Z_QQ of each front (full square) from its parent's finished block.
+// Z_QQ of each front (full square) from its parent's finished block; one
+// wave per column as in k_extend_add.
 __global__ __launch_bounds__(256) void k_gather(const DFront* __restrict__ fr,
                                                 const int32_t* __restrict__ list, int nf,
                                                 const int32_t* __restrict__ rel, double* ar) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int fi = blockIdx.y; fi < nf; fi += gridDim.y) {
     const DFront f = fr[list[fi]];
     if (f.poff < 0) continue;
-    const int64_t q = f.F - f.k;
+    const int q = f.F - f.k;
     const int32_t* rl = rel + f.rel;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < q * q;
-         e += (int64_t)gridDim.x * blockDim.x) {
-      const int64_t b = e / q, a = e % q;
-      ar[f.off + (f.k + b) * (int64_t)f.F + f.k + a] =
-          ar[f.poff + (int64_t)rl[b] * f.pF + rl[a]];
+    for (int b = blockIdx.x * 4 + w; b < q; b += gridDim.x * 4) {
+      double* dst = ar + f.off + (int64_t)(f.k + b) * f.F + f.k;
+      const double* src = ar + f.poff + (int64_t)rl[b] * f.pF;
+      for (int a = lane; a < q; a += 64) dst[a] = src[rl[a]];
     }
   }
 }
@@ -224,6 +227,7 @@ __global__ __launch_bounds__(256) void k_tile(const DFront* __restrict__ fr,
     if (FACTOR) {
 #pragma unroll
       for (int c = 0; c < PT; ++c) {
+        if (c >= w) break;  // the rest of the tile is identity padding
         double* bf = buf[c & 1];
         if (g == (c & 3)) bf[r] = v[c >> 2];
         __syncthreads();
@@ -252,6 +256,7 @@ __global__ __launch_bounds__(256) void k_tile(const DFront* __restrict__ fr,
     for (int j = 0; j < 16; ++j) v[j] = (g + 4 * j == r) ? 1.0 : 0.0;
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
+      if (k >= w) break;  // rows past the panel width keep the identity
       double* bk = buf[k & 1];
       if (g == (k & 3)) {
         v[k >> 2] /= T[k][k];
@@ -276,7 +281,7 @@ __global__ __launch_bounds__(256) void k_tile(const DFront* __restrict__ fr,
       double z[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) z[j] = 0.0;
-      for (int k = 0; k < PT; ++k) {
+      for (int k = 0; k < w; ++k) {  // the inverse is block diagonal past w
         const double xr = T[k][r];
 #pragma unroll
         for (int j = 0; j < 16; ++j) z[j] += xr * T[k][g + 4 * j];
@@ -734,8 +739,7 @@ reff_status selinv_run(const SelinvPlan& P, const SelinvDevice& D, hipStream_t s
     if (d + 1 < nlev)
       for (int rank = 0; rank < 2; ++rank)
         for (const GroupDev& C : D.lv[(size_t)d + 1].groups) {
-          const unsigned gx = (unsigned)std::max<int64_t>(
-              1, std::min<int64_t>((C.maxq * C.maxq + 255) / 256, 1024));
+          const unsigned gx = (unsigned)std::max<int64_t>(1, (C.maxq + 3) / 4);
           hipLaunchKernelGGL(k_extend_add, dim3(gx, gy(C.nf)), dim3(256), 0, st_, dF,
                              dl + C.list_off, C.nf, rank, rel, ar);
         }
@@ -767,7 +771,7 @@ reff_status selinv_run(const SelinvPlan& P, const SelinvDevice& D, hipStream_t s
     for (const GroupDev& G : V.groups) {
       const int32_t* l = dl + G.list_off;
       if (d > 0 && G.maxq > 0) {
-        const unsigned gx = (unsigned)std::min<int64_t>((G.maxq * G.maxq + 255) / 256, 1024);
+        const unsigned gx = (unsigned)std::max<int64_t>(1, (G.maxq + 3) / 4);
         hipLaunchKernelGGL(k_gather, dim3(gx, gy(G.nf)), dim3(256), 0, st_, dF, l, G.nf, rel,
                            ar);
       }
