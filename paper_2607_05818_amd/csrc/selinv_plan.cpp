@@ -68,42 +68,64 @@ struct Builder {
     return id;
   }
 
-  // Free nodes just outside the box, all tiers, in elimination order.
+  // Free nodes just outside the box, all tiers, in elimination order.  Each
+  // side of the box lies on one ancestor separator, whose pivots run tier by
+  // tier along the line, so a side taken tier by tier is one increasing run
+  // of that separator's order; the runs of different sides do not
+  // interleave, so ordering them by their first node orders the set.
   void boundary(const SnFront& f, std::vector<int64_t>& q) const {
     q.clear();
-    for (int32_t t = 0; t < nt; ++t) {
-      const int64_t tb = t * plane;
-      if (f.x0 > 0)
-        for (int32_t y = f.y0; y < f.y1; ++y) q.push_back(tb + (int64_t)y * nx + f.x0 - 1);
-      if (f.x1 < nx)
-        for (int32_t y = f.y0; y < f.y1; ++y) q.push_back(tb + (int64_t)y * nx + f.x1);
-      if (f.y0 > 0)
-        for (int32_t x = f.x0; x < f.x1; ++x) q.push_back(tb + (int64_t)(f.y0 - 1) * nx + x);
-      if (f.y1 < ny)
-        for (int32_t x = f.x0; x < f.x1; ++x) q.push_back(tb + (int64_t)f.y1 * nx + x);
+    int64_t run[4][2];  // [first ord, start in q] per side
+    int nrun = 0;
+    std::vector<int64_t> tmp;
+    auto side = [&](int64_t x0, int64_t dx, int64_t y0, int64_t dy, int32_t len) {
+      const size_t start = q.size();
+      for (int32_t t = 0; t < nt; ++t)
+        for (int32_t i = 0; i < len; ++i) {
+          const int64_t v = t * plane + (y0 + dy * i) * nx + x0 + dx * i;
+          if (is_free(v)) q.push_back(v);
+        }
+      if (q.size() > start) {
+        run[nrun][0] = ord[(size_t)q[start]];
+        run[nrun][1] = (int64_t)start;
+        ++nrun;
+      }
+    };
+    if (f.x0 > 0) side(f.x0 - 1, 0, f.y0, 1, f.y1 - f.y0);
+    if (f.x1 < nx) side(f.x1, 0, f.y0, 1, f.y1 - f.y0);
+    if (f.y0 > 0) side(f.x0, 1, f.y0 - 1, 0, f.x1 - f.x0);
+    if (f.y1 < ny) side(f.x0, 1, f.y1, 0, f.x1 - f.x0);
+    if (nrun <= 1) return;
+    int idx[4] = {0, 1, 2, 3};
+    std::sort(idx, idx + nrun, [&](int a, int b) { return run[a][0] < run[b][0]; });
+    tmp.reserve(q.size());
+    for (int r = 0; r < nrun; ++r) {
+      const int k = idx[r];
+      int64_t end = (int64_t)q.size();
+      for (int j = 0; j < nrun; ++j)
+        if (run[j][1] > run[k][1]) end = std::min(end, run[j][1]);
+      tmp.insert(tmp.end(), q.begin() + run[k][1], q.begin() + end);
     }
-    q.erase(std::remove_if(q.begin(), q.end(), [&](int64_t v) { return !is_free(v); }),
-            q.end());
-    std::sort(q.begin(), q.end(),
-              [&](int64_t a, int64_t b) { return ord[(size_t)a] < ord[(size_t)b]; });
+    q.swap(tmp);
   }
 
   // Conductances of the edges at node v: calls fn(u, g) for every neighbour
   // u (pads included) and returns the sum.
   template <typename Fn>
   double edges(int64_t v, Fn fn) const {
-    const int64_t t = v / plane, rem = v % plane, y = rem / nx, x = rem % nx;
+    const int32_t vi = (int32_t)v, pl = (int32_t)plane;
+    const int32_t t = vi / pl, rem = vi - t * pl, y = rem / nx, x = rem - y * nx;
     double s = 0.0;
     auto e = [&](int64_t u, double g) {
       s += g;
       fn(u, g);
     };
-    const double* gxt = gx + t * (int64_t)ny * (nx - 1);
-    const double* gyt = gy + t * (int64_t)(ny - 1) * nx;
-    if (x > 0) e(v - 1, gxt[y * (nx - 1) + x - 1]);
-    if (x + 1 < nx) e(v + 1, gxt[y * (nx - 1) + x]);
-    if (y > 0) e(v - nx, gyt[(y - 1) * nx + x]);
-    if (y + 1 < ny) e(v + nx, gyt[y * nx + x]);
+    const double* gxt = gx + (int64_t)t * ny * (nx - 1);
+    const double* gyt = gy + (int64_t)t * (ny - 1) * nx;
+    if (x > 0) e(v - 1, gxt[(int64_t)y * (nx - 1) + x - 1]);
+    if (x + 1 < nx) e(v + 1, gxt[(int64_t)y * (nx - 1) + x]);
+    if (y > 0) e(v - nx, gyt[(int64_t)(y - 1) * nx + x]);
+    if (y + 1 < ny) e(v + nx, gyt[(int64_t)y * nx + x]);
     const int32_t j = tsv_of[(size_t)rem];
     if (j >= 0) {
       if (t > 0) e(v - plane, tsv_g[(int64_t)j * (nt - 1) + t - 1]);
@@ -126,6 +148,10 @@ bool build_selinv_plan(int32_t nt, int32_t nx, int32_t ny, const double* gx, con
             {}, {}, 0};
   const int64_t n = b.plane * nt;
   plan.n = n;
+  if (n >= ((int64_t)1 << 31)) {
+    err = "more than 2^31 - 1 nodes";
+    return false;
+  }
   b.tsv_of.assign((size_t)b.plane, -1);
   for (int32_t j = 0; j < n_tsv; ++j)
     b.tsv_of[(size_t)((int64_t)tsv_xy[2 * j + 1] * nx + tsv_xy[2 * j])] = j;
@@ -197,6 +223,18 @@ bool build_selinv_plan(int32_t nt, int32_t nx, int32_t ny, const double* gx, con
 
   // positions inside a front's index set; child maps and original entries
   std::vector<int32_t> pos((size_t)n, -1);
+  {
+    std::vector<int64_t> piv_per_level(plan.levels.size(), 0);
+    for (const SnFront& f : plan.fronts) piv_per_level[(size_t)f.depth] += f.k;
+    for (size_t d = 0; d < plan.levels.size(); ++d) {
+      plan.levels[d].ent_idx.reserve((size_t)(piv_per_level[d] * 4));
+      plan.levels[d].ent_val.reserve((size_t)(piv_per_level[d] * 4));
+    }
+    int64_t nrel = 0;
+    for (const SnFront& f : plan.fronts)
+      if (f.parent >= 0) nrel += f.F - f.k;
+    plan.rel.reserve((size_t)nrel);
+  }
   for (size_t s = 0; s < plan.fronts.size(); ++s) {
     const SnFront& f = plan.fronts[s];
     for (int32_t a = 0; a < f.k; ++a) pos[(size_t)plan.piv_node[(size_t)(f.piv + a)]] = a;
