@@ -217,9 +217,10 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes,
  * reff_selinv_diag for many stacks (candidate TSV plans, Sec. I and IV-B) in
  * one call, with no handle: the plans' dissection trees are analysed on
  * host threads and merged by depth, so every plan's fronts of one tree
- * level share the same launches; device memory is allocated for the call
- * and released before it returns (the sum of the plans'
- * reff_selinv_info().device_bytes).  Inputs as reff_batch_plans:
+ * level share the same launches.  Device memory (about the sum of the plans'
+ * reff_selinv_info().device_bytes) comes from a workspace the library keeps
+ * between calls (reff_release_cached_memory frees it).  Inputs as
+ * reff_batch_plans:
  *   plans    host array of n_plans stack descriptions (validated as
  *            reff_build_pdn does, and checked for connectivity).
  *   nodes    NULL, or host array of n_plans node-id arrays (an entry NULL =
@@ -233,6 +234,15 @@ reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
                               const int64_t* const* nodes, const int64_t* n_nodes,
                               double* const* R_out, const reff_solve_opts* opts,
                               reff_selinv_stats* st);
+
+/*
+ * reff_selinv_batch carves its device buffers from one workspace per device
+ * that the library keeps between calls (grown when a call needs more), so
+ * that repeated batches do not map their fronts afresh.  This frees the
+ * workspace of `device` (a no-op while a batch is using it).
+ * Errors: INVALID_ARG, DEVICE.
+ */
+reff_status reff_release_cached_memory(int32_t device);
 
 /* The plan reff_selinv_diag would use for a stack (host only, no device
  * needed): fronts, levels, largest front, device bytes and flop counts.

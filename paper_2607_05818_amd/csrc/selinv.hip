@@ -40,6 +40,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -595,6 +596,22 @@ SelinvSizes selinv_sizes(const SelinvPlan& P) {
 
 // Device state of a handle's plan: the uploaded tables and every work
 // buffer, allocated on the first call and kept with the handle.
+// A batch of plans can need 100 GB of fronts, and mapping that much device
+// memory afresh costs up to seconds per call; the batch path therefore
+// carves its buffers from one workspace per device that is kept between
+// calls (grown when a call needs more; reff_release_cached_memory frees
+// it).  A call that finds it in use allocates its own.
+struct WorkspaceCache {
+  std::mutex mu;
+  void* p = nullptr;
+  size_t bytes = 0;
+  bool busy = false;
+};
+WorkspaceCache g_ws[64];
+
+constexpr size_t ALIGN = 256;
+size_t aligned(size_t b) { return (std::max<size_t>(b, 1) + ALIGN - 1) / ALIGN * ALIGN; }
+
 struct SelinvDevice {
   std::vector<LevelDev> lv;
   SelinvSizes sz;
@@ -604,14 +621,57 @@ struct SelinvDevice {
   int32_t *rel = nullptr, *dl = nullptr;
   DFront* dF = nullptr;
   int* bad = nullptr;
-  std::vector<void*> ptrs;
+  std::vector<void*> ptrs;       // own allocations
+  WorkspaceCache* ws = nullptr;  // or buffers carved from a cached workspace
+  char* carve = nullptr;
+  size_t carve_left = 0;
   ~SelinvDevice() {
     for (void* q : ptrs) (void)hipFree(q);
+    if (ws) {
+      std::lock_guard<std::mutex> lk(ws->mu);
+      ws->busy = false;
+    }
+  }
+  // Take `total` bytes from the device's cached workspace for the buffers
+  // that follow (false: use own allocations).
+  hipError_t reserve(size_t total, bool& from_cache) {
+    from_cache = false;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= 64) return e;
+    WorkspaceCache& c = g_ws[dev];
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (c.busy) return hipSuccess;
+    if (c.bytes < total) {
+      if (c.p) (void)hipFree(c.p);
+      c.p = nullptr;
+      c.bytes = 0;
+      e = hipMalloc(&c.p, total);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c.p = nullptr;
+        return hipSuccess;  // fall back to own allocations
+      }
+      c.bytes = total;
+    }
+    c.busy = true;
+    ws = &c;
+    carve = (char*)c.p;
+    carve_left = c.bytes;
+    from_cache = true;
+    return hipSuccess;
   }
   template <typename T>
   hipError_t get(T** out, size_t count) {
+    const size_t b = aligned(count * sizeof(T));
+    if (ws && b <= carve_left) {
+      *out = (T*)carve;
+      carve += b;
+      carve_left -= b;
+      return hipSuccess;
+    }
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    hipError_t e = hipMalloc(&q, b);
     if (e == hipSuccess) ptrs.push_back(q);
     *out = (T*)q;
     return e;
@@ -625,7 +685,8 @@ struct SelinvDevice {
   }
 };
 
-std::shared_ptr<SelinvDevice> selinv_device_build(const SelinvPlan& P, reff_status& s) {
+std::shared_ptr<SelinvDevice> selinv_device_build(const SelinvPlan& P, reff_status& s,
+                                                  bool use_cache = false) {
   s = REFF_OK;
   auto D = std::make_shared<SelinvDevice>();
   std::vector<DFront> dfr(P.fronts.size());
@@ -668,7 +729,19 @@ std::shared_ptr<SelinvDevice> selinv_device_build(const SelinvPlan& P, reff_stat
     lists.insert(lists.end(), L.fronts.begin(), L.fronts.end());
     V.groups = std::move(groups[d]);
   }
-  hipError_t e = D->get(&D->ar, (size_t)P.arena);
+  hipError_t e = hipSuccess;
+  if (use_cache) {
+    const SelinvSizes& z = D->sz;
+    const size_t total = aligned(8 * (size_t)P.arena) + 2 * aligned(8 * (size_t)z.tiles) +
+                         aligned(8 * (size_t)z.ybuf) + aligned(8 * (size_t)z.part) +
+                         aligned(8 * (size_t)z.ysp) + aligned(8 * (size_t)P.n) + aligned(4) +
+                         2 * aligned(8 * (size_t)n_ent) + aligned(8 * P.piv_node.size()) +
+                         aligned(4 * P.rel.size()) + aligned(4 * lists.size()) +
+                         aligned(sizeof(DFront) * dfr.size());
+    bool cached = false;
+    e = D->reserve(total, cached);
+  }
+  if (e == hipSuccess) e = D->get(&D->ar, (size_t)P.arena);
   if (e == hipSuccess) e = D->get(&D->Li, (size_t)D->sz.tiles);
   if (e == hipSuccess) e = D->get(&D->Z0, (size_t)D->sz.tiles);
   if (e == hipSuccess) e = D->get(&D->Yb, (size_t)D->sz.ybuf);
@@ -901,6 +974,20 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
   return REFF_OK;
 }
 
+reff_status reff_release_cached_memory(int32_t device) {
+  using namespace reff;
+  if (device < 0 || device >= 64) return host_fail(REFF_ERR_INVALID_ARG, "bad device");
+  WorkspaceCache& c = g_ws[device];
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (!c.p || c.busy) return REFF_OK;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipFree(c.p);
+  c.p = nullptr;
+  c.bytes = 0;
+  if (e != hipSuccess) return dev_status(e, "releasing cached memory");
+  return REFF_OK;
+}
+
 reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
                               const int64_t* const* nodes, const int64_t* n_nodes,
                               double* const* R_out, const reff_solve_opts* opts,
@@ -951,7 +1038,7 @@ reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
   sp.clear();
   const auto t_plan = std::chrono::steady_clock::now();
   reff_status s;
-  auto dev_sp = selinv_device_build(P, s);
+  auto dev_sp = selinv_device_build(P, s, true);
   if (!dev_sp) return s;
   const SelinvDevice& D = *dev_sp;
   const auto t_setup = std::chrono::steady_clock::now();

@@ -152,6 +152,8 @@ _lib.reff_selinv_batch.argtypes = [C.POINTER(reff_pdn_desc), C.c_int32,
                                    C.POINTER(C.c_void_p), C.POINTER(reff_solve_opts),
                                    C.POINTER(reff_selinv_stats)]
 _lib.reff_selinv_batch.restype = C.c_int
+_lib.reff_release_cached_memory.argtypes = [C.c_int32]
+_lib.reff_release_cached_memory.restype = C.c_int
 _lib.reff_stream_probe.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                    C.c_void_p]
 _lib.reff_stream_probe.restype = C.c_int
@@ -360,6 +362,11 @@ def reff_selinv_batch(plans, nodes=None, R_out=None, *, stream=None):
     _check(_lib.reff_selinv_batch(structs, k, nptrs, ncount, optrs, C.byref(o), C.byref(st)))
     del keep, node_arrs
     return outs, st.as_dict()
+
+
+def reff_release_cached_memory(device=0):
+    """Return the device memory the sparse-direct path keeps pooled."""
+    _check(_lib.reff_release_cached_memory(int(device)))
 
 
 def reff_stream_probe(kind, src, dst, nbytes, blocks, stream=None):

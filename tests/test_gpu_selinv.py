@@ -169,6 +169,11 @@ def test_batch_of_ragged_plans_matches_unit_solves_and_single_calls():
         assert np.all(outs[i][~m] == 0.0)
         if m.any():  # a 1 x 1 x 1 stack is all pad
             assert np.max(np.abs(outs[i][m] - alone[m]) / alone[m]) <= 1e-12
+    # the pooled device memory goes back to the device, and calls still work
+    reff.reff_release_cached_memory(0)
+    again, _ = reff.reff_selinv_batch(plans, nodes)
+    for i in range(len(plans)):
+        assert np.array_equal(again[i], outs[i])
 
 
 def test_batch_all_256_recipe_plans_against_stored_oracle_values():
