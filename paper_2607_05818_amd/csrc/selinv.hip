@@ -788,7 +788,8 @@ std::shared_ptr<SelinvDevice> selinv_device_of(reff_pdn_t* p, const SelinvPlan& 
 // factorisation finished (the call synchronises there to read the pivot
 // flag).
 reff_status selinv_run(const SelinvPlan& P, const SelinvDevice& D, hipStream_t st_,
-                       std::chrono::steady_clock::time_point& t_fact) {
+                       std::chrono::steady_clock::time_point& t_fact,
+                       const std::vector<uint8_t>* need = nullptr) {
   double *ar = D.ar, *Li = D.Li, *Z0 = D.Z0, *Yb = D.Yb, *part = D.part, *Ysp = D.Ysp;
   double* Rfull = D.Rfull;
   const int32_t *rel = D.rel, *dl = D.dl;
@@ -838,34 +839,64 @@ reff_status selinv_run(const SelinvPlan& P, const SelinvDevice& D, hipStream_t s
   if (e != hipSuccess) return dev_status(e, "selected inversion: factorisation");
   if (hbad) return host_fail(REFF_ERR_DEVICE, "sparse Cholesky: a pivot was not positive");
   t_fact = std::chrono::steady_clock::now();
+  // With a request, the selected inversion visits only the needed fronts:
+  // each launch group runs over the compacted list of its needed fronts
+  // (their scratch slots and Y offsets are those of the full group).
+  Bufs lb;
+  int32_t* dact = nullptr;
+  std::vector<std::vector<std::pair<int64_t, int>>> act_rng(P.levels.size());
+  if (need) {
+    std::vector<int32_t> act;
+    for (size_t d = 0; d < P.levels.size(); ++d) {
+      const SelinvLevel& L = P.levels[d];
+      for (const GroupDev& G : D.lv[d].groups) {
+        const int64_t lbase = G.list_off - D.lv[d].groups.front().list_off;
+        const int64_t a0 = (int64_t)act.size();
+        for (int j = 0; j < G.nf; ++j) {
+          const int32_t fi = L.fronts[(size_t)(lbase + j)];
+          if ((*need)[(size_t)fi]) act.push_back(fi);
+        }
+        act_rng[d].push_back({a0, (int)((int64_t)act.size() - a0)});
+      }
+    }
+    e = put(lb, &dact, act, st_);
+    if (e == hipSuccess) e = hipStreamSynchronize(st_);
+    if (e != hipSuccess) return dev_status(e, "selected inversion: request lists");
+  }
   // selected inversion, roots first
   for (int d = 0; d < nlev && e == hipSuccess; ++d) {
     const LevelDev& V = D.lv[(size_t)d];
-    for (const GroupDev& G : V.groups) {
+    for (size_t gi = 0; gi < V.groups.size(); ++gi) {
+      const GroupDev& G = V.groups[gi];
       const int32_t* l = dl + G.list_off;
+      int nfa = G.nf;
+      if (need) {
+        l = dact + act_rng[(size_t)d][gi].first;
+        nfa = act_rng[(size_t)d][gi].second;
+        if (nfa == 0) continue;
+      }
       if (d > 0 && G.maxq > 0) {
         const unsigned gx = (unsigned)std::max<int64_t>(1, (G.maxq + 3) / 4);
-        hipLaunchKernelGGL(k_gather, dim3(gx, gy(G.nf)), dim3(256), 0, st_, dF, l, G.nf, rel,
-                           ar);
+        hipLaunchKernelGGL(k_gather, dim3(gx, gy(nfa)), dim3(256), 0, st_, dF, l, nfa, rel, ar);
       }
       for (int jp = G.max_panels - 1; jp >= 0; --jp) {
         const int mt = G.mt[(size_t)jp], ms = G.ms[(size_t)jp];
-        hipLaunchKernelGGL(k_tile<false>, dim3(gy(G.nf)), dim3(256), 0, st_, dF, l, G.nf, jp, ar,
+        hipLaunchKernelGGL(k_tile<false>, dim3(gy(nfa)), dim3(256), 0, st_, dF, l, nfa, jp, ar,
                            Li, Z0, bad);
         if (mt > 0) {
-          hipLaunchKernelGGL(k_front_gemm<OP_LHAT>, dim3((unsigned)mt, gy(G.nf)), dim3(256), 0,
-                             st_, dF, l, G.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
-          hipLaunchKernelGGL(k_front_gemm<OP_Y>, dim3((unsigned)(mt * G.ysplit), gy(G.nf)),
-                             dim3(256), 0, st_, dF, l, G.nf, jp, ar, Li, Yb, part, mt, G.ysplit,
+          hipLaunchKernelGGL(k_front_gemm<OP_LHAT>, dim3((unsigned)mt, gy(nfa)), dim3(256), 0,
+                             st_, dF, l, nfa, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
+          hipLaunchKernelGGL(k_front_gemm<OP_Y>, dim3((unsigned)(mt * G.ysplit), gy(nfa)),
+                             dim3(256), 0, st_, dF, l, nfa, jp, ar, Li, Yb, part, mt, G.ysplit,
                              Ysp, G.ylev);
           if (G.ysplit > 1)
-            hipLaunchKernelGGL(k_ysum, dim3((unsigned)mt, gy(G.nf)), dim3(256), 0, st_, dF, l,
-                               G.nf, jp, G.ysplit, (const double*)Ysp, G.ylev, Yb);
-          hipLaunchKernelGGL(k_front_gemm<OP_PART>, dim3((unsigned)ms, gy(G.nf)), dim3(256), 0,
-                             st_, dF, l, G.nf, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
+            hipLaunchKernelGGL(k_ysum, dim3((unsigned)mt, gy(nfa)), dim3(256), 0, st_, dF, l,
+                               nfa, jp, G.ysplit, (const double*)Ysp, G.ylev, Yb);
+          hipLaunchKernelGGL(k_front_gemm<OP_PART>, dim3((unsigned)ms, gy(nfa)), dim3(256), 0,
+                             st_, dF, l, nfa, jp, ar, Li, Yb, part, mt, 1, Ysp, (int64_t)0);
         }
-        hipLaunchKernelGGL(k_finish, dim3((unsigned)(1 + mt), gy(G.nf)), dim3(256), 0, st_, dF,
-                           l, G.nf, jp, ar, Z0, Yb, part, D.piv, Rfull);
+        hipLaunchKernelGGL(k_finish, dim3((unsigned)(1 + mt), gy(nfa)), dim3(256), 0, st_, dF,
+                           l, nfa, jp, ar, Z0, Yb, part, D.piv, Rfull);
       }
     }
     e = hipGetLastError();
@@ -939,8 +970,12 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
   }
   if (e == hipSuccess && !out_dev && count > 0) e = b.get(&dout, (size_t)count);
   if (e != hipSuccess) return dev_status(e, "selected inversion: output buffers");
+  // a node list needs only its fronts and their ancestors inverted
+  double fl_sel = P.flops_selinv;
+  std::vector<uint8_t> need;
+  if (nodes) need = needed_fronts(P, std::vector<int64_t>(nodes, nodes + count), &fl_sel);
   std::chrono::steady_clock::time_point t_fact;
-  s = selinv_run(P, D, st_, t_fact);
+  s = selinv_run(P, D, st_, t_fact, nodes ? &need : nullptr);
   if (s != REFF_OK) return s;
   // output
   if (e == hipSuccess && count > 0) {
@@ -964,7 +999,7 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, 
     for (const SnFront& f : P.fronts) st->max_front = std::max<int64_t>(st->max_front, f.F);
     st->device_bytes = D.sz.bytes;
     st->flops_factor = P.flops_factor;
-    st->flops_selinv = P.flops_selinv;
+    st->flops_selinv = fl_sel;
     st->seconds = std::chrono::duration<double>(t1 - t0).count();
     st->seconds_plan = std::chrono::duration<double>(t_plan - t0).count();
     st->seconds_factor = std::chrono::duration<double>(t_fact - t_plan).count();
@@ -1042,18 +1077,26 @@ reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
   if (!dev_sp) return s;
   const SelinvDevice& D = *dev_sp;
   const auto t_setup = std::chrono::steady_clock::now();
-  std::chrono::steady_clock::time_point t_fact;
-  s = selinv_run(P, D, st_, t_fact);
-  if (s != REFF_OK) return s;
   // requested nodes of every plan, in plan order, picked into one array
   std::vector<int64_t> ids;
   int64_t total = 0;
-  for (size_t i = 0; i < np; ++i) total += cnt[i];
+  bool every = true;
+  for (size_t i = 0; i < np; ++i) {
+    total += cnt[i];
+    every = every && !(nodes && nodes[i]);
+  }
   ids.reserve((size_t)total);
   for (size_t i = 0; i < np; ++i) {
     const bool given = nodes && nodes[i];
     for (int64_t k = 0; k < cnt[i]; ++k) ids.push_back(base[i] + (given ? nodes[i][k] : k));
   }
+  // with node lists, only their fronts and ancestors are inverted
+  double fl_sel = P.flops_selinv;
+  std::vector<uint8_t> need;
+  if (!every) need = needed_fronts(P, ids, &fl_sel);
+  std::chrono::steady_clock::time_point t_fact;
+  s = selinv_run(P, D, st_, t_fact, every ? nullptr : &need);
+  if (s != REFF_OK) return s;
   Bufs b;
   int64_t* dids = nullptr;
   double* dres = nullptr;
@@ -1092,7 +1135,7 @@ reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
     for (const SnFront& f : P.fronts) st->max_front = std::max<int64_t>(st->max_front, f.F);
     st->device_bytes = D.sz.bytes;
     st->flops_factor = P.flops_factor;
-    st->flops_selinv = P.flops_selinv;
+    st->flops_selinv = fl_sel;
     st->seconds = std::chrono::duration<double>(t1 - t0).count();
     st->seconds_plan = std::chrono::duration<double>(t_plan - t0).count();
     st->seconds_factor = std::chrono::duration<double>(t_fact - t_plan).count();

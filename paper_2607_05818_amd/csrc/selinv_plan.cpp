@@ -8,6 +8,32 @@
 
 namespace reff {
 
+// Selected-inversion flops of one front: per 64-column panel of width w
+// with m rows below it, Lhat (m w^2), Y = -Z_RR Lhat (2 m^2 w), the
+// -Lhat^T Y product (2 m w^2), and the tile's L^-T L^-1 (w^3).
+static double selinv_front_flops(const SnFront& f) {
+  double fl = 0.0;
+  for (int32_t j0 = 0; j0 < f.k; j0 += 64) {
+    const double w = std::min(64, f.k - j0), m = f.F - j0 - w;
+    fl += 2.0 * m * w * w + 2.0 * m * m * w + 2.0 * m * w * w + w * w * w;
+  }
+  return fl;
+}
+
+std::vector<uint8_t> needed_fronts(const SelinvPlan& P, const std::vector<int64_t>& ids,
+                                   double* flops) {
+  std::vector<uint8_t> need(P.fronts.size(), 0);
+  for (int64_t v : ids)
+    for (int32_t f = P.node_front[(size_t)v]; f >= 0 && !need[(size_t)f];
+         f = P.fronts[(size_t)f].parent)
+      need[(size_t)f] = 1;
+  double fl = 0.0;
+  for (size_t i = 0; i < P.fronts.size(); ++i)
+    if (need[i]) fl += selinv_front_flops(P.fronts[i]);
+  if (flops) *flops = fl;
+  return need;
+}
+
 namespace {
 
 struct Builder {
@@ -184,6 +210,10 @@ bool build_selinv_plan(int32_t nt, int32_t nx, int32_t ny, const double* gx, con
     }
   }
 
+  plan.node_front.assign((size_t)n, -1);
+  for (size_t i = 0; i < plan.fronts.size(); ++i)
+    for (int32_t a = 0; a < plan.fronts[i].k; ++a)
+      plan.node_front[(size_t)plan.piv_node[(size_t)(plan.fronts[i].piv + a)]] = (int32_t)i;
   // update sets, sizes, levels
   std::vector<std::vector<int64_t>> Q(plan.fronts.size());
   int32_t max_depth = 0;
@@ -212,10 +242,7 @@ bool build_selinv_plan(int32_t nt, int32_t nx, int32_t ny, const double* gx, con
       L.max_F = std::max<int64_t>(L.max_F, f.F);
       const double k = f.k, q = f.F - f.k;
       plan.flops_factor += k * k * k / 3.0 + k * k * q + k * q * q;
-      for (int32_t j0 = 0; j0 < f.k; j0 += 64) {
-        const double w = std::min(64, f.k - j0), m = f.F - j0 - w;
-        plan.flops_selinv += 2.0 * m * w * w + 2.0 * m * m * w + 2.0 * m * w * w + w * w * w;
-      }
+      plan.flops_selinv += selinv_front_flops(f);
     }
     L.arena_end = off;
   }
@@ -336,6 +363,7 @@ SelinvPlan merge_selinv_plans(const std::vector<SelinvPlan>& plans, std::vector<
   M.fronts.resize((size_t)nf);
   M.rel.resize((size_t)nr);
   M.piv_node.resize((size_t)npv);
+  M.node_front.resize((size_t)M.n);
   // every plan fills its own slices
   selinv_parallel_for(np, [&](size_t i) {
     const SelinvPlan& P = plans[i];
@@ -349,6 +377,8 @@ SelinvPlan merge_selinv_plans(const std::vector<SelinvPlan>& plans, std::vector<
     std::copy(P.rel.begin(), P.rel.end(), M.rel.begin() + r0[i]);
     for (size_t j = 0; j < P.piv_node.size(); ++j)
       M.piv_node[(size_t)p0[i] + j] = P.piv_node[j] + base[i];
+    for (size_t v = 0; v < P.node_front.size(); ++v)
+      M.node_front[(size_t)base[i] + v] = P.node_front[v] < 0 ? -1 : P.node_front[v] + f0[i];
     for (size_t d = 0; d < P.levels.size(); ++d) {
       const SelinvLevel& PL = P.levels[d];
       SelinvLevel& L = M.levels[d];

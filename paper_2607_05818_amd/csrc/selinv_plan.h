@@ -58,6 +58,7 @@ struct SelinvPlan {
   std::vector<SelinvLevel> levels; // by depth, 0 = roots
   std::vector<int32_t> rel;        // child Q -> parent front positions
   std::vector<int64_t> piv_node;   // pivots' node ids, front by front
+  std::vector<int32_t> node_front; // front whose pivot a node is, -1 for pads
   int64_t arena = 0;               // doubles
   double flops_factor = 0.0, flops_selinv = 0.0;
 };
@@ -67,6 +68,14 @@ struct SelinvPlan {
 // arena laid out again level by level.  base receives each plan's first
 // node id.
 SelinvPlan merge_selinv_plans(const std::vector<SelinvPlan>& plans, std::vector<int64_t>& base);
+
+// The fronts a selected inversion must visit to produce R for the given
+// node ids: each node's own front and all of that front's ancestors (the
+// recurrence for a front reads only its parent's finished block).  Returns
+// one flag per front (1 = needed) and their share of flops_selinv in
+// *flops.  Node ids must lie in [0, n).
+std::vector<uint8_t> needed_fronts(const SelinvPlan& P, const std::vector<int64_t>& ids,
+                                   double* flops);
 
 // Run body(i) for i < count on up to 16 host threads.
 void selinv_parallel_for(size_t count, const std::function<void(size_t)>& body);

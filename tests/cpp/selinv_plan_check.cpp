@@ -106,7 +106,10 @@ static std::vector<double> dense_diag(const Stack& S) {
 
 // The panel factorisation and block Takahashi recurrence of the device
 // kernels, as plain loops over a plan (any forest); R per node id.
-static std::vector<double> numeric(const SelinvPlan& P) {
+// need: with a flag per front, the selected inversion visits only the
+// flagged fronts (R stays 0 elsewhere).
+static std::vector<double> numeric(const SelinvPlan& P,
+                                   const std::vector<uint8_t>* need = nullptr) {
   std::vector<double> ar((size_t)P.arena, 0.0);
   auto at = [&](const SnFront& f, int64_t r, int64_t c) -> double& {
     chk(r >= 0 && r < f.F && c >= 0 && c < f.F, "front index");
@@ -164,6 +167,7 @@ static std::vector<double> numeric(const SelinvPlan& P) {
   std::vector<double> R((size_t)P.n, 0.0);
   for (size_t d = 0; d < P.levels.size(); ++d) {
     for (int32_t fi : P.levels[d].fronts) {
+      if (need && !(*need)[(size_t)fi]) continue;
       const SnFront& f = P.fronts[(size_t)fi];
       const int32_t q = f.F - f.k;
       if (f.parent >= 0) {
@@ -227,15 +231,63 @@ static double worst_rel(const std::vector<double>& got, const double* want, int6
   return worst;
 }
 
+// node_front: every pivot maps to its own front, nothing else maps.
+static void check_node_front(const SelinvPlan& P) {
+  chk((int64_t)P.node_front.size() == P.n, "node_front size");
+  int64_t mapped = 0;
+  for (int32_t f : P.node_front) mapped += f >= 0;
+  chk(mapped == P.n_free, "node_front covers the free nodes");
+  for (size_t i = 0; i < P.fronts.size(); ++i)
+    for (int32_t a = 0; a < P.fronts[i].k; ++a)
+      chk(P.node_front[(size_t)P.piv_node[(size_t)(P.fronts[i].piv + a)]] == (int32_t)i,
+          "pivot maps to its front");
+}
+
+// A request of a few node ids: the flagged fronts are closed under
+// parents, contain every requested free node, the partial recurrence
+// gives the requested values bit for bit, and all ids flag every front
+// that has pivots.
+static int partial(const SelinvPlan& P, const std::vector<double>& full, int seed, int count) {
+  std::mt19937_64 rng(seed);
+  std::vector<int64_t> ids((size_t)count);
+  for (auto& v : ids) v = (int64_t)(rng() % (uint64_t)P.n);
+  double fl = -1;
+  const std::vector<uint8_t> need = needed_fronts(P, ids, &fl);
+  size_t nn = 0;
+  for (size_t i = 0; i < P.fronts.size(); ++i) {
+    if (!need[i]) continue;
+    ++nn;
+    if (P.fronts[i].parent >= 0) chk(need[(size_t)P.fronts[i].parent], "closed under parents");
+  }
+  for (int64_t v : ids)
+    if (P.node_front[(size_t)v] >= 0) chk(need[(size_t)P.node_front[(size_t)v]], "own front");
+  const std::vector<double> R = numeric(P, &need);
+  for (int64_t v : ids) chk(R[(size_t)v] == full[(size_t)v], "partial value");
+  std::vector<int64_t> all((size_t)P.n);
+  for (int64_t v = 0; v < P.n; ++v) all[(size_t)v] = v;
+  double fa = -1;
+  const std::vector<uint8_t> every = needed_fronts(P, all, &fa);
+  for (size_t i = 0; i < P.fronts.size(); ++i)  // fronts without pivots may go unflagged
+    chk(every[i] == 1 || P.fronts[i].k == 0, "all ids need every front with pivots");
+  chk(std::fabs(fa - P.flops_selinv) <= 1e-9 * P.flops_selinv + 1e-9, "flops of all fronts");
+  chk(fl <= fa, "partial flops");
+  printf("  partial request of %d ids: %zu of %zu fronts, %.1f%% of the inversion flops\n",
+         count, nn, P.fronts.size(), fa > 0 ? 100.0 * fl / fa : 0.0);
+  return 0;
+}
+
 int run(int seed, int nt, int nx, int ny, int ntsv, int npad, int leaf) {
   const Stack S = make_stack(seed, nt, nx, ny, ntsv, npad);
   SelinvPlan P;
   if (!plan_of(S, leaf, P)) return 1;
   const std::vector<double> want = dense_diag(S);
-  const double worst = worst_rel(numeric(P), want.data(), P.n);
+  check_node_front(P);
+  const std::vector<double> R = numeric(P);
+  const double worst = worst_rel(R, want.data(), P.n);
   printf("seed %d %dx%dx%d tsv %d pads %d leaf %d: fronts %zu levels %zu arena %lld worst %.3e\n",
          seed, nt, nx, ny, ntsv, npad, leaf, P.fronts.size(), P.levels.size(),
          (long long)P.arena, worst);
+  partial(P, R, seed + 1000, 3);
   return worst < 1e-10 ? 0 : 1;
 }
 
@@ -249,7 +301,9 @@ int run_merged() {
     if (!plan_of(S[i], 16, plans[i])) return 1;
   std::vector<int64_t> base;
   const SelinvPlan M = merge_selinv_plans(plans, base);
+  check_node_front(M);
   const std::vector<double> R = numeric(M);
+  partial(M, R, 99, 5);
   double worst = 0;
   for (int i = 0; i < 3; ++i) {
     const std::vector<double> want = dense_diag(S[i]);

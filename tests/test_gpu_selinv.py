@@ -194,3 +194,48 @@ def test_batch_all_256_recipe_plans_against_stored_oracle_values():
     worst = max(_max_rel(outs[i], np.array(gold["R"][i])) for i in range(len(plans)))
     print("worst relative error over 16,384 nodes", worst, flush=True)
     assert worst <= TOL
+
+
+@pytest.mark.parametrize("seed,nt,side,ntsv,npad,count", [(61, 4, 100, 300, 40, 5),
+                                                          (62, 2, 97, 50, 7, 1),
+                                                          (63, 3, 64, 80, 6, 200)])
+def test_node_request_inverts_only_needed_fronts(seed, nt, side, ntsv, npad, count):
+    """A node list makes the selected inversion visit only the fronts that
+    hold the nodes and their ancestors; each front's arithmetic is the same,
+    so the values equal those of the full map bit for bit, and the reported
+    inversion flops drop with the request."""
+    reff = _reff()
+    d = gen.small_random_desc(seed, nt, side, side - 3, ntsv, npad)
+    _say("selinv node request", seed, nt, side, count)
+    h = reff.reff_build_pdn(d)
+    full, st_full = reff.reff_selinv_diag(h)
+    ids = np.random.default_rng(seed).integers(0, len(full), size=count)
+    ids[0] = ro.pad_nodes(d)[0]
+    got, st = reff.reff_selinv_diag(h, ids)
+    print("inversion flops", st["flops_selinv"], "of", st_full["flops_selinv"], flush=True)
+    assert np.array_equal(got, full[ids])
+    assert got[0] == 0.0
+    assert st["flops_selinv"] < st_full["flops_selinv"]
+    assert st["flops_factor"] == st_full["flops_factor"]
+    # the full map afterwards is unchanged by the partial call
+    again, _ = reff.reff_selinv_diag(h)
+    assert np.array_equal(again, full)
+    h.close()
+
+
+def test_batch_node_requests_equal_full_batch():
+    """Batched requests take the same partial inversion over the merged
+    forest: equal bit for bit to the all-node batch at the same ids."""
+    reff = _reff()
+    shapes = [(301, 2, 40, 33, 20, 4), (302, 3, 50, 21, 30, 2), (303, 1, 9, 70, 0, 3)]
+    plans = [gen.small_random_desc(s, nt, nx, ny, k, p) for s, nt, nx, ny, k, p in shapes]
+    _say("selinv batch node requests vs all-node batch")
+    full, st_full = reff.reff_selinv_batch(plans, [None] * len(plans))
+    rng = np.random.default_rng(303)
+    nodes = [rng.integers(0, gen.n_nodes(d), size=7) for d in plans]
+    nodes[1] = None  # one plan asks for every node
+    got, st = reff.reff_selinv_batch(plans, nodes)
+    for i in range(len(plans)):
+        want = full[i] if nodes[i] is None else full[i][nodes[i]]
+        assert np.array_equal(got[i], want)
+    assert st["flops_selinv"] < st_full["flops_selinv"]
