@@ -72,8 +72,11 @@ def kernel_bytes(n, fp32=True, mixed_with_d=True, cheb=1):
       residual update (K2): read Q, R (P, D); write R (D)       -> 3 (6) S w
                          + Dinv; with the polynomial preconditioner it also
                          writes z_1 = D^-1 R / theta            -> + S w
-                         unless the first pass forms z_1 itself
+                         unless the first pass forms z_1 itself, and the
+                         solution update D += P A moves to K3
       search block (K3): read P, R (or Z); write Y              -> 3 S w + d, Dinv
+                         (polynomial preconditioner: also read and write
+                         D                                      -> + 2 S w)
       Chebyshev passes (degree k > 1), all passes of one application: the
                          vector words of cheb_words, each pass also reading
                          d, cE, cN, Dinv and the slot
@@ -82,8 +85,9 @@ def kernel_bytes(n, fp32=True, mixed_with_d=True, cheb=1):
     w = 4 if fp32 else 8
     k1 = n * (4 * S * w + 3 * w + 4)
     z1 = cheb > 1 and not cheb_folds_z1(cheb, fp32)
-    k2 = n * ((6 if mixed_with_d else 3) * S * w + w + (S * w if z1 else 0))
-    k3 = n * (3 * S * w + 2 * w)
+    d_in_k3 = mixed_with_d and cheb > 1
+    k2 = n * ((6 if mixed_with_d and not d_in_k3 else 3) * S * w + w + (S * w if z1 else 0))
+    k3 = n * ((5 if d_in_k3 else 3) * S * w + 2 * w)
     kp = kg = 0
     if cheb > 1:
         words, passes = cheb_words(cheb, fp32)
@@ -98,10 +102,11 @@ def kernel_flops(cheb=1):
     upper triangular (10 of the 16 16 x 16 blocks of T are nonzero) plus the
     Grams P^T Q and P^T R; K2 = Q A, P A and (Jacobi) Q^T Z; K3 = P B and
     Y^T D Y; the Chebyshev passes are stencil arithmetic (no matrix-core
-    work); the preconditioner's Q^T Z Gram."""
+    work); the preconditioner's Q^T Z Gram.  With the polynomial
+    preconditioner P A is formed in K3 instead of K2."""
     g = 2 * S * S
     if cheb > 1:
-        return [2 * g * 10 // 16 + 2 * g, 2 * g, 2 * g, 0, g]
+        return [2 * g * 10 // 16 + 2 * g, g, 3 * g, 0, g]
     return [2 * g * 10 // 16 + 2 * g, 3 * g, 2 * g, 0, 0]
 
 

@@ -787,15 +787,21 @@ __global__ __launch_bounds__(WG, 4) void k_update_r(Coef<T> c, Work wk,
 // ---------------------------------------------------------------- K3
 // Y = Dinv R - P B;  W4 = Y^T D Y (block variant).
 // With ZBUF the argument R is the preconditioned residual Z (polynomial
-// preconditioner) and Y = Z - P B.
-template <typename T, bool DIAG, bool ZBUF = false>
+// preconditioner) and Y = Z - P B.  With WITH_D (block variant with ZBUF
+// only) the kernel also takes the solution update D += P A of this
+// iteration from K2: it reads P anyway, so P is read once per iteration.
+template <typename T, bool DIAG, bool ZBUF = false, bool WITH_D = false>
 __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
                                                     const T* __restrict__ delta,
                                                     const T* __restrict__ R,
                                                     const T* __restrict__ P, T* __restrict__ Y,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part,
+                                                    const T* __restrict__ alpha = nullptr,
+                                                    T* __restrict__ D = nullptr) {
+  static_assert(!WITH_D || (ZBUF && !DIAG), "D update only in the polynomial block variant");
   __shared__ __align__(16) T sP[DIAG ? 1 : CH][LDW];  // P rows, then Y rows
   __shared__ __align__(16) T sR[DIAG ? 1 : CH][LDW];  // R rows, then D Y rows
+  __shared__ __align__(16) T sD[WITH_D ? CH : 1][WITH_D ? LDW : 1];
   __shared__ __align__(16) T sDv[CH][2];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -805,16 +811,17 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
   const UnitCtx u = unit_ctx(wk, lu);
   const int uidx = wk.uid[lu];
   const T* de = delta + (size_t)u.plan * S * S;
-  T breg[DIAG ? 1 : S / 4];
+  T breg[DIAG ? 1 : S / 4], areg[WITH_D ? S / 4 : 1];
   if (DIAG)
     breg[0] = de[lane];
   else
     load_bcol<T>(de, cb, lane, breg);
+  if (WITH_D) load_bcol<T>(alpha + (size_t)u.plan * S * S, cb, lane, areg);
   double a4[2][4];
   zero_acc(a4);
   const int64_t cofs = u.pd.cbase - u.pd.vbase;
   // Rows of one chunk (clamped to the unit's last row; zeroed when staged).
-  T rv[NODES_PER_WAVE], pv[NODES_PER_WAVE];
+  T rv[NODES_PER_WAVE], pv[NODES_PER_WAVE], dv[WITH_D ? NODES_PER_WAVE : 1];
   T dinv_t = T(0), d_t = T(0);
   auto load_chunk = [&](int64_t base) {
 #pragma unroll
@@ -822,6 +829,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
       const int64_t v = min(base + w * NODES_PER_WAVE + i, u.end - 1);
       pv[i] = P[v * S + lane];
       rv[i] = R[v * S + lane];
+      if (WITH_D) dv[i] = D[v * S + lane];
     }
     if (threadIdx.x < CH) {
       const int64_t v = min(base + threadIdx.x, u.end - 1) + cofs;
@@ -852,6 +860,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
       const bool ok = base + row < u.end;
       sP[row][lane] = ok ? pv[i] : T(0);
       sR[row][lane] = ok ? rv[i] : T(0);
+      if (WITH_D) sD[row][lane] = ok ? dv[i] : T(0);
     }
     if (threadIdx.x < CH) {
       const bool ok = base + threadIdx.x < u.end;
@@ -861,11 +870,14 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
     if (base + CH < u.end) load_chunk(base + CH);
     __syncthreads();
     const auto pd = prod_tile<T>(sP, nb, breg, lane);
-    T yn[4];
+    typename Acc<T>::type pa = {0, 0, 0, 0};
+    if (WITH_D) pa = prod_tile<T>(sP, nb, areg, lane);
+    T yn[4], dn[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = nb * 16 + tile_row<T>(lane, r), col = cb * 16 + (lane & 15);
       yn[r] = (ZBUF ? sR[row][col] : sDv[row][0] * sR[row][col]) - pd[r];
+      if (WITH_D) dn[r] = sD[row][col] + pa[r];
     }
     __syncthreads();
 #pragma unroll
@@ -873,6 +885,7 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
       const int row = nb * 16 + tile_row<T>(lane, r), col = cb * 16 + (lane & 15);
       sP[row][col] = yn[r];
       sR[row][col] = sDv[row][1] * yn[r];
+      if (WITH_D) sD[row][col] = dn[r];
     }
     __syncthreads();
     gram_chunk<T>(sP, sR, w, lane, a4);
@@ -880,7 +893,10 @@ __global__ __launch_bounds__(WG, 4) void k_update_y(Coef<T> c, Work wk,
     for (int i = 0; i < NODES_PER_WAVE; ++i) {
       const int row = w * NODES_PER_WAVE + i;
       const int64_t v = base + row;
-      if (v < u.end) Y[v * S + lane] = sP[row][lane];
+      if (v < u.end) {
+        Y[v * S + lane] = sP[row][lane];
+        if (WITH_D) D[v * S + lane] = sD[row][lane];
+      }
     }
     __syncthreads();
   }
@@ -2750,12 +2766,9 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
   } else if (cheb) {
     const T it = (T)b.cheb_invtheta;
     T* z1 = cheb_folds_z1<T>(b) ? nullptr : (T*)b.Za;  // z_1 = D^-1 R / theta
-    if (with_d)
-      hipLaunchKernelGGL((k_update_r<T, false, true, true>), g, blk, 0, st, c, wk, al, Q, P, R, D,
-                         b.part, z1, it);
-    else
-      hipLaunchKernelGGL((k_update_r<T, false, false, true>), g, blk, 0, st, c, wk, al, Q, P, R,
-                         D, b.part, z1, it);
+    // D += P A moves to K3, which reads P anyway
+    hipLaunchKernelGGL((k_update_r<T, false, false, true>), g, blk, 0, st, c, wk, al, Q, P, R, D,
+                       b.part, z1, it);
   } else {
     if (with_d)
       hipLaunchKernelGGL((k_update_r<T, false, true>), g, blk, 0, st, c, wk, al, Q, P, R, D,
@@ -2783,7 +2796,10 @@ static hipError_t iteration_t(bool indep, bool with_d, const Coef<T>& c, const S
     hipLaunchKernelGGL((k_update_y<T, true>), g, blk, 0, st, c, wk, de, R, P, Y, b.part);
     if (ev) hipEventRecord(ev[5], st);
   } else {
-    if (cheb)
+    if (cheb && with_d)
+      hipLaunchKernelGGL((k_update_y<T, false, true, true>), g, blk, 0, st, c, wk, de, Z, P, Y,
+                         b.part, al, D);
+    else if (cheb)
       hipLaunchKernelGGL((k_update_y<T, false, true>), g, blk, 0, st, c, wk, de, Z, P, Y, b.part);
     else
       hipLaunchKernelGGL((k_update_y<T, false>), g, blk, 0, st, c, wk, de, R, P, Y, b.part);
