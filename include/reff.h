@@ -112,6 +112,14 @@ typedef struct {
                             so the results are those of PCG with a stronger
                             preconditioner; fewer, costlier iterations);
                             0 => 19.  The independent variant uses Jacobi. */
+  int32_t pairs_resident_blocks;
+                         /* reff_query_pairs: solution blocks (64 endpoints
+                            each, n_nodes x 64 float64) kept on the device
+                            at once; 0 => as many as half the free device
+                            memory holds.  When the request needs more, the
+                            endpoints are solved in groups of that many
+                            blocks and memory stays bounded by the group
+                            (see reff_query_pairs). */
 } reff_solve_opts;
 
 typedef struct {
@@ -279,6 +287,15 @@ typedef enum {
  * (Sec. III-D: m x n bump-load pairs from m + n solves).
  *   a, b     host int64 node ids; R_out float64[m*n] row-major (host, or
  *            device if opts->out_on_device).  R(x,x) = 0.
+ * The distinct endpoints are solved in blocks of 64 columns.  When every
+ * solution block fits on the device at once (opts->pairs_resident_blocks),
+ * K_uv = (G^-1)_uv comes from the bilinear estimate x_u[v] + x_v[u] -
+ * x_u^T G x_v, whose error is second order in the solve error.  Otherwise
+ * the blocks are solved in groups that fit and dropped after each group:
+ * device memory is bounded by the group, K_uv within a group as above and
+ * across groups the first-order estimate (x_u[v] + x_v[u]) / 2; the solves
+ * then run to min(rel_tol, max(rel_tol^2, 1e-14)) so that the first-order
+ * terms stay near the requested accuracy.
  * Errors as reff_solve_diag.
  */
 reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m,

@@ -413,6 +413,7 @@ struct Opts {
   bool progress = false;          // progress lines on stderr
   int cheb = 19;                  // Chebyshev preconditioner degree (1 = Jacobi)
   int brhs = S;                   // right-hand sides dealt to one block (32 or 64)
+  int32_t resident = 0;           // reff_query_pairs: solution blocks on the device (0 = auto)
 };
 
 reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
@@ -452,6 +453,8 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
   // and the automatic choice (0) is 64.
   out.brhs = o->block_rhs == 32 ? 32 : S;
   out.timing = o->timing == 1;
+  if (o->pairs_resident_blocks < 0) return fail(REFF_ERR_INVALID_ARG, "pairs_resident_blocks < 0");
+  out.resident = o->pairs_resident_blocks;
   return REFF_OK;
 }
 
@@ -1452,44 +1455,67 @@ reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m, const int6
   HIPCHK(up(d_bid, b, (size_t)n * sizeof(int64_t)));
   HIPCHK(up(d_blk, blk_of.data(), (size_t)U * sizeof(int32_t)));
   HIPCHK(up(d_col, col_of.data(), (size_t)U * sizeof(int32_t)));
+  // Solution blocks kept on the device at once: all of them when they fit
+  // (every cross term exact to second order), else groups of `grp` blocks,
+  // each dropped once its endpoint rows and in-group cross terms are taken.
+  const size_t blk_bytes = (size_t)nn * S * sizeof(double);
+  int64_t grp = std::max<int64_t>(nblk, 1);
+  if (o.resident > 0) {
+    grp = std::min<int64_t>(grp, o.resident);
+  } else if (nblk > 0) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    const size_t avail = fr + p->ws.xs.bytes;  // the held solution buffer is reusable
+    grp = std::min<int64_t>(grp, std::max<int64_t>(1, (int64_t)(avail / 2 / blk_bytes)));
+  }
+  Opts og = o;
+  if (grp < nblk) og.tol = std::min(o.tol, std::max(o.tol * o.tol, 1e-14));
   if (U > 0) {
     reff_status rs;
-    if ((rs = ensure(p->ws.xs, (size_t)nblk * nn * S * sizeof(double))) != REFF_OK) return rs;
+    if ((rs = ensure(p->ws.xs, (size_t)grp * blk_bytes)) != REFF_OK) return rs;
     if ((rs = ensure(p->ws.out, (size_t)(U + 1) * sizeof(double))) != REFF_OK) return rs;
     double* xs = (double*)p->ws.xs.p;
-    std::vector<int64_t> xoff((size_t)nblk);
-    for (int64_t bb = 0; bb < nblk; ++bb) xoff[(size_t)bb] = bb * nn * S;
-    std::vector<BlockResult> br;
-    solve_rs = run_blocks(p->ws, *cs, stacks, jobs, (double*)p->ws.out.p, o, br, st, xs, &xoff);
-    if (solve_rs != REFF_OK && solve_rs != REFF_ERR_NO_CONVERGENCE) return solve_rs;
-    add_stats(st, br, 0, br.size());
-    // x_u[v] for every endpoint pair: the endpoint rows of each block
-    for (int64_t bb = 0; bb < nblk; ++bb)
-      HIPCHK(launch_gather_rows(xs + bb * nn * S, (const int64_t*)d_nodes, U,
-                                (double*)d_rows + bb * U * S, o.stream));
-    // Cross terms x_u^T G x_v between (and within) solved blocks: the
-    // bilinear estimate K_uv = x_u[v] + x_v[u] - x_u^T G x_v has an error that
-    // is a product of the two solution errors (second order).  All block
-    // pairs are queued on the stream; nothing waits on the host.
-    SolveBuffers sb;
-    PinnedBuf pin;
-    if ((rs = single_work(p->ws, stacks[0], sb, o.stream, pin)) != REFF_OK) return rs;
     const Coef<double> c64 = coef64(*cs);
-    for (int64_t b1 = 0; b1 < nblk; ++b1)
-      for (int64_t b2 = b1; b2 < nblk; ++b2) {
-        HIPCHK(launch_cross_gram(c64, xs + b1 * nn * S, xs + b2 * nn * S, sb, o.stream));
-        HIPCHK(hipMemcpyAsync((double*)d_cg + (b1 * nblk + b2) * S * S, sb.W,
-                              S * S * sizeof(double), hipMemcpyDeviceToDevice, o.stream));
-      }
-    HIPCHK(hipStreamSynchronize(o.stream));  // the pinned tables of single_work
+    for (int64_t g0 = 0; g0 < nblk; g0 += grp) {
+      const int64_t g1 = std::min(nblk, g0 + grp);
+      std::vector<BlockJob> gj(jobs.begin() + g0, jobs.begin() + g1);
+      std::vector<int64_t> xoff((size_t)(g1 - g0));
+      for (int64_t bb = g0; bb < g1; ++bb) xoff[(size_t)(bb - g0)] = (bb - g0) * nn * S;
+      std::vector<BlockResult> br;
+      const reff_status gs =
+          run_blocks(p->ws, *cs, stacks, gj, (double*)p->ws.out.p, og, br, st, xs, &xoff);
+      if (gs != REFF_OK && gs != REFF_ERR_NO_CONVERGENCE) return gs;
+      if (gs != REFF_OK) solve_rs = gs;
+      add_stats(st, br, 0, br.size());
+      // x_u[v] for every endpoint pair: the endpoint rows of each block
+      for (int64_t bb = g0; bb < g1; ++bb)
+        HIPCHK(launch_gather_rows(xs + (bb - g0) * nn * S, (const int64_t*)d_nodes, U,
+                                  (double*)d_rows + bb * U * S, o.stream));
+      // Cross terms x_u^T G x_v between (and within) the group's blocks: the
+      // bilinear estimate K_uv = x_u[v] + x_v[u] - x_u^T G x_v has an error
+      // that is a product of the two solution errors (second order).  The
+      // group's pairs are queued on the stream; the host waits once per
+      // group, before the next group's solves overwrite the blocks.
+      SolveBuffers sb;
+      PinnedBuf pin;
+      if ((rs = single_work(p->ws, stacks[0], sb, o.stream, pin)) != REFF_OK) return rs;
+      for (int64_t b1 = g0; b1 < g1; ++b1)
+        for (int64_t b2 = b1; b2 < g1; ++b2) {
+          HIPCHK(launch_cross_gram(c64, xs + (b1 - g0) * nn * S, xs + (b2 - g0) * nn * S, sb,
+                                   o.stream));
+          HIPCHK(hipMemcpyAsync((double*)d_cg + (b1 * nblk + b2) * S * S, sb.W,
+                                S * S * sizeof(double), hipMemcpyDeviceToDevice, o.stream));
+        }
+      HIPCHK(hipStreamSynchronize(o.stream));  // the pinned tables of single_work
+    }
   }
   if (m * n > 0) {
     double* dst = o.out_dev ? R_out : (double*)d_out;
     HIPCHK(launch_pairs_finish(m, n, (const int64_t*)d_ia, (const int64_t*)d_ib,
                                (const int64_t*)d_aid, (const int64_t*)d_bid,
                                (const int32_t*)d_blk, (const int32_t*)d_col,
-                               (const double*)d_rows, (const double*)d_cg, U, nblk, dst,
-                               o.stream));
+                               (const double*)d_rows, (const double*)d_cg, U, nblk, grp,
+                               dst, o.stream));
     if (!o.out_dev)
       HIPCHK(hipMemcpyAsync(R_out, d_out, (size_t)(m * n) * sizeof(double),
                             hipMemcpyDeviceToHost, o.stream));

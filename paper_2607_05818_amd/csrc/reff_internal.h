@@ -256,11 +256,12 @@ hipError_t launch_rows_times_loads(const double* X, const int32_t* rptr, const i
                                    const double* rw, int64_t nrows, const double* amps,
                                    int n_scen, double* out, int64_t ld, hipStream_t st);
 // R(a_i, b_j) on the device from gathered endpoint rows and block cross Grams
-// (see k_pairs_finish in reff_kernels.hip).
+// (see k_pairs_finish in reff_kernels.hip); blocks bu, bv with bu / grp !=
+// bv / grp were not resident together and have no cross Gram.
 hipError_t launch_pairs_finish(int64_t m, int64_t n, const int64_t* ia, const int64_t* ib,
                                const int64_t* aid, const int64_t* bid, const int32_t* blk,
                                const int32_t* col, const double* rows, const double* cg, int64_t U,
-                               int64_t nblk, double* out, hipStream_t st);
+                               int64_t nblk, int64_t grp, double* out, hipStream_t st);
 hipError_t launch_cross_gram(const Coef<double>& c, const double* Xa, const double* Xb,
                              const SolveBuffers& b, hipStream_t st);
 // rows[i*S + k] = X[nodes[i]*S + k] for i < count.

@@ -2899,12 +2899,15 @@ __global__ void k_pairs_finish(int64_t m, int64_t n, const int64_t* __restrict__
                                const int64_t* __restrict__ bid, const int32_t* __restrict__ blk,
                                const int32_t* __restrict__ col, const double* __restrict__ rows,
                                const double* __restrict__ cg, int64_t U, int64_t nblk,
-                               double* __restrict__ out) {
+                               int64_t grp, double* __restrict__ out) {
+  // Blocks of one resident group (bu / grp == bv / grp) have their cross
+  // Gram: bilinear estimate.  Across groups: the symmetric first-order one.
   auto K = [&](int64_t u, int64_t v) -> double {
     if (u < 0 || v < 0) return 0.0;
     const int64_t bu = blk[u], cu = col[u], bv = blk[v], cv = col[v];
     const double xuv = rows[(bu * U + v) * S + cu];
     const double xvu = rows[(bv * U + u) * S + cv];
+    if (bu / grp != bv / grp) return 0.5 * (xuv + xvu);
     const double g = bu <= bv ? cg[((bu * nblk + bv) * S + cu) * S + cv]
                               : cg[((bv * nblk + bu) * S + cv) * S + cu];
     return xuv + xvu - g;
@@ -2921,11 +2924,11 @@ __global__ void k_pairs_finish(int64_t m, int64_t n, const int64_t* __restrict__
 hipError_t launch_pairs_finish(int64_t m, int64_t n, const int64_t* ia, const int64_t* ib,
                                const int64_t* aid, const int64_t* bid, const int32_t* blk,
                                const int32_t* col, const double* rows, const double* cg, int64_t U,
-                               int64_t nblk, double* out, hipStream_t st) {
+                               int64_t nblk, int64_t grp, double* out, hipStream_t st) {
   if (m * n <= 0) return hipSuccess;
   const int64_t blocks = std::min<int64_t>((m * n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_pairs_finish, dim3((unsigned)blocks), dim3(256), 0, st, m, n, ia, ib, aid,
-                     bid, blk, col, rows, cg, U, nblk, out);
+                     bid, blk, col, rows, cg, U, nblk, std::max<int64_t>(grp, 1), out);
   return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ class reff_solve_opts(C.Structure):
         ("block_rhs", C.c_int32), ("stream", C.c_void_p), ("out_on_device", C.c_int32),
         ("krylov", C.c_int), ("max_ir_steps", C.c_int32), ("timing", C.c_int32),
         ("graphs", C.c_int32), ("progress", C.c_int32), ("precond_degree", C.c_int32),
+        ("pairs_resident_blocks", C.c_int32),
     ]
 
 
@@ -392,8 +393,11 @@ def reff_selinv_info(desc):
 
 def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
                      precision=REFF_PREC_FP64, rel_tol=0.0, max_iters=0,
-                     krylov=REFF_KRYLOV_BLOCK, stream=None, max_ir_steps=0, precond_degree=0):
-    """m x n pair resistances R(a_i, b_j).  Returns (R_out, stats)."""
+                     krylov=REFF_KRYLOV_BLOCK, stream=None, max_ir_steps=0, precond_degree=0,
+                     resident_blocks=0):
+    """m x n pair resistances R(a_i, b_j).  Returns (R_out, stats).
+    resident_blocks: solution blocks kept on the device at once (0 = as many
+    as half the free device memory holds)."""
     a = np.ascontiguousarray(a, dtype=np.int64)
     b = np.ascontiguousarray(b, dtype=np.int64)
     m, n = len(a), len(b)
@@ -403,6 +407,7 @@ def reff_query_pairs(pdn: PDN, a, b, mode=REFF_PAIRS_GROUNDED, R_out=None, *,
     optr = R_out.data_ptr() if out_dev else R_out.ctypes.data
     o = _opts(precision, rel_tol, max_iters, krylov, stream, out_dev, max_ir_steps,
               precond_degree=precond_degree)
+    o.pairs_resident_blocks = int(resident_blocks)
     st = reff_solve_stats()
     _check(_lib.reff_query_pairs(pdn.handle, a.ctypes.data, m, b.ctypes.data, n, int(mode),
                                  optr, C.byref(o), C.byref(st)))

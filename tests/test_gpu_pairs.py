@@ -143,3 +143,44 @@ def test_thousand_endpoints_recipe_side_256():
     print(f"max rel err {err:.3e}; {500 * 500 / dt:.3g} pairs/s ({dt:.2f} s)", flush=True)
     assert got[2, 1] == 0.0
     assert err <= 1e-6
+    # bounded memory: four solution blocks on the device at a time (four
+    # groups; cross-group terms first order after tighter solves)
+    _say("1000 endpoints, side 256, fp64, groups of 4 resident blocks")
+    t0 = time.perf_counter()
+    grp, st = reff.reff_query_pairs(h, a, b, mode=reff.REFF_PAIRS_GROUNDED,
+                                    precision=reff.REFF_PREC_FP64, rel_tol=1e-10,
+                                    resident_blocks=4)
+    dt = time.perf_counter() - t0
+    err = _rel(grp, want)
+    print(f"grouped: max rel err {err:.3e}; {500 * 500 / dt:.3g} pairs/s ({dt:.2f} s)", flush=True)
+    assert grp[2, 1] == 0.0
+    assert err <= 1e-6
+
+
+@pytest.mark.parametrize("prec,tol,rel_tol", [(0, 1e-6, 1e-7), (1, 1e-3, 1e-4)],
+                         ids=["fp64", "mixed"])
+@pytest.mark.parametrize("resident", [1, 2])
+def test_pairs_in_bounded_groups(prec, tol, rel_tol, resident):
+    """100 x 100 endpoints on the 2 x 32 x 32 stack (about 200 distinct, four
+    solve blocks) with one or two solution blocks on the device at a time:
+    the grouped path against the oracle and beside the all-resident call."""
+    reff = _reff()
+    d = gen.config1()
+    rng = np.random.default_rng(23)
+    a = rng.choice(2048, size=100, replace=False)
+    b = rng.choice(2048, size=100, replace=False)
+    a[0] = ro.pad_nodes(d)[0]
+    b[1] = a[3]
+    want = ro.pairs(d, a, b, ro.GROUNDED)
+    _say("bounded pairs, resident", resident, "prec", prec)
+    h = reff.reff_build_pdn(d)
+    full, _ = reff.reff_query_pairs(h, a, b, reff.REFF_PAIRS_GROUNDED, precision=prec,
+                                    rel_tol=rel_tol)
+    got, st = reff.reff_query_pairs(h, a, b, reff.REFF_PAIRS_GROUNDED, precision=prec,
+                                    rel_tol=rel_tol, resident_blocks=resident)
+    err, err_full = _rel(got, want), _rel(full, want)
+    print("max rel err grouped", err, "all resident", err_full, st, flush=True)
+    assert got[3, 1] == 0.0
+    assert err <= tol and err_full <= tol
+    with pytest.raises(reff.ReffError):
+        reff.reff_query_pairs(h, a, b, reff.REFF_PAIRS_GROUNDED, resident_blocks=-1)
