@@ -463,7 +463,8 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram_strip(Coef<T> c, Work wk
   constexpr int NPW = NODES_PER_WAVE;
   __shared__ __align__(16) T win[3][HWW][LDW];
   __shared__ __align__(16) T sR[2][CH][LDW];  // R rows of row y in buffer s % 2
-  __shared__ __align__(16) T sQ[CH][LDW];     // G Y rows, then Q rows
+  __shared__ __align__(16) T sQ[CH][LDW];     // G Y rows
+  __shared__ __align__(16) T sQo[CH][LDW];    // Q rows
   __shared__ __align__(16) T sP[CH][LDW];
   // Stencil coefficients of row y (buffer s % 2): d, cE from node x0-1 on,
   // cN (buffer s % 2 = row y, the other = row y-1), TSV slot.
@@ -621,28 +622,30 @@ __global__ __launch_bounds__(WG, 4) void k_stencil_gram_strip(Coef<T> c, Work wk
     __syncthreads();
     typename Acc<T>::type pt, qt;
     prod_tile2<T>(&win[sc][1], sQ, nb, breg, lane, pt, qt, cb + 1);
-    __syncthreads();
+    // Two barriers per row.  sP, sQo and sR[b ^ 1] were last read by the
+    // previous row's Grams, which precede the barrier after this row's
+    // stencil; so were the window slot of row y - 1 and the coefficients of
+    // row y - 1 (read by this row's stencil).  Row y + 2, R of row y + 1 and
+    // the coefficients of row y + 1 go there now, before the barrier that
+    // opens the Grams and makes them visible to the next row's stencil.
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = nb * 16 + tile_row<T>(lane, r), col = cb * 16 + (lane & 15);
       sP[row][col] = pt[r];
-      sQ[row][col] = qt[r];
+      sQo[row][col] = qt[r];
     }
-    __syncthreads();
-    gram_chunk2<T>(sP, sQ, sR[b], w, lane, a1, a2);
-    // Row y + 2 replaces row y - 1 (last read by the stencil above); the
-    // coefficients of row y + 1 replace those of row y - 1.
     store_row(ss, ny_v, ny_h, y + 2);
     store_r(b ^ 1, r_v);
     store_coef(b ^ 1, c_v, c_sl);
+    __syncthreads();
+    gram_chunk2<T>(sP, sQo, sR[b], w, lane, a1, a2);
     // nodes past a ragged strip's width store the last node's row again
 #pragma unroll
     for (int i = 0; i < NPW; ++i) {
       const int jc = min(w * NPW + i, wdt - 1);
       P[(obase + jc) * S + lane] = sP[jc][lane];
-      Q[(obase + jc) * S + lane] = sQ[jc][lane];
+      Q[(obase + jc) * S + lane] = sQo[jc][lane];
     }
-    __syncthreads();
   }
   gram_store<T>(part_of(part, sidx, 0), w, lane, a1);
   gram_store<T>(part_of(part, sidx, 1), w, lane, a2);
