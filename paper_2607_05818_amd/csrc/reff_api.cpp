@@ -520,9 +520,12 @@ constexpr int TARGET_UNITS = 1024;  // 4 workgroups of 512 threads per CU
 
 // Split the solve blocks of a group into work units: each block's row range
 // is cut into chunk-aligned pieces, about TARGET_UNITS in total, in
-// proportion to the block sizes.
+// proportion to the block sizes, and at least `floor` per block where the
+// block has 64 chunks per unit to give: blocks converge at different times
+// and leave the active lists, so a block that runs on alone still spreads
+// over the whole device.
 void make_units(const std::vector<PlanDesc>& in, std::vector<PlanDesc>& plans,
-                std::vector<Unit>& units, int target = TARGET_UNITS) {
+                std::vector<Unit>& units, int target = TARGET_UNITS, int floor = 0) {
   int64_t rows = 0;
   for (const PlanDesc& p : in) rows += p.n;
   plans = in;
@@ -531,6 +534,7 @@ void make_units(const std::vector<PlanDesc>& in, std::vector<PlanDesc>& plans,
     PlanDesc& p = plans[i];
     const int64_t nch = (p.n + CH - 1) / CH;
     int64_t k = (target * p.n + rows - 1) / std::max<int64_t>(rows, 1);
+    k = std::max<int64_t>(k, std::min<int64_t>(floor, nch / 64));
     k = std::max<int64_t>(1, std::min<int64_t>(k, nch));
     const int64_t cpu = (nch + k - 1) / k;  // chunks per unit
     p.unit_begin = (int32_t)units.size();
@@ -557,9 +561,10 @@ int64_t max_strip_rows(int64_t nx) {
 // Strips for the stencil kernel of a group (float32 block variant): every
 // block's tiers are cut into CH-wide x strips and, when that gives too few
 // workgroups, into y segments, about TARGET_UNITS strips in total (and no
-// more than max_strip_rows rows each).
+// more than max_strip_rows rows each); at least `floor` per block while the
+// segments keep 64 rows or more (as for work units).
 void make_strips(std::vector<PlanDesc>& plans, std::vector<Strip>& strips,
-                 int target = TARGET_UNITS) {
+                 int target = TARGET_UNITS, int floor = 0) {
   int64_t rows = 0;
   for (const PlanDesc& p : plans) rows += p.n;
   strips.clear();
@@ -567,7 +572,8 @@ void make_strips(std::vector<PlanDesc>& plans, std::vector<Strip>& strips,
     PlanDesc& p = plans[i];
     const int64_t nx = p.nx, ny = p.plane / p.nx, nt = p.n / p.plane;
     const int64_t nsx = (nx + CH - 1) / CH;
-    const int64_t want = std::max<int64_t>(1, (target * p.n + rows - 1) / std::max<int64_t>(rows, 1));
+    int64_t want = std::max<int64_t>(1, (target * p.n + rows - 1) / std::max<int64_t>(rows, 1));
+    want = std::max<int64_t>(want, std::min<int64_t>(floor, nt * nsx * std::max<int64_t>(1, ny / 64)));
     const int64_t ysegs = std::min<int64_t>(ny, std::max<int64_t>(1, (want + nt * nsx - 1) / (nt * nsx)));
     const int64_t hcap = max_strip_rows(nx);
     const int64_t H = std::min<int64_t>((ny + ysegs - 1) / ysegs, std::max<int64_t>(hcap, 1));
@@ -724,16 +730,24 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
   // device-resident active lists), so chunks can span several iterations
   // with one host round trip each.
   if (use_graph) poll = 4;
+  // rows of the jobs from j on, so that groups come out balanced: a group
+  // closes once it holds its share of the remaining rows (16 equal blocks
+  // under a budget of 15 make two groups of 8, not 15 + 1)
+  std::vector<int64_t> rows_from(jobs.size() + 1, 0);
+  for (size_t j = jobs.size(); j-- > 0;)
+    rows_from[j] = rows_from[j + 1] + stacks[(size_t)jobs[j].stack].n;
   size_t j0 = 0;
   while (j0 < jobs.size()) {
     // ---- group of jobs within the row budget
+    const int64_t ngr = (rows_from[j0] + budget_rows - 1) / budget_rows;
+    const int64_t cap = std::min(budget_rows, (rows_from[j0] + ngr - 1) / std::max<int64_t>(ngr, 1));
     size_t j1 = j0;
     int64_t rows = 0, slot_rows = 0;
     int max_slots = 0;  // most TSV slots of one block
     std::vector<PlanDesc> pin;
     while (j1 < jobs.size()) {
       const StackInfo& sk = stacks[(size_t)jobs[j1].stack];
-      if (j1 > j0 && rows + sk.n > budget_rows) break;
+      if (j1 > j0 && (rows >= cap || rows + sk.n > budget_rows)) break;
       PlanDesc pd{};
       pd.cbase = sk.cbase;
       pd.vbase = rows;
@@ -783,11 +797,15 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     for (size_t attempt = 0; attempt <= trials.size(); ++attempt) {
     const bool trial = attempt < trials.size();
     const TuneChoice tc = trial ? trials[attempt] : target;
-    make_units(pin, plans, units, tc.units);
+    // one stack (a request on one network): a floor of work per block, so
+    // that the last unconverged blocks still fill the device; plan batches
+    // keep the tuned totals
+    const int floor = stacks.size() == 1 ? TARGET_UNITS / 2 : 0;
+    make_units(pin, plans, units, tc.units, floor);
     nu = (int)units.size();
     strips.clear();
     const bool cheb = !o.indep && o.cheb > 1;
-    if ((fp32 || cheb) && !o.indep) make_strips(plans, strips, tc.strips);
+    if ((fp32 || cheb) && !o.indep) make_strips(plans, strips, tc.strips, floor);
     ns = (int)strips.size();
     // ---- buffers
     reff_status rs;
