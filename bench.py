@@ -727,8 +727,9 @@ def large_run(args, reff, gen, log):
     """The large stack (8 tiers of 2048 x 2048, 33,554,432 nodes): a full
     map is out of reach on one GPU, so the first `large_blocks` 64-node
     blocks of a seeded sample are solved (mixed precision), the 1M-node
-    wall time is projected from that rate, and the first block is checked
-    against the float64 block PCG on the same GPU at rel_tol 1e-8."""
+    wall time is projected from that rate, the first block is checked
+    against the float64 block PCG on the same GPU at rel_tol 1e-8, and the
+    first 16 nodes against the oracle's Rayleigh window bounds."""
     import numpy as np
     import torch
     desc = gen.config5()
@@ -753,6 +754,21 @@ def large_run(args, reff, gen, log):
     got = out.cpu().numpy()[:S]
     err = float(np.max(np.abs(got - ref) / ref))
     log(f"float64 check: {S / dt64:.2f} nodes/s, {st64['iters_total']} iterations, max rel diff {err:.2e}")
+    # the oracle at this size: Rayleigh window bounds (exact float64 solves
+    # of the 129 x 129-column window around each node, outside cut or
+    # merged into the supply) on the first 16 nodes
+    from oracle import bounds
+    allr = out.cpu().numpy()
+    half, inside, finite, gaps = 64, 0, 0, []
+    a = time.perf_counter()
+    for v, r in zip(nodes[:16], allr[:16]):
+        lo, hi = bounds.window_bounds(desc, v, half)
+        inside += int(lo * (1 - 1e-3) <= r <= hi * (1 + 1e-3))
+        if np.isfinite(hi):
+            finite += 1
+            gaps.append((hi - lo) / r)
+    log(f"Rayleigh window bounds: {inside}/16 inside, {finite} finite upper bounds, "
+        f"{time.perf_counter() - a:.1f} s")
     kms = np.array(st["kernel_ms"])
     kl = np.array(st["kernel_launches"])
     rec = {
@@ -769,6 +785,10 @@ def large_run(args, reff, gen, log):
         "projected_hours_for_1M_nodes": 1e6 / (len(nodes) / dt) / 3600,
         "fp64_check": {"nodes": S, "max_rel_diff": err, "iters": st64["iters_total"],
                        "nodes_per_s": S / dt64, "rel_tol": 1e-8},
+        "oracle_bounds": {"kind": "Rayleigh window bounds (oracle/bounds.py)", "nodes": 16,
+                          "window": f"{2 * half + 1} x {2 * half + 1} columns, all tiers",
+                          "inside_within_1e-3": inside, "finite_upper": finite,
+                          "median_rel_gap": float(np.median(gaps)) if gaps else None},
     }
     print(json.dumps(rec), flush=True)
 

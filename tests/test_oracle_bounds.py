@@ -1,0 +1,83 @@
+"""Pins of oracle/bounds.py (Rayleigh window bounds on R_i) against what
+the mathematics fixes: a chain's series and parallel closed forms, the exact
+values of the independent oracle on small stacks (reff_oracle.diag, a dense
+inverse or sparse LU), the whole-plane window (no cut, no merge: both bounds
+exact) and the monotone closing-in of nested windows."""
+import numpy as np
+import pytest
+
+from oracle import bounds as ob
+from oracle import reff_oracle as ro
+from paper_2607_05818_amd import gen
+
+REL = 1e-11  # float64 solves of the same small systems, different orders
+
+
+def _chain(g):
+    """One tier, len(g) + 1 nodes in a row, edge j between x = j and j + 1,
+    the pad at x = 0."""
+    n = len(g) + 1
+    return gen.make_desc(1, n, 1, np.asarray(g).reshape(1, 1, n - 1),
+                         np.zeros((1, 0, n)), np.zeros((0, 2)), np.zeros((0, 0)),
+                         np.array([[0, 0]]))
+
+
+@pytest.mark.parametrize("i,half", [(5, 2), (5, 5), (5, 7), (9, 3), (1, 1), (11, 4)])
+def test_chain_closed_forms(i, half):
+    """Series resistances along the chain: the upper bound is the path to
+    the pad when the window holds it (else infinite); the lower bound is the
+    parallel combination of the paths to the pad or the left ring node and
+    to the right ring node (none when the window reaches the chain's end)."""
+    rng = np.random.default_rng(100 + i + half)
+    g = rng.uniform(0.5, 2.0, size=12)
+    d = _chain(g)
+    n = len(g) + 1
+    x0, x1 = max(0, i - half), min(n, i + half + 1)
+    to_pad = float(np.sum(1.0 / g[:i]))
+    up = to_pad if x0 == 0 else np.inf
+    left = to_pad if x0 == 0 else float(np.sum(1.0 / g[x0 - 1:i]))
+    right = float(np.sum(1.0 / g[i:x1])) if x1 < n else np.inf
+    low = 1.0 / (1.0 / left + (0.0 if np.isinf(right) else 1.0 / right))
+    lo, hi = ob.window_bounds(d, i, half)
+    assert lo == pytest.approx(low, rel=REL)
+    if np.isinf(up):
+        assert np.isinf(hi)
+    else:
+        assert hi == pytest.approx(up, rel=REL)
+    # the exact value lies between
+    assert lo <= to_pad * (1 + REL) and to_pad <= hi * (1 + REL)
+
+
+@pytest.mark.parametrize("seed,nt,nx,ny,ntsv,npad", [(31, 2, 9, 7, 5, 2), (32, 3, 12, 5, 8, 3),
+                                                     (33, 1, 10, 10, 0, 1), (34, 4, 6, 8, 6, 2)])
+def test_bounds_bracket_exact_values_and_close_in(seed, nt, nx, ny, ntsv, npad):
+    d = gen.small_random_desc(seed, nt, nx, ny, ntsv, npad)
+    exact = ro.diag(d)
+    n = nt * nx * ny
+    for v in range(0, n, 3):
+        prev = (0.0, np.inf)
+        for half in (1, 2, 3, 5, 8):
+            lo, hi = ob.window_bounds(d, v, half)
+            assert lo <= exact[v] * (1 + REL) + 1e-15
+            assert exact[v] <= hi * (1 + REL)
+            # nested windows: cut less, merge less
+            assert lo >= prev[0] * (1 - REL) and hi <= prev[1] * (1 + REL)
+            prev = (lo, hi)
+        # a window holding the whole plane cuts and merges nothing
+        lo, hi = ob.window_bounds(d, v, max(nx, ny))
+        if exact[v] == 0.0:
+            assert lo == 0.0 and hi == 0.0
+        else:
+            assert lo == pytest.approx(exact[v], rel=REL)
+            assert hi == pytest.approx(exact[v], rel=REL)
+
+
+def test_window_without_pad_on_upper_tier_has_no_upper_bound():
+    """An upper-tier node whose window holds no TSV column cannot reach a
+    pad inside the window: the upper bound is infinite, the lower finite."""
+    d = gen.make_desc(2, 9, 9, np.ones((2, 9, 8)), np.ones((2, 8, 9)), np.array([[0, 0]]),
+                      np.ones((1, 1)), np.array([[0, 0]]))
+    v = 81 + 4 * 9 + 4  # tier 1, (4, 4)
+    lo, hi = ob.window_bounds(d, v, 2)
+    assert np.isinf(hi) and 0 < lo < np.inf
+    assert lo <= ro.diag(d, [v])[0]
