@@ -233,6 +233,39 @@ def grid_pairs_compare(reff, log, M=512, N=512, P=256, reps=5):
             "direct_form_equiv_tflops": direct, "max_rel_err_sampled": err}
 
 
+def large_compare(reff, gen, log, rel_tol, half=64):
+    """The large workload at full size (8 tiers of 2048 x 2048, 33,554,432
+    nodes): one mixed-precision block of 64 seeded nodes (one call, set-up
+    included), its first 16 nodes checked against the oracle's Rayleigh
+    window bounds (oracle/bounds.py: exact float64 solves of the window
+    around each node with the outside cut or merged into the supply).
+    `bench.py --large` adds a float64 check of the whole block."""
+    import numpy as np
+    from oracle import bounds
+    reff.reff_release_cached_memory(0)  # the batched direct path's workspace
+    desc = gen.config5()
+    nodes = gen.sample_free_nodes(desc, S, 5005)
+    h = reff.reff_build_pdn(desc, device=0)
+    a = time.perf_counter()
+    R, st = reff.reff_solve_diag(h, nodes, precision=reff.REFF_PREC_MIXED, rel_tol=rel_tol)
+    dt = time.perf_counter() - a
+    h.close()
+    inside, finite, gaps = 0, 0, []
+    for v, r in zip(nodes[:16], R[:16]):
+        lo, hi = bounds.window_bounds(desc, v, half)
+        inside += int(lo * (1 - 1e-3) <= r <= hi * (1 + 1e-3))
+        if np.isfinite(hi):
+            finite += 1
+            gaps.append((hi - lo) / r)
+    log(f"large stack: {S / dt:.2f} nodes/s ({dt:.1f} s, {st['iters_total']} block iterations); "
+        f"{inside}/16 inside the oracle's window bounds")
+    return {"workload": "8 tiers x 2048 x 2048 (33,554,432 nodes), 64 seeded nodes, mixed",
+            "nodes_per_s": S / dt, "seconds": dt, "iters": st["iters_total"],
+            "oracle_bounds": {"nodes": 16, "window": f"{2 * half + 1} x {2 * half + 1} columns",
+                              "inside_within_1e-3": inside, "finite_upper": finite,
+                              "median_rel_gap": float(np.median(gaps)) if gaps else None}}
+
+
 def batched_compare(reff, gen, log, rel_tol, n_seq=16, reps=3):
     """The batching workload: 256 candidate TSV plans (2-4 tiers, sides
     64-256, about 22M nodes in total) with one seeded 64-node block per
@@ -854,6 +887,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the full-size large-stack leg (about a minute)")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--large", action="store_true",
                     help="only the large-stack subset measurement (8 x 2048 x 2048)")
@@ -1077,6 +1112,8 @@ def main():
         compare["batched_plans"] = batched_compare(reff, gen, log, args.rel_tol)
     if not args.no_surrogate and args.precision == "mixed":
         compare["surrogate_screened"] = surrogate_compare(reff, gen, log, args.rel_tol)
+    if not args.no_large and not args.no_compare and args.precision == "mixed":
+        compare["large_stack"] = large_compare(reff, gen, log, args.rel_tol)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -225,10 +225,15 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes,
  * reff_selinv_diag for many stacks (candidate TSV plans, Sec. I and IV-B) in
  * one call, with no handle: the plans' dissection trees are analysed on
  * host threads and merged by depth, so every plan's fronts of one tree
- * level share the same launches.  Device memory (about the sum of the plans'
- * reff_selinv_info().device_bytes) comes from a workspace the library keeps
- * between calls (reff_release_cached_memory frees it).  Inputs as
- * reff_batch_plans:
+ * level share the same launches.  Batches above 8M nodes run as up to four
+ * chunks of consecutive plans, the host analysis of a chunk overlapping the
+ * device work of the one before.  Device memory (about the sum of a chunk's
+ * plans' reff_selinv_info().device_bytes) comes from a workspace the library
+ * keeps between calls (reff_release_cached_memory frees it).  With node
+ * lists, only the fronts holding the requested nodes and their ancestors go
+ * through the selected inversion (same values bit for bit).  In `st`,
+ * seconds_plan is the host analysis the device work did not hide.  Inputs
+ * as reff_batch_plans:
  *   plans    host array of n_plans stack descriptions (validated as
  *            reff_build_pdn does, and checked for connectivity).
  *   nodes    NULL, or host array of n_plans node-id arrays (an entry NULL =
@@ -237,6 +242,9 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes,
  *   opts     NULL => defaults; only stream and out_on_device are read.  Runs
  *            on the current device.
  * Errors: INVALID_ARG (naming the plan), DISCONNECTED, OUT_OF_MEMORY, DEVICE.
+ * Descriptors and node ids are validated before any device work, and so is
+ * the analysis of the first chunk (of every plan, below 8M nodes); R_out is
+ * written only when the call succeeds.
  */
 reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
                               const int64_t* const* nodes, const int64_t* n_nodes,

@@ -797,10 +797,9 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
     for (size_t attempt = 0; attempt <= trials.size(); ++attempt) {
     const bool trial = attempt < trials.size();
     const TuneChoice tc = trial ? trials[attempt] : target;
-    // one stack (a request on one network): a floor of work per block, so
-    // that the last unconverged blocks still fill the device; plan batches
-    // keep the tuned totals
-    const int floor = stacks.size() == 1 ? TARGET_UNITS / 2 : 0;
+    // a floor of work per block (where the block is large enough), so that
+    // the last unconverged blocks of a group still fill the device
+    const int floor = TARGET_UNITS / 2;
     make_units(pin, plans, units, tc.units, floor);
     nu = (int)units.size();
     strips.clear();

@@ -42,6 +42,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "reff_internal.h"
@@ -1053,94 +1054,169 @@ reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
         return host_fail(REFF_ERR_INVALID_ARG,
                          who + "node id " + std::to_string(nodes[i][k]) + " out of range");
   }
-  // symbolic analysis of every plan on host threads, then one forest
-  std::vector<SelinvPlan> sp(np);
-  std::vector<std::string> err(np);
-  std::vector<char> ok(np, 0), disc(np, 0);
-  selinv_parallel_for(np, [&](size_t i) {
-    const reff_pdn_desc& d = plans[i];
-    bool dis = false;
-    ok[i] = build_selinv_plan(d.n_tiers, d.nx, d.ny, d.gx, d.gy, d.n_tsv, d.tsv_xy, d.tsv_g,
-                              d.n_pads, d.pad_xy, LEAF_AREA, sp[i], err[i], &dis);
-    disc[i] = dis;
-  });
-  for (size_t i = 0; i < np; ++i)
-    if (!ok[i])
-      return host_fail(disc[i] ? REFF_ERR_DISCONNECTED : REFF_ERR_INVALID_ARG,
-                       "plan " + std::to_string(i) + ": " + err[i]);
-  std::vector<int64_t> base;
-  const SelinvPlan P = merge_selinv_plans(sp, base);
-  sp.clear();
-  const auto t_plan = std::chrono::steady_clock::now();
-  reff_status s;
-  auto dev_sp = selinv_device_build(P, s, true);
-  if (!dev_sp) return s;
-  const SelinvDevice& D = *dev_sp;
-  const auto t_setup = std::chrono::steady_clock::now();
-  // requested nodes of every plan, in plan order, picked into one array
-  std::vector<int64_t> ids;
+  // Plans are taken in chunks of consecutive plans with about equal node
+  // counts (one chunk below 8M nodes, at most four): the host analysis of
+  // chunk c + 1 runs on host threads while the device factors and inverts
+  // chunk c, and each chunk is one forest (the plans' trees merged by
+  // depth) on the device workspace.
+  int64_t tot_n = 0;
+  std::vector<int64_t> pn(np);
+  for (size_t i = 0; i < np; ++i) {
+    pn[i] = (int64_t)plans[i].n_tiers * plans[i].nx * plans[i].ny;
+    tot_n += pn[i];
+  }
+  const int64_t nch = std::max<int64_t>(
+      1, std::min<int64_t>({(int64_t)4, (int64_t)np, tot_n / (int64_t(8) << 20)}));
+  std::vector<size_t> cb{0};
+  {
+    const int64_t share = (tot_n + nch - 1) / nch;
+    int64_t acc = 0;
+    for (size_t i = 0; i < np; ++i) {
+      acc += pn[i];
+      if (acc >= share * (int64_t)cb.size() && (int64_t)cb.size() < nch && i + 1 < np)
+        cb.push_back(i + 1);
+    }
+    cb.push_back(np);
+  }
+  struct Chunk {
+    SelinvPlan P;
+    std::vector<int64_t> base;
+    reff_status s = REFF_OK;
+    std::string err;
+  };
+  auto analyse = [&](size_t c, Chunk& out) {
+    const size_t p0 = cb[c], p1 = cb[c + 1];
+    std::vector<SelinvPlan> sp(p1 - p0);
+    std::vector<std::string> err(p1 - p0);
+    std::vector<char> ok(p1 - p0, 0), disc(p1 - p0, 0);
+    selinv_parallel_for(p1 - p0, [&](size_t k) {
+      const reff_pdn_desc& d = plans[p0 + k];
+      bool dis = false;
+      ok[k] = build_selinv_plan(d.n_tiers, d.nx, d.ny, d.gx, d.gy, d.n_tsv, d.tsv_xy, d.tsv_g,
+                                d.n_pads, d.pad_xy, LEAF_AREA, sp[k], err[k], &dis);
+      disc[k] = dis;
+    });
+    for (size_t k = 0; k < p1 - p0; ++k)
+      if (!ok[k]) {
+        out.s = disc[k] ? REFF_ERR_DISCONNECTED : REFF_ERR_INVALID_ARG;
+        out.err = "plan " + std::to_string(p0 + k) + ": " + err[k];
+        return;
+      }
+    out.P = merge_selinv_plans(sp, out.base);
+  };
+  // requested nodes of every plan, in plan order, into one device array
   int64_t total = 0;
-  bool every = true;
-  for (size_t i = 0; i < np; ++i) {
-    total += cnt[i];
-    every = every && !(nodes && nodes[i]);
-  }
-  ids.reserve((size_t)total);
-  for (size_t i = 0; i < np; ++i) {
-    const bool given = nodes && nodes[i];
-    for (int64_t k = 0; k < cnt[i]; ++k) ids.push_back(base[i] + (given ? nodes[i][k] : k));
-  }
-  // with node lists, only their fronts and ancestors are inverted
-  double fl_sel = P.flops_selinv;
-  std::vector<uint8_t> need;
-  if (!every) need = needed_fronts(P, ids, &fl_sel);
-  std::chrono::steady_clock::time_point t_fact;
-  s = selinv_run(P, D, st_, t_fact, every ? nullptr : &need);
-  if (s != REFF_OK) return s;
+  std::vector<int64_t> out_at(np + 1, 0);
+  for (size_t i = 0; i < np; ++i) out_at[i + 1] = out_at[i] + cnt[i];
+  total = out_at[np];
+  double t_plan = 0.0, t_setup = 0.0, t_factor = 0.0, t_selinv = 0.0;
+  int64_t n_fronts = 0, max_front = 0, dev_bytes = 0;
+  int32_t n_levels = 0;
+  double fl_fact = 0.0, fl_sel = 0.0;
+  auto tp = std::chrono::steady_clock::now();
+  auto cur = std::make_unique<Chunk>();
+  analyse(0, *cur);
+  t_plan += std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count();
+  // a plan of the first chunk that fails its analysis is refused before any
+  // device work; later chunks' failures come after earlier chunks' device
+  // work, with nothing written to R_out either way
+  if (cur->s != REFF_OK) return host_fail(cur->s, cur->err);
   Bufs b;
-  int64_t* dids = nullptr;
   double* dres = nullptr;
-  hipError_t e = put(b, &dids, ids, st_);
-  if (e == hipSuccess) e = b.get(&dres, (size_t)total);
-  if (e == hipSuccess && total > 0) {
-    hipLaunchKernelGGL(k_pick, flat(total), dim3(256), 0, st_, D.Rfull, dids, total, dres);
-    e = hipGetLastError();
+  hipError_t e = b.get(&dres, (size_t)total);
+  if (e != hipSuccess) return dev_status(e, "selected inversion batch: output");
+  for (size_t c = 0; c + 1 < cb.size(); ++c) {
+    if (cur->s != REFF_OK) return host_fail(cur->s, cur->err);
+    auto next = std::make_unique<Chunk>();
+    std::thread ahead;
+    if (c + 2 < cb.size()) ahead = std::thread([&, c] { analyse(c + 1, *next); });
+    struct Join {
+      std::thread& t;
+      ~Join() {
+        if (t.joinable()) t.join();
+      }
+    } join{ahead};
+    const SelinvPlan& P = cur->P;
+    const size_t p0 = cb[c], p1 = cb[c + 1];
+    const auto t0c = std::chrono::steady_clock::now();
+    reff_status s;
+    auto dev_sp = selinv_device_build(P, s, true);
+    if (!dev_sp) return s;
+    const SelinvDevice& D = *dev_sp;
+    const auto t_set = std::chrono::steady_clock::now();
+    std::vector<int64_t> ids;
+    ids.reserve((size_t)(out_at[p1] - out_at[p0]));
+    bool every = true;
+    for (size_t i = p0; i < p1; ++i) {
+      const bool given = nodes && nodes[i];
+      every = every && !given;
+      for (int64_t k = 0; k < cnt[i]; ++k)
+        ids.push_back(cur->base[i - p0] + (given ? nodes[i][k] : k));
+    }
+    // with node lists, only their fronts and ancestors are inverted
+    double fl = P.flops_selinv;
+    std::vector<uint8_t> need;
+    if (!every) need = needed_fronts(P, ids, &fl);
+    std::chrono::steady_clock::time_point t_fact;
+    s = selinv_run(P, D, st_, t_fact, every ? nullptr : &need);
+    if (s != REFF_OK) return s;
+    Bufs bc;
+    int64_t* dids = nullptr;
+    e = put(bc, &dids, ids, st_);
+    const int64_t nc = (int64_t)ids.size();
+    if (e == hipSuccess && nc > 0) {
+      hipLaunchKernelGGL(k_pick, flat(nc), dim3(256), 0, st_, D.Rfull, dids, nc,
+                         dres + out_at[p0]);
+      e = hipGetLastError();
+    }
+    // the workspace and the staged ids are reused or freed after this
+    if (e == hipSuccess) e = hipStreamSynchronize(st_);
+    if (e != hipSuccess) return dev_status(e, "selected inversion batch");
+    const auto t_end = std::chrono::steady_clock::now();
+    t_setup += std::chrono::duration<double>(t_set - t0c).count();
+    t_factor += std::chrono::duration<double>(t_fact - t_set).count();
+    t_selinv += std::chrono::duration<double>(t_end - t_fact).count();
+    n_fronts += (int64_t)P.fronts.size();
+    n_levels = std::max<int32_t>(n_levels, (int32_t)P.levels.size());
+    for (const SnFront& f : P.fronts) max_front = std::max<int64_t>(max_front, f.F);
+    dev_bytes = std::max<int64_t>(dev_bytes, D.sz.bytes);
+    fl_fact += P.flops_factor;
+    fl_sel += fl;
+    dev_sp.reset();
+    // the next chunk's analysis: whatever of it the device work did not hide
+    const auto tw = std::chrono::steady_clock::now();
+    if (ahead.joinable()) ahead.join();
+    t_plan += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count();
+    cur = std::move(next);
   }
   std::vector<double> host;
-  if (e == hipSuccess && !out_dev) {
+  if (!out_dev) {
     host.resize((size_t)total);
     if (total > 0)
       e = hipMemcpyAsync(host.data(), dres, sizeof(double) * total, hipMemcpyDeviceToHost, st_);
   }
-  int64_t at = 0;
-  for (size_t i = 0; i < np && e == hipSuccess; ++i) {
+  for (size_t i = 0; i < np && e == hipSuccess; ++i)
     if (cnt[i] > 0 && out_dev)
-      e = hipMemcpyAsync(R_out[i], dres + at, sizeof(double) * cnt[i], hipMemcpyDeviceToDevice,
-                         st_);
-    at += cnt[i];
-  }
+      e = hipMemcpyAsync(R_out[i], dres + out_at[i], sizeof(double) * cnt[i],
+                         hipMemcpyDeviceToDevice, st_);
   if (e == hipSuccess) e = hipStreamSynchronize(st_);
   if (e != hipSuccess) return dev_status(e, "selected inversion batch");
-  if (!out_dev) {
-    at = 0;
-    for (size_t i = 0; i < np; ++i) {
-      if (cnt[i] > 0) std::memcpy(R_out[i], host.data() + at, sizeof(double) * cnt[i]);
-      at += cnt[i];
-    }
-  }
+  if (!out_dev)
+    for (size_t i = 0; i < np; ++i)
+      if (cnt[i] > 0) std::memcpy(R_out[i], host.data() + out_at[i], sizeof(double) * cnt[i]);
   const auto t1 = std::chrono::steady_clock::now();
   if (st) {
-    st->n_fronts = (int64_t)P.fronts.size();
-    st->n_levels = (int32_t)P.levels.size();
-    for (const SnFront& f : P.fronts) st->max_front = std::max<int64_t>(st->max_front, f.F);
-    st->device_bytes = D.sz.bytes;
-    st->flops_factor = P.flops_factor;
+    st->n_fronts = n_fronts;
+    st->n_levels = n_levels;
+    st->max_front = max_front;
+    st->device_bytes = dev_bytes;
+    st->flops_factor = fl_fact;
     st->flops_selinv = fl_sel;
     st->seconds = std::chrono::duration<double>(t1 - t0).count();
-    st->seconds_plan = std::chrono::duration<double>(t_plan - t0).count();
-    st->seconds_factor = std::chrono::duration<double>(t_fact - t_plan).count();
-    st->seconds_selinv = std::chrono::duration<double>(t1 - t_fact).count();
-    st->seconds_setup = std::chrono::duration<double>(t_setup - t_plan).count();
+    st->seconds_plan = t_plan;
+    st->seconds_setup = t_setup;
+    st->seconds_factor = t_factor + t_setup;
+    st->seconds_selinv = t_selinv;
   }
   return REFF_OK;
 }
