@@ -831,7 +831,7 @@ def full_map_run(args, reff, gen, log):
     mixed precision, one part of `parts` contiguous id ranges per run (a whole
     map takes about 20 minutes), compared node by node with the stored oracle
     map (selected inversion, float32 storage); pads must come out exactly 0.
-    The part's results are saved under gpurun_out/ for a later merge."""
+    The part's results are saved under --out-dir for a later merge."""
     import numpy as np
     import torch
     desc = gen.config2()
@@ -857,7 +857,7 @@ def full_map_run(args, reff, gen, log):
     rel = np.abs(got[free] - want[free]) / want[free]
     n_ok = int(np.sum(rel <= 1e-3))
     pads_zero = bool(np.all(got[~free] == 0.0))
-    odir = os.path.join(ROOT, "gpurun_out")
+    odir = args.out_dir
     os.makedirs(odir, exist_ok=True)
     np.save(os.path.join(odir, f"fullmap_config2_part{i}of{k}.npy"), got)
     rec = {"full_map_part": i, "parts": k, "ids": [lo, hi], "free_nodes": int(free.sum()),
@@ -898,6 +898,8 @@ def main():
                          "contiguous node-id ranges, against the stored oracle map")
     ap.add_argument("--part", type=int, default=0)
     ap.add_argument("--parts", type=int, default=1)
+    ap.add_argument("--out-dir", default=os.path.join(ROOT, "fullmap_parts"),
+                    help="where --full-map saves its part's results")
     ap.add_argument("--surrogate-scale", action="store_true",
                     help="the learned screen at 4000 training plans x 1024 labels, "
                          "32 held-out exact maps; prints that record (several minutes)")
@@ -933,7 +935,7 @@ def main():
         print(json.dumps(stream_probe_run()), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(solves shard by node blocks; see the design notes)", file=sys.stderr)
         sys.exit(2)
 

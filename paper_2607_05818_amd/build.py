@@ -1,7 +1,7 @@
 """Build libreff.so (HIP for gfx950) in-tree with hipcc.
 
-Run as ``python -m paper_2607_05818_amd.build``; the package's
-``__graft_entry__.build()`` calls ``build()`` too.
+Run as ``python -m paper_2607_05818_amd.build``; the repository's entry
+module calls ``build()`` too.
 """
 from __future__ import annotations
 
