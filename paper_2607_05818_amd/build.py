@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libreff.so")
 
 SOURCES = ["reff_api.cpp", "reff_kernels.hip", "grid_pairs.hip", "reduced_pairs.hip", "ir_drop.hip",
-           "selinv.hip", "selinv_plan.cpp", "stream_probe.hip", "surrogate_api.cpp", "surrogate_kernels.hip"]
+           "selinv.hip", "selinv_plan.cpp", "stream_probe.hip", "surrogate_api.cpp", "surrogate_kernels.hip",
+           "coef_prep.hip"]
 
 # Packed FP32 arithmetic is disabled for every HIP translation unit.
 HIP_FLAGS = [

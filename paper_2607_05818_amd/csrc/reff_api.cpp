@@ -15,6 +15,7 @@
 #include <numeric>
 #include <random>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "reff_internal.h"
@@ -95,6 +96,11 @@ reff_status validate_desc(const reff_pdn_desc* d) {
 namespace reff {
 reff_status host_fail(reff_status s, const std::string& msg) { return fail(s, msg); }
 reff_status host_validate_desc(const reff_pdn_desc* d) { return validate_desc(d); }
+// D^-1 and the float32 coefficient copies from the float64 arrays
+// (coef_prep.hip)
+hipError_t launch_coef_derived(const double* d, const double* cE, const double* cN, int64_t n,
+                               double* dinv64, float* d32, float* dinv32, float* cE32,
+                               float* cN32, hipStream_t st);
 }  // namespace reff
 
 namespace {
@@ -358,10 +364,6 @@ reff_status make_coefset_multi(const std::vector<const reff_pdn_desc*>& ds,
   });
   for (size_t i = 0; i < np; ++i)
     if (st[i] != REFF_OK) return fail(st[i], "plan " + std::to_string(i) + ": " + msg[i]);
-  std::vector<double> dinv(h.d.size());
-  parallel_chunks(h.d.size(), [&](size_t lo, size_t hi) {
-    for (size_t i = lo; i < hi; ++i) dinv[i] = 1.0 / h.d[i];
-  });
   reff_status rs = REFF_OK;
   auto& owned = extra;
   auto upload_owned = [&](const std::vector<double>& src, double** d64, float** d32) {
@@ -369,10 +371,30 @@ reff_status make_coefset_multi(const std::vector<const reff_pdn_desc*>& ds,
     rs = upload<double>(src, d64, owned);
     if (rs == REFF_OK) rs = upload<float>(src, d32, owned);
   };
-  upload_owned(h.d, &cs.d64, &cs.d32);
-  upload_owned(dinv, &cs.dinv64, &cs.dinv32);
-  upload_owned(h.cE, &cs.cE64, &cs.cE32);
-  upload_owned(h.cN, &cs.cN64, &cs.cN32);
+  // d, cE and cN go up in float64; D^-1 and the float32 copies of the four
+  // per-node arrays are formed on the device (coef_prep.hip)
+  const size_t nn = h.d.size();
+  auto alloc = [&](auto** out) {
+    if (rs != REFF_OK) return;
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(*out)>>;
+    if (hipMalloc((void**)out, std::max<size_t>(1, nn) * sizeof(T)) != hipSuccess) {
+      rs = fail(REFF_ERR_OUT_OF_MEMORY, "coefficient arrays");
+      return;
+    }
+    owned.push_back(*out);
+  };
+  if (rs == REFF_OK) rs = upload<double>(h.d, &cs.d64, owned);
+  if (rs == REFF_OK) rs = upload<double>(h.cE, &cs.cE64, owned);
+  if (rs == REFF_OK) rs = upload<double>(h.cN, &cs.cN64, owned);
+  alloc(&cs.dinv64);
+  alloc(&cs.d32);
+  alloc(&cs.dinv32);
+  alloc(&cs.cE32);
+  alloc(&cs.cN32);
+  if (rs != REFF_OK) return rs;
+  HIPCHK(reff::launch_coef_derived(cs.d64, cs.cE64, cs.cN64, (int64_t)nn, cs.dinv64, cs.d32, cs.dinv32,
+                             cs.cE32, cs.cN32, nullptr));
+  HIPCHK(hipStreamSynchronize(nullptr));
   upload_owned(h.up, &cs.up64, &cs.up32);
   upload_owned(h.dn, &cs.dn64, &cs.dn32);
   if (rs != REFF_OK) return rs;
