@@ -225,7 +225,7 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes,
  * reff_selinv_diag for many stacks (candidate TSV plans, Sec. I and IV-B) in
  * one call, with no handle: the plans' dissection trees are analysed on
  * host threads and merged by depth, so every plan's fronts of one tree
- * level share the same launches.  Batches above 8M nodes run as up to four
+ * level share the same launches.  Batches above 4M nodes run as up to four
  * chunks of consecutive plans, the host analysis of a chunk overlapping the
  * device work of the one before.  Device memory (about the sum of a chunk's
  * plans' reff_selinv_info().device_bytes) comes from a workspace the library
@@ -243,7 +243,7 @@ reff_status reff_selinv_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes,
  *            on the current device.
  * Errors: INVALID_ARG (naming the plan), DISCONNECTED, OUT_OF_MEMORY, DEVICE.
  * Descriptors and node ids are validated before any device work, and so is
- * the analysis of the first chunk (of every plan, below 8M nodes); R_out is
+ * the analysis of the first chunk (of every plan, below 4M nodes); R_out is
  * written only when the call succeeds.
  */
 reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,

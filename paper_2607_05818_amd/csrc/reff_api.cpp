@@ -1961,9 +1961,19 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
   std::vector<const reff_pdn_desc*> ds((size_t)n_plans);
   std::vector<std::vector<int64_t>> gnds((size_t)n_plans);
   std::vector<StackInfo> stacks((size_t)n_plans);
+  {
+    // descriptors checked on host threads; the first bad plan is reported
+    std::vector<reff_status> vs((size_t)n_plans, REFF_OK);
+    std::vector<std::string> vm((size_t)n_plans);
+    parallel_for((size_t)n_plans, [&](size_t i) {
+      vs[i] = validate_desc(&plans[i]);
+      if (vs[i] != REFF_OK) vm[i] = g_err;  // this thread's message
+    });
+    for (int32_t i = 0; i < n_plans; ++i)
+      if (vs[(size_t)i] != REFF_OK)
+        return fail(vs[(size_t)i], "plan " + std::to_string(i) + ": " + vm[(size_t)i]);
+  }
   for (int32_t i = 0; i < n_plans; ++i) {
-    s = validate_desc(&plans[i]);
-    if (s != REFF_OK) return fail(s, "plan " + std::to_string(i) + ": " + g_err);
     ds[(size_t)i] = &plans[i];
     for (int32_t j = 0; j < plans[i].n_pads; ++j)
       gnds[(size_t)i].push_back((int64_t)plans[i].pad_xy[2 * j + 1] * plans[i].nx +

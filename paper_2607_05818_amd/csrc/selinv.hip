@@ -1040,10 +1040,16 @@ reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
   hipStream_t st_ = opts ? (hipStream_t)opts->stream : nullptr;
   const size_t np = (size_t)n_plans;
   std::vector<int64_t> cnt(np);
+  // descriptors checked on host threads; the first bad plan is reported
+  std::vector<reff_status> vs(np, REFF_OK);
+  std::vector<std::string> vm(np);
+  selinv_parallel_for(np, [&](size_t i) {
+    vs[i] = host_validate_desc(&plans[i]);
+    if (vs[i] != REFF_OK) vm[i] = reff_last_error();  // this thread's message
+  });
   for (size_t i = 0; i < np; ++i) {
     const std::string who = "plan " + std::to_string(i) + ": ";
-    reff_status v = host_validate_desc(&plans[i]);
-    if (v != REFF_OK) return host_fail(v, who + reff_last_error());
+    if (vs[i] != REFF_OK) return host_fail(vs[i], who + vm[i]);
     const int64_t n = (int64_t)plans[i].n_tiers * plans[i].nx * plans[i].ny;
     const bool given = nodes && nodes[i];
     if (given && (!n_nodes || n_nodes[i] < 0)) return host_fail(REFF_ERR_INVALID_ARG, who + "bad n_nodes");
@@ -1055,7 +1061,7 @@ reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
                          who + "node id " + std::to_string(nodes[i][k]) + " out of range");
   }
   // Plans are taken in chunks of consecutive plans with about equal node
-  // counts (one chunk below 8M nodes, at most four): the host analysis of
+  // counts (one chunk below 4M nodes, at most four): the host analysis of
   // chunk c + 1 runs on host threads while the device factors and inverts
   // chunk c, and each chunk is one forest (the plans' trees merged by
   // depth) on the device workspace.
@@ -1066,7 +1072,7 @@ reff_status reff_selinv_batch(const reff_pdn_desc* plans, int32_t n_plans,
     tot_n += pn[i];
   }
   const int64_t nch = std::max<int64_t>(
-      1, std::min<int64_t>({(int64_t)4, (int64_t)np, tot_n / (int64_t(8) << 20)}));
+      1, std::min<int64_t>({(int64_t)4, (int64_t)np, tot_n / (int64_t(4) << 20)}));
   std::vector<size_t> cb{0};
   {
     const int64_t share = (tot_n + nch - 1) / nch;
