@@ -707,7 +707,7 @@ reff_status run_blocks(Workspace& ws, const CoefSet& cs, const std::vector<Stack
   const int ncheb = (!o.indep && o.cheb > 1) ? (o.cheb > 2 ? 4 : 2) : 0;  // iterate arrays
   const size_t row_bytes =
       S * (tsz * (5 + (with_d ? 1 : 0) + ncheb) + (o.mixed ? sizeof(double) : 0));
-  const int64_t budget_rows = std::max<int64_t>(1, (int64_t)(48e9 / (double)row_bytes));
+  const int64_t budget_rows = std::max<int64_t>(1, (int64_t)(96e9 / (double)row_bytes));
   const Coef<double> c64 = coef64(cs);
   const Coef<float> c32 = coef32(cs);
   const void* coef = fp32 ? (const void*)&c32 : (const void*)&c64;
