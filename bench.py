@@ -266,6 +266,34 @@ def large_compare(reff, gen, log, rel_tol, half=64):
                               "median_rel_gap": float(np.median(gaps)) if gaps else None}}
 
 
+def batched_only_run(rel_tol, reps=2):
+    """The 256-plan batch alone (for kernel traces of the batched call): a
+    warm-up call on four plans, then `reps` timed reff_batch_plans calls
+    over all plans in mixed precision, each checked against the stored
+    oracle values."""
+    import numpy as np
+    import torch
+    from paper_2607_05818_amd import gen, reff
+    plans = gen.config3_plans()
+    nodes = gen.config3_samples(plans)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "config3_sample.json")))
+    want = [np.array(g) for g in gold["R"]]
+    reff.reff_batch_plans(plans[:4], nodes[:4], precision=reff.REFF_PREC_MIXED, rel_tol=rel_tol)
+    torch.cuda.synchronize()
+    dts, n_ok = [], 0
+    for _ in range(reps):
+        a = time.perf_counter()
+        outs, _ = reff.reff_batch_plans(plans, nodes, precision=reff.REFF_PREC_MIXED,
+                                        rel_tol=rel_tol)
+        torch.cuda.synchronize()
+        dts.append(time.perf_counter() - a)
+        rel = np.concatenate([np.abs(outs[i] - want[i]) / want[i] for i in range(len(plans))])
+        n_ok = int(np.sum(rel <= 1e-3))
+    total = sum(len(x) for x in nodes)
+    return {"workload": "256 TSV plans, 64 seeded nodes per plan, mixed", "nodes": total,
+            "n_ok": n_ok, "seconds_all": dts, "nodes_per_s": n_ok / min(dts)}
+
+
 def batched_compare(reff, gen, log, rel_tol, n_seq=16, reps=3):
     """The batching workload: 256 candidate TSV plans (2-4 tiers, sides
     64-256, about 22M nodes in total) with one seeded 64-node block per
@@ -913,6 +941,9 @@ def main():
                     help="--direct-only: tier side of the 4-tier stack (512: the benchmark "
                          "stack, checked against the stored oracle map; larger sides draw "
                          "the same recipe and check 32 nodes against block-PCG solves)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 256-plan batch (mixed block PCG, 64 seeded nodes per plan): "
+                         "one warm-up call on four plans, then two timed calls; one JSON record")
     ap.add_argument("--stream-probe", action="store_true",
                     help="only the HBM bandwidth probes (copy, read, write, 3-read/2-write, "
                          "non-temporal copy) over grid sizes; prints one JSON record")
@@ -933,6 +964,9 @@ def main():
         return
     if args.stream_probe:
         print(json.dumps(stream_probe_run()), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps(batched_only_run(args.rel_tol)), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "

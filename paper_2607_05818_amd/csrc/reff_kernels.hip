@@ -1481,9 +1481,12 @@ __global__ __launch_bounds__(WG, sizeof(T) == 4 ? 4 : 2) void k_cheb2_strip(Coef
 // Two launches, one wave per item (4 waves per workgroup, no synchronisation
 // inside a launch): k_cheb_tsv_a forms TA item (slot, k), k_cheb_tsv_b then TB
 // item (slot); a node's TSV partners are the next and previous slot (the
-// slots of a TSV column are consecutive over its tiers).  Grid (items / 4,
-// active blocks).
+// slots of a TSV column are consecutive over its tiers).  Grid (x, active
+// blocks): the waves of a block's row of workgroups stride over its items,
+// and x is capped so that a batch of many plans, whose largest plan sets
+// the item count, launches no more than about TSV_GRID_CAP workgroups.
 constexpr int TSV_WAVES = 4;
+constexpr int TSV_GRID_CAP = 65536;
 
 template <typename T, bool HAS_PREV>
 __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv_a(
@@ -1495,10 +1498,11 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv_a(
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if ((int)blockIdx.y >= wk.cnt[2]) return;
   const PlanDesc pd = wk.plans[act[blockIdx.y]];
-  const int item = blockIdx.x * TSV_WAVES + w;
-  if (item >= 5 * (pd.slot_end - pd.slot_begin)) return;  // the whole wave
+  const int nitems = 5 * (pd.slot_end - pd.slot_begin);
   const int nx = pd.nx;
   const int ny = (int)(pd.plane / pd.nx);
+  for (int item = blockIdx.x * TSV_WAVES + w; item < nitems;  // wave-uniform
+       item += gridDim.x * TSV_WAVES) {
   const int qi = item / 5, k = item % 5;
   const int64_t loc = c.tnode[pd.slot_begin + qi] - pd.cbase;  // node within the stack
   const int64_t rem = loc % pd.plane;
@@ -1511,6 +1515,7 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv_a(
                                        pd.vbase + loc + dx + (int64_t)dy * nx, xn, yn, a1, a2,
                                        ith);
   TA[((pd.sbase + qi) * 5 + k) * S + lane] = z;
+  }
 }
 
 template <typename T, bool HAS_PREV>
@@ -1522,10 +1527,11 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv_b(
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if ((int)blockIdx.y >= wk.cnt[2]) return;
   const PlanDesc pd = wk.plans[act[blockIdx.y]];
-  const int qi = blockIdx.x * TSV_WAVES + w;
-  if (qi >= pd.slot_end - pd.slot_begin) return;  // the whole wave
+  const int nslot = pd.slot_end - pd.slot_begin;
   const int nx = pd.nx;
   const int64_t cofs = pd.cbase - pd.vbase;
+  for (int qi = blockIdx.x * TSV_WAVES + w; qi < nslot;  // wave-uniform
+       qi += gridDim.x * TSV_WAVES) {
   const int q = pd.slot_begin + qi;
   const int64_t u = c.tnode[q];  // coefficient index
   const int64_t loc = u - pd.cbase;
@@ -1544,6 +1550,7 @@ __global__ __launch_bounds__(64 * TSV_WAVES) void k_cheb_tsv_b(
                 ldc(c.cE, u), cw, ldc(c.cN, u), cs, gu, gd,
                 FIRST ? cheb_z1(c, R, v, cofs, ith) : zin[v * S + lane], R[v * S + lane],
                 ldc(c.dinv, u), b1, b2);
+  }
 }
 
 // Three Chebyshev steps in one pass over a strip (float32, block variant):
@@ -2642,8 +2649,10 @@ static T* cheb_steps(const Coef<T>& c, const SolveBuffers& b, hipStream_t st, T*
       coef(j + 2, c1, c2);
       const T* zp = prev < 0 ? nullptr : buf[prev];
       if (b.max_tsv_slots > 0) {
-        const dim3 ga((5 * b.max_tsv_slots + TSV_WAVES - 1) / TSV_WAVES, b.n_act);
-        const dim3 gb((b.max_tsv_slots + TSV_WAVES - 1) / TSV_WAVES, b.n_act);
+        const int gcap = std::max(1, TSV_GRID_CAP / std::max(b.n_act, 1));
+        const dim3 ga(std::min((5 * b.max_tsv_slots + TSV_WAVES - 1) / TSV_WAVES, gcap),
+                      b.n_act);
+        const dim3 gb(std::min((b.max_tsv_slots + TSV_WAVES - 1) / TSV_WAVES, gcap), b.n_act);
         const dim3 tb(64 * TSV_WAVES);
         const T* zc = (const T*)buf[cur];
         if (prev < 0) {
