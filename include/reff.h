@@ -111,7 +111,10 @@ typedef struct {
                             q(D^-1 G) D^-1 of that degree (SPD and fixed,
                             so the results are those of PCG with a stronger
                             preconditioner; fewer, costlier iterations);
-                            0 => 19.  The independent variant uses Jacobi. */
+                            0 => by the larger side of the stack's tiers
+                            (of a batch's largest plan): 19 up to 640
+                            nodes, 31 above.  The independent variant uses
+                            Jacobi. */
   int32_t pairs_resident_blocks;
                          /* reff_query_pairs: solution blocks (64 endpoints
                             each, n_nodes x 64 float64) kept on the device

@@ -434,9 +434,18 @@ struct Opts {
   const char* tune_db = nullptr;  // tuning database path (batched solves)
   bool progress = false;          // progress lines on stderr
   int cheb = 19;                  // Chebyshev preconditioner degree (1 = Jacobi)
+  bool cheb_auto = false;         // degree chosen by the stack's size (precond_degree 0)
   int brhs = S;                   // right-hand sides dealt to one block (32 or 64)
   int32_t resident = 0;           // reff_query_pairs: solution blocks on the device (0 = auto)
 };
+
+// Default Chebyshev degree by the larger side of the stack's tiers: the
+// spectrum of D^-1 G widens with the grid, so larger grids take a higher
+// degree (fewer, costlier iterations).  Measured (mixed precision, 64 to 512
+// sampled nodes): 4 x 512 x 512, degrees 13 / 16 / 19 / 22 / 25 give 820 /
+// 852 / 872 / 861 / 863 nodes/s; 8 x 1024 x 1024, 19 / 25 / 31 give 55.4 /
+// 58.3 / 59.7; 8 x 2048 x 2048, 2.25 / 2.39 / 2.47.
+int auto_cheb_degree(int64_t side) { return side <= 640 ? 19 : 31; }
 
 reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
   reff_solve_opts z;
@@ -470,6 +479,7 @@ reff_status parse_opts(const reff_solve_opts* o, Opts& out) {
   if (o->precond_degree < 0 || o->precond_degree > MAX_CHEB)
     return fail(REFF_ERR_INVALID_ARG, "precond_degree must be in [0, 32]");
   out.cheb = o->precond_degree == 0 ? 19 : o->precond_degree;
+  out.cheb_auto = o->precond_degree == 0;
   // The kernels map one right-hand side to one lane of a 64-wide wave, so a
   // block always streams 64 columns: 32 leaves half of them empty (no saving)
   // and the automatic choice (0) is 64.
@@ -1365,6 +1375,7 @@ reff_status reff_solve_diag(reff_pdn p, const int64_t* nodes, int64_t n_nodes, d
   Opts o;
   reff_status s = parse_opts(opts, o);
   if (s != REFF_OK) return s;
+  if (o.cheb_auto) o.cheb = auto_cheb_degree(std::max<int64_t>(p->nx, p->ny));
   if (nodes && n_nodes < 0) return fail(REFF_ERR_INVALID_ARG, "n_nodes < 0");
   const int64_t count = nodes ? n_nodes : p->n;
   if (count > 0 && !R_out) return fail(REFF_ERR_INVALID_ARG, "R_out is NULL");
@@ -1414,6 +1425,7 @@ reff_status reff_query_pairs(reff_pdn p, const int64_t* a, int64_t m, const int6
   Opts o;
   reff_status s = parse_opts(opts, o);
   if (s != REFF_OK) return s;
+  if (o.cheb_auto) o.cheb = auto_cheb_degree(std::max<int64_t>(p->nx, p->ny));
   for (int64_t i = 0; i < m; ++i)
     if (a[i] < 0 || a[i] >= p->n) return fail(REFF_ERR_INVALID_ARG, "node id out of range in a");
   for (int64_t j = 0; j < n; ++j)
@@ -1599,6 +1611,7 @@ reff_status reff_ir_drop(reff_pdn p, const int64_t* load_nodes, int64_t n_loads,
   Opts o;
   reff_status s = parse_opts(opts, o);
   if (s != REFF_OK) return s;
+  if (o.cheb_auto) o.cheb = auto_cheb_degree(std::max<int64_t>(p->nx, p->ny));
   // Point values of a response are accurate to about the square root of the
   // energy-norm error the solver controls; the defaults are tighter than
   // those of reff_solve_diag accordingly.
@@ -1942,6 +1955,12 @@ reff_status reff_batch_plans(const reff_pdn_desc* plans, int32_t n_plans,
   Opts o;
   reff_status s = parse_opts(opts ? &opts->solve : nullptr, o);
   if (s != REFF_OK) return s;
+  if (o.cheb_auto && plans) {
+    int64_t side = 0;
+    for (int32_t i = 0; i < n_plans; ++i)
+      side = std::max<int64_t>(side, std::max(plans[i].nx, plans[i].ny));
+    o.cheb = auto_cheb_degree(side);
+  }
   o.tune_db = opts ? opts->tune_db : nullptr;
   reff_surrogate sg = opts ? (reff_surrogate)opts->surrogate : nullptr;
   double spot_frac = 0.01, fb_err = 1e-2;
