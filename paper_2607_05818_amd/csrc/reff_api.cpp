@@ -556,10 +556,24 @@ constexpr int TARGET_UNITS = 1024;  // 4 workgroups of 512 threads per CU
 // block has 64 chunks per unit to give: blocks converge at different times
 // and leave the active lists, so a block that runs on alone still spreads
 // over the whole device.
+// Most work pieces a floor may bring a launch to: every piece has its S x S
+// partial Grams reduced each iteration, so a batch of thousands of small
+// plans keeps the proportional split instead.
+constexpr int64_t MAX_FLOOR_PIECES = 16384;
+
 void make_units(const std::vector<PlanDesc>& in, std::vector<PlanDesc>& plans,
                 std::vector<Unit>& units, int target = TARGET_UNITS, int floor = 0) {
   int64_t rows = 0;
   for (const PlanDesc& p : in) rows += p.n;
+  if (floor > 0) {
+    int64_t total = 0;
+    for (const PlanDesc& p : in) {
+      const int64_t nch = (p.n + CH - 1) / CH;
+      total += std::max<int64_t>((target * p.n + rows - 1) / std::max<int64_t>(rows, 1),
+                                 std::min<int64_t>(floor, nch / 64));
+    }
+    if (total > MAX_FLOOR_PIECES) floor = 0;
+  }
   plans = in;
   units.clear();
   for (size_t i = 0; i < plans.size(); ++i) {
@@ -599,6 +613,16 @@ void make_strips(std::vector<PlanDesc>& plans, std::vector<Strip>& strips,
                  int target = TARGET_UNITS, int floor = 0) {
   int64_t rows = 0;
   for (const PlanDesc& p : plans) rows += p.n;
+  if (floor > 0) {
+    int64_t total = 0;
+    for (const PlanDesc& p : plans) {
+      const int64_t nx = p.nx, ny = p.plane / p.nx, nt = p.n / p.plane;
+      const int64_t nsx = (nx + CH - 1) / CH;
+      total += std::max<int64_t>((target * p.n + rows - 1) / std::max<int64_t>(rows, 1),
+                                 std::min<int64_t>(floor, nt * nsx * std::max<int64_t>(1, ny / 64)));
+    }
+    if (total > MAX_FLOOR_PIECES) floor = 0;
+  }
   strips.clear();
   for (size_t i = 0; i < plans.size(); ++i) {
     PlanDesc& p = plans[i];
