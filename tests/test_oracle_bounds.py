@@ -81,3 +81,37 @@ def test_window_without_pad_on_upper_tier_has_no_upper_bound():
     lo, hi = ob.window_bounds(d, v, 2)
     assert np.isinf(hi) and 0 < lo < np.inf
     assert lo <= ro.diag(d, [v])[0]
+
+
+def test_planted_mistakes_are_caught():
+    """Plausible mistakes in the bounds fail the pins above: merging the
+    outside without keeping the resistors that reach it (the lower bound then
+    loses its paths to the ring) breaks the chain's parallel form, and a
+    window shifted by one column stops bracketing the exact values."""
+    rng = np.random.default_rng(7)
+    g = rng.uniform(0.5, 2.0, size=12)
+    d = _chain(g)
+    i, half = 6, 3  # window [3, 10) of 13 nodes: ring nodes at 2 and 10
+    # correct lower bound: paths to both ring nodes
+    left = float(np.sum(1.0 / g[i - half - 1:i]))
+    right = float(np.sum(1.0 / g[i:i + half + 1]))
+    want = 1.0 / (1.0 / left + 1.0 / right)
+    lo, _ = ob.window_bounds(d, i, half)
+    assert lo == pytest.approx(want, rel=REL)
+    # planted: the ring grounded but the window's edges to it cut -> the
+    # node has no path to ground inside the window
+    w = ob.sub_desc(d, i - half, i + half + 1, 0, 1)
+    L = ro.laplacian(w)
+    assert np.isinf(ob._resistance(L, [], half))
+    # planted: a window shifted one column away from the node's own column
+    s = gen.small_random_desc(41, 2, 12, 9, 6, 2)
+    exact = ro.diag(s)
+    bad = 0
+    for v in range(0, 2 * 12 * 9, 5):
+        t, rem = divmod(v, 12 * 9)
+        y, x = divmod(rem, 12)
+        if x + 1 >= 12 or exact[v] == 0.0:
+            continue
+        lo, hi = ob.window_bounds(s, v + 1, 2)  # bounds of the neighbour, not of v
+        bad += not (lo <= exact[v] * (1 + REL) and exact[v] <= hi * (1 + REL))
+    assert bad > 0
