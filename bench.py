@@ -175,7 +175,7 @@ def cpu_baseline(desc, batch_nodes, want, full_map=True):
         "unit": "nodes/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"the batch of {len(batch_nodes)} nodes on the same stack: float64 sparse "
+        "sample": (f"the first {len(batch_nodes)} nodes of the timed batch, same stack: float64 sparse "
                    f"Cholesky of G (nested dissection, multifrontal; assembly included) "
                    f"{t1 - t0:.1f} s + {len(batch_nodes)} unit-current solves {t2 - t1:.1f} s, "
                    f"measured, {threads} threads; max rel diff to the stored values {err:.1e}"),
