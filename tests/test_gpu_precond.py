@@ -119,3 +119,23 @@ def test_wide_tier_falls_back_to_two_step_passes():
     _say("stack after the wide tier")
     got2, _ = reff.reff_solve_diag(reff.reff_build_pdn(d2), nodes2, precision=1, rel_tol=1e-4)
     assert float(np.max(np.abs(got2 - want2) / want2)) <= 1e-3
+
+
+@pytest.mark.parametrize("nx,ny,deg", [(96, 40, 19), (700, 24, 31)])
+def test_automatic_degree_follows_the_grid(nx, ny, deg):
+    """precond_degree 0 picks 19 up to 640 nodes a side and 31 above: the
+    solves are deterministic, so the default call equals the explicit
+    degree bit for bit (and stays within the mixed bar of the oracle)."""
+    reff = _reff()
+    d = gen.small_random_desc(900 + nx, 2, nx, ny, 12, 4)
+    nodes = gen.sample_free_nodes(d, 64, 5)
+    _say("automatic degree", nx, ny, "expects", deg)
+    h = reff.reff_build_pdn(d)
+    auto, st_a = reff.reff_solve_diag(h, nodes, precision=reff.REFF_PREC_MIXED, rel_tol=1e-4)
+    expl, st_e = reff.reff_solve_diag(h, nodes, precision=reff.REFF_PREC_MIXED, rel_tol=1e-4,
+                                      precond_degree=deg)
+    assert np.array_equal(auto, expl)
+    assert st_a["iters_total"] == st_e["iters_total"]
+    want = ro.diag(d, nodes)
+    assert float(np.max(np.abs(auto - want) / want)) <= 1e-3
+    h.close()
