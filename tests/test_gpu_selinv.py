@@ -239,3 +239,36 @@ def test_batch_node_requests_equal_full_batch():
         want = full[i] if nodes[i] is None else full[i][nodes[i]]
         assert np.array_equal(got[i], want)
     assert st["flops_selinv"] < st_full["flops_selinv"]
+
+
+def test_batch_in_chunks_all_nodes_equal_single_calls():
+    """A batch above 8M nodes runs as several chunks of plans (the host
+    analysis of one under the device work of the previous): every node of
+    every plan, written to device memory, against reff_selinv_diag of the
+    plan alone (1e-12: the forests may split products differently)."""
+    import torch
+    reff = _reff()
+    plans = gen.config3_plans()
+    order = np.argsort([-gen.n_nodes(d) for d in plans], kind="stable")
+    pick, tot = [], 0
+    for i in order:
+        pick.append(plans[int(i)])
+        tot += gen.n_nodes(plans[int(i)])
+        if tot > 9 << 20:
+            break
+    _say("selinv batch in chunks,", len(pick), "plans,", tot, "nodes")
+    dev = [torch.full((gen.n_nodes(d),), -1.0, dtype=torch.float64, device="cuda") for d in pick]
+    _, st = reff.reff_selinv_batch(pick, None, dev)
+    torch.cuda.synchronize()
+    print({k: v for k, v in st.items()}, flush=True)
+    worst = 0.0
+    for d, out in zip(pick, dev):
+        h = reff.reff_build_pdn(d)
+        alone, _ = reff.reff_selinv_diag(h)
+        h.close()
+        got = out.cpu().numpy()
+        m = alone > 0
+        assert np.all(got[~m] == 0.0)
+        worst = max(worst, float(np.max(np.abs(got[m] - alone[m]) / alone[m])))
+    print("worst relative difference to single calls", worst, flush=True)
+    assert worst <= 1e-12
