@@ -7,6 +7,7 @@ R_i = (G^-1)_ii (paper Sec. II-B, Eq. 2 with the bumps merged into the
 grounded supply) for a seeded sample of nodes, or for every node.
 
     python tests/golden/make_golden.py [config2] [config3] [config2_full] [config5_quarter]
+                                       [config5_bounds]
 """
 import json
 import os
@@ -108,15 +109,44 @@ def config5_quarter():
     }
 
 
+def config5_bounds():
+    """The full-size large workload (8 tiers of 2048 x 2048): no exact
+    oracle solve fits one host, so the benchmark checks its first 16 seeded
+    nodes against Rayleigh window bounds (oracle/bounds.py, 129 x 129
+    columns around each node, all tiers); null marks an infinite upper
+    bound."""
+    from oracle import bounds
+    desc = gen.config5()
+    nodes = gen.sample_free_nodes(desc, 64, 5005)[:16]
+    t0 = time.time()
+    lo, hi = [], []
+    for v in nodes:
+        a, b = bounds.window_bounds(desc, int(v), 64)
+        lo.append(float(a))
+        hi.append(float(b) if np.isfinite(b) else None)
+    dt = time.time() - t0
+    return {
+        "what": ("Rayleigh window bounds on R_i = (G^-1)_ii (cut outside: upper; outside "
+                 "merged into the supply: lower), large workload at full size"),
+        "inputs": ("gen.config5(seed=1005); nodes = gen.sample_free_nodes(desc, 64, 5005)[:16]; "
+                   "bounds.window_bounds(desc, v, 64)"),
+        "oracle_seconds": dt,
+        "nodes": [int(v) for v in nodes],
+        "lo": lo,
+        "hi": hi,
+    }
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["config2", "config3", "config2_full", "config5_quarter"]
+    which = sys.argv[1:] or ["config2", "config3", "config2_full", "config5_quarter", "config5_bounds"]
     if "config2_full" in which:
         print("wrote config2_fullmap_f32.npy", config2_full())
     for name, fn in (("config2", config2_sample), ("config3", config3_sample),
-                     ("config5_quarter", config5_quarter)):
+                     ("config5_quarter", config5_quarter), ("config5_bounds", config5_bounds)):
         if name not in which:
             continue
         out = fn()
-        with open(os.path.join(HERE, name + "_sample.json"), "w") as f:
+        fname = name + ("" if name.endswith("bounds") else "_sample") + ".json"
+        with open(os.path.join(HERE, fname), "w") as f:
             json.dump(out, f, indent=0)
-        print("wrote", name + "_sample.json", out["oracle_seconds"])
+        print("wrote", fname, out["oracle_seconds"])

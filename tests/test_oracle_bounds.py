@@ -115,3 +115,22 @@ def test_planted_mistakes_are_caught():
         lo, hi = ob.window_bounds(s, v + 1, 2)  # bounds of the neighbour, not of v
         bad += not (lo <= exact[v] * (1 + REL) and exact[v] <= hi * (1 + REL))
     assert bad > 0
+
+
+def test_stored_large_stack_bounds_reproduce():
+    """tests/golden/config5_bounds.json (the benchmark's check of the
+    full-size large stack) holds what the oracle computes: its node sample
+    and two of its bound pairs recomputed here."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config5_bounds.json")))
+    d = gen.config5()
+    nodes = gen.sample_free_nodes(d, 64, 5005)[:16]
+    assert [int(v) for v in nodes] == g["nodes"]
+    for j in (0, 5):
+        lo, hi = ob.window_bounds(d, int(nodes[j]), 64)
+        assert lo == pytest.approx(g["lo"][j], rel=1e-12)
+        if g["hi"][j] is None:
+            assert np.isinf(hi)
+        else:
+            assert hi == pytest.approx(g["hi"][j], rel=1e-12)
