@@ -37,3 +37,25 @@ def test_block_kernel_flops():
     assert k1 == 2 * g * 10 // 16 + 2 * g            # P = Y T, Q = (G Y) T (10 of 16 blocks of T), 2 Grams
     assert (k2, k3, kp, kg) == (g, 3 * g, 0, g)        # Q A; P B, P A, Y^T D Y; none; Q^T Z
     assert bench.kernel_flops(cheb=1)[1:3] == [3 * g, 2 * g]
+
+
+def test_stored_bounds_check():
+    """The large-stack check reads the stored oracle bounds: values at the
+    lower bounds count as inside, values 1 % above a finite upper bound do
+    not, and another node sample is not checked at all."""
+    import json
+    import os
+
+    import numpy as np
+    g = json.load(open(os.path.join(bench.ROOT, "tests", "golden", "config5_bounds.json")))
+    nodes = np.array(g["nodes"] + [0] * 48)
+    lo = np.array(g["lo"] + [0.0] * 48)
+    rec = bench.stored_bounds_check(nodes, lo)
+    assert rec["inside_within_1e-3"] == 16
+    finite = [j for j, h in enumerate(g["hi"]) if h is not None]
+    assert rec["finite_upper"] == len(finite) > 0
+    over = lo.copy()
+    for j in finite:
+        over[j] = 1.01 * g["hi"][j]
+    assert bench.stored_bounds_check(nodes, over)["inside_within_1e-3"] == 16 - len(finite)
+    assert bench.stored_bounds_check(nodes[::-1].copy(), lo) is None
